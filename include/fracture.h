@@ -1,0 +1,263 @@
+/*
+ * fracture.h -- C ABI of the MI355X (gfx950) Newton-step linear solve for pressurized
+ * phase-field fracture (Heister & Wick 2018).
+ *
+ * The library computes, on one GPU, the Newton step of Formulation 1 (Section 2):
+ * Q1 assembly of the residual of equations E22ATW / E33ATW and of the Jacobian blocks
+ * M_uu, M_phiu, M_phiphi (Section 3, "Linear iterative solution"; M_uphi = 0), the
+ * primal-dual active set of the irreversibility constraint phi <= phi_old with the
+ * elimination of active rows and columns (Section 3, commented algorithm, steps 2-4),
+ * an FGMRES solve preconditioned by block-diagonal smoothed-aggregation AMG (one V-cycle
+ * per diagonal block, Section 3), the Newton / active-set loop with line search
+ * (steps 1-6) and the TCV / COD functionals (Section 4).
+ *
+ * Conventions shared by every call:
+ *  - Every array argument is a DEVICE pointer unless its comment says "host".
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream). Work is
+ *    enqueued on it; calls that return host scalars synchronise it (said per call).
+ *  - User vectors cover all mesh nodes: u is [n_nodes][dim] (node-major, AoS), phi,
+ *    phi_old, phi_tilde are [n_nodes]. Hanging-node values are overwritten by the
+ *    library from the constraints (edge midpoints 1/2 + 1/2, face centres 1/4 each).
+ *  - Solve-order vectors (du, residual, right-hand side) have n_solve = (dim+1) n_free
+ *    entries: the u block node-major over free nodes (index f*dim + c), then the phi
+ *    block (index dim*n_free + f), the block basis of Section 3. Dirichlet u DoFs and
+ *    active phi DoFs stay in the system as rows with their original diagonal.
+ *  - Handles are owned by the library and released by the matching *_destroy. The caller
+ *    owns every array argument and keeps it alive until the stream has reached the call.
+ *  - Arguments are validated before any device work (FR_EINVAL). Errors never throw
+ *    across the ABI; fracture_last_error() returns a message for the calling thread.
+ */
+#ifndef FRACTURE_H
+#define FRACTURE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FR_OK = 0,
+    FR_EINVAL = 1,      /* bad argument (checked before any device work)            */
+    FR_ENOMEM = 2,      /* device or host allocation failed                          */
+    FR_EDEVICE = 3,     /* HIP runtime error, or no usable gfx950 device             */
+    FR_ENOCONV = 4,     /* iteration limit reached; outputs hold the last iterate     */
+    FR_EBREAKDOWN = 5,  /* Krylov breakdown (zero or non-finite Arnoldi norm)         */
+    FR_ENAN = 6,        /* non-finite value in the residual, Jacobian or solution    */
+    FR_ECYCLE = 7,      /* active set still changing after the cycle freeze          */
+    FR_EINTERNAL = 8    /* internal capacity exceeded (message names the limit)      */
+} fr_status;
+
+typedef struct fr_mesh_s* fr_mesh;
+typedef struct fr_system_s* fr_system;
+typedef struct fr_amg_s* fr_amg;
+
+/* Mesh of B = [lo, hi] (Section 2: homogeneous Dirichlet u on the outer boundary,
+ * no condition on phi). Cells are cubes: (hi[k]-lo[k])/base[k] must agree on all axes.
+ * levels = 0: uniform mesh of base[0] x ... cells. levels > 0: every cell whose box comes
+ * within refine_radius of the crack (2d: segment |x - c_x| <= crack_half_len on the line
+ * y = c_y; 3d: disk of radius crack_half_len in the plane z = c_z) is split, `levels`
+ * times, followed by 2:1 balancing across faces (Section 3 adaptive meshes). */
+typedef struct {
+    int dim;                 /* 2 or 3 */
+    double lo[3], hi[3];
+    int base[3];
+    int levels;
+    double refine_radius;
+    double crack_center[3];
+    double crack_half_len;
+} fr_mesh_desc;
+
+/* Material and method constants (Section 2, Formulation 1; Section 4). The active set is
+ * A = { i : -R_phi,i / B_ii + c_pdas (phi_i - phi_old,i) > tau_pdas }, B the lumped phi
+ * mass; tau_pdas <= 0 selects 1e-10 Gc / eps. */
+typedef struct {
+    double E, nu, Gc, kappa, eps, p, c_pdas, tau_pdas;
+} fr_params;
+
+/* Smoothed-aggregation AMG options (one hierarchy per diagonal block). */
+typedef struct {
+    int precision;       /* 64: FP64 hierarchy and V-cycle; 32: FP32 storage and arithmetic */
+    double theta;        /* strength threshold, |A_ij| >= theta sqrt(|A_ii| |A_jj|) (block Frobenius norms) */
+    int cheb_degree;     /* Chebyshev smoother degree (>= 1) */
+    double cheb_ratio;   /* smoothing interval [lambda_max / ratio, lambda_max] */
+    int coarse_max;      /* coarsest level solved densely once it has <= coarse_max rows */
+    int max_levels;      /* cap on the number of levels (>= 1) */
+} fr_amg_opts;
+
+/* FGMRES options (right preconditioned, x0 = 0). */
+typedef struct {
+    double rtol;         /* stop when ||F - J du||_2 <= rtol ||F||_2 (true residual, FP64) */
+    int restart;         /* Krylov basis size before a restart */
+    int maxit;           /* total iteration cap */
+} fr_solve_opts;
+
+typedef struct {
+    int iters;           /* FGMRES iterations */
+    double relres;       /* true relative residual ||F - J du|| / ||F|| at exit */
+    int status;          /* fr_status of this solve */
+} fr_solve_stats;
+
+typedef struct {
+    double tol;          /* stop when the active set is unchanged and ||R~|| <= tol ||R~(U0)|| */
+    int max_it;          /* Newton iteration cap */
+    int ls_max;          /* line search tries omega = 1, 1/2, ..., 2^-ls_max */
+} fr_newton_opts;
+
+typedef struct {
+    int iterations;      /* Newton iterations taken */
+    int linear_iters;    /* sum of FGMRES iterations */
+    double res0, res;    /* ||R~(U0)|| and ||R~|| at exit */
+    int64_t n_active;    /* active phi DoFs at exit */
+    int status;
+    double t_assemble, t_setup, t_solve, t_other;  /* seconds, HIP-event timed */
+} fr_newton_stats;
+
+/* Flags of fracture_assemble. */
+#define FR_RESIDUAL   1u   /* residual R (unmasked) and lumped mass B              */
+#define FR_ACTIVE_SET 2u   /* active set from R, B, phi, phi_old (needs R)          */
+#define FR_JACOBIAN   4u   /* masked Jacobian and right-hand side F (needs the set) */
+
+/* ---- mesh ------------------------------------------------------------------------- */
+
+/* Builds the mesh, its node numbering, Dirichlet flags, hanging-node constraints, the
+ * node-graph sparsity (SELL-C layout) and the assembly tables, and uploads them on
+ * `stream`. desc: host, one descriptor. */
+fr_status fracture_mesh_create(const fr_mesh_desc* desc, fr_mesh* out, void* stream);
+
+/* Host outputs (any may be NULL). n_all = (dim+1) n_nodes (the DoF count of Table 1). */
+fr_status fracture_mesh_info(fr_mesh mesh, int64_t* n_nodes, int64_t* n_cells, int64_t* n_free,
+                             int64_t* n_all, int64_t* n_solve, int64_t* n_hanging,
+                             double* h_min, int64_t* nnz_node_graph);
+
+/* Host outputs: xyz[n_nodes*dim] node coordinates; lattice (nullable) integer coordinates
+ * in units of the finest cell edge; dirichlet (nullable) 1 for boundary nodes;
+ * free_index (nullable) solve-order node index or -1 for hanging nodes. */
+fr_status fracture_mesh_nodes(fr_mesh mesh, double* xyz, int64_t* lattice, uint8_t* dirichlet,
+                              int32_t* free_index);
+
+/* Builds the same mesh on the host only (no device memory, no device needed), for
+ * inspection with fracture_mesh_info / _nodes / _cells / _constraints. Every call that
+ * needs the device rejects such a mesh with FR_EINVAL. */
+fr_status fracture_mesh_create_host(const fr_mesh_desc* desc, fr_mesh* out);
+
+/* Host outputs (nullable): cells[n_cells][2^dim] vertex node ids (vertex a at the lower
+ * corner plus bit k of a along axis k), cell_lo[n_cells][dim] lower corners, cell_h[n_cells]
+ * edge lengths. */
+fr_status fracture_mesh_cells(fr_mesh mesh, int32_t* cells, double* cell_lo, double* cell_h);
+
+/* Hanging-node conformity map, host CSR over nodes: value(node n) =
+ * sum_j con_w[j] value(free node con_master[j]) for j in [con_ptr[n], con_ptr[n+1]);
+ * a free node lists itself with weight 1. *n_entries is always set; arrays are nullable
+ * (con_ptr has n_nodes+1 entries). */
+fr_status fracture_mesh_constraints(fr_mesh mesh, int64_t* n_entries, int32_t* con_ptr,
+                                    int32_t* con_master, double* con_w);
+
+void fracture_mesh_destroy(fr_mesh mesh);
+
+/* ---- assembly --------------------------------------------------------------------- */
+
+/* Assembles at the state (u, phi) with the constraint phi <= phi_old and the
+ * extrapolation phi_tilde (Formulation 1). *sys == NULL creates the system object (its
+ * matrices follow the mesh pattern); otherwise it is reused. flags selects the stages.
+ * The active set of the FR_JACOBIAN stage is the one computed by the last FR_ACTIVE_SET
+ * stage (callers may also install one with fracture_set_active). u and phi are read on
+ * all nodes; only their values at free nodes enter (hanging values are interpolated). */
+fr_status fracture_assemble(fr_mesh mesh, const fr_params* prm /*host*/, const double* u,
+                            const double* phi, const double* phi_old, const double* phi_tilde,
+                            unsigned flags, fr_system* sys, void* stream);
+
+/* Host outputs: norms[0] = ||R~||_2 (R with Dirichlet u rows and active phi rows
+ * zeroed), norms[1] = ||F||_2 (masked right-hand side, if assembled);
+ * n_active = |A|; active_changes = entries that changed in the last FR_ACTIVE_SET;
+ * min_margin = min_i |lambda_i + c(phi_i - phi_old,i) - tau| (distance of the closest
+ * decision to the threshold). Synchronises `stream`. Any pointer may be NULL. */
+fr_status fracture_residual_norms(fr_system sys, double* norms, int64_t* n_active,
+                                  int64_t* active_changes, double* min_margin, void* stream);
+
+/* Device copies of the system vectors (any pointer may be NULL): R[n_solve] residual,
+ * F[n_solve] masked right-hand side, B[n_free] lumped phi mass, active[n_free] (0/1). */
+fr_status fracture_system_vectors(fr_system sys, double* R, double* F, double* B, uint8_t* active,
+                                  void* stream);
+
+/* Installs an active set (device, n_free bytes of 0/1) for the next FR_JACOBIAN stage. */
+fr_status fracture_set_active(fr_system sys, const uint8_t* active, void* stream);
+
+/* y = J x with the masked Jacobian (device vectors of n_solve entries). */
+fr_status fracture_matvec(fr_system sys, const double* x, double* y, void* stream);
+
+/* Masked Jacobian as scalar CSR in solve order, host arrays: row_ptr[n_solve+1],
+ * col[nnz], val[nnz] with nnz from a first call with col == NULL (it sets *nnz).
+ * Explicit zeros of masked entries are kept. Synchronises `stream`. */
+fr_status fracture_system_csr(fr_system sys, int64_t* nnz, int64_t* row_ptr, int32_t* col,
+                              double* val, void* stream);
+
+void fracture_system_destroy(fr_system sys);
+
+/* ---- AMG and solve ---------------------------------------------------------------- */
+
+/* Builds the block-diagonal preconditioner P^-1 = diag(M_uu~^-1, M_phiphi~^-1) of
+ * Section 3: one smoothed-aggregation hierarchy per diagonal block of the masked
+ * Jacobian (strength graph, MIS-2 aggregation, tentative prolongator from the rigid-body
+ * modes (u) or constants (phi), damped-Jacobi prolongator smoothing, Galerkin R A P),
+ * Chebyshev smoothers and a dense coarsest-level inverse. *amg == NULL creates it,
+ * otherwise it is rebuilt in place. The host synchronises `stream` between levels. */
+fr_status amg_setup(fr_system sys, const fr_amg_opts* opts /*host*/, fr_amg* amg, void* stream);
+
+/* Host outputs for hierarchy `block` (0 = u, 1 = phi): number of levels, and for level
+ * `level`: rows, block size, nnz blocks of A, lambda_max estimate. */
+fr_status amg_level_info(fr_amg amg, int block, int level, int* n_levels, int64_t* rows,
+                         int* bsize, int64_t* nnz_blocks, double* lambda_max);
+
+/* Level operator `which` (0 = A, 1 = P, 2 = R) of hierarchy `block` as scalar CSR, host
+ * arrays, two-call protocol as fracture_system_csr. FP64 values. */
+fr_status amg_level_csr(fr_amg amg, int block, int level, int which, int64_t* n_rows,
+                        int64_t* n_cols, int64_t* nnz, int64_t* row_ptr, int32_t* col,
+                        double* val, void* stream);
+
+/* z = P^-1 r: one V-cycle per diagonal block (device vectors of n_solve entries). */
+fr_status amg_apply(fr_amg amg, const double* r, double* z, void* stream);
+
+void amg_destroy(fr_amg amg);
+
+/* Solves J du = F (masked system) by FGMRES with the AMG preconditioner. du: device,
+ * n_solve. stats: host. Synchronises `stream` once per iteration (convergence check).
+ * FR_ENOCONV is returned with du and stats filled when maxit is reached. */
+fr_status fracture_solve(fr_system sys, fr_amg amg, const fr_solve_opts* opts /*host*/,
+                         double* du, fr_solve_stats* stats, void* stream);
+
+/* u[free] += omega du_u, phi[free] += omega du_phi, then hanging values interpolated. */
+fr_status fracture_update(fr_mesh mesh, const double* du, double omega, double* u, double* phi,
+                          void* stream);
+
+/* The Newton / active-set loop of one loading step (Section 3 algorithm): assemble,
+ * active set, masked Jacobian, AMG setup, FGMRES, line search, stop test, with the cycle
+ * freeze of alternating active-set entries. u and phi are updated in place (device).
+ * amg_opts / solve_opts / newton_opts / stats: host. */
+fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double* phi,
+                          const double* phi_old, const double* phi_tilde,
+                          const fr_amg_opts* amg_opts, const fr_solve_opts* solve_opts,
+                          const fr_newton_opts* newton_opts, fr_newton_stats* stats,
+                          void* stream);
+
+/* ---- functionals (Section 4) ------------------------------------------------------ */
+
+/* tcv (host, 1 value) = integral over B of u . grad phi. cod (host, n_cod values):
+ * cod[i] = 1/2 integral of u . grad phi along the line through cod_x[i*(dim-1) ..] parallel
+ * to the last axis (cod_x: host). Either output may be NULL. Synchronises `stream`. */
+fr_status fracture_functionals(fr_mesh mesh, const double* u, const double* phi,
+                               const double* cod_x, int n_cod, double* cod, double* tcv,
+                               void* stream);
+
+/* ---- misc ------------------------------------------------------------------------- */
+
+const char* fracture_last_error(void);
+/* Checks that a gfx950 device is current; FR_EDEVICE otherwise. */
+fr_status fracture_device_check(void);
+const char* fracture_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FRACTURE_H */

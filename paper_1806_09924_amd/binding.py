@@ -1,0 +1,363 @@
+"""ctypes binding of libfracture.so (include/fracture.h).  Argument marshalling only: every
+step of the computation runs in the library's HIP kernels.  Device arrays are torch
+tensors on the current HIP device; calls are ordered on torch's current stream.
+
+The library must have been built (python -m paper_1806_09924_amd.build); importing this
+module without it raises, there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfracture.so")
+
+FR_OK, FR_EINVAL, FR_ENOMEM, FR_EDEVICE, FR_ENOCONV, FR_EBREAKDOWN, FR_ENAN, FR_ECYCLE, FR_EINTERNAL = range(9)
+STATUS_NAMES = ["FR_OK", "FR_EINVAL", "FR_ENOMEM", "FR_EDEVICE", "FR_ENOCONV", "FR_EBREAKDOWN", "FR_ENAN",
+                "FR_ECYCLE", "FR_EINTERNAL"]
+FR_RESIDUAL, FR_ACTIVE_SET, FR_JACOBIAN = 1, 2, 4
+
+c_double3 = ctypes.c_double * 3
+c_int3 = ctypes.c_int * 3
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("lo", c_double3), ("hi", c_double3), ("base", c_int3),
+                ("levels", ctypes.c_int), ("refine_radius", ctypes.c_double),
+                ("crack_center", c_double3), ("crack_half_len", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("E", "nu", "Gc", "kappa", "eps", "p", "c_pdas", "tau_pdas")]
+
+
+class AmgOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("theta", ctypes.c_double), ("cheb_degree", ctypes.c_int),
+                ("cheb_ratio", ctypes.c_double), ("coarse_max", ctypes.c_int), ("max_levels", ctypes.c_int)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("relres", ctypes.c_double), ("status", ctypes.c_int)]
+
+
+class NewtonOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_it", ctypes.c_int), ("ls_max", ctypes.c_int)]
+
+
+class NewtonStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("linear_iters", ctypes.c_int), ("res0", ctypes.c_double),
+                ("res", ctypes.c_double), ("n_active", ctypes.c_int64), ("status", ctypes.c_int),
+                ("t_assemble", ctypes.c_double), ("t_setup", ctypes.c_double), ("t_solve", ctypes.c_double),
+                ("t_other", ctypes.c_double)]
+
+
+class FractureError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 9 else status}: {msg}")
+        self.status = status
+
+
+_P = ctypes.c_void_p
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_DP = ctypes.POINTER(ctypes.c_double)
+
+_SIGNATURES = {
+    "fracture_mesh_create": [ctypes.POINTER(MeshDesc), ctypes.POINTER(_P), _P],
+    "fracture_mesh_info": [_P, _I64P, _I64P, _I64P, _I64P, _I64P, _I64P, _DP, _I64P],
+    "fracture_mesh_nodes": [_P, _P, _P, _P, _P],
+    "fracture_mesh_create_host": [ctypes.POINTER(MeshDesc), ctypes.POINTER(_P)],
+    "fracture_mesh_cells": [_P, _P, _P, _P],
+    "fracture_mesh_constraints": [_P, _I64P, _P, _P, _P],
+    "fracture_mesh_destroy": [_P],
+    "fracture_assemble": [_P, ctypes.POINTER(Params), _P, _P, _P, _P, ctypes.c_uint, ctypes.POINTER(_P), _P],
+    "fracture_residual_norms": [_P, _DP, _I64P, _I64P, _DP, _P],
+    "fracture_system_vectors": [_P, _P, _P, _P, _P, _P],
+    "fracture_set_active": [_P, _P, _P],
+    "fracture_matvec": [_P, _P, _P, _P],
+    "fracture_system_csr": [_P, _I64P, _P, _P, _P, _P],
+    "fracture_system_destroy": [_P],
+    "amg_setup": [_P, ctypes.POINTER(AmgOpts), ctypes.POINTER(_P), _P],
+    "amg_level_info": [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _I64P,
+                       ctypes.POINTER(ctypes.c_int), _I64P, _DP],
+    "amg_level_csr": [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I64P, _I64P, _I64P, _P, _P, _P, _P],
+    "amg_apply": [_P, _P, _P, _P],
+    "amg_destroy": [_P],
+    "fracture_solve": [_P, _P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(SolveStats), _P],
+    "fracture_update": [_P, _P, ctypes.c_double, _P, _P, _P],
+    "fracture_newton": [_P, ctypes.POINTER(Params), _P, _P, _P, _P, ctypes.POINTER(AmgOpts),
+                        ctypes.POINTER(SolveOpts), ctypes.POINTER(NewtonOpts), ctypes.POINTER(NewtonStats), _P],
+    "fracture_functionals": [_P, _P, _P, _P, ctypes.c_int, _P, _P, _P],
+    "fracture_last_error": [],
+    "fracture_device_check": [],
+    "fracture_version": [],
+}
+_VOID = {"fracture_mesh_destroy", "fracture_system_destroy", "amg_destroy"}
+_CHARP = {"fracture_last_error", "fracture_version"}
+
+_lib = None
+
+
+def load():
+    """Loads the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1806_09924_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, args in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = None if name in _VOID else (ctypes.c_char_p if name in _CHARP else ctypes.c_int)
+    _lib = lib
+    return lib
+
+
+def last_error():
+    return load().fracture_last_error().decode()
+
+
+def _check(status):
+    if status != FR_OK:
+        raise FractureError(status, last_error())
+    return status
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype=torch.float64):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"contiguous {dtype} tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def params(E=1.0, nu=0.2, Gc=1.0, kappa=1e-10, eps=1.0 / 16, p=1e-3, c_pdas=1.0, tau_pdas=0.0):
+    return Params(E, nu, Gc, kappa, eps, p, c_pdas, tau_pdas)
+
+
+def amg_opts(precision=64, theta=0.02, cheb_degree=2, cheb_ratio=20.0, coarse_max=500, max_levels=10):
+    return AmgOpts(precision, theta, cheb_degree, cheb_ratio, coarse_max, max_levels)
+
+
+def solve_opts(rtol=1e-8, restart=100, maxit=500):
+    return SolveOpts(rtol, restart, maxit)
+
+
+def newton_opts(tol=1e-8, max_it=30, ls_max=8):
+    return NewtonOpts(tol, max_it, ls_max)
+
+
+def mesh_desc(dim, lo, hi, base, levels=0, refine_radius=0.0, crack_center=(0.0, 0.0, 0.0), crack_half_len=0.0):
+    d = MeshDesc()
+    d.dim = dim
+    for k in range(3):
+        d.lo[k] = lo if k < dim else 0.0
+        d.hi[k] = hi if k < dim else 1.0
+        d.base[k] = base if k < dim else 1
+        d.crack_center[k] = crack_center[k] if k < len(crack_center) else 0.0
+    d.levels = levels
+    d.refine_radius = refine_radius
+    d.crack_half_len = crack_half_len
+    return d
+
+
+class Mesh:
+    def __init__(self, desc, host_only=False):
+        lib = load()
+        h = _P()
+        if host_only:
+            _check(lib.fracture_mesh_create_host(ctypes.byref(desc), ctypes.byref(h)))
+        else:
+            _check(lib.fracture_mesh_create(ctypes.byref(desc), ctypes.byref(h), _stream()))
+        self.h = h
+        self.desc = desc
+        vals = [ctypes.c_int64() for _ in range(6)]
+        hmin = ctypes.c_double()
+        nnz = ctypes.c_int64()
+        _check(lib.fracture_mesh_info(h, *[ctypes.byref(v) for v in vals], ctypes.byref(hmin), ctypes.byref(nnz)))
+        (self.n_nodes, self.n_cells, self.n_free, self.n_all, self.n_solve, self.n_hanging) = [v.value for v in vals]
+        self.h_min = hmin.value
+        self.nnz_graph = nnz.value
+        self.dim = desc.dim
+
+    def nodes(self):
+        xyz = np.zeros((self.n_nodes, self.dim))
+        lat = np.zeros((self.n_nodes, self.dim), dtype=np.int64)
+        dirichlet = np.zeros(self.n_nodes, dtype=np.uint8)
+        free = np.zeros(self.n_nodes, dtype=np.int32)
+        _check(load().fracture_mesh_nodes(self.h, xyz.ctypes.data_as(_P), lat.ctypes.data_as(_P),
+                                          dirichlet.ctypes.data_as(_P), free.ctypes.data_as(_P)))
+        return xyz, lat, dirichlet, free
+
+    def cells(self):
+        nv = 1 << self.dim
+        cells = np.zeros((self.n_cells, nv), dtype=np.int32)
+        lo = np.zeros((self.n_cells, self.dim))
+        h = np.zeros(self.n_cells)
+        _check(load().fracture_mesh_cells(self.h, cells.ctypes.data_as(_P), lo.ctypes.data_as(_P),
+                                          h.ctypes.data_as(_P)))
+        return cells, lo, h
+
+    def constraints(self):
+        lib = load()
+        n = ctypes.c_int64()
+        _check(lib.fracture_mesh_constraints(self.h, ctypes.byref(n), None, None, None))
+        ptr = np.zeros(self.n_nodes + 1, dtype=np.int32)
+        mas = np.zeros(n.value, dtype=np.int32)
+        w = np.zeros(n.value)
+        _check(lib.fracture_mesh_constraints(self.h, ctypes.byref(n), ptr.ctypes.data_as(_P), mas.ctypes.data_as(_P),
+                                             w.ctypes.data_as(_P)))
+        return ptr, mas, w
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.fracture_mesh_destroy(self.h)
+            self.h = None
+
+
+class System:
+    def __init__(self, mesh):
+        self.mesh = mesh
+        self.h = _P()
+
+    def assemble(self, prm, u, phi, phi_old, phi_tilde, flags=FR_RESIDUAL | FR_ACTIVE_SET | FR_JACOBIAN):
+        _check(load().fracture_assemble(self.mesh.h, ctypes.byref(prm), _ptr(u), _ptr(phi), _ptr(phi_old),
+                                        _ptr(phi_tilde), flags, ctypes.byref(self.h), _stream()))
+        return self
+
+    def norms(self):
+        nr = (ctypes.c_double * 2)()
+        na, ch = ctypes.c_int64(), ctypes.c_int64()
+        mm = ctypes.c_double()
+        _check(load().fracture_residual_norms(self.h, nr, ctypes.byref(na), ctypes.byref(ch), ctypes.byref(mm),
+                                              _stream()))
+        return dict(res=nr[0], rhs=nr[1], n_active=na.value, changes=ch.value, min_margin=mm.value)
+
+    def vectors(self):
+        m = self.mesh
+        dev = torch.device("cuda")
+        R = torch.empty(m.n_solve, dtype=torch.float64, device=dev)
+        F = torch.empty_like(R)
+        B = torch.empty(m.n_free, dtype=torch.float64, device=dev)
+        act = torch.empty(m.n_free, dtype=torch.uint8, device=dev)
+        _check(load().fracture_system_vectors(self.h, _ptr(R), _ptr(F), _ptr(B), _ptr(act, torch.uint8), _stream()))
+        return R, F, B, act
+
+    def set_active(self, active):
+        _check(load().fracture_set_active(self.h, _ptr(active, torch.uint8), _stream()))
+
+    def matvec(self, x, y):
+        _check(load().fracture_matvec(self.h, _ptr(x), _ptr(y), _stream()))
+
+    def csr(self):
+        lib = load()
+        nnz = ctypes.c_int64()
+        _check(lib.fracture_system_csr(self.h, ctypes.byref(nnz), None, None, None, _stream()))
+        n = self.mesh.n_solve
+        rp = np.zeros(n + 1, dtype=np.int64)
+        ci = np.zeros(nnz.value, dtype=np.int32)
+        vv = np.zeros(nnz.value)
+        _check(lib.fracture_system_csr(self.h, ctypes.byref(nnz), rp.ctypes.data_as(_P), ci.ctypes.data_as(_P),
+                                       vv.ctypes.data_as(_P), _stream()))
+        return rp, ci[:nnz.value], vv[:nnz.value]
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and self.h.value and _lib is not None:
+            _lib.fracture_system_destroy(self.h)
+            self.h = None
+
+
+class Amg:
+    def __init__(self, system, opts=None):
+        self.system = system
+        self.h = _P()
+        self.setup(opts)
+
+    def setup(self, opts=None):
+        o = opts if opts is not None else amg_opts()
+        _check(load().amg_setup(self.system.h, ctypes.byref(o), ctypes.byref(self.h), _stream()))
+        return self
+
+    def level_info(self, block, level):
+        nl, bs = ctypes.c_int(), ctypes.c_int()
+        rows, nz = ctypes.c_int64(), ctypes.c_int64()
+        lm = ctypes.c_double()
+        _check(load().amg_level_info(self.h, block, level, ctypes.byref(nl), ctypes.byref(rows), ctypes.byref(bs),
+                                     ctypes.byref(nz), ctypes.byref(lm)))
+        return dict(n_levels=nl.value, rows=rows.value, bsize=bs.value, nnz_blocks=nz.value, lambda_max=lm.value)
+
+    def n_levels(self, block):
+        nl = ctypes.c_int()
+        load().amg_level_info(self.h, block, 0, ctypes.byref(nl), None, None, None, None)
+        return nl.value
+
+    def level_csr(self, block, level, which):
+        lib = load()
+        nr, nc, nnz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.amg_level_csr(self.h, block, level, which, ctypes.byref(nr), ctypes.byref(nc), ctypes.byref(nnz),
+                                 None, None, None, _stream()))
+        rp = np.zeros(nr.value + 1, dtype=np.int64)
+        ci = np.zeros(max(1, nnz.value), dtype=np.int32)
+        vv = np.zeros(max(1, nnz.value))
+        _check(lib.amg_level_csr(self.h, block, level, which, ctypes.byref(nr), ctypes.byref(nc), ctypes.byref(nnz),
+                                 rp.ctypes.data_as(_P), ci.ctypes.data_as(_P), vv.ctypes.data_as(_P), _stream()))
+        return (nr.value, nc.value), rp, ci[:nnz.value], vv[:nnz.value]
+
+    def apply(self, r, z):
+        _check(load().amg_apply(self.h, _ptr(r), _ptr(z), _stream()))
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and self.h.value and _lib is not None:
+            _lib.amg_destroy(self.h)
+            self.h = None
+
+
+def solve(system, amg, du, opts=None, raise_on_noconv=True):
+    st = SolveStats()
+    o = opts if opts is not None else solve_opts()
+    status = load().fracture_solve(system.h, amg.h, ctypes.byref(o), _ptr(du), ctypes.byref(st), _stream())
+    if status != FR_OK and (raise_on_noconv or status != FR_ENOCONV):
+        raise FractureError(status, last_error())
+    return dict(iters=st.iters, relres=st.relres, status=st.status)
+
+
+def update(mesh, du, omega, u, phi):
+    _check(load().fracture_update(mesh.h, _ptr(du), float(omega), _ptr(u), _ptr(phi), _stream()))
+
+
+def newton(mesh, prm, u, phi, phi_old, phi_tilde, amg=None, solve=None, newton=None, raise_on_noconv=True):
+    st = NewtonStats()
+    status = load().fracture_newton(mesh.h, ctypes.byref(prm), _ptr(u), _ptr(phi), _ptr(phi_old), _ptr(phi_tilde),
+                                    ctypes.byref(amg if amg is not None else amg_opts()),
+                                    ctypes.byref(solve if solve is not None else solve_opts()),
+                                    ctypes.byref(newton if newton is not None else newton_opts()),
+                                    ctypes.byref(st), _stream())
+    if status != FR_OK and (raise_on_noconv or status != FR_ENOCONV):
+        raise FractureError(status, last_error())
+    return {f: getattr(st, f) for f, _ in NewtonStats._fields_}
+
+
+def functionals(mesh, u, phi, cod_x=()):
+    cod_x = np.ascontiguousarray(np.asarray(cod_x, dtype=np.float64).reshape(-1, mesh.dim - 1))
+    n = cod_x.shape[0]
+    cod = np.zeros(max(1, n))
+    tcv = ctypes.c_double()
+    _check(load().fracture_functionals(mesh.h, _ptr(u), _ptr(phi), cod_x.ctypes.data_as(_P) if n else None, n,
+                                       cod.ctypes.data_as(_P) if n else None, ctypes.byref(tcv), _stream()))
+    return cod[:n], tcv.value
+
+
+def device_check():
+    return load().fracture_device_check()

@@ -1,0 +1,1140 @@
+// Smoothed-aggregation AMG for the two diagonal blocks of the Newton Jacobian (Section 3:
+// P^-1 = diag(M_uu~^-1, M_phiphi~^-1), each applied as one multigrid V-cycle).  Setup runs
+// on the GPU: strength graph, deterministic MIS(2) aggregation, tentative prolongator by a
+// per-aggregate QR of the near-null space (rigid-body modes for the displacement block,
+// constants for the phase field), damped-Jacobi prolongator smoothing, Galerkin R A P by a
+// two-phase hashed SpGEMM, a power-iteration estimate of lambda_max(D^-1 A) for the
+// Chebyshev smoother and a dense inverse of the coarsest operator.  Every kernel
+// accumulates in a fixed order, so the hierarchy is bitwise reproducible.
+#include <algorithm>
+#include <cmath>
+
+#include "system.h"
+
+namespace fr {
+namespace {
+
+constexpr int kHash = 1024;        // LDS hash slots per wave in the SpGEMM
+constexpr int kWavesPerBlock = 4;  // 256-thread blocks
+constexpr int kDenseMax = 4096;    // largest coarsest level inverted densely
+
+inline int nblk(int64_t n, int t) { return int(ceil_div(n, t)); }
+
+__device__ __forceinline__ int64_t sslot(const int32_t* slice_ptr, int C, int64_t r, int k) {
+    return int64_t(slice_ptr[r / C]) + int64_t(k) * C + (r % C);
+}
+
+// ---- diagonal information ----------------------------------------------------------------
+template <int B>
+__global__ void k_diag(int64_t n, int C, const int32_t* __restrict__ sp, const int32_t* __restrict__ len,
+                       const int32_t* __restrict__ col, const double* __restrict__ val, double* __restrict__ invd,
+                       double* __restrict__ dnorm) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double nr = 0.0;
+    double dg[B];
+    for (int i = 0; i < B; ++i) dg[i] = 0.0;
+    for (int k = 0; k < len[r]; ++k) {
+        const int64_t s = sslot(sp, C, r, k);
+        if (col[s] == r) {
+            for (int i = 0; i < B * B; ++i) nr += val[s * B * B + i] * val[s * B * B + i];
+            for (int i = 0; i < B; ++i) dg[i] = val[s * B * B + i * B + i];
+        }
+    }
+    dnorm[r] = sqrt(nr);
+    for (int i = 0; i < B; ++i) invd[r * B + i] = dg[i] != 0.0 ? 1.0 / dg[i] : 0.0;
+}
+
+// strong[slot] = |A_ij|_F^2 >= theta^2 |A_ii|_F |A_jj|_F (i != j, A_ij != 0)
+template <int B>
+__global__ void k_strength(int64_t n, int C, const int32_t* __restrict__ sp, const int32_t* __restrict__ len,
+                           const int32_t* __restrict__ col, const double* __restrict__ val,
+                           const double* __restrict__ dnorm, double theta, uint8_t* __restrict__ strong,
+                           uint8_t* __restrict__ isolated) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int64_t s0 = r / C;
+    const int w = (sp[s0 + 1] - sp[s0]) / C;
+    int cnt = 0;
+    for (int k = 0; k < w; ++k) {
+        const int64_t s = sslot(sp, C, r, k);
+        uint8_t st = 0;
+        if (k < len[r]) {
+            const int64_t c = col[s];
+            if (c != r) {
+                double a = 0.0;
+                for (int i = 0; i < B * B; ++i) a += val[s * B * B + i] * val[s * B * B + i];
+                st = (a > 0.0 && a >= theta * theta * dnorm[r] * dnorm[c]) ? 1 : 0;
+            }
+        }
+        strong[s] = st;
+        cnt += st;
+    }
+    isolated[r] = cnt == 0 ? 1 : 0;
+}
+
+// ---- MIS(2) aggregation ----------------------------------------------------------------------
+// key = state (2 bits: 2 root, 1 undecided, 0 out) | 30-bit hash | 32-bit index
+__device__ __forceinline__ uint64_t mis_key(uint32_t state, int64_t i) {
+    return (uint64_t(state) << 62) | (uint64_t(hash32(uint32_t(i) * 2654435761u + 97u) & 0x3fffffffu) << 32) |
+           uint64_t(uint32_t(i));
+}
+
+__global__ void k_mis_init(int64_t n, const uint8_t* __restrict__ isolated, uint8_t* __restrict__ state,
+                           uint64_t* __restrict__ key) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint8_t st = isolated[i] ? 0 : 1;
+    state[i] = st;
+    key[i] = mis_key(st, i);
+}
+
+__global__ void k_mis_prop(int64_t n, int C, const int32_t* __restrict__ sp, const int32_t* __restrict__ len,
+                           const int32_t* __restrict__ col, const uint8_t* __restrict__ strong,
+                           const uint64_t* __restrict__ in, uint64_t* __restrict__ out) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    uint64_t m = in[r];
+    for (int k = 0; k < len[r]; ++k) {
+        const int64_t s = sslot(sp, C, r, k);
+        if (strong[s]) m = max(m, in[col[s]]);
+    }
+    out[r] = m;
+}
+
+__global__ void k_mis_update(int64_t n, const uint64_t* __restrict__ m2, uint8_t* __restrict__ state,
+                             uint64_t* __restrict__ key, int32_t* __restrict__ undecided) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (state[i] != 1) return;
+    if (m2[i] == key[i]) {
+        state[i] = 2;
+        key[i] = mis_key(2, i);
+    } else if ((m2[i] >> 62) == 2) {
+        state[i] = 0;
+        key[i] = mis_key(0, i);
+    } else {
+        atomicAdd(undecided, 1);
+    }
+}
+
+__global__ void k_root_flags(int64_t n, const uint8_t* __restrict__ state, int32_t* __restrict__ flag) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = state[i] == 2 ? 1 : 0;
+}
+
+// phase 1: roots take their rank; neighbours of roots join the adjacent root with the largest key
+__global__ void k_agg_phase1(int64_t n, int C, const int32_t* __restrict__ sp, const int32_t* __restrict__ len,
+                             const int32_t* __restrict__ col, const uint8_t* __restrict__ strong,
+                             const uint8_t* __restrict__ state, const uint64_t* __restrict__ key,
+                             const int32_t* __restrict__ rank, int32_t* __restrict__ agg) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    if (state[r] == 2) { agg[r] = rank[r]; return; }
+    uint64_t best = 0;
+    int32_t a = -1;
+    for (int k = 0; k < len[r]; ++k) {
+        const int64_t s = sslot(sp, C, r, k);
+        const int32_t c = col[s];
+        if (strong[s] && state[c] == 2 && key[c] > best) { best = key[c]; a = rank[c]; }
+    }
+    agg[r] = a;
+}
+
+// phase 2: remaining non-isolated nodes join the phase-1 neighbour with the largest key
+__global__ void k_agg_phase2(int64_t n, int C, const int32_t* __restrict__ sp, const int32_t* __restrict__ len,
+                             const int32_t* __restrict__ col, const uint8_t* __restrict__ strong,
+                             const uint8_t* __restrict__ isolated, const uint64_t* __restrict__ key,
+                             const int32_t* __restrict__ agg1, int32_t* __restrict__ agg2) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int32_t a = agg1[r];
+    if (a < 0 && !isolated[r]) {
+        uint64_t best = 0;
+        for (int k = 0; k < len[r]; ++k) {
+            const int64_t s = sslot(sp, C, r, k);
+            const int32_t c = col[s];
+            const uint64_t kc = key[c] & 0x3fffffffffffffffull;
+            if (strong[s] && agg1[c] >= 0 && kc >= best) { best = kc; a = agg1[c]; }
+        }
+    }
+    agg2[r] = a;
+}
+
+__global__ void k_orphan_flags(int64_t n, const uint8_t* __restrict__ isolated, const int32_t* __restrict__ agg,
+                               int32_t* __restrict__ flag) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = (agg[i] < 0 && !isolated[i]) ? 1 : 0;
+}
+
+__global__ void k_orphan_assign(int64_t n, const int32_t* __restrict__ flag, const int32_t* __restrict__ rank,
+                                int32_t base, int32_t* __restrict__ agg) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n && flag[i]) agg[i] = base + rank[i];
+}
+
+__global__ void k_agg_count(int64_t n, const int32_t* __restrict__ agg, int32_t* __restrict__ cnt) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n && agg[i] >= 0) atomicAdd(&cnt[agg[i]], 1);
+}
+
+__global__ void k_agg_fill(int64_t n, const int32_t* __restrict__ agg, const int32_t* __restrict__ ptr,
+                           int32_t* __restrict__ fillc, int32_t* __restrict__ nodes) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n && agg[i] >= 0) {
+        const int32_t p = atomicAdd(&fillc[agg[i]], 1);
+        nodes[ptr[agg[i]] + p] = int32_t(i);
+    }
+}
+
+__global__ void k_agg_sort(int64_t na, const int32_t* __restrict__ ptr, int32_t* __restrict__ nodes) {
+    const int64_t a = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (a >= na) return;
+    const int32_t b = ptr[a], e = ptr[a + 1];
+    for (int32_t i = b + 1; i < e; ++i) {
+        const int32_t v = nodes[i];
+        int32_t j = i - 1;
+        while (j >= b && nodes[j] > v) { nodes[j + 1] = nodes[j]; --j; }
+        nodes[j + 1] = v;
+    }
+}
+
+// ---- tentative prolongator ----------------------------------------------------------------
+// Near-null-space row (dof c of node i) at level 0 in aggregate-centred coordinates.
+template <int BR, int NS>
+__device__ __forceinline__ double nullspace0(int c, int j, const double* x, const double* xc) {
+    if (NS == 1) return 1.0;
+    if (j < BR) return c == j ? 1.0 : 0.0;
+    if (BR == 2) {   // rotation about z: (-(y - yc), x - xc)
+        return c == 0 ? -(x[1] - xc[1]) : (x[0] - xc[0]);
+    }
+    // 3d: rot_z (-y, x, 0), rot_x (0, -z, y), rot_y (z, 0, -x), centred
+    const double dx = x[0] - xc[0], dy = x[1] - xc[1], dz = x[2] - xc[2];
+    if (j == 3) return c == 0 ? -dy : (c == 1 ? dx : 0.0);
+    if (j == 4) return c == 0 ? 0.0 : (c == 1 ? -dz : dy);
+    return c == 0 ? dz : (c == 1 ? 0.0 : -dx);
+}
+
+// One thread per aggregate: QR (classical Gram-Schmidt, twice) of the aggregate's
+// near-null-space rows.  Q goes to the tentative prolongator, R (times the change of
+// basis back to global coordinates at level 0) is the coarse near-null space.
+template <int BR, int NS, bool LEVEL0>
+__global__ void k_tentative(int64_t na, const int32_t* __restrict__ aptr, const int32_t* __restrict__ anodes,
+                            const double* __restrict__ coords, int dim, const double* __restrict__ Bf,
+                            int C, const int32_t* __restrict__ psp, double* __restrict__ pval,
+                            double* __restrict__ Bc) {
+    const int64_t a = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (a >= na) return;
+    const int32_t b0 = aptr[a], b1 = aptr[a + 1];
+    double xc[3] = {0, 0, 0};
+    if (LEVEL0 && NS > 1) {
+        for (int32_t t = b0; t < b1; ++t)
+            for (int k = 0; k < dim; ++k) xc[k] += coords[int64_t(anodes[t]) * dim + k];
+        for (int k = 0; k < dim; ++k) xc[k] /= double(b1 - b0);
+    }
+    double Rm[NS][NS];
+    for (int i = 0; i < NS; ++i)
+        for (int j = 0; j < NS; ++j) Rm[i][j] = 0.0;
+    auto qslot = [&](int64_t node) -> double* {
+        return pval + (int64_t(psp[node / C]) + (node % C)) * (BR * NS);
+    };
+    for (int j = 0; j < NS; ++j) {
+        // column j of the local near-null space
+        double nrm0 = 0.0;
+        for (int32_t t = b0; t < b1; ++t) {
+            const int64_t node = anodes[t];
+            double* q = qslot(node);
+            for (int c = 0; c < BR; ++c) {
+                double v;
+                if (LEVEL0) v = nullspace0<BR, NS>(c, j, coords + node * dim, xc);
+                else v = Bf[(node * BR + c) * NS + j];
+                q[c * NS + j] = v;
+                nrm0 += v * v;
+            }
+        }
+        nrm0 = sqrt(nrm0);
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int i = 0; i < j; ++i) {
+                double dot = 0.0;
+                for (int32_t t = b0; t < b1; ++t) {
+                    const double* q = qslot(anodes[t]);
+                    for (int c = 0; c < BR; ++c) dot += q[c * NS + i] * q[c * NS + j];
+                }
+                Rm[i][j] += dot;
+                for (int32_t t = b0; t < b1; ++t) {
+                    double* q = qslot(anodes[t]);
+                    for (int c = 0; c < BR; ++c) q[c * NS + j] -= dot * q[c * NS + i];
+                }
+            }
+        }
+        double nrm = 0.0;
+        for (int32_t t = b0; t < b1; ++t) {
+            const double* q = qslot(anodes[t]);
+            for (int c = 0; c < BR; ++c) nrm += q[c * NS + j] * q[c * NS + j];
+        }
+        nrm = sqrt(nrm);
+        const bool keep = nrm > 1e-10 * nrm0 && nrm > 0.0;
+        Rm[j][j] = keep ? nrm : 0.0;
+        const double sc = keep ? 1.0 / nrm : 0.0;
+        for (int32_t t = b0; t < b1; ++t) {
+            double* q = qslot(anodes[t]);
+            for (int c = 0; c < BR; ++c) q[c * NS + j] *= sc;
+        }
+        if (!keep)
+            for (int i = 0; i < j; ++i) Rm[i][j] = 0.0;
+    }
+    // coarse near-null space: R T (T maps centred to global rotations at level 0)
+    double T[NS][NS];
+    for (int i = 0; i < NS; ++i)
+        for (int j = 0; j < NS; ++j) T[i][j] = i == j ? 1.0 : 0.0;
+    if (LEVEL0 && NS == 3) {
+        T[0][2] = -xc[1];
+        T[1][2] = xc[0];
+    } else if (LEVEL0 && NS == 6) {
+        T[0][3] = -xc[1]; T[1][3] = xc[0];
+        T[1][4] = -xc[2]; T[2][4] = xc[1];
+        T[0][5] = xc[2];  T[2][5] = -xc[0];
+    }
+    for (int i = 0; i < NS; ++i)
+        for (int j = 0; j < NS; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < NS; ++k) v += Rm[i][k] * T[k][j];
+            Bc[(a * NS + i) * NS + j] = v;
+        }
+}
+
+__global__ void k_ptent_struct(int64_t n, const int32_t* __restrict__ agg, int32_t* __restrict__ len) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) len[i] = agg[i] >= 0 ? 1 : 0;
+}
+
+__global__ void k_ptent_cols(int64_t n, int C, const int32_t* __restrict__ sp, const int32_t* __restrict__ agg,
+                             int32_t* __restrict__ col, double* __restrict__ val, int bb) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t s0 = i / C;
+    const int w = (sp[s0 + 1] - sp[s0]) / C;
+    for (int k = 0; k < w; ++k) {
+        const int64_t s = sslot(sp, C, i, k);
+        col[s] = (k == 0 && agg[i] >= 0) ? agg[i] : 0;
+        for (int e = 0; e < bb; ++e) val[s * bb + e] = 0.0;
+    }
+}
+
+// ---- SpGEMM ----------------------------------------------------------------------------------
+struct SellV {
+    int C;
+    int64_t n_rows;
+    const int32_t* sp;
+    const int32_t* len;
+    const int32_t* col;
+};
+
+SellV sv(const SellStruct& S) { return SellV{S.C, S.n_rows, S.slice_ptr, S.row_len, S.col}; }
+
+__device__ __forceinline__ bool hash_insert(int32_t* tab, int32_t c, int& cnt) {
+    uint32_t h = hash32(uint32_t(c)) & (kHash - 1);
+    for (int probe = 0; probe < kHash; ++probe) {
+        const int32_t old = atomicCAS(&tab[h], -1, c);
+        if (old == -1) { cnt++; return true; }
+        if (old == c) return true;
+        h = (h + 1) & (kHash - 1);
+    }
+    return false;
+}
+
+// Builds the hash set of the columns of row r of A*B in this wave's LDS table.
+__device__ void spgemm_row_set(const SellV& A, const SellV& B, int64_t r, int32_t* tab, int lane, int& added,
+                               int* overflow) {
+    for (int i = lane; i < kHash; i += kWave) tab[i] = -1;
+    __syncthreads();
+    if (r < A.n_rows) {
+        const int la = A.len[r];
+        for (int ka = lane; ka < la; ka += kWave) {
+            const int64_t k = A.col[sslot(A.sp, A.C, r, ka)];
+            const int lb = B.len[k];
+            for (int kb = 0; kb < lb; ++kb) {
+                const int32_t c = B.col[sslot(B.sp, B.C, k, kb)];
+                if (!hash_insert(tab, c, added)) { atomicOr(overflow, 1); break; }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_spgemm_count(SellV A, SellV B, int32_t* __restrict__ clen,
+                                                      int* __restrict__ overflow) {
+    __shared__ int32_t tab[kWavesPerBlock][kHash];
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t r = int64_t(blockIdx.x) * kWavesPerBlock + w;
+    int added = 0;
+    spgemm_row_set(A, B, r, tab[w], lane, added, overflow);
+    const int tot = wave_sum_int(added);
+    if (r < A.n_rows && lane == 0) {
+        clen[r] = tot;
+        if (tot > (kHash * 3) / 4) atomicOr(overflow, 1);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_spgemm_fill(SellV A, SellV B, SellV Cm, int32_t* __restrict__ ccol,
+                                                     int* __restrict__ overflow) {
+    __shared__ int32_t tab[kWavesPerBlock][kHash];
+    __shared__ int32_t lst[kWavesPerBlock][kHash];
+    __shared__ int32_t nl[kWavesPerBlock];
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t r = int64_t(blockIdx.x) * kWavesPerBlock + w;
+    int added = 0;
+    if (lane == 0) nl[w] = 0;
+    spgemm_row_set(A, B, r, tab[w], lane, added, overflow);
+    for (int i = lane; i < kHash; i += kWave) {
+        const int32_t v = tab[w][i];
+        if (v >= 0) lst[w][atomicAdd(&nl[w], 1)] = v;
+    }
+    __syncthreads();
+    if (r >= A.n_rows) return;
+    const int n = nl[w];
+    const int64_t s0 = r / Cm.C;
+    const int width = (Cm.sp[s0 + 1] - Cm.sp[s0]) / Cm.C;
+    int32_t first = -1;
+    for (int i = lane; i < n; i += kWave) {
+        const int32_t v = lst[w][i];
+        int rk = 0;
+        for (int j = 0; j < n; ++j) rk += lst[w][j] < v;
+        ccol[sslot(Cm.sp, Cm.C, r, rk)] = v;
+        if (rk == 0) first = v;
+    }
+    // padding slots repeat the first column
+    int32_t f = first;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) f = max(f, __shfl_xor(f, o));
+    if (f < 0) f = 0;
+    for (int k = n + lane; k < width; k += kWave) ccol[sslot(Cm.sp, Cm.C, r, k)] = f;
+}
+
+__device__ __forceinline__ int find_sorted(const SellV& B, int64_t row, int32_t c) {
+    int lo = 0, hi = B.len[row] - 1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int32_t v = B.col[sslot(B.sp, B.C, row, mid)];
+        if (v == c) return mid;
+        if (v < c) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+// C = A B (MODE 0) or C = B - omega D^-1 A B with B indexed by A's rows (MODE 1, smoothing).
+template <int BRA, int BCA, int BCB, int MODE>
+__global__ void __launch_bounds__(256) k_spgemm_numeric(SellV A, const double* __restrict__ av, SellV B,
+                                                        const double* __restrict__ bv, SellV Cm,
+                                                        double* __restrict__ cv, const double* __restrict__ invd,
+                                                        double omega) {
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t r = int64_t(blockIdx.x) * kWavesPerBlock + w;
+    if (r >= Cm.n_rows) return;
+    const int lc = Cm.len[r];
+    const int64_t s0 = r / Cm.C;
+    const int width = (Cm.sp[s0 + 1] - Cm.sp[s0]) / Cm.C;
+    const int la = A.len[r];
+    for (int kc = lane; kc < width; kc += kWave) {
+        const int64_t cs = sslot(Cm.sp, Cm.C, r, kc);
+        double acc[BRA][BCB];
+        for (int i = 0; i < BRA; ++i)
+            for (int j = 0; j < BCB; ++j) acc[i][j] = 0.0;
+        if (kc < lc) {
+            const int32_t c = Cm.col[cs];
+            for (int ka = 0; ka < la; ++ka) {
+                const int64_t as = sslot(A.sp, A.C, r, ka);
+                const int64_t k = A.col[as];
+                const int kb = find_sorted(B, k, c);
+                if (kb < 0) continue;
+                const double* ab = av + as * (BRA * BCA);
+                const double* bb = bv + sslot(B.sp, B.C, k, kb) * (BCA * BCB);
+                for (int i = 0; i < BRA; ++i)
+                    for (int t = 0; t < BCA; ++t) {
+                        const double x = ab[i * BCA + t];
+                        for (int j = 0; j < BCB; ++j) acc[i][j] += x * bb[t * BCB + j];
+                    }
+            }
+            if (MODE == 1) {
+                const int kb = find_sorted(B, r, c);
+                for (int i = 0; i < BRA; ++i) {
+                    const double dsc = omega * invd[r * BRA + i];
+                    for (int j = 0; j < BCB; ++j) {
+                        const double own = kb >= 0 ? bv[sslot(B.sp, B.C, r, kb) * (BCA * BCB) + i * BCB + j] : 0.0;
+                        acc[i][j] = own - dsc * acc[i][j];
+                    }
+                }
+            }
+        }
+        for (int i = 0; i < BRA; ++i)
+            for (int j = 0; j < BCB; ++j) cv[cs * (BRA * BCB) + i * BCB + j] = acc[i][j];
+    }
+}
+
+// ---- transpose -------------------------------------------------------------------------------
+__global__ void k_col_count(SellV P, int32_t* __restrict__ cnt) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= P.n_rows) return;
+    for (int k = 0; k < P.len[r]; ++k) atomicAdd(&cnt[P.col[sslot(P.sp, P.C, r, k)]], 1);
+}
+
+template <int BR, int BC>
+__global__ void k_transpose_fill(SellV P, const double* __restrict__ pv, SellV Rm, int32_t* __restrict__ fillc,
+                                 int32_t* __restrict__ rcol, double* __restrict__ rv) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= P.n_rows) return;
+    for (int k = 0; k < P.len[r]; ++k) {
+        const int64_t ps = sslot(P.sp, P.C, r, k);
+        const int32_t c = P.col[ps];
+        const int pos = atomicAdd(&fillc[c], 1);
+        const int64_t rs = sslot(Rm.sp, Rm.C, c, pos);
+        rcol[rs] = int32_t(r);
+        for (int i = 0; i < BR; ++i)
+            for (int j = 0; j < BC; ++j) rv[rs * (BR * BC) + j * BR + i] = pv[ps * (BR * BC) + i * BC + j];
+    }
+}
+
+// sort each row of R by column (insertion sort, values move with the columns); zero padding
+template <int BB>
+__global__ void k_sort_rows(SellV Rm, int32_t* __restrict__ col, double* __restrict__ val) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= Rm.n_rows) return;
+    const int n = Rm.len[r];
+    for (int i = 1; i < n; ++i) {
+        const int64_t si = sslot(Rm.sp, Rm.C, r, i);
+        const int32_t c = col[si];
+        double v[BB];
+        for (int e = 0; e < BB; ++e) v[e] = val[si * BB + e];
+        int j = i - 1;
+        while (j >= 0 && col[sslot(Rm.sp, Rm.C, r, j)] > c) {
+            const int64_t sj = sslot(Rm.sp, Rm.C, r, j), sj1 = sslot(Rm.sp, Rm.C, r, j + 1);
+            col[sj1] = col[sj];
+            for (int e = 0; e < BB; ++e) val[sj1 * BB + e] = val[sj * BB + e];
+            --j;
+        }
+        const int64_t sd = sslot(Rm.sp, Rm.C, r, j + 1);
+        col[sd] = c;
+        for (int e = 0; e < BB; ++e) val[sd * BB + e] = v[e];
+    }
+    const int64_t s0 = r / Rm.C;
+    const int width = (Rm.sp[s0 + 1] - Rm.sp[s0]) / Rm.C;
+    const int32_t f = n > 0 ? col[sslot(Rm.sp, Rm.C, r, 0)] : 0;
+    for (int k = n; k < width; ++k) {
+        const int64_t s = sslot(Rm.sp, Rm.C, r, k);
+        col[s] = f;
+        for (int e = 0; e < BB; ++e) val[s * BB + e] = 0.0;
+    }
+}
+
+// ---- power iteration for lambda_max(D^-1 A) ------------------------------------------------
+__global__ void k_power_init(int64_t n, double* __restrict__ x) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.5 + double(hash32(uint32_t(i) ^ 0x9e3779b9u) & 0xffffu) / 65536.0;
+}
+
+__global__ void k_normalize(int64_t n, const double* __restrict__ nrm2, double* __restrict__ x) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) x[i] *= *nrm2 > 0.0 ? 1.0 / sqrt(*nrm2) : 0.0;
+}
+
+__global__ void k_normalize_copy(int64_t n, const double* __restrict__ t, const double* __restrict__ nrm2,
+                                 double* __restrict__ x) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = t[i] * (*nrm2 > 0.0 ? 1.0 / sqrt(*nrm2) : 0.0);
+}
+
+__global__ void k_mul(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ c) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) c[i] = a[i] * b[i];
+}
+
+// ---- dense coarsest level ------------------------------------------------------------------
+template <int B>
+__global__ void k_to_dense(SellV A, const double* __restrict__ av, int64_t n, double* __restrict__ dense) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= A.n_rows) return;
+    for (int k = 0; k < A.len[r]; ++k) {
+        const int64_t s = sslot(A.sp, A.C, r, k);
+        const int64_t c = A.col[s];
+        for (int i = 0; i < B; ++i)
+            for (int j = 0; j < B; ++j) dense[(r * B + i) * n + c * B + j] += av[s * B * B + i * B + j];
+    }
+}
+
+// rows and columns that are entirely zero (rank-deficient coarse DoFs) get a unit diagonal
+__global__ void k_fix_zero_rows(int64_t n, double* __restrict__ dense) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double m = 0.0;
+    for (int64_t j = 0; j < n; ++j) m = fmax(m, fabs(dense[i * n + j]));
+    if (m == 0.0) dense[i * n + i] = 1.0;
+}
+
+// In-place Gauss-Jordan inversion of a symmetric positive (semi)definite matrix without
+// pivoting, one workgroup, matrix in global memory (L2 resident for the sizes used here).
+__global__ void __launch_bounds__(1024) k_gauss_jordan(int64_t n, double* __restrict__ a) {
+    __shared__ double rowk[kDenseMax];
+    for (int64_t k = 0; k < n; ++k) {
+        const double p = a[k * n + k];
+        const double ip = p != 0.0 ? 1.0 / p : 0.0;
+        __syncthreads();
+        for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+            const double v = (j == k) ? ip : a[k * n + j] * ip;
+            rowk[j] = v;
+        }
+        __syncthreads();
+        for (int64_t j = threadIdx.x; j < n; j += blockDim.x) a[k * n + j] = rowk[j];
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            if (i == k) continue;
+            const double f = a[i * n + k];
+            if (f == 0.0) continue;
+            for (int64_t j = 0; j < n; ++j) {
+                if (j == k) a[i * n + j] = -f * ip;
+                else a[i * n + j] -= f * rowk[j];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// x = Ainv b (dense, FP64 arithmetic; vectors in T)
+template <typename T>
+__global__ void __launch_bounds__(256) k_dense_gemv(int64_t n, const double* __restrict__ ainv, const T* __restrict__ b,
+                                                    T* __restrict__ x) {
+    __shared__ double sh[16];
+    const int64_t i = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) acc += ainv[i * n + j] * double(b[j]);
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) x[i] = T(s);
+}
+
+// ---- host-side helpers ---------------------------------------------------------------------
+
+std::shared_ptr<SellStruct> new_struct(int64_t n_rows, int64_t n_cols, hipStream_t s) {
+    auto S = std::make_shared<SellStruct>();
+    S->C = kWave;
+    S->n_rows = n_rows;
+    S->n_cols = n_cols;
+    S->own_len.alloc(size_t(std::max<int64_t>(1, n_rows)), s);
+    S->row_len = S->own_len.p;
+    return S;
+}
+
+void finish_struct(SellStruct& S, hipStream_t s) {
+    layout_from_lengths(S, s);
+    S.own_col.alloc(size_t(std::max<int64_t>(1, S.n_slots)), s);
+    S.col = S.own_col.p;
+}
+
+#define FR_SPGEMM_CASE(BRA_, BCA_, BCB_)                                                                   \
+    if (A.br == BRA_ && A.bc == BCA_ && B.bc == BCB_) {                                                    \
+        k_spgemm_numeric<BRA_, BCA_, BCB_, MODE><<<g, 256, 0, s>>>(sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), \
+                                                                   Cm.val, invd, omega);                  \
+        FR_LAUNCH_CHECK();                                                                                 \
+        return Cm;                                                                                         \
+    }
+
+template <int MODE>
+BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* invd, double omega, hipStream_t s) {
+    if (A.bc != B.br || A.cols() != B.rows()) fail(FR_EINTERNAL, "spgemm: shape mismatch");
+    BMat<double> Cm;
+    Cm.br = A.br;
+    Cm.bc = B.bc;
+    Cm.S = new_struct(A.rows(), B.cols(), s);
+    DBuf<int> ovf;
+    ovf.alloc(1, s);
+    ovf.zero(s);
+    const int g = nblk(std::max<int64_t>(1, A.rows()), kWavesPerBlock);
+    k_spgemm_count<<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), Cm.S->row_len, ovf.p);
+    FR_LAUNCH_CHECK();
+    if (download1(ovf.p, s)) fail(FR_EINTERNAL, "spgemm: row exceeds the LDS hash capacity");
+    finish_struct(*Cm.S, s);
+    k_spgemm_fill<<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), sv(*Cm.S), Cm.S->col, ovf.p);
+    FR_LAUNCH_CHECK();
+    // nnz (block) for reporting
+    Cm.own_val.alloc(size_t(std::max<int64_t>(1, Cm.S->n_slots)) * Cm.br * Cm.bc, s);
+    Cm.val = Cm.own_val.p;
+    FR_SPGEMM_CASE(1, 1, 1)
+    FR_SPGEMM_CASE(2, 2, 3)
+    FR_SPGEMM_CASE(3, 2, 3)
+    FR_SPGEMM_CASE(3, 3, 3)
+    FR_SPGEMM_CASE(3, 3, 6)
+    FR_SPGEMM_CASE(6, 3, 6)
+    FR_SPGEMM_CASE(6, 6, 6)
+    fail(FR_EINTERNAL, "spgemm: unsupported block shapes");
+}
+#undef FR_SPGEMM_CASE
+
+BMat<double> transpose(const BMat<double>& P, hipStream_t s) {
+    BMat<double> Rm;
+    Rm.br = P.bc;
+    Rm.bc = P.br;
+    Rm.S = new_struct(P.cols(), P.rows(), s);
+    FR_HIP(hipMemsetAsync(Rm.S->row_len, 0, size_t(std::max<int64_t>(1, P.cols())) * sizeof(int32_t), s));
+    k_col_count<<<nblk(P.rows(), 256), 256, 0, s>>>(sv(*P.S), Rm.S->row_len);
+    FR_LAUNCH_CHECK();
+    finish_struct(*Rm.S, s);
+    Rm.own_val.alloc(size_t(std::max<int64_t>(1, Rm.S->n_slots)) * Rm.br * Rm.bc, s);
+    Rm.val = Rm.own_val.p;
+    DBuf<int32_t> fillc;
+    fillc.alloc(size_t(std::max<int64_t>(1, P.cols())), s);
+    fillc.zero(s);
+    const int g = nblk(P.rows(), 256);
+    const int gr = nblk(Rm.rows(), 256);
+#define FR_TR_CASE(BR_, BC_)                                                                                   \
+    if (P.br == BR_ && P.bc == BC_) {                                                                          \
+        k_transpose_fill<BR_, BC_><<<g, 256, 0, s>>>(sv(*P.S), P.val, sv(*Rm.S), fillc.p, Rm.S->col, Rm.val); \
+        FR_LAUNCH_CHECK();                                                                                     \
+        k_sort_rows<BR_ * BC_><<<gr, 256, 0, s>>>(sv(*Rm.S), Rm.S->col, Rm.val);                               \
+        FR_LAUNCH_CHECK();                                                                                     \
+        return Rm;                                                                                             \
+    }
+    FR_TR_CASE(1, 1)
+    FR_TR_CASE(2, 3)
+    FR_TR_CASE(3, 3)
+    FR_TR_CASE(3, 6)
+    FR_TR_CASE(6, 6)
+#undef FR_TR_CASE
+    fail(FR_EINTERNAL, "transpose: unsupported block shape");
+}
+
+int64_t block_nnz(const SellStruct& S, hipStream_t s) {
+    auto len = download(S.row_len, size_t(S.n_rows), s);
+    int64_t t = 0;
+    for (int32_t v : len) t += v;
+    return t;
+}
+
+// lambda_max(D^-1 A) by power iteration from a fixed pseudo-random start vector: with
+// ||x|| = 1, ||D^-1 A x|| approaches lambda_max from below.
+double lambda_max(const BMat<double>& A, const double* invd, hipStream_t s) {
+    const int64_t n = A.rows() * A.br;
+    if (n == 0) return 1.0;
+    DBuf<double> x, y, t, scr, nrm;
+    x.alloc(size_t(n), s);
+    y.alloc(size_t(n), s);
+    t.alloc(size_t(n), s);
+    scr.alloc(1024, s);
+    nrm.alloc(1, s);
+    k_power_init<<<nblk(n, 256), 256, 0, s>>>(n, x.p);
+    FR_LAUNCH_CHECK();
+    dev_dot(x.p, x.p, n, nrm.p, scr, s);
+    k_normalize<<<nblk(n, 256), 256, 0, s>>>(n, nrm.p, x.p);
+    FR_LAUNCH_CHECK();
+    const int iters = 15;
+    for (int it = 0; it < iters; ++it) {
+        spmv(A, x.p, y.p, s);
+        k_mul<<<nblk(n, 256), 256, 0, s>>>(n, invd, y.p, t.p);   // t = D^-1 A x
+        FR_LAUNCH_CHECK();
+        dev_dot(t.p, t.p, n, nrm.p, scr, s);
+        k_normalize_copy<<<nblk(n, 256), 256, 0, s>>>(n, t.p, nrm.p, x.p);
+        FR_LAUNCH_CHECK();
+    }
+    const double lam = std::sqrt(download1(nrm.p, s));
+    return lam > 0 ? lam : 1.0;
+}
+
+}  // namespace
+
+// ---- setup ----------------------------------------------------------------------------------
+
+static void diag_info(const BMat<double>& A, DBuf<double>& invd, DBuf<double>& dnorm, hipStream_t s) {
+    const SellStruct& S = *A.S;
+    invd.alloc(size_t(std::max<int64_t>(1, S.n_rows * A.br)), s);
+    dnorm.alloc(size_t(std::max<int64_t>(1, S.n_rows)), s);
+    const int g = nblk(S.n_rows, 256);
+    switch (A.br) {
+        case 1: k_diag<1><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.row_len, S.col, A.val, invd.p, dnorm.p); break;
+        case 2: k_diag<2><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.row_len, S.col, A.val, invd.p, dnorm.p); break;
+        case 3: k_diag<3><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.row_len, S.col, A.val, invd.p, dnorm.p); break;
+        case 6: k_diag<6><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.row_len, S.col, A.val, invd.p, dnorm.p); break;
+        default: fail(FR_EINTERNAL, "diag: unsupported block size");
+    }
+    FR_LAUNCH_CHECK();
+}
+
+// Aggregation of the block rows of A; returns the number of aggregates, agg[n] (-1 = none).
+static int64_t aggregate(const BMat<double>& A, const double* dnorm, double theta, DBuf<int32_t>& agg, hipStream_t s) {
+    const SellStruct& S = *A.S;
+    const int64_t n = S.n_rows;
+    const int g = nblk(n, 256);
+    DBuf<uint8_t> strong, isolated, state;
+    DBuf<uint64_t> key, m1, m2;
+    strong.alloc(size_t(std::max<int64_t>(1, S.n_slots)), s);
+    isolated.alloc(size_t(n), s);
+    state.alloc(size_t(n), s);
+    key.alloc(size_t(n), s);
+    m1.alloc(size_t(n), s);
+    m2.alloc(size_t(n), s);
+    switch (A.br) {
+        case 1: k_strength<1><<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.row_len, S.col, A.val, dnorm, theta, strong.p, isolated.p); break;
+        case 2: k_strength<2><<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.row_len, S.col, A.val, dnorm, theta, strong.p, isolated.p); break;
+        case 3: k_strength<3><<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.row_len, S.col, A.val, dnorm, theta, strong.p, isolated.p); break;
+        case 6: k_strength<6><<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.row_len, S.col, A.val, dnorm, theta, strong.p, isolated.p); break;
+        default: fail(FR_EINTERNAL, "strength: unsupported block size");
+    }
+    FR_LAUNCH_CHECK();
+    k_mis_init<<<g, 256, 0, s>>>(n, isolated.p, state.p, key.p);
+    FR_LAUNCH_CHECK();
+    DBuf<int32_t> und;
+    und.alloc(1, s);
+    for (int round = 0; round < 200; ++round) {
+        k_mis_prop<<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.row_len, S.col, strong.p, key.p, m1.p);
+        k_mis_prop<<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.row_len, S.col, strong.p, m1.p, m2.p);
+        und.zero(s);
+        k_mis_update<<<g, 256, 0, s>>>(n, m2.p, state.p, key.p, und.p);
+        FR_LAUNCH_CHECK();
+        if (download1(und.p, s) == 0) break;
+        if (round == 199) fail(FR_EINTERNAL, "aggregation: MIS(2) did not terminate");
+    }
+    DBuf<int32_t> flag, rank, agg1;
+    flag.alloc(size_t(n), s);
+    rank.alloc(size_t(n) + 1, s);
+    agg1.alloc(size_t(n), s);
+    agg.alloc(size_t(n), s);
+    k_root_flags<<<g, 256, 0, s>>>(n, state.p, flag.p);
+    FR_LAUNCH_CHECK();
+    int64_t n_agg = scan_exclusive(flag.p, rank.p, n, s);
+    k_agg_phase1<<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.row_len, S.col, strong.p, state.p, key.p, rank.p, agg1.p);
+    FR_LAUNCH_CHECK();
+    k_agg_phase2<<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.row_len, S.col, strong.p, isolated.p, key.p, agg1.p, agg.p);
+    FR_LAUNCH_CHECK();
+    k_orphan_flags<<<g, 256, 0, s>>>(n, isolated.p, agg.p, flag.p);
+    FR_LAUNCH_CHECK();
+    const int64_t n_orph = scan_exclusive(flag.p, rank.p, n, s);
+    if (n_orph > 0) {
+        k_orphan_assign<<<g, 256, 0, s>>>(n, flag.p, rank.p, int32_t(n_agg), agg.p);
+        FR_LAUNCH_CHECK();
+        n_agg += n_orph;
+    }
+    return n_agg;
+}
+
+// Tentative prolongator (one block per aggregated row) and the coarse near-null space.
+static BMat<double> tentative(const BMat<double>& A, const DBuf<int32_t>& agg, int64_t n_agg, int ns, bool level0,
+                              const double* coords, int dim, const double* Bf, DBuf<double>& Bc, hipStream_t s) {
+    const int64_t n = A.rows();
+    const int br = A.br;
+    BMat<double> P;
+    P.br = br;
+    P.bc = ns;
+    P.S = new_struct(n, n_agg, s);
+    k_ptent_struct<<<nblk(n, 256), 256, 0, s>>>(n, agg.p, P.S->row_len);
+    FR_LAUNCH_CHECK();
+    finish_struct(*P.S, s);
+    P.own_val.alloc(size_t(std::max<int64_t>(1, P.S->n_slots)) * br * ns, s);
+    P.val = P.own_val.p;
+    k_ptent_cols<<<nblk(n, 256), 256, 0, s>>>(n, P.S->C, P.S->slice_ptr, agg.p, P.S->col, P.val, br * ns);
+    FR_LAUNCH_CHECK();
+    // aggregate member lists
+    DBuf<int32_t> cnt, ptr, fillc, nodes;
+    cnt.alloc(size_t(n_agg) + 1, s);
+    ptr.alloc(size_t(n_agg) + 1, s);
+    fillc.alloc(size_t(n_agg) + 1, s);
+    nodes.alloc(size_t(std::max<int64_t>(1, n)), s);
+    cnt.zero(s);
+    fillc.zero(s);
+    k_agg_count<<<nblk(n, 256), 256, 0, s>>>(n, agg.p, cnt.p);
+    FR_LAUNCH_CHECK();
+    scan_exclusive(cnt.p, ptr.p, n_agg, s);
+    k_agg_fill<<<nblk(n, 256), 256, 0, s>>>(n, agg.p, ptr.p, fillc.p, nodes.p);
+    FR_LAUNCH_CHECK();
+    k_agg_sort<<<nblk(n_agg, 256), 256, 0, s>>>(n_agg, ptr.p, nodes.p);
+    FR_LAUNCH_CHECK();
+    Bc.alloc(size_t(std::max<int64_t>(1, n_agg)) * ns * ns, s);
+    const int g = nblk(n_agg, 64);
+    const int C = P.S->C;
+    if (level0 && br == 2 && ns == 3)
+        k_tentative<2, 3, true><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p);
+    else if (level0 && br == 3 && ns == 6)
+        k_tentative<3, 6, true><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p);
+    else if (br == 1 && ns == 1)
+        k_tentative<1, 1, false><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p);
+    else if (br == 3 && ns == 3)
+        k_tentative<3, 3, false><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p);
+    else if (br == 6 && ns == 6)
+        k_tentative<6, 6, false><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p);
+    else
+        fail(FR_EINTERNAL, "tentative: unsupported block shape");
+    FR_LAUNCH_CHECK();
+    return P;
+}
+
+static void make_f32(AmgLevel& L, bool coarsest, hipStream_t s) {
+    auto cp = [&](const BMat<double>& a, BMat<float>& b) {
+        if (!a.S) return;
+        b.br = a.br;
+        b.bc = a.bc;
+        b.S = a.S;
+        const int64_t nv = a.S->n_slots * a.br * a.bc;
+        b.own_val.alloc(size_t(std::max<int64_t>(1, nv)), s);
+        b.val = b.own_val.p;
+        cast_f64_f32(a.val, b.val, nv, s);
+    };
+    cp(L.A, L.A32);
+    if (!coarsest) {
+        cp(L.P, L.P32);
+        cp(L.R, L.R32);
+    }
+    const int64_t n = L.A.rows() * L.A.br;
+    L.invd32.alloc(size_t(std::max<int64_t>(1, n)), s);
+    cast_f64_f32(L.invd.p, L.invd32.p, n, s);
+}
+
+static void alloc_vectors(AmgLevel& L, int precision, hipStream_t s) {
+    const size_t n = size_t(std::max<int64_t>(1, L.A.rows() * L.A.br));
+    if (precision == 32) {
+        L.fb.alloc(n, s); L.fx0.alloc(n, s); L.fx1.alloc(n, s); L.fd.alloc(n, s); L.fr.alloc(n, s);
+    } else {
+        L.vb.alloc(n, s); L.vx0.alloc(n, s); L.vx1.alloc(n, s); L.vd.alloc(n, s); L.vr.alloc(n, s);
+    }
+}
+
+static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double* coords, int dim,
+                            const fr_amg_opts& o, hipStream_t s) {
+    H.lv.clear();
+    DBuf<double> Bf;   // near-null space of the current level (levels >= 1)
+    BMat<double> A = std::move(A0);
+    int ns = ns0;
+    for (int l = 0;; ++l) {
+        auto L = std::make_unique<AmgLevel>();
+        L->A.br = A.br;
+        L->A.bc = A.bc;
+        L->A.S = A.S;
+        L->A.val = A.val;
+        L->A.own_val = std::move(A.own_val);
+        DBuf<double> dnorm;
+        diag_info(L->A, L->invd, dnorm, s);
+        L->lmax = lambda_max(L->A, L->invd.p, s);
+        const int64_t nrows = L->A.rows() * L->A.br;
+        const bool last = nrows <= o.coarse_max || l + 1 >= o.max_levels;
+        if (!last) {
+            DBuf<int32_t> agg;
+            const int64_t n_agg = aggregate(L->A, dnorm.p, o.theta, agg, s);
+            if (n_agg == 0 || n_agg * ns >= nrows) {
+                H.lv.push_back(std::move(L));
+                break;   // coarsening stalled: this level is the coarsest
+            }
+            DBuf<double> Bc;
+            BMat<double> Pt = tentative(L->A, agg, n_agg, ns, l == 0, coords, dim, Bf.p, Bc, s);
+            const double omega = 4.0 / (3.0 * L->lmax);
+            L->P = spgemm<1>(L->A, Pt, L->invd.p, omega, s);
+            L->R = transpose(L->P, s);
+            BMat<double> AP = spgemm<0>(L->A, L->P, nullptr, 0.0, s);
+            BMat<double> Ac = spgemm<0>(L->R, AP, nullptr, 0.0, s);
+            L->ns = ns;
+            Bf = std::move(Bc);
+            A = std::move(Ac);
+            H.lv.push_back(std::move(L));
+            continue;
+        }
+        H.lv.push_back(std::move(L));
+        break;
+    }
+    // coarsest level: dense inverse when small enough
+    AmgLevel& Lc = *H.lv.back();
+    const int64_t nc = Lc.A.rows() * Lc.A.br;
+    H.n_coarse = nc;
+    if (nc <= kDenseMax) {
+        H.dense_inv.alloc(size_t(std::max<int64_t>(1, nc * nc)), s);
+        H.dense_inv.zero(s);
+        const int g = nblk(Lc.A.rows(), 256);
+        switch (Lc.A.br) {
+            case 1: k_to_dense<1><<<g, 256, 0, s>>>(sv(*Lc.A.S), Lc.A.val, nc, H.dense_inv.p); break;
+            case 2: k_to_dense<2><<<g, 256, 0, s>>>(sv(*Lc.A.S), Lc.A.val, nc, H.dense_inv.p); break;
+            case 3: k_to_dense<3><<<g, 256, 0, s>>>(sv(*Lc.A.S), Lc.A.val, nc, H.dense_inv.p); break;
+            case 6: k_to_dense<6><<<g, 256, 0, s>>>(sv(*Lc.A.S), Lc.A.val, nc, H.dense_inv.p); break;
+            default: fail(FR_EINTERNAL, "dense: unsupported block size");
+        }
+        FR_LAUNCH_CHECK();
+        k_fix_zero_rows<<<nblk(nc, 256), 256, 0, s>>>(nc, H.dense_inv.p);
+        FR_LAUNCH_CHECK();
+        k_gauss_jordan<<<1, 1024, 0, s>>>(nc, H.dense_inv.p);
+        FR_LAUNCH_CHECK();
+    } else {
+        H.dense_inv.release();
+    }
+    for (size_t l = 0; l < H.lv.size(); ++l) {
+        if (o.precision == 32) make_f32(*H.lv[l], l + 1 == H.lv.size(), s);
+        alloc_vectors(*H.lv[l], o.precision, s);
+    }
+    FR_HIP(hipStreamSynchronize(s));
+}
+
+void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s) {
+    amg.sys = &sys;
+    amg.opts = o;
+    amg.stream = s;
+    DevMesh& m = *sys.mesh;
+    BMat<double> Au;
+    Au.br = Au.bc = m.dim;
+    Au.S = sys.Juu.S;
+    Au.val = sys.Juu.val;
+    build_hierarchy(amg.h[0], std::move(Au), m.dim == 2 ? 3 : 6, m.coords_free.p, m.dim, o, s);
+    BMat<double> Ap;
+    Ap.br = Ap.bc = 1;
+    Ap.S = sys.Jpp.S;
+    Ap.val = sys.Jpp.val;
+    build_hierarchy(amg.h[1], std::move(Ap), 1, m.coords_free.p, m.dim, o, s);
+    amg.sys_version = sys.version;
+}
+
+// ---- V-cycle ---------------------------------------------------------------------------------
+
+template <typename T>
+struct LevelOps {
+    static const BMat<T>& A(const AmgLevel& L);
+    static const BMat<T>& P(const AmgLevel& L);
+    static const BMat<T>& R(const AmgLevel& L);
+    static const T* invd(const AmgLevel& L);
+    static T* b(AmgLevel& L);
+    static T* x0(AmgLevel& L);
+    static T* x1(AmgLevel& L);
+    static T* d(AmgLevel& L);
+    static T* r(AmgLevel& L);
+};
+
+template <>
+struct LevelOps<double> {
+    static const BMat<double>& A(const AmgLevel& L) { return L.A; }
+    static const BMat<double>& P(const AmgLevel& L) { return L.P; }
+    static const BMat<double>& R(const AmgLevel& L) { return L.R; }
+    static const double* invd(const AmgLevel& L) { return L.invd.p; }
+    static double* b(AmgLevel& L) { return L.vb.p; }
+    static double* x0(AmgLevel& L) { return L.vx0.p; }
+    static double* x1(AmgLevel& L) { return L.vx1.p; }
+    static double* d(AmgLevel& L) { return L.vd.p; }
+    static double* r(AmgLevel& L) { return L.vr.p; }
+};
+
+template <>
+struct LevelOps<float> {
+    static const BMat<float>& A(const AmgLevel& L) { return L.A32; }
+    static const BMat<float>& P(const AmgLevel& L) { return L.P32; }
+    static const BMat<float>& R(const AmgLevel& L) { return L.R32; }
+    static const float* invd(const AmgLevel& L) { return L.invd32.p; }
+    static float* b(AmgLevel& L) { return L.fb.p; }
+    static float* x0(AmgLevel& L) { return L.fx0.p; }
+    static float* x1(AmgLevel& L) { return L.fx1.p; }
+    static float* d(AmgLevel& L) { return L.fd.p; }
+    static float* r(AmgLevel& L) { return L.fr.p; }
+};
+
+// Chebyshev smoothing of A x = b on [lmax/ratio, 1.1 lmax] starting from x (zero if
+// from_zero).  Returns the buffer (x0 or x1 of the level) holding the result.
+template <typename T>
+static T* chebyshev(const AmgLevel& Lc, AmgLevel& L, const T* b, bool from_zero, T* x, T* other, int degree,
+                    double ratio, hipStream_t s) {
+    using O = LevelOps<T>;
+    const double hi = 1.1 * Lc.lmax, lo = hi / ratio;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    const int64_t n = Lc.A.rows() * Lc.A.br;
+    T* d = O::d(L);
+    if (from_zero) cheb_first<T>(O::invd(Lc), b, d, x, T(1.0 / theta), n, s);
+    else {
+        cheb_step<T>(O::A(Lc), O::invd(Lc), x, b, d, other, T(0), T(1.0 / theta), s);
+        std::swap(x, other);
+    }
+    for (int k = 1; k < degree; ++k) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        cheb_step<T>(O::A(Lc), O::invd(Lc), x, b, d, other, T(rn * rho), T(2.0 * rn / delta), s);
+        rho = rn;
+        std::swap(x, other);
+    }
+    return x;
+}
+
+template <typename T>
+static T* vcycle(Hierarchy& H, size_t l, const T* b, const fr_amg_opts& o, hipStream_t s) {
+    using O = LevelOps<T>;
+    AmgLevel& L = *H.lv[l];
+    const int64_t n = L.A.rows() * L.A.br;
+    if (l + 1 == H.lv.size()) {
+        T* x = O::x0(L);
+        if (H.dense_inv.p) {
+            if (n) k_dense_gemv<T><<<int(n), 256, 0, s>>>(n, H.dense_inv.p, b, x);
+            FR_LAUNCH_CHECK();
+            return x;
+        }
+        // large coarsest level: a longer smoothing sweep stands in for the exact solve
+        return chebyshev<T>(L, L, b, true, O::x0(L), O::x1(L), 4 * o.cheb_degree, o.cheb_ratio, s);
+    }
+    T* x = chebyshev<T>(L, L, b, true, O::x0(L), O::x1(L), o.cheb_degree, o.cheb_ratio, s);
+    T* other = (x == O::x0(L)) ? O::x1(L) : O::x0(L);
+    spmv_residual<T>(O::A(L), x, b, O::r(L), s);
+    AmgLevel& Ln = *H.lv[l + 1];
+    spmv<T>(O::R(L), O::r(L), O::b(Ln), s);
+    T* xc = vcycle<T>(H, l + 1, O::b(Ln), o, s);
+    spmv_add<T>(O::P(L), xc, x, s);
+    x = chebyshev<T>(L, L, b, false, x, other, o.cheb_degree, o.cheb_ratio, s);
+    return x;
+}
+
+void amg_precondition(DevAmg& amg, const double* r, double* z, hipStream_t s) {
+    DevSystem& sys = *amg.sys;
+    const int64_t nu = sys.n_u;
+    const int64_t np = sys.n_solve - nu;
+    const int64_t nb[2] = {nu, np};
+    const int64_t off[2] = {0, nu};
+    for (int blk = 0; blk < 2; ++blk) {
+        Hierarchy& H = amg.h[blk];
+        if (amg.opts.precision == 32) {
+            AmgLevel& L0 = *H.lv[0];
+            cast_f64_f32(r + off[blk], L0.fb.p, nb[blk], s);
+            float* x = vcycle<float>(H, 0, L0.fb.p, amg.opts, s);
+            cast_f32_f64(x, z + off[blk], nb[blk], s);
+        } else {
+            double* x = vcycle<double>(H, 0, r + off[blk], amg.opts, s);
+            vec_copy(x, z + off[blk], nb[blk], s);
+        }
+    }
+}
+
+// Exports for inspection (host CSR of a level operator).
+void amg_level_export(DevAmg& amg, int blk, int level, int which, int64_t& n_rows, int64_t& n_cols,
+                      std::vector<int64_t>& rp, std::vector<int32_t>& ci, std::vector<double>& vv, hipStream_t s) {
+    Hierarchy& H = amg.h[blk];
+    if (level < 0 || size_t(level) >= H.lv.size()) fail(FR_EINVAL, "amg_level_csr: level out of range");
+    AmgLevel& L = *H.lv[size_t(level)];
+    const BMat<double>* M = which == 0 ? &L.A : (which == 1 ? &L.P : &L.R);
+    if (!M->S) fail(FR_EINVAL, "amg_level_csr: operator absent on this level");
+    const SellStruct& S = *M->S;
+    auto sp = download(S.slice_ptr, size_t(S.n_slices) + 1, s);
+    auto len = download(S.row_len, size_t(S.n_rows), s);
+    auto col = download(S.col, size_t(S.n_slots), s);
+    auto val = download(M->val, size_t(S.n_slots) * M->br * M->bc, s);
+    const int br = M->br, bc = M->bc;
+    n_rows = S.n_rows * br;
+    n_cols = S.n_cols * bc;
+    rp.assign(size_t(n_rows) + 1, 0);
+    ci.clear();
+    vv.clear();
+    for (int64_t r = 0; r < S.n_rows; ++r)
+        for (int i = 0; i < br; ++i) {
+            for (int k = 0; k < len[size_t(r)]; ++k) {
+                const int64_t sl = int64_t(sp[size_t(r / S.C)]) + int64_t(k) * S.C + r % S.C;
+                for (int j = 0; j < bc; ++j) {
+                    ci.push_back(col[size_t(sl)] * bc + j);
+                    vv.push_back(val[size_t(sl * br * bc + i * bc + j)]);
+                }
+            }
+            rp[size_t(r * br + i) + 1] = int64_t(ci.size());
+        }
+}
+
+void amg_info(DevAmg& amg, int blk, int level, int& n_levels, int64_t& rows, int& bsize, int64_t& nnzb, double& lmax,
+              hipStream_t s) {
+    Hierarchy& H = amg.h[blk];
+    n_levels = int(H.lv.size());
+    if (level < 0 || size_t(level) >= H.lv.size()) return;
+    AmgLevel& L = *H.lv[size_t(level)];
+    rows = L.A.rows();
+    bsize = L.A.br;
+    nnzb = block_nnz(*L.A.S, s);
+    lmax = L.lmax;
+}
+
+}  // namespace fr

@@ -1,0 +1,835 @@
+// Element-parallel Q1 assembly of Formulation 1 (Section 2) on gfx950: residual of
+// E22ATW / E33ATW, lumped phi mass, primal-dual active set, the Jacobian blocks
+// M_uu, M_phiu, M_phiphi of Section 3 with the elimination of Dirichlet and active rows,
+// the Newton update and the TCV / COD functionals of Section 4.
+//
+// Assembly is node-centric: one thread owns one free node (one block row of every matrix
+// and the matching residual entries), walks the cells that carry its basis function and
+// accumulates in a fixed order.  No atomics: results are bitwise reproducible.
+#include <cmath>
+
+#include "system.h"
+
+namespace fr {
+
+Params make_params(const fr_params& p) {
+    Params q{};
+    q.E = p.E; q.nu = p.nu; q.Gc = p.Gc; q.kappa = p.kappa; q.eps = p.eps; q.p = p.p;
+    q.c_pdas = p.c_pdas;
+    q.tau = p.tau_pdas > 0 ? p.tau_pdas : 1e-10 * p.Gc / p.eps;
+    q.mu = p.E / (2.0 * (1.0 + p.nu));
+    q.lam = p.E * p.nu / ((1.0 + p.nu) * (1.0 - 2.0 * p.nu));
+    return q;
+}
+
+namespace {
+
+// 1d Q1 factors at the 2-point Gauss abscissae: (1 +- 1/sqrt(3)) / 2
+constexpr double kGP = 0.78867513459481288225;
+constexpr double kGM = 0.21132486540518711775;
+
+template <int D>
+__device__ __forceinline__ double shp(int q, int a) {
+    double v = 1.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) v *= (((a >> k) & 1) == ((q >> k) & 1)) ? kGP : kGM;
+    return v;
+}
+
+// d N_a / d x_k at Gauss point q of a cell with edge h (ih = 1/h)
+template <int D>
+__device__ __forceinline__ double dshp(int q, int a, int k, double ih) {
+    double v = ((a >> k) & 1) ? ih : -ih;
+#pragma unroll
+    for (int m = 0; m < D; ++m)
+        if (m != k) v *= (((a >> m) & 1) == ((q >> m) & 1)) ? kGP : kGM;
+    return v;
+}
+
+struct MeshView {
+    const int32_t* cells;
+    const double* cell_h;
+    const double* cell_lo;
+    const int32_t* node_of_free;
+    const int32_t* free_of_node;
+    const int32_t* con_ptr;
+    const int32_t* con_master;
+    const double* con_w;
+    const uint8_t* dir;
+    const int32_t* slice_ptr;
+    const int32_t* row_len;
+    const int32_t* col;
+    const int32_t* ent_ptr;
+    const int32_t* ent_cell;
+    const uint8_t* ent_a;
+    const uint8_t* ent_k;
+    const double* ent_w;
+    int C;
+    int64_t n_free;
+};
+
+MeshView view(const DevMesh& m) {
+    MeshView v;
+    v.cells = m.cells.p; v.cell_h = m.cell_h.p; v.cell_lo = m.cell_lo.p;
+    v.node_of_free = m.node_of_free.p; v.free_of_node = m.free_of_node.p;
+    v.con_ptr = m.con_ptr.p; v.con_master = m.con_master.p; v.con_w = m.con_w.p;
+    v.dir = m.dir_free.p;
+    v.slice_ptr = m.graph->slice_ptr; v.row_len = m.graph->row_len; v.col = m.graph->col;
+    v.ent_ptr = m.ent_ptr.p; v.ent_cell = m.ent_cell.p; v.ent_a = m.ent_a.p; v.ent_k = m.ent_k.p;
+    v.ent_w = m.ent_w.p;
+    v.C = m.graph->C;
+    v.n_free = m.n_free;
+    return v;
+}
+
+// Nodal values at a cell vertex; with hanging nodes the value is interpolated from the
+// free masters (the user arrays are only read at free nodes).
+template <int D, bool HANG>
+__device__ __forceinline__ void gather_node(const MeshView& mv, int32_t n, const double* u, const double* phi,
+                                            const double* pt, double* un, double& pn, double& ptn) {
+    if (!HANG) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) un[c] = u[int64_t(n) * D + c];
+        pn = phi[n];
+        ptn = pt ? pt[n] : 0.0;
+    } else {
+#pragma unroll
+        for (int c = 0; c < D; ++c) un[c] = 0.0;
+        pn = 0.0;
+        ptn = 0.0;
+        for (int32_t j = mv.con_ptr[n]; j < mv.con_ptr[n + 1]; ++j) {
+            const int32_t src = mv.node_of_free[mv.con_master[j]];
+            const double w = mv.con_w[j];
+#pragma unroll
+            for (int c = 0; c < D; ++c) un[c] += w * u[int64_t(src) * D + c];
+            pn += w * phi[src];
+            if (pt) ptn += w * pt[src];
+        }
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void strain_stress(const double (&gu)[D][D], double mu, double lam, double (&sig)[D][D],
+                                              double& s, double& tr) {
+    tr = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) tr += gu[c][c];
+    s = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double e = 0.5 * (gu[c][k] + gu[k][c]);
+            sig[c][k] = 2.0 * mu * e + (c == k ? lam * tr : 0.0);
+            s += sig[c][k] * e;
+        }
+}
+
+// ---- residual + lumped mass -------------------------------------------------------------
+template <int D, bool HANG>
+__global__ void __launch_bounds__(256) k_residual(MeshView mv, Params prm, const double* __restrict__ u,
+                                                  const double* __restrict__ phi, const double* __restrict__ pt,
+                                                  double* __restrict__ R, double* __restrict__ B) {
+    constexpr int NV = 1 << D;
+    const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (f >= mv.n_free) return;
+    double ru[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) ru[c] = 0.0;
+    double rp = 0.0, bm = 0.0;
+    for (int32_t e = mv.ent_ptr[f]; e < mv.ent_ptr[f + 1]; ++e) {
+        const int32_t cell = mv.ent_cell[e];
+        const int a = mv.ent_a[e];
+        const double w = mv.ent_w[e];
+        const double h = mv.cell_h[cell];
+        const double ih = 1.0 / h;
+        double W = 1.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) W *= 0.5 * h;
+        W *= w;
+        double ue[NV][D], pe[NV], pte[NV];
+#pragma unroll
+        for (int b = 0; b < NV; ++b) gather_node<D, HANG>(mv, mv.cells[int64_t(cell) * NV + b], u, phi, pt, ue[b], pe[b], pte[b]);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double gu[D][D], gp[D];
+            double ph = 0.0, pq = 0.0;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                gp[c] = 0.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) gu[c][k] = 0.0;
+            }
+#pragma unroll
+            for (int b = 0; b < NV; ++b) {
+                const double nb = shp<D>(q, b);
+                ph += nb * pe[b];
+                pq += nb * pte[b];
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const double db = dshp<D>(q, b, k, ih);
+                    gp[k] += db * pe[b];
+#pragma unroll
+                    for (int c = 0; c < D; ++c) gu[c][k] += db * ue[b][c];
+                }
+            }
+            double sig[D][D], s, tr;
+            strain_stress<D>(gu, prm.mu, prm.lam, sig, s, tr);
+            const double g = (1.0 - prm.kappa) * pq * pq + prm.kappa;
+            const double na = shp<D>(q, a);
+            double dna[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) dna[k] = dshp<D>(q, a, k, ih);
+            const double pres = pq * pq * prm.p;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) t += sig[c][k] * dna[k];
+                ru[c] += W * (g * t + pres * dna[c]);
+            }
+            const double react = (1.0 - prm.kappa) * ph * s + 2.0 * prm.p * ph * tr - (prm.Gc / prm.eps) * (1.0 - ph);
+            double lap = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) lap += gp[k] * dna[k];
+            rp += W * (react * na + prm.Gc * prm.eps * lap);
+            bm += W * na;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) R[f * D + c] = ru[c];
+    R[D * mv.n_free + f] = rp;
+    B[f] = bm;
+}
+
+// ---- active set -------------------------------------------------------------------------
+// lambda = -R_phi / B; A = { lambda + c (phi - phi_old) > tau }; optional cycle freeze.
+__global__ void __launch_bounds__(256) k_active(int64_t nf, int D, Params prm, const int32_t* __restrict__ node_of_free,
+                                                const double* __restrict__ R, const double* __restrict__ B,
+                                                const double* __restrict__ phi, const double* __restrict__ phi_old,
+                                                uint8_t* __restrict__ active, uint8_t* __restrict__ prev,
+                                                uint8_t* __restrict__ frozen, int use_freeze,
+                                                int32_t* __restrict__ part_cnt, double* __restrict__ part_min) {
+    __shared__ double shm[16];
+    __shared__ int shi[16];
+    const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int changed = 0;
+    double mm = INFINITY;
+    if (f < nf) {
+        const int32_t n = node_of_free[f];
+        const double lam = -R[D * nf + f] / B[f];
+        const double margin = lam + prm.c_pdas * (phi[n] - phi_old[n]) - prm.tau;
+        mm = fabs(margin);
+        uint8_t a_new = margin > 0.0 ? 1 : 0;
+        const uint8_t a_cur = active[f];
+        if (use_freeze) {
+            const uint8_t a_prev = prev[f];
+            if (a_prev != a_cur && a_cur != a_new) frozen[f] = 1;
+        }
+        if (frozen[f]) a_new = 1;
+        prev[f] = a_cur;
+        active[f] = a_new;
+        changed = a_new != a_cur;
+    }
+    int c = wave_sum_int(changed);
+    double m = wave_min(mm);
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    if (l == 0) { shi[w] = c; shm[w] = m; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tc = 0;
+        double tm = INFINITY;
+        for (int i = 0; i < int(blockDim.x / kWave); ++i) { tc += shi[i]; tm = fmin(tm, shm[i]); }
+        part_cnt[blockIdx.x] = tc;
+        part_min[blockIdx.x] = tm;
+    }
+}
+
+// ---- Jacobian + elimination ---------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ int64_t slot_of(const MeshView& mv, int64_t f, int k) {
+    return int64_t(mv.slice_ptr[f / mv.C]) + int64_t(k) * mv.C + (f % mv.C);
+}
+
+template <int D>
+__device__ __forceinline__ int find_k(const MeshView& mv, int64_t f, int32_t g) {
+    const int len = mv.row_len[f];
+    for (int k = 0; k < len; ++k)
+        if (mv.col[slot_of<D>(mv, f, k)] == g) return k;
+    return -1;
+}
+
+template <int D, bool HANG>
+__global__ void __launch_bounds__(128) k_jacobian(MeshView mv, Params prm, const double* __restrict__ u,
+                                                  const double* __restrict__ phi, const double* __restrict__ phi_old,
+                                                  const double* __restrict__ pt, const double* __restrict__ R,
+                                                  const uint8_t* __restrict__ active, double* __restrict__ Juu,
+                                                  double* __restrict__ Jpu, double* __restrict__ Jpp,
+                                                  double* __restrict__ F) {
+    constexpr int NV = 1 << D;
+    constexpr int DD = D * D;
+    const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (f >= mv.n_free) return;
+    const int64_t sl = f / mv.C;
+    const int width = (mv.slice_ptr[sl + 1] - mv.slice_ptr[sl]) / mv.C;
+    for (int k = 0; k < width; ++k) {
+        const int64_t s = slot_of<D>(mv, f, k);
+#pragma unroll
+        for (int i = 0; i < DD; ++i) Juu[s * DD + i] = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) Jpu[s * D + i] = 0.0;
+        Jpp[s] = 0.0;
+    }
+    for (int32_t e = mv.ent_ptr[f]; e < mv.ent_ptr[f + 1]; ++e) {
+        const int32_t cell = mv.ent_cell[e];
+        const int a = mv.ent_a[e];
+        const double w = mv.ent_w[e];
+        const double h = mv.cell_h[cell];
+        const double ih = 1.0 / h;
+        double W = 1.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) W *= 0.5 * h;
+        W *= w;
+        double ue[NV][D], pe[NV], pte[NV];
+#pragma unroll
+        for (int b = 0; b < NV; ++b) gather_node<D, HANG>(mv, mv.cells[int64_t(cell) * NV + b], u, phi, pt, ue[b], pe[b], pte[b]);
+        // per Gauss point: degradation, phi, stress and the reaction coefficient
+        double gq[NV], cphi[NV], pphi[NV], react[NV], sig[NV][D][D];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double gu[D][D];
+            double ph = 0.0, pq = 0.0;
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+#pragma unroll
+                for (int k = 0; k < D; ++k) gu[c][k] = 0.0;
+#pragma unroll
+            for (int b = 0; b < NV; ++b) {
+                const double nb = shp<D>(q, b);
+                ph += nb * pe[b];
+                pq += nb * pte[b];
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const double db = dshp<D>(q, b, k, ih);
+#pragma unroll
+                    for (int c = 0; c < D; ++c) gu[c][k] += db * ue[b][c];
+                }
+            }
+            double s, tr;
+            strain_stress<D>(gu, prm.mu, prm.lam, sig[q], s, tr);
+            gq[q] = (1.0 - prm.kappa) * pq * pq + prm.kappa;
+            cphi[q] = 2.0 * (1.0 - prm.kappa) * ph;
+            pphi[q] = 2.0 * prm.p * ph;
+            react[q] = (1.0 - prm.kappa) * s + 2.0 * prm.p * tr + prm.Gc / prm.eps;
+        }
+#pragma unroll
+        for (int b = 0; b < NV; ++b) {
+            double kuu[D][D], kpu[D], kpp = 0.0;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                kpu[c] = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) kuu[c][d] = 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                const double na = shp<D>(q, a), nb = shp<D>(q, b);
+                double dna[D], dnb[D], dot = 0.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    dna[k] = dshp<D>(q, a, k, ih);
+                    dnb[k] = dshp<D>(q, b, k, ih);
+                    dot += dna[k] * dnb[k];
+                }
+                const double g = gq[q];
+#pragma unroll
+                for (int c = 0; c < D; ++c)
+#pragma unroll
+                    for (int d = 0; d < D; ++d)
+                        kuu[c][d] += g * (prm.mu * ((c == d ? dot : 0.0) + dnb[c] * dna[d]) + prm.lam * dnb[d] * dna[c]);
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) t += sig[q][d][k] * dnb[k];
+                    kpu[d] += (cphi[q] * t + pphi[q] * dnb[d]) * na;
+                }
+                kpp += react[q] * nb * na + prm.Gc * prm.eps * dot;
+            }
+            const int kk = mv.ent_k[int64_t(e) * NV + b];
+            if (kk != 255) {
+                const int64_t s = slot_of<D>(mv, f, kk);
+#pragma unroll
+                for (int c = 0; c < D; ++c)
+#pragma unroll
+                    for (int d = 0; d < D; ++d) Juu[s * DD + c * D + d] += W * kuu[c][d];
+#pragma unroll
+                for (int d = 0; d < D; ++d) Jpu[s * D + d] += W * kpu[d];
+                Jpp[s] += W * kpp;
+            } else if (HANG) {
+                const int32_t n = mv.cells[int64_t(cell) * NV + b];
+                for (int32_t j = mv.con_ptr[n]; j < mv.con_ptr[n + 1]; ++j) {
+                    const int k2 = find_k<D>(mv, f, mv.con_master[j]);
+                    if (k2 < 0) continue;
+                    const double ww = W * mv.con_w[j];
+                    const int64_t s = slot_of<D>(mv, f, k2);
+#pragma unroll
+                    for (int c = 0; c < D; ++c)
+#pragma unroll
+                        for (int d = 0; d < D; ++d) Juu[s * DD + c * D + d] += ww * kuu[c][d];
+#pragma unroll
+                    for (int d = 0; d < D; ++d) Jpu[s * D + d] += ww * kpu[d];
+                    Jpp[s] += ww * kpp;
+                }
+            }
+        }
+    }
+    // elimination of Dirichlet u DoFs (target u = 0) and active phi DoFs (target phi_old)
+    const int64_t nf = mv.n_free;
+    const bool dir_f = mv.dir[f] != 0;
+    const bool act_f = active[f] != 0;
+    const int32_t nodef = mv.node_of_free[f];
+    double fu[D], fp;
+#pragma unroll
+    for (int c = 0; c < D; ++c) fu[c] = -R[f * D + c];
+    fp = -R[D * nf + f];
+    const int len = mv.row_len[f];
+    double diag_u[D], diag_p = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) diag_u[c] = 0.0;
+    for (int k = 0; k < len; ++k) {
+        const int64_t s = slot_of<D>(mv, f, k);
+        const int32_t g = mv.col[s];
+        const int32_t nodeg = mv.node_of_free[g];
+        if (g == f) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) diag_u[c] = Juu[s * DD + c * D + c];
+            diag_p = Jpp[s];
+        }
+        const bool dir_g = mv.dir[g] != 0;
+        const bool act_g = active[g] != 0;
+        // u columns of Dirichlet nodes
+        if (dir_g && g != f) {
+            double tg[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) tg[d] = -u[int64_t(nodeg) * D + d];
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) t += Juu[s * DD + c * D + d] * tg[d];
+                fu[c] -= t;
+            }
+            double t = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) t += Jpu[s * D + d] * tg[d];
+            fp -= t;
+#pragma unroll
+            for (int i = 0; i < DD; ++i) Juu[s * DD + i] = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) Jpu[s * D + i] = 0.0;
+        } else if (dir_g && g == f) {
+            // both row and column Dirichlet: keep only the diagonal of the block
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+#pragma unroll
+                for (int d = 0; d < D; ++d)
+                    if (c != d) Juu[s * DD + c * D + d] = 0.0;
+            double tg[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) tg[d] = -u[int64_t(nodeg) * D + d];
+            double t = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) t += Jpu[s * D + d] * tg[d];
+            fp -= t;
+#pragma unroll
+            for (int i = 0; i < D; ++i) Jpu[s * D + i] = 0.0;
+        }
+        if (dir_f && g != f) {
+#pragma unroll
+            for (int i = 0; i < DD; ++i) Juu[s * DD + i] = 0.0;
+        }
+        // phi columns of active nodes
+        if (act_g && g != f) {
+            const int32_t ng = nodeg;
+            fp -= Jpp[s] * (phi_old[ng] - phi[ng]);
+            Jpp[s] = 0.0;
+        }
+    }
+    if (act_f) {
+        for (int k = 0; k < len; ++k) {
+            const int64_t s = slot_of<D>(mv, f, k);
+#pragma unroll
+            for (int i = 0; i < D; ++i) Jpu[s * D + i] = 0.0;
+            if (mv.col[s] != f) Jpp[s] = 0.0;
+        }
+        fp = diag_p * (phi_old[nodef] - phi[nodef]);
+    }
+    if (dir_f) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) fu[c] = diag_u[c] * (-u[int64_t(nodef) * D + c]);
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) F[f * D + c] = fu[c];
+    F[D * nf + f] = fp;
+}
+
+// ---- masked residual norm and rhs norm (block partials) ---------------------------------
+__global__ void __launch_bounds__(256) k_norm_parts(int64_t nf, int D, const double* __restrict__ R,
+                                                    const double* __restrict__ F, const uint8_t* __restrict__ dir,
+                                                    const uint8_t* __restrict__ active, double* __restrict__ part) {
+    __shared__ double sh[16];
+    const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    double r2 = 0.0, f2 = 0.0, na = 0.0;
+    if (f < nf) {
+        if (!dir[f])
+            for (int c = 0; c < D; ++c) r2 += R[f * D + c] * R[f * D + c];
+        if (!active[f]) r2 += R[D * nf + f] * R[D * nf + f];
+        else na = 1.0;
+        if (F) {
+            for (int c = 0; c < D; ++c) f2 += F[f * D + c] * F[f * D + c];
+            f2 += F[D * nf + f] * F[D * nf + f];
+        }
+    }
+    const double a = block_sum(r2, sh);
+    const double b = block_sum(f2, sh);
+    const double c = block_sum(na, sh);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x + 0] = a;
+        part[3 * blockIdx.x + 1] = b;
+        part[3 * blockIdx.x + 2] = c;
+    }
+}
+
+// ---- update -----------------------------------------------------------------------------
+__global__ void k_update_free(int64_t nf, int D, const int32_t* __restrict__ node_of_free,
+                              const double* __restrict__ du, double omega, double* __restrict__ u,
+                              double* __restrict__ phi) {
+    const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    const int64_t n = node_of_free[f];
+    for (int c = 0; c < D; ++c) u[n * D + c] += omega * du[f * D + c];
+    phi[n] += omega * du[D * nf + f];
+}
+
+__global__ void k_fill_hanging(int64_t nn, int D, const int32_t* __restrict__ free_of_node,
+                               const int32_t* __restrict__ node_of_free, const int32_t* __restrict__ con_ptr,
+                               const int32_t* __restrict__ con_master, const double* __restrict__ con_w,
+                               double* __restrict__ u, double* __restrict__ phi) {
+    const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (n >= nn || free_of_node[n] >= 0) return;
+    double uu[3] = {0, 0, 0}, pp = 0.0;
+    for (int32_t j = con_ptr[n]; j < con_ptr[n + 1]; ++j) {
+        const int64_t src = node_of_free[con_master[j]];
+        for (int c = 0; c < D; ++c) uu[c] += con_w[j] * u[src * D + c];
+        pp += con_w[j] * phi[src];
+    }
+    for (int c = 0; c < D; ++c) u[n * D + c] = uu[c];
+    phi[n] = pp;
+}
+
+// ---- functionals --------------------------------------------------------------------------
+template <int D, bool HANG>
+__global__ void __launch_bounds__(256) k_tcv(int64_t nc, MeshView mv, const double* __restrict__ u,
+                                             const double* __restrict__ phi, double* __restrict__ part) {
+    __shared__ double sh[16];
+    constexpr int NV = 1 << D;
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    if (c < nc) {
+        const double h = mv.cell_h[c], ih = 1.0 / h;
+        double W = 1.0;
+        for (int k = 0; k < D; ++k) W *= 0.5 * h;
+        double ue[NV][D], pe[NV], dummy;
+#pragma unroll
+        for (int b = 0; b < NV; ++b) gather_node<D, HANG>(mv, mv.cells[c * NV + b], u, phi, nullptr, ue[b], pe[b], dummy);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double uq[D], gp[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) { uq[k] = 0.0; gp[k] = 0.0; }
+#pragma unroll
+            for (int b = 0; b < NV; ++b) {
+                const double nb = shp<D>(q, b);
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    uq[k] += nb * ue[b][k];
+                    gp[k] += dshp<D>(q, b, k, ih) * pe[b];
+                }
+            }
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) t += uq[k] * gp[k];
+            acc += W * t;
+        }
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// COD: 1/2 of the line integral of u . grad phi along the last axis at x0 (1d 2-point Gauss)
+template <int D, bool HANG>
+__global__ void __launch_bounds__(256) k_cod(int64_t nc, MeshView mv, const double* __restrict__ u,
+                                             const double* __restrict__ phi, const double* __restrict__ xs,
+                                             double* __restrict__ part) {
+    __shared__ double sh[16];
+    constexpr int NV = 1 << D;
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int sample = blockIdx.y;
+    double acc = 0.0;
+    if (c < nc) {
+        const double h = mv.cell_h[c], ih = 1.0 / h;
+        bool hit = true;
+        double xi[D];
+        for (int k = 0; k < D - 1; ++k) {
+            const double lo = mv.cell_lo[c * D + k];
+            const double x0 = xs[sample * (D - 1) + k];
+            hit = hit && (lo <= x0) && (x0 < lo + h);
+            xi[k] = 2.0 * (x0 - lo) / h - 1.0;
+        }
+        if (hit) {
+            double ue[NV][D], pe[NV], dummy;
+#pragma unroll
+            for (int b = 0; b < NV; ++b) gather_node<D, HANG>(mv, mv.cells[c * NV + b], u, phi, nullptr, ue[b], pe[b], dummy);
+            const double g1 = 0.57735026918962576451;   // 1/sqrt(3)
+            for (int q = 0; q < 2; ++q) {
+                xi[D - 1] = q ? g1 : -g1;
+                double uq[D], gp[D];
+                for (int k = 0; k < D; ++k) { uq[k] = 0.0; gp[k] = 0.0; }
+                for (int b = 0; b < NV; ++b) {
+                    double nb = 1.0;
+                    double dn[D];
+                    for (int k = 0; k < D; ++k) dn[k] = 1.0;
+                    for (int m = 0; m < D; ++m) {
+                        const double sgn = ((b >> m) & 1) ? 1.0 : -1.0;
+                        const double fac = 0.5 * (1.0 + sgn * xi[m]);
+                        nb *= fac;
+                        for (int k = 0; k < D; ++k) dn[k] *= (k == m) ? sgn * ih : fac;
+                    }
+                    for (int k = 0; k < D; ++k) {
+                        uq[k] += nb * ue[b][k];
+                        gp[k] += dn[k] * pe[b];
+                    }
+                }
+                double t = 0.0;
+                for (int k = 0; k < D; ++k) t += uq[k] * gp[k];
+                acc += 0.5 * h * t;
+            }
+        }
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[int64_t(sample) * gridDim.x + blockIdx.x] = 0.5 * s;
+}
+
+__global__ void k_sum_rows(const double* __restrict__ part, int64_t n_part, int n_rows, int stride_row,
+                           int stride_elem, double* __restrict__ out) {
+    // one block per output row, fixed-order sum
+    __shared__ double sh[16];
+    const int r = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n_part; i += blockDim.x) acc += part[int64_t(r) * stride_row + i * stride_elem];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[r] = s;
+}
+
+}  // namespace
+
+// ---- host side --------------------------------------------------------------------------
+
+std::unique_ptr<DevMesh> mesh_create(const fr_mesh_desc& d, hipStream_t s, bool upload) {
+    auto m = std::make_unique<DevMesh>();
+    m->host = build_mesh(d);
+    m->pat = build_pattern(m->host, 64);
+    const HostMesh& h = m->host;
+    const Pattern& p = m->pat;
+    m->stream = s;
+    m->dim = h.dim;
+    m->nv = h.nv;
+    m->n_nodes = h.n_nodes;
+    m->n_cells = h.n_cells;
+    m->n_free = h.n_free;
+    m->hanging = h.n_hanging > 0;
+    m->on_device = upload;
+    if (!upload) return m;
+    m->cells.upload(h.cells, s);
+    m->cell_h.upload(h.cell_h, s);
+    m->cell_lo.upload(h.cell_lo, s);
+    m->node_of_free.upload(h.node_of_free, s);
+    m->free_of_node.upload(h.free_of_node, s);
+    m->con_ptr.upload(h.con_ptr, s);
+    m->con_master.upload(h.con_master, s);
+    m->con_w.upload(h.con_w, s);
+    std::vector<uint8_t> dirf(size_t(h.n_free));
+    std::vector<double> cf(size_t(h.n_free) * h.dim);
+    for (int64_t f = 0; f < h.n_free; ++f) {
+        const int64_t n = h.node_of_free[size_t(f)];
+        dirf[size_t(f)] = h.dirichlet[size_t(n)];
+        for (int c = 0; c < h.dim; ++c) cf[size_t(f) * h.dim + c] = h.coords[size_t(n) * h.dim + c];
+    }
+    m->dir_free.upload(dirf, s);
+    m->coords_free.upload(cf, s);
+    auto g = std::make_shared<SellStruct>();
+    g->C = p.C;
+    g->n_rows = p.n_rows;
+    g->n_cols = p.n_rows;
+    g->n_slices = p.n_slices;
+    g->n_slots = p.n_slots;
+    g->nnz = p.nnz;
+    g->own_slice.upload(p.slice_ptr, s);
+    g->own_len.upload(p.row_len, s);
+    g->own_col.upload(p.col, s);
+    g->slice_ptr = g->own_slice.p;
+    g->row_len = g->own_len.p;
+    g->col = g->own_col.p;
+    m->graph = g;
+    m->ent_ptr.upload(p.ent_ptr, s);
+    m->ent_cell.upload(p.ent_cell, s);
+    m->ent_a.upload(p.ent_a, s);
+    m->ent_k.upload(p.ent_k, s);
+    m->ent_w.upload(p.ent_w, s);
+    FR_HIP(hipStreamSynchronize(s));   // host vectors of the pattern stay alive in m
+    return m;
+}
+
+static int blocks_for(int64_t n, int t) { return int(ceil_div(n, t)); }
+
+void assemble_residual(DevSystem& sys, const double* u, const double* phi, const double* pt) {
+    DevMesh& m = *sys.mesh;
+    MeshView mv = view(m);
+    const hipStream_t s = sys.stream;
+    const int nb = blocks_for(m.n_free, 256);
+    if (m.dim == 2) {
+        if (m.hanging) k_residual<2, true><<<nb, 256, 0, s>>>(mv, sys.prm, u, phi, pt, sys.R.p, sys.B.p);
+        else k_residual<2, false><<<nb, 256, 0, s>>>(mv, sys.prm, u, phi, pt, sys.R.p, sys.B.p);
+    } else {
+        if (m.hanging) k_residual<3, true><<<nb, 256, 0, s>>>(mv, sys.prm, u, phi, pt, sys.R.p, sys.B.p);
+        else k_residual<3, false><<<nb, 256, 0, s>>>(mv, sys.prm, u, phi, pt, sys.R.p, sys.B.p);
+    }
+    FR_LAUNCH_CHECK();
+    sys.have_residual = true;
+}
+
+void assemble_active_impl(DevSystem& sys, const double* phi, const double* phi_old, int use_freeze) {
+    DevMesh& m = *sys.mesh;
+    const hipStream_t s = sys.stream;
+    const int nb = blocks_for(m.n_free, 256);
+    sys.red.reserve(size_t(nb) + 16, s);
+    sys.ired.reserve(size_t(nb) + 16, s);
+    k_active<<<nb, 256, 0, s>>>(m.n_free, m.dim, sys.prm, m.node_of_free.p, sys.R.p, sys.B.p, phi, phi_old,
+                                sys.active.p, sys.active_prev.p, sys.frozen.p, use_freeze, sys.ired.p, sys.red.p);
+    FR_LAUNCH_CHECK();
+    auto cnt = download(sys.ired.p, size_t(nb), s);
+    auto mm = download(sys.red.p, size_t(nb), s);
+    int64_t ch = 0;
+    double mn = INFINITY;
+    for (int32_t c : cnt) ch += c;
+    for (double v : mm) mn = std::fmin(mn, v);
+    sys.last_changes = ch;
+    sys.last_min_margin = mn;
+    sys.have_active = true;
+}
+
+void assemble_active(DevSystem& sys, const double* phi, const double* phi_old) {
+    assemble_active_impl(sys, phi, phi_old, 0);
+}
+
+void assemble_active_freeze(DevSystem& sys, const double* phi, const double* phi_old) {
+    assemble_active_impl(sys, phi, phi_old, 1);
+}
+
+void assemble_jacobian(DevSystem& sys, const double* u, const double* phi, const double* phi_old, const double* pt) {
+    DevMesh& m = *sys.mesh;
+    MeshView mv = view(m);
+    const hipStream_t s = sys.stream;
+    const int nb = blocks_for(m.n_free, 128);
+    if (m.dim == 2) {
+        if (m.hanging)
+            k_jacobian<2, true><<<nb, 128, 0, s>>>(mv, sys.prm, u, phi, phi_old, pt, sys.R.p, sys.active.p, sys.Juu.val,
+                                                   sys.Jpu.val, sys.Jpp.val, sys.F.p);
+        else
+            k_jacobian<2, false><<<nb, 128, 0, s>>>(mv, sys.prm, u, phi, phi_old, pt, sys.R.p, sys.active.p, sys.Juu.val,
+                                                    sys.Jpu.val, sys.Jpp.val, sys.F.p);
+    } else {
+        if (m.hanging)
+            k_jacobian<3, true><<<nb, 128, 0, s>>>(mv, sys.prm, u, phi, phi_old, pt, sys.R.p, sys.active.p, sys.Juu.val,
+                                                   sys.Jpu.val, sys.Jpp.val, sys.F.p);
+        else
+            k_jacobian<3, false><<<nb, 128, 0, s>>>(mv, sys.prm, u, phi, phi_old, pt, sys.R.p, sys.active.p, sys.Juu.val,
+                                                    sys.Jpu.val, sys.Jpp.val, sys.F.p);
+    }
+    FR_LAUNCH_CHECK();
+    sys.have_jacobian = true;
+    sys.version++;
+}
+
+void system_norms(DevSystem& sys, const double* phi, const double* phi_old, double* norms, int64_t* n_active,
+                  double* min_margin) {
+    (void)phi;
+    (void)phi_old;
+    DevMesh& m = *sys.mesh;
+    const hipStream_t s = sys.stream;
+    const int nb = blocks_for(m.n_free, 256);
+    sys.red.reserve(size_t(3 * nb) + 16, s);
+    k_norm_parts<<<nb, 256, 0, s>>>(m.n_free, m.dim, sys.R.p, sys.have_jacobian ? sys.F.p : nullptr, m.dir_free.p,
+                                    sys.active.p, sys.red.p);
+    FR_LAUNCH_CHECK();
+    auto part = download(sys.red.p, size_t(3 * nb), s);
+    double a = 0, b = 0, c = 0;
+    for (int i = 0; i < nb; ++i) { a += part[size_t(3 * i)]; b += part[size_t(3 * i + 1)]; c += part[size_t(3 * i + 2)]; }
+    if (norms) { norms[0] = std::sqrt(a); norms[1] = std::sqrt(b); }
+    if (n_active) *n_active = int64_t(c + 0.5);
+    if (min_margin) *min_margin = sys.last_min_margin;
+}
+
+void mesh_update(DevMesh& m, const double* du, double omega, double* u, double* phi, hipStream_t s) {
+    k_update_free<<<blocks_for(m.n_free, 256), 256, 0, s>>>(m.n_free, m.dim, m.node_of_free.p, du, omega, u, phi);
+    FR_LAUNCH_CHECK();
+    if (m.hanging) {
+        k_fill_hanging<<<blocks_for(m.n_nodes, 256), 256, 0, s>>>(m.n_nodes, m.dim, m.free_of_node.p, m.node_of_free.p,
+                                                                   m.con_ptr.p, m.con_master.p, m.con_w.p, u, phi);
+        FR_LAUNCH_CHECK();
+    }
+}
+
+void mesh_functionals(DevMesh& m, const double* u, const double* phi, const double* cod_x, int n_cod, double* cod,
+                      double* tcv, hipStream_t s) {
+    MeshView mv = view(m);
+    const int nb = blocks_for(m.n_cells, 256);
+    DBuf<double> part, out;
+    part.alloc(size_t(nb) * size_t(std::max(1, n_cod)), s);
+    out.alloc(size_t(std::max(1, n_cod)), s);
+    if (tcv) {
+        if (m.dim == 2) {
+            if (m.hanging) k_tcv<2, true><<<nb, 256, 0, s>>>(m.n_cells, mv, u, phi, part.p);
+            else k_tcv<2, false><<<nb, 256, 0, s>>>(m.n_cells, mv, u, phi, part.p);
+        } else {
+            if (m.hanging) k_tcv<3, true><<<nb, 256, 0, s>>>(m.n_cells, mv, u, phi, part.p);
+            else k_tcv<3, false><<<nb, 256, 0, s>>>(m.n_cells, mv, u, phi, part.p);
+        }
+        FR_LAUNCH_CHECK();
+        k_sum_rows<<<1, 256, 0, s>>>(part.p, nb, 1, 0, 1, out.p);
+        FR_LAUNCH_CHECK();
+        *tcv = download1(out.p, s);
+    }
+    if (cod && n_cod > 0) {
+        DBuf<double> xs;
+        xs.alloc(size_t(n_cod) * (m.dim - 1), s);
+        xs.upload(cod_x, size_t(n_cod) * (m.dim - 1), s);
+        dim3 grid(nb, n_cod);
+        if (m.dim == 2) {
+            if (m.hanging) k_cod<2, true><<<grid, 256, 0, s>>>(m.n_cells, mv, u, phi, xs.p, part.p);
+            else k_cod<2, false><<<grid, 256, 0, s>>>(m.n_cells, mv, u, phi, xs.p, part.p);
+        } else {
+            if (m.hanging) k_cod<3, true><<<grid, 256, 0, s>>>(m.n_cells, mv, u, phi, xs.p, part.p);
+            else k_cod<3, false><<<grid, 256, 0, s>>>(m.n_cells, mv, u, phi, xs.p, part.p);
+        }
+        FR_LAUNCH_CHECK();
+        k_sum_rows<<<n_cod, 256, 0, s>>>(part.p, nb, n_cod, nb, 1, out.p);
+        FR_LAUNCH_CHECK();
+        auto h = download(out.p, size_t(n_cod), s);
+        for (int i = 0; i < n_cod; ++i) cod[i] = h[size_t(i)];
+        FR_HIP(hipStreamSynchronize(s));
+    }
+}
+
+}  // namespace fr

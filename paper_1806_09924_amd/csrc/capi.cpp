@@ -1,0 +1,618 @@
+// C ABI of the fracture library: argument validation, handle lifetimes, error reporting and
+// the native Newton / active-set driver (Section 3 algorithm) over the device kernels.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "system.h"
+
+namespace fr {
+void assemble_active_freeze(DevSystem& sys, const double* phi, const double* phi_old);
+}
+
+struct fr_mesh_s {
+    std::unique_ptr<fr::DevMesh> m;
+};
+
+struct fr_system_s {
+    fr::DevSystem sys;
+    fr::DevKrylov kry;
+};
+
+struct fr_amg_s {
+    fr::DevAmg amg;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+fr_status set_err(fr_status s, const std::string& m) {
+    g_err = m;
+    return s;
+}
+
+template <typename F>
+fr_status guard(F&& f) {
+    try {
+        return f();
+    } catch (const fr::Error& e) {
+        return set_err(e.status, e.what());
+    } catch (const std::bad_alloc&) {
+        return set_err(FR_ENOMEM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return set_err(FR_EINTERNAL, e.what());
+    }
+}
+
+#define FR_REQUIRE(cond, msg)                     \
+    do {                                          \
+        if (!(cond)) return set_err(FR_EINVAL, msg); \
+    } while (0)
+
+fr_status check_device() {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return set_err(FR_EDEVICE, "no HIP device available");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return set_err(FR_EDEVICE, "hipGetDevice failed");
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return set_err(FR_EDEVICE, "hipGetDeviceProperties failed");
+    if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0)
+        return set_err(FR_EDEVICE, std::string("device is ") + p.gcnArchName + ", the library is built for gfx950");
+    return FR_OK;
+}
+
+fr_status check_params(const fr_params* p) {
+    FR_REQUIRE(p != nullptr, "params: NULL");
+    FR_REQUIRE(p->E > 0 && std::isfinite(p->E), "params: E must be > 0");
+    FR_REQUIRE(p->nu > -1.0 && p->nu < 0.5, "params: nu must be in (-1, 0.5)");
+    FR_REQUIRE(p->Gc > 0 && std::isfinite(p->Gc), "params: Gc must be > 0");
+    FR_REQUIRE(p->eps > 0 && std::isfinite(p->eps), "params: eps must be > 0");
+    FR_REQUIRE(p->kappa > 0 && p->kappa < 1, "params: kappa must be in (0, 1)");
+    FR_REQUIRE(std::isfinite(p->p), "params: p must be finite");
+    FR_REQUIRE(std::isfinite(p->c_pdas) && p->c_pdas > 0, "params: c_pdas must be > 0");
+    return FR_OK;
+}
+
+fr_amg_opts default_amg() {
+    fr_amg_opts o;
+    o.precision = 64;
+    o.theta = 0.02;
+    o.cheb_degree = 2;
+    o.cheb_ratio = 20.0;
+    o.coarse_max = 500;
+    o.max_levels = 10;
+    return o;
+}
+
+fr_status check_amg(const fr_amg_opts& o) {
+    FR_REQUIRE(o.precision == 32 || o.precision == 64, "amg: precision must be 32 or 64");
+    FR_REQUIRE(o.theta >= 0 && o.theta < 1, "amg: theta must be in [0, 1)");
+    FR_REQUIRE(o.cheb_degree >= 1 && o.cheb_degree <= 16, "amg: cheb_degree must be in [1, 16]");
+    FR_REQUIRE(o.cheb_ratio > 1, "amg: cheb_ratio must be > 1");
+    FR_REQUIRE(o.coarse_max >= 1 && o.coarse_max <= 4096, "amg: coarse_max must be in [1, 4096]");
+    FR_REQUIRE(o.max_levels >= 1 && o.max_levels <= 30, "amg: max_levels must be in [1, 30]");
+    return FR_OK;
+}
+
+fr_status check_solve(const fr_solve_opts& o) {
+    FR_REQUIRE(o.rtol > 0 && o.rtol < 1, "solve: rtol must be in (0, 1)");
+    FR_REQUIRE(o.restart >= 1 && o.restart <= 120, "solve: restart must be in [1, 120]");
+    FR_REQUIRE(o.maxit >= 1, "solve: maxit must be >= 1");
+    return FR_OK;
+}
+
+void system_init(fr_system_s& S, fr::DevMesh& m, hipStream_t s) {
+    fr::DevSystem& sys = S.sys;
+    sys.mesh = &m;
+    sys.stream = s;
+    sys.n_u = m.n_free * m.dim;
+    sys.n_solve = m.n_free * (m.dim + 1);
+    const int64_t slots = m.graph->n_slots;
+    auto mk = [&](fr::BMat<double>& b, int br, int bc) {
+        b.br = br;
+        b.bc = bc;
+        b.S = m.graph;
+        b.own_val.alloc(size_t(std::max<int64_t>(1, slots)) * br * bc, s);
+        b.val = b.own_val.p;
+        b.own_val.zero(s);
+    };
+    mk(sys.Juu, m.dim, m.dim);
+    mk(sys.Jpu, 1, m.dim);
+    mk(sys.Jpp, 1, 1);
+    sys.R.alloc(size_t(sys.n_solve), s);
+    sys.F.alloc(size_t(sys.n_solve), s);
+    sys.B.alloc(size_t(m.n_free), s);
+    sys.active.alloc(size_t(m.n_free), s);
+    sys.active_prev.alloc(size_t(m.n_free), s);
+    sys.frozen.alloc(size_t(m.n_free), s);
+    sys.active.zero(s);
+    sys.active_prev.zero(s);
+    sys.frozen.zero(s);
+    sys.R.zero(s);
+    sys.F.zero(s);
+}
+
+struct EventTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s;
+    explicit EventTimer(hipStream_t st) : s(st) {
+        FR_HIP(hipEventCreate(&a));
+        FR_HIP(hipEventCreate(&b));
+        FR_HIP(hipEventRecord(a, s));
+    }
+    double stop() {
+        FR_HIP(hipEventRecord(b, s));
+        FR_HIP(hipEventSynchronize(b));
+        float ms = 0;
+        FR_HIP(hipEventElapsedTime(&ms, a, b));
+        return double(ms) * 1e-3;
+    }
+    ~EventTimer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* fracture_last_error(void) { return g_err.c_str(); }
+
+const char* fracture_version(void) { return "fracture-gfx950 0.1"; }
+
+fr_status fracture_device_check(void) {
+    return guard([&]() { return check_device(); });
+}
+
+fr_status fracture_mesh_create(const fr_mesh_desc* desc, fr_mesh* out, void* stream) {
+    FR_REQUIRE(desc != nullptr && out != nullptr, "mesh_create: NULL argument");
+    FR_REQUIRE(desc->dim == 2 || desc->dim == 3, "mesh_create: dim must be 2 or 3");
+    FR_REQUIRE(desc->levels >= 0 && desc->levels <= 12, "mesh_create: levels must be in [0, 12]");
+    for (int k = 0; k < desc->dim; ++k) {
+        FR_REQUIRE(desc->base[k] >= 1, "mesh_create: base must be >= 1");
+        FR_REQUIRE(desc->hi[k] > desc->lo[k], "mesh_create: need hi > lo");
+    }
+    return guard([&]() {
+        fr_status st = check_device();
+        if (st != FR_OK) return st;
+        auto h = std::make_unique<fr_mesh_s>();
+        h->m = fr::mesh_create(*desc, fr::as_stream(stream), true);
+        *out = h.release();
+        return FR_OK;
+    });
+}
+
+fr_status fracture_mesh_create_host(const fr_mesh_desc* desc, fr_mesh* out) {
+    FR_REQUIRE(desc != nullptr && out != nullptr, "mesh_create_host: NULL argument");
+    FR_REQUIRE(desc->dim == 2 || desc->dim == 3, "mesh_create_host: dim must be 2 or 3");
+    return guard([&]() {
+        auto h = std::make_unique<fr_mesh_s>();
+        h->m = fr::mesh_create(*desc, nullptr, false);
+        *out = h.release();
+        return FR_OK;
+    });
+}
+
+fr_status fracture_mesh_cells(fr_mesh mesh, int32_t* cells, double* cell_lo, double* cell_h) {
+    FR_REQUIRE(mesh != nullptr && mesh->m, "mesh_cells: NULL mesh");
+    const fr::HostMesh& h = mesh->m->host;
+    if (cells) std::memcpy(cells, h.cells.data(), h.cells.size() * sizeof(int32_t));
+    if (cell_lo) std::memcpy(cell_lo, h.cell_lo.data(), h.cell_lo.size() * sizeof(double));
+    if (cell_h) std::memcpy(cell_h, h.cell_h.data(), h.cell_h.size() * sizeof(double));
+    return FR_OK;
+}
+
+fr_status fracture_mesh_constraints(fr_mesh mesh, int64_t* n_entries, int32_t* con_ptr, int32_t* con_master,
+                                    double* con_w) {
+    FR_REQUIRE(mesh != nullptr && mesh->m && n_entries, "mesh_constraints: NULL argument");
+    const fr::HostMesh& h = mesh->m->host;
+    *n_entries = int64_t(h.con_master.size());
+    if (con_ptr) std::memcpy(con_ptr, h.con_ptr.data(), h.con_ptr.size() * sizeof(int32_t));
+    if (con_master) std::memcpy(con_master, h.con_master.data(), h.con_master.size() * sizeof(int32_t));
+    if (con_w) std::memcpy(con_w, h.con_w.data(), h.con_w.size() * sizeof(double));
+    return FR_OK;
+}
+
+fr_status fracture_mesh_info(fr_mesh mesh, int64_t* n_nodes, int64_t* n_cells, int64_t* n_free, int64_t* n_all,
+                             int64_t* n_solve, int64_t* n_hanging, double* h_min, int64_t* nnz_node_graph) {
+    FR_REQUIRE(mesh != nullptr && mesh->m, "mesh_info: NULL mesh");
+    const fr::HostMesh& h = mesh->m->host;
+    if (n_nodes) *n_nodes = h.n_nodes;
+    if (n_cells) *n_cells = h.n_cells;
+    if (n_free) *n_free = h.n_free;
+    if (n_all) *n_all = (h.dim + 1) * h.n_nodes;
+    if (n_solve) *n_solve = (h.dim + 1) * h.n_free;
+    if (n_hanging) *n_hanging = h.n_hanging;
+    if (h_min) *h_min = h.h_min;
+    if (nnz_node_graph) *nnz_node_graph = mesh->m->pat.nnz;
+    return FR_OK;
+}
+
+fr_status fracture_mesh_nodes(fr_mesh mesh, double* xyz, int64_t* lattice, uint8_t* dirichlet, int32_t* free_index) {
+    FR_REQUIRE(mesh != nullptr && mesh->m, "mesh_nodes: NULL mesh");
+    const fr::HostMesh& h = mesh->m->host;
+    const size_t nd = size_t(h.n_nodes) * h.dim;
+    if (xyz) std::memcpy(xyz, h.coords.data(), nd * sizeof(double));
+    if (lattice) std::memcpy(lattice, h.lattice.data(), nd * sizeof(int64_t));
+    if (dirichlet) std::memcpy(dirichlet, h.dirichlet.data(), size_t(h.n_nodes));
+    if (free_index) std::memcpy(free_index, h.free_of_node.data(), size_t(h.n_nodes) * sizeof(int32_t));
+    return FR_OK;
+}
+
+void fracture_mesh_destroy(fr_mesh mesh) {
+    if (!mesh) return;
+    if (mesh->m) (void)hipStreamSynchronize(mesh->m->stream);
+    delete mesh;
+}
+
+fr_status fracture_assemble(fr_mesh mesh, const fr_params* prm, const double* u, const double* phi,
+                            const double* phi_old, const double* phi_tilde, unsigned flags, fr_system* sys,
+                            void* stream) {
+    FR_REQUIRE(mesh != nullptr && mesh->m, "assemble: NULL mesh");
+    FR_REQUIRE(mesh->m->on_device, "assemble: host-only mesh");
+    FR_REQUIRE(sys != nullptr, "assemble: NULL system pointer");
+    FR_REQUIRE((flags & ~7u) == 0 && flags != 0, "assemble: unknown or empty flags");
+    fr_status ps = check_params(prm);
+    if (ps != FR_OK) return ps;
+    if (flags & (FR_RESIDUAL | FR_JACOBIAN)) FR_REQUIRE(u && phi && phi_tilde, "assemble: u, phi, phi_tilde required");
+    if (flags & (FR_ACTIVE_SET | FR_JACOBIAN)) FR_REQUIRE(phi && phi_old, "assemble: phi, phi_old required");
+    if (*sys && (*sys)->sys.mesh != mesh->m.get()) return set_err(FR_EINVAL, "assemble: system belongs to another mesh");
+    if (!*sys && (flags & (FR_ACTIVE_SET | FR_JACOBIAN)) && !(flags & FR_RESIDUAL))
+        return set_err(FR_EINVAL, "assemble: a new system needs FR_RESIDUAL first");
+    if (*sys && (flags & FR_ACTIVE_SET) && !(flags & FR_RESIDUAL) && !(*sys)->sys.have_residual)
+        return set_err(FR_EINVAL, "assemble: FR_ACTIVE_SET needs a residual");
+    return guard([&]() {
+        hipStream_t s = fr::as_stream(stream);
+        std::unique_ptr<fr_system_s> created;
+        fr_system_s* S = *sys;
+        if (!S) {
+            created = std::make_unique<fr_system_s>();
+            S = created.get();
+            system_init(*S, *mesh->m, s);
+        }
+        S->sys.stream = s;
+        S->sys.prm = fr::make_params(*prm);
+        if (flags & FR_RESIDUAL) fr::assemble_residual(S->sys, u, phi, phi_tilde);
+        if (flags & FR_ACTIVE_SET) fr::assemble_active(S->sys, phi, phi_old);
+        if (flags & FR_JACOBIAN) fr::assemble_jacobian(S->sys, u, phi, phi_old, phi_tilde);
+        if (created) *sys = created.release();
+        return FR_OK;
+    });
+}
+
+fr_status fracture_residual_norms(fr_system sys, double* norms, int64_t* n_active, int64_t* active_changes,
+                                  double* min_margin, void* stream) {
+    FR_REQUIRE(sys != nullptr, "residual_norms: NULL system");
+    FR_REQUIRE(sys->sys.have_residual, "residual_norms: nothing assembled");
+    return guard([&]() {
+        sys->sys.stream = fr::as_stream(stream);
+        double nr[2] = {0, 0};
+        fr::system_norms(sys->sys, nullptr, nullptr, nr, n_active, min_margin);
+        if (norms) { norms[0] = nr[0]; norms[1] = nr[1]; }
+        if (active_changes) *active_changes = sys->sys.last_changes;
+        return FR_OK;
+    });
+}
+
+fr_status fracture_system_vectors(fr_system sys, double* R, double* F, double* B, uint8_t* active, void* stream) {
+    FR_REQUIRE(sys != nullptr, "system_vectors: NULL system");
+    return guard([&]() {
+        hipStream_t s = fr::as_stream(stream);
+        const fr::DevSystem& S = sys->sys;
+        const int64_t nf = S.mesh->n_free;
+        if (R) FR_HIP(hipMemcpyAsync(R, S.R.p, size_t(S.n_solve) * 8, hipMemcpyDeviceToDevice, s));
+        if (F) FR_HIP(hipMemcpyAsync(F, S.F.p, size_t(S.n_solve) * 8, hipMemcpyDeviceToDevice, s));
+        if (B) FR_HIP(hipMemcpyAsync(B, S.B.p, size_t(nf) * 8, hipMemcpyDeviceToDevice, s));
+        if (active) FR_HIP(hipMemcpyAsync(active, S.active.p, size_t(nf), hipMemcpyDeviceToDevice, s));
+        return FR_OK;
+    });
+}
+
+fr_status fracture_set_active(fr_system sys, const uint8_t* active, void* stream) {
+    FR_REQUIRE(sys != nullptr && active != nullptr, "set_active: NULL argument");
+    return guard([&]() {
+        hipStream_t s = fr::as_stream(stream);
+        fr::DevSystem& S = sys->sys;
+        FR_HIP(hipMemcpyAsync(S.active.p, active, size_t(S.mesh->n_free), hipMemcpyDeviceToDevice, s));
+        S.have_active = true;
+        return FR_OK;
+    });
+}
+
+fr_status fracture_matvec(fr_system sys, const double* x, double* y, void* stream) {
+    FR_REQUIRE(sys != nullptr && x != nullptr && y != nullptr, "matvec: NULL argument");
+    FR_REQUIRE(sys->sys.have_jacobian, "matvec: no Jacobian assembled");
+    return guard([&]() {
+        fr::jspmv(sys->sys, x, y, fr::as_stream(stream));
+        return FR_OK;
+    });
+}
+
+fr_status fracture_system_csr(fr_system sys, int64_t* nnz, int64_t* row_ptr, int32_t* col, double* val, void* stream) {
+    FR_REQUIRE(sys != nullptr && nnz != nullptr, "system_csr: NULL argument");
+    FR_REQUIRE(sys->sys.have_jacobian, "system_csr: no Jacobian assembled");
+    return guard([&]() {
+        hipStream_t s = fr::as_stream(stream);
+        fr::DevSystem& S = sys->sys;
+        const fr::DevMesh& m = *S.mesh;
+        const fr::Pattern& p = m.pat;
+        const int D = m.dim;
+        const int64_t nf = m.n_free;
+        const int64_t total = p.nnz * int64_t(D * D + D + D + 1);
+        if (!col) {
+            *nnz = total;
+            return FR_OK;
+        }
+        FR_REQUIRE(row_ptr && val && *nnz >= total, "system_csr: output arrays too small");
+        auto uu = fr::download(S.Juu.val, size_t(p.n_slots) * D * D, s);
+        auto pu = fr::download(S.Jpu.val, size_t(p.n_slots) * D, s);
+        auto pp = fr::download(S.Jpp.val, size_t(p.n_slots), s);
+        int64_t c = 0;
+        auto slot = [&](int64_t f, int k) { return int64_t(p.slice_ptr[size_t(f / p.C)]) + int64_t(k) * p.C + f % p.C; };
+        row_ptr[0] = 0;
+        for (int64_t f = 0; f < nf; ++f)
+            for (int r = 0; r < D; ++r) {
+                for (int k = 0; k < p.row_len[size_t(f)]; ++k) {
+                    const int64_t sl = slot(f, k);
+                    const int64_t g = p.col[size_t(sl)];
+                    for (int d = 0; d < D; ++d) {
+                        col[c] = int32_t(g * D + d);
+                        val[c++] = uu[size_t(sl * D * D + r * D + d)];
+                    }
+                }
+                row_ptr[f * D + r + 1] = c;
+            }
+        for (int64_t f = 0; f < nf; ++f) {
+            for (int k = 0; k < p.row_len[size_t(f)]; ++k) {
+                const int64_t sl = slot(f, k);
+                const int64_t g = p.col[size_t(sl)];
+                for (int d = 0; d < D; ++d) {
+                    col[c] = int32_t(g * D + d);
+                    val[c++] = pu[size_t(sl * D + d)];
+                }
+            }
+            for (int k = 0; k < p.row_len[size_t(f)]; ++k) {
+                const int64_t sl = slot(f, k);
+                col[c] = int32_t(D * nf + p.col[size_t(sl)]);
+                val[c++] = pp[size_t(sl)];
+            }
+            row_ptr[D * nf + f + 1] = c;
+        }
+        *nnz = c;
+        return FR_OK;
+    });
+}
+
+void fracture_system_destroy(fr_system sys) {
+    if (!sys) return;
+    (void)hipStreamSynchronize(sys->sys.stream);
+    delete sys;
+}
+
+fr_status amg_setup(fr_system sys, const fr_amg_opts* opts, fr_amg* amg, void* stream) {
+    FR_REQUIRE(sys != nullptr && amg != nullptr, "amg_setup: NULL argument");
+    FR_REQUIRE(sys->sys.have_jacobian, "amg_setup: no Jacobian assembled");
+    fr_amg_opts o = opts ? *opts : default_amg();
+    fr_status cs = check_amg(o);
+    if (cs != FR_OK) return cs;
+    if (*amg && (*amg)->amg.sys && (*amg)->amg.sys != &sys->sys) return set_err(FR_EINVAL, "amg_setup: preconditioner belongs to another system");
+    return guard([&]() {
+        hipStream_t s = fr::as_stream(stream);
+        std::unique_ptr<fr_amg_s> created;
+        fr_amg_s* A = *amg;
+        if (!A) {
+            created = std::make_unique<fr_amg_s>();
+            A = created.get();
+        }
+        fr::amg_build(A->amg, sys->sys, o, s);
+        if (created) *amg = created.release();
+        return FR_OK;
+    });
+}
+
+fr_status amg_level_info(fr_amg amg, int block, int level, int* n_levels, int64_t* rows, int* bsize,
+                         int64_t* nnz_blocks, double* lambda_max) {
+    FR_REQUIRE(amg != nullptr, "amg_level_info: NULL amg");
+    FR_REQUIRE(block == 0 || block == 1, "amg_level_info: block must be 0 or 1");
+    return guard([&]() {
+        int nl = 0, bs = 0;
+        int64_t r = 0, nz = 0;
+        double lm = 0;
+        fr::amg_info(amg->amg, block, level, nl, r, bs, nz, lm, amg->amg.stream);
+        if (n_levels) *n_levels = nl;
+        if (level < 0 || level >= nl) return set_err(FR_EINVAL, "amg_level_info: level out of range");
+        if (rows) *rows = r;
+        if (bsize) *bsize = bs;
+        if (nnz_blocks) *nnz_blocks = nz;
+        if (lambda_max) *lambda_max = lm;
+        return FR_OK;
+    });
+}
+
+fr_status amg_level_csr(fr_amg amg, int block, int level, int which, int64_t* n_rows, int64_t* n_cols, int64_t* nnz,
+                        int64_t* row_ptr, int32_t* col, double* val, void* stream) {
+    FR_REQUIRE(amg != nullptr && nnz != nullptr, "amg_level_csr: NULL argument");
+    FR_REQUIRE(block == 0 || block == 1, "amg_level_csr: block must be 0 or 1");
+    FR_REQUIRE(which >= 0 && which <= 2, "amg_level_csr: which must be 0 (A), 1 (P) or 2 (R)");
+    return guard([&]() {
+        int64_t nr = 0, nc = 0;
+        std::vector<int64_t> rp;
+        std::vector<int32_t> ci;
+        std::vector<double> vv;
+        fr::amg_level_export(amg->amg, block, level, which, nr, nc, rp, ci, vv, fr::as_stream(stream));
+        if (n_rows) *n_rows = nr;
+        if (n_cols) *n_cols = nc;
+        if (!col) {
+            *nnz = int64_t(ci.size());
+            return FR_OK;
+        }
+        if (*nnz < int64_t(ci.size()) || !row_ptr || !val) return set_err(FR_EINVAL, "amg_level_csr: output arrays too small");
+        std::memcpy(row_ptr, rp.data(), rp.size() * sizeof(int64_t));
+        std::memcpy(col, ci.data(), ci.size() * sizeof(int32_t));
+        std::memcpy(val, vv.data(), vv.size() * sizeof(double));
+        *nnz = int64_t(ci.size());
+        return FR_OK;
+    });
+}
+
+fr_status amg_apply(fr_amg amg, const double* r, double* z, void* stream) {
+    FR_REQUIRE(amg != nullptr && r != nullptr && z != nullptr, "amg_apply: NULL argument");
+    return guard([&]() {
+        fr::amg_precondition(amg->amg, r, z, fr::as_stream(stream));
+        return FR_OK;
+    });
+}
+
+void amg_destroy(fr_amg amg) {
+    if (!amg) return;
+    if (amg->amg.stream) (void)hipStreamSynchronize(amg->amg.stream);
+    delete amg;
+}
+
+fr_status fracture_solve(fr_system sys, fr_amg amg, const fr_solve_opts* opts, double* du, fr_solve_stats* stats,
+                         void* stream) {
+    FR_REQUIRE(sys != nullptr && amg != nullptr && opts != nullptr && du != nullptr, "solve: NULL argument");
+    FR_REQUIRE(sys->sys.have_jacobian, "solve: no Jacobian assembled");
+    FR_REQUIRE(amg->amg.sys == &sys->sys, "solve: preconditioner built for another system");
+    fr_status cs = check_solve(*opts);
+    if (cs != FR_OK) return cs;
+    return guard([&]() {
+        fr_solve_stats st{};
+        const fr_status r = fr::fgmres(sys->sys, amg->amg, *opts, du, st, sys->kry, fr::as_stream(stream));
+        if (stats) *stats = st;
+        if (r == FR_ENOCONV) set_err(r, "solve: iteration limit reached");
+        if (r == FR_ENAN) set_err(r, "solve: non-finite value in the Krylov iteration");
+        return r;
+    });
+}
+
+fr_status fracture_update(fr_mesh mesh, const double* du, double omega, double* u, double* phi, void* stream) {
+    FR_REQUIRE(mesh != nullptr && mesh->m && du && u && phi, "update: NULL argument");
+    FR_REQUIRE(mesh->m->on_device, "update: host-only mesh");
+    FR_REQUIRE(std::isfinite(omega), "update: omega must be finite");
+    return guard([&]() {
+        fr::mesh_update(*mesh->m, du, omega, u, phi, fr::as_stream(stream));
+        return FR_OK;
+    });
+}
+
+fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double* phi, const double* phi_old,
+                          const double* phi_tilde, const fr_amg_opts* amg_opts, const fr_solve_opts* solve_opts,
+                          const fr_newton_opts* newton_opts, fr_newton_stats* stats, void* stream) {
+    FR_REQUIRE(mesh != nullptr && mesh->m, "newton: NULL mesh");
+    FR_REQUIRE(mesh->m->on_device, "newton: host-only mesh");
+    FR_REQUIRE(u && phi && phi_old && phi_tilde, "newton: NULL state array");
+    fr_status ps = check_params(prm);
+    if (ps != FR_OK) return ps;
+    const fr_amg_opts ao = amg_opts ? *amg_opts : default_amg();
+    if (check_amg(ao) != FR_OK) return FR_EINVAL;
+    fr_solve_opts so{1e-8, 100, 500};
+    if (solve_opts) so = *solve_opts;
+    if (check_solve(so) != FR_OK) return FR_EINVAL;
+    fr_newton_opts no{1e-8, 30, 8};
+    if (newton_opts) no = *newton_opts;
+    FR_REQUIRE(no.tol > 0 && no.max_it >= 1 && no.ls_max >= 0 && no.ls_max <= 60, "newton: bad options");
+    return guard([&]() {
+        hipStream_t s = fr::as_stream(stream);
+        fr::DevMesh& m = *mesh->m;
+        fr_newton_stats ns{};
+        auto S = std::make_unique<fr_system_s>();
+        system_init(*S, m, s);
+        fr::DevSystem& sys = S->sys;
+        sys.prm = fr::make_params(*prm);
+        auto A = std::make_unique<fr_amg_s>();
+        const int64_t nn = m.n_nodes;
+        fr::DBuf<double> du, u_save, p_save;
+        du.alloc(size_t(sys.n_solve), s);
+        u_save.alloc(size_t(nn) * m.dim, s);
+        p_save.alloc(size_t(nn), s);
+        double t_asm = 0, t_setup = 0, t_solve = 0, t_other = 0;
+        {
+            EventTimer t(s);
+            fr::assemble_residual(sys, u, phi, phi_tilde);
+            fr::assemble_active(sys, phi, phi_old);
+            t_asm += t.stop();
+        }
+        double nr[2];
+        fr::system_norms(sys, nullptr, nullptr, nr, nullptr, nullptr);
+        const double r0 = nr[0];
+        double rk = r0;
+        ns.res0 = r0;
+        int it = 0;
+        fr_status status = FR_ENOCONV;
+        while (it < no.max_it) {
+            {
+                EventTimer t(s);
+                fr::assemble_jacobian(sys, u, phi, phi_old, phi_tilde);
+                t_asm += t.stop();
+            }
+            {
+                EventTimer t(s);
+                fr::amg_build(A->amg, sys, ao, s);
+                t_setup += t.stop();
+            }
+            fr_solve_stats st{};
+            {
+                EventTimer t(s);
+                const fr_status r = fr::fgmres(sys, A->amg, so, du.p, st, S->kry, s);
+                t_solve += t.stop();
+                ns.linear_iters += st.iters;
+                if (r == FR_ENAN) { status = FR_ENAN; break; }
+            }
+            EventTimer t(s);
+            // line search on ||R~|| with the current active set
+            FR_HIP(hipMemcpyAsync(u_save.p, u, size_t(nn) * m.dim * 8, hipMemcpyDeviceToDevice, s));
+            FR_HIP(hipMemcpyAsync(p_save.p, phi, size_t(nn) * 8, hipMemcpyDeviceToDevice, s));
+            for (int mm = 0; mm <= no.ls_max; ++mm) {
+                const double omega = std::ldexp(1.0, -mm);
+                if (mm > 0) {
+                    FR_HIP(hipMemcpyAsync(u, u_save.p, size_t(nn) * m.dim * 8, hipMemcpyDeviceToDevice, s));
+                    FR_HIP(hipMemcpyAsync(phi, p_save.p, size_t(nn) * 8, hipMemcpyDeviceToDevice, s));
+                }
+                fr::mesh_update(m, du.p, omega, u, phi, s);
+                fr::assemble_residual(sys, u, phi, phi_tilde);
+                fr::system_norms(sys, nullptr, nullptr, nr, nullptr, nullptr);
+                if (nr[0] < rk) break;
+            }
+            ++it;
+            if (it >= 2) fr::assemble_active_freeze(sys, phi, phi_old);
+            else fr::assemble_active(sys, phi, phi_old);
+            int64_t n_act = 0;
+            fr::system_norms(sys, nullptr, nullptr, nr, &n_act, nullptr);
+            rk = nr[0];
+            ns.n_active = n_act;
+            t_other += t.stop();
+            if (!std::isfinite(rk)) { status = FR_ENAN; break; }
+            if (sys.last_changes == 0 && rk <= no.tol * r0) { status = FR_OK; break; }
+        }
+        ns.iterations = it;
+        ns.res = rk;
+        ns.status = status;
+        ns.t_assemble = t_asm;
+        ns.t_setup = t_setup;
+        ns.t_solve = t_solve;
+        ns.t_other = t_other;
+        if (stats) *stats = ns;
+        FR_HIP(hipStreamSynchronize(s));
+        if (status == FR_ENOCONV) set_err(status, "newton: iteration limit reached");
+        return status;
+    });
+}
+
+fr_status fracture_functionals(fr_mesh mesh, const double* u, const double* phi, const double* cod_x, int n_cod,
+                               double* cod, double* tcv, void* stream) {
+    FR_REQUIRE(mesh != nullptr && mesh->m && u && phi, "functionals: NULL argument");
+    FR_REQUIRE(mesh->m->on_device, "functionals: host-only mesh");
+    FR_REQUIRE(n_cod >= 0 && n_cod <= 65535, "functionals: n_cod out of range");
+    FR_REQUIRE(n_cod == 0 || (cod_x && cod), "functionals: cod_x and cod required when n_cod > 0");
+    return guard([&]() {
+        fr::mesh_functionals(*mesh->m, u, phi, cod_x, n_cod, cod, tcv, fr::as_stream(stream));
+        return FR_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,48 @@
+// Host-side mesh, node numbering, hanging-node constraints, node-graph sparsity and the
+// node-centric assembly tables.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+#include "../../include/fracture.h"
+
+namespace fr {
+
+struct HostMesh {
+    int dim = 2, nv = 4;
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    double h_min = 0;                   // edge of the finest cell (lattice unit)
+    int64_t n_nodes = 0, n_cells = 0, n_free = 0, n_hanging = 0;
+    std::vector<double> coords;         // [n_nodes][dim]
+    std::vector<int64_t> lattice;       // [n_nodes][dim], units of h_min
+    std::vector<int32_t> cells;         // [n_cells][nv], vertex a at lower corner + bits(a) * size
+    std::vector<double> cell_lo;        // [n_cells][dim]
+    std::vector<double> cell_h;         // [n_cells]
+    std::vector<uint8_t> dirichlet;     // [n_nodes]
+    std::vector<int32_t> free_of_node;  // [n_nodes], -1 for hanging nodes
+    std::vector<int32_t> node_of_free;  // [n_free]
+    // Conformity: value(node) = sum_j con_w[j] * value(free con_master[j]), j in [con_ptr[n], con_ptr[n+1]).
+    std::vector<int32_t> con_ptr, con_master;
+    std::vector<double> con_w;
+};
+
+// Node-graph pattern in SELL-C layout plus the tables of the node-centric assembly.
+struct Pattern {
+    int C = 64;
+    int64_t n_rows = 0, n_slices = 0, n_slots = 0, nnz = 0;
+    int max_row = 0;
+    std::vector<int32_t> slice_ptr;   // [n_slices+1] first slot of each slice
+    std::vector<int32_t> row_len;     // [n_rows]
+    std::vector<int32_t> col;         // [n_slots] column (free node); padding points at the row itself
+    // Row entries: the cells (and local vertex) where the row's basis function lives.
+    std::vector<int32_t> ent_ptr;     // [n_rows+1]
+    std::vector<int32_t> ent_cell;    // [n_ent]
+    std::vector<uint8_t> ent_a;       // [n_ent] local vertex of the row node (or of its hanging dependent)
+    std::vector<double> ent_w;        // [n_ent] weight of the row's basis function at that vertex
+    std::vector<uint8_t> ent_k;       // [n_ent][nv] position of vertex b's node in the row, 255 = hanging
+};
+
+HostMesh build_mesh(const fr_mesh_desc& d);
+Pattern build_pattern(const HostMesh& m, int C);
+
+}  // namespace fr

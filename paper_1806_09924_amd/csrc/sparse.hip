@@ -1,0 +1,394 @@
+// Block SELL-C sparse kernels (HBM-streaming, one thread per block row, lanes of a wave
+// read consecutive slots), the fused coupled-Jacobian product, Chebyshev smoothing steps
+// and small deterministic device primitives (scan, dot, casts).
+#include <algorithm>
+
+#include "system.h"
+
+namespace fr {
+namespace {
+
+// MODE 0: y = A x; 1: y = b - A x; 2: y += A x
+template <typename T, int BR, int BC, int MODE>
+__global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, int C, const int32_t* __restrict__ slice_ptr,
+                                              const int32_t* __restrict__ col, const T* __restrict__ val,
+                                              const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    const int64_t s = r / C;
+    const int lane = int(r - s * C);
+    const int32_t p0 = slice_ptr[s];
+    const int w = (slice_ptr[s + 1] - p0) / C;
+    T acc[BR];
+#pragma unroll
+    for (int i = 0; i < BR; ++i) acc[i] = T(0);
+    int64_t slot = int64_t(p0) + lane;
+    for (int k = 0; k < w; ++k, slot += C) {
+        const int64_t c = col[slot];
+        const T* v = val + slot * (BR * BC);
+        T xv[BC];
+#pragma unroll
+        for (int j = 0; j < BC; ++j) xv[j] = x[c * BC + j];
+#pragma unroll
+        for (int i = 0; i < BR; ++i)
+#pragma unroll
+            for (int j = 0; j < BC; ++j) acc[i] += v[i * BC + j] * xv[j];
+    }
+#pragma unroll
+    for (int i = 0; i < BR; ++i) {
+        if (MODE == 0) y[r * BR + i] = acc[i];
+        else if (MODE == 1) y[r * BR + i] = b[r * BR + i] - acc[i];
+        else y[r * BR + i] += acc[i];
+    }
+}
+
+// Chebyshev step: r = b - A x_old; d = alpha d + beta D^-1 r; x_new = x_old + d
+template <typename T, int B>
+__global__ void __launch_bounds__(256) k_cheb(int64_t n_rows, int C, const int32_t* __restrict__ slice_ptr,
+                                              const int32_t* __restrict__ col, const T* __restrict__ val,
+                                              const T* __restrict__ invd, const T* __restrict__ x_old,
+                                              const T* __restrict__ b, T* __restrict__ d, T* __restrict__ x_new,
+                                              T alpha, T beta) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    const int64_t s = r / C;
+    const int lane = int(r - s * C);
+    const int32_t p0 = slice_ptr[s];
+    const int w = (slice_ptr[s + 1] - p0) / C;
+    T acc[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) acc[i] = T(0);
+    int64_t slot = int64_t(p0) + lane;
+    for (int k = 0; k < w; ++k, slot += C) {
+        const int64_t c = col[slot];
+        const T* v = val + slot * (B * B);
+        T xv[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) xv[j] = x_old[c * B + j];
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+#pragma unroll
+            for (int j = 0; j < B; ++j) acc[i] += v[i * B + j] * xv[j];
+    }
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+        const int64_t e = r * B + i;
+        const T res = b[e] - acc[i];
+        const T dn = (alpha != T(0) ? alpha * d[e] : T(0)) + beta * invd[e] * res;
+        d[e] = dn;
+        x_new[e] = x_old[e] + dn;
+    }
+}
+
+template <typename T>
+__global__ void k_cheb_first(int64_t n, const T* __restrict__ invd, const T* __restrict__ b, T* __restrict__ d,
+                             T* __restrict__ x, T beta) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const T v = beta * invd[i] * b[i];
+    d[i] = v;
+    x[i] = v;
+}
+
+// y = J x over the coupled system (u rows: M_uu; phi rows: M_phiu and M_phiphi).
+template <int D>
+__global__ void __launch_bounds__(256) k_jspmv(int64_t nf, int C, const int32_t* __restrict__ slice_ptr,
+                                               const int32_t* __restrict__ col, const double* __restrict__ uu,
+                                               const double* __restrict__ pu, const double* __restrict__ pp,
+                                               const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= nf) return;
+    const int64_t s = r / C;
+    const int lane = int(r - s * C);
+    const int32_t p0 = slice_ptr[s];
+    const int w = (slice_ptr[s + 1] - p0) / C;
+    const double* xp = x + D * nf;
+    double au[D], ap = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) au[i] = 0.0;
+    int64_t slot = int64_t(p0) + lane;
+    for (int k = 0; k < w; ++k, slot += C) {
+        const int64_t c = col[slot];
+        double xu[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) xu[j] = x[c * D + j];
+        const double xph = xp[c];
+        const double* vu = uu + slot * (D * D);
+        const double* vp = pu + slot * D;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) au[i] += vu[i * D + j] * xu[j];
+#pragma unroll
+        for (int j = 0; j < D; ++j) ap += vp[j] * xu[j];
+        ap += pp[slot] * xph;
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) y[r * D + i] = au[i];
+    y[D * nf + r] = ap;
+}
+
+// ---- scan ---------------------------------------------------------------------------------
+constexpr int kScanT = 256, kScanI = 8, kScanTile = kScanT * kScanI;
+
+__device__ inline int32_t block_excl_scan(int32_t v, int32_t* sh, int32_t& total) {
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    int32_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int32_t t = __shfl_up(x, o);
+        if (lane >= o) x += t;
+    }
+    if (lane == kWave - 1) sh[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t a = 0;
+        for (int i = 0; i < int(blockDim.x / kWave); ++i) { const int32_t t = sh[i]; sh[i] = a; a += t; }
+        sh[16] = a;
+    }
+    __syncthreads();
+    const int32_t r = x - v + sh[w];
+    total = sh[16];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(kScanT) k_tile_sums(const int32_t* __restrict__ in, int64_t n, int32_t* __restrict__ sums) {
+    __shared__ int32_t sh[32];
+    const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanI;
+    int32_t t = 0;
+#pragma unroll
+    for (int i = 0; i < kScanI; ++i)
+        if (base + i < n) t += in[base + i];
+    int32_t tot;
+    block_excl_scan(t, sh, tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_sums(int32_t* __restrict__ sums, int64_t nb) {
+    __shared__ int32_t sh[32];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < nb; b0 += blockDim.x) {
+        const int64_t i = b0 + threadIdx.x;
+        const int32_t v = i < nb ? sums[i] : 0;
+        int32_t tot;
+        const int32_t ex = block_excl_scan(v, sh, tot);
+        if (i < nb) sums[i] = ex + carry;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[nb] = carry;
+}
+
+__global__ void __launch_bounds__(kScanT) k_tile_scan(const int32_t* __restrict__ in, int64_t n,
+                                                      const int32_t* __restrict__ sums, int32_t* __restrict__ out) {
+    __shared__ int32_t sh[32];
+    const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanI;
+    int32_t loc[kScanI];
+    int32_t t = 0;
+#pragma unroll
+    for (int i = 0; i < kScanI; ++i) {
+        loc[i] = (base + i < n) ? in[base + i] : 0;
+        t += loc[i];
+    }
+    int32_t tot;
+    int32_t run = block_excl_scan(t, sh, tot) + sums[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kScanI; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += loc[i];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = sums[gridDim.x];
+}
+
+// ---- reductions, casts --------------------------------------------------------------------
+constexpr int kDotBlocks = 512;
+
+__global__ void __launch_bounds__(256) k_dot_parts(const double* __restrict__ x, const double* __restrict__ y, int64_t n,
+                                                   double* __restrict__ part) {
+    __shared__ double sh[16];
+    double acc = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        acc += x[i] * y[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_sum_parts(const double* __restrict__ part, int n, double* __restrict__ out) {
+    __shared__ double sh[16];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) *out = s;
+}
+
+template <typename A, typename B>
+__global__ void k_cast(const A* __restrict__ x, B* __restrict__ y, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = B(x[i]);
+}
+
+__global__ void k_fill(double* __restrict__ y, double v, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = v;
+}
+
+__global__ void k_slice_width(const int32_t* __restrict__ row_len, int64_t n_rows, int C, int64_t n_slices,
+                              int32_t* __restrict__ wC) {
+    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= n_slices) return;
+    int w = 0;
+    for (int64_t r = s * C; r < std::min<int64_t>(n_rows, (s + 1) * C); ++r) w = max(w, row_len[r]);
+    wC[s] = w * C;
+}
+
+inline int nblk(int64_t n, int t) { return int(ceil_div(n, t)); }
+
+}  // namespace
+
+int64_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
+    const int64_t nb = std::max<int64_t>(1, ceil_div(n, kScanTile));
+    DBuf<int32_t> sums;
+    sums.alloc(size_t(nb) + 1, s);
+    k_tile_sums<<<int(nb), kScanT, 0, s>>>(in, n, sums.p);
+    FR_LAUNCH_CHECK();
+    k_scan_sums<<<1, 1024, 0, s>>>(sums.p, nb);
+    FR_LAUNCH_CHECK();
+    k_tile_scan<<<int(nb), kScanT, 0, s>>>(in, n, sums.p, out);
+    FR_LAUNCH_CHECK();
+    return int64_t(download1(out + n, s));
+}
+
+void dev_dot(const double* x, const double* y, int64_t n, double* dres, DBuf<double>& scratch, hipStream_t s) {
+    scratch.reserve(kDotBlocks, s);
+    k_dot_parts<<<kDotBlocks, 256, 0, s>>>(x, y, n, scratch.p);
+    FR_LAUNCH_CHECK();
+    k_sum_parts<<<1, 256, 0, s>>>(scratch.p, kDotBlocks, dres);
+    FR_LAUNCH_CHECK();
+}
+
+double host_norm2(const double* x, int64_t n, DBuf<double>& scratch, hipStream_t s) {
+    scratch.reserve(kDotBlocks + 1, s);
+    k_dot_parts<<<kDotBlocks, 256, 0, s>>>(x, x, n, scratch.p);
+    FR_LAUNCH_CHECK();
+    k_sum_parts<<<1, 256, 0, s>>>(scratch.p, kDotBlocks, scratch.p + kDotBlocks);
+    FR_LAUNCH_CHECK();
+    return std::sqrt(download1(scratch.p + kDotBlocks, s));
+}
+
+void cast_f64_f32(const double* x, float* y, int64_t n, hipStream_t s) {
+    if (n) k_cast<double, float><<<nblk(n, 256), 256, 0, s>>>(x, y, n);
+    FR_LAUNCH_CHECK();
+}
+
+void cast_f32_f64(const float* x, double* y, int64_t n, hipStream_t s) {
+    if (n) k_cast<float, double><<<nblk(n, 256), 256, 0, s>>>(x, y, n);
+    FR_LAUNCH_CHECK();
+}
+
+void vec_copy(const double* x, double* y, int64_t n, hipStream_t s) {
+    if (n) FR_HIP(hipMemcpyAsync(y, x, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+
+void vec_fill(double* y, double v, int64_t n, hipStream_t s) {
+    if (n) k_fill<<<nblk(n, 256), 256, 0, s>>>(y, v, n);
+    FR_LAUNCH_CHECK();
+}
+
+void layout_from_lengths(SellStruct& S, hipStream_t s) {
+    S.n_slices = ceil_div(S.n_rows, S.C);
+    DBuf<int32_t> wc;
+    wc.alloc(size_t(S.n_slices) + 1, s);
+    if (S.n_slices) k_slice_width<<<nblk(S.n_slices, 256), 256, 0, s>>>(S.row_len, S.n_rows, S.C, S.n_slices, wc.p);
+    FR_LAUNCH_CHECK();
+    S.own_slice.alloc(size_t(S.n_slices) + 1, s);
+    S.slice_ptr = S.own_slice.p;
+    S.n_slots = scan_exclusive(wc.p, S.slice_ptr, S.n_slices, s);
+    if (S.n_slots >= (int64_t(1) << 31)) fail(FR_EINTERNAL, "sell: more than 2^31 slots");
+}
+
+#define FR_BLOCK_DISPATCH(BR_, BC_, CALL)                                                         \
+    if (br == BR_ && bc == BC_) { CALL(BR_, BC_); return; }
+
+#define FR_ALL_BLOCKS(CALL)                                                                       \
+    FR_BLOCK_DISPATCH(1, 1, CALL)                                                                 \
+    FR_BLOCK_DISPATCH(2, 2, CALL)                                                                 \
+    FR_BLOCK_DISPATCH(2, 3, CALL)                                                                 \
+    FR_BLOCK_DISPATCH(3, 2, CALL)                                                                 \
+    FR_BLOCK_DISPATCH(3, 3, CALL)                                                                 \
+    FR_BLOCK_DISPATCH(3, 6, CALL)                                                                 \
+    FR_BLOCK_DISPATCH(6, 3, CALL)                                                                 \
+    FR_BLOCK_DISPATCH(6, 6, CALL)                                                                 \
+    fail(FR_EINTERNAL, "spmv: unsupported block shape");
+
+template <typename T, int MODE>
+static void spmv_mode(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_t s) {
+    const int br = A.br, bc = A.bc;
+    const SellStruct& S = *A.S;
+    if (S.n_rows == 0) return;
+    const int g = nblk(S.n_rows, 256);
+#define FR_SPMV_CALL(BR_, BC_)                                                                     \
+    k_spmv<T, BR_, BC_, MODE><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, x, b, y); \
+    FR_LAUNCH_CHECK();
+    FR_ALL_BLOCKS(FR_SPMV_CALL)
+#undef FR_SPMV_CALL
+}
+
+template <typename T>
+void spmv(const BMat<T>& A, const T* x, T* y, hipStream_t s) { spmv_mode<T, 0>(A, x, nullptr, y, s); }
+template <typename T>
+void spmv_residual(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_t s) { spmv_mode<T, 1>(A, x, b, y, s); }
+template <typename T>
+void spmv_add(const BMat<T>& A, const T* x, T* y, hipStream_t s) { spmv_mode<T, 2>(A, x, nullptr, y, s); }
+
+template <typename T>
+void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d, T* x_new, T alpha, T beta,
+               hipStream_t s) {
+    const SellStruct& S = *A.S;
+    if (S.n_rows == 0) return;
+    const int g = nblk(S.n_rows, 256);
+    switch (A.br) {
+        case 1: k_cheb<T, 1><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, invd, x_old, b, d, x_new, alpha, beta); break;
+        case 2: k_cheb<T, 2><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, invd, x_old, b, d, x_new, alpha, beta); break;
+        case 3: k_cheb<T, 3><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, invd, x_old, b, d, x_new, alpha, beta); break;
+        case 6: k_cheb<T, 6><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, invd, x_old, b, d, x_new, alpha, beta); break;
+        default: fail(FR_EINTERNAL, "cheb: unsupported block size");
+    }
+    FR_LAUNCH_CHECK();
+}
+
+template <typename T>
+void cheb_first(const T* invd, const T* b, T* d, T* x, T beta, int64_t n, hipStream_t s) {
+    if (n) k_cheb_first<T><<<nblk(n, 256), 256, 0, s>>>(n, invd, b, d, x, beta);
+    FR_LAUNCH_CHECK();
+}
+
+void jspmv(const DevSystem& sys, const double* x, double* y, hipStream_t s) {
+    const SellStruct& S = *sys.Juu.S;
+    const int g = nblk(S.n_rows, 256);
+    if (sys.mesh->dim == 2)
+        k_jspmv<2><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, sys.Juu.val, sys.Jpu.val, sys.Jpp.val, x, y);
+    else
+        k_jspmv<3><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, sys.Juu.val, sys.Jpu.val, sys.Jpp.val, x, y);
+    FR_LAUNCH_CHECK();
+}
+
+void system_matvec(DevSystem& sys, const double* x, double* y) { jspmv(sys, x, y, sys.stream); }
+
+template void spmv<double>(const BMat<double>&, const double*, double*, hipStream_t);
+template void spmv<float>(const BMat<float>&, const float*, float*, hipStream_t);
+template void spmv_residual<double>(const BMat<double>&, const double*, const double*, double*, hipStream_t);
+template void spmv_residual<float>(const BMat<float>&, const float*, const float*, float*, hipStream_t);
+template void spmv_add<double>(const BMat<double>&, const double*, double*, hipStream_t);
+template void spmv_add<float>(const BMat<float>&, const float*, float*, hipStream_t);
+template void cheb_step<double>(const BMat<double>&, const double*, const double*, const double*, double*, double*,
+                                double, double, hipStream_t);
+template void cheb_step<float>(const BMat<float>&, const float*, const float*, const float*, float*, float*, float,
+                               float, hipStream_t);
+template void cheb_first<double>(const double*, const double*, double*, double*, double, int64_t, hipStream_t);
+template void cheb_first<float>(const float*, const float*, float*, float*, float, int64_t, hipStream_t);
+
+}  // namespace fr

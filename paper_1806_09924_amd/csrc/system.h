@@ -1,0 +1,164 @@
+// Device-resident objects behind the C handles: mesh, assembled system, sparse matrices
+// in block SELL-C layout, AMG hierarchies and the Krylov workspace.
+#pragma once
+#include <memory>
+#include <vector>
+
+#include "common.h"
+#include "mesh.h"
+
+namespace fr {
+
+// Material and method constants as the kernels see them.
+struct Params {
+    double E, nu, Gc, kappa, eps, p, c_pdas, tau;
+    double mu, lam;
+};
+
+Params make_params(const fr_params& p);
+
+// ---- sparse storage ---------------------------------------------------------------------
+// Block SELL-C: rows are grouped in slices of C consecutive block rows; inside a slice the
+// k-th entry of the row at lane l sits at slot slice_ptr[s] + k*C + l (lanes read
+// consecutive slots: coalesced).  A slot holds a column index and a br x bc block stored
+// row-major.  Padding slots repeat a valid column of the row with a zero block.
+struct SellStruct {
+    int C = 64;
+    int64_t n_rows = 0, n_cols = 0, n_slices = 0, n_slots = 0, nnz = 0;
+    int32_t* slice_ptr = nullptr;   // [n_slices+1]
+    int32_t* row_len = nullptr;     // [n_rows]
+    int32_t* col = nullptr;         // [n_slots]
+    DBuf<int32_t> own_slice, own_len, own_col;
+};
+
+template <typename T>
+struct BMat {
+    int br = 1, bc = 1;
+    std::shared_ptr<SellStruct> S;
+    T* val = nullptr;               // [n_slots * br * bc]
+    DBuf<T> own_val;
+    int64_t rows() const { return S ? S->n_rows : 0; }
+    int64_t cols() const { return S ? S->n_cols : 0; }
+};
+
+// ---- mesh -------------------------------------------------------------------------------
+struct DevMesh {
+    HostMesh host;
+    Pattern pat;
+    hipStream_t stream = nullptr;
+    int dim = 2, nv = 4;
+    int64_t n_nodes = 0, n_cells = 0, n_free = 0;
+    bool hanging = false;
+    bool on_device = false;                      // false: host-only mesh (inspection)
+    DBuf<int32_t> cells, node_of_free, free_of_node, con_ptr, con_master;
+    DBuf<double> cell_h, cell_lo, con_w, coords_free;
+    DBuf<uint8_t> dir_free;                      // Dirichlet flag per free node
+    std::shared_ptr<SellStruct> graph;           // node graph (free x free)
+    DBuf<int32_t> ent_ptr, ent_cell;
+    DBuf<uint8_t> ent_a, ent_k;
+    DBuf<double> ent_w;
+};
+
+std::unique_ptr<DevMesh> mesh_create(const fr_mesh_desc& d, hipStream_t s, bool upload);
+
+// ---- assembled system -------------------------------------------------------------------
+struct DevSystem {
+    DevMesh* mesh = nullptr;
+    Params prm{};
+    hipStream_t stream = nullptr;
+    int64_t n_solve = 0, n_u = 0;
+    BMat<double> Juu, Jpu, Jpp;                  // share the node-graph structure
+    DBuf<double> R, F, B;                        // residual, masked rhs, lumped mass
+    DBuf<uint8_t> active, active_prev, frozen;   // per free node
+    DBuf<double> red;                            // reduction scratch
+    DBuf<int32_t> ired;
+    bool have_residual = false, have_active = false, have_jacobian = false;
+    int64_t last_changes = 0;
+    double last_min_margin = 0.0;
+    uint64_t version = 0;                        // bumped at every Jacobian assembly
+};
+
+void assemble_residual(DevSystem& sys, const double* u, const double* phi, const double* pt);
+void assemble_active(DevSystem& sys, const double* phi, const double* phi_old);
+void assemble_active_freeze(DevSystem& sys, const double* phi, const double* phi_old);
+void assemble_jacobian(DevSystem& sys, const double* u, const double* phi, const double* phi_old,
+                       const double* pt);
+// norms: [0] ||R~||, [1] ||F||; also n_active, min |margin|
+void system_norms(DevSystem& sys, const double* phi, const double* phi_old, double* norms,
+                  int64_t* n_active, double* min_margin);
+void system_matvec(DevSystem& sys, const double* x, double* y);
+void mesh_update(DevMesh& m, const double* du, double omega, double* u, double* phi, hipStream_t s);
+void mesh_functionals(DevMesh& m, const double* u, const double* phi, const double* cod_x, int n_cod,
+                      double* cod, double* tcv, hipStream_t s);
+
+// ---- generic device primitives (sparse.hip) ---------------------------------------------
+// out[0..n] exclusive scan of in[0..n-1]; returns the total (synchronises).
+int64_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
+// sum of squares / dot in a fixed order; result written to *dres (device).
+void dev_dot(const double* x, const double* y, int64_t n, double* dres, DBuf<double>& scratch, hipStream_t s);
+double host_norm2(const double* x, int64_t n, DBuf<double>& scratch, hipStream_t s);
+void cast_f64_f32(const double* x, float* y, int64_t n, hipStream_t s);
+void cast_f32_f64(const float* x, double* y, int64_t n, hipStream_t s);
+void vec_copy(const double* x, double* y, int64_t n, hipStream_t s);
+void vec_fill(double* y, double v, int64_t n, hipStream_t s);
+void layout_from_lengths(SellStruct& S, hipStream_t s);   // row_len set -> slice_ptr, n_slots
+
+template <typename T>
+void spmv(const BMat<T>& A, const T* x, T* y, hipStream_t s);                 // y = A x
+template <typename T>
+void spmv_residual(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_t s);  // y = b - A x
+template <typename T>
+void spmv_add(const BMat<T>& A, const T* x, T* y, hipStream_t s);             // y += A x
+template <typename T>
+void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d, T* x_new,
+               T alpha, T beta, hipStream_t s);
+template <typename T>
+void cheb_first(const T* invd, const T* b, T* d, T* x, T beta, int64_t n, hipStream_t s);
+// fused J-SpMV over the three blocks: y = J x (solve order)
+void jspmv(const DevSystem& sys, const double* x, double* y, hipStream_t s);
+
+// ---- AMG (amg.hip) ----------------------------------------------------------------------
+struct AmgLevel {
+    BMat<double> A, P, R;
+    BMat<float> A32, P32, R32;
+    DBuf<double> invd;
+    DBuf<float> invd32;
+    double lmax = 0;
+    int ns = 1;                                  // near-nullspace size (block size of the next level)
+    // V-cycle work vectors (scalar length n = rows * br)
+    DBuf<double> vb, vx0, vx1, vd, vr;
+    DBuf<float> fb, fx0, fx1, fd, fr;
+};
+
+struct Hierarchy {
+    std::vector<std::unique_ptr<AmgLevel>> lv;
+    DBuf<double> dense_inv;                      // coarsest A^-1, row-major
+    int64_t n_coarse = 0;
+};
+
+struct DevAmg {
+    DevSystem* sys = nullptr;
+    fr_amg_opts opts{};
+    hipStream_t stream = nullptr;
+    Hierarchy h[2];                              // 0: u block, 1: phi block
+    uint64_t sys_version = 0;
+};
+
+void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s);
+void amg_precondition(DevAmg& amg, const double* r, double* z, hipStream_t s);
+void amg_level_export(DevAmg& amg, int blk, int level, int which, int64_t& n_rows, int64_t& n_cols,
+                      std::vector<int64_t>& rp, std::vector<int32_t>& ci, std::vector<double>& vv, hipStream_t s);
+void amg_info(DevAmg& amg, int blk, int level, int& n_levels, int64_t& rows, int& bsize, int64_t& nnzb,
+              double& lmax, hipStream_t s);
+
+// ---- Krylov (krylov.hip) ----------------------------------------------------------------
+struct DevKrylov {
+    int64_t n = 0;
+    int m = 0;
+    DBuf<double> V, Z, w, h, part, x, r;
+};
+
+fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du, fr_solve_stats& st,
+                 DevKrylov& ws, hipStream_t s);
+
+}  // namespace fr

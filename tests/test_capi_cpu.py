@@ -1,0 +1,144 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared symbol, rejects
+bad arguments before touching the device, reports a missing device, and builds meshes on
+the host (uniform and adaptive) whose counts and constraints match the paper's conventions."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1806_09924_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fracture.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:fr_status|void|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return B.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in B._SIGNATURES, f"binding lacks {n}"
+
+
+def test_version_and_error_string(lib):
+    assert B.load().fracture_version().decode().startswith("fracture-gfx950")
+    st = lib.fracture_mesh_create(None, None, None)
+    assert st == B.FR_EINVAL
+    assert "NULL" in B.last_error()
+
+
+def test_argument_validation_before_device(lib):
+    d = B.mesh_desc(4, -1.0, 1.0, 8)
+    h = ctypes.c_void_p()
+    assert lib.fracture_mesh_create(ctypes.byref(d), ctypes.byref(h), None) == B.FR_EINVAL
+    assert "dim" in B.last_error()
+    d = B.mesh_desc(2, 1.0, -1.0, 8)
+    assert lib.fracture_mesh_create(ctypes.byref(d), ctypes.byref(h), None) == B.FR_EINVAL
+    p = B.params(nu=0.7)
+    sysh = ctypes.c_void_p()
+    assert lib.fracture_assemble(None, ctypes.byref(p), None, None, None, None, 7, ctypes.byref(sysh), None) == B.FR_EINVAL
+    assert lib.fracture_solve(None, None, None, None, None, None) == B.FR_EINVAL
+    assert lib.amg_setup(None, None, None, None) == B.FR_EINVAL
+    assert lib.fracture_functionals(None, None, None, None, 0, None, None, None) == B.FR_EINVAL
+
+
+def test_host_only_mesh_is_rejected_by_device_calls(lib):
+    m = B.Mesh(B.mesh_desc(2, -1.0, 1.0, 4), host_only=True)
+    p = B.params()
+    sysh = ctypes.c_void_p()
+    assert lib.fracture_assemble(m.h, ctypes.byref(p), None, None, None, None, 1, ctypes.byref(sysh), None) == B.FR_EINVAL
+    assert "host-only" in B.last_error()
+
+
+@pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES", None) is None and os.path.exists("/dev/kfd"),
+                    reason="a GPU may be present")
+def test_missing_device_is_reported(lib):
+    st = lib.fracture_device_check()
+    assert st == B.FR_EDEVICE
+    d = B.mesh_desc(2, -1.0, 1.0, 4)
+    h = ctypes.c_void_p()
+    assert lib.fracture_mesh_create(ctypes.byref(d), ctypes.byref(h), None) == B.FR_EDEVICE
+
+
+@pytest.mark.parametrize("ref", [1, 2, 3, 4])
+def test_table1_dofs_from_library_mesh(ref):
+    n = 2 ** (ref + 3)
+    m = B.Mesh(B.mesh_desc(2, -1.0, 1.0, n), host_only=True)
+    table = {1: 867, 2: 3267, 3: 12675, 4: 49923}
+    assert m.n_all == table[ref] and m.n_solve == m.n_all and m.n_hanging == 0
+    assert m.nnz_graph == (3 * n - 1) ** 2 if False else True
+    # node graph of a uniform Q1 mesh: 9-point stencil
+    deg = np.array([3] * 2 + [3] * 0)
+    assert m.nnz_graph == (3 * (n + 1) - 2) ** 2
+
+
+def test_uniform_mesh_matches_oracle_numbering():
+    from oracle import mesh as omesh
+    for dim, n in ((2, 6), (3, 3)):
+        m = B.Mesh(B.mesh_desc(dim, -2.0, 2.0, n), host_only=True)
+        xyz, lat, dirichlet, free = m.nodes()
+        om = omesh.uniform(dim, -2.0, 2.0, n)
+        assert np.array_equal(lat, om.lattice)
+        assert np.allclose(xyz, om.coords, rtol=0, atol=1e-15)
+        assert np.array_equal(dirichlet.astype(bool), om.dirichlet)
+        cells, lo, h = m.cells()
+        assert np.array_equal(cells, om.cells)
+        assert np.array_equal(free, np.arange(m.n_nodes))
+
+
+def _check_conformity(m):
+    """Hanging nodes sit at edge midpoints (2d) / edge midpoints or face centres (3d) of a
+    coarser neighbour and their weights interpolate linear functions exactly."""
+    xyz, lat, dirichlet, free = m.nodes()
+    ptr, mas, w = m.constraints()
+    node_of_free = np.nonzero(free >= 0)[0]
+    hang = np.nonzero(free < 0)[0]
+    assert len(hang) == m.n_hanging
+    rng = np.random.default_rng(0)
+    a = rng.standard_normal(m.dim)
+    lin = xyz @ a + 0.3
+    for n in hang:
+        js = slice(ptr[n], ptr[n + 1])
+        assert np.isclose(w[js].sum(), 1.0)
+        assert len(w[js]) in (2, 4)
+        assert np.isclose((w[js] * lin[node_of_free[mas[js]]]).sum(), lin[n], atol=1e-12)
+    for n in node_of_free:
+        assert ptr[n + 1] - ptr[n] == 1 and w[ptr[n]] == 1.0
+
+
+def test_adaptive_quadtree_balance_and_constraints():
+    d = B.mesh_desc(2, -2.0, 2.0, 8, levels=3, refine_radius=0.3, crack_center=(0.0, 0.0), crack_half_len=0.5)
+    m = B.Mesh(d, host_only=True)
+    assert m.n_hanging > 0
+    assert np.isclose(m.h_min, 0.5 / 8)
+    cells, lo, h = m.cells()
+    # cells tile the domain
+    assert np.isclose((h ** 2).sum(), 16.0)
+    # 2:1 balance: neighbouring cells (sharing a point) differ by at most one level
+    centers = lo + 0.5 * h[:, None]
+    for i in range(len(h)):
+        near = np.all(np.abs(centers - centers[i]) <= 0.5 * (h + h[i])[:, None] + 1e-12, axis=1)
+        assert np.all(h[near] <= 2 * h[i] + 1e-12) and np.all(h[near] >= 0.5 * h[i] - 1e-12)
+    _check_conformity(m)
+
+
+def test_adaptive_octree_constraints():
+    d = B.mesh_desc(3, -1.0, 1.0, 4, levels=2, refine_radius=0.2, crack_center=(0.0, 0.0, 0.0), crack_half_len=0.4)
+    m = B.Mesh(d, host_only=True)
+    assert m.n_hanging > 0
+    cells, lo, h = m.cells()
+    assert np.isclose((h ** 3).sum(), 8.0)
+    _check_conformity(m)
