@@ -846,10 +846,17 @@ static BMat<double> tentative(const BMat<double>& A, const DBuf<int32_t>& agg, i
     Bc.alloc(size_t(std::max<int64_t>(1, n_agg)) * ns * ns, s);
     const int g = nblk(n_agg, 64);
     const int C = P.S->C;
+    // level 0 builds the near-null space from coordinates; coarser levels read the R
+    // factors of the level above, which must exist
+    if (!level0 && Bf == nullptr) fail(FR_EINTERNAL, "tentative: coarse level without a near-null space");
     if (level0 && br == 2 && ns == 3)
         k_tentative<2, 3, true><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p);
     else if (level0 && br == 3 && ns == 6)
         k_tentative<3, 6, true><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p);
+    else if (level0 && br == 1 && ns == 1)
+        k_tentative<1, 1, true><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p);
+    else if (level0)
+        fail(FR_EINTERNAL, "tentative: unsupported level-0 block shape");
     else if (br == 1 && ns == 1)
         k_tentative<1, 1, false><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p);
     else if (br == 3 && ns == 3)
