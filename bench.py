@@ -1,0 +1,187 @@
+"""Benchmark: the Newton / active-set loop of one loading step of the 2d Sneddon problem on a
+uniform 2048 x 2048 Q1 mesh of [-10, 10]^2 (12,595,203 DoFs), on one MI355X.
+
+One step = reset the state to (u = 0, phi = phi_0) and run the whole loop: assembly of the
+residual and masked Jacobian, active set, AMG setup of both diagonal blocks, FGMRES to the
+1e-8 relative residual, line search and stop test, repeated until the Newton loop stops.
+
+value = N_solve * (FGMRES iterations summed over the K timed steps) / wall time / 1e6
+        (MDoF-iter/s, the whole loop in the denominator).  Also printed: the FGMRES-only
+rate, the same loop with the FP32 AMG hierarchy, the per-kernel roofline of the dominant
+kernel from HIP events inside the timed region, and the FP64 oracle's rate on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Newton linear-solve MDoF-iter/s + HBM GB/s; FP32-AMG vs FP64 at 1e-8 residual"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=2048, help="cells per axis (2048 is the benchmark workload)")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=256, help="cells per axis of the oracle's sample")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n_cpu, L_full, n_full, iters_per_newton):
+    """The FP64 oracle (one exact Newton step: residual, active set, masked Jacobian, block
+    forward substitution by sparse LU) on a square of the benchmark mesh with the same h,
+    eps and crack, timed on this host."""
+    import numpy as np
+    from oracle import mesh as omesh, newton as onewton
+    from oracle.material import Params as OParams
+    from inputs import crack_band_phi
+    h = 2 * L_full / n_full
+    L = 0.5 * n_cpu * h
+    m = omesh.uniform(2, -L, L, n_cpu)
+    prm = OParams(eps=2 * h, kappa=1e-10, p=1e-3)
+    phi0 = crack_band_phi(m.coords, 0.25, prm.eps)
+    u0 = np.zeros((m.n_nodes, 2))
+    c0, t0 = time.process_time(), time.perf_counter()
+    st = onewton.newton_step_system(m, prm, u0, phi0, phi0, phi0)
+    onewton.solve_block(m, st.Jm, st.F)
+    t1, c1 = time.perf_counter(), time.process_time()
+    wall = t1 - t0
+    cores = max(1, int(round((c1 - c0) / wall)))
+    value = m.n_solve * iters_per_newton / wall / 1e6
+    return dict(value=value, unit="MDoF-iter/s", cores=cores, kind="oracle",
+                sample=(f"one exact Newton step (assembly + active set + masked Jacobian + sparse-LU block "
+                        f"forward substitution) on [-{L:g},{L:g}]^2 with {n_cpu}^2 cells, the benchmark's h, eps "
+                        f"and crack: N_solve={m.n_solve}, {wall:.2f} s; value = N_solve x the GPU's FGMRES "
+                        f"iterations per Newton step ({iters_per_newton:.1f}) / time"),
+                seconds=wall, n_solve=m.n_solve)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the batched and domain-decomposed sharding is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1806_09924_amd import binding as B
+    from inputs import crack_band_phi
+
+    torch.cuda.set_device(0)
+    L, n, l0 = 10.0, args.n, 0.25
+    h = 2 * L / n
+    eps = 2 * h
+    log(f"mesh {n}x{n} on [-{L},{L}]^2")
+    mesh = B.Mesh(B.mesh_desc(2, -L, L, n))
+    xyz = mesh.nodes()[0]
+    phi0_h = crack_band_phi(xyz, l0, eps)
+    dev = torch.device("cuda:0")
+    phi0 = torch.as_tensor(phi0_h, dtype=torch.float64, device=dev)
+    u = torch.zeros((mesh.n_nodes, 2), dtype=torch.float64, device=dev)
+    phi = phi0.clone()
+    prm = B.params(E=1.0, nu=0.2, Gc=1.0, kappa=1e-10, eps=eps, p=1e-3)
+    sopts = B.solve_opts(rtol=1e-8, restart=100, maxit=500)
+    nopts = B.newton_opts(tol=1e-8, max_it=30, ls_max=8)
+
+    def step(precision):
+        u.zero_()
+        phi.copy_(phi0)
+        return B.newton(mesh, prm, u, phi, phi0, phi0, amg=B.amg_opts(precision=precision), solve=sopts,
+                        newton=nopts)
+
+    def run(precision, steps, warmup, profile):
+        for i in range(warmup):
+            st = step(precision)
+            log(f"warmup fp{precision}: newton={st['iterations']} fgmres={st['linear_iters']} "
+                f"asm={st['t_assemble']:.3f}s setup={st['t_setup']:.3f}s solve={st['t_solve']:.3f}s")
+        torch.cuda.synchronize()
+        if profile:
+            B.profile(True)
+        stats = []
+        t0 = time.perf_counter()
+        for i in range(steps):
+            stats.append(step(precision))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = B.profile_read() if profile else {}
+        if profile:
+            B.profile(False)
+        for st in stats:
+            log(f"fp{precision}: newton={st['iterations']} fgmres={st['linear_iters']} "
+                f"asm={st['t_assemble']:.3f}s setup={st['t_setup']:.3f}s solve={st['t_solve']:.3f}s "
+                f"other={st['t_other']:.3f}s status={st['status']}")
+        return t1 - t0, stats, prof
+
+    wall, stats, prof = run(64, args.steps, args.warmup, not args.no_profile)
+    iters = sum(s["linear_iters"] for s in stats)
+    t_solve = sum(s["t_solve"] for s in stats)
+    newton_its = sum(s["iterations"] for s in stats)
+    value = mesh.n_solve * iters / wall / 1e6
+    cod, tcv = B.functionals(mesh, u, phi, [[h / 2]])
+    tcv_exact = 2 * np.pi * 1e-3 * l0 ** 2 * (1 - 0.2 ** 2)
+    out = {
+        "metric": METRIC, "value": value, "unit": "MDoF-iter/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"sneddon2d_{n}: 2d Sneddon, [-10,10]^2, {n}x{n} Q1, eps=2h, l0=0.25, p=1e-3, E=1, "
+                               f"nu=0.2, Gc=1, kappa=1e-10, full Newton/active-set loop, FGMRES rtol 1e-8, "
+                               f"FP64 SA-AMG block preconditioner",
+                   "n_solve": mesh.n_solve, "n_all": mesh.n_all},
+        "newton_iterations_per_step": newton_its / args.steps,
+        "fgmres_iterations_per_newton": iters / max(1, newton_its),
+        "solve_only_mdof_iter_s": mesh.n_solve * iters / t_solve / 1e6,
+        "phase_seconds_per_step": {k: sum(s[k] for s in stats) / args.steps
+                                   for k in ("t_assemble", "t_setup", "t_solve", "t_other")},
+        "tcv": tcv, "tcv_sneddon": tcv_exact, "tcv_rel_err_vs_sneddon": tcv / tcv_exact - 1,
+        "cod_center": float(cod[0]),
+    }
+    if prof:
+        kern = {k: v for k, v in prof.items() if not k.startswith("vcycle")}
+        dom = max(kern, key=lambda k: kern[k]["ms"])
+        d = kern[dom]
+        avg_ms = d["ms"] / d["launches"]
+        bytes_per = d["bytes"] / d["launches"]
+        ach = bytes_per / (avg_ms * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                           "bytes_per_launch": bytes_per, "avg_launch_ms": avg_ms, "launches": d["launches"]}
+        out["kernels"] = {k: {"launches": v["launches"], "ms_total": v["ms"],
+                              "gbs": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 and v["bytes"] > 0 else None}
+                          for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
+    if not args.no_fp32:
+        w32, s32, p32 = run(32, args.steps, 1, True)
+        it32 = sum(s["linear_iters"] for s in s32)
+        ts32 = sum(s["t_solve"] for s in s32)
+        v32 = mesh.n_solve * it32 / w32 / 1e6
+        out["fp32_amg"] = {
+            "value": v32, "ms_per_step": 1e3 * w32 / args.steps,
+            "fgmres_iterations_per_newton": it32 / max(1, sum(s["iterations"] for s in s32)),
+            "solve_only_mdof_iter_s": mesh.n_solve * it32 / ts32 / 1e6,
+            "speedup_whole_step": (wall / args.steps) / (w32 / args.steps),
+            "speedup_time_to_solution": t_solve / ts32,
+            "vcycle_ms": {k: v["ms"] for k, v in p32.items() if k.startswith("vcycle")},
+        }
+        if prof:
+            out["fp32_amg"]["vcycle_ms_fp64"] = {k: v["ms"] for k, v in prof.items() if k.startswith("vcycle")}
+    if not args.no_cpu:
+        log("oracle timing on the host")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, L, n, out["fgmres_iterations_per_newton"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -250,6 +250,19 @@ fr_status fracture_functionals(fr_mesh mesh, const double* u, const double* phi,
                                const double* cod_x, int n_cod, double* cod, double* tcv,
                                void* stream);
 
+/* ---- kernel timing ---------------------------------------------------------------- */
+
+/* enable != 0 starts recording a HIP event pair on the launch stream around every launch
+ * of the sparse, smoother, coupled-Jacobian and Gram-Schmidt kernels (and one pair around
+ * each block's V-cycle), together with the algorithmic bytes each launch must move;
+ * 0 stops. Either call discards what was recorded. */
+fr_status fracture_profile(int enable);
+
+/* Entry i of the recording (host outputs): kernel name (valid until the next
+ * fracture_profile call), launches, summed event time in ms, summed algorithmic bytes.
+ * FR_EINVAL once i is past the last entry. Synchronises the recorded events. */
+fr_status fracture_profile_read(int i, const char** name, int64_t* launches, double* ms, double* bytes);
+
 /* ---- misc ------------------------------------------------------------------------- */
 
 const char* fracture_last_error(void);

@@ -93,6 +93,8 @@ _SIGNATURES = {
     "fracture_newton": [_P, ctypes.POINTER(Params), _P, _P, _P, _P, ctypes.POINTER(AmgOpts),
                         ctypes.POINTER(SolveOpts), ctypes.POINTER(NewtonOpts), ctypes.POINTER(NewtonStats), _P],
     "fracture_functionals": [_P, _P, _P, _P, ctypes.c_int, _P, _P, _P],
+    "fracture_profile": [ctypes.c_int],
+    "fracture_profile_read": [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), _I64P, _DP, _DP],
     "fracture_last_error": [],
     "fracture_device_check": [],
     "fracture_version": [],
@@ -361,3 +363,24 @@ def functionals(mesh, u, phi, cod_x=()):
 
 def device_check():
     return load().fracture_device_check()
+
+
+def profile(enable):
+    """Starts (True) or stops (False) per-kernel HIP-event timing inside the library."""
+    _check(load().fracture_profile(1 if enable else 0))
+
+
+def profile_read():
+    """{kernel: dict(launches, ms, bytes)} of the current recording."""
+    lib = load()
+    out = {}
+    i = 0
+    while True:
+        name = ctypes.c_char_p()
+        n = ctypes.c_int64()
+        ms, by = ctypes.c_double(), ctypes.c_double()
+        if lib.fracture_profile_read(i, ctypes.byref(name), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)) != FR_OK:
+            break
+        out[name.value.decode()] = dict(launches=n.value, ms=ms.value, bytes=by.value)
+        i += 1
+    return out

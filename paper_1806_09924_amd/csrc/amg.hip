@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "profile.h"
 #include "system.h"
 
 namespace fr {
@@ -622,10 +623,18 @@ std::shared_ptr<SellStruct> new_struct(int64_t n_rows, int64_t n_cols, hipStream
     return S;
 }
 
+int64_t block_nnz(const SellStruct& S, hipStream_t s) {
+    auto len = download(S.row_len, size_t(S.n_rows), s);
+    int64_t t = 0;
+    for (int32_t v : len) t += v;
+    return t;
+}
+
 void finish_struct(SellStruct& S, hipStream_t s) {
     layout_from_lengths(S, s);
     S.own_col.alloc(size_t(std::max<int64_t>(1, S.n_slots)), s);
     S.col = S.own_col.p;
+    S.nnz = block_nnz(S, s);
 }
 
 #define FR_SPGEMM_CASE(BRA_, BCA_, BCB_)                                                                   \
@@ -698,13 +707,6 @@ BMat<double> transpose(const BMat<double>& P, hipStream_t s) {
     FR_TR_CASE(6, 6)
 #undef FR_TR_CASE
     fail(FR_EINTERNAL, "transpose: unsupported block shape");
-}
-
-int64_t block_nnz(const SellStruct& S, hipStream_t s) {
-    auto len = download(S.row_len, size_t(S.n_rows), s);
-    int64_t t = 0;
-    for (int32_t v : len) t += v;
-    return t;
 }
 
 // lambda_max(D^-1 A) by power iteration from a fixed pseudo-random start vector: with
@@ -1088,6 +1090,7 @@ void amg_precondition(DevAmg& amg, const double* r, double* z, hipStream_t s) {
     const int64_t off[2] = {0, nu};
     for (int blk = 0; blk < 2; ++blk) {
         Hierarchy& H = amg.h[blk];
+        ProfScope ps(blk == 0 ? "vcycle_u" : "vcycle_phi", s, 0.0);
         if (amg.opts.precision == 32) {
             AmgLevel& L0 = *H.lv[0];
             cast_f64_f32(r + off[blk], L0.fb.p, nb[blk], s);

@@ -6,6 +6,7 @@
 #include <memory>
 #include <string>
 
+#include "profile.h"
 #include "system.h"
 
 namespace fr {
@@ -161,6 +162,20 @@ struct EventTimer {
 extern "C" {
 
 const char* fracture_last_error(void) { return g_err.c_str(); }
+
+fr_status fracture_profile(int enable) {
+    return guard([&]() {
+        fr::prof_enable(enable != 0);
+        return FR_OK;
+    });
+}
+
+fr_status fracture_profile_read(int i, const char** name, int64_t* launches, double* ms, double* bytes) {
+    return guard([&]() {
+        if (!fr::prof_read(i, name, launches, ms, bytes)) return set_err(FR_EINVAL, "profile_read: no such entry");
+        return FR_OK;
+    });
+}
 
 const char* fracture_version(void) { return "fracture-gfx950 0.1"; }
 

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <vector>
 
+#include "profile.h"
 #include "system.h"
 
 namespace fr {
@@ -182,20 +183,34 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
             jspmv(sys, Zj, ws.w.p, s);
             const int nv = j + 1;
             const dim3 gd(kRowBlocks, unsigned(ceil_div(nv, kGroup)));
+            const double md_bytes = double(nv + 1) * double(n) * 8.0;
+            const double up_bytes = double(nv + 2) * double(n) * 8.0;
             // pass 1
-            k_multidot<<<gd, 256, 0, s>>>(ws.V.p, n, nv, ws.w.p, part);
-            FR_LAUNCH_CHECK();
+            {
+                ProfScope ps("gs_multidot", s, md_bytes);
+                k_multidot<<<gd, 256, 0, s>>>(ws.V.p, n, nv, ws.w.p, part);
+                FR_LAUNCH_CHECK();
+            }
             k_reduce_parts<<<nv, 256, 0, s>>>(part, kRowBlocks, h, 0);
             FR_LAUNCH_CHECK();
-            k_update<<<gridN, 256, 0, s>>>(ws.V.p, n, nv, h, ws.w.p, nullptr);
-            FR_LAUNCH_CHECK();
+            {
+                ProfScope ps("gs_update", s, up_bytes);
+                k_update<<<gridN, 256, 0, s>>>(ws.V.p, n, nv, h, ws.w.p, nullptr);
+                FR_LAUNCH_CHECK();
+            }
             // pass 2 (re-orthogonalisation); the correction is added to h
-            k_multidot<<<gd, 256, 0, s>>>(ws.V.p, n, nv, ws.w.p, part);
-            FR_LAUNCH_CHECK();
+            {
+                ProfScope ps("gs_multidot", s, md_bytes);
+                k_multidot<<<gd, 256, 0, s>>>(ws.V.p, n, nv, ws.w.p, part);
+                FR_LAUNCH_CHECK();
+            }
             k_reduce_parts<<<nv, 256, 0, s>>>(part, kRowBlocks, h2, 0);
             FR_LAUNCH_CHECK();
-            k_update<<<gridN, 256, 0, s>>>(ws.V.p, n, nv, h2, ws.w.p, part);
-            FR_LAUNCH_CHECK();
+            {
+                ProfScope ps("gs_update", s, up_bytes);
+                k_update<<<gridN, 256, 0, s>>>(ws.V.p, n, nv, h2, ws.w.p, part);
+                FR_LAUNCH_CHECK();
+            }
             reduce_to(h + nv, gridN);       // ||w||^2 in h[j+1]
             k_scale_copy<<<int(ceil_div(n, 256)), 256, 0, s>>>(n, ws.w.p, h + nv, ws.V.p + int64_t(j + 1) * n);
             FR_LAUNCH_CHECK();

@@ -2,7 +2,9 @@
 // read consecutive slots), the fused coupled-Jacobian product, Chebyshev smoothing steps
 // and small deterministic device primitives (scan, dot, casts).
 #include <algorithm>
+#include <cstdio>
 
+#include "profile.h"
 #include "system.h"
 
 namespace fr {
@@ -330,6 +332,11 @@ static void spmv_mode(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_
     const SellStruct& S = *A.S;
     if (S.n_rows == 0) return;
     const int g = nblk(S.n_rows, 256);
+    char name[48];
+    std::snprintf(name, sizeof(name), "spmv_%s_%dx%d_m%d", sizeof(T) == 8 ? "f64" : "f32", br, bc, MODE);
+    const double bytes = double(S.nnz) * (br * bc * sizeof(T) + 4) + double(S.n_cols) * bc * sizeof(T) +
+                         double(S.n_rows) * br * sizeof(T) * (MODE == 0 ? 1 : 2);
+    ProfScope ps(name, s, bytes);
 #define FR_SPMV_CALL(BR_, BC_)                                                                     \
     k_spmv<T, BR_, BC_, MODE><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, x, b, y); \
     FR_LAUNCH_CHECK();
@@ -350,6 +357,11 @@ void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d
     const SellStruct& S = *A.S;
     if (S.n_rows == 0) return;
     const int g = nblk(S.n_rows, 256);
+    char name[48];
+    std::snprintf(name, sizeof(name), "cheb_%s_b%d", sizeof(T) == 8 ? "f64" : "f32", A.br);
+    // matrix once, x gathered once, b, d, D^-1 read, d and x_new written
+    const double bytes = double(S.nnz) * (A.br * A.bc * sizeof(T) + 4) + double(S.n_rows) * A.br * sizeof(T) * 6;
+    ProfScope ps(name, s, bytes);
     switch (A.br) {
         case 1: k_cheb<T, 1><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, invd, x_old, b, d, x_new, alpha, beta); break;
         case 2: k_cheb<T, 2><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, invd, x_old, b, d, x_new, alpha, beta); break;
@@ -369,6 +381,9 @@ void cheb_first(const T* invd, const T* b, T* d, T* x, T beta, int64_t n, hipStr
 void jspmv(const DevSystem& sys, const double* x, double* y, hipStream_t s) {
     const SellStruct& S = *sys.Juu.S;
     const int g = nblk(S.n_rows, 256);
+    const int D = sys.mesh->dim;
+    const double bytes = double(S.nnz) * ((D * D + D + 1) * 8 + 4) + double(S.n_rows) * (D + 1) * 8 * 2;
+    ProfScope ps(D == 2 ? "jspmv_d2" : "jspmv_d3", s, bytes);
     if (sys.mesh->dim == 2)
         k_jspmv<2><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, sys.Juu.val, sys.Jpu.val, sys.Jpp.val, x, y);
     else
