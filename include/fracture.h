@@ -84,6 +84,10 @@ typedef struct {
     double cheb_ratio;   /* smoothing interval [lambda_max / ratio, lambda_max] */
     int coarse_max;      /* coarsest level solved densely once it has <= coarse_max rows */
     int max_levels;      /* cap on the number of levels (>= 1) */
+    int reuse_u_block;   /* nonzero: amg_setup keeps an existing displacement-block hierarchy.
+                            M_uu depends only on phi_tilde and the Dirichlet set, so within one
+                            loading step it does not change between Newton iterations;
+                            fracture_newton rebuilds it once per call when this is set. */
 } fr_amg_opts;
 
 /* FGMRES options (right preconditioned, x0 = 0). */

@@ -35,7 +35,8 @@ class Params(ctypes.Structure):
 
 class AmgOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("theta", ctypes.c_double), ("cheb_degree", ctypes.c_int),
-                ("cheb_ratio", ctypes.c_double), ("coarse_max", ctypes.c_int), ("max_levels", ctypes.c_int)]
+                ("cheb_ratio", ctypes.c_double), ("coarse_max", ctypes.c_int), ("max_levels", ctypes.c_int),
+                ("reuse_u_block", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -149,8 +150,9 @@ def params(E=1.0, nu=0.2, Gc=1.0, kappa=1e-10, eps=1.0 / 16, p=1e-3, c_pdas=1.0,
     return Params(E, nu, Gc, kappa, eps, p, c_pdas, tau_pdas)
 
 
-def amg_opts(precision=64, theta=0.02, cheb_degree=2, cheb_ratio=20.0, coarse_max=500, max_levels=10):
-    return AmgOpts(precision, theta, cheb_degree, cheb_ratio, coarse_max, max_levels)
+def amg_opts(precision=64, theta=0.02, cheb_degree=2, cheb_ratio=20.0, coarse_max=256, max_levels=10,
+             reuse_u_block=1):
+    return AmgOpts(precision, theta, cheb_degree, cheb_ratio, coarse_max, max_levels, reuse_u_block)
 
 
 def solve_opts(rtol=1e-8, restart=100, maxit=500):

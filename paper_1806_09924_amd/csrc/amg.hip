@@ -333,83 +333,103 @@ struct SellV {
 
 SellV sv(const SellStruct& S) { return SellV{S.C, S.n_rows, S.slice_ptr, S.row_len, S.col}; }
 
+// Hashed SpGEMM symbolic phase.  A group of G lanes (G in {8,16,32,64}) owns one output
+// row and an LDS hash set of HS = 16 G slots; a wave holds 64/G rows.  The set of columns
+// is deterministic, the order of the table is not, so the fill kernel ranks the entries.
+template <int G>
 __device__ __forceinline__ bool hash_insert(int32_t* tab, int32_t c, int& cnt) {
-    uint32_t h = hash32(uint32_t(c)) & (kHash - 1);
-    for (int probe = 0; probe < kHash; ++probe) {
+    constexpr int HS = 16 * G;
+    uint32_t h = hash32(uint32_t(c)) & (HS - 1);
+    for (int probe = 0; probe < HS; ++probe) {
         const int32_t old = atomicCAS(&tab[h], -1, c);
         if (old == -1) { cnt++; return true; }
         if (old == c) return true;
-        h = (h + 1) & (kHash - 1);
+        h = (h + 1) & (HS - 1);
     }
     return false;
 }
 
-// Builds the hash set of the columns of row r of A*B in this wave's LDS table.
-__device__ void spgemm_row_set(const SellV& A, const SellV& B, int64_t r, int32_t* tab, int lane, int& added,
+template <int G>
+__device__ __forceinline__ int group_sum(int v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Builds the hash set of the columns of row r of A*B in this group's LDS table.
+template <int G>
+__device__ void spgemm_row_set(const SellV& A, const SellV& B, int64_t r, int32_t* tab, int lg, int& added,
                                int* overflow) {
-    for (int i = lane; i < kHash; i += kWave) tab[i] = -1;
+    constexpr int HS = 16 * G;
+    for (int i = lg; i < HS; i += G) tab[i] = -1;
     __syncthreads();
     if (r < A.n_rows) {
         const int la = A.len[r];
-        for (int ka = lane; ka < la; ka += kWave) {
+        for (int ka = lg; ka < la; ka += G) {
             const int64_t k = A.col[sslot(A.sp, A.C, r, ka)];
             const int lb = B.len[k];
             for (int kb = 0; kb < lb; ++kb) {
                 const int32_t c = B.col[sslot(B.sp, B.C, k, kb)];
-                if (!hash_insert(tab, c, added)) { atomicOr(overflow, 1); break; }
+                if (!hash_insert<G>(tab, c, added)) { atomicOr(overflow, 1); break; }
             }
         }
     }
     __syncthreads();
 }
 
+template <int G>
 __global__ void __launch_bounds__(256) k_spgemm_count(SellV A, SellV B, int32_t* __restrict__ clen,
                                                       int* __restrict__ overflow) {
     __shared__ int32_t tab[kWavesPerBlock][kHash];
-    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t r = int64_t(blockIdx.x) * kWavesPerBlock + w;
+    constexpr int RPW = kWave / G, HS = 16 * G;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, gi = lane / G, lg = lane % G;
+    const int64_t r = (int64_t(blockIdx.x) * kWavesPerBlock + w) * RPW + gi;
     int added = 0;
-    spgemm_row_set(A, B, r, tab[w], lane, added, overflow);
-    const int tot = wave_sum_int(added);
-    if (r < A.n_rows && lane == 0) {
+    spgemm_row_set<G>(A, B, r, &tab[w][gi * HS], lg, added, overflow);
+    const int tot = group_sum<G>(added);
+    if (r < A.n_rows && lg == 0) {
         clen[r] = tot;
-        if (tot > (kHash * 3) / 4) atomicOr(overflow, 1);
+        if (tot > (HS * 3) / 4) atomicOr(overflow, 1);
     }
 }
 
+template <int G>
 __global__ void __launch_bounds__(256) k_spgemm_fill(SellV A, SellV B, SellV Cm, int32_t* __restrict__ ccol,
                                                      int* __restrict__ overflow) {
     __shared__ int32_t tab[kWavesPerBlock][kHash];
     __shared__ int32_t lst[kWavesPerBlock][kHash];
-    __shared__ int32_t nl[kWavesPerBlock];
-    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t r = int64_t(blockIdx.x) * kWavesPerBlock + w;
+    __shared__ int32_t nl[kWavesPerBlock][kWave / G];
+    constexpr int RPW = kWave / G, HS = 16 * G;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, gi = lane / G, lg = lane % G;
+    const int64_t r = (int64_t(blockIdx.x) * kWavesPerBlock + w) * RPW + gi;
+    int32_t* mytab = &tab[w][gi * HS];
+    int32_t* mylst = &lst[w][gi * HS];
     int added = 0;
-    if (lane == 0) nl[w] = 0;
-    spgemm_row_set(A, B, r, tab[w], lane, added, overflow);
-    for (int i = lane; i < kHash; i += kWave) {
-        const int32_t v = tab[w][i];
-        if (v >= 0) lst[w][atomicAdd(&nl[w], 1)] = v;
+    if (lg == 0) nl[w][gi] = 0;
+    spgemm_row_set<G>(A, B, r, mytab, lg, added, overflow);
+    for (int i = lg; i < HS; i += G) {
+        const int32_t v = mytab[i];
+        if (v >= 0) mylst[atomicAdd(&nl[w][gi], 1)] = v;
     }
     __syncthreads();
     if (r >= A.n_rows) return;
-    const int n = nl[w];
+    const int n = nl[w][gi];
     const int64_t s0 = r / Cm.C;
     const int width = (Cm.sp[s0 + 1] - Cm.sp[s0]) / Cm.C;
     int32_t first = -1;
-    for (int i = lane; i < n; i += kWave) {
-        const int32_t v = lst[w][i];
+    for (int i = lg; i < n; i += G) {
+        const int32_t v = mylst[i];
         int rk = 0;
-        for (int j = 0; j < n; ++j) rk += lst[w][j] < v;
+        for (int j = 0; j < n; ++j) rk += mylst[j] < v;
         ccol[sslot(Cm.sp, Cm.C, r, rk)] = v;
         if (rk == 0) first = v;
     }
     // padding slots repeat the first column
     int32_t f = first;
 #pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) f = max(f, __shfl_xor(f, o));
+    for (int o = G / 2; o > 0; o >>= 1) f = max(f, __shfl_xor(f, o));
     if (f < 0) f = 0;
-    for (int k = n + lane; k < width; k += kWave) ccol[sslot(Cm.sp, Cm.C, r, k)] = f;
+    for (int k = n + lg; k < width; k += G) ccol[sslot(Cm.sp, Cm.C, r, k)] = f;
 }
 
 __device__ __forceinline__ int find_sorted(const SellV& B, int64_t row, int32_t c) {
@@ -425,19 +445,20 @@ __device__ __forceinline__ int find_sorted(const SellV& B, int64_t row, int32_t 
 }
 
 // C = A B (MODE 0) or C = B - omega D^-1 A B with B indexed by A's rows (MODE 1, smoothing).
-template <int BRA, int BCA, int BCB, int MODE>
+template <int BRA, int BCA, int BCB, int MODE, int G>
 __global__ void __launch_bounds__(256) k_spgemm_numeric(SellV A, const double* __restrict__ av, SellV B,
                                                         const double* __restrict__ bv, SellV Cm,
                                                         double* __restrict__ cv, const double* __restrict__ invd,
                                                         double omega) {
-    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t r = int64_t(blockIdx.x) * kWavesPerBlock + w;
+    constexpr int RPW = kWave / G;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, gi = lane / G, lg = lane % G;
+    const int64_t r = (int64_t(blockIdx.x) * kWavesPerBlock + w) * RPW + gi;
     if (r >= Cm.n_rows) return;
     const int lc = Cm.len[r];
     const int64_t s0 = r / Cm.C;
     const int width = (Cm.sp[s0 + 1] - Cm.sp[s0]) / Cm.C;
     const int la = A.len[r];
-    for (int kc = lane; kc < width; kc += kWave) {
+    for (int kc = lg; kc < width; kc += G) {
         const int64_t cs = sslot(Cm.sp, Cm.C, r, kc);
         double acc[BRA][BCB];
         for (int i = 0; i < BRA; ++i)
@@ -496,35 +517,46 @@ __global__ void k_transpose_fill(SellV P, const double* __restrict__ pv, SellV R
     }
 }
 
-// sort each row of R by column (insertion sort, values move with the columns); zero padding
+// One wave per row: order the row's (unique) columns by rank and move the blocks from the
+// unsorted staging arrays into place; padding repeats the smallest column with zero blocks.
+constexpr int kRankMax = 1024;
+
 template <int BB>
-__global__ void k_sort_rows(SellV Rm, int32_t* __restrict__ col, double* __restrict__ val) {
-    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_rank_rows(SellV Rm, const int32_t* __restrict__ tcol,
+                                                   const double* __restrict__ tval, int32_t* __restrict__ col,
+                                                   double* __restrict__ val, int* __restrict__ overflow) {
+    __shared__ int32_t keys[kWavesPerBlock][kRankMax];
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t r = int64_t(blockIdx.x) * kWavesPerBlock + w;
     if (r >= Rm.n_rows) return;
     const int n = Rm.len[r];
-    for (int i = 1; i < n; ++i) {
-        const int64_t si = sslot(Rm.sp, Rm.C, r, i);
-        const int32_t c = col[si];
-        double v[BB];
-        for (int e = 0; e < BB; ++e) v[e] = val[si * BB + e];
-        int j = i - 1;
-        while (j >= 0 && col[sslot(Rm.sp, Rm.C, r, j)] > c) {
-            const int64_t sj = sslot(Rm.sp, Rm.C, r, j), sj1 = sslot(Rm.sp, Rm.C, r, j + 1);
-            col[sj1] = col[sj];
-            for (int e = 0; e < BB; ++e) val[sj1 * BB + e] = val[sj * BB + e];
-            --j;
-        }
-        const int64_t sd = sslot(Rm.sp, Rm.C, r, j + 1);
-        col[sd] = c;
-        for (int e = 0; e < BB; ++e) val[sd * BB + e] = v[e];
+    if (n > kRankMax) {
+        if (lane == 0) atomicOr(overflow, 1);
+        return;
+    }
+    int32_t mn = 0x7fffffff;
+    for (int e = lane; e < n; e += kWave) {
+        keys[w][e] = tcol[sslot(Rm.sp, Rm.C, r, e)];
+        mn = min(mn, keys[w][e]);
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) mn = min(mn, __shfl_xor(mn, o));
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int e = lane; e < n; e += kWave) {
+        const int32_t v = keys[w][e];
+        int rk = 0;
+        for (int j = 0; j < n; ++j) rk += keys[w][j] < v;
+        const int64_t src = sslot(Rm.sp, Rm.C, r, e), dst = sslot(Rm.sp, Rm.C, r, rk);
+        col[dst] = v;
+        for (int b = 0; b < BB; ++b) val[dst * BB + b] = tval[src * BB + b];
     }
     const int64_t s0 = r / Rm.C;
     const int width = (Rm.sp[s0 + 1] - Rm.sp[s0]) / Rm.C;
-    const int32_t f = n > 0 ? col[sslot(Rm.sp, Rm.C, r, 0)] : 0;
-    for (int k = n; k < width; ++k) {
+    for (int k = n + lane; k < width; k += kWave) {
         const int64_t s = sslot(Rm.sp, Rm.C, r, k);
-        col[s] = f;
-        for (int e = 0; e < BB; ++e) val[s * BB + e] = 0.0;
+        col[s] = n > 0 ? mn : 0;
+        for (int b = 0; b < BB; ++b) val[s * BB + b] = 0.0;
     }
 }
 
@@ -574,23 +606,28 @@ __global__ void k_fix_zero_rows(int64_t n, double* __restrict__ dense) {
 
 // In-place Gauss-Jordan inversion of a symmetric positive (semi)definite matrix without
 // pivoting, one workgroup, matrix in global memory (L2 resident for the sizes used here).
+// Waves walk rows, lanes walk columns, so every pass is coalesced; the pivot row and
+// column are staged in LDS.
 __global__ void __launch_bounds__(1024) k_gauss_jordan(int64_t n, double* __restrict__ a) {
     __shared__ double rowk[kDenseMax];
+    __shared__ double colk[kDenseMax];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
     for (int64_t k = 0; k < n; ++k) {
         const double p = a[k * n + k];
         const double ip = p != 0.0 ? 1.0 / p : 0.0;
-        __syncthreads();
         for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-            const double v = (j == k) ? ip : a[k * n + j] * ip;
-            rowk[j] = v;
+            rowk[j] = (j == k) ? ip : a[k * n + j] * ip;
+            colk[j] = a[j * n + k];
         }
         __syncthreads();
-        for (int64_t j = threadIdx.x; j < n; j += blockDim.x) a[k * n + j] = rowk[j];
-        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-            if (i == k) continue;
-            const double f = a[i * n + k];
+        for (int64_t i = wave; i < n; i += nw) {
+            if (i == k) {
+                for (int64_t j = lane; j < n; j += kWave) a[i * n + j] = rowk[j];
+                continue;
+            }
+            const double f = colk[i];
             if (f == 0.0) continue;
-            for (int64_t j = 0; j < n; ++j) {
+            for (int64_t j = lane; j < n; j += kWave) {
                 if (j == k) a[i * n + j] = -f * ip;
                 else a[i * n + j] -= f * rowk[j];
             }
@@ -623,10 +660,15 @@ std::shared_ptr<SellStruct> new_struct(int64_t n_rows, int64_t n_cols, hipStream
     return S;
 }
 
-int64_t block_nnz(const SellStruct& S, hipStream_t s) {
+int64_t block_nnz(const SellStruct& S, hipStream_t s, int* max_len = nullptr) {
     auto len = download(S.row_len, size_t(S.n_rows), s);
     int64_t t = 0;
-    for (int32_t v : len) t += v;
+    int mx = 0;
+    for (int32_t v : len) {
+        t += v;
+        mx = std::max(mx, int(v));
+    }
+    if (max_len) *max_len = mx;
     return t;
 }
 
@@ -634,16 +676,41 @@ void finish_struct(SellStruct& S, hipStream_t s) {
     layout_from_lengths(S, s);
     S.own_col.alloc(size_t(std::max<int64_t>(1, S.n_slots)), s);
     S.col = S.own_col.p;
-    S.nnz = block_nnz(S, s);
+    S.nnz = block_nnz(S, s, &S.max_len);
 }
 
-#define FR_SPGEMM_CASE(BRA_, BCA_, BCB_)                                                                   \
-    if (A.br == BRA_ && A.bc == BCA_ && B.bc == BCB_) {                                                    \
-        k_spgemm_numeric<BRA_, BCA_, BCB_, MODE><<<g, 256, 0, s>>>(sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), \
-                                                                   Cm.val, invd, omega);                  \
-        FR_LAUNCH_CHECK();                                                                                 \
-        return Cm;                                                                                         \
+template <int BRA, int BCA, int BCB, int MODE>
+void spgemm_numeric(const BMat<double>& A, const BMat<double>& B, BMat<double>& Cm, const double* invd, double omega,
+                    hipStream_t s) {
+    const int ml = Cm.S->max_len;
+    const int64_t rows = std::max<int64_t>(1, A.rows());
+#define FR_NUM_G(G_)                                                                                          \
+    k_spgemm_numeric<BRA, BCA, BCB, MODE, G_><<<nblk(rows, kWavesPerBlock * (kWave / G_)), 256, 0, s>>>(      \
+        sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), Cm.val, invd, omega);
+    if (ml <= 8) { FR_NUM_G(8) }
+    else if (ml <= 16) { FR_NUM_G(16) }
+    else if (ml <= 32) { FR_NUM_G(32) }
+    else { FR_NUM_G(64) }
+#undef FR_NUM_G
+    FR_LAUNCH_CHECK();
+}
+
+#define FR_SPGEMM_CASE(BRA_, BCA_, BCB_)                                        \
+    if (A.br == BRA_ && A.bc == BCA_ && B.bc == BCB_) {                         \
+        spgemm_numeric<BRA_, BCA_, BCB_, MODE>(A, B, Cm, invd, omega, s);       \
+        return Cm;                                                              \
     }
+
+template <int G>
+bool spgemm_symbolic(const BMat<double>& A, const BMat<double>& B, BMat<double>& Cm, DBuf<int>& ovf, hipStream_t s,
+                     bool fill) {
+    const int g = nblk(std::max<int64_t>(1, A.rows()), kWavesPerBlock * (kWave / G));
+    ovf.zero(s);
+    if (!fill) k_spgemm_count<G><<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), Cm.S->row_len, ovf.p);
+    else k_spgemm_fill<G><<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), sv(*Cm.S), Cm.S->col, ovf.p);
+    FR_LAUNCH_CHECK();
+    return download1(ovf.p, s) == 0;
+}
 
 template <int MODE>
 BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* invd, double omega, hipStream_t s) {
@@ -654,15 +721,13 @@ BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* 
     Cm.S = new_struct(A.rows(), B.cols(), s);
     DBuf<int> ovf;
     ovf.alloc(1, s);
-    ovf.zero(s);
-    const int g = nblk(std::max<int64_t>(1, A.rows()), kWavesPerBlock);
-    k_spgemm_count<<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), Cm.S->row_len, ovf.p);
-    FR_LAUNCH_CHECK();
-    if (download1(ovf.p, s)) fail(FR_EINTERNAL, "spgemm: row exceeds the LDS hash capacity");
+    // small hash sets first (8 rows per wave); a row that does not fit reruns with 64 lanes
+    bool small = spgemm_symbolic<8>(A, B, Cm, ovf, s, false);
+    if (!small && !spgemm_symbolic<64>(A, B, Cm, ovf, s, false))
+        fail(FR_EINTERNAL, "spgemm: row exceeds the LDS hash capacity");
     finish_struct(*Cm.S, s);
-    k_spgemm_fill<<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), sv(*Cm.S), Cm.S->col, ovf.p);
-    FR_LAUNCH_CHECK();
-    // nnz (block) for reporting
+    const bool ok = small ? spgemm_symbolic<8>(A, B, Cm, ovf, s, true) : spgemm_symbolic<64>(A, B, Cm, ovf, s, true);
+    if (!ok) fail(FR_EINTERNAL, "spgemm: fill overflow");
     Cm.own_val.alloc(size_t(std::max<int64_t>(1, Cm.S->n_slots)) * Cm.br * Cm.bc, s);
     Cm.val = Cm.own_val.p;
     FR_SPGEMM_CASE(1, 1, 1)
@@ -685,20 +750,28 @@ BMat<double> transpose(const BMat<double>& P, hipStream_t s) {
     k_col_count<<<nblk(P.rows(), 256), 256, 0, s>>>(sv(*P.S), Rm.S->row_len);
     FR_LAUNCH_CHECK();
     finish_struct(*Rm.S, s);
-    Rm.own_val.alloc(size_t(std::max<int64_t>(1, Rm.S->n_slots)) * Rm.br * Rm.bc, s);
+    const size_t nvals = size_t(std::max<int64_t>(1, Rm.S->n_slots)) * Rm.br * Rm.bc;
+    Rm.own_val.alloc(nvals, s);
     Rm.val = Rm.own_val.p;
-    DBuf<int32_t> fillc;
+    DBuf<int32_t> fillc, tcol;
+    DBuf<double> tval;
+    DBuf<int> ovf;
     fillc.alloc(size_t(std::max<int64_t>(1, P.cols())), s);
     fillc.zero(s);
+    tcol.alloc(size_t(std::max<int64_t>(1, Rm.S->n_slots)), s);
+    tval.alloc(nvals, s);
+    ovf.alloc(1, s);
+    ovf.zero(s);
     const int g = nblk(P.rows(), 256);
-    const int gr = nblk(Rm.rows(), 256);
-#define FR_TR_CASE(BR_, BC_)                                                                                   \
-    if (P.br == BR_ && P.bc == BC_) {                                                                          \
-        k_transpose_fill<BR_, BC_><<<g, 256, 0, s>>>(sv(*P.S), P.val, sv(*Rm.S), fillc.p, Rm.S->col, Rm.val); \
-        FR_LAUNCH_CHECK();                                                                                     \
-        k_sort_rows<BR_ * BC_><<<gr, 256, 0, s>>>(sv(*Rm.S), Rm.S->col, Rm.val);                               \
-        FR_LAUNCH_CHECK();                                                                                     \
-        return Rm;                                                                                             \
+    const int gr = nblk(Rm.rows(), kWavesPerBlock);
+#define FR_TR_CASE(BR_, BC_)                                                                                    \
+    if (P.br == BR_ && P.bc == BC_) {                                                                           \
+        k_transpose_fill<BR_, BC_><<<g, 256, 0, s>>>(sv(*P.S), P.val, sv(*Rm.S), fillc.p, tcol.p, tval.p);      \
+        FR_LAUNCH_CHECK();                                                                                      \
+        k_rank_rows<BR_ * BC_><<<gr, 256, 0, s>>>(sv(*Rm.S), tcol.p, tval.p, Rm.S->col, Rm.val, ovf.p);         \
+        FR_LAUNCH_CHECK();                                                                                      \
+        if (download1(ovf.p, s)) fail(FR_EINTERNAL, "transpose: a row is longer than the rank buffer");       \
+        return Rm;                                                                                              \
     }
     FR_TR_CASE(1, 1)
     FR_TR_CASE(2, 3)
@@ -973,15 +1046,19 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
 }
 
 void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s) {
+    const bool keep_u = o.reuse_u_block && amg.sys == &sys && !amg.h[0].lv.empty() &&
+                        amg.opts.precision == o.precision && amg.h[0].lv[0]->A.val == sys.Juu.val;
     amg.sys = &sys;
     amg.opts = o;
     amg.stream = s;
     DevMesh& m = *sys.mesh;
-    BMat<double> Au;
-    Au.br = Au.bc = m.dim;
-    Au.S = sys.Juu.S;
-    Au.val = sys.Juu.val;
-    build_hierarchy(amg.h[0], std::move(Au), m.dim == 2 ? 3 : 6, m.coords_free.p, m.dim, o, s);
+    if (!keep_u) {
+        BMat<double> Au;
+        Au.br = Au.bc = m.dim;
+        Au.S = sys.Juu.S;
+        Au.val = sys.Juu.val;
+        build_hierarchy(amg.h[0], std::move(Au), m.dim == 2 ? 3 : 6, m.coords_free.p, m.dim, o, s);
+    }
     BMat<double> Ap;
     Ap.br = Ap.bc = 1;
     Ap.S = sys.Jpp.S;

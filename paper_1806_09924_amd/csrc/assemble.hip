@@ -675,6 +675,7 @@ std::unique_ptr<DevMesh> mesh_create(const fr_mesh_desc& d, hipStream_t s, bool 
     g->n_slices = p.n_slices;
     g->n_slots = p.n_slots;
     g->nnz = p.nnz;
+    g->max_len = p.max_row;
     g->own_slice.upload(p.slice_ptr, s);
     g->own_len.upload(p.row_len, s);
     g->own_col.upload(p.col, s);

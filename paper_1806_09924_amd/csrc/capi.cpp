@@ -83,8 +83,9 @@ fr_amg_opts default_amg() {
     o.theta = 0.02;
     o.cheb_degree = 2;
     o.cheb_ratio = 20.0;
-    o.coarse_max = 500;
+    o.coarse_max = 256;
     o.max_levels = 10;
+    o.reuse_u_block = 1;
     return o;
 }
 
@@ -567,7 +568,9 @@ fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double*
             }
             {
                 EventTimer t(s);
-                fr::amg_build(A->amg, sys, ao, s);
+                fr_amg_opts ao_it = ao;
+                ao_it.reuse_u_block = (it > 0 && ao.reuse_u_block) ? 1 : 0;
+                fr::amg_build(A->amg, sys, ao_it, s);
                 t_setup += t.stop();
             }
             fr_solve_stats st{};

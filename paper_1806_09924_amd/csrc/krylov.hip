@@ -37,6 +37,87 @@ __global__ void __launch_bounds__(256) k_multidot(const double* __restrict__ V, 
     }
 }
 
+// Multi-vector dot, one pass over the basis: each thread holds kE elements of w in
+// registers and streams V_0..V_{nv-1}; per vector a wave reduction and a per-block LDS
+// row give part[v * gridDim.x + block].
+constexpr int kE = 4;
+
+__device__ __forceinline__ void block_store_parts(double (*sh)[4], int nv, double* __restrict__ part) {
+    __syncthreads();
+    for (int v = threadIdx.x; v < nv; v += blockDim.x)
+        part[int64_t(v) * gridDim.x + blockIdx.x] = sh[v][0] + sh[v][1] + sh[v][2] + sh[v][3];
+}
+
+__global__ void __launch_bounds__(256) k_multidot2(const double* __restrict__ V, int64_t n, int nv,
+                                                   const double* __restrict__ w, double* __restrict__ part) {
+    __shared__ double sh[128][4];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t base = int64_t(blockIdx.x) * (256 * kE) + threadIdx.x;
+    double wv[kE];
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+        const int64_t i = base + 256 * e;
+        wv[e] = i < n ? w[i] : 0.0;
+    }
+    for (int v = 0; v < nv; ++v) {
+        const double* Vv = V + int64_t(v) * n;
+        double acc = 0.0;
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+            const int64_t i = base + 256 * e;
+            if (i < n) acc += Vv[i] * wv[e];
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) sh[v][wave] = acc;
+    }
+    block_store_parts(sh, nv, part);
+}
+
+// w -= sum_k c[k] V_k, then the dots of the updated w with the same vectors (the second
+// sweep re-reads the block's slice of V while it is still in cache).
+__global__ void __launch_bounds__(256) k_update_dot(const double* __restrict__ V, int64_t n, int nv,
+                                                    const double* __restrict__ c, double* __restrict__ w,
+                                                    double* __restrict__ part) {
+    __shared__ double sh[128][4];
+    __shared__ double cs[128];
+    for (int k = threadIdx.x; k < nv; k += blockDim.x) cs[k] = c[k];
+    __syncthreads();
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t base = int64_t(blockIdx.x) * (256 * kE) + threadIdx.x;
+    double wv[kE];
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+        const int64_t i = base + 256 * e;
+        wv[e] = i < n ? w[i] : 0.0;
+    }
+    for (int v = 0; v < nv; ++v) {
+        const double* Vv = V + int64_t(v) * n;
+        const double cv = cs[v];
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+            const int64_t i = base + 256 * e;
+            if (i < n) wv[e] -= cv * Vv[i];
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+        const int64_t i = base + 256 * e;
+        if (i < n) w[i] = wv[e];
+    }
+    for (int v = 0; v < nv; ++v) {
+        const double* Vv = V + int64_t(v) * n;
+        double acc = 0.0;
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+            const int64_t i = base + 256 * e;
+            if (i < n) acc += Vv[i] * wv[e];
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) sh[v][wave] = acc;
+    }
+    block_store_parts(sh, nv, part);
+}
+
 // h[v] (+)= sum_bx part[v * nb + bx]
 __global__ void __launch_bounds__(256) k_reduce_parts(const double* __restrict__ part, int nb,
                                                       double* __restrict__ h, int accumulate) {
@@ -120,9 +201,10 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
         ws.w.alloc(size_t(n), s);
         ws.r.alloc(size_t(n), s);
         ws.h.alloc(1024, s);
-        ws.part.alloc(size_t(kRowBlocks) * 128 + 1024, s);
+        ws.part.alloc(size_t(std::max<int64_t>(kRowBlocks, ceil_div(n, 256 * kE))) * 128 + 1024, s);
     }
     const int gridN = int(std::min<int64_t>(1024, ceil_div(n, 256)));
+    const int nbE = int(ceil_div(n, 256 * kE));
     double* part = ws.part.p;
     double* h = ws.h.p;          // [0, 122): Hessenberg column of the current iteration
     double* h2 = ws.h.p + 256;   // [256, 378): re-orthogonalisation coefficients
@@ -182,30 +264,25 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
             amg_precondition(amg, Vj, Zj, s);
             jspmv(sys, Zj, ws.w.p, s);
             const int nv = j + 1;
-            const dim3 gd(kRowBlocks, unsigned(ceil_div(nv, kGroup)));
             const double md_bytes = double(nv + 1) * double(n) * 8.0;
             const double up_bytes = double(nv + 2) * double(n) * 8.0;
-            // pass 1
+            // pass 1: h = V^T w
             {
                 ProfScope ps("gs_multidot", s, md_bytes);
-                k_multidot<<<gd, 256, 0, s>>>(ws.V.p, n, nv, ws.w.p, part);
+                k_multidot2<<<nbE, 256, 0, s>>>(ws.V.p, n, nv, ws.w.p, part);
                 FR_LAUNCH_CHECK();
             }
-            k_reduce_parts<<<nv, 256, 0, s>>>(part, kRowBlocks, h, 0);
+            k_reduce_parts<<<nv, 256, 0, s>>>(part, nbE, h, 0);
             FR_LAUNCH_CHECK();
+            // w -= V h and, in the same sweep, h2 = V^T w (re-orthogonalisation coefficients)
             {
-                ProfScope ps("gs_update", s, up_bytes);
-                k_update<<<gridN, 256, 0, s>>>(ws.V.p, n, nv, h, ws.w.p, nullptr);
+                ProfScope ps("gs_update_dot", s, up_bytes);
+                k_update_dot<<<nbE, 256, 0, s>>>(ws.V.p, n, nv, h, ws.w.p, part);
                 FR_LAUNCH_CHECK();
             }
-            // pass 2 (re-orthogonalisation); the correction is added to h
-            {
-                ProfScope ps("gs_multidot", s, md_bytes);
-                k_multidot<<<gd, 256, 0, s>>>(ws.V.p, n, nv, ws.w.p, part);
-                FR_LAUNCH_CHECK();
-            }
-            k_reduce_parts<<<nv, 256, 0, s>>>(part, kRowBlocks, h2, 0);
+            k_reduce_parts<<<nv, 256, 0, s>>>(part, nbE, h2, 0);
             FR_LAUNCH_CHECK();
+            // w -= V h2 and ||w||^2
             {
                 ProfScope ps("gs_update", s, up_bytes);
                 k_update<<<gridN, 256, 0, s>>>(ws.V.p, n, nv, h2, ws.w.p, part);

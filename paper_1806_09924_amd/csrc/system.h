@@ -25,6 +25,7 @@ Params make_params(const fr_params& p);
 struct SellStruct {
     int C = 64;
     int64_t n_rows = 0, n_cols = 0, n_slices = 0, n_slots = 0, nnz = 0;
+    int max_len = 0;                // longest row (entries)
     int32_t* slice_ptr = nullptr;   // [n_slices+1]
     int32_t* row_len = nullptr;     // [n_rows]
     int32_t* col = nullptr;         // [n_slots]
