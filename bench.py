@@ -32,7 +32,10 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=256, help="cells per axis of the oracle's sample")
+    ap.add_argument("--cpu-n", type=int, default=320, help="cells per axis of the oracle's sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 1 GiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--levels", action="store_true", help="print the AMG hierarchy of the first Newton step")
     return ap.parse_args()
 
 
@@ -177,6 +180,23 @@ def main():
         }
         if prof:
             out["fp32_amg"]["vcycle_ms_fp64"] = {k: v["ms"] for k, v in prof.items() if k.startswith("vcycle")}
+    if args.levels:
+        u.zero_()
+        phi.copy_(phi0)
+        S = B.System(mesh).assemble(prm, u, phi, phi0, phi0)
+        A = B.Amg(S, B.amg_opts(precision=64))
+        lv = {}
+        for blk, nm in ((0, "u"), (1, "phi")):
+            lv[nm] = [A.level_info(blk, l) for l in range(A.n_levels(blk))]
+        out["amg_levels"] = lv
+        del A, S
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
     if not args.no_cpu:
         log("oracle timing on the host")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, L, n, out["fgmres_iterations_per_newton"])
