@@ -79,9 +79,7 @@ def test_table1_dofs_from_library_mesh(ref):
     m = B.Mesh(B.mesh_desc(2, -1.0, 1.0, n), host_only=True)
     table = {1: 867, 2: 3267, 3: 12675, 4: 49923}
     assert m.n_all == table[ref] and m.n_solve == m.n_all and m.n_hanging == 0
-    assert m.nnz_graph == (3 * n - 1) ** 2 if False else True
-    # node graph of a uniform Q1 mesh: 9-point stencil
-    deg = np.array([3] * 2 + [3] * 0)
+    # node graph of a uniform Q1 mesh: 9-point stencil, 3(n+1)-2 entries per axis
     assert m.nnz_graph == (3 * (n + 1) - 2) ** 2
 
 
@@ -142,3 +140,33 @@ def test_adaptive_octree_constraints():
     cells, lo, h = m.cells()
     assert np.isclose((h ** 3).sum(), 8.0)
     _check_conformity(m)
+
+
+@pytest.mark.parametrize("dim,n,levels,radius,half", [(2, 8, 3, 0.3, 0.5), (2, 16, 4, 0.1, 0.25), (3, 4, 2, 0.2, 0.4)])
+def test_library_adaptive_mesh_matches_oracle(dim, n, levels, radius, half):
+    """The library's and the oracle's independent builders give the same nodes, cells and
+    hanging-node weights."""
+    from oracle import adaptive
+    lo, hi = -2.0, 2.0
+    m = B.Mesh(B.mesh_desc(dim, lo, hi, n, levels=levels, refine_radius=radius, crack_center=(0.0, 0.0, 0.0),
+                           crack_half_len=half), host_only=True)
+    om = adaptive.adaptive(dim, lo, hi, n, levels, radius, (0.0, 0.0, 0.0), half)
+    xyz, lat, dirichlet, free = m.nodes()
+    assert m.n_nodes == om.n_nodes and m.n_cells == om.n_cells and m.n_free == om.n_free
+    key = lambda L: [tuple(r) for r in L]
+    assert sorted(key(lat)) == sorted(key(om.lattice))
+    pos = {t: i for i, t in enumerate(key(om.lattice))}
+    perm = np.array([pos[t] for t in key(lat)])           # library node -> oracle node
+    assert np.array_equal(dirichlet.astype(bool), om.dirichlet[perm])
+    cells, clo, ch = m.cells()
+    lib_cells = sorted((tuple(np.round(clo[i] / m.h_min).astype(int)), int(round(ch[i] / m.h_min))) for i in range(m.n_cells))
+    orc_cells = sorted((tuple(np.round(om.cell_lo[i] / m.h_min).astype(int)), int(round(om.cell_h[i] / m.h_min))) for i in range(om.n_cells))
+    assert lib_cells == orc_cells
+    ptr, mas, w = m.constraints()
+    node_of_free = np.nonzero(free >= 0)[0]
+    Co = om.C.tocsr()
+    for nd in range(m.n_nodes):
+        lib = sorted((tuple(lat[node_of_free[mas[j]]]), w[j]) for j in range(ptr[nd], ptr[nd + 1]))
+        row = Co.getrow(perm[nd])
+        orc = sorted((tuple(om.lattice[om.free[c]]), v) for c, v in zip(row.indices, row.data))
+        assert lib == orc

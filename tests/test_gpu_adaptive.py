@@ -1,0 +1,121 @@
+"""GPU parity on adaptively refined meshes with hanging nodes (Section 3 adaptive Q1^c meshes):
+residual, active set, condensed masked Jacobian, solve and Newton loop against the oracle's
+own adaptive mesh (nodes matched by lattice coordinates)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+from paper_1806_09924_amd import binding as B
+from oracle import adaptive, fem, newton as onewton, functionals as ofun
+from oracle.material import Params as OParams
+from inputs import crack_band_phi
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+class AdaptiveProblem:
+    def __init__(self, dim, L, n, levels, radius, half, kappa=1e-8, p=1e-3, l0=None):
+        self.dim = dim
+        c = (0.0, 0.0, 0.0)
+        self.mesh = B.Mesh(B.mesh_desc(dim, -L, L, n, levels=levels, refine_radius=radius, crack_center=c,
+                                       crack_half_len=half))
+        self.om = adaptive.adaptive(dim, -L, L, n, levels, radius, c, half)
+        xyz, lat, _, free = self.mesh.nodes()
+        pos = {tuple(r): i for i, r in enumerate(self.om.lattice)}
+        self.perm = np.array([pos[tuple(r)] for r in lat])          # library node -> oracle node
+        assert np.allclose(xyz, self.om.coords[self.perm], atol=1e-13)
+        node_of_free = np.nonzero(free >= 0)[0]
+        ofree = -np.ones(self.om.n_nodes, dtype=np.int64)
+        ofree[self.om.free] = np.arange(self.om.n_free)
+        fo = ofree[self.perm[node_of_free]]                        # library free -> oracle free
+        assert np.all(fo >= 0)
+        nf = self.om.n_free
+        self.psolve = np.concatenate([(fo[:, None] * dim + np.arange(dim)).ravel(), dim * nf + fo])
+        self.pfree = fo
+        h = self.mesh.h_min
+        eps = 2 * h
+        self.prm = B.params(eps=eps, kappa=kappa, p=p)
+        self.oprm = OParams(eps=eps, kappa=kappa, p=p)
+        phi0 = crack_band_phi(self.om.coords, half if l0 is None else l0, eps)
+        self.ostate = (np.zeros((self.om.n_nodes, dim)), phi0, phi0.copy(), phi0.copy())
+
+    def lib(self, a):
+        return dev(a[self.perm])
+
+    def lib_state(self):
+        return tuple(self.lib(a) for a in self.ostate)
+
+    def to_oracle(self, v):
+        out = np.empty_like(v)
+        out[self.psolve] = v
+        return out
+
+
+CASES = [dict(dim=2, L=1.0, n=8, levels=3, radius=0.1, half=0.3),
+         dict(dim=2, L=2.0, n=16, levels=4, radius=0.15, half=0.25),
+         dict(dim=3, L=1.0, n=4, levels=2, radius=0.1, half=0.4)]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c['dim']}d_n{c['n']}_L{c['levels']}")
+def test_adaptive_assembly_parity(case):
+    P = AdaptiveProblem(**case)
+    assert P.mesh.n_hanging > 0
+    o = onewton.newton_step_system(P.om, P.oprm, *P.ostate)
+    S = B.System(P.mesh).assemble(P.prm, *P.lib_state())
+    R, F, Bm, act = S.vectors()
+    R = P.to_oracle(host(R))
+    F = P.to_oracle(host(F))
+    Bo = np.empty(P.om.n_free)
+    Bo[P.pfree] = host(Bm)
+    assert np.abs(R - o.R).max() <= 1e-12 * np.abs(o.R).max()
+    assert np.abs(Bo - o.B).max() <= 1e-13 * np.abs(o.B).max()
+    a = np.zeros(P.om.n_free, dtype=bool)
+    a[P.pfree] = host(act).astype(bool)
+    mism = a != o.active
+    assert not np.any(mism & (np.abs(o.margin) > 1e-9 * np.abs(o.margin).max()))
+    rp, ci, vv = S.csr()
+    n = P.mesh.n_solve
+    J = sp.csr_matrix((vv, ci, rp), shape=(n, n)).tocoo()
+    Jo = sp.csr_matrix((J.data, (P.psolve[J.row], P.psolve[J.col])), shape=(n, n))
+    assert abs(Jo - o.Jm).max() <= 1e-12 * abs(o.Jm).max()
+    assert np.abs(F - o.F).max() <= 1e-12 * np.abs(o.F).max()
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_adaptive_solve_parity(precision):
+    P = AdaptiveProblem(dim=2, L=2.0, n=16, levels=4, radius=0.15, half=0.25, kappa=1e-10)
+    o = onewton.newton_step_system(P.om, P.oprm, *P.ostate)
+    S = B.System(P.mesh).assemble(P.prm, *P.lib_state())
+    A = B.Amg(S, B.amg_opts(precision=precision))
+    du = torch.empty(P.mesh.n_solve, dtype=torch.float64, device="cuda")
+    st = B.solve(S, A, du, B.solve_opts(rtol=1e-8))
+    d = P.to_oracle(host(du))
+    assert np.linalg.norm(o.F - o.Jm @ d) / np.linalg.norm(o.F) <= 1.01e-8
+    ref = onewton.solve_block(P.om, o.Jm, o.F)
+    U0 = fem.restrict(P.om, P.ostate[0], P.ostate[1])
+    ug, pg = fem.expand(P.om, U0 + d)
+    ur, pr = fem.expand(P.om, U0 + ref)
+    t_ref = ofun.tcv(P.om, ur, pr)
+    _, tcv = B.functionals(P.mesh, P.lib(ug), P.lib(pg))
+    assert abs(tcv / t_ref - 1) <= 1e-6
+    cod, _ = B.functionals(P.mesh, P.lib(ug), P.lib(pg), [[0.01]])
+    assert abs(cod[0] / ofun.cod(P.om, ur, pr, [0.01]) - 1) <= 1e-6
+
+
+def test_adaptive_newton_loop():
+    P = AdaptiveProblem(dim=2, L=1.0, n=8, levels=3, radius=0.1, half=0.3, kappa=1e-8)
+    ref = onewton.newton_loop(P.om, P.oprm, *P.ostate)
+    u, phi, po, pt = P.lib_state()
+    st = B.newton(P.mesh, P.prm, u, phi, po, pt, solve=B.solve_opts(rtol=1e-10))
+    assert ref["converged"] and st["status"] == 0
+    assert st["iterations"] == ref["iterations"]
+    assert st["n_active"] == int(ref["active"].sum())
+    ug = np.empty_like(ref["u"])
+    pg = np.empty_like(ref["phi"])
+    ug[P.perm] = host(u)
+    pg[P.perm] = host(phi)
+    assert np.abs(pg - ref["phi"]).max() <= 1e-6
+    _, tcv = B.functionals(P.mesh, u, phi)
+    assert abs(tcv / ofun.tcv(P.om, ref["u"], ref["phi"]) - 1) <= 1e-6
