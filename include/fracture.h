@@ -158,6 +158,20 @@ fr_status fracture_mesh_cells(fr_mesh mesh, int32_t* cells, double* cell_lo, dou
 fr_status fracture_mesh_constraints(fr_mesh mesh, int64_t* n_entries, int32_t* con_ptr,
                                     int32_t* con_master, double* con_w);
 
+/* Batch of n_inst independent meshes (desc: host, n_inst descriptors of one dim) stored as
+ * their disjoint union: nodes, cells and free nodes are numbered instance by instance, and
+ * every other call treats the batch as one system whose instances never couple (the
+ * batched studies over domain size and eps of Section 4). fracture_assemble then takes
+ * n_inst parameter sets, fracture_solve fills n_inst stats and tests convergence per
+ * instance, fracture_functionals reports per instance. fracture_newton needs n_inst = 1. */
+fr_status fracture_mesh_create_batch(const fr_mesh_desc* desc, int n_inst, fr_mesh* out, void* stream);
+
+/* Host outputs (nullable) for instance inst of a (batched) mesh: offsets and counts of its
+ * nodes, free nodes and cells in the union, and its finest cell edge. */
+fr_status fracture_mesh_instance(fr_mesh mesh, int inst, int64_t* node_offset, int64_t* n_nodes,
+                                 int64_t* free_offset, int64_t* n_free, int64_t* cell_offset,
+                                 int64_t* n_cells, double* h_min);
+
 void fracture_mesh_destroy(fr_mesh mesh);
 
 /* ---- assembly --------------------------------------------------------------------- */
@@ -167,7 +181,8 @@ void fracture_mesh_destroy(fr_mesh mesh);
  * matrices follow the mesh pattern); otherwise it is reused. flags selects the stages.
  * The active set of the FR_JACOBIAN stage is the one computed by the last FR_ACTIVE_SET
  * stage (callers may also install one with fracture_set_active). u and phi are read on
- * all nodes; only their values at free nodes enter (hanging values are interpolated). */
+ * all nodes; only their values at free nodes enter (hanging values are interpolated).
+ * prm: host, one parameter set per instance (one for an ordinary mesh). */
 fr_status fracture_assemble(fr_mesh mesh, const fr_params* prm /*host*/, const double* u,
                             const double* phi, const double* phi_old, const double* phi_tilde,
                             unsigned flags, fr_system* sys, void* stream);
@@ -226,8 +241,10 @@ fr_status amg_apply(fr_amg amg, const double* r, double* z, void* stream);
 void amg_destroy(fr_amg amg);
 
 /* Solves J du = F (masked system) by FGMRES with the AMG preconditioner. du: device,
- * n_solve. stats: host. Synchronises `stream` once per iteration (convergence check).
- * FR_ENOCONV is returned with du and stats filled when maxit is reached. */
+ * n_solve. stats: host, one per instance (nullable); each instance stops on its own
+ * relative residual, the return value is the worst instance status. Synchronises `stream`
+ * once per iteration (one flag per instance). FR_ENOCONV is returned with du and stats
+ * filled when maxit is reached. */
 fr_status fracture_solve(fr_system sys, fr_amg amg, const fr_solve_opts* opts /*host*/,
                          double* du, fr_solve_stats* stats, void* stream);
 
@@ -247,9 +264,10 @@ fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double*
 
 /* ---- functionals (Section 4) ------------------------------------------------------ */
 
-/* tcv (host, 1 value) = integral over B of u . grad phi. cod (host, n_cod values):
- * cod[i] = 1/2 integral of u . grad phi along the line through cod_x[i*(dim-1) ..] parallel
- * to the last axis (cod_x: host). Either output may be NULL. Synchronises `stream`. */
+/* Per instance i (n_inst of them; 1 for an ordinary mesh): tcv[i] (host) = integral over
+ * B_i of u . grad phi; cod[i*n_cod + k] (host) = 1/2 integral of u . grad phi along the
+ * line through cod_x[(i*n_cod + k)*(dim-1) ..] parallel to the last axis (cod_x: host, in
+ * the instance's coordinates). Either output may be NULL. Synchronises `stream`. */
 fr_status fracture_functionals(fr_mesh mesh, const double* u, const double* phi,
                                const double* cod_x, int n_cod, double* cod, double* tcv,
                                void* stream);

@@ -73,6 +73,8 @@ _SIGNATURES = {
     "fracture_mesh_info": [_P, _I64P, _I64P, _I64P, _I64P, _I64P, _I64P, _DP, _I64P],
     "fracture_mesh_nodes": [_P, _P, _P, _P, _P],
     "fracture_mesh_create_host": [ctypes.POINTER(MeshDesc), ctypes.POINTER(_P)],
+    "fracture_mesh_create_batch": [ctypes.POINTER(MeshDesc), ctypes.c_int, ctypes.POINTER(_P), _P],
+    "fracture_mesh_instance": [_P, ctypes.c_int, _I64P, _I64P, _I64P, _I64P, _I64P, _I64P, _DP],
     "fracture_mesh_cells": [_P, _P, _P, _P],
     "fracture_mesh_constraints": [_P, _I64P, _P, _P, _P],
     "fracture_mesh_destroy": [_P],
@@ -178,10 +180,18 @@ def mesh_desc(dim, lo, hi, base, levels=0, refine_radius=0.0, crack_center=(0.0,
 
 
 class Mesh:
+    """A mesh, or a batch of independent meshes when `desc` is a list of descriptors."""
+
     def __init__(self, desc, host_only=False):
         lib = load()
         h = _P()
-        if host_only:
+        self.n_inst = 1
+        if isinstance(desc, (list, tuple)):
+            arr = (MeshDesc * len(desc))(*desc)
+            self.n_inst = len(desc)
+            _check(lib.fracture_mesh_create_batch(arr, len(desc), ctypes.byref(h), _stream()))
+            desc = desc[0]
+        elif host_only:
             _check(lib.fracture_mesh_create_host(ctypes.byref(desc), ctypes.byref(h)))
         else:
             _check(lib.fracture_mesh_create(ctypes.byref(desc), ctypes.byref(h), _stream()))
@@ -204,6 +214,15 @@ class Mesh:
         _check(load().fracture_mesh_nodes(self.h, xyz.ctypes.data_as(_P), lat.ctypes.data_as(_P),
                                           dirichlet.ctypes.data_as(_P), free.ctypes.data_as(_P)))
         return xyz, lat, dirichlet, free
+
+    def instance(self, i):
+        v = [ctypes.c_int64() for _ in range(6)]
+        hm = ctypes.c_double()
+        _check(load().fracture_mesh_instance(self.h, i, *[ctypes.byref(x) for x in v], ctypes.byref(hm)))
+        keys = ("node_offset", "n_nodes", "free_offset", "n_free", "cell_offset", "n_cells")
+        out = {k: x.value for k, x in zip(keys, v)}
+        out["h_min"] = hm.value
+        return out
 
     def cells(self):
         nv = 1 << self.dim
@@ -237,7 +256,12 @@ class System:
         self.h = _P()
 
     def assemble(self, prm, u, phi, phi_old, phi_tilde, flags=FR_RESIDUAL | FR_ACTIVE_SET | FR_JACOBIAN):
-        _check(load().fracture_assemble(self.mesh.h, ctypes.byref(prm), _ptr(u), _ptr(phi), _ptr(phi_old),
+        """prm: one Params, or a list of one per instance of a batched mesh."""
+        plist = list(prm) if isinstance(prm, (list, tuple)) else [prm]
+        if len(plist) != self.mesh.n_inst:
+            raise ValueError(f"need {self.mesh.n_inst} parameter sets, got {len(plist)}")
+        arr = (Params * len(plist))(*plist)
+        _check(load().fracture_assemble(self.mesh.h, arr, _ptr(u), _ptr(phi), _ptr(phi_old),
                                         _ptr(phi_tilde), flags, ctypes.byref(self.h), _stream()))
         return self
 
@@ -329,12 +353,15 @@ class Amg:
 
 
 def solve(system, amg, du, opts=None, raise_on_noconv=True):
-    st = SolveStats()
+    """FGMRES; returns the stats dict (a list of them for a batched mesh)."""
+    ni = system.mesh.n_inst
+    st = (SolveStats * ni)()
     o = opts if opts is not None else solve_opts()
-    status = load().fracture_solve(system.h, amg.h, ctypes.byref(o), _ptr(du), ctypes.byref(st), _stream())
+    status = load().fracture_solve(system.h, amg.h, ctypes.byref(o), _ptr(du), st, _stream())
     if status != FR_OK and (raise_on_noconv or status != FR_ENOCONV):
         raise FractureError(status, last_error())
-    return dict(iters=st.iters, relres=st.relres, status=st.status)
+    out = [dict(iters=s.iters, relres=s.relres, status=s.status) for s in st]
+    return out[0] if ni == 1 else out
 
 
 def update(mesh, du, omega, u, phi):
@@ -354,13 +381,18 @@ def newton(mesh, prm, u, phi, phi_old, phi_tilde, amg=None, solve=None, newton=N
 
 
 def functionals(mesh, u, phi, cod_x=()):
-    cod_x = np.ascontiguousarray(np.asarray(cod_x, dtype=np.float64).reshape(-1, mesh.dim - 1))
-    n = cod_x.shape[0]
-    cod = np.zeros(max(1, n))
-    tcv = ctypes.c_double()
+    """(cod, tcv). One mesh: cod_x [n_cod][dim-1] -> cod [n_cod], tcv float. Batched mesh:
+    cod_x [n_inst][n_cod][dim-1] -> cod [n_inst][n_cod], tcv [n_inst]."""
+    ni = mesh.n_inst
+    cod_x = np.ascontiguousarray(np.asarray(cod_x, dtype=np.float64).reshape(ni, -1, mesh.dim - 1))
+    n = cod_x.shape[1]
+    cod = np.zeros(max(1, ni * n))
+    tcv = np.zeros(ni)
     _check(load().fracture_functionals(mesh.h, _ptr(u), _ptr(phi), cod_x.ctypes.data_as(_P) if n else None, n,
-                                       cod.ctypes.data_as(_P) if n else None, ctypes.byref(tcv), _stream()))
-    return cod[:n], tcv.value
+                                       cod.ctypes.data_as(_P) if n else None, tcv.ctypes.data_as(_P), _stream()))
+    if ni == 1:
+        return cod[:n], float(tcv[0])
+    return cod[:ni * n].reshape(ni, n), tcv
 
 
 def device_check():

@@ -66,6 +66,9 @@ struct MeshView {
     const double* ent_w;
     int C;
     int64_t n_free;
+    const int32_t* inst_of_free;   // nullptr for one instance
+    const int32_t* inst_of_cell;
+    const Params* prm_arr;         // per-instance constants, nullptr for one instance
 };
 
 MeshView view(const DevMesh& m) {
@@ -79,7 +82,20 @@ MeshView view(const DevMesh& m) {
     v.ent_w = m.ent_w.p;
     v.C = m.graph->C;
     v.n_free = m.n_free;
+    v.inst_of_free = m.n_inst > 1 ? m.inst_of_free.p : nullptr;
+    v.inst_of_cell = m.n_inst > 1 ? m.inst_of_cell.p : nullptr;
+    v.prm_arr = nullptr;
     return v;
+}
+
+MeshView view(const DevSystem& sys) {
+    MeshView v = view(*sys.mesh);
+    v.prm_arr = sys.mesh->n_inst > 1 ? sys.prm_d.p : nullptr;
+    return v;
+}
+
+__device__ __forceinline__ Params row_params(const MeshView& mv, const Params& prm0, int64_t f) {
+    return mv.prm_arr ? mv.prm_arr[mv.inst_of_free[f]] : prm0;
 }
 
 // Nodal values at a cell vertex; with hanging nodes the value is interpolated from the
@@ -127,12 +143,13 @@ __device__ __forceinline__ void strain_stress(const double (&gu)[D][D], double m
 
 // ---- residual + lumped mass -------------------------------------------------------------
 template <int D, bool HANG>
-__global__ void __launch_bounds__(256) k_residual(MeshView mv, Params prm, const double* __restrict__ u,
+__global__ void __launch_bounds__(256) k_residual(MeshView mv, Params prm0, const double* __restrict__ u,
                                                   const double* __restrict__ phi, const double* __restrict__ pt,
                                                   double* __restrict__ R, double* __restrict__ B) {
     constexpr int NV = 1 << D;
     const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (f >= mv.n_free) return;
+    const Params prm = row_params(mv, prm0, f);
     double ru[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) ru[c] = 0.0;
@@ -204,7 +221,9 @@ __global__ void __launch_bounds__(256) k_residual(MeshView mv, Params prm, const
 
 // ---- active set -------------------------------------------------------------------------
 // lambda = -R_phi / B; A = { lambda + c (phi - phi_old) > tau }; optional cycle freeze.
-__global__ void __launch_bounds__(256) k_active(int64_t nf, int D, Params prm, const int32_t* __restrict__ node_of_free,
+__global__ void __launch_bounds__(256) k_active(int64_t nf, int D, Params prm0, const Params* __restrict__ prm_arr,
+                                                const int32_t* __restrict__ inst_of_free,
+                                                const int32_t* __restrict__ node_of_free,
                                                 const double* __restrict__ R, const double* __restrict__ B,
                                                 const double* __restrict__ phi, const double* __restrict__ phi_old,
                                                 uint8_t* __restrict__ active, uint8_t* __restrict__ prev,
@@ -217,6 +236,7 @@ __global__ void __launch_bounds__(256) k_active(int64_t nf, int D, Params prm, c
     double mm = INFINITY;
     if (f < nf) {
         const int32_t n = node_of_free[f];
+        const Params prm = prm_arr ? prm_arr[inst_of_free[f]] : prm0;
         const double lam = -R[D * nf + f] / B[f];
         const double margin = lam + prm.c_pdas * (phi[n] - phi_old[n]) - prm.tau;
         mm = fabs(margin);
@@ -260,7 +280,7 @@ __device__ __forceinline__ int find_k(const MeshView& mv, int64_t f, int32_t g) 
 }
 
 template <int D, bool HANG>
-__global__ void __launch_bounds__(128) k_jacobian(MeshView mv, Params prm, const double* __restrict__ u,
+__global__ void __launch_bounds__(128) k_jacobian(MeshView mv, Params prm0, const double* __restrict__ u,
                                                   const double* __restrict__ phi, const double* __restrict__ phi_old,
                                                   const double* __restrict__ pt, const double* __restrict__ R,
                                                   const uint8_t* __restrict__ active, double* __restrict__ Juu,
@@ -270,6 +290,7 @@ __global__ void __launch_bounds__(128) k_jacobian(MeshView mv, Params prm, const
     constexpr int DD = D * D;
     const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (f >= mv.n_free) return;
+    const Params prm = row_params(mv, prm0, f);
     const int64_t sl = f / mv.C;
     const int width = (mv.slice_ptr[sl + 1] - mv.slice_ptr[sl]) / mv.C;
     for (int k = 0; k < width; ++k) {
@@ -530,11 +551,11 @@ __global__ void k_fill_hanging(int64_t nn, int D, const int32_t* __restrict__ fr
 
 // ---- functionals --------------------------------------------------------------------------
 template <int D, bool HANG>
-__global__ void __launch_bounds__(256) k_tcv(int64_t nc, MeshView mv, const double* __restrict__ u,
+__global__ void __launch_bounds__(256) k_tcv(int64_t c0, int64_t nc, MeshView mv, const double* __restrict__ u,
                                              const double* __restrict__ phi, double* __restrict__ part) {
     __shared__ double sh[16];
     constexpr int NV = 1 << D;
-    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t c = c0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;   // cells [c0, nc)
     double acc = 0.0;
     if (c < nc) {
         const double h = mv.cell_h[c], ih = 1.0 / h;
@@ -569,12 +590,12 @@ __global__ void __launch_bounds__(256) k_tcv(int64_t nc, MeshView mv, const doub
 
 // COD: 1/2 of the line integral of u . grad phi along the last axis at x0 (1d 2-point Gauss)
 template <int D, bool HANG>
-__global__ void __launch_bounds__(256) k_cod(int64_t nc, MeshView mv, const double* __restrict__ u,
+__global__ void __launch_bounds__(256) k_cod(int64_t c0, int64_t nc, MeshView mv, const double* __restrict__ u,
                                              const double* __restrict__ phi, const double* __restrict__ xs,
                                              double* __restrict__ part) {
     __shared__ double sh[16];
     constexpr int NV = 1 << D;
-    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t c = c0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;   // cells [c0, nc)
     const int sample = blockIdx.y;
     double acc = 0.0;
     if (c < nc) {
@@ -636,9 +657,10 @@ __global__ void k_sum_rows(const double* __restrict__ part, int64_t n_part, int 
 
 // ---- host side --------------------------------------------------------------------------
 
-std::unique_ptr<DevMesh> mesh_create(const fr_mesh_desc& d, hipStream_t s, bool upload) {
+std::unique_ptr<DevMesh> mesh_create(const fr_mesh_desc* d, int n_inst, hipStream_t s, bool upload) {
     auto m = std::make_unique<DevMesh>();
-    m->host = build_mesh(d);
+    m->host = build_mesh_batch(d, n_inst);
+    m->n_inst = n_inst;
     m->pat = build_pattern(m->host, 64);
     const HostMesh& h = m->host;
     const Pattern& p = m->pat;
@@ -651,6 +673,15 @@ std::unique_ptr<DevMesh> mesh_create(const fr_mesh_desc& d, hipStream_t s, bool 
     m->hanging = h.n_hanging > 0;
     m->on_device = upload;
     if (!upload) return m;
+    if (n_inst > 1) {
+        std::vector<int32_t> iof(size_t(h.n_free)), ioc(size_t(h.n_cells));
+        for (int i = 0; i < n_inst; ++i) {
+            for (int64_t f = h.free_off[size_t(i)]; f < h.free_off[size_t(i) + 1]; ++f) iof[size_t(f)] = i;
+            for (int64_t c = h.cell_off[size_t(i)]; c < h.cell_off[size_t(i) + 1]; ++c) ioc[size_t(c)] = i;
+        }
+        m->inst_of_free.upload(iof, s);
+        m->inst_of_cell.upload(ioc, s);
+    }
     m->cells.upload(h.cells, s);
     m->cell_h.upload(h.cell_h, s);
     m->cell_lo.upload(h.cell_lo, s);
@@ -696,7 +727,7 @@ static int blocks_for(int64_t n, int t) { return int(ceil_div(n, t)); }
 
 void assemble_residual(DevSystem& sys, const double* u, const double* phi, const double* pt) {
     DevMesh& m = *sys.mesh;
-    MeshView mv = view(m);
+    MeshView mv = view(sys);
     const hipStream_t s = sys.stream;
     const int nb = blocks_for(m.n_free, 256);
     if (m.dim == 2) {
@@ -716,7 +747,8 @@ void assemble_active_impl(DevSystem& sys, const double* phi, const double* phi_o
     const int nb = blocks_for(m.n_free, 256);
     sys.red.reserve(size_t(nb) + 16, s);
     sys.ired.reserve(size_t(nb) + 16, s);
-    k_active<<<nb, 256, 0, s>>>(m.n_free, m.dim, sys.prm, m.node_of_free.p, sys.R.p, sys.B.p, phi, phi_old,
+    k_active<<<nb, 256, 0, s>>>(m.n_free, m.dim, sys.prm, m.n_inst > 1 ? sys.prm_d.p : nullptr,
+                                m.n_inst > 1 ? m.inst_of_free.p : nullptr, m.node_of_free.p, sys.R.p, sys.B.p, phi, phi_old,
                                 sys.active.p, sys.active_prev.p, sys.frozen.p, use_freeze, sys.ired.p, sys.red.p);
     FR_LAUNCH_CHECK();
     auto cnt = download(sys.ired.p, size_t(nb), s);
@@ -740,7 +772,7 @@ void assemble_active_freeze(DevSystem& sys, const double* phi, const double* phi
 
 void assemble_jacobian(DevSystem& sys, const double* u, const double* phi, const double* phi_old, const double* pt) {
     DevMesh& m = *sys.mesh;
-    MeshView mv = view(m);
+    MeshView mv = view(sys);
     const hipStream_t s = sys.stream;
     const int nb = blocks_for(m.n_free, 128);
     if (m.dim == 2) {
@@ -795,42 +827,51 @@ void mesh_update(DevMesh& m, const double* du, double omega, double* u, double* 
 void mesh_functionals(DevMesh& m, const double* u, const double* phi, const double* cod_x, int n_cod, double* cod,
                       double* tcv, hipStream_t s) {
     MeshView mv = view(m);
-    const int nb = blocks_for(m.n_cells, 256);
-    DBuf<double> part, out;
-    part.alloc(size_t(nb) * size_t(std::max(1, n_cod)), s);
+    const HostMesh& hm = m.host;
+    const int D1 = m.dim - 1;
+    DBuf<double> part, out, xs;
+    const int nb_max = blocks_for(std::max<int64_t>(1, m.n_cells), 256);
+    part.alloc(size_t(nb_max) * size_t(std::max(1, n_cod)), s);
     out.alloc(size_t(std::max(1, n_cod)), s);
-    if (tcv) {
-        if (m.dim == 2) {
-            if (m.hanging) k_tcv<2, true><<<nb, 256, 0, s>>>(m.n_cells, mv, u, phi, part.p);
-            else k_tcv<2, false><<<nb, 256, 0, s>>>(m.n_cells, mv, u, phi, part.p);
-        } else {
-            if (m.hanging) k_tcv<3, true><<<nb, 256, 0, s>>>(m.n_cells, mv, u, phi, part.p);
-            else k_tcv<3, false><<<nb, 256, 0, s>>>(m.n_cells, mv, u, phi, part.p);
-        }
-        FR_LAUNCH_CHECK();
-        k_sum_rows<<<1, 256, 0, s>>>(part.p, nb, 1, 0, 1, out.p);
-        FR_LAUNCH_CHECK();
-        *tcv = download1(out.p, s);
+    if (n_cod > 0) {
+        xs.alloc(size_t(m.n_inst) * n_cod * D1, s);
+        xs.upload(cod_x, size_t(m.n_inst) * n_cod * D1, s);
     }
-    if (cod && n_cod > 0) {
-        DBuf<double> xs;
-        xs.alloc(size_t(n_cod) * (m.dim - 1), s);
-        xs.upload(cod_x, size_t(n_cod) * (m.dim - 1), s);
-        dim3 grid(nb, n_cod);
-        if (m.dim == 2) {
-            if (m.hanging) k_cod<2, true><<<grid, 256, 0, s>>>(m.n_cells, mv, u, phi, xs.p, part.p);
-            else k_cod<2, false><<<grid, 256, 0, s>>>(m.n_cells, mv, u, phi, xs.p, part.p);
-        } else {
-            if (m.hanging) k_cod<3, true><<<grid, 256, 0, s>>>(m.n_cells, mv, u, phi, xs.p, part.p);
-            else k_cod<3, false><<<grid, 256, 0, s>>>(m.n_cells, mv, u, phi, xs.p, part.p);
+    // one reduction per instance over its cell range (instances never share cells)
+    for (int i = 0; i < m.n_inst; ++i) {
+        const int64_t c0 = hm.cell_off[size_t(i)], c1 = hm.cell_off[size_t(i) + 1];
+        const int nb = blocks_for(std::max<int64_t>(1, c1 - c0), 256);
+        if (tcv) {
+            if (m.dim == 2) {
+                if (m.hanging) k_tcv<2, true><<<nb, 256, 0, s>>>(c0, c1, mv, u, phi, part.p);
+                else k_tcv<2, false><<<nb, 256, 0, s>>>(c0, c1, mv, u, phi, part.p);
+            } else {
+                if (m.hanging) k_tcv<3, true><<<nb, 256, 0, s>>>(c0, c1, mv, u, phi, part.p);
+                else k_tcv<3, false><<<nb, 256, 0, s>>>(c0, c1, mv, u, phi, part.p);
+            }
+            FR_LAUNCH_CHECK();
+            k_sum_rows<<<1, 256, 0, s>>>(part.p, nb, 1, 0, 1, out.p);
+            FR_LAUNCH_CHECK();
+            tcv[i] = download1(out.p, s);
         }
-        FR_LAUNCH_CHECK();
-        k_sum_rows<<<n_cod, 256, 0, s>>>(part.p, nb, n_cod, nb, 1, out.p);
-        FR_LAUNCH_CHECK();
-        auto h = download(out.p, size_t(n_cod), s);
-        for (int i = 0; i < n_cod; ++i) cod[i] = h[size_t(i)];
-        FR_HIP(hipStreamSynchronize(s));
+        if (cod && n_cod > 0) {
+            dim3 grid(nb, n_cod);
+            const double* xi = xs.p + size_t(i) * n_cod * D1;
+            if (m.dim == 2) {
+                if (m.hanging) k_cod<2, true><<<grid, 256, 0, s>>>(c0, c1, mv, u, phi, xi, part.p);
+                else k_cod<2, false><<<grid, 256, 0, s>>>(c0, c1, mv, u, phi, xi, part.p);
+            } else {
+                if (m.hanging) k_cod<3, true><<<grid, 256, 0, s>>>(c0, c1, mv, u, phi, xi, part.p);
+                else k_cod<3, false><<<grid, 256, 0, s>>>(c0, c1, mv, u, phi, xi, part.p);
+            }
+            FR_LAUNCH_CHECK();
+            k_sum_rows<<<n_cod, 256, 0, s>>>(part.p, nb, n_cod, nb, 1, out.p);
+            FR_LAUNCH_CHECK();
+            auto h = download(out.p, size_t(n_cod), s);
+            for (int k = 0; k < n_cod; ++k) cod[size_t(i) * n_cod + k] = h[size_t(k)];
+        }
     }
+    FR_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace fr

@@ -196,10 +196,49 @@ fr_status fracture_mesh_create(const fr_mesh_desc* desc, fr_mesh* out, void* str
         fr_status st = check_device();
         if (st != FR_OK) return st;
         auto h = std::make_unique<fr_mesh_s>();
-        h->m = fr::mesh_create(*desc, fr::as_stream(stream), true);
+        h->m = fr::mesh_create(desc, 1, fr::as_stream(stream), true);
         *out = h.release();
         return FR_OK;
     });
+}
+
+fr_status fracture_mesh_create_batch(const fr_mesh_desc* desc, int n_inst, fr_mesh* out, void* stream) {
+    FR_REQUIRE(desc != nullptr && out != nullptr, "mesh_create_batch: NULL argument");
+    FR_REQUIRE(n_inst >= 1 && n_inst <= 65535, "mesh_create_batch: n_inst must be in [1, 65535]");
+    for (int i = 0; i < n_inst; ++i) {
+        FR_REQUIRE(desc[i].dim == desc[0].dim, "mesh_create_batch: instances must share dim");
+        FR_REQUIRE(desc[i].dim == 2 || desc[i].dim == 3, "mesh_create_batch: dim must be 2 or 3");
+        FR_REQUIRE(desc[i].levels >= 0 && desc[i].levels <= 12, "mesh_create_batch: levels must be in [0, 12]");
+        for (int k = 0; k < desc[i].dim; ++k) {
+            FR_REQUIRE(desc[i].base[k] >= 1, "mesh_create_batch: base must be >= 1");
+            FR_REQUIRE(desc[i].hi[k] > desc[i].lo[k], "mesh_create_batch: need hi > lo");
+        }
+    }
+    return guard([&]() {
+        fr_status st = check_device();
+        if (st != FR_OK) return st;
+        auto h = std::make_unique<fr_mesh_s>();
+        h->m = fr::mesh_create(desc, n_inst, fr::as_stream(stream), true);
+        *out = h.release();
+        return FR_OK;
+    });
+}
+
+fr_status fracture_mesh_instance(fr_mesh mesh, int inst, int64_t* node_offset, int64_t* n_nodes,
+                                 int64_t* free_offset, int64_t* n_free, int64_t* cell_offset, int64_t* n_cells,
+                                 double* h_min) {
+    FR_REQUIRE(mesh != nullptr && mesh->m, "mesh_instance: NULL mesh");
+    const fr::HostMesh& h = mesh->m->host;
+    FR_REQUIRE(inst >= 0 && inst < h.n_inst, "mesh_instance: instance out of range");
+    const size_t i = size_t(inst);
+    if (node_offset) *node_offset = h.node_off[i];
+    if (n_nodes) *n_nodes = h.node_off[i + 1] - h.node_off[i];
+    if (free_offset) *free_offset = h.free_off[i];
+    if (n_free) *n_free = h.free_off[i + 1] - h.free_off[i];
+    if (cell_offset) *cell_offset = h.cell_off[i];
+    if (n_cells) *n_cells = h.cell_off[i + 1] - h.cell_off[i];
+    if (h_min) *h_min = h.inst_h_min[i];
+    return FR_OK;
 }
 
 fr_status fracture_mesh_create_host(const fr_mesh_desc* desc, fr_mesh* out) {
@@ -207,7 +246,7 @@ fr_status fracture_mesh_create_host(const fr_mesh_desc* desc, fr_mesh* out) {
     FR_REQUIRE(desc->dim == 2 || desc->dim == 3, "mesh_create_host: dim must be 2 or 3");
     return guard([&]() {
         auto h = std::make_unique<fr_mesh_s>();
-        h->m = fr::mesh_create(*desc, nullptr, false);
+        h->m = fr::mesh_create(desc, 1, nullptr, false);
         *out = h.release();
         return FR_OK;
     });
@@ -272,8 +311,11 @@ fr_status fracture_assemble(fr_mesh mesh, const fr_params* prm, const double* u,
     FR_REQUIRE(mesh->m->on_device, "assemble: host-only mesh");
     FR_REQUIRE(sys != nullptr, "assemble: NULL system pointer");
     FR_REQUIRE((flags & ~7u) == 0 && flags != 0, "assemble: unknown or empty flags");
-    fr_status ps = check_params(prm);
-    if (ps != FR_OK) return ps;
+    FR_REQUIRE(prm != nullptr, "assemble: NULL params");
+    for (int i = 0; i < mesh->m->n_inst; ++i) {
+        fr_status ps = check_params(prm + i);
+        if (ps != FR_OK) return ps;
+    }
     if (flags & (FR_RESIDUAL | FR_JACOBIAN)) FR_REQUIRE(u && phi && phi_tilde, "assemble: u, phi, phi_tilde required");
     if (flags & (FR_ACTIVE_SET | FR_JACOBIAN)) FR_REQUIRE(phi && phi_old, "assemble: phi, phi_old required");
     if (*sys && (*sys)->sys.mesh != mesh->m.get()) return set_err(FR_EINVAL, "assemble: system belongs to another mesh");
@@ -291,7 +333,11 @@ fr_status fracture_assemble(fr_mesh mesh, const fr_params* prm, const double* u,
             system_init(*S, *mesh->m, s);
         }
         S->sys.stream = s;
-        S->sys.prm = fr::make_params(*prm);
+        S->sys.prm = fr::make_params(prm[0]);
+        const int ni = mesh->m->n_inst;
+        S->sys.prm_h.resize(size_t(ni));
+        for (int i = 0; i < ni; ++i) S->sys.prm_h[size_t(i)] = fr::make_params(prm[i]);
+        if (ni > 1) S->sys.prm_d.upload(S->sys.prm_h, s);
         if (flags & FR_RESIDUAL) fr::assemble_residual(S->sys, u, phi, phi_tilde);
         if (flags & FR_ACTIVE_SET) fr::assemble_active(S->sys, phi, phi_old);
         if (flags & FR_JACOBIAN) fr::assemble_jacobian(S->sys, u, phi, phi_old, phi_tilde);
@@ -497,9 +543,7 @@ fr_status fracture_solve(fr_system sys, fr_amg amg, const fr_solve_opts* opts, d
     fr_status cs = check_solve(*opts);
     if (cs != FR_OK) return cs;
     return guard([&]() {
-        fr_solve_stats st{};
-        const fr_status r = fr::fgmres(sys->sys, amg->amg, *opts, du, st, sys->kry, fr::as_stream(stream));
-        if (stats) *stats = st;
+        const fr_status r = fr::fgmres(sys->sys, amg->amg, *opts, du, stats, sys->kry, fr::as_stream(stream));
         if (r == FR_ENOCONV) set_err(r, "solve: iteration limit reached");
         if (r == FR_ENAN) set_err(r, "solve: non-finite value in the Krylov iteration");
         return r;
@@ -521,6 +565,7 @@ fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double*
                           const fr_newton_opts* newton_opts, fr_newton_stats* stats, void* stream) {
     FR_REQUIRE(mesh != nullptr && mesh->m, "newton: NULL mesh");
     FR_REQUIRE(mesh->m->on_device, "newton: host-only mesh");
+    FR_REQUIRE(mesh->m->n_inst == 1, "newton: batched meshes take single Newton steps (assemble/amg_setup/solve)");
     FR_REQUIRE(u && phi && phi_old && phi_tilde, "newton: NULL state array");
     fr_status ps = check_params(prm);
     if (ps != FR_OK) return ps;
@@ -540,6 +585,7 @@ fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double*
         system_init(*S, m, s);
         fr::DevSystem& sys = S->sys;
         sys.prm = fr::make_params(*prm);
+        sys.prm_h = {sys.prm};
         auto A = std::make_unique<fr_amg_s>();
         const int64_t nn = m.n_nodes;
         fr::DBuf<double> du, u_save, p_save;
@@ -576,7 +622,7 @@ fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double*
             fr_solve_stats st{};
             {
                 EventTimer t(s);
-                const fr_status r = fr::fgmres(sys, A->amg, so, du.p, st, S->kry, s);
+                const fr_status r = fr::fgmres(sys, A->amg, so, du.p, &st, S->kry, s);
                 t_solve += t.stop();
                 ns.linear_iters += st.iters;
                 if (r == FR_ENAN) { status = FR_ENAN; break; }

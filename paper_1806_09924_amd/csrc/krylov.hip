@@ -1,9 +1,15 @@
 // Flexible GMRES (right preconditioned, restarted) for the masked Newton system of Section 3,
-// FP64 throughout.  Arnoldi orthogonalisation is classical Gram-Schmidt with one
-// re-orthogonalisation pass (CGS2): a multi-vector dot kernel and a multi-vector update
-// kernel stream the basis once each per pass; the small Hessenberg least-squares problem
-// (Givens rotations) is solved on the host from the j+2 coefficients copied back per
-// iteration, which is also the convergence check.
+// FP64, for one instance or many independent instances solved in lockstep.
+//
+// The solve vector of a batch is the disjoint union of the instances (u block, then phi
+// block, each instance-major), so SpMV and the V-cycles run on the union unchanged.  Every
+// reduction is segmented: vector kernels run over a table of blocks that never straddle an
+// instance, partial sums are combined per instance in a fixed order (deterministic).
+// Arnoldi uses classical Gram-Schmidt with one re-orthogonalisation pass (CGS2): one
+// multi-vector dot sweep, one fused update + dot sweep, one update + norm sweep.  Givens
+// rotations, the convergence test and the back substitution run on the device, one thread
+// per instance; the host reads one flag word per instance per iteration to stop.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -13,252 +19,391 @@
 namespace fr {
 namespace {
 
-constexpr int kGroup = 8;        // basis vectors per multidot block row
-constexpr int kRowBlocks = 256;  // blocks per group along the vector
+constexpr int kE = 4;                 // elements per thread in the vector sweeps
+constexpr int kChunk = 256 * kE;      // elements per block
+constexpr int kMaxM = 120;            // largest restart length
 
-// part[(v) * kRowBlocks + bx] = sum over this block's rows of V_v[i] w[i], v in [v0, v0+kGroup)
-__global__ void __launch_bounds__(256) k_multidot(const double* __restrict__ V, int64_t n, int nv,
-                                                  const double* __restrict__ w, double* __restrict__ part) {
-    __shared__ double sh[16];
-    const int v0 = blockIdx.y * kGroup;
-    double acc[kGroup];
-#pragma unroll
-    for (int g = 0; g < kGroup; ++g) acc[g] = 0.0;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-        const double wi = w[i];
-#pragma unroll
-        for (int g = 0; g < kGroup; ++g)
-            if (v0 + g < nv) acc[g] += V[int64_t(v0 + g) * n + i] * wi;
-    }
-#pragma unroll
-    for (int g = 0; g < kGroup; ++g) {
-        const double s = block_sum(acc[g], sh);
-        if (threadIdx.x == 0 && v0 + g < nv) part[int64_t(v0 + g) * gridDim.x + blockIdx.x] = s;
-    }
-}
+struct Seg {
+    const int64_t* start;   // [nb] first element of the block
+    const int32_t* len;     // [nb] elements in the block (<= kChunk)
+    const int32_t* inst;    // [nb] instance of the block
+};
 
-// Multi-vector dot, one pass over the basis: each thread holds kE elements of w in
-// registers and streams V_0..V_{nv-1}; per vector a wave reduction and a per-block LDS
-// row give part[v * gridDim.x + block].
-constexpr int kE = 4;
-
-__device__ __forceinline__ void block_store_parts(double (*sh)[4], int nv, double* __restrict__ part) {
+__device__ __forceinline__ void store_block_parts(double (*sh)[4], int nv, double* __restrict__ part) {
     __syncthreads();
     for (int v = threadIdx.x; v < nv; v += blockDim.x)
         part[int64_t(v) * gridDim.x + blockIdx.x] = sh[v][0] + sh[v][1] + sh[v][2] + sh[v][3];
 }
 
-__global__ void __launch_bounds__(256) k_multidot2(const double* __restrict__ V, int64_t n, int nv,
-                                                   const double* __restrict__ w, double* __restrict__ part) {
-    __shared__ double sh[128][4];
+// part[v * nb + b] = sum over block b of V_v[i] w[i]
+__global__ void __launch_bounds__(256) k_seg_dots(const double* __restrict__ V, int64_t n, int nv,
+                                                  const double* __restrict__ w, Seg sg, double* __restrict__ part) {
+    __shared__ double sh[kMaxM + 8][4];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t base = int64_t(blockIdx.x) * (256 * kE) + threadIdx.x;
+    const int64_t s0 = sg.start[blockIdx.x];
+    const int len = sg.len[blockIdx.x];
     double wv[kE];
 #pragma unroll
     for (int e = 0; e < kE; ++e) {
-        const int64_t i = base + 256 * e;
-        wv[e] = i < n ? w[i] : 0.0;
+        const int o = threadIdx.x + 256 * e;
+        wv[e] = o < len ? w[s0 + o] : 0.0;
     }
     for (int v = 0; v < nv; ++v) {
-        const double* Vv = V + int64_t(v) * n;
+        const double* Vv = V + int64_t(v) * n + s0;
         double acc = 0.0;
 #pragma unroll
         for (int e = 0; e < kE; ++e) {
-            const int64_t i = base + 256 * e;
-            if (i < n) acc += Vv[i] * wv[e];
+            const int o = threadIdx.x + 256 * e;
+            if (o < len) acc += Vv[o] * wv[e];
         }
         acc = wave_sum(acc);
         if (lane == 0) sh[v][wave] = acc;
     }
-    block_store_parts(sh, nv, part);
+    store_block_parts(sh, nv, part);
 }
 
-// w -= sum_k c[k] V_k, then the dots of the updated w with the same vectors (the second
-// sweep re-reads the block's slice of V while it is still in cache).
-__global__ void __launch_bounds__(256) k_update_dot(const double* __restrict__ V, int64_t n, int nv,
-                                                    const double* __restrict__ c, double* __restrict__ w,
-                                                    double* __restrict__ part) {
-    __shared__ double sh[128][4];
-    __shared__ double cs[128];
-    for (int k = threadIdx.x; k < nv; k += blockDim.x) cs[k] = c[k];
+// w -= sum_k c_inst[k] V_k over the block, then part[v * nb + b] = V_v . w (new w).
+__global__ void __launch_bounds__(256) k_seg_update_dot(const double* __restrict__ V, int64_t n, int nv,
+                                                        const double* __restrict__ c, int cstride,
+                                                        double* __restrict__ w, Seg sg, double* __restrict__ part) {
+    __shared__ double sh[kMaxM + 8][4];
+    __shared__ double cs[kMaxM + 8];
+    const int64_t s0 = sg.start[blockIdx.x];
+    const int len = sg.len[blockIdx.x];
+    const double* ci = c + int64_t(sg.inst[blockIdx.x]) * cstride;
+    for (int k = threadIdx.x; k < nv; k += blockDim.x) cs[k] = ci[k];
     __syncthreads();
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t base = int64_t(blockIdx.x) * (256 * kE) + threadIdx.x;
     double wv[kE];
 #pragma unroll
     for (int e = 0; e < kE; ++e) {
-        const int64_t i = base + 256 * e;
-        wv[e] = i < n ? w[i] : 0.0;
+        const int o = threadIdx.x + 256 * e;
+        wv[e] = o < len ? w[s0 + o] : 0.0;
     }
     for (int v = 0; v < nv; ++v) {
-        const double* Vv = V + int64_t(v) * n;
+        const double* Vv = V + int64_t(v) * n + s0;
         const double cv = cs[v];
 #pragma unroll
         for (int e = 0; e < kE; ++e) {
-            const int64_t i = base + 256 * e;
-            if (i < n) wv[e] -= cv * Vv[i];
+            const int o = threadIdx.x + 256 * e;
+            if (o < len) wv[e] -= cv * Vv[o];
         }
     }
 #pragma unroll
     for (int e = 0; e < kE; ++e) {
-        const int64_t i = base + 256 * e;
-        if (i < n) w[i] = wv[e];
+        const int o = threadIdx.x + 256 * e;
+        if (o < len) w[s0 + o] = wv[e];
     }
     for (int v = 0; v < nv; ++v) {
-        const double* Vv = V + int64_t(v) * n;
+        const double* Vv = V + int64_t(v) * n + s0;
         double acc = 0.0;
 #pragma unroll
         for (int e = 0; e < kE; ++e) {
-            const int64_t i = base + 256 * e;
-            if (i < n) acc += Vv[i] * wv[e];
+            const int o = threadIdx.x + 256 * e;
+            if (o < len) acc += Vv[o] * wv[e];
         }
         acc = wave_sum(acc);
         if (lane == 0) sh[v][wave] = acc;
     }
-    block_store_parts(sh, nv, part);
+    store_block_parts(sh, nv, part);
 }
 
-// h[v] (+)= sum_bx part[v * nb + bx]
-__global__ void __launch_bounds__(256) k_reduce_parts(const double* __restrict__ part, int nb,
-                                                      double* __restrict__ h, int accumulate) {
+// w -= sum_k c_inst[k] V_k; part[b] = sum of the new w^2 over the block
+__global__ void __launch_bounds__(256) k_seg_update_norm(const double* __restrict__ V, int64_t n, int nv,
+                                                         const double* __restrict__ c, int cstride,
+                                                         double* __restrict__ w, Seg sg, double* __restrict__ part) {
     __shared__ double sh[16];
-    const int v = blockIdx.x;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += part[int64_t(v) * nb + i];
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) h[v] = accumulate ? h[v] + s : s;
-}
-
-// w -= sum_k c[k] V_k; optional partial sums of the squared result
-__global__ void __launch_bounds__(256) k_update(const double* __restrict__ V, int64_t n, int nv,
-                                                const double* __restrict__ c, double* __restrict__ w,
-                                                double* __restrict__ part) {
-    __shared__ double sh[16];
-    __shared__ double cs[128];
-    for (int k = threadIdx.x; k < nv && k < 128; k += blockDim.x) cs[k] = c[k];
+    __shared__ double cs[kMaxM + 8];
+    const int64_t s0 = sg.start[blockIdx.x];
+    const int len = sg.len[blockIdx.x];
+    const double* ci = c + int64_t(sg.inst[blockIdx.x]) * cstride;
+    for (int k = threadIdx.x; k < nv; k += blockDim.x) cs[k] = ci[k];
     __syncthreads();
     double acc = 0.0;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-        double t = w[i];
-        for (int k = 0; k < nv; ++k) t -= (k < 128 ? cs[k] : c[k]) * V[int64_t(k) * n + i];
-        w[i] = t;
-        acc += t * t;
-    }
-    if (part) {
-        const double s = block_sum(acc, sh);
-        if (threadIdx.x == 0) part[blockIdx.x] = s;
-    }
-}
-
-// y = x / ||x|| with ||x||^2 read from the device
-__global__ void k_scale_copy(int64_t n, const double* __restrict__ x, const double* __restrict__ nrm2,
-                             double* __restrict__ y) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) {
-        const double v = *nrm2;
-        y[i] = v > 0.0 ? x[i] / sqrt(v) : 0.0;
-    }
-}
-
-// x += sum_j y[j] Z_j
-__global__ void __launch_bounds__(256) k_combine(const double* __restrict__ Z, int64_t n, int nz,
-                                                 const double* __restrict__ y, double* __restrict__ x) {
-    __shared__ double ys[128];
-    for (int k = threadIdx.x; k < nz && k < 128; k += blockDim.x) ys[k] = y[k];
-    __syncthreads();
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-        double t = x[i];
-        for (int k = 0; k < nz; ++k) t += (k < 128 ? ys[k] : y[k]) * Z[int64_t(k) * n + i];
-        x[i] = t;
-    }
-}
-
-// r = F - r (r holds J x on entry); partial sums of r^2
-__global__ void __launch_bounds__(256) k_resid(int64_t n, const double* __restrict__ F, double* __restrict__ r,
-                                               double* __restrict__ part) {
-    __shared__ double sh[16];
-    double acc = 0.0;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-        const double t = F[i] - r[i];
-        r[i] = t;
-        acc += t * t;
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+        const int o = threadIdx.x + 256 * e;
+        if (o < len) {
+            double t = w[s0 + o];
+            for (int k = 0; k < nv; ++k) t -= cs[k] * V[int64_t(k) * n + s0 + o];
+            w[s0 + o] = t;
+            acc += t * t;
+        }
     }
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// r = F - r (r holds J x on entry, or nothing when from_zero: r = F); part[b] = sum r^2
+__global__ void __launch_bounds__(256) k_seg_resid(const double* __restrict__ F, double* __restrict__ r, int from_zero,
+                                                   Seg sg, double* __restrict__ part) {
+    __shared__ double sh[16];
+    const int64_t s0 = sg.start[blockIdx.x];
+    const int len = sg.len[blockIdx.x];
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+        const int o = threadIdx.x + 256 * e;
+        if (o < len) {
+            const double t = from_zero ? F[s0 + o] : F[s0 + o] - r[s0 + o];
+            r[s0 + o] = t;
+            acc += t * t;
+        }
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// dst = src * scale[inst]
+__global__ void __launch_bounds__(256) k_seg_scale(const double* __restrict__ src, double* __restrict__ dst,
+                                                   const double* __restrict__ scale, Seg sg) {
+    const int64_t s0 = sg.start[blockIdx.x];
+    const int len = sg.len[blockIdx.x];
+    const double a = scale[sg.inst[blockIdx.x]];
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+        const int o = threadIdx.x + 256 * e;
+        if (o < len) dst[s0 + o] = a * src[s0 + o];
+    }
+}
+
+// x += sum_k y_inst[k] Z_k
+__global__ void __launch_bounds__(256) k_seg_combine(const double* __restrict__ Z, int64_t n, int nz,
+                                                     const double* __restrict__ y, int ystride,
+                                                     double* __restrict__ x, Seg sg) {
+    __shared__ double ys[kMaxM + 8];
+    const int64_t s0 = sg.start[blockIdx.x];
+    const int len = sg.len[blockIdx.x];
+    const double* yi = y + int64_t(sg.inst[blockIdx.x]) * ystride;
+    for (int k = threadIdx.x; k < nz; k += blockDim.x) ys[k] = yi[k];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+        const int o = threadIdx.x + 256 * e;
+        if (o < len) {
+            double t = x[s0 + o];
+            for (int k = 0; k < nz; ++k) t += ys[k] * Z[int64_t(k) * n + s0 + o];
+            x[s0 + o] = t;
+        }
+    }
+}
+
+// out[inst * stride + v] = sum of part[v * nb + b] over the blocks of the instance
+__global__ void __launch_bounds__(256) k_seg_reduce(const double* __restrict__ part, int nb,
+                                                    const int32_t* __restrict__ bptr, double* __restrict__ out,
+                                                    int stride) {
+    __shared__ double sh[16];
+    const int v = blockIdx.x, inst = blockIdx.y;
+    double acc = 0.0;
+    for (int b = bptr[inst] + threadIdx.x; b < bptr[inst + 1]; b += blockDim.x) acc += part[int64_t(v) * nb + b];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[int64_t(inst) * stride + v] = s;
+}
+
+// Per-instance solver state (device).
+struct State {
+    double* h1;      // [ni][m+2] pass-1 coefficients (then the Hessenberg column)
+    double* h2;      // [ni][m+2] pass-2 coefficients
+    double* nrm2;    // [ni] ||w||^2 after orthogonalisation
+    double* H;       // [ni][(m+1) m] upper triangle after rotations, column-major
+    double* cs;      // [ni][m]
+    double* sn;      // [ni][m]
+    double* g;       // [ni][m+1]
+    double* y;       // [ni][m]
+    double* target;  // [ni] rtol ||F_i||
+    double* scale;   // [ni] 1/||w|| for the next basis vector (0 once done)
+    double* beta2;   // [ni] squared residual norm
+    int* done;       // [ni] converged (or stopped) in this cycle
+    int* jused;      // [ni] Krylov columns used by the instance in this cycle
+    int* bad;        // [ni] non-finite value seen
+};
+
+// new cycle: g = (beta, 0, ...), scale = 1/beta, done when beta <= target
+__global__ void k_cycle_start(int ni, int m, State st) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ni) return;
+    const double beta = sqrt(st.beta2[i]);
+    for (int k = 0; k <= m; ++k) st.g[int64_t(i) * (m + 1) + k] = 0.0;
+    st.g[int64_t(i) * (m + 1)] = beta;
+    const bool fin = isfinite(beta);
+    if (!fin) st.bad[i] = 1;
+    const bool dn = !fin || beta <= st.target[i];
+    st.done[i] = dn ? 1 : 0;
+    st.jused[i] = 0;
+    st.scale[i] = (!dn && beta > 0.0) ? 1.0 / beta : 0.0;
+}
+
+// Hessenberg column j: combine the two passes, apply the previous rotations, make the new
+// one, update g, test convergence.  Instances already done are left untouched.
+__global__ void k_givens(int ni, int m, int j, State st) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ni) return;
+    if (st.done[i]) {
+        st.scale[i] = 0.0;
+        return;
+    }
+    double* h = st.h1 + int64_t(i) * (m + 2);
+    const double* h2 = st.h2 + int64_t(i) * (m + 2);
+    double* cs = st.cs + int64_t(i) * m;
+    double* sn = st.sn + int64_t(i) * m;
+    double* g = st.g + int64_t(i) * (m + 1);
+    double* H = st.H + int64_t(i) * (m + 1) * m;
+    for (int k = 0; k <= j; ++k) h[k] += h2[k];
+    const double nw = sqrt(st.nrm2[i]);
+    h[j + 1] = nw;
+    for (int k = 0; k < j; ++k) {
+        const double a = h[k], b = h[k + 1];
+        h[k] = cs[k] * a + sn[k] * b;
+        h[k + 1] = -sn[k] * a + cs[k] * b;
+    }
+    const double a = h[j], b = h[j + 1];
+    const double r = hypot(a, b);
+    cs[j] = r > 0.0 ? a / r : 1.0;
+    sn[j] = r > 0.0 ? b / r : 0.0;
+    h[j] = r;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    for (int k = 0; k <= j; ++k) H[int64_t(j) * (m + 1) + k] = h[k];
+    st.jused[i] = j + 1;
+    const bool fin = isfinite(nw) && isfinite(g[j + 1]);
+    if (!fin) st.bad[i] = 1;
+    const bool conv = fabs(g[j + 1]) <= st.target[i];
+    const bool brk = !(nw > 0.0);      // invariant subspace: the solution is in the basis
+    if (!fin || conv || brk || j + 1 == m) st.done[i] = 1;
+    st.scale[i] = (st.done[i] || !(nw > 0.0)) ? 0.0 : 1.0 / nw;
+}
+
+// y = H^-1 g on the jused x jused upper triangle
+__global__ void k_backsolve(int ni, int m, State st) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ni) return;
+    const int ju = st.jused[i];
+    const double* H = st.H + int64_t(i) * (m + 1) * m;
+    const double* g = st.g + int64_t(i) * (m + 1);
+    double* y = st.y + int64_t(i) * m;
+    for (int k = 0; k < m; ++k) y[k] = 0.0;
+    for (int r = ju - 1; r >= 0; --r) {
+        double t = g[r];
+        for (int k = r + 1; k < ju; ++k) t -= H[int64_t(k) * (m + 1) + r] * y[k];
+        const double d = H[int64_t(r) * (m + 1) + r];
+        y[r] = d != 0.0 ? t / d : 0.0;
+    }
+}
+
 }  // namespace
 
-fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du, fr_solve_stats& st, DevKrylov& ws,
-                 hipStream_t s) {
+// Block table of the segmented sweeps (built once per system / restart length).
+static void build_table(DevSystem& sys, DevKrylov& ws, hipStream_t s) {
+    const HostMesh& hm = sys.mesh->host;
+    const int D = sys.mesh->dim;
+    const int64_t nf = hm.n_free;
+    std::vector<int64_t> st;
+    std::vector<int32_t> ln, in, bp;
+    for (int i = 0; i < hm.n_inst; ++i) {
+        bp.push_back(int32_t(st.size()));
+        const int64_t f0 = hm.free_off[size_t(i)], f1 = hm.free_off[size_t(i) + 1];
+        const int64_t ranges[2][2] = {{D * f0, D * f1}, {D * nf + f0, D * nf + f1}};
+        for (auto& r : ranges)
+            for (int64_t a = r[0]; a < r[1]; a += kChunk) {
+                st.push_back(a);
+                ln.push_back(int32_t(std::min<int64_t>(kChunk, r[1] - a)));
+                in.push_back(i);
+            }
+    }
+    bp.push_back(int32_t(st.size()));
+    ws.seg_start.upload(st, s);
+    ws.seg_len.upload(ln, s);
+    ws.seg_inst.upload(in, s);
+    ws.seg_bptr.upload(bp, s);
+    ws.nb = int(st.size());
+    ws.n_inst = hm.n_inst;
+}
+
+fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du, fr_solve_stats* stats,
+                 DevKrylov& ws, hipStream_t s) {
     const int64_t n = sys.n_solve;
-    const int m = std::max(1, std::min(o.restart, 120));
-    if (ws.n != n || ws.m < m) {
+    const int ni = sys.mesh->n_inst;
+    const int m = std::max(1, std::min(o.restart, kMaxM));
+    if (ws.n != n || ws.m != m || ws.n_inst != ni) {
         ws.n = n;
         ws.m = m;
         ws.V.alloc(size_t(m + 1) * size_t(n), s);
         ws.Z.alloc(size_t(m) * size_t(n), s);
         ws.w.alloc(size_t(n), s);
-        ws.r.alloc(size_t(n), s);
-        ws.h.alloc(1024, s);
-        ws.part.alloc(size_t(std::max<int64_t>(kRowBlocks, ceil_div(n, 256 * kE))) * 128 + 1024, s);
+        build_table(sys, ws, s);
+        ws.part.alloc(size_t(ws.nb) * (kMaxM + 2) + 64, s);
+        const size_t per = size_t(2 * (m + 2) + 1 + (m + 1) * m + 2 * m + (m + 1) + m + 3);
+        ws.state.alloc(per * size_t(ni), s);
+        ws.istate.alloc(size_t(3 * ni), s);
     }
-    const int gridN = int(std::min<int64_t>(1024, ceil_div(n, 256)));
-    const int nbE = int(ceil_div(n, 256 * kE));
+    const int M = ws.m;
+    State st;
+    {
+        double* p = ws.state.p;
+        auto take = [&](size_t k) { double* q = p; p += k * size_t(ni); return q; };
+        st.h1 = take(M + 2);
+        st.h2 = take(M + 2);
+        st.nrm2 = take(1);
+        st.H = take(size_t(M + 1) * M);
+        st.cs = take(M);
+        st.sn = take(M);
+        st.g = take(M + 1);
+        st.y = take(M);
+        st.target = take(1);
+        st.scale = take(1);
+        st.beta2 = take(1);
+        st.done = ws.istate.p;
+        st.jused = ws.istate.p + ni;
+        st.bad = ws.istate.p + 2 * ni;
+    }
+    const Seg sg{ws.seg_start.p, ws.seg_len.p, ws.seg_inst.p};
+    const int nb = ws.nb;
+    const int gi = int(ceil_div(ni, 64));
     double* part = ws.part.p;
-    double* h = ws.h.p;          // [0, 122): Hessenberg column of the current iteration
-    double* h2 = ws.h.p + 256;   // [256, 378): re-orthogonalisation coefficients
-    double* yv = ws.h.p + 512;   // [512, 633): combination coefficients
-    double* nrm = ws.h.p + 768;  // squared norm scratch
+    FR_HIP(hipMemsetAsync(ws.istate.p, 0, size_t(3 * ni) * sizeof(int), s));
 
-    auto reduce_to = [&](double* out, int nb) {
-        k_reduce_parts<<<1, 256, 0, s>>>(part, nb, out, 0);
-        FR_LAUNCH_CHECK();
-    };
-
-    // ||F||
-    k_update<<<gridN, 256, 0, s>>>(ws.V.p, n, 0, h, sys.F.p, part);   // nv = 0: only the norm of F
+    // ||F_i||, targets
+    k_seg_resid<<<nb, 256, 0, s>>>(sys.F.p, ws.w.p, 1, sg, part);
     FR_LAUNCH_CHECK();
-    reduce_to(nrm, gridN);
-    const double bnorm = std::sqrt(download1(nrm, s));
-    FR_HIP(hipMemsetAsync(du, 0, size_t(n) * sizeof(double), s));
-    st.iters = 0;
-    st.relres = 0.0;
-    st.status = FR_OK;
-    if (!(bnorm > 0.0)) {
-        if (std::isnan(bnorm)) { st.status = FR_ENAN; return FR_ENAN; }
-        return FR_OK;
+    k_seg_reduce<<<dim3(1, ni), 256, 0, s>>>(part, nb, ws.seg_bptr.p, st.beta2, 1);
+    FR_LAUNCH_CHECK();
+    std::vector<double> bn2 = download(st.beta2, size_t(ni), s);
+    const size_t nis = static_cast<size_t>(ni);
+    std::vector<double> bnorm(nis, 0.0), target(nis, 0.0);
+    for (int i = 0; i < ni; ++i) {
+        bnorm[size_t(i)] = std::sqrt(bn2[size_t(i)]);
+        target[size_t(i)] = o.rtol * bnorm[size_t(i)];
     }
-    const double target = o.rtol * bnorm;
+    FR_HIP(hipMemcpyAsync(st.target, target.data(), size_t(ni) * 8, hipMemcpyHostToDevice, s));
+    FR_HIP(hipMemsetAsync(du, 0, size_t(n) * sizeof(double), s));
+
+    std::vector<int> iters(size_t(ni), 0), conv(size_t(ni), 0);
+    std::vector<double> relres(size_t(ni), 0.0);
     int total = 0;
     bool first = true;
-    const size_t ms = static_cast<size_t>(m);
-    std::vector<double> H((ms + 1) * ms, 0.0), cs(ms, 0.0), sn(ms, 0.0), g(ms + 1, 0.0);
     while (true) {
-        // r = F - J x
-        double beta;
-        if (first) {
-            vec_copy(sys.F.p, ws.w.p, n, s);
-            beta = bnorm;
-            dev_dot(ws.w.p, ws.w.p, n, nrm, ws.part, s);
-        } else {
-            jspmv(sys, du, ws.w.p, s);
-            k_resid<<<gridN, 256, 0, s>>>(n, sys.F.p, ws.w.p, part);
-            FR_LAUNCH_CHECK();
-            reduce_to(nrm, gridN);
-            beta = std::sqrt(download1(nrm, s));
-        }
-        first = false;
-        st.relres = beta / bnorm;
-        if (beta <= target) break;
-        if (total >= o.maxit) { st.status = FR_ENOCONV; break; }
-        k_scale_copy<<<int(ceil_div(n, 256)), 256, 0, s>>>(n, ws.w.p, nrm, ws.V.p);
+        // r = F - J x per instance, its norm, the new cycle
+        if (!first) jspmv(sys, du, ws.w.p, s);
+        k_seg_resid<<<nb, 256, 0, s>>>(sys.F.p, ws.w.p, first ? 1 : 0, sg, part);
         FR_LAUNCH_CHECK();
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
+        k_seg_reduce<<<dim3(1, ni), 256, 0, s>>>(part, nb, ws.seg_bptr.p, st.beta2, 1);
+        FR_LAUNCH_CHECK();
+        first = false;
+        k_cycle_start<<<gi, 64, 0, s>>>(ni, M, st);
+        FR_LAUNCH_CHECK();
+        std::vector<double> b2 = download(st.beta2, size_t(ni), s);
+        std::vector<int> dn = download(st.done, size_t(ni), s);
+        bool all_done = true;
+        for (int i = 0; i < ni; ++i) {
+            relres[size_t(i)] = bnorm[size_t(i)] > 0 ? std::sqrt(b2[size_t(i)]) / bnorm[size_t(i)] : 0.0;
+            conv[size_t(i)] = dn[size_t(i)];
+            all_done = all_done && dn[size_t(i)];
+        }
+        if (all_done || total >= o.maxit) break;
+        k_seg_scale<<<nb, 256, 0, s>>>(ws.w.p, ws.V.p, st.scale, sg);
+        FR_LAUNCH_CHECK();
         int j = 0;
-        bool breakdown = false;
-        for (; j < m && total < o.maxit; ++j) {
+        for (; j < M && total < o.maxit; ++j) {
             double* Vj = ws.V.p + int64_t(j) * n;
             double* Zj = ws.Z.p + int64_t(j) * n;
             amg_precondition(amg, Vj, Zj, s);
@@ -266,74 +411,69 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
             const int nv = j + 1;
             const double md_bytes = double(nv + 1) * double(n) * 8.0;
             const double up_bytes = double(nv + 2) * double(n) * 8.0;
-            // pass 1: h = V^T w
             {
                 ProfScope ps("gs_multidot", s, md_bytes);
-                k_multidot2<<<nbE, 256, 0, s>>>(ws.V.p, n, nv, ws.w.p, part);
+                k_seg_dots<<<nb, 256, 0, s>>>(ws.V.p, n, nv, ws.w.p, sg, part);
                 FR_LAUNCH_CHECK();
             }
-            k_reduce_parts<<<nv, 256, 0, s>>>(part, nbE, h, 0);
+            k_seg_reduce<<<dim3(nv, ni), 256, 0, s>>>(part, nb, ws.seg_bptr.p, st.h1, M + 2);
             FR_LAUNCH_CHECK();
-            // w -= V h and, in the same sweep, h2 = V^T w (re-orthogonalisation coefficients)
             {
                 ProfScope ps("gs_update_dot", s, up_bytes);
-                k_update_dot<<<nbE, 256, 0, s>>>(ws.V.p, n, nv, h, ws.w.p, part);
+                k_seg_update_dot<<<nb, 256, 0, s>>>(ws.V.p, n, nv, st.h1, M + 2, ws.w.p, sg, part);
                 FR_LAUNCH_CHECK();
             }
-            k_reduce_parts<<<nv, 256, 0, s>>>(part, nbE, h2, 0);
+            k_seg_reduce<<<dim3(nv, ni), 256, 0, s>>>(part, nb, ws.seg_bptr.p, st.h2, M + 2);
             FR_LAUNCH_CHECK();
-            // w -= V h2 and ||w||^2
             {
                 ProfScope ps("gs_update", s, up_bytes);
-                k_update<<<gridN, 256, 0, s>>>(ws.V.p, n, nv, h2, ws.w.p, part);
+                k_seg_update_norm<<<nb, 256, 0, s>>>(ws.V.p, n, nv, st.h2, M + 2, ws.w.p, sg, part);
                 FR_LAUNCH_CHECK();
             }
-            reduce_to(h + nv, gridN);       // ||w||^2 in h[j+1]
-            k_scale_copy<<<int(ceil_div(n, 256)), 256, 0, s>>>(n, ws.w.p, h + nv, ws.V.p + int64_t(j + 1) * n);
+            k_seg_reduce<<<dim3(1, ni), 256, 0, s>>>(part, nb, ws.seg_bptr.p, st.nrm2, 1);
             FR_LAUNCH_CHECK();
-            std::vector<double> hh = download(h, size_t(nv + 1), s);
-            std::vector<double> hc = download(h2, size_t(nv), s);
-            for (int i = 0; i < nv; ++i) hh[size_t(i)] += hc[size_t(i)];
-            hh[size_t(nv)] = std::sqrt(hh[size_t(nv)]);
+            k_givens<<<gi, 64, 0, s>>>(ni, M, j, st);
+            FR_LAUNCH_CHECK();
+            k_seg_scale<<<nb, 256, 0, s>>>(ws.w.p, ws.V.p + int64_t(j + 1) * n, st.scale, sg);
+            FR_LAUNCH_CHECK();
             ++total;
-            if (!std::isfinite(hh[size_t(nv)])) { st.status = FR_ENAN; breakdown = true; }
-            // Givens
-            for (int i = 0; i < j; ++i) {
-                const double a = hh[size_t(i)], b = hh[size_t(i + 1)];
-                hh[size_t(i)] = cs[size_t(i)] * a + sn[size_t(i)] * b;
-                hh[size_t(i + 1)] = -sn[size_t(i)] * a + cs[size_t(i)] * b;
-            }
-            const double a = hh[size_t(j)], b = hh[size_t(j + 1)];
-            const double rr = std::hypot(a, b);
-            cs[size_t(j)] = rr > 0 ? a / rr : 1.0;
-            sn[size_t(j)] = rr > 0 ? b / rr : 0.0;
-            hh[size_t(j)] = rr;
-            hh[size_t(j + 1)] = 0.0;
-            g[size_t(j + 1)] = -sn[size_t(j)] * g[size_t(j)];
-            g[size_t(j)] = cs[size_t(j)] * g[size_t(j)];
-            for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = hh[size_t(i)];
-            if (breakdown) { ++j; break; }
-            if (std::fabs(g[size_t(j + 1)]) <= target) { ++j; break; }
-            if (hh[size_t(j)] == 0.0) { ++j; break; }
+            std::vector<int> d2 = download(st.done, size_t(ni), s);
+            bool all = true;
+            for (int i = 0; i < ni; ++i) all = all && d2[size_t(i)];
+            if (all) { ++j; break; }
         }
-        // back substitution H y = g
-        std::vector<double> y(size_t(j), 0.0);
-        for (int i = j - 1; i >= 0; --i) {
-            double t = g[size_t(i)];
-            for (int k = i + 1; k < j; ++k) t -= H[size_t(i) * m + k] * y[size_t(k)];
-            const double d = H[size_t(i) * m + i];
-            y[size_t(i)] = d != 0.0 ? t / d : 0.0;
+        k_backsolve<<<gi, 64, 0, s>>>(ni, M, st);
+        FR_LAUNCH_CHECK();
+        std::vector<int> ju = download(st.jused, size_t(ni), s);
+        int jmax = 0;
+        for (int i = 0; i < ni; ++i) {
+            iters[size_t(i)] += ju[size_t(i)];
+            jmax = std::max(jmax, ju[size_t(i)]);
         }
-        if (j > 0) {
-            FR_HIP(hipMemcpyAsync(yv, y.data(), size_t(j) * sizeof(double), hipMemcpyHostToDevice, s));
-            k_combine<<<gridN, 256, 0, s>>>(ws.Z.p, n, j, yv, du);
+        if (jmax > 0) {
+            k_seg_combine<<<nb, 256, 0, s>>>(ws.Z.p, n, jmax, st.y, M, du, sg);
             FR_LAUNCH_CHECK();
         }
-        if (st.status == FR_ENAN) break;
+        std::vector<int> bad = download(st.bad, size_t(ni), s);
+        bool any_bad = false;
+        for (int b : bad) any_bad = any_bad || b;
+        if (any_bad) break;
     }
-    st.iters = total;
-    if (st.status == FR_OK && st.relres > o.rtol) st.status = FR_ENOCONV;
-    return fr_status(st.status);
+    std::vector<int> bad = download(st.bad, size_t(ni), s);
+    fr_status worst = FR_OK;
+    for (int i = 0; i < ni; ++i) {
+        fr_status si = FR_OK;
+        if (bad[size_t(i)]) si = FR_ENAN;
+        else if (!(relres[size_t(i)] <= o.rtol)) si = FR_ENOCONV;
+        if (stats) {
+            stats[i].iters = iters[size_t(i)];
+            stats[i].relres = relres[size_t(i)];
+            stats[i].status = si;
+        }
+        if (si == FR_ENAN) worst = FR_ENAN;
+        else if (si == FR_ENOCONV && worst == FR_OK) worst = FR_ENOCONV;
+    }
+    return worst;
 }
 
 }  // namespace fr

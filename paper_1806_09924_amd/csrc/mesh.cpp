@@ -367,6 +367,57 @@ HostMesh build_mesh(const fr_mesh_desc& d) {
     return m;
 }
 
+HostMesh build_mesh_batch(const fr_mesh_desc* d, int n) {
+    if (n < 1) fail(FR_EINVAL, "mesh: need at least one instance");
+    if (n == 1) {
+        HostMesh m = build_mesh(d[0]);
+        m.node_off = {0, m.n_nodes};
+        m.cell_off = {0, m.n_cells};
+        m.free_off = {0, m.n_free};
+        m.inst_h_min = {m.h_min};
+        return m;
+    }
+    HostMesh u;
+    u.dim = d[0].dim;
+    u.nv = 1 << u.dim;
+    u.n_inst = n;
+    u.node_off.assign(size_t(n) + 1, 0);
+    u.cell_off.assign(size_t(n) + 1, 0);
+    u.free_off.assign(size_t(n) + 1, 0);
+    u.h_min = 1e300;
+    u.con_ptr.push_back(0);
+    for (int i = 0; i < n; ++i) {
+        if (d[i].dim != u.dim) fail(FR_EINVAL, "mesh: all instances of a batch must have the same dim");
+        HostMesh m = build_mesh(d[i]);
+        const int64_t no = u.n_nodes, fo = u.n_free;
+        if (no + m.n_nodes >= (int64_t(1) << 31)) fail(FR_EINVAL, "mesh: batch has too many nodes");
+        u.coords.insert(u.coords.end(), m.coords.begin(), m.coords.end());
+        u.lattice.insert(u.lattice.end(), m.lattice.begin(), m.lattice.end());
+        for (int32_t v : m.cells) u.cells.push_back(int32_t(v + no));
+        u.cell_lo.insert(u.cell_lo.end(), m.cell_lo.begin(), m.cell_lo.end());
+        u.cell_h.insert(u.cell_h.end(), m.cell_h.begin(), m.cell_h.end());
+        u.dirichlet.insert(u.dirichlet.end(), m.dirichlet.begin(), m.dirichlet.end());
+        for (int32_t f : m.free_of_node) u.free_of_node.push_back(f < 0 ? -1 : int32_t(f + fo));
+        for (int32_t v : m.node_of_free) u.node_of_free.push_back(int32_t(v + no));
+        const int32_t cbase = u.con_ptr.back();
+        for (size_t k = 1; k < m.con_ptr.size(); ++k) u.con_ptr.push_back(cbase + m.con_ptr[k]);
+        for (int32_t v : m.con_master) u.con_master.push_back(int32_t(v + fo));
+        u.con_w.insert(u.con_w.end(), m.con_w.begin(), m.con_w.end());
+        u.n_nodes += m.n_nodes;
+        u.n_cells += m.n_cells;
+        u.n_free += m.n_free;
+        u.n_hanging += m.n_hanging;
+        u.h_min = std::min(u.h_min, m.h_min);
+        u.inst_h_min.push_back(m.h_min);
+        u.node_off[size_t(i) + 1] = u.n_nodes;
+        u.cell_off[size_t(i) + 1] = u.n_cells;
+        u.free_off[size_t(i) + 1] = u.n_free;
+        if (i == 0)
+            for (int k = 0; k < 3; ++k) { u.lo[k] = m.lo[k]; u.hi[k] = m.hi[k]; }
+    }
+    return u;
+}
+
 Pattern build_pattern(const HostMesh& m, int C) {
     Pattern p;
     p.C = C;

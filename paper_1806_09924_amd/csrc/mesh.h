@@ -24,6 +24,11 @@ struct HostMesh {
     // Conformity: value(node) = sum_j con_w[j] * value(free con_master[j]), j in [con_ptr[n], con_ptr[n+1]).
     std::vector<int32_t> con_ptr, con_master;
     std::vector<double> con_w;
+    // Independent instances stored as a disjoint union (instance-major numbering of nodes,
+    // cells and free nodes); one instance: n_inst = 1 and the offsets are {0, total}.
+    int n_inst = 1;
+    std::vector<int64_t> node_off, cell_off, free_off;   // [n_inst+1]
+    std::vector<double> inst_h_min;                        // [n_inst]
 };
 
 // Node-graph pattern in SELL-C layout plus the tables of the node-centric assembly.
@@ -43,6 +48,8 @@ struct Pattern {
 };
 
 HostMesh build_mesh(const fr_mesh_desc& d);
+// Disjoint union of n independent meshes of the same dimension.
+HostMesh build_mesh_batch(const fr_mesh_desc* d, int n);
 Pattern build_pattern(const HostMesh& m, int C);
 
 }  // namespace fr

@@ -51,6 +51,8 @@ struct DevMesh {
     int64_t n_nodes = 0, n_cells = 0, n_free = 0;
     bool hanging = false;
     bool on_device = false;                      // false: host-only mesh (inspection)
+    int n_inst = 1;                              // independent instances (disjoint union)
+    DBuf<int32_t> inst_of_free, inst_of_cell;    // only when n_inst > 1
     DBuf<int32_t> cells, node_of_free, free_of_node, con_ptr, con_master;
     DBuf<double> cell_h, cell_lo, con_w, coords_free;
     DBuf<uint8_t> dir_free;                      // Dirichlet flag per free node
@@ -60,12 +62,14 @@ struct DevMesh {
     DBuf<double> ent_w;
 };
 
-std::unique_ptr<DevMesh> mesh_create(const fr_mesh_desc& d, hipStream_t s, bool upload);
+std::unique_ptr<DevMesh> mesh_create(const fr_mesh_desc* d, int n_inst, hipStream_t s, bool upload);
 
 // ---- assembled system -------------------------------------------------------------------
 struct DevSystem {
     DevMesh* mesh = nullptr;
-    Params prm{};
+    Params prm{};                                // instance 0
+    std::vector<Params> prm_h;                   // per instance
+    DBuf<Params> prm_d;                          // per instance (device), when n_inst > 1
     hipStream_t stream = nullptr;
     int64_t n_solve = 0, n_u = 0;
     BMat<double> Juu, Jpu, Jpp;                  // share the node-graph structure
@@ -155,11 +159,15 @@ void amg_info(DevAmg& amg, int blk, int level, int& n_levels, int64_t& rows, int
 // ---- Krylov (krylov.hip) ----------------------------------------------------------------
 struct DevKrylov {
     int64_t n = 0;
-    int m = 0;
-    DBuf<double> V, Z, w, h, part, x, r;
+    int m = 0, n_inst = 0, nb = 0;
+    DBuf<double> V, Z, w, part, state;
+    DBuf<int> istate;
+    DBuf<int64_t> seg_start;                     // segmented-sweep block table
+    DBuf<int32_t> seg_len, seg_inst, seg_bptr;
 };
 
-fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du, fr_solve_stats& st,
+// stats: host, one per instance (nullable). Returns the worst instance status.
+fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du, fr_solve_stats* stats,
                  DevKrylov& ws, hipStream_t s);
 
 }  // namespace fr
