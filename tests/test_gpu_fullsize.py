@@ -1,0 +1,133 @@
+"""Parity at the benchmark's full size (2048 x 2048 Q1 on [-10,10]^2, 12,595,203 DoFs) in
+the configuration bench.py times.  The oracle cannot solve this size in a test, so it
+checks sampled rows it can compute exactly (residual, active set, J x) from the cells around
+them, and properties that hold at any size: the oracle-evaluated residual rows of the GPU
+solution, the KKT conditions after the Newton loop, and TCV of the GPU fields."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1806_09924_amd import binding as B
+from oracle import mesh as omesh, fem, newton as onewton, functionals as ofun
+from oracle.material import Params as OParams
+from inputs import crack_band_phi
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+L, N, L0 = 10.0, 2048, 0.25
+
+
+@pytest.fixture(scope="module")
+def big():
+    mesh = B.Mesh(B.mesh_desc(2, -L, L, N))
+    om = omesh.uniform(2, -L, L, N)
+    h = 2 * L / N
+    eps = 2 * h
+    phi0 = crack_band_phi(om.coords, L0, eps)
+    rng = np.random.default_rng(2048)
+    n1 = N + 1
+    # sample: random nodes, the crack region, boundary nodes and corners
+    ii, jj = np.meshgrid(np.arange(N // 2 - 40, N // 2 + 41), np.arange(N // 2 - 6, N // 2 + 7), indexing="ij")
+    crack = (ii + n1 * jj).ravel()
+    bnd = np.concatenate([np.arange(0, n1, 97), n1 * np.arange(0, n1, 89), [n1 * n1 - 1]])
+    sample = np.unique(np.concatenate([rng.integers(0, n1 * n1, 1500), crack, bnd]))
+    return dict(mesh=mesh, om=om, prm=B.params(eps=eps, kappa=1e-10, p=1e-3),
+                oprm=OParams(eps=eps, kappa=1e-10, p=1e-3), phi0=phi0, sample=sample)
+
+
+def _rows_ctx(om, sample, rings):
+    """Cells within `rings` node layers of the sample (rows of the sample complete)."""
+    n1 = N + 1
+    i, j = sample % n1, sample // n1
+    cells = []
+    for di in range(-rings, rings):
+        for dj in range(-rings, rings):
+            ci, cj = i + di, j + dj
+            ok = (ci >= 0) & (ci < N) & (cj >= 0) & (cj < N)
+            cells.append((ci + N * cj)[ok])
+    return np.unique(np.concatenate(cells))
+
+
+def _neighbours(sample):
+    n1 = N + 1
+    i, j = sample % n1, sample // n1
+    out = []
+    for di in (-1, 0, 1):
+        for dj in (-1, 0, 1):
+            ci, cj = i + di, j + dj
+            ok = (ci >= 0) & (ci <= N) & (cj >= 0) & (cj <= N)
+            out.append((ci + n1 * cj)[ok])
+    return np.unique(np.concatenate(out))
+
+
+def test_fullsize_assembly_sampled_rows(big):
+    m, om, S_ = big["mesh"], big["om"], big["sample"]
+    assert m.n_all == 12595203 == om.n_all
+    u0 = np.zeros((om.n_nodes, 2))
+    phi0 = big["phi0"]
+    S = B.System(m).assemble(big["prm"], dev(u0), dev(phi0), dev(phi0), dev(phi0))
+    R, F, Bm, act = S.vectors()
+    R, F, Bm, act = host(R), host(F), host(Bm), host(act).astype(bool)
+    nb = _neighbours(S_)
+    cells = _rows_ctx(om, nb, 1)
+    Ru, Rp, mass = fem.residual_all(om, big["oprm"], u0, phi0, phi0, cells_idx=cells)
+    nf = om.n_free
+    scale = max(np.abs(R).max(), 1e-300)
+    assert np.abs(R[2 * S_] - Ru[S_, 0]).max() <= 1e-12 * scale
+    assert np.abs(R[2 * S_ + 1] - Ru[S_, 1]).max() <= 1e-12 * scale
+    assert np.abs(R[2 * nf + S_] - Rp[S_]).max() <= 1e-12 * scale
+    assert np.abs(Bm[S_] - mass[S_]).max() <= 1e-13 * mass.max()
+    # active set at the sample and its neighbours, decided in FP64 from complete rows
+    lam = -Rp[nb] / mass[nb]
+    margin = lam + (phi0[nb] - phi0[nb]) - big["oprm"].tau
+    ref_act = margin > 0
+    assert np.array_equal(act[nb], ref_act) or not np.any((act[nb] != ref_act) & (np.abs(margin) > 1e-9))
+    assert act.sum() == int((phi0 == 0).sum()) == 153      # the three node rows of the initial band
+    # J x on the sample rows against the oracle's rows (masked with the active set)
+    x = np.random.default_rng(7).standard_normal(m.n_solve)
+    y = torch.empty(m.n_solve, dtype=torch.float64, device="cuda")
+    S.matvec(dev(x), y)
+    y = host(y)
+    J = fem.jacobian_all(om, big["oprm"], u0, phi0, phi0, cells_idx=_rows_ctx(om, S_, 1)).tocsr()
+    fixed = np.zeros(m.n_solve, dtype=bool)
+    fixed[:2 * nf] = np.repeat(om.dirichlet, 2)
+    fixed[2 * nf:] = act
+    rows = np.concatenate([2 * S_, 2 * S_ + 1, 2 * nf + S_])
+    Jr = J[rows]
+    diag = np.asarray(J[rows, rows]).ravel()
+    keep = ~fixed
+    ref = np.where(fixed[rows], diag * x[rows], Jr @ np.where(keep, x, 0.0))
+    assert np.abs(y[rows] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_fullsize_newton_loop_kkt_and_functionals(big):
+    m, om, S_ = big["mesh"], big["om"], big["sample"]
+    phi0 = big["phi0"]
+    u = torch.zeros((om.n_nodes, 2), dtype=torch.float64, device="cuda")
+    phi = dev(phi0)
+    st = B.newton(m, big["prm"], u, phi, dev(phi0), dev(phi0))
+    assert st["status"] == 0 and st["iterations"] <= 6
+    assert st["linear_iters"] / st["iterations"] <= 66        # within 2x Table 1 (ref 8: 30-33)
+    ug, pg = host(u), host(phi)
+    # KKT at sampled nodes from complete oracle rows
+    nb = _neighbours(S_)
+    Ru, Rp, mass = fem.residual_all(om, big["oprm"], ug, pg, phi0, cells_idx=_rows_ctx(om, nb, 1))
+    res0 = st["res0"]
+    inner = ~om.dirichlet[S_]
+    assert np.abs(Ru[S_][inner]).max() <= 1e-7 * res0
+    # feasibility up to the active-set threshold tau = 1e-10 G_c / eps (inactive DoFs may sit
+    # within tau above phi_old)
+    assert np.all(pg[S_] <= phi0[S_] + 2 * big["oprm"].tau)
+    lam = -Rp[S_] / mass[S_]
+    act = lam + (pg[S_] - phi0[S_]) - big["oprm"].tau > 0
+    assert np.all(np.abs(pg[S_][act] - phi0[S_][act]) <= 1e-10)
+    assert np.abs(Rp[S_][~act]).max() <= 1e-7 * res0
+    # functionals of the GPU fields: GPU reduction vs the oracle's, and Sneddon's band
+    xs = [[0.5 * (2 * L / N)]]
+    cod, tcv = B.functionals(m, u, phi, xs)
+    t_o = ofun.tcv(om, ug, pg)
+    assert abs(tcv / t_o - 1) <= 1e-12
+    assert abs(cod[0] / ofun.cod(om, ug, pg, xs[0]) - 1) <= 1e-12
+    exact = ofun.sneddon_tcv(2, 1e-3, L0, 1.0, 0.2)
+    assert abs(tcv / exact - 1) <= 0.10
