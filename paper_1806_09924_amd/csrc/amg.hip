@@ -103,19 +103,44 @@ __global__ void k_mis_prop(int64_t n, int C, const int32_t* __restrict__ sp, con
     out[r] = m;
 }
 
-__global__ void k_mis_update(int64_t n, const uint64_t* __restrict__ m2, uint8_t* __restrict__ state,
-                             uint64_t* __restrict__ key, int32_t* __restrict__ undecided) {
+__global__ void __launch_bounds__(256) k_mis_update(int64_t n, const uint64_t* __restrict__ m2,
+                                                    uint8_t* __restrict__ state, uint64_t* __restrict__ key,
+                                                    int32_t* __restrict__ undecided) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (state[i] != 1) return;
-    if (m2[i] == key[i]) {
-        state[i] = 2;
-        key[i] = mis_key(2, i);
-    } else if ((m2[i] >> 62) == 2) {
-        state[i] = 0;
-        key[i] = mis_key(0, i);
-    } else {
-        atomicAdd(undecided, 1);
+    int und = 0;
+    if (i < n && state[i] == 1) {
+        if (m2[i] == key[i]) {
+            state[i] = 2;
+            key[i] = mis_key(2, i);
+        } else if ((m2[i] >> 62) == 2) {
+            state[i] = 0;
+            key[i] = mis_key(0, i);
+        } else {
+            und = 1;
+        }
+    }
+    // one atomic per wave with undecided nodes (the count only decides termination)
+    und = wave_sum_int(und);
+    if (threadIdx.x % kWave == 0 && und) atomicAdd(undecided, und);
+}
+
+// nnz (sum) and the longest row of a structure, without copying row_len to the host
+__global__ void __launch_bounds__(256) k_len_stats(const int32_t* __restrict__ len, int64_t n,
+                                                   unsigned long long* __restrict__ out) {
+    int64_t s = 0;
+    int mx = 0;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        s += len[i];
+        mx = max(mx, len[i]);
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        s += __shfl_xor(s, o);
+        mx = max(mx, __shfl_xor(mx, o));
+    }
+    if (threadIdx.x % kWave == 0) {
+        atomicAdd(&out[0], (unsigned long long)s);
+        atomicMax(&out[1], (unsigned long long)mx);
     }
 }
 
@@ -233,56 +258,102 @@ __global__ void k_tentative(int64_t na, const int32_t* __restrict__ aptr, const 
             for (int k = 0; k < dim; ++k) xc[k] += coords[int64_t(anodes[t]) * dim + k];
         for (int k = 0; k < dim; ++k) xc[k] /= double(b1 - b0);
     }
-    double Rm[NS][NS];
-    for (int i = 0; i < NS; ++i)
-        for (int j = 0; j < NS; ++j) Rm[i][j] = 0.0;
-    auto qslot = [&](int64_t node) -> double* {
-        return pval + (int64_t(psp[node / C]) + (node % C)) * (BR * NS);
+    // Cholesky QR, twice: G = B^T B = R1^T R1, then the Gram matrix of B R1^-1 gives R2,
+    // Q = B (R2 R1)^-1, R = R2 R1.  The aggregate's rows are regenerated on every pass
+    // (from the coordinates at level 0), so Q is written once.  A column whose remaining
+    // norm falls below 1e-10 of its own norm is dependent and dropped (zero in Q and R).
+    auto brow = [&](int64_t node, int c, double* v) {
+        for (int j = 0; j < NS; ++j)
+            v[j] = LEVEL0 ? nullspace0<BR, NS>(c, j, coords + node * dim, xc) : Bf[(node * BR + c) * NS + j];
     };
-    for (int j = 0; j < NS; ++j) {
-        // column j of the local near-null space
-        double nrm0 = 0.0;
+    double Ri[NS][NS];   // accumulated R^-1 (upper triangular)
+    double Rm[NS][NS];   // accumulated R
+    for (int i = 0; i < NS; ++i)
+        for (int j = 0; j < NS; ++j) Ri[i][j] = Rm[i][j] = (i == j) ? 1.0 : 0.0;
+    bool drop[NS];
+    for (int j = 0; j < NS; ++j) drop[j] = false;
+    for (int pass = 0; pass < 2; ++pass) {
+        double G[NS][NS];
+        for (int i = 0; i < NS; ++i)
+            for (int j = 0; j < NS; ++j) G[i][j] = 0.0;
         for (int32_t t = b0; t < b1; ++t) {
             const int64_t node = anodes[t];
-            double* q = qslot(node);
             for (int c = 0; c < BR; ++c) {
-                double v;
-                if (LEVEL0) v = nullspace0<BR, NS>(c, j, coords + node * dim, xc);
-                else v = Bf[(node * BR + c) * NS + j];
-                q[c * NS + j] = v;
-                nrm0 += v * v;
+                double v[NS], q[NS];
+                brow(node, c, v);
+                for (int j = 0; j < NS; ++j) {
+                    double s = 0.0;
+                    for (int k = 0; k <= j; ++k) s += v[k] * Ri[k][j];
+                    q[j] = s;
+                }
+                for (int i = 0; i < NS; ++i)
+                    for (int j = i; j < NS; ++j) G[i][j] += q[i] * q[j];
             }
         }
-        nrm0 = sqrt(nrm0);
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int i = 0; i < j; ++i) {
-                double dot = 0.0;
-                for (int32_t t = b0; t < b1; ++t) {
-                    const double* q = qslot(anodes[t]);
-                    for (int c = 0; c < BR; ++c) dot += q[c * NS + i] * q[c * NS + j];
-                }
-                Rm[i][j] += dot;
-                for (int32_t t = b0; t < b1; ++t) {
-                    double* q = qslot(anodes[t]);
-                    for (int c = 0; c < BR; ++c) q[c * NS + j] -= dot * q[c * NS + i];
-                }
+        // R = chol(G) (upper), dependent columns dropped
+        double Rp[NS][NS];
+        for (int i = 0; i < NS; ++i)
+            for (int j = 0; j < NS; ++j) Rp[i][j] = 0.0;
+        for (int j = 0; j < NS; ++j) {
+            if (drop[j]) continue;
+            double d = G[j][j];
+            for (int k = 0; k < j; ++k) d -= Rp[k][j] * Rp[k][j];
+            if (!(d > 1e-20 * G[j][j]) || !(G[j][j] > 0.0)) {
+                drop[j] = true;
+                continue;
+            }
+            Rp[j][j] = sqrt(d);
+            for (int k = j + 1; k < NS; ++k) {
+                double s = G[j][k];
+                for (int i = 0; i < j; ++i) s -= Rp[i][j] * Rp[i][k];
+                Rp[j][k] = s / Rp[j][j];
             }
         }
-        double nrm = 0.0;
-        for (int32_t t = b0; t < b1; ++t) {
-            const double* q = qslot(anodes[t]);
-            for (int c = 0; c < BR; ++c) nrm += q[c * NS + j] * q[c * NS + j];
+        // inverse of this pass's factor (dropped rows/columns stay zero)
+        double Pi[NS][NS];
+        for (int i = 0; i < NS; ++i)
+            for (int j = 0; j < NS; ++j) Pi[i][j] = 0.0;
+        for (int j = 0; j < NS; ++j) {
+            if (drop[j]) continue;
+            Pi[j][j] = 1.0 / Rp[j][j];
+            for (int i = j - 1; i >= 0; --i) {
+                if (drop[i]) continue;
+                double s = 0.0;
+                for (int k = i + 1; k <= j; ++k) s += Rp[i][k] * Pi[k][j];
+                Pi[i][j] = -s / Rp[i][i];
+            }
         }
-        nrm = sqrt(nrm);
-        const bool keep = nrm > 1e-10 * nrm0 && nrm > 0.0;
-        Rm[j][j] = keep ? nrm : 0.0;
-        const double sc = keep ? 1.0 / nrm : 0.0;
-        for (int32_t t = b0; t < b1; ++t) {
-            double* q = qslot(anodes[t]);
-            for (int c = 0; c < BR; ++c) q[c * NS + j] *= sc;
+        // Ri <- Ri Pi, Rm <- Rp Rm
+        double T1[NS][NS], T2[NS][NS];
+        for (int i = 0; i < NS; ++i)
+            for (int j = 0; j < NS; ++j) {
+                double a1 = 0.0, a2 = 0.0;
+                for (int k = 0; k < NS; ++k) {
+                    a1 += Ri[i][k] * Pi[k][j];
+                    a2 += Rp[i][k] * Rm[k][j];
+                }
+                T1[i][j] = a1;
+                T2[i][j] = a2;
+            }
+        for (int i = 0; i < NS; ++i)
+            for (int j = 0; j < NS; ++j) {
+                Ri[i][j] = drop[j] ? 0.0 : T1[i][j];
+                Rm[i][j] = drop[i] ? 0.0 : T2[i][j];
+            }
+    }
+    // Q = B R^-1 into the tentative prolongator (one block per node, at its aggregate)
+    for (int32_t t = b0; t < b1; ++t) {
+        const int64_t node = anodes[t];
+        double* q = pval + (int64_t(psp[node / C]) + (node % C)) * (BR * NS);
+        for (int c = 0; c < BR; ++c) {
+            double v[NS];
+            brow(node, c, v);
+            for (int j = 0; j < NS; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < NS; ++k) s += v[k] * Ri[k][j];
+                q[c * NS + j] = s;
+            }
         }
-        if (!keep)
-            for (int i = 0; i < j; ++i) Rm[i][j] = 0.0;
     }
     // coarse near-null space: R T (T maps centred to global rotations at level 0)
     double T[NS][NS];
@@ -577,9 +648,25 @@ __global__ void k_normalize_copy(int64_t n, const double* __restrict__ t, const 
     if (i < n) x[i] = t[i] * (*nrm2 > 0.0 ? 1.0 / sqrt(*nrm2) : 0.0);
 }
 
-__global__ void k_mul(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ c) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) c[i] = a[i] * b[i];
+__global__ void __launch_bounds__(256) k_mul_dot(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                                                 double* __restrict__ c, double* __restrict__ part) {
+    __shared__ double sh[16];
+    double acc = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const double v = a[i] * b[i];
+        c[i] = v;
+        acc += v * v;
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_sum_parts1(const double* __restrict__ part, int n, double* __restrict__ out) {
+    __shared__ double sh[16];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) *out = s;
 }
 
 // ---- dense coarsest level ------------------------------------------------------------------
@@ -661,15 +748,17 @@ std::shared_ptr<SellStruct> new_struct(int64_t n_rows, int64_t n_cols, hipStream
 }
 
 int64_t block_nnz(const SellStruct& S, hipStream_t s, int* max_len = nullptr) {
-    auto len = download(S.row_len, size_t(S.n_rows), s);
-    int64_t t = 0;
-    int mx = 0;
-    for (int32_t v : len) {
-        t += v;
-        mx = std::max(mx, int(v));
+    DBuf<unsigned long long> st;
+    st.alloc(2, s);
+    st.zero(s);
+    if (S.n_rows > 0) {
+        const int g = int(std::min<int64_t>(1024, ceil_div(S.n_rows, 256)));
+        k_len_stats<<<g, 256, 0, s>>>(S.row_len, S.n_rows, st.p);
+        FR_LAUNCH_CHECK();
     }
-    if (max_len) *max_len = mx;
-    return t;
+    auto h = download(st.p, 2, s);
+    if (max_len) *max_len = int(h[1]);
+    return int64_t(h[0]);
 }
 
 void finish_struct(SellStruct& S, hipStream_t s) {
@@ -679,11 +768,101 @@ void finish_struct(SellStruct& S, hipStream_t s) {
     S.nnz = block_nnz(S, s, &S.max_len);
 }
 
+// Row-merge numeric phase: a group of G lanes owns one output row; the row's sorted columns
+// and its accumulator blocks sit in LDS.  For every entry A_ik (in column order) the lanes
+// walk row k of B, find each column's position in the output row by binary search in LDS
+// and add A_ik B_kc there; within one A entry the columns are distinct, so no two lanes
+// touch the same accumulator, and the summation order is fixed.
+template <int BRA, int BCA, int BCB, int MODE, int G>
+__global__ void __launch_bounds__(256) k_spgemm_merge(SellV A, const double* __restrict__ av, SellV B,
+                                                      const double* __restrict__ bv, SellV Cm, double* __restrict__ cv,
+                                                      const double* __restrict__ invd, double omega, int LC) {
+    extern __shared__ double smem[];
+    constexpr int RPW = kWave / G, RPB = kWavesPerBlock * RPW, BB = BRA * BCB;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, gi = lane / G, lg = lane % G;
+    const int slot_in_block = w * RPW + gi;
+    double* acc = smem + size_t(slot_in_block) * LC * BB;
+    int32_t* cols = reinterpret_cast<int32_t*>(smem + size_t(RPB) * LC * BB) + slot_in_block * LC;
+    const int64_t r = int64_t(blockIdx.x) * RPB + slot_in_block;
+    if (r >= Cm.n_rows) return;
+    const int lc = Cm.len[r];
+    for (int k = lg; k < lc; k += G) {
+        cols[k] = Cm.col[sslot(Cm.sp, Cm.C, r, k)];
+        for (int e = 0; e < BB; ++e) acc[k * BB + e] = 0.0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int la = A.len[r];
+    for (int ka = 0; ka < la; ++ka) {
+        const int64_t as = sslot(A.sp, A.C, r, ka);
+        const int64_t k = A.col[as];
+        double ab[BRA * BCA];
+        for (int e = 0; e < BRA * BCA; ++e) ab[e] = av[as * (BRA * BCA) + e];
+        const int lb = B.len[k];
+        for (int kb = lg; kb < lb; kb += G) {
+            const int64_t bs = sslot(B.sp, B.C, k, kb);
+            const int32_t c = B.col[bs];
+            int lo = 0, hi = lc - 1, p = -1;
+            while (lo <= hi) {
+                const int mid = (lo + hi) >> 1;
+                const int32_t v = cols[mid];
+                if (v == c) { p = mid; break; }
+                if (v < c) lo = mid + 1;
+                else hi = mid - 1;
+            }
+            if (p < 0) continue;
+            const double* bb = bv + bs * (BCA * BCB);
+            for (int i = 0; i < BRA; ++i)
+                for (int j = 0; j < BCB; ++j) {
+                    double t = 0.0;
+                    for (int q = 0; q < BCA; ++q) t += ab[i * BCA + q] * bb[q * BCB + j];
+                    acc[p * BB + i * BCB + j] += t;
+                }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    const int64_t s0 = r / Cm.C;
+    const int width = (Cm.sp[s0 + 1] - Cm.sp[s0]) / Cm.C;
+    for (int kc = lg; kc < width; kc += G) {
+        const int64_t cs = sslot(Cm.sp, Cm.C, r, kc);
+        if (kc < lc) {
+            if (MODE == 1) {
+                const int kb = find_sorted(B, r, cols[kc]);
+                for (int i = 0; i < BRA; ++i) {
+                    const double dsc = omega * invd[r * BRA + i];
+                    for (int j = 0; j < BCB; ++j) {
+                        const double own = kb >= 0 ? bv[sslot(B.sp, B.C, r, kb) * (BCA * BCB) + i * BCB + j] : 0.0;
+                        cv[cs * BB + i * BCB + j] = own - dsc * acc[kc * BB + i * BCB + j];
+                    }
+                }
+            } else {
+                for (int e = 0; e < BB; ++e) cv[cs * BB + e] = acc[kc * BB + e];
+            }
+        } else {
+            for (int e = 0; e < BB; ++e) cv[cs * BB + e] = 0.0;
+        }
+    }
+}
+
 template <int BRA, int BCA, int BCB, int MODE>
 void spgemm_numeric(const BMat<double>& A, const BMat<double>& B, BMat<double>& Cm, const double* invd, double omega,
                     hipStream_t s) {
     const int ml = Cm.S->max_len;
     const int64_t rows = std::max<int64_t>(1, A.rows());
+    // row merge in LDS when the output rows fit (16 lanes per row, 16 rows per block)
+    {
+        constexpr int G = 16, RPB = kWavesPerBlock * (kWave / G), BB = BRA * BCB;
+        int LC = 8;
+        while (LC < ml) LC <<= 1;
+        const size_t lds = size_t(RPB) * LC * (BB * sizeof(double) + sizeof(int32_t));
+        if (ml <= 256 && lds <= 64 * 1024) {
+            k_spgemm_merge<BRA, BCA, BCB, MODE, G><<<nblk(rows, RPB), 256, lds, s>>>(
+                sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), Cm.val, invd, omega, LC);
+            FR_LAUNCH_CHECK();
+            return;
+        }
+    }
 #define FR_NUM_G(G_)                                                                                          \
     k_spgemm_numeric<BRA, BCA, BCB, MODE, G_><<<nblk(rows, kWavesPerBlock * (kWave / G_)), 256, 0, s>>>(      \
         sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), Cm.val, invd, omega);
@@ -798,12 +977,14 @@ double lambda_max(const BMat<double>& A, const double* invd, hipStream_t s) {
     dev_dot(x.p, x.p, n, nrm.p, scr, s);
     k_normalize<<<nblk(n, 256), 256, 0, s>>>(n, nrm.p, x.p);
     FR_LAUNCH_CHECK();
-    const int iters = 15;
+    const int iters = 10;
+    const int gd = int(std::min<int64_t>(512, ceil_div(n, 256)));
     for (int it = 0; it < iters; ++it) {
         spmv(A, x.p, y.p, s);
-        k_mul<<<nblk(n, 256), 256, 0, s>>>(n, invd, y.p, t.p);   // t = D^-1 A x
+        k_mul_dot<<<gd, 256, 0, s>>>(n, invd, y.p, t.p, scr.p);   // t = D^-1 A x, partial |t|^2
         FR_LAUNCH_CHECK();
-        dev_dot(t.p, t.p, n, nrm.p, scr, s);
+        k_sum_parts1<<<1, 256, 0, s>>>(scr.p, gd, nrm.p);
+        FR_LAUNCH_CHECK();
         k_normalize_copy<<<nblk(n, 256), 256, 0, s>>>(n, t.p, nrm.p, x.p);
         FR_LAUNCH_CHECK();
     }

@@ -83,7 +83,7 @@ fr_amg_opts default_amg() {
     o.theta = 0.02;
     o.cheb_degree = 2;
     o.cheb_ratio = 20.0;
-    o.coarse_max = 256;
+    o.coarse_max = 96;
     o.max_levels = 10;
     o.reuse_u_block = 1;
     return o;
