@@ -106,9 +106,10 @@ __global__ void k_mis_prop(int64_t n, int C, const int32_t* __restrict__ sp, con
 __global__ void __launch_bounds__(256) k_mis_update(int64_t n, const uint64_t* __restrict__ m2,
                                                     uint8_t* __restrict__ state, uint64_t* __restrict__ key,
                                                     int32_t* __restrict__ undecided) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    __shared__ int sh[4];
     int und = 0;
-    if (i < n && state[i] == 1) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        if (state[i] != 1) continue;
         if (m2[i] == key[i]) {
             state[i] = 2;
             key[i] = mis_key(2, i);
@@ -119,30 +120,17 @@ __global__ void __launch_bounds__(256) k_mis_update(int64_t n, const uint64_t* _
             und = 1;
         }
     }
-    // one atomic per wave with undecided nodes (the count only decides termination)
+    if (!undecided) return;
+    // one atomic per block (the count only decides termination)
     und = wave_sum_int(und);
-    if (threadIdx.x % kWave == 0 && und) atomicAdd(undecided, und);
+    if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = und;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int t = sh[0] + sh[1] + sh[2] + sh[3];
+        if (t) atomicAdd(undecided, t);
+    }
 }
 
-// nnz (sum) and the longest row of a structure, without copying row_len to the host
-__global__ void __launch_bounds__(256) k_len_stats(const int32_t* __restrict__ len, int64_t n,
-                                                   unsigned long long* __restrict__ out) {
-    int64_t s = 0;
-    int mx = 0;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-        s += len[i];
-        mx = max(mx, len[i]);
-    }
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-        s += __shfl_xor(s, o);
-        mx = max(mx, __shfl_xor(mx, o));
-    }
-    if (threadIdx.x % kWave == 0) {
-        atomicAdd(&out[0], (unsigned long long)s);
-        atomicMax(&out[1], (unsigned long long)mx);
-    }
-}
 
 __global__ void k_root_flags(int64_t n, const uint8_t* __restrict__ state, int32_t* __restrict__ flag) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -747,25 +735,10 @@ std::shared_ptr<SellStruct> new_struct(int64_t n_rows, int64_t n_cols, hipStream
     return S;
 }
 
-int64_t block_nnz(const SellStruct& S, hipStream_t s, int* max_len = nullptr) {
-    DBuf<unsigned long long> st;
-    st.alloc(2, s);
-    st.zero(s);
-    if (S.n_rows > 0) {
-        const int g = int(std::min<int64_t>(1024, ceil_div(S.n_rows, 256)));
-        k_len_stats<<<g, 256, 0, s>>>(S.row_len, S.n_rows, st.p);
-        FR_LAUNCH_CHECK();
-    }
-    auto h = download(st.p, 2, s);
-    if (max_len) *max_len = int(h[1]);
-    return int64_t(h[0]);
-}
-
-void finish_struct(SellStruct& S, hipStream_t s) {
-    layout_from_lengths(S, s);
+void finish_struct(SellStruct& S, hipStream_t s, const int* flag = nullptr, int* flag_out = nullptr) {
+    layout_from_lengths(S, s, flag, flag_out);
     S.own_col.alloc(size_t(std::max<int64_t>(1, S.n_slots)), s);
     S.col = S.own_col.p;
-    S.nnz = block_nnz(S, s, &S.max_len);
 }
 
 // Row-merge numeric phase: a group of G lanes owns one output row; the row's sorted columns
@@ -881,18 +854,18 @@ void spgemm_numeric(const BMat<double>& A, const BMat<double>& B, BMat<double>& 
     }
 
 template <int G>
-bool spgemm_symbolic(const BMat<double>& A, const BMat<double>& B, BMat<double>& Cm, DBuf<int>& ovf, hipStream_t s,
+void spgemm_symbolic(const BMat<double>& A, const BMat<double>& B, BMat<double>& Cm, int* ovf, hipStream_t s,
                      bool fill) {
     const int g = nblk(std::max<int64_t>(1, A.rows()), kWavesPerBlock * (kWave / G));
-    ovf.zero(s);
-    if (!fill) k_spgemm_count<G><<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), Cm.S->row_len, ovf.p);
-    else k_spgemm_fill<G><<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), sv(*Cm.S), Cm.S->col, ovf.p);
+    if (!fill) k_spgemm_count<G><<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), Cm.S->row_len, ovf);
+    else k_spgemm_fill<G><<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), sv(*Cm.S), Cm.S->col, ovf);
     FR_LAUNCH_CHECK();
-    return download1(ovf.p, s) == 0;
 }
 
+// `errs` collects overflow flags that are checked once at the end of the setup
 template <int MODE>
-BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* invd, double omega, hipStream_t s) {
+BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* invd, double omega, int* errs,
+                    hipStream_t s) {
     if (A.bc != B.br || A.cols() != B.rows()) fail(FR_EINTERNAL, "spgemm: shape mismatch");
     BMat<double> Cm;
     Cm.br = A.br;
@@ -900,13 +873,22 @@ BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* 
     Cm.S = new_struct(A.rows(), B.cols(), s);
     DBuf<int> ovf;
     ovf.alloc(1, s);
+    ovf.zero(s);
     // small hash sets first (8 rows per wave); a row that does not fit reruns with 64 lanes
-    bool small = spgemm_symbolic<8>(A, B, Cm, ovf, s, false);
-    if (!small && !spgemm_symbolic<64>(A, B, Cm, ovf, s, false))
-        fail(FR_EINTERNAL, "spgemm: row exceeds the LDS hash capacity");
-    finish_struct(*Cm.S, s);
-    const bool ok = small ? spgemm_symbolic<8>(A, B, Cm, ovf, s, true) : spgemm_symbolic<64>(A, B, Cm, ovf, s, true);
-    if (!ok) fail(FR_EINTERNAL, "spgemm: fill overflow");
+    spgemm_symbolic<8>(A, B, Cm, ovf.p, s, false);
+    int over = 0;
+    layout_from_lengths(*Cm.S, s, ovf.p, &over);
+    const bool small = over == 0;
+    if (!small) {
+        ovf.zero(s);
+        spgemm_symbolic<64>(A, B, Cm, ovf.p, s, false);
+        layout_from_lengths(*Cm.S, s, ovf.p, &over);
+        if (over) fail(FR_EINTERNAL, "spgemm: row exceeds the LDS hash capacity");
+    }
+    Cm.S->own_col.alloc(size_t(std::max<int64_t>(1, Cm.S->n_slots)), s);
+    Cm.S->col = Cm.S->own_col.p;
+    if (small) spgemm_symbolic<8>(A, B, Cm, errs, s, true);
+    else spgemm_symbolic<64>(A, B, Cm, errs, s, true);
     Cm.own_val.alloc(size_t(std::max<int64_t>(1, Cm.S->n_slots)) * Cm.br * Cm.bc, s);
     Cm.val = Cm.own_val.p;
     FR_SPGEMM_CASE(1, 1, 1)
@@ -920,7 +902,7 @@ BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* 
 }
 #undef FR_SPGEMM_CASE
 
-BMat<double> transpose(const BMat<double>& P, hipStream_t s) {
+BMat<double> transpose(const BMat<double>& P, int* errs, hipStream_t s) {
     BMat<double> Rm;
     Rm.br = P.bc;
     Rm.bc = P.br;
@@ -934,22 +916,18 @@ BMat<double> transpose(const BMat<double>& P, hipStream_t s) {
     Rm.val = Rm.own_val.p;
     DBuf<int32_t> fillc, tcol;
     DBuf<double> tval;
-    DBuf<int> ovf;
     fillc.alloc(size_t(std::max<int64_t>(1, P.cols())), s);
     fillc.zero(s);
     tcol.alloc(size_t(std::max<int64_t>(1, Rm.S->n_slots)), s);
     tval.alloc(nvals, s);
-    ovf.alloc(1, s);
-    ovf.zero(s);
     const int g = nblk(P.rows(), 256);
     const int gr = nblk(Rm.rows(), kWavesPerBlock);
 #define FR_TR_CASE(BR_, BC_)                                                                                    \
     if (P.br == BR_ && P.bc == BC_) {                                                                           \
         k_transpose_fill<BR_, BC_><<<g, 256, 0, s>>>(sv(*P.S), P.val, sv(*Rm.S), fillc.p, tcol.p, tval.p);      \
         FR_LAUNCH_CHECK();                                                                                      \
-        k_rank_rows<BR_ * BC_><<<gr, 256, 0, s>>>(sv(*Rm.S), tcol.p, tval.p, Rm.S->col, Rm.val, ovf.p);         \
+        k_rank_rows<BR_ * BC_><<<gr, 256, 0, s>>>(sv(*Rm.S), tcol.p, tval.p, Rm.S->col, Rm.val, errs);          \
         FR_LAUNCH_CHECK();                                                                                      \
-        if (download1(ovf.p, s)) fail(FR_EINTERNAL, "transpose: a row is longer than the rank buffer");       \
         return Rm;                                                                                              \
     }
     FR_TR_CASE(1, 1)
@@ -1036,14 +1014,17 @@ static int64_t aggregate(const BMat<double>& A, const double* dnorm, double thet
     FR_LAUNCH_CHECK();
     DBuf<int32_t> und;
     und.alloc(1, s);
-    for (int round = 0; round < 200; ++round) {
+    // rounds once decided are no-ops, so termination is checked every third round only
+    const int gu = int(std::min<int64_t>(1024, ceil_div(n, 256)));
+    for (int round = 0; round < 240; ++round) {
         k_mis_prop<<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.row_len, S.col, strong.p, key.p, m1.p);
         k_mis_prop<<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.row_len, S.col, strong.p, m1.p, m2.p);
-        und.zero(s);
-        k_mis_update<<<g, 256, 0, s>>>(n, m2.p, state.p, key.p, und.p);
+        const bool check = round % 3 == 2;
+        if (check) und.zero(s);
+        k_mis_update<<<gu, 256, 0, s>>>(n, m2.p, state.p, key.p, check ? und.p : nullptr);
         FR_LAUNCH_CHECK();
-        if (download1(und.p, s) == 0) break;
-        if (round == 199) fail(FR_EINTERNAL, "aggregation: MIS(2) did not terminate");
+        if (check && download1(und.p, s) == 0) break;
+        if (round == 239) fail(FR_EINTERNAL, "aggregation: MIS(2) did not terminate");
     }
     DBuf<int32_t> flag, rank, agg1;
     flag.alloc(size_t(n), s);
@@ -1094,7 +1075,7 @@ static BMat<double> tentative(const BMat<double>& A, const DBuf<int32_t>& agg, i
     fillc.zero(s);
     k_agg_count<<<nblk(n, 256), 256, 0, s>>>(n, agg.p, cnt.p);
     FR_LAUNCH_CHECK();
-    scan_exclusive(cnt.p, ptr.p, n_agg, s);
+    scan_exclusive_async(cnt.p, ptr.p, n_agg, s);
     k_agg_fill<<<nblk(n, 256), 256, 0, s>>>(n, agg.p, ptr.p, fillc.p, nodes.p);
     FR_LAUNCH_CHECK();
     k_agg_sort<<<nblk(n_agg, 256), 256, 0, s>>>(n_agg, ptr.p, nodes.p);
@@ -1158,6 +1139,9 @@ static void alloc_vectors(AmgLevel& L, int precision, hipStream_t s) {
 static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double* coords, int dim,
                             const fr_amg_opts& o, hipStream_t s) {
     H.lv.clear();
+    DBuf<int> errs;    // capacity overflows of the SpGEMM fills and transposes, read once at the end
+    errs.alloc(1, s);
+    errs.zero(s);
     DBuf<double> Bf;   // near-null space of the current level (levels >= 1)
     BMat<double> A = std::move(A0);
     int ns = ns0;
@@ -1183,10 +1167,10 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
             DBuf<double> Bc;
             BMat<double> Pt = tentative(L->A, agg, n_agg, ns, l == 0, coords, dim, Bf.p, Bc, s);
             const double omega = 4.0 / (3.0 * L->lmax);
-            L->P = spgemm<1>(L->A, Pt, L->invd.p, omega, s);
-            L->R = transpose(L->P, s);
-            BMat<double> AP = spgemm<0>(L->A, L->P, nullptr, 0.0, s);
-            BMat<double> Ac = spgemm<0>(L->R, AP, nullptr, 0.0, s);
+            L->P = spgemm<1>(L->A, Pt, L->invd.p, omega, errs.p, s);
+            L->R = transpose(L->P, errs.p, s);
+            BMat<double> AP = spgemm<0>(L->A, L->P, nullptr, 0.0, errs.p, s);
+            BMat<double> Ac = spgemm<0>(L->R, AP, nullptr, 0.0, errs.p, s);
             L->ns = ns;
             Bf = std::move(Bc);
             A = std::move(Ac);
@@ -1223,7 +1207,7 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
         if (o.precision == 32) make_f32(*H.lv[l], l + 1 == H.lv.size(), s);
         alloc_vectors(*H.lv[l], o.precision, s);
     }
-    FR_HIP(hipStreamSynchronize(s));
+    if (download1(errs.p, s)) fail(FR_EINTERNAL, "amg setup: a row exceeded the SpGEMM / transpose LDS capacity");
 }
 
 void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s) {
@@ -1340,14 +1324,38 @@ static T* vcycle(Hierarchy& H, size_t l, const T* b, const fr_amg_opts& o, hipSt
     return x;
 }
 
+static void precondition_block(DevAmg& amg, Hierarchy& H, const double* r, double* z, int64_t n, int blk,
+                               hipStream_t s);
+
 void amg_precondition(DevAmg& amg, const double* r, double* z, hipStream_t s) {
     DevSystem& sys = *amg.sys;
     const int64_t nu = sys.n_u;
     const int64_t np = sys.n_solve - nu;
     const int64_t nb[2] = {nu, np};
     const int64_t off[2] = {0, nu};
-    for (int blk = 0; blk < 2; ++blk) {
+    if (!amg.side) {
+        FR_HIP(hipStreamCreateWithFlags(&amg.side, hipStreamNonBlocking));
+        FR_HIP(hipEventCreateWithFlags(&amg.ev_fork, hipEventDisableTiming));
+        FR_HIP(hipEventCreateWithFlags(&amg.ev_join, hipEventDisableTiming));
+    }
+    // fork: the phi block's V-cycle on the side stream, the u block's on the caller's
+    FR_HIP(hipEventRecord(amg.ev_fork, s));
+    FR_HIP(hipStreamWaitEvent(amg.side, amg.ev_fork, 0));
+    for (int blk = 1; blk >= 0; --blk) {
         Hierarchy& H = amg.h[blk];
+        const hipStream_t st = blk == 1 ? amg.side : s;
+        precondition_block(amg, H, r + off[blk], z + off[blk], nb[blk], blk, st);
+    }
+    // join
+    FR_HIP(hipEventRecord(amg.ev_join, amg.side));
+    FR_HIP(hipStreamWaitEvent(s, amg.ev_join, 0));
+}
+
+static void precondition_block(DevAmg& amg, Hierarchy& H, const double* r, double* z, int64_t n, int blk,
+                               hipStream_t s) {
+    const int64_t nb[2] = {n, n};
+    const int64_t off[2] = {0, 0};
+    {
         ProfScope ps(blk == 0 ? "vcycle_u" : "vcycle_phi", s, 0.0);
         if (amg.opts.precision == 32) {
             AmgLevel& L0 = *H.lv[0];
@@ -1401,7 +1409,8 @@ void amg_info(DevAmg& amg, int blk, int level, int& n_levels, int64_t& rows, int
     AmgLevel& L = *H.lv[size_t(level)];
     rows = L.A.rows();
     bsize = L.A.br;
-    nnzb = block_nnz(*L.A.S, s);
+    (void)s;
+    nnzb = L.A.S->nnz;
     lmax = L.lmax;
 }
 

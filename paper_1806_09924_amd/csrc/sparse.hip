@@ -251,7 +251,7 @@ inline int nblk(int64_t n, int t) { return int(ceil_div(n, t)); }
 
 }  // namespace
 
-int64_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
+void scan_exclusive_async(const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
     const int64_t nb = std::max<int64_t>(1, ceil_div(n, kScanTile));
     DBuf<int32_t> sums;
     sums.alloc(size_t(nb) + 1, s);
@@ -261,6 +261,10 @@ int64_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_t s
     FR_LAUNCH_CHECK();
     k_tile_scan<<<int(nb), kScanT, 0, s>>>(in, n, sums.p, out);
     FR_LAUNCH_CHECK();
+}
+
+int64_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
+    scan_exclusive_async(in, out, n, s);
     return int64_t(download1(out + n, s));
 }
 
@@ -300,7 +304,42 @@ void vec_fill(double* y, double v, int64_t n, hipStream_t s) {
     FR_LAUNCH_CHECK();
 }
 
-void layout_from_lengths(SellStruct& S, hipStream_t s) {
+// total slots, nnz and longest row of a structure (and an optional flag word) in one
+// device record, so that building a structure costs a single host round trip
+__global__ void __launch_bounds__(256) k_struct_stats(const int32_t* __restrict__ len, int64_t n,
+                                                      const int32_t* __restrict__ slots_total,
+                                                      const int* __restrict__ flag,
+                                                      unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long sh_s[16];
+    __shared__ int sh_m[16];
+    unsigned long long sum = 0;
+    int mx = 0;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        sum += (unsigned long long)len[i];
+        mx = max(mx, len[i]);
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        sum += __shfl_xor(sum, o);
+        mx = max(mx, __shfl_xor(mx, o));
+    }
+    const int w = threadIdx.x / kWave;
+    if (threadIdx.x % kWave == 0) { sh_s[w] = sum; sh_m[w] = mx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        int m = 0;
+        for (int i = 0; i < int(blockDim.x / kWave); ++i) { t += sh_s[i]; m = max(m, sh_m[i]); }
+        atomicAdd(&out[1], t);
+        atomicMax(&out[2], (unsigned long long)m);
+        if (blockIdx.x == 0) {
+            out[0] = (unsigned long long)(*slots_total);
+            out[3] = flag ? (unsigned long long)(*flag) : 0ull;
+        }
+    }
+}
+
+void layout_from_lengths(SellStruct& S, hipStream_t s, const int* flag, int* flag_out) {
     S.n_slices = ceil_div(S.n_rows, S.C);
     DBuf<int32_t> wc;
     wc.alloc(size_t(S.n_slices) + 1, s);
@@ -308,7 +347,18 @@ void layout_from_lengths(SellStruct& S, hipStream_t s) {
     FR_LAUNCH_CHECK();
     S.own_slice.alloc(size_t(S.n_slices) + 1, s);
     S.slice_ptr = S.own_slice.p;
-    S.n_slots = scan_exclusive(wc.p, S.slice_ptr, S.n_slices, s);
+    scan_exclusive_async(wc.p, S.slice_ptr, S.n_slices, s);
+    DBuf<unsigned long long> st;
+    st.alloc(4, s);
+    st.zero(s);
+    const int g = int(std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(S.n_rows, 256))));
+    k_struct_stats<<<g, 256, 0, s>>>(S.row_len, S.n_rows, S.slice_ptr + S.n_slices, flag, st.p);
+    FR_LAUNCH_CHECK();
+    auto h = download(st.p, 4, s);
+    S.n_slots = int64_t(h[0]);
+    S.nnz = int64_t(h[1]);
+    S.max_len = int(h[2]);
+    if (flag_out) *flag_out = int(h[3]);
     if (S.n_slots >= (int64_t(1) << 31)) fail(FR_EINTERNAL, "sell: more than 2^31 slots");
 }
 

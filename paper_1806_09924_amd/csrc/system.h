@@ -106,7 +106,10 @@ void cast_f64_f32(const double* x, float* y, int64_t n, hipStream_t s);
 void cast_f32_f64(const float* x, double* y, int64_t n, hipStream_t s);
 void vec_copy(const double* x, double* y, int64_t n, hipStream_t s);
 void vec_fill(double* y, double v, int64_t n, hipStream_t s);
-void layout_from_lengths(SellStruct& S, hipStream_t s);   // row_len set -> slice_ptr, n_slots
+// row_len set -> slice_ptr, n_slots, nnz, max_len (one host round trip; flag, when given,
+// is read in the same trip into *flag_out)
+void layout_from_lengths(SellStruct& S, hipStream_t s, const int* flag = nullptr, int* flag_out = nullptr);
+void scan_exclusive_async(const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
 
 template <typename T>
 void spmv(const BMat<T>& A, const T* x, T* y, hipStream_t s);                 // y = A x
@@ -147,6 +150,15 @@ struct DevAmg {
     hipStream_t stream = nullptr;
     Hierarchy h[2];                              // 0: u block, 1: phi block
     uint64_t sys_version = 0;
+    // the phi V-cycle runs on a second stream (default priority) beside the u V-cycle
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    ~DevAmg() {
+        if (side) (void)hipStreamSynchronize(side);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (side) (void)hipStreamDestroy(side);
+    }
 };
 
 void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s);
