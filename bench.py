@@ -59,14 +59,19 @@ def counted_traffic(kernel):
         return None
     txt = open(path).read()
     t = re.search(r"^traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt, re.M)
-    h = re.search(r"^source: (\S+) sha256 prefix ([0-9a-f]+)", txt, re.M)
+    h = re.search(r"^source: (\S+) kernel (\w+) sha256 prefix ([0-9a-f]+)", txt, re.M)
     if not t or not h:
         return None
     src = os.path.join(ROOT, h.group(1))
     if not os.path.exists(src):
         return None
-    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    return float(t.group(1)) if cur.startswith(h.group(2)) else None
+    # the kernel's own template definition, up to its closing brace at column 0
+    m = re.search(r"(template <[^\n]*>\n__global__ void __launch_bounds__\(\d+\) " + h.group(2) + r"\(.*?\n\}\n)",
+                  open(src).read(), re.S)
+    if not m:
+        return None
+    cur = hashlib.sha256(m.group(1).encode()).hexdigest()
+    return float(t.group(1)) if cur.startswith(h.group(3)) else None
 
 
 def cpu_baseline(n_cpu, L_full, n_full, iters_per_newton):
