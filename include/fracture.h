@@ -88,6 +88,10 @@ typedef struct {
                             M_uu depends only on phi_tilde and the Dirichlet set, so within one
                             loading step it does not change between Newton iterations;
                             fracture_newton rebuilds it once per call when this is set. */
+    int refresh_phi;     /* nonzero: amg_setup on a system whose phase-field hierarchy exists keeps
+                            that hierarchy's aggregates and sparsity and recomputes its values
+                            (the Jacobian pattern never changes; masked entries stay as zeros);
+                            fracture_newton does this from the second Newton iteration on. */
 } fr_amg_opts;
 
 /* FGMRES options (right preconditioned, x0 = 0). */
@@ -255,7 +259,11 @@ fr_status fracture_update(fr_mesh mesh, const double* du, double omega, double* 
 /* The Newton / active-set loop of one loading step (Section 3 algorithm): assemble,
  * active set, masked Jacobian, AMG setup, FGMRES, line search, stop test, with the cycle
  * freeze of alternating active-set entries. u and phi are updated in place (device).
- * amg_opts / solve_opts / newton_opts / stats: host. */
+ * amg_opts / solve_opts / newton_opts / stats: host.
+ * The working storage (system, preconditioner, Krylov bases) stays with the mesh for the
+ * next call, which recomputes all of it; calls on one mesh run one at a time. It is freed
+ * by fracture_mesh_destroy, or by a call on another stream (the first stream must stay
+ * valid until then). Synchronises `stream`. */
 fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double* phi,
                           const double* phi_old, const double* phi_tilde,
                           const fr_amg_opts* amg_opts, const fr_solve_opts* solve_opts,
@@ -276,8 +284,9 @@ fr_status fracture_functionals(fr_mesh mesh, const double* u, const double* phi,
 
 /* enable != 0 starts recording a HIP event pair on the launch stream around every launch
  * of the sparse, smoother, coupled-Jacobian and Gram-Schmidt kernels (and one pair around
- * each block's V-cycle), together with the algorithmic bytes each launch must move;
- * 0 stops. Either call discards what was recorded. */
+ * each block's V-cycle and each AMG setup phase, names "setup_*", which include any host
+ * round trips), together with the algorithmic bytes each launch must move; 0 stops.
+ * Either call discards what was recorded. */
 fr_status fracture_profile(int enable);
 
 /* Entry i of the recording (host outputs): kernel name (valid until the next
@@ -286,6 +295,12 @@ fr_status fracture_profile(int enable);
 fr_status fracture_profile_read(int i, const char** name, int64_t* launches, double* ms, double* bytes);
 
 /* ---- misc ------------------------------------------------------------------------- */
+
+/* Device memory of every object comes from one stream-ordered pool per device that keeps
+ * freed memory mapped for reuse (allocation then costs no driver call). This returns the
+ * current device's unused pool memory to the driver; it synchronises the device. Objects
+ * that are alive keep their memory. */
+fr_status fracture_trim_pool(void);
 
 const char* fracture_last_error(void);
 /* Checks that a gfx950 device is current; FR_EDEVICE otherwise. */

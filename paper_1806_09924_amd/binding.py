@@ -36,7 +36,7 @@ class Params(ctypes.Structure):
 class AmgOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("theta", ctypes.c_double), ("cheb_degree", ctypes.c_int),
                 ("cheb_ratio", ctypes.c_double), ("coarse_max", ctypes.c_int), ("max_levels", ctypes.c_int),
-                ("reuse_u_block", ctypes.c_int)]
+                ("reuse_u_block", ctypes.c_int), ("refresh_phi", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -100,6 +100,7 @@ _SIGNATURES = {
     "fracture_profile_read": [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), _I64P, _DP, _DP],
     "fracture_last_error": [],
     "fracture_device_check": [],
+    "fracture_trim_pool": [],
     "fracture_version": [],
 }
 _VOID = {"fracture_mesh_destroy", "fracture_system_destroy", "amg_destroy"}
@@ -153,8 +154,8 @@ def params(E=1.0, nu=0.2, Gc=1.0, kappa=1e-10, eps=1.0 / 16, p=1e-3, c_pdas=1.0,
 
 
 def amg_opts(precision=64, theta=0.02, cheb_degree=2, cheb_ratio=20.0, coarse_max=96, max_levels=12,
-             reuse_u_block=1):
-    return AmgOpts(precision, theta, cheb_degree, cheb_ratio, coarse_max, max_levels, reuse_u_block)
+             reuse_u_block=1, refresh_phi=1):
+    return AmgOpts(precision, theta, cheb_degree, cheb_ratio, coarse_max, max_levels, reuse_u_block, refresh_phi)
 
 
 def solve_opts(rtol=1e-8, restart=100, maxit=500):
@@ -393,6 +394,10 @@ def functionals(mesh, u, phi, cod_x=()):
     if ni == 1:
         return cod[:n], float(tcv[0])
     return cod[:ni * n].reshape(ni, n), tcv
+
+
+def trim_pool():
+    _check(load().fracture_trim_pool())
 
 
 def device_check():

@@ -347,10 +347,10 @@ __global__ void k_tentative(int64_t na, const int32_t* __restrict__ aptr, const 
     double T[NS][NS];
     for (int i = 0; i < NS; ++i)
         for (int j = 0; j < NS; ++j) T[i][j] = i == j ? 1.0 : 0.0;
-    if (LEVEL0 && NS == 3) {
+    if constexpr (LEVEL0 && NS == 3) {
         T[0][2] = -xc[1];
         T[1][2] = xc[0];
-    } else if (LEVEL0 && NS == 6) {
+    } else if constexpr (LEVEL0 && NS == 6) {
         T[0][3] = -xc[1]; T[1][3] = xc[0];
         T[1][4] = -xc[2]; T[2][4] = xc[1];
         T[0][5] = xc[2];  T[2][5] = -xc[0];
@@ -619,6 +619,24 @@ __global__ void __launch_bounds__(256) k_rank_rows(SellV Rm, const int32_t* __re
     }
 }
 
+// Values of R = P^T into an existing structure (one thread per row of R): entry (r, c) of R
+// is entry (c, r) of P, found by binary search in P's sorted row c.
+template <int BR, int BC>
+__global__ void k_transpose_values(SellV P, const double* __restrict__ pv, SellV Rm, double* __restrict__ rv) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= Rm.n_rows) return;
+    const int n = Rm.len[r];
+    const int64_t s0 = r / Rm.C;
+    const int width = (Rm.sp[s0 + 1] - Rm.sp[s0]) / Rm.C;
+    for (int k = 0; k < width; ++k) {
+        const int64_t rs = sslot(Rm.sp, Rm.C, r, k);
+        const int kp = k < n ? find_sorted(P, Rm.col[rs], int32_t(r)) : -1;
+        const double* pb = kp >= 0 ? pv + sslot(P.sp, P.C, Rm.col[rs], kp) * (BR * BC) : nullptr;
+        for (int i = 0; i < BR; ++i)
+            for (int j = 0; j < BC; ++j) rv[rs * (BR * BC) + j * BR + i] = pb ? pb[i * BC + j] : 0.0;
+    }
+}
+
 // ---- power iteration for lambda_max(D^-1 A) ------------------------------------------------
 __global__ void k_power_init(int64_t n, double* __restrict__ x) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -850,8 +868,25 @@ void spgemm_numeric(const BMat<double>& A, const BMat<double>& B, BMat<double>& 
 #define FR_SPGEMM_CASE(BRA_, BCA_, BCB_)                                        \
     if (A.br == BRA_ && A.bc == BCA_ && B.bc == BCB_) {                         \
         spgemm_numeric<BRA_, BCA_, BCB_, MODE>(A, B, Cm, invd, omega, s);       \
-        return Cm;                                                              \
+        return;                                                                 \
     }
+
+// Values of C = A B (MODE 0) or C = B - omega D^-1 A B (MODE 1) into C's existing structure.
+template <int MODE>
+void spgemm_values(const BMat<double>& A, const BMat<double>& B, BMat<double>& Cm, const double* invd, double omega,
+                   hipStream_t s) {
+    if (A.bc != B.br || A.cols() != B.rows() || Cm.rows() != A.rows() || Cm.br != A.br || Cm.bc != B.bc)
+        fail(FR_EINTERNAL, "spgemm: shape mismatch");
+    FR_SPGEMM_CASE(1, 1, 1)
+    FR_SPGEMM_CASE(2, 2, 3)
+    FR_SPGEMM_CASE(3, 2, 3)
+    FR_SPGEMM_CASE(3, 3, 3)
+    FR_SPGEMM_CASE(3, 3, 6)
+    FR_SPGEMM_CASE(6, 3, 6)
+    FR_SPGEMM_CASE(6, 6, 6)
+    fail(FR_EINTERNAL, "spgemm: unsupported block shapes");
+}
+#undef FR_SPGEMM_CASE
 
 template <int G>
 void spgemm_symbolic(const BMat<double>& A, const BMat<double>& B, BMat<double>& Cm, int* ovf, hipStream_t s,
@@ -891,16 +926,28 @@ BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* 
     else spgemm_symbolic<64>(A, B, Cm, errs, s, true);
     Cm.own_val.alloc(size_t(std::max<int64_t>(1, Cm.S->n_slots)) * Cm.br * Cm.bc, s);
     Cm.val = Cm.own_val.p;
-    FR_SPGEMM_CASE(1, 1, 1)
-    FR_SPGEMM_CASE(2, 2, 3)
-    FR_SPGEMM_CASE(3, 2, 3)
-    FR_SPGEMM_CASE(3, 3, 3)
-    FR_SPGEMM_CASE(3, 3, 6)
-    FR_SPGEMM_CASE(6, 3, 6)
-    FR_SPGEMM_CASE(6, 6, 6)
-    fail(FR_EINTERNAL, "spgemm: unsupported block shapes");
+    spgemm_values<MODE>(A, B, Cm, invd, omega, s);
+    return Cm;
 }
-#undef FR_SPGEMM_CASE
+
+void transpose_values(const BMat<double>& P, BMat<double>& Rm, hipStream_t s) {
+    if (Rm.rows() != P.cols() || Rm.cols() != P.rows() || Rm.br != P.bc || Rm.bc != P.br)
+        fail(FR_EINTERNAL, "transpose: shape mismatch");
+    const int g = nblk(std::max<int64_t>(1, Rm.rows()), 256);
+#define FR_TV_CASE(BR_, BC_)                                                                  \
+    if (P.br == BR_ && P.bc == BC_) {                                                         \
+        k_transpose_values<BR_, BC_><<<g, 256, 0, s>>>(sv(*P.S), P.val, sv(*Rm.S), Rm.val);   \
+        FR_LAUNCH_CHECK();                                                                    \
+        return;                                                                               \
+    }
+    FR_TV_CASE(1, 1)
+    FR_TV_CASE(2, 3)
+    FR_TV_CASE(3, 3)
+    FR_TV_CASE(3, 6)
+    FR_TV_CASE(6, 6)
+#undef FR_TV_CASE
+    fail(FR_EINTERNAL, "transpose: unsupported block shape");
+}
 
 BMat<double> transpose(const BMat<double>& P, int* errs, hipStream_t s) {
     BMat<double> Rm;
@@ -1136,56 +1183,13 @@ static void alloc_vectors(AmgLevel& L, int precision, hipStream_t s) {
     }
 }
 
-static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double* coords, int dim,
-                            const fr_amg_opts& o, hipStream_t s) {
-    H.lv.clear();
-    DBuf<int> errs;    // capacity overflows of the SpGEMM fills and transposes, read once at the end
-    errs.alloc(1, s);
-    errs.zero(s);
-    DBuf<double> Bf;   // near-null space of the current level (levels >= 1)
-    BMat<double> A = std::move(A0);
-    int ns = ns0;
-    for (int l = 0;; ++l) {
-        auto L = std::make_unique<AmgLevel>();
-        L->A.br = A.br;
-        L->A.bc = A.bc;
-        L->A.S = A.S;
-        L->A.val = A.val;
-        L->A.own_val = std::move(A.own_val);
-        DBuf<double> dnorm;
-        diag_info(L->A, L->invd, dnorm, s);
-        L->lmax = lambda_max(L->A, L->invd.p, s);
-        const int64_t nrows = L->A.rows() * L->A.br;
-        const bool last = nrows <= o.coarse_max || l + 1 >= o.max_levels;
-        if (!last) {
-            DBuf<int32_t> agg;
-            const int64_t n_agg = aggregate(L->A, dnorm.p, o.theta, agg, s);
-            if (n_agg == 0 || n_agg * ns >= nrows) {
-                H.lv.push_back(std::move(L));
-                break;   // coarsening stalled: this level is the coarsest
-            }
-            DBuf<double> Bc;
-            BMat<double> Pt = tentative(L->A, agg, n_agg, ns, l == 0, coords, dim, Bf.p, Bc, s);
-            const double omega = 4.0 / (3.0 * L->lmax);
-            L->P = spgemm<1>(L->A, Pt, L->invd.p, omega, errs.p, s);
-            L->R = transpose(L->P, errs.p, s);
-            BMat<double> AP = spgemm<0>(L->A, L->P, nullptr, 0.0, errs.p, s);
-            BMat<double> Ac = spgemm<0>(L->R, AP, nullptr, 0.0, errs.p, s);
-            L->ns = ns;
-            Bf = std::move(Bc);
-            A = std::move(Ac);
-            H.lv.push_back(std::move(L));
-            continue;
-        }
-        H.lv.push_back(std::move(L));
-        break;
-    }
-    // coarsest level: dense inverse when small enough
+// Coarsest level: dense inverse when small enough.
+static void coarse_inverse(Hierarchy& H, hipStream_t s) {
     AmgLevel& Lc = *H.lv.back();
     const int64_t nc = Lc.A.rows() * Lc.A.br;
     H.n_coarse = nc;
     if (nc <= kDenseMax) {
-        H.dense_inv.alloc(size_t(std::max<int64_t>(1, nc * nc)), s);
+        H.dense_inv.reserve(size_t(std::max<int64_t>(1, nc * nc)), s);
         H.dense_inv.zero(s);
         const int g = nblk(Lc.A.rows(), 256);
         switch (Lc.A.br) {
@@ -1203,6 +1207,80 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
     } else {
         H.dense_inv.release();
     }
+}
+
+// `keep` stores the tentative prolongators and the products A P so that the values can later
+// be recomputed for a new matrix with the same sparsity (refresh_hierarchy).
+static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double* coords, int dim,
+                            const fr_amg_opts& o, bool keep, hipStream_t s) {
+    H.lv.clear();
+    H.refreshable = keep;
+    DBuf<int> errs;    // capacity overflows of the SpGEMM fills and transposes, read once at the end
+    errs.alloc(1, s);
+    errs.zero(s);
+    DBuf<double> Bf;   // near-null space of the current level (levels >= 1)
+    BMat<double> A = std::move(A0);
+    int ns = ns0;
+    for (int l = 0;; ++l) {
+        auto L = std::make_unique<AmgLevel>();
+        L->A.br = A.br;
+        L->A.bc = A.bc;
+        L->A.S = A.S;
+        L->A.val = A.val;
+        L->A.own_val = std::move(A.own_val);
+        DBuf<double> dnorm;
+        {
+            ProfScope ps("setup_lambda", s, 0.0);
+            diag_info(L->A, L->invd, dnorm, s);
+            L->lmax = lambda_max(L->A, L->invd.p, s);
+        }
+        const int64_t nrows = L->A.rows() * L->A.br;
+        const bool last = nrows <= o.coarse_max || l + 1 >= o.max_levels;
+        if (!last) {
+            DBuf<int32_t> agg;
+            int64_t n_agg = 0;
+            {
+                ProfScope ps("setup_aggregate", s, 0.0);
+                n_agg = aggregate(L->A, dnorm.p, o.theta, agg, s);
+            }
+            if (n_agg == 0 || n_agg * ns >= nrows) {
+                H.lv.push_back(std::move(L));
+                break;   // coarsening stalled: this level is the coarsest
+            }
+            DBuf<double> Bc;
+            BMat<double> Pt, AP, Ac;
+            {
+                ProfScope ps("setup_tentative", s, 0.0);
+                Pt = tentative(L->A, agg, n_agg, ns, l == 0, coords, dim, Bf.p, Bc, s);
+            }
+            {
+                ProfScope ps("setup_smooth_p", s, 0.0);
+                const double omega = 4.0 / (3.0 * L->lmax);
+                L->P = spgemm<1>(L->A, Pt, L->invd.p, omega, errs.p, s);
+                L->R = transpose(L->P, errs.p, s);
+            }
+            {
+                ProfScope ps("setup_rap", s, 0.0);
+                AP = spgemm<0>(L->A, L->P, nullptr, 0.0, errs.p, s);
+                Ac = spgemm<0>(L->R, AP, nullptr, 0.0, errs.p, s);
+            }
+            L->ns = ns;
+            if (keep) {
+                L->Pt = std::move(Pt);
+                L->AP = std::move(AP);
+            }
+            Bf = std::move(Bc);
+            A = std::move(Ac);
+            H.lv.push_back(std::move(L));
+            continue;
+        }
+        H.lv.push_back(std::move(L));
+        break;
+    }
+    {
+        ProfScope ps("setup_coarse", s, 0.0);
+        coarse_inverse(H, s);
+    }
     for (size_t l = 0; l < H.lv.size(); ++l) {
         if (o.precision == 32) make_f32(*H.lv[l], l + 1 == H.lv.size(), s);
         alloc_vectors(*H.lv[l], o.precision, s);
@@ -1210,9 +1288,35 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
     if (download1(errs.p, s)) fail(FR_EINTERNAL, "amg setup: a row exceeded the SpGEMM / transpose LDS capacity");
 }
 
+// Same aggregates, tentative prolongators and sparsity; new values from the level-0 matrix
+// at a0 (whose structure is the one the hierarchy was built on).
+static void refresh_hierarchy(Hierarchy& H, double* a0, const fr_amg_opts& o, hipStream_t s) {
+    const size_t nl = H.lv.size();
+    H.lv[0]->A.val = a0;
+    for (size_t l = 0; l < nl; ++l) {
+        AmgLevel& L = *H.lv[l];
+        DBuf<double> dnorm;
+        diag_info(L.A, L.invd, dnorm, s);
+        L.lmax = lambda_max(L.A, L.invd.p, s);
+        if (l + 1 == nl) break;
+        const double omega = 4.0 / (3.0 * L.lmax);
+        spgemm_values<1>(L.A, L.Pt, L.P, L.invd.p, omega, s);
+        transpose_values(L.P, L.R, s);
+        spgemm_values<0>(L.A, L.P, L.AP, nullptr, 0.0, s);
+        spgemm_values<0>(L.R, L.AP, H.lv[l + 1]->A, nullptr, 0.0, s);
+    }
+    coarse_inverse(H, s);
+    if (o.precision == 32)
+        for (size_t l = 0; l < nl; ++l) make_f32(*H.lv[l], l + 1 == nl, s);
+}
+
 void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s) {
     const bool keep_u = o.reuse_u_block && amg.sys == &sys && !amg.h[0].lv.empty() &&
                         amg.opts.precision == o.precision && amg.h[0].lv[0]->A.val == sys.Juu.val;
+    const bool same_shape = amg.opts.precision == o.precision && amg.opts.theta == o.theta &&
+                            amg.opts.coarse_max == o.coarse_max && amg.opts.max_levels == o.max_levels;
+    const bool refresh_phi = o.refresh_phi && amg.sys == &sys && !amg.h[1].lv.empty() && amg.h[1].refreshable &&
+                             same_shape && amg.h[1].lv[0]->A.S == sys.Jpp.S;
     amg.sys = &sys;
     amg.opts = o;
     amg.stream = s;
@@ -1222,13 +1326,18 @@ void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s)
         Au.br = Au.bc = m.dim;
         Au.S = sys.Juu.S;
         Au.val = sys.Juu.val;
-        build_hierarchy(amg.h[0], std::move(Au), m.dim == 2 ? 3 : 6, m.coords_free.p, m.dim, o, s);
+        build_hierarchy(amg.h[0], std::move(Au), m.dim == 2 ? 3 : 6, m.coords_free.p, m.dim, o, false, s);
     }
-    BMat<double> Ap;
-    Ap.br = Ap.bc = 1;
-    Ap.S = sys.Jpp.S;
-    Ap.val = sys.Jpp.val;
-    build_hierarchy(amg.h[1], std::move(Ap), 1, m.coords_free.p, m.dim, o, s);
+    if (refresh_phi) {
+        ProfScope ps("setup_refresh_phi", s, 0.0);
+        refresh_hierarchy(amg.h[1], sys.Jpp.val, o, s);
+    } else {
+        BMat<double> Ap;
+        Ap.br = Ap.bc = 1;
+        Ap.S = sys.Jpp.S;
+        Ap.val = sys.Jpp.val;
+        build_hierarchy(amg.h[1], std::move(Ap), 1, m.coords_free.p, m.dim, o, o.refresh_phi != 0, s);
+    }
     amg.sys_version = sys.version;
 }
 

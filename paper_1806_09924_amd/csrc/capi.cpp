@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 
 #include "profile.h"
@@ -13,10 +14,6 @@ namespace fr {
 void assemble_active_freeze(DevSystem& sys, const double* phi, const double* phi_old);
 }
 
-struct fr_mesh_s {
-    std::unique_ptr<fr::DevMesh> m;
-};
-
 struct fr_system_s {
     fr::DevSystem sys;
     fr::DevKrylov kry;
@@ -24,6 +21,22 @@ struct fr_system_s {
 
 struct fr_amg_s {
     fr::DevAmg amg;
+};
+
+// Working storage of fracture_newton, kept with the mesh between calls: the assembled
+// system, the preconditioner, the Krylov bases and the line-search copies.  Everything in
+// it is recomputed by every call; only the allocations are reused.
+struct NewtonWork {
+    hipStream_t stream = nullptr;
+    fr_system_s S;
+    fr_amg_s A;
+    fr::DBuf<double> du, u_save, p_save;
+};
+
+struct fr_mesh_s {
+    std::unique_ptr<fr::DevMesh> m;
+    std::mutex newton_mu;                        // fracture_newton calls on one mesh run one at a time
+    std::unique_ptr<NewtonWork> nw;              // released before the mesh
 };
 
 namespace {
@@ -86,6 +99,7 @@ fr_amg_opts default_amg() {
     o.coarse_max = 96;
     o.max_levels = 10;
     o.reuse_u_block = 1;
+    o.refresh_phi = 1;
     return o;
 }
 
@@ -106,30 +120,38 @@ fr_status check_solve(const fr_solve_opts& o) {
     return FR_OK;
 }
 
+// Allocates the system's arrays (kept when the system already belongs to this mesh) and
+// resets its state as for a new system.
 void system_init(fr_system_s& S, fr::DevMesh& m, hipStream_t s) {
     fr::DevSystem& sys = S.sys;
+    const bool fresh = sys.mesh != &m || sys.R.p == nullptr;
     sys.mesh = &m;
     sys.stream = s;
     sys.n_u = m.n_free * m.dim;
     sys.n_solve = m.n_free * (m.dim + 1);
+    sys.have_residual = sys.have_active = sys.have_jacobian = false;
+    sys.last_changes = 0;
+    sys.last_min_margin = 0.0;
     const int64_t slots = m.graph->n_slots;
     auto mk = [&](fr::BMat<double>& b, int br, int bc) {
         b.br = br;
         b.bc = bc;
         b.S = m.graph;
-        b.own_val.alloc(size_t(std::max<int64_t>(1, slots)) * br * bc, s);
+        if (fresh) b.own_val.alloc(size_t(std::max<int64_t>(1, slots)) * br * bc, s);
         b.val = b.own_val.p;
         b.own_val.zero(s);
     };
     mk(sys.Juu, m.dim, m.dim);
     mk(sys.Jpu, 1, m.dim);
     mk(sys.Jpp, 1, 1);
-    sys.R.alloc(size_t(sys.n_solve), s);
-    sys.F.alloc(size_t(sys.n_solve), s);
-    sys.B.alloc(size_t(m.n_free), s);
-    sys.active.alloc(size_t(m.n_free), s);
-    sys.active_prev.alloc(size_t(m.n_free), s);
-    sys.frozen.alloc(size_t(m.n_free), s);
+    if (fresh) {
+        sys.R.alloc(size_t(sys.n_solve), s);
+        sys.F.alloc(size_t(sys.n_solve), s);
+        sys.B.alloc(size_t(m.n_free), s);
+        sys.active.alloc(size_t(m.n_free), s);
+        sys.active_prev.alloc(size_t(m.n_free), s);
+        sys.frozen.alloc(size_t(m.n_free), s);
+    }
     sys.active.zero(s);
     sys.active_prev.zero(s);
     sys.frozen.zero(s);
@@ -179,6 +201,13 @@ fr_status fracture_profile_read(int i, const char** name, int64_t* launches, dou
 }
 
 const char* fracture_version(void) { return "fracture-gfx950 0.1"; }
+
+fr_status fracture_trim_pool(void) {
+    return guard([&]() {
+        fr::trim_pool();
+        return FR_OK;
+    });
+}
 
 fr_status fracture_device_check(void) {
     return guard([&]() { return check_device(); });
@@ -300,6 +329,7 @@ fr_status fracture_mesh_nodes(fr_mesh mesh, double* xyz, int64_t* lattice, uint8
 
 void fracture_mesh_destroy(fr_mesh mesh) {
     if (!mesh) return;
+    if (mesh->nw) (void)hipStreamSynchronize(mesh->nw->stream);
     if (mesh->m) (void)hipStreamSynchronize(mesh->m->stream);
     delete mesh;
 }
@@ -580,18 +610,32 @@ fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double*
     return guard([&]() {
         hipStream_t s = fr::as_stream(stream);
         fr::DevMesh& m = *mesh->m;
+        std::lock_guard<std::mutex> lk(mesh->newton_mu);
+        if (mesh->nw && mesh->nw->stream != s) {
+            // storage is freed on the stream it was allocated on
+            FR_HIP(hipStreamSynchronize(mesh->nw->stream));
+            mesh->nw.reset();
+        }
+        const bool fresh = !mesh->nw;
+        if (fresh) {
+            mesh->nw = std::make_unique<NewtonWork>();
+            mesh->nw->stream = s;
+        }
+        NewtonWork& W = *mesh->nw;
         fr_newton_stats ns{};
-        auto S = std::make_unique<fr_system_s>();
+        fr_system_s* S = &W.S;
         system_init(*S, m, s);
         fr::DevSystem& sys = S->sys;
         sys.prm = fr::make_params(*prm);
         sys.prm_h = {sys.prm};
-        auto A = std::make_unique<fr_amg_s>();
+        fr_amg_s* A = &W.A;
         const int64_t nn = m.n_nodes;
-        fr::DBuf<double> du, u_save, p_save;
-        du.alloc(size_t(sys.n_solve), s);
-        u_save.alloc(size_t(nn) * m.dim, s);
-        p_save.alloc(size_t(nn), s);
+        fr::DBuf<double>& du = W.du;
+        fr::DBuf<double>& u_save = W.u_save;
+        fr::DBuf<double>& p_save = W.p_save;
+        if (du.p == nullptr) du.alloc(size_t(sys.n_solve), s);
+        if (u_save.p == nullptr) u_save.alloc(size_t(nn) * m.dim, s);
+        if (p_save.p == nullptr) p_save.alloc(size_t(nn), s);
         double t_asm = 0, t_setup = 0, t_solve = 0, t_other = 0;
         {
             EventTimer t(s);
@@ -616,6 +660,7 @@ fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double*
                 EventTimer t(s);
                 fr_amg_opts ao_it = ao;
                 ao_it.reuse_u_block = (it > 0 && ao.reuse_u_block) ? 1 : 0;
+                ao_it.refresh_phi = (it > 0 && ao.refresh_phi) ? 1 : 0;
                 fr::amg_build(A->amg, sys, ao_it, s);
                 t_setup += t.stop();
             }

@@ -35,7 +35,13 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Stream-ordered device buffer.  Freed on the stream it was allocated on.
+// The library's stream-ordered pool of the current device (created on first use) and the
+// call that returns its unused memory to the driver (synchronises the device).
+hipMemPool_t device_pool();
+void trim_pool();
+
+// Stream-ordered device buffer from the library pool.  Freed on the stream it was
+// allocated on.
 template <typename T>
 struct DBuf {
     T* p = nullptr;
@@ -54,7 +60,7 @@ struct DBuf {
         release();
         s = stream;
         n = count;
-        if (count) FR_HIP(hipMallocAsync(reinterpret_cast<void**>(&p), count * sizeof(T), stream));
+        if (count) FR_HIP(hipMallocFromPoolAsync(reinterpret_cast<void**>(&p), count * sizeof(T), device_pool(), stream));
     }
     // Grows (never shrinks); contents are not preserved.
     void reserve(size_t count, hipStream_t stream) {

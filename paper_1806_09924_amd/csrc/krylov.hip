@@ -319,6 +319,20 @@ static void build_table(DevSystem& sys, DevKrylov& ws, hipStream_t s) {
     ws.n_inst = hm.n_inst;
 }
 
+// Doubles the basis capacity (up to the restart length), keeping V_0..V_j and Z_0..Z_{j-1}.
+static void grow_basis(DevKrylov& ws, int j, hipStream_t s) {
+    const int cap = std::min(ws.m, std::max(j + 1, 2 * ws.cap));
+    const size_t n = size_t(ws.n);
+    DBuf<double> V, Z;
+    V.alloc(size_t(cap + 1) * n, s);
+    Z.alloc(size_t(cap) * n, s);
+    FR_HIP(hipMemcpyAsync(V.p, ws.V.p, size_t(j + 1) * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (j > 0) FR_HIP(hipMemcpyAsync(Z.p, ws.Z.p, size_t(j) * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    ws.V = std::move(V);
+    ws.Z = std::move(Z);
+    ws.cap = cap;
+}
+
 fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du, fr_solve_stats* stats,
                  DevKrylov& ws, hipStream_t s) {
     const int64_t n = sys.n_solve;
@@ -327,8 +341,10 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
     if (ws.n != n || ws.m != m || ws.n_inst != ni) {
         ws.n = n;
         ws.m = m;
-        ws.V.alloc(size_t(m + 1) * size_t(n), s);
-        ws.Z.alloc(size_t(m) * size_t(n), s);
+        // the bases start at kInitBasis vectors and grow with the iterations a cycle takes
+        ws.cap = std::min(m, kInitBasis);
+        ws.V.alloc(size_t(ws.cap + 1) * size_t(n), s);
+        ws.Z.alloc(size_t(ws.cap) * size_t(n), s);
         ws.w.alloc(size_t(n), s);
         build_table(sys, ws, s);
         ws.part.alloc(size_t(ws.nb) * (kMaxM + 2) + 64, s);
@@ -404,6 +420,7 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
         FR_LAUNCH_CHECK();
         int j = 0;
         for (; j < M && total < o.maxit; ++j) {
+            if (j + 1 > ws.cap) grow_basis(ws, j, s);
             double* Vj = ws.V.p + int64_t(j) * n;
             double* Zj = ws.Z.p + int64_t(j) * n;
             amg_precondition(amg, Vj, Zj, s);

@@ -69,7 +69,7 @@ ProfScope::ProfScope(const char* name, hipStream_t stream, double bytes) {
     idx = it->second;
     s = stream;
     Entry& e = g_entries[size_t(idx)];
-    if (e.ev.size() >= 512) drain(e);
+    if (e.ev.size() >= 16384) drain(e);   // bounded event pool; folding synchronises
     hipEvent_t a = take_event(), b = take_event();
     (void)hipEventRecord(a, s);
     e.ev.push_back({a, b});

@@ -10,24 +10,38 @@
 namespace fr {
 namespace {
 
-// MODE 0: y = A x; 1: y = b - A x; 2: y += A x
-template <typename T, int BR, int BC, int MODE>
-__global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, int C, const int32_t* __restrict__ slice_ptr,
-                                              const int32_t* __restrict__ col, const T* __restrict__ val,
-                                              const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y) {
-    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= n_rows) return;
-    const int64_t s = r / C;
-    const int lane = int(r - s * C);
-    const int32_t p0 = slice_ptr[s];
-    const int w = (slice_ptr[s + 1] - p0) / C;
-    T acc[BR];
+// acc += (row of A) x over the w slots of one SELL row starting at `slot` (stride C).  The
+// entries are taken U at a time with every load of a group issued before its products, so
+// a lane keeps several gathers in flight; the summation order stays entry by entry.
+template <typename T, int BR, int BC, int U>
+__device__ __forceinline__ void row_product(int w, int C, int64_t slot, const int32_t* __restrict__ col,
+                                            const T* __restrict__ val, const T* __restrict__ x, T* acc) {
+    constexpr int BB = BR * BC;
+    int k = 0;
+    for (; k + U <= w; k += U, slot += int64_t(U) * C) {
+        int64_t c[U];
 #pragma unroll
-    for (int i = 0; i < BR; ++i) acc[i] = T(0);
-    int64_t slot = int64_t(p0) + lane;
-    for (int k = 0; k < w; ++k, slot += C) {
+        for (int u = 0; u < U; ++u) c[u] = col[slot + int64_t(u) * C];
+        T xv[U][BC];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < BC; ++j) xv[u][j] = x[c[u] * BC + j];
+        T v[U][BB];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < BB; ++e) v[u][e] = val[(slot + int64_t(u) * C) * BB + e];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int i = 0; i < BR; ++i)
+#pragma unroll
+                for (int j = 0; j < BC; ++j) acc[i] += v[u][i * BC + j] * xv[u][j];
+    }
+    for (; k < w; ++k, slot += C) {
         const int64_t c = col[slot];
-        const T* v = val + slot * (BR * BC);
+        const T* v = val + slot * BB;
         T xv[BC];
 #pragma unroll
         for (int j = 0; j < BC; ++j) xv[j] = x[c * BC + j];
@@ -36,6 +50,64 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, int C, const int32
 #pragma unroll
             for (int j = 0; j < BC; ++j) acc[i] += v[i * BC + j] * xv[j];
     }
+}
+
+// With G > 1 lanes per row (small levels, long rows: few rows would leave most of the chip
+// idle), lane g of a group takes entries g, g+G, ... and the group combines its partial sums
+// by an xor butterfly, which leaves the same total on every lane of the group.
+template <typename T, int BR, int BC, int G, int U>
+__device__ __forceinline__ void row_product_g(int w, int C, int64_t slot0, int g, const int32_t* __restrict__ col,
+                                              const T* __restrict__ val, const T* __restrict__ x, T* acc) {
+    if constexpr (G == 1) {
+        row_product<T, BR, BC, U>(w, C, slot0, col, val, x, acc);
+    } else {
+        constexpr int BB = BR * BC;
+        for (int k = g; k < w; k += G) {
+            const int64_t slot = slot0 + int64_t(k) * C;
+            const int64_t c = col[slot];
+            const T* v = val + slot * BB;
+            T xv[BC];
+#pragma unroll
+            for (int j = 0; j < BC; ++j) xv[j] = x[c * BC + j];
+#pragma unroll
+            for (int i = 0; i < BR; ++i)
+#pragma unroll
+                for (int j = 0; j < BC; ++j) acc[i] += v[i * BC + j] * xv[j];
+        }
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1)
+#pragma unroll
+            for (int i = 0; i < BR; ++i) acc[i] += __shfl_xor(acc[i], o, kWave);
+    }
+}
+
+// Lanes per row for a SELL matrix: 1, 4, 16 or 64, growing while the launch would have
+// fewer than 2^20 lanes and the longest row has entries for them.
+inline int lanes_per_row(const SellStruct& S) {
+    int G = 1;
+    while (G < 64 && S.n_rows * G < (int64_t(1) << 20) && G < S.max_len) G *= 4;
+    return G;
+}
+
+// MODE 0: y = A x; 1: y = b - A x; 2: y += A x
+template <typename T, int BR, int BC, int MODE, int G>
+__global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, int C, const int32_t* __restrict__ slice_ptr,
+                                              const int32_t* __restrict__ col, const T* __restrict__ val,
+                                              const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y) {
+    constexpr int U = BR * BC == 1 ? 8 : (BR * BC <= 4 ? 4 : 2);
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t r = t / G;
+    const int g = int(t % G);
+    if (r >= n_rows) return;   // whole groups leave together
+    const int64_t s = r / C;
+    const int lane = int(r - s * C);
+    const int32_t p0 = slice_ptr[s];
+    const int w = (slice_ptr[s + 1] - p0) / C;
+    T acc[BR];
+#pragma unroll
+    for (int i = 0; i < BR; ++i) acc[i] = T(0);
+    row_product_g<T, BR, BC, G, U>(w, C, int64_t(p0) + lane, g, col, val, x, acc);
+    if (g != 0) return;
 #pragma unroll
     for (int i = 0; i < BR; ++i) {
         if (MODE == 0) y[r * BR + i] = acc[i];
@@ -45,13 +117,16 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, int C, const int32
 }
 
 // Chebyshev step: r = b - A x_old; d = alpha d + beta D^-1 r; x_new = x_old + d
-template <typename T, int B>
+template <typename T, int B, int G>
 __global__ void __launch_bounds__(256) k_cheb(int64_t n_rows, int C, const int32_t* __restrict__ slice_ptr,
                                               const int32_t* __restrict__ col, const T* __restrict__ val,
                                               const T* __restrict__ invd, const T* __restrict__ x_old,
                                               const T* __restrict__ b, T* __restrict__ d, T* __restrict__ x_new,
                                               T alpha, T beta) {
-    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    constexpr int U = B == 1 ? 8 : (B == 6 ? 1 : 2);
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t r = t / G;
+    const int g = int(t % G);
     if (r >= n_rows) return;
     const int64_t s = r / C;
     const int lane = int(r - s * C);
@@ -60,18 +135,8 @@ __global__ void __launch_bounds__(256) k_cheb(int64_t n_rows, int C, const int32
     T acc[B];
 #pragma unroll
     for (int i = 0; i < B; ++i) acc[i] = T(0);
-    int64_t slot = int64_t(p0) + lane;
-    for (int k = 0; k < w; ++k, slot += C) {
-        const int64_t c = col[slot];
-        const T* v = val + slot * (B * B);
-        T xv[B];
-#pragma unroll
-        for (int j = 0; j < B; ++j) xv[j] = x_old[c * B + j];
-#pragma unroll
-        for (int i = 0; i < B; ++i)
-#pragma unroll
-            for (int j = 0; j < B; ++j) acc[i] += v[i * B + j] * xv[j];
-    }
+    row_product_g<T, B, B, G, U>(w, C, int64_t(p0) + lane, g, col, val, x_old, acc);
+    if (g != 0) return;
 #pragma unroll
     for (int i = 0; i < B; ++i) {
         const int64_t e = r * B + i;
@@ -381,17 +446,26 @@ static void spmv_mode(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_
     const int br = A.br, bc = A.bc;
     const SellStruct& S = *A.S;
     if (S.n_rows == 0) return;
-    const int g = nblk(S.n_rows, 256);
     char name[48];
     std::snprintf(name, sizeof(name), "spmv_%s_%dx%d_m%d", sizeof(T) == 8 ? "f64" : "f32", br, bc, MODE);
     const double bytes = double(S.nnz) * (br * bc * sizeof(T) + 4) + double(S.n_cols) * bc * sizeof(T) +
                          double(S.n_rows) * br * sizeof(T) * (MODE == 0 ? 1 : 2);
     ProfScope ps(name, s, bytes);
-#define FR_SPMV_CALL(BR_, BC_)                                                                     \
-    k_spmv<T, BR_, BC_, MODE><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, x, b, y); \
+    const int G = lanes_per_row(S);
+    const int gg = nblk(S.n_rows * G, 256);
+#define FR_SPMV_G(BR_, BC_, G_)                                                                      \
+    k_spmv<T, BR_, BC_, MODE, G_><<<gg, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, x, b, y);
+#define FR_SPMV_CALL(BR_, BC_)                                                                       \
+    switch (G) {                                                                                     \
+        case 1: FR_SPMV_G(BR_, BC_, 1) break;                                                        \
+        case 4: FR_SPMV_G(BR_, BC_, 4) break;                                                        \
+        case 16: FR_SPMV_G(BR_, BC_, 16) break;                                                      \
+        default: FR_SPMV_G(BR_, BC_, 64) break;                                                      \
+    }                                                                                                \
     FR_LAUNCH_CHECK();
     FR_ALL_BLOCKS(FR_SPMV_CALL)
 #undef FR_SPMV_CALL
+#undef FR_SPMV_G
 }
 
 template <typename T>
@@ -406,19 +480,32 @@ void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d
                hipStream_t s) {
     const SellStruct& S = *A.S;
     if (S.n_rows == 0) return;
-    const int g = nblk(S.n_rows, 256);
     char name[48];
     std::snprintf(name, sizeof(name), "cheb_%s_b%d", sizeof(T) == 8 ? "f64" : "f32", A.br);
     // matrix once, x gathered once, b, d, D^-1 read, d and x_new written
     const double bytes = double(S.nnz) * (A.br * A.bc * sizeof(T) + 4) + double(S.n_rows) * A.br * sizeof(T) * 6;
     ProfScope ps(name, s, bytes);
+    const int G = lanes_per_row(S);
+    const int gg = nblk(S.n_rows * G, 256);
+#define FR_CHEB_G(B_, G_)                                                                            \
+    k_cheb<T, B_, G_><<<gg, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, invd, x_old, b, d, x_new, \
+                                         alpha, beta);
+#define FR_CHEB_CALL(B_)                                                                             \
+    switch (G) {                                                                                     \
+        case 1: FR_CHEB_G(B_, 1) break;                                                              \
+        case 4: FR_CHEB_G(B_, 4) break;                                                              \
+        case 16: FR_CHEB_G(B_, 16) break;                                                            \
+        default: FR_CHEB_G(B_, 64) break;                                                            \
+    }
     switch (A.br) {
-        case 1: k_cheb<T, 1><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, invd, x_old, b, d, x_new, alpha, beta); break;
-        case 2: k_cheb<T, 2><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, invd, x_old, b, d, x_new, alpha, beta); break;
-        case 3: k_cheb<T, 3><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, invd, x_old, b, d, x_new, alpha, beta); break;
-        case 6: k_cheb<T, 6><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, invd, x_old, b, d, x_new, alpha, beta); break;
+        case 1: FR_CHEB_CALL(1) break;
+        case 2: FR_CHEB_CALL(2) break;
+        case 3: FR_CHEB_CALL(3) break;
+        case 6: FR_CHEB_CALL(6) break;
         default: fail(FR_EINTERNAL, "cheb: unsupported block size");
     }
+#undef FR_CHEB_CALL
+#undef FR_CHEB_G
     FR_LAUNCH_CHECK();
 }
 

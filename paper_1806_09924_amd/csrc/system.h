@@ -128,6 +128,7 @@ void jspmv(const DevSystem& sys, const double* x, double* y, hipStream_t s);
 // ---- AMG (amg.hip) ----------------------------------------------------------------------
 struct AmgLevel {
     BMat<double> A, P, R;
+    BMat<double> Pt, AP;                         // kept for a numeric-only refresh
     BMat<float> A32, P32, R32;
     DBuf<double> invd;
     DBuf<float> invd32;
@@ -142,6 +143,7 @@ struct Hierarchy {
     std::vector<std::unique_ptr<AmgLevel>> lv;
     DBuf<double> dense_inv;                      // coarsest A^-1, row-major
     int64_t n_coarse = 0;
+    bool refreshable = false;                    // Pt and AP kept on every level but the last
 };
 
 struct DevAmg {
@@ -169,9 +171,12 @@ void amg_info(DevAmg& amg, int blk, int level, int& n_levels, int64_t& rows, int
               double& lmax, hipStream_t s);
 
 // ---- Krylov (krylov.hip) ----------------------------------------------------------------
+constexpr int kInitBasis = 24;                   // initial Krylov basis capacity (vectors)
+
 struct DevKrylov {
     int64_t n = 0;
     int m = 0, n_inst = 0, nb = 0;
+    int cap = 0;                                 // vectors held in Z (V holds cap + 1)
     DBuf<double> V, Z, w, part, state;
     DBuf<int> istate;
     DBuf<int64_t> seg_start;                     // segmented-sweep block table

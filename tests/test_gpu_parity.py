@@ -125,22 +125,68 @@ def test_amg_hierarchy_algebra():
     for blk, ref in ((0, o.Jm[:nu, :nu]), (1, o.Jm[nu:, nu:])):
         nl = A.n_levels(blk)
         assert nl >= 2
-        shp, rp, ci, vv = A.level_csr(blk, 0, 0)
-        A0 = sp.csr_matrix((vv, ci, rp), shape=shp)
-        assert abs(A0 - ref).max() <= 1e-12 * abs(ref).max()
-        for lev in range(nl - 1):
-            sA, rp, ci, vv = A.level_csr(blk, lev, 0)
-            Al = sp.csr_matrix((vv, ci, rp), shape=sA)
-            sP, rp, ci, vv = A.level_csr(blk, lev, 1)
-            Pl = sp.csr_matrix((vv, ci, rp), shape=sP)
-            sR, rp, ci, vv = A.level_csr(blk, lev, 2)
-            Rl = sp.csr_matrix((vv, ci, rp), shape=sR)
-            assert abs(Rl - Pl.T).max() == 0.0
-            sC, rp, ci, vv = A.level_csr(blk, lev + 1, 0)
-            Ac = sp.csr_matrix((vv, ci, rp), shape=sC)
-            ref_c = Rl @ Al @ Pl
-            assert abs(Ac - ref_c).max() <= 1e-11 * abs(ref_c).max()
-            assert sC[0] < sA[0]
+        _galerkin_checks(A, blk, ref)
+        rows = [A.level_info(blk, lev)["rows"] for lev in range(nl)]
+        assert all(b < a for a, b in zip(rows, rows[1:]))
+
+
+def _galerkin_checks(A, blk, ref0):
+    nl = A.n_levels(blk)
+    shp, rp, ci, vv = A.level_csr(blk, 0, 0)
+    A0 = sp.csr_matrix((vv, ci, rp), shape=shp)
+    assert abs(A0 - ref0).max() <= 1e-12 * abs(ref0).max()
+    for lev in range(nl - 1):
+        sA, rp, ci, vv = A.level_csr(blk, lev, 0)
+        Al = sp.csr_matrix((vv, ci, rp), shape=sA)
+        sP, rp, ci, vv = A.level_csr(blk, lev, 1)
+        Pl = sp.csr_matrix((vv, ci, rp), shape=sP)
+        sR, rp, ci, vv = A.level_csr(blk, lev, 2)
+        Rl = sp.csr_matrix((vv, ci, rp), shape=sR)
+        assert abs(Rl - Pl.T).max() == 0.0
+        sC, rp, ci, vv = A.level_csr(blk, lev + 1, 0)
+        Ac = sp.csr_matrix((vv, ci, rp), shape=sC)
+        ref_c = Rl @ Al @ Pl
+        assert abs(Ac - ref_c).max() <= 1e-11 * abs(ref_c).max()
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_amg_phase_field_refresh(precision):
+    """A refreshed phase-field hierarchy (aggregates and sparsity kept, values recomputed
+    for a new Jacobian with another active set) is the Galerkin hierarchy of the new
+    matrix and preconditions it about as well as a rebuilt one."""
+    P = Problem(2, 2.0, 64)
+    S = _gpu_system(P)
+    opts = B.amg_opts(precision=precision, refresh_phi=1)
+    A = B.Amg(S, opts)
+    nl = A.n_levels(1)
+    before = [A.level_info(1, lev) for lev in range(nl)]
+    P0_1 = A.level_csr(1, 0, 1)[3].copy()
+    u0, phi0, po, pt = P.state
+    rng = np.random.default_rng(5)
+    u2 = 1e-3 * rng.standard_normal(u0.shape)
+    u2[P.omesh.dirichlet] = 0.0
+    phi2 = np.clip(phi0 - rng.uniform(0.0, 0.05, phi0.shape), 0.0, 1.0)
+    o = _oracle_system(P, u=u2, phi=phi2)
+    S.assemble(P.prm, dev(u2), dev(phi2), dev(po), dev(pt))
+    S.set_active(torch.as_tensor(o.active.astype(np.uint8), device="cuda"))
+    S.assemble(P.prm, dev(u2), dev(phi2), dev(po), dev(pt), flags=B.FR_JACOBIAN)
+    A.setup(opts)
+    assert A.n_levels(1) == nl
+    after = [A.level_info(1, lev) for lev in range(nl)]
+    for b, a in zip(before, after):
+        assert (b["rows"], b["nnz_blocks"]) == (a["rows"], a["nnz_blocks"])
+    assert np.abs(A.level_csr(1, 0, 1)[3] - P0_1).max() > 0.0     # new values
+    nu = 2 * P.mesh.n_free
+    _galerkin_checks(A, 1, o.Jm[nu:, nu:])
+    fresh = B.Amg(S, B.amg_opts(precision=precision, refresh_phi=0))
+    its = []
+    for amg in (A, fresh):
+        du = torch.empty(P.mesh.n_solve, dtype=torch.float64, device="cuda")
+        st = B.solve(S, amg, du, B.solve_opts(rtol=1e-8))
+        d = host(du)
+        assert np.linalg.norm(o.F - o.Jm @ d) / np.linalg.norm(o.F) <= 1.01e-8
+        its.append(st["iters"])
+    assert its[0] <= its[1] + 4
 
 
 def test_vcycle_is_linear_and_symmetric():
@@ -246,3 +292,47 @@ def test_newton_loop_matches_oracle():
     _, tcv = B.functionals(P.mesh, u, phi)
     assert abs(tcv / t_ref - 1) <= 1e-6
     assert st["n_active"] == int(ref["active"].sum())
+
+
+def test_pool_trim_and_run_to_run_determinism():
+    """Two identical solves, with the pool's unused memory handed back in between, give
+    bit-identical updates (fixed reduction orders; no atomics in the numeric kernels)."""
+    outs = []
+    for _ in range(2):
+        P = Problem(2, 2.0, 64)
+        S = _gpu_system(P)
+        A = B.Amg(S)
+        du = torch.empty(P.mesh.n_solve, dtype=torch.float64, device="cuda")
+        B.solve(S, A, du, B.solve_opts(rtol=1e-8))
+        outs.append(host(du))
+        del A, S, P
+        B.trim_pool()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_newton_reuses_working_storage_exactly():
+    """fracture_newton keeps its storage with the mesh: repeated calls, a call at the other
+    precision in between, and a call on another stream all give bit-identical results."""
+    P = Problem(2, 1.0, 32, l0=0.25, kappa=1e-8)
+
+    def run(precision=64):
+        u, phi, po, pt = P.dstate()
+        st = B.newton(P.mesh, P.prm, u, phi, po, pt, amg=B.amg_opts(precision=precision),
+                      solve=B.solve_opts(rtol=1e-10))
+        return st, host(u), host(phi)
+
+    st0, u0, p0 = run()
+    st1, u1, p1 = run()
+    assert np.array_equal(u0, u1) and np.array_equal(p0, p1)
+    assert (st0["iterations"], st0["linear_iters"]) == (st1["iterations"], st1["linear_iters"])
+    run(32)
+    _, u2, p2 = run()
+    assert np.array_equal(u0, u2) and np.array_equal(p0, p2)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        _, u3, p3 = run()
+    torch.cuda.synchronize()
+    assert np.array_equal(u0, u3) and np.array_equal(p0, p3)
+    _, u4, p4 = run()
+    assert np.array_equal(u0, u4) and np.array_equal(p0, p4)
