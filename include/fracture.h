@@ -296,10 +296,11 @@ fr_status fracture_profile_read(int i, const char** name, int64_t* launches, dou
 
 /* ---- misc ------------------------------------------------------------------------- */
 
-/* Device memory of every object comes from one stream-ordered pool per device that keeps
- * freed memory mapped for reuse (allocation then costs no driver call). This returns the
- * current device's unused pool memory to the driver; it synchronises the device. Objects
- * that are alive keep their memory. */
+/* Device memory of every object comes from a stream-ordered pool per device, and memory an
+ * object gives up is cached for later allocations on the same stream (repeated calls of
+ * one size then make no allocation calls). This hands the current device's cached and
+ * unused pool memory back to the driver; it synchronises the device. Objects that are
+ * alive keep their memory. */
 fr_status fracture_trim_pool(void);
 
 const char* fracture_last_error(void);

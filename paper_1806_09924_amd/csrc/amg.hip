@@ -8,6 +8,8 @@
 // accumulates in a fixed order, so the hierarchy is bitwise reproducible.
 #include <algorithm>
 #include <cmath>
+#include <exception>
+#include <thread>
 
 #include "profile.h"
 #include "system.h"
@@ -1310,6 +1312,17 @@ static void refresh_hierarchy(Hierarchy& H, double* a0, const fr_amg_opts& o, hi
         for (size_t l = 0; l < nl; ++l) make_f32(*H.lv[l], l + 1 == nl, s);
 }
 
+static void ensure_side(DevAmg& amg) {
+    if (amg.side) return;
+    FR_HIP(hipStreamCreateWithFlags(&amg.side, hipStreamNonBlocking));
+    FR_HIP(hipEventCreateWithFlags(&amg.ev_fork, hipEventDisableTiming));
+    FR_HIP(hipEventCreateWithFlags(&amg.ev_join, hipEventDisableTiming));
+}
+
+// The displacement hierarchy lives on the caller's stream, the phase-field hierarchy on the
+// side stream (its buffers are allocated, used and freed there).  When both are built from
+// scratch the phase-field setup runs in a second host thread, so that the host round trips
+// of one setup overlap the device work of the other.
 void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s) {
     const bool keep_u = o.reuse_u_block && amg.sys == &sys && !amg.h[0].lv.empty() &&
                         amg.opts.precision == o.precision && amg.h[0].lv[0]->A.val == sys.Juu.val;
@@ -1320,24 +1333,59 @@ void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s)
     amg.sys = &sys;
     amg.opts = o;
     amg.stream = s;
+    ensure_side(amg);
     DevMesh& m = *sys.mesh;
-    if (!keep_u) {
+    // fork: the side stream follows everything enqueued on s so far (the Jacobian, and
+    // every earlier use of the buffers that the phase-field setup frees)
+    FR_HIP(hipEventRecord(amg.ev_fork, s));
+    FR_HIP(hipStreamWaitEvent(amg.side, amg.ev_fork, 0));
+    const hipStream_t side = amg.side;
+    auto phi_setup = [&amg, &sys, &m, o, refresh_phi, side]() {
+        if (refresh_phi) {
+            ProfScope ps("setup_refresh_phi", side, 0.0);
+            refresh_hierarchy(amg.h[1], sys.Jpp.val, o, side);
+        } else {
+            BMat<double> Ap;
+            Ap.br = Ap.bc = 1;
+            Ap.S = sys.Jpp.S;
+            Ap.val = sys.Jpp.val;
+            build_hierarchy(amg.h[1], std::move(Ap), 1, m.coords_free.p, m.dim, o, o.refresh_phi != 0, side);
+        }
+    };
+    auto u_setup = [&]() {
         BMat<double> Au;
         Au.br = Au.bc = m.dim;
         Au.S = sys.Juu.S;
         Au.val = sys.Juu.val;
         build_hierarchy(amg.h[0], std::move(Au), m.dim == 2 ? 3 : 6, m.coords_free.p, m.dim, o, false, s);
-    }
-    if (refresh_phi) {
-        ProfScope ps("setup_refresh_phi", s, 0.0);
-        refresh_hierarchy(amg.h[1], sys.Jpp.val, o, s);
+    };
+    if (keep_u) {
+        phi_setup();
     } else {
-        BMat<double> Ap;
-        Ap.br = Ap.bc = 1;
-        Ap.S = sys.Jpp.S;
-        Ap.val = sys.Jpp.val;
-        build_hierarchy(amg.h[1], std::move(Ap), 1, m.coords_free.p, m.dim, o, o.refresh_phi != 0, s);
+        int dev = 0;
+        FR_HIP(hipGetDevice(&dev));
+        std::exception_ptr phi_err;
+        std::thread worker([&]() {
+            try {
+                FR_HIP(hipSetDevice(dev));
+                phi_setup();
+            } catch (...) {
+                phi_err = std::current_exception();
+            }
+        });
+        std::exception_ptr u_err;
+        try {
+            u_setup();
+        } catch (...) {
+            u_err = std::current_exception();
+        }
+        worker.join();
+        if (u_err) std::rethrow_exception(u_err);
+        if (phi_err) std::rethrow_exception(phi_err);
     }
+    // join
+    FR_HIP(hipEventRecord(amg.ev_join, side));
+    FR_HIP(hipStreamWaitEvent(s, amg.ev_join, 0));
     amg.sys_version = sys.version;
 }
 
@@ -1442,11 +1490,7 @@ void amg_precondition(DevAmg& amg, const double* r, double* z, hipStream_t s) {
     const int64_t np = sys.n_solve - nu;
     const int64_t nb[2] = {nu, np};
     const int64_t off[2] = {0, nu};
-    if (!amg.side) {
-        FR_HIP(hipStreamCreateWithFlags(&amg.side, hipStreamNonBlocking));
-        FR_HIP(hipEventCreateWithFlags(&amg.ev_fork, hipEventDisableTiming));
-        FR_HIP(hipEventCreateWithFlags(&amg.ev_join, hipEventDisableTiming));
-    }
+    ensure_side(amg);
     // fork: the phi block's V-cycle on the side stream, the u block's on the caller's
     FR_HIP(hipEventRecord(amg.ev_fork, s));
     FR_HIP(hipStreamWaitEvent(amg.side, amg.ev_fork, 0));

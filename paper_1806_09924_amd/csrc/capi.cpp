@@ -660,7 +660,9 @@ fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double*
                 EventTimer t(s);
                 fr_amg_opts ao_it = ao;
                 ao_it.reuse_u_block = (it > 0 && ao.reuse_u_block) ? 1 : 0;
-                ao_it.refresh_phi = (it > 0 && ao.refresh_phi) ? 1 : 0;
+                // the first iteration of every call builds both hierarchies from scratch (the
+                // phase-field one keeps what a later refresh needs when refresh_phi is set)
+                if (it == 0) A->amg.h[1].refreshable = false;
                 fr::amg_build(A->amg, sys, ao_it, s);
                 t_setup += t.stop();
             }

@@ -35,13 +35,16 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// The library's stream-ordered pool of the current device (created on first use) and the
-// call that returns its unused memory to the driver (synchronises the device).
-hipMemPool_t device_pool();
+// Device memory of the current device, stream ordered: a block freed on stream s is reused
+// by later allocations on s.  trim_pool hands every cached block and the pool's unused
+// memory back to the driver (synchronises the device); forget_stream does so for the
+// blocks cached for s (synchronises s), before s is destroyed.
+void* dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
 void trim_pool();
+void forget_stream(hipStream_t s);
 
-// Stream-ordered device buffer from the library pool.  Freed on the stream it was
-// allocated on.
+// Stream-ordered device buffer.  Released on the stream it was allocated on.
 template <typename T>
 struct DBuf {
     T* p = nullptr;
@@ -60,14 +63,14 @@ struct DBuf {
         release();
         s = stream;
         n = count;
-        if (count) FR_HIP(hipMallocFromPoolAsync(reinterpret_cast<void**>(&p), count * sizeof(T), device_pool(), stream));
+        if (count) p = static_cast<T*>(dev_alloc(count * sizeof(T), stream));
     }
     // Grows (never shrinks); contents are not preserved.
     void reserve(size_t count, hipStream_t stream) {
         if (count > n || p == nullptr) alloc(count, stream);
     }
     void release() {
-        if (p) { (void)hipFreeAsync(p, s); p = nullptr; n = 0; }
+        if (p) { dev_free(p, s); p = nullptr; n = 0; }
     }
     void upload(const T* h, size_t count, hipStream_t stream) {
         if (count) FR_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, stream));

@@ -8,9 +8,14 @@
 namespace fr {
 namespace {
 
+struct Pair {
+    hipEvent_t a = nullptr, b = nullptr;
+    bool closed = false;                          // b recorded (the scope has ended)
+};
+
 struct Entry {
     std::string name;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<Pair> ev;
     double bytes = 0.0;
     double ms = 0.0;
     int64_t launches = 0;
@@ -33,16 +38,25 @@ hipEvent_t take_event() {
     return e;
 }
 
-// Folds the finished events of an entry into its totals and returns them to the pool.
+// Folds the closed event pairs of an entry into its totals and returns their events to the
+// pool; pairs of scopes still open (another thread) stay.  Errors of these calls are
+// cleared so that they do not surface at a later launch check.
 void drain(Entry& e) {
+    std::vector<Pair> open;
     for (auto& p : e.ev) {
-        (void)hipEventSynchronize(p.second);
+        if (!p.closed) {
+            open.push_back(p);
+            continue;
+        }
         float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, p.first, p.second) == hipSuccess) e.ms += double(ms);
-        g_pool.push_back(p.first);
-        g_pool.push_back(p.second);
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess)
+            e.ms += double(ms);
+        else
+            (void)hipGetLastError();
+        g_pool.push_back(p.a);
+        g_pool.push_back(p.b);
     }
-    e.ev.clear();
+    e.ev.swap(open);
 }
 
 }  // namespace
@@ -57,6 +71,7 @@ void prof_enable(bool on) {
     g_on = on;
 }
 
+// Each scope owns its event pair, so scopes of one name may overlap (two host threads).
 ProfScope::ProfScope(const char* name, hipStream_t stream, double bytes) {
     if (!g_on) return;
     std::lock_guard<std::mutex> lk(g_mu);
@@ -70,9 +85,10 @@ ProfScope::ProfScope(const char* name, hipStream_t stream, double bytes) {
     s = stream;
     Entry& e = g_entries[size_t(idx)];
     if (e.ev.size() >= 16384) drain(e);   // bounded event pool; folding synchronises
-    hipEvent_t a = take_event(), b = take_event();
+    a = take_event();
+    b = take_event();
     (void)hipEventRecord(a, s);
-    e.ev.push_back({a, b});
+    e.ev.push_back(Pair{a, b, false});
     e.bytes += bytes;
     e.launches += 1;
 }
@@ -80,7 +96,14 @@ ProfScope::ProfScope(const char* name, hipStream_t stream, double bytes) {
 ProfScope::~ProfScope() {
     if (idx < 0) return;
     std::lock_guard<std::mutex> lk(g_mu);
-    (void)hipEventRecord(g_entries[size_t(idx)].ev.back().second, s);
+    (void)hipEventRecord(b, s);
+    if (size_t(idx) >= g_entries.size()) return;   // registry reset while the scope was open
+    auto& ev = g_entries[size_t(idx)].ev;
+    for (auto p = ev.rbegin(); p != ev.rend(); ++p)
+        if (p->a == a) {
+            p->closed = true;
+            break;
+        }
 }
 
 int prof_count() {

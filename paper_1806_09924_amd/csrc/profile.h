@@ -12,6 +12,7 @@ void prof_enable(bool on);
 struct ProfScope {
     int idx = -1;
     hipStream_t s = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
     ProfScope(const char* name, hipStream_t stream, double bytes);
     ~ProfScope();
 };

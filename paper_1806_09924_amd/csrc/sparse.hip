@@ -82,10 +82,11 @@ __device__ __forceinline__ void row_product_g(int w, int C, int64_t slot0, int g
 }
 
 // Lanes per row for a SELL matrix: 1, 4, 16 or 64, growing while the launch would have
-// fewer than 2^20 lanes and the longest row has entries for them.
+// fewer than 2^20 lanes and an average row still has an entry for every lane.
 inline int lanes_per_row(const SellStruct& S) {
+    const int64_t avg = S.n_rows > 0 ? S.nnz / S.n_rows : 0;
     int G = 1;
-    while (G < 64 && S.n_rows * G < (int64_t(1) << 20) && G < S.max_len) G *= 4;
+    while (G < 64 && S.n_rows * G < (int64_t(1) << 20) && 4 * G <= avg) G *= 4;
     return G;
 }
 

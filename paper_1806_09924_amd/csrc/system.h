@@ -156,7 +156,12 @@ struct DevAmg {
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     ~DevAmg() {
-        if (side) (void)hipStreamSynchronize(side);
+        // the phase-field hierarchy's buffers are freed on the side stream: before it goes
+        for (auto& H : h) {
+            H.lv.clear();
+            H.dense_inv.release();
+        }
+        if (side) forget_stream(side);   // synchronises the side stream
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (side) (void)hipStreamDestroy(side);
