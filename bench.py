@@ -107,8 +107,9 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the batched and domain-decomposed sharding is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; independent instances "
+              "would shard across GPUs with no exchange, one large instance by node slabs with one-layer "
+              "halos and one all-reduce of the Gram-Schmidt coefficients per FGMRES iteration.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
