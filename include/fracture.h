@@ -81,7 +81,8 @@ typedef struct {
     int precision;       /* 64: FP64 hierarchy and V-cycle; 32: FP32 storage and arithmetic */
     double theta;        /* strength threshold, |A_ij| >= theta sqrt(|A_ii| |A_jj|) (block Frobenius norms) */
     int cheb_degree;     /* Chebyshev smoother degree (>= 1) */
-    double cheb_ratio;   /* smoothing interval [lambda_max / ratio, lambda_max] */
+    double cheb_ratio;   /* smoothing interval [1.1 lambda_max / ratio, 1.1 lambda_max] of D^-1 A
+                            (default 12) */
     int coarse_max;      /* coarsest level solved densely once it has <= coarse_max rows */
     int max_levels;      /* cap on the number of levels (>= 1) */
     int reuse_u_block;   /* nonzero: amg_setup keeps an existing displacement-block hierarchy.

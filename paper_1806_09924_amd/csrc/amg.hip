@@ -10,6 +10,7 @@
 #include <cmath>
 #include <exception>
 #include <thread>
+#include <type_traits>
 
 #include "profile.h"
 #include "system.h"
@@ -1431,44 +1432,53 @@ struct LevelOps<float> {
 };
 
 // Chebyshev smoothing of A x = b on [lmax/ratio, 1.1 lmax] starting from x (zero if
-// from_zero).  Returns the buffer (x0 or x1 of the level) holding the result.
+// from_zero).  Returns the buffer holding the result: x0 or x1 of the level, or `out` when
+// given (the last step writes there).
 template <typename T>
 static T* chebyshev(const AmgLevel& Lc, AmgLevel& L, const T* b, bool from_zero, T* x, T* other, int degree,
-                    double ratio, hipStream_t s) {
+                    double ratio, hipStream_t s, T* out = nullptr) {
     using O = LevelOps<T>;
     const double hi = 1.1 * Lc.lmax, lo = hi / ratio;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     double rho = 1.0 / sigma;
     const int64_t n = Lc.A.rows() * Lc.A.br;
     T* d = O::d(L);
-    if (from_zero) cheb_first<T>(O::invd(Lc), b, d, x, T(1.0 / theta), n, s);
-    else {
-        cheb_step<T>(O::A(Lc), O::invd(Lc), x, b, d, other, T(0), T(1.0 / theta), s);
+    if (from_zero) {
+        cheb_first<T>(O::invd(Lc), b, d, (degree == 1 && out) ? out : x, T(1.0 / theta), n, s);
+        if (degree == 1 && out) return out;
+    } else {
+        T* dst = (degree == 1 && out) ? out : other;
+        cheb_step<T>(O::A(Lc), O::invd(Lc), x, b, d, dst, T(0), T(1.0 / theta), s);
+        if (dst == out) return out;
         std::swap(x, other);
     }
     for (int k = 1; k < degree; ++k) {
         const double rn = 1.0 / (2.0 * sigma - rho);
-        cheb_step<T>(O::A(Lc), O::invd(Lc), x, b, d, other, T(rn * rho), T(2.0 * rn / delta), s);
+        T* dst = (k + 1 == degree && out) ? out : other;
+        cheb_step<T>(O::A(Lc), O::invd(Lc), x, b, d, dst, T(rn * rho), T(2.0 * rn / delta), s);
         rho = rn;
+        if (dst == out) return out;
         std::swap(x, other);
     }
     return x;
 }
 
+// One V-cycle from level l for A_l x = b; the result is returned (a level buffer, or `out`
+// when given: the last smoothing step of level l writes there).
 template <typename T>
-static T* vcycle(Hierarchy& H, size_t l, const T* b, const fr_amg_opts& o, hipStream_t s) {
+static T* vcycle(Hierarchy& H, size_t l, const T* b, const fr_amg_opts& o, hipStream_t s, T* out = nullptr) {
     using O = LevelOps<T>;
     AmgLevel& L = *H.lv[l];
     const int64_t n = L.A.rows() * L.A.br;
     if (l + 1 == H.lv.size()) {
-        T* x = O::x0(L);
+        T* x = out ? out : O::x0(L);
         if (H.dense_inv.p) {
             if (n) k_dense_gemv<T><<<int(n), 256, 0, s>>>(n, H.dense_inv.p, b, x);
             FR_LAUNCH_CHECK();
             return x;
         }
         // large coarsest level: a longer smoothing sweep stands in for the exact solve
-        return chebyshev<T>(L, L, b, true, O::x0(L), O::x1(L), 4 * o.cheb_degree, o.cheb_ratio, s);
+        return chebyshev<T>(L, L, b, true, O::x0(L), O::x1(L), 4 * o.cheb_degree, o.cheb_ratio, s, out);
     }
     T* x = chebyshev<T>(L, L, b, true, O::x0(L), O::x1(L), o.cheb_degree, o.cheb_ratio, s);
     T* other = (x == O::x0(L)) ? O::x1(L) : O::x0(L);
@@ -1477,52 +1487,56 @@ static T* vcycle(Hierarchy& H, size_t l, const T* b, const fr_amg_opts& o, hipSt
     spmv<T>(O::R(L), O::r(L), O::b(Ln), s);
     T* xc = vcycle<T>(H, l + 1, O::b(Ln), o, s);
     spmv_add<T>(O::P(L), xc, x, s);
-    x = chebyshev<T>(L, L, b, false, x, other, o.cheb_degree, o.cheb_ratio, s);
-    return x;
+    return chebyshev<T>(L, L, b, false, x, other, o.cheb_degree, o.cheb_ratio, s, out);
 }
 
-static void precondition_block(DevAmg& amg, Hierarchy& H, const double* r, double* z, int64_t n, int blk,
-                               hipStream_t s);
-
-void amg_precondition(DevAmg& amg, const double* r, double* z, hipStream_t s) {
+// z = M^-1 r with M^-1 = diag(V-cycle(M_uu), V-cycle(M_phiphi)).  The phi block's cycle
+// runs on the side stream, the u block's on the caller's; the u cycle is enqueued first: its
+// level-0 sweeps keep the device busy while the host enqueues the phi cycle, whose small
+// levels then run beside the u work.  ZT is double, or float for the FP32 hierarchy (whose
+// result is FP32 anyway: keeping it so loses nothing).
+template <typename ZT>
+static void precondition(DevAmg& amg, const double* r, ZT* z, hipStream_t s) {
     DevSystem& sys = *amg.sys;
     const int64_t nu = sys.n_u;
-    const int64_t np = sys.n_solve - nu;
-    const int64_t nb[2] = {nu, np};
+    const int64_t nb[2] = {nu, sys.n_solve - nu};
     const int64_t off[2] = {0, nu};
     ensure_side(amg);
-    // fork: the phi block's V-cycle on the side stream, the u block's on the caller's
     FR_HIP(hipEventRecord(amg.ev_fork, s));
     FR_HIP(hipStreamWaitEvent(amg.side, amg.ev_fork, 0));
-    for (int blk = 1; blk >= 0; --blk) {
+    for (int blk = 0; blk <= 1; ++blk) {
         Hierarchy& H = amg.h[blk];
         const hipStream_t st = blk == 1 ? amg.side : s;
-        precondition_block(amg, H, r + off[blk], z + off[blk], nb[blk], blk, st);
+        ProfScope ps(blk == 0 ? "vcycle_u" : "vcycle_phi", st, 0.0);
+        if constexpr (std::is_same<ZT, float>::value) {
+            AmgLevel& L0 = *H.lv[0];
+            cast_f64_f32(r + off[blk], L0.fb.p, nb[blk], st);
+            vcycle<float>(H, 0, L0.fb.p, amg.opts, st, z + off[blk]);
+        } else {
+            vcycle<double>(H, 0, r + off[blk], amg.opts, st, z + off[blk]);
+        }
     }
-    // join
     FR_HIP(hipEventRecord(amg.ev_join, amg.side));
     FR_HIP(hipStreamWaitEvent(s, amg.ev_join, 0));
 }
 
-static void precondition_block(DevAmg& amg, Hierarchy& H, const double* r, double* z, int64_t n, int blk,
-                               hipStream_t s) {
-    const int64_t nb[2] = {n, n};
-    const int64_t off[2] = {0, 0};
-    {
-        ProfScope ps(blk == 0 ? "vcycle_u" : "vcycle_phi", s, 0.0);
-        if (amg.opts.precision == 32) {
-            AmgLevel& L0 = *H.lv[0];
-            cast_f64_f32(r + off[blk], L0.fb.p, nb[blk], s);
-            float* x = vcycle<float>(H, 0, L0.fb.p, amg.opts, s);
-            cast_f32_f64(x, z + off[blk], nb[blk], s);
-        } else {
-            double* x = vcycle<double>(H, 0, r + off[blk], amg.opts, s);
-            vec_copy(x, z + off[blk], nb[blk], s);
-        }
+void amg_precondition(DevAmg& amg, const double* r, double* z, hipStream_t s) {
+    if (amg.opts.precision == 32) {
+        // FP32 hierarchy, FP64 output
+        DevSystem& sys = *amg.sys;
+        amg.z32.reserve(size_t(std::max<int64_t>(1, sys.n_solve)), s);
+        precondition<float>(amg, r, amg.z32.p, s);
+        cast_f32_f64(amg.z32.p, z, sys.n_solve, s);
+    } else {
+        precondition<double>(amg, r, z, s);
     }
 }
 
-// Exports for inspection (host CSR of a level operator).
+void amg_precondition32(DevAmg& amg, const double* r, float* z, hipStream_t s) {
+    if (amg.opts.precision != 32) fail(FR_EINTERNAL, "amg_precondition32: the hierarchy is FP64");
+    precondition<float>(amg, r, z, s);
+}
+
 void amg_level_export(DevAmg& amg, int blk, int level, int which, int64_t& n_rows, int64_t& n_cols,
                       std::vector<int64_t>& rp, std::vector<int32_t>& ci, std::vector<double>& vv, hipStream_t s) {
     Hierarchy& H = amg.h[blk];

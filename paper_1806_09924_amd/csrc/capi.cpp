@@ -95,7 +95,7 @@ fr_amg_opts default_amg() {
     o.precision = 64;
     o.theta = 0.02;
     o.cheb_degree = 2;
-    o.cheb_ratio = 20.0;
+    o.cheb_ratio = 12.0;
     o.coarse_max = 96;
     o.max_levels = 10;
     o.reuse_u_block = 1;

@@ -20,6 +20,9 @@ namespace fr {
 namespace {
 
 constexpr int kE = 4;                 // elements per thread in the vector sweeps
+// the second Gram-Schmidt pass runs where the first cut |w| by more than this factor
+// (the orthogonality left is then at least 2^-10 u-level: about 1e-13)
+constexpr double kReorthEta = 1.0 / 1024.0;
 constexpr int kChunk = 256 * kE;      // elements per block
 constexpr int kMaxM = 120;            // largest restart length
 
@@ -29,109 +32,81 @@ struct Seg {
     const int32_t* inst;    // [nb] instance of the block
 };
 
-__device__ __forceinline__ void store_block_parts(double (*sh)[4], int nv, double* __restrict__ part) {
-    __syncthreads();
-    for (int v = threadIdx.x; v < nv; v += blockDim.x)
-        part[int64_t(v) * gridDim.x + blockIdx.x] = sh[v][0] + sh[v][1] + sh[v][2] + sh[v][3];
-}
-
-// part[v * nb + b] = sum over block b of V_v[i] w[i]
+// part[v * nb + g] = sum over segment g of V_v[i] w[i] (v < nv), and with `self` also
+// part[nv * nb + g] = sum of w[i]^2.  Segments of an instance whose flag in `need` is 0 are
+// skipped (need may be null); the grid may be smaller than the segment count.
 __global__ void __launch_bounds__(256) k_seg_dots(const double* __restrict__ V, int64_t n, int nv,
-                                                  const double* __restrict__ w, Seg sg, double* __restrict__ part) {
+                                                  const double* __restrict__ w, Seg sg, int nb,
+                                                  double* __restrict__ part, const int* __restrict__ need, int self) {
     __shared__ double sh[kMaxM + 8][4];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t s0 = sg.start[blockIdx.x];
-    const int len = sg.len[blockIdx.x];
-    double wv[kE];
-#pragma unroll
-    for (int e = 0; e < kE; ++e) {
-        const int o = threadIdx.x + 256 * e;
-        wv[e] = o < len ? w[s0 + o] : 0.0;
-    }
-    for (int v = 0; v < nv; ++v) {
-        const double* Vv = V + int64_t(v) * n + s0;
-        double acc = 0.0;
+    const int rows = nv + (self ? 1 : 0);
+    for (int g = blockIdx.x; g < nb; g += gridDim.x) {
+        if (need && !need[sg.inst[g]]) continue;
+        const int64_t s0 = sg.start[g];
+        const int len = sg.len[g];
+        double wv[kE];
 #pragma unroll
         for (int e = 0; e < kE; ++e) {
             const int o = threadIdx.x + 256 * e;
-            if (o < len) acc += Vv[o] * wv[e];
+            wv[e] = o < len ? w[s0 + o] : 0.0;
         }
-        acc = wave_sum(acc);
-        if (lane == 0) sh[v][wave] = acc;
+        for (int v = 0; v < nv; ++v) {
+            const double* Vv = V + int64_t(v) * n + s0;
+            double acc = 0.0;
+#pragma unroll
+            for (int e = 0; e < kE; ++e) {
+                const int o = threadIdx.x + 256 * e;
+                if (o < len) acc += Vv[o] * wv[e];
+            }
+            acc = wave_sum(acc);
+            if (lane == 0) sh[v][wave] = acc;
+        }
+        if (self) {
+            double acc = 0.0;
+#pragma unroll
+            for (int e = 0; e < kE; ++e) acc += wv[e] * wv[e];   // wv is 0 past len
+            acc = wave_sum(acc);
+            if (lane == 0) sh[nv][wave] = acc;
+        }
+        __syncthreads();
+        for (int v = threadIdx.x; v < rows; v += blockDim.x)
+            part[int64_t(v) * nb + g] = sh[v][0] + sh[v][1] + sh[v][2] + sh[v][3];
+        __syncthreads();
     }
-    store_block_parts(sh, nv, part);
 }
 
-// w -= sum_k c_inst[k] V_k over the block, then part[v * nb + b] = V_v . w (new w).
-__global__ void __launch_bounds__(256) k_seg_update_dot(const double* __restrict__ V, int64_t n, int nv,
-                                                        const double* __restrict__ c, int cstride,
-                                                        double* __restrict__ w, Seg sg, double* __restrict__ part) {
-    __shared__ double sh[kMaxM + 8][4];
-    __shared__ double cs[kMaxM + 8];
-    const int64_t s0 = sg.start[blockIdx.x];
-    const int len = sg.len[blockIdx.x];
-    const double* ci = c + int64_t(sg.inst[blockIdx.x]) * cstride;
-    for (int k = threadIdx.x; k < nv; k += blockDim.x) cs[k] = ci[k];
-    __syncthreads();
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    double wv[kE];
-#pragma unroll
-    for (int e = 0; e < kE; ++e) {
-        const int o = threadIdx.x + 256 * e;
-        wv[e] = o < len ? w[s0 + o] : 0.0;
-    }
-    for (int v = 0; v < nv; ++v) {
-        const double* Vv = V + int64_t(v) * n + s0;
-        const double cv = cs[v];
-#pragma unroll
-        for (int e = 0; e < kE; ++e) {
-            const int o = threadIdx.x + 256 * e;
-            if (o < len) wv[e] -= cv * Vv[o];
-        }
-    }
-#pragma unroll
-    for (int e = 0; e < kE; ++e) {
-        const int o = threadIdx.x + 256 * e;
-        if (o < len) w[s0 + o] = wv[e];
-    }
-    for (int v = 0; v < nv; ++v) {
-        const double* Vv = V + int64_t(v) * n + s0;
-        double acc = 0.0;
-#pragma unroll
-        for (int e = 0; e < kE; ++e) {
-            const int o = threadIdx.x + 256 * e;
-            if (o < len) acc += Vv[o] * wv[e];
-        }
-        acc = wave_sum(acc);
-        if (lane == 0) sh[v][wave] = acc;
-    }
-    store_block_parts(sh, nv, part);
-}
-
-// w -= sum_k c_inst[k] V_k; part[b] = sum of the new w^2 over the block
+// w -= sum_k c_inst[k] V_k; part[g] = sum of the new w^2 over segment g.  Segments of an
+// instance whose flag in `need` is 0 are skipped (need may be null); the grid may be
+// smaller than the segment count.
 __global__ void __launch_bounds__(256) k_seg_update_norm(const double* __restrict__ V, int64_t n, int nv,
                                                          const double* __restrict__ c, int cstride,
-                                                         double* __restrict__ w, Seg sg, double* __restrict__ part) {
+                                                         double* __restrict__ w, Seg sg, int nb,
+                                                         double* __restrict__ part, const int* __restrict__ need) {
     __shared__ double sh[16];
     __shared__ double cs[kMaxM + 8];
-    const int64_t s0 = sg.start[blockIdx.x];
-    const int len = sg.len[blockIdx.x];
-    const double* ci = c + int64_t(sg.inst[blockIdx.x]) * cstride;
-    for (int k = threadIdx.x; k < nv; k += blockDim.x) cs[k] = ci[k];
-    __syncthreads();
-    double acc = 0.0;
+    for (int g = blockIdx.x; g < nb; g += gridDim.x) {
+        if (need && !need[sg.inst[g]]) continue;
+        const int64_t s0 = sg.start[g];
+        const int len = sg.len[g];
+        const double* ci = c + int64_t(sg.inst[g]) * cstride;
+        for (int k = threadIdx.x; k < nv; k += blockDim.x) cs[k] = ci[k];
+        __syncthreads();
+        double acc = 0.0;
 #pragma unroll
-    for (int e = 0; e < kE; ++e) {
-        const int o = threadIdx.x + 256 * e;
-        if (o < len) {
-            double t = w[s0 + o];
-            for (int k = 0; k < nv; ++k) t -= cs[k] * V[int64_t(k) * n + s0 + o];
-            w[s0 + o] = t;
-            acc += t * t;
+        for (int e = 0; e < kE; ++e) {
+            const int o = threadIdx.x + 256 * e;
+            if (o < len) {
+                double t = w[s0 + o];
+                for (int k = 0; k < nv; ++k) t -= cs[k] * V[int64_t(k) * n + s0 + o];
+                w[s0 + o] = t;
+                acc += t * t;
+            }
         }
+        const double sum = block_sum(acc, sh);
+        if (threadIdx.x == 0) part[g] = sum;
+        __syncthreads();
     }
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 // r = F - r (r holds J x on entry, or nothing when from_zero: r = F); part[b] = sum r^2
@@ -167,8 +142,9 @@ __global__ void __launch_bounds__(256) k_seg_scale(const double* __restrict__ sr
     }
 }
 
-// x += sum_k y_inst[k] Z_k
-__global__ void __launch_bounds__(256) k_seg_combine(const double* __restrict__ Z, int64_t n, int nz,
+// x += sum_k y_inst[k] Z_k (Z FP64, or FP32 widened exactly)
+template <typename TZ>
+__global__ void __launch_bounds__(256) k_seg_combine(const TZ* __restrict__ Z, int64_t n, int nz,
                                                      const double* __restrict__ y, int ystride,
                                                      double* __restrict__ x, Seg sg) {
     __shared__ double ys[kMaxM + 8];
@@ -182,21 +158,32 @@ __global__ void __launch_bounds__(256) k_seg_combine(const double* __restrict__ 
         const int o = threadIdx.x + 256 * e;
         if (o < len) {
             double t = x[s0 + o];
-            for (int k = 0; k < nz; ++k) t += ys[k] * Z[int64_t(k) * n + s0 + o];
+            for (int k = 0; k < nz; ++k) t += ys[k] * double(Z[int64_t(k) * n + s0 + o]);
             x[s0 + o] = t;
         }
     }
 }
 
-// out[inst * stride + v] = sum of part[v * nb + b] over the blocks of the instance
-__global__ void __launch_bounds__(256) k_seg_reduce(const double* __restrict__ part, int nb,
-                                                    const int32_t* __restrict__ bptr, double* __restrict__ out,
-                                                    int stride) {
+// out[inst * stride + v] = sum of part[v * nb + b] over the blocks of the instance (only
+// for instances whose flag in `only` is set, when given).  Four independent partial sums
+// per thread keep several loads in flight; the order is fixed.
+constexpr int kReduceT = 512;
+__global__ void __launch_bounds__(kReduceT) k_seg_reduce(const double* __restrict__ part, int nb,
+                                                         const int32_t* __restrict__ bptr, double* __restrict__ out,
+                                                         int stride, const int* __restrict__ only = nullptr) {
     __shared__ double sh[16];
     const int v = blockIdx.x, inst = blockIdx.y;
-    double acc = 0.0;
-    for (int b = bptr[inst] + threadIdx.x; b < bptr[inst + 1]; b += blockDim.x) acc += part[int64_t(v) * nb + b];
-    const double s = block_sum(acc, sh);
+    if (only && !only[inst]) return;
+    const double* p = part + int64_t(v) * nb;
+    const int b1 = bptr[inst + 1];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    int b = bptr[inst] + threadIdx.x;
+    for (; b + 3 * kReduceT < b1; b += 4 * kReduceT) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] += p[b + q * kReduceT];
+    }
+    for (; b < b1; b += kReduceT) a[0] += p[b];
+    const double s = block_sum((a[0] + a[1]) + (a[2] + a[3]), sh);
     if (threadIdx.x == 0) out[int64_t(inst) * stride + v] = s;
 }
 
@@ -216,7 +203,23 @@ struct State {
     int* done;       // [ni] converged (or stopped) in this cycle
     int* jused;      // [ni] Krylov columns used by the instance in this cycle
     int* bad;        // [ni] non-finite value seen
+    int* need;       // [ni] the second Gram-Schmidt pass is applied in this iteration
 };
+
+// Classical Gram-Schmidt with the second pass only where it is needed: after one pass the
+// part of w left in the span of the basis is of the order of the unit roundoff times
+// |w_before| / |w_after|, so the pass is repeated where the norm dropped below eta times its
+// value before (h1[nv] holds |w_before|^2, nrm2 |w_after|^2).  h2 is cleared everywhere;
+// the second pass fills it where it runs.
+__global__ void k_reorth_decide(int ni, int m, int nv, State st, double eta2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ni) return;
+    double* h2 = st.h2 + int64_t(i) * (m + 2);
+    for (int k = 0; k <= nv; ++k) h2[k] = 0.0;
+    const double before = st.h1[int64_t(i) * (m + 2) + nv];
+    const double after = st.nrm2[i];
+    st.need[i] = (!st.done[i] && !(after >= eta2 * before)) ? 1 : 0;   // NaN -> second pass
+}
 
 // new cycle: g = (beta, 0, ...), scale = 1/beta, done when beta <= target
 __global__ void k_cycle_start(int ni, int m, State st) {
@@ -319,17 +322,23 @@ static void build_table(DevSystem& sys, DevKrylov& ws, hipStream_t s) {
     ws.n_inst = hm.n_inst;
 }
 
-// Doubles the basis capacity (up to the restart length), keeping V_0..V_j and Z_0..Z_{j-1}.
+// Doubles the basis capacity (up to the restart length), keeping V_0..V_j and Z_0..Z_{j-1}
+// (Z in the precision it is kept in).
+template <typename T>
+static void grow_keep(DBuf<T>& b, size_t keep, size_t count, hipStream_t s) {
+    if (!b.p) return;
+    DBuf<T> nb;
+    nb.alloc(count, s);
+    if (keep) FR_HIP(hipMemcpyAsync(nb.p, b.p, keep * sizeof(T), hipMemcpyDeviceToDevice, s));
+    b = std::move(nb);
+}
+
 static void grow_basis(DevKrylov& ws, int j, hipStream_t s) {
     const int cap = std::min(ws.m, std::max(j + 1, 2 * ws.cap));
     const size_t n = size_t(ws.n);
-    DBuf<double> V, Z;
-    V.alloc(size_t(cap + 1) * n, s);
-    Z.alloc(size_t(cap) * n, s);
-    FR_HIP(hipMemcpyAsync(V.p, ws.V.p, size_t(j + 1) * n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    if (j > 0) FR_HIP(hipMemcpyAsync(Z.p, ws.Z.p, size_t(j) * n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    ws.V = std::move(V);
-    ws.Z = std::move(Z);
+    grow_keep(ws.V, size_t(j + 1) * n, size_t(cap + 1) * n, s);
+    grow_keep(ws.Z, size_t(j) * n, size_t(cap) * n, s);
+    grow_keep(ws.Z32, size_t(j) * n, size_t(cap) * n, s);
     ws.cap = cap;
 }
 
@@ -338,19 +347,28 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
     const int64_t n = sys.n_solve;
     const int ni = sys.mesh->n_inst;
     const int m = std::max(1, std::min(o.restart, kMaxM));
-    if (ws.n != n || ws.m != m || ws.n_inst != ni) {
+    const bool z32 = amg.opts.precision == 32;
+    if (ws.n != n || ws.m != m || ws.n_inst != ni || ws.z32 != z32) {
         ws.n = n;
         ws.m = m;
-        // the bases start at kInitBasis vectors and grow with the iterations a cycle takes
+        ws.z32 = z32;
+        // the bases start at kInitBasis vectors and grow with the iterations a cycle takes;
+        // Z is kept in the preconditioner's precision
         ws.cap = std::min(m, kInitBasis);
         ws.V.alloc(size_t(ws.cap + 1) * size_t(n), s);
-        ws.Z.alloc(size_t(ws.cap) * size_t(n), s);
+        if (z32) {
+            ws.Z.release();
+            ws.Z32.alloc(size_t(ws.cap) * size_t(n), s);
+        } else {
+            ws.Z32.release();
+            ws.Z.alloc(size_t(ws.cap) * size_t(n), s);
+        }
         ws.w.alloc(size_t(n), s);
         build_table(sys, ws, s);
         ws.part.alloc(size_t(ws.nb) * (kMaxM + 2) + 64, s);
         const size_t per = size_t(2 * (m + 2) + 1 + (m + 1) * m + 2 * m + (m + 1) + m + 3);
         ws.state.alloc(per * size_t(ni), s);
-        ws.istate.alloc(size_t(3 * ni), s);
+        ws.istate.alloc(size_t(4 * ni), s);
     }
     const int M = ws.m;
     State st;
@@ -371,17 +389,18 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
         st.done = ws.istate.p;
         st.jused = ws.istate.p + ni;
         st.bad = ws.istate.p + 2 * ni;
+        st.need = ws.istate.p + 3 * ni;
     }
     const Seg sg{ws.seg_start.p, ws.seg_len.p, ws.seg_inst.p};
     const int nb = ws.nb;
     const int gi = int(ceil_div(ni, 64));
     double* part = ws.part.p;
-    FR_HIP(hipMemsetAsync(ws.istate.p, 0, size_t(3 * ni) * sizeof(int), s));
+    FR_HIP(hipMemsetAsync(ws.istate.p, 0, size_t(4 * ni) * sizeof(int), s));
 
     // ||F_i||, targets
     k_seg_resid<<<nb, 256, 0, s>>>(sys.F.p, ws.w.p, 1, sg, part);
     FR_LAUNCH_CHECK();
-    k_seg_reduce<<<dim3(1, ni), 256, 0, s>>>(part, nb, ws.seg_bptr.p, st.beta2, 1);
+    k_seg_reduce<<<dim3(1, ni), kReduceT, 0, s>>>(part, nb, ws.seg_bptr.p, st.beta2, 1);
     FR_LAUNCH_CHECK();
     std::vector<double> bn2 = download(st.beta2, size_t(ni), s);
     const size_t nis = static_cast<size_t>(ni);
@@ -402,7 +421,7 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
         if (!first) jspmv(sys, du, ws.w.p, s);
         k_seg_resid<<<nb, 256, 0, s>>>(sys.F.p, ws.w.p, first ? 1 : 0, sg, part);
         FR_LAUNCH_CHECK();
-        k_seg_reduce<<<dim3(1, ni), 256, 0, s>>>(part, nb, ws.seg_bptr.p, st.beta2, 1);
+        k_seg_reduce<<<dim3(1, ni), kReduceT, 0, s>>>(part, nb, ws.seg_bptr.p, st.beta2, 1);
         FR_LAUNCH_CHECK();
         first = false;
         k_cycle_start<<<gi, 64, 0, s>>>(ni, M, st);
@@ -422,33 +441,47 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
         for (; j < M && total < o.maxit; ++j) {
             if (j + 1 > ws.cap) grow_basis(ws, j, s);
             double* Vj = ws.V.p + int64_t(j) * n;
-            double* Zj = ws.Z.p + int64_t(j) * n;
-            amg_precondition(amg, Vj, Zj, s);
-            jspmv(sys, Zj, ws.w.p, s);
+            if (z32) {
+                float* Zj = ws.Z32.p + int64_t(j) * n;
+                amg_precondition32(amg, Vj, Zj, s);
+                jspmv(sys, Zj, ws.w.p, s);
+            } else {
+                double* Zj = ws.Z.p + int64_t(j) * n;
+                amg_precondition(amg, Vj, Zj, s);
+                jspmv(sys, Zj, ws.w.p, s);
+            }
             const int nv = j + 1;
             const double md_bytes = double(nv + 1) * double(n) * 8.0;
             const double up_bytes = double(nv + 2) * double(n) * 8.0;
+            const int gc = std::min(nb, 1024);   // grid of the conditional second pass
             {
                 ProfScope ps("gs_multidot", s, md_bytes);
-                k_seg_dots<<<nb, 256, 0, s>>>(ws.V.p, n, nv, ws.w.p, sg, part);
+                k_seg_dots<<<nb, 256, 0, s>>>(ws.V.p, n, nv, ws.w.p, sg, nb, part, nullptr, 1);
                 FR_LAUNCH_CHECK();
             }
-            k_seg_reduce<<<dim3(nv, ni), 256, 0, s>>>(part, nb, ws.seg_bptr.p, st.h1, M + 2);
-            FR_LAUNCH_CHECK();
-            {
-                ProfScope ps("gs_update_dot", s, up_bytes);
-                k_seg_update_dot<<<nb, 256, 0, s>>>(ws.V.p, n, nv, st.h1, M + 2, ws.w.p, sg, part);
-                FR_LAUNCH_CHECK();
-            }
-            k_seg_reduce<<<dim3(nv, ni), 256, 0, s>>>(part, nb, ws.seg_bptr.p, st.h2, M + 2);
+            k_seg_reduce<<<dim3(nv + 1, ni), kReduceT, 0, s>>>(part, nb, ws.seg_bptr.p, st.h1, M + 2);
             FR_LAUNCH_CHECK();
             {
                 ProfScope ps("gs_update", s, up_bytes);
-                k_seg_update_norm<<<nb, 256, 0, s>>>(ws.V.p, n, nv, st.h2, M + 2, ws.w.p, sg, part);
+                k_seg_update_norm<<<nb, 256, 0, s>>>(ws.V.p, n, nv, st.h1, M + 2, ws.w.p, sg, nb, part, nullptr);
                 FR_LAUNCH_CHECK();
             }
-            k_seg_reduce<<<dim3(1, ni), 256, 0, s>>>(part, nb, ws.seg_bptr.p, st.nrm2, 1);
+            k_seg_reduce<<<dim3(1, ni), kReduceT, 0, s>>>(part, nb, ws.seg_bptr.p, st.nrm2, 1);
             FR_LAUNCH_CHECK();
+            k_reorth_decide<<<gi, 64, 0, s>>>(ni, M, nv, st, kReorthEta * kReorthEta);
+            FR_LAUNCH_CHECK();
+            {
+                // the bytes depend on how many instances need the pass (a device decision)
+                ProfScope ps("gs_second_pass", s, 0.0);
+                k_seg_dots<<<gc, 256, 0, s>>>(ws.V.p, n, nv, ws.w.p, sg, nb, part, st.need, 0);
+                FR_LAUNCH_CHECK();
+                k_seg_reduce<<<dim3(nv, ni), kReduceT, 0, s>>>(part, nb, ws.seg_bptr.p, st.h2, M + 2, st.need);
+                FR_LAUNCH_CHECK();
+                k_seg_update_norm<<<gc, 256, 0, s>>>(ws.V.p, n, nv, st.h2, M + 2, ws.w.p, sg, nb, part, st.need);
+                FR_LAUNCH_CHECK();
+                k_seg_reduce<<<dim3(1, ni), kReduceT, 0, s>>>(part, nb, ws.seg_bptr.p, st.nrm2, 1, st.need);
+                FR_LAUNCH_CHECK();
+            }
             k_givens<<<gi, 64, 0, s>>>(ni, M, j, st);
             FR_LAUNCH_CHECK();
             k_seg_scale<<<nb, 256, 0, s>>>(ws.w.p, ws.V.p + int64_t(j + 1) * n, st.scale, sg);
@@ -468,7 +501,8 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
             jmax = std::max(jmax, ju[size_t(i)]);
         }
         if (jmax > 0) {
-            k_seg_combine<<<nb, 256, 0, s>>>(ws.Z.p, n, jmax, st.y, M, du, sg);
+            if (z32) k_seg_combine<float><<<nb, 256, 0, s>>>(ws.Z32.p, n, jmax, st.y, M, du, sg);
+            else k_seg_combine<double><<<nb, 256, 0, s>>>(ws.Z.p, n, jmax, st.y, M, du, sg);
             FR_LAUNCH_CHECK();
         }
         std::vector<int> bad = download(st.bad, size_t(ni), s);

@@ -158,19 +158,20 @@ __global__ void k_cheb_first(int64_t n, const T* __restrict__ invd, const T* __r
     x[i] = v;
 }
 
-// y = J x over the coupled system (u rows: M_uu; phi rows: M_phiu and M_phiphi).
-template <int D>
+// y = J x over the coupled system (u rows: M_uu; phi rows: M_phiu and M_phiphi).  x is FP64,
+// or FP32 (widened exactly on load); the arithmetic is FP64.
+template <int D, typename TX>
 __global__ void __launch_bounds__(256) k_jspmv(int64_t nf, int C, const int32_t* __restrict__ slice_ptr,
                                                const int32_t* __restrict__ col, const double* __restrict__ uu,
                                                const double* __restrict__ pu, const double* __restrict__ pp,
-                                               const double* __restrict__ x, double* __restrict__ y) {
+                                               const TX* __restrict__ x, double* __restrict__ y) {
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= nf) return;
     const int64_t s = r / C;
     const int lane = int(r - s * C);
     const int32_t p0 = slice_ptr[s];
     const int w = (slice_ptr[s + 1] - p0) / C;
-    const double* xp = x + D * nf;
+    const TX* xp = x + D * nf;
     double au[D], ap = 0.0;
 #pragma unroll
     for (int i = 0; i < D; ++i) au[i] = 0.0;
@@ -179,8 +180,8 @@ __global__ void __launch_bounds__(256) k_jspmv(int64_t nf, int C, const int32_t*
         const int64_t c = col[slot];
         double xu[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) xu[j] = x[c * D + j];
-        const double xph = xp[c];
+        for (int j = 0; j < D; ++j) xu[j] = double(x[c * D + j]);
+        const double xph = double(xp[c]);
         const double* vu = uu + slot * (D * D);
         const double* vp = pu + slot * D;
 #pragma unroll
@@ -516,18 +517,24 @@ void cheb_first(const T* invd, const T* b, T* d, T* x, T beta, int64_t n, hipStr
     FR_LAUNCH_CHECK();
 }
 
-void jspmv(const DevSystem& sys, const double* x, double* y, hipStream_t s) {
+template <typename TX>
+static void jspmv_t(const DevSystem& sys, const TX* x, double* y, hipStream_t s) {
     const SellStruct& S = *sys.Juu.S;
     const int g = nblk(S.n_rows, 256);
     const int D = sys.mesh->dim;
-    const double bytes = double(S.nnz) * ((D * D + D + 1) * 8 + 4) + double(S.n_rows) * (D + 1) * 8 * 2;
-    ProfScope ps(D == 2 ? "jspmv_d2" : "jspmv_d3", s, bytes);
-    if (sys.mesh->dim == 2)
-        k_jspmv<2><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, sys.Juu.val, sys.Jpu.val, sys.Jpp.val, x, y);
+    const double bytes = double(S.nnz) * ((D * D + D + 1) * 8 + 4) + double(S.n_rows) * (D + 1) * (sizeof(TX) + 8);
+    char name[32];
+    std::snprintf(name, sizeof(name), "jspmv_d%d%s", D, sizeof(TX) == 4 ? "_x32" : "");
+    ProfScope ps(name, s, bytes);
+    if (D == 2)
+        k_jspmv<2, TX><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, sys.Juu.val, sys.Jpu.val, sys.Jpp.val, x, y);
     else
-        k_jspmv<3><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, sys.Juu.val, sys.Jpu.val, sys.Jpp.val, x, y);
+        k_jspmv<3, TX><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, sys.Juu.val, sys.Jpu.val, sys.Jpp.val, x, y);
     FR_LAUNCH_CHECK();
 }
+
+void jspmv(const DevSystem& sys, const double* x, double* y, hipStream_t s) { jspmv_t<double>(sys, x, y, s); }
+void jspmv(const DevSystem& sys, const float* x, double* y, hipStream_t s) { jspmv_t<float>(sys, x, y, s); }
 
 void system_matvec(DevSystem& sys, const double* x, double* y) { jspmv(sys, x, y, sys.stream); }
 

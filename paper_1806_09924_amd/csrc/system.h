@@ -122,8 +122,9 @@ void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d
                T alpha, T beta, hipStream_t s);
 template <typename T>
 void cheb_first(const T* invd, const T* b, T* d, T* x, T beta, int64_t n, hipStream_t s);
-// fused J-SpMV over the three blocks: y = J x (solve order)
+// fused J-SpMV over the three blocks: y = J x (solve order); x may be FP32 (exactly widened)
 void jspmv(const DevSystem& sys, const double* x, double* y, hipStream_t s);
+void jspmv(const DevSystem& sys, const float* x, double* y, hipStream_t s);
 
 // ---- AMG (amg.hip) ----------------------------------------------------------------------
 struct AmgLevel {
@@ -155,6 +156,7 @@ struct DevAmg {
     // the phi V-cycle runs on a second stream (default priority) beside the u V-cycle
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    DBuf<float> z32;                             // FP32 result staging of amg_precondition
     ~DevAmg() {
         // the phase-field hierarchy's buffers are freed on the side stream: before it goes
         for (auto& H : h) {
@@ -170,6 +172,8 @@ struct DevAmg {
 
 void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s);
 void amg_precondition(DevAmg& amg, const double* r, double* z, hipStream_t s);
+// FP32 hierarchy only: z (FP32) = M^-1 r
+void amg_precondition32(DevAmg& amg, const double* r, float* z, hipStream_t s);
 void amg_level_export(DevAmg& amg, int blk, int level, int which, int64_t& n_rows, int64_t& n_cols,
                       std::vector<int64_t>& rp, std::vector<int32_t>& ci, std::vector<double>& vv, hipStream_t s);
 void amg_info(DevAmg& amg, int blk, int level, int& n_levels, int64_t& rows, int& bsize, int64_t& nnzb,
@@ -182,7 +186,9 @@ struct DevKrylov {
     int64_t n = 0;
     int m = 0, n_inst = 0, nb = 0;
     int cap = 0;                                 // vectors held in Z (V holds cap + 1)
+    bool z32 = false;                            // Z kept in FP32 (FP32 preconditioner)
     DBuf<double> V, Z, w, part, state;
+    DBuf<float> Z32;                             // the Z basis when the preconditioner is FP32
     DBuf<int> istate;
     DBuf<int64_t> seg_start;                     // segmented-sweep block table
     DBuf<int32_t> seg_len, seg_inst, seg_bptr;
