@@ -46,10 +46,33 @@ def log(msg):
 PROFILE_OF = {"cheb_f64_b2": "cheb_f64_b2_sneddon2d_2048.md"}
 
 
+def kernel_digest(src_text, kernel):
+    """sha256 of a kernel's template definition together with every __device__ helper of the
+    same file that it reaches (so a change in a helper counts as a change of the kernel)."""
+    import hashlib
+    import re
+    m = re.search(r"(template <[^\n]*>\n__global__ void __launch_bounds__\(\d+\) " + kernel + r"\(.*?\n\}\n)",
+                  src_text, re.S)
+    if not m:
+        return None
+    helpers = {}
+    for d in re.finditer(r"((?:template <[^\n]*>\n)?__device__ __forceinline__ [^\n(]*?(\w+)\(.*?\n\}\n)", src_text,
+                         re.S):
+        helpers[d.group(2)] = d.group(1)
+    seen, todo, text = set(), [m.group(1)], m.group(1)
+    while todo:
+        body = todo.pop()
+        for name, h in helpers.items():
+            if name not in seen and re.search(r"\b" + name + r"\b", body):
+                seen.add(name)
+                todo.append(h)
+    text += "".join(helpers[n] for n in sorted(seen))
+    return hashlib.sha256(text.encode()).hexdigest()
+
+
 def counted_traffic(kernel):
     """HBM bytes per launch from the committed rocprofv3 PMC summary of this kernel, or None
     when there is none or the kernel's source changed since the counters were taken."""
-    import hashlib
     import re
     name = PROFILE_OF.get(kernel)
     if not name:
@@ -65,13 +88,8 @@ def counted_traffic(kernel):
     src = os.path.join(ROOT, h.group(1))
     if not os.path.exists(src):
         return None
-    # the kernel's own template definition, up to its closing brace at column 0
-    m = re.search(r"(template <[^\n]*>\n__global__ void __launch_bounds__\(\d+\) " + h.group(2) + r"\(.*?\n\}\n)",
-                  open(src).read(), re.S)
-    if not m:
-        return None
-    cur = hashlib.sha256(m.group(1).encode()).hexdigest()
-    return float(t.group(1)) if cur.startswith(h.group(3)) else None
+    cur = kernel_digest(open(src).read(), h.group(2))
+    return float(t.group(1)) if cur and cur.startswith(h.group(3)) else None
 
 
 def cpu_baseline(n_cpu, L_full, n_full, iters_per_newton):

@@ -1510,7 +1510,7 @@ static void precondition(DevAmg& amg, const double* r, ZT* z, hipStream_t s) {
         ProfScope ps(blk == 0 ? "vcycle_u" : "vcycle_phi", st, 0.0);
         if constexpr (std::is_same<ZT, float>::value) {
             AmgLevel& L0 = *H.lv[0];
-            cast_f64_f32(r + off[blk], L0.fb.p, nb[blk], st);
+            if (r) cast_f64_f32(r + off[blk], L0.fb.p, nb[blk], st);   // else staged by the caller
             vcycle<float>(H, 0, L0.fb.p, amg.opts, st, z + off[blk]);
         } else {
             vcycle<double>(H, 0, r + off[blk], amg.opts, st, z + off[blk]);
@@ -1535,6 +1535,11 @@ void amg_precondition(DevAmg& amg, const double* r, double* z, hipStream_t s) {
 void amg_precondition32(DevAmg& amg, const double* r, float* z, hipStream_t s) {
     if (amg.opts.precision != 32) fail(FR_EINTERNAL, "amg_precondition32: the hierarchy is FP64");
     precondition<float>(amg, r, z, s);
+}
+
+float* amg_input32(DevAmg& amg, int blk) {
+    if (amg.opts.precision != 32 || amg.h[blk].lv.empty()) fail(FR_EINTERNAL, "amg_input32: no FP32 hierarchy");
+    return amg.h[blk].lv[0]->fb.p;
 }
 
 void amg_level_export(DevAmg& amg, int blk, int level, int which, int64_t& n_rows, int64_t& n_cols,

@@ -129,16 +129,26 @@ __global__ void __launch_bounds__(256) k_seg_resid(const double* __restrict__ F,
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// dst = src * scale[inst]
+// dst = src * scale[inst]; with an FP32 preconditioner also its input: the same values in
+// FP32, u part (solve index < n_u) to f_u, phi part to f_p.
 __global__ void __launch_bounds__(256) k_seg_scale(const double* __restrict__ src, double* __restrict__ dst,
-                                                   const double* __restrict__ scale, Seg sg) {
+                                                   const double* __restrict__ scale, Seg sg, float* __restrict__ f_u,
+                                                   float* __restrict__ f_p, int64_t n_u) {
     const int64_t s0 = sg.start[blockIdx.x];
     const int len = sg.len[blockIdx.x];
     const double a = scale[sg.inst[blockIdx.x]];
 #pragma unroll
     for (int e = 0; e < kE; ++e) {
         const int o = threadIdx.x + 256 * e;
-        if (o < len) dst[s0 + o] = a * src[s0 + o];
+        if (o < len) {
+            const int64_t i = s0 + o;
+            const double v = a * src[i];
+            dst[i] = v;
+            if (f_u) {
+                if (i < n_u) f_u[i] = float(v);
+                else f_p[i - n_u] = float(v);
+            }
+        }
     }
 }
 
@@ -392,6 +402,10 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
         st.need = ws.istate.p + 3 * ni;
     }
     const Seg sg{ws.seg_start.p, ws.seg_len.p, ws.seg_inst.p};
+    // FP32 preconditioner: the basis vectors are written in FP32 too, straight into the
+    // hierarchies' level-0 right-hand sides
+    float* f_u = z32 ? amg_input32(amg, 0) : nullptr;
+    float* f_p = z32 ? amg_input32(amg, 1) : nullptr;
     const int nb = ws.nb;
     const int gi = int(ceil_div(ni, 64));
     double* part = ws.part.p;
@@ -435,7 +449,7 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
             all_done = all_done && dn[size_t(i)];
         }
         if (all_done || total >= o.maxit) break;
-        k_seg_scale<<<nb, 256, 0, s>>>(ws.w.p, ws.V.p, st.scale, sg);
+        k_seg_scale<<<nb, 256, 0, s>>>(ws.w.p, ws.V.p, st.scale, sg, f_u, f_p, sys.n_u);
         FR_LAUNCH_CHECK();
         int j = 0;
         for (; j < M && total < o.maxit; ++j) {
@@ -443,7 +457,7 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
             double* Vj = ws.V.p + int64_t(j) * n;
             if (z32) {
                 float* Zj = ws.Z32.p + int64_t(j) * n;
-                amg_precondition32(amg, Vj, Zj, s);
+                amg_precondition32(amg, nullptr, Zj, s);   // input staged by k_seg_scale
                 jspmv(sys, Zj, ws.w.p, s);
             } else {
                 double* Zj = ws.Z.p + int64_t(j) * n;
@@ -484,7 +498,7 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
             }
             k_givens<<<gi, 64, 0, s>>>(ni, M, j, st);
             FR_LAUNCH_CHECK();
-            k_seg_scale<<<nb, 256, 0, s>>>(ws.w.p, ws.V.p + int64_t(j + 1) * n, st.scale, sg);
+            k_seg_scale<<<nb, 256, 0, s>>>(ws.w.p, ws.V.p + int64_t(j + 1) * n, st.scale, sg, f_u, f_p, sys.n_u);
             FR_LAUNCH_CHECK();
             ++total;
             std::vector<int> d2 = download(st.done, size_t(ni), s);

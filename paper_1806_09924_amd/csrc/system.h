@@ -172,8 +172,10 @@ struct DevAmg {
 
 void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s);
 void amg_precondition(DevAmg& amg, const double* r, double* z, hipStream_t s);
-// FP32 hierarchy only: z (FP32) = M^-1 r
+// FP32 hierarchy only: z (FP32) = M^-1 r.  r == nullptr: the input is already in the
+// level-0 right-hand sides, amg_input32(amg, 0) (u part) and amg_input32(amg, 1) (phi part).
 void amg_precondition32(DevAmg& amg, const double* r, float* z, hipStream_t s);
+float* amg_input32(DevAmg& amg, int blk);
 void amg_level_export(DevAmg& amg, int blk, int level, int which, int64_t& n_rows, int64_t& n_cols,
                       std::vector<int64_t>& rp, std::vector<int32_t>& ci, std::vector<double>& vv, hipStream_t s);
 void amg_info(DevAmg& amg, int blk, int level, int& n_levels, int64_t& rows, int& bsize, int64_t& nnzb,
