@@ -581,34 +581,35 @@ __global__ void k_transpose_fill(SellV P, const double* __restrict__ pv, SellV R
 
 // One wave per row: order the row's (unique) columns by rank and move the blocks from the
 // unsorted staging arrays into place; padding repeats the smallest column with zero blocks.
+// Rows of up to kRankMax entries rank against a copy of their keys in LDS, longer ones
+// against the staging array itself.
 constexpr int kRankMax = 1024;
 
 template <int BB>
 __global__ void __launch_bounds__(256) k_rank_rows(SellV Rm, const int32_t* __restrict__ tcol,
                                                    const double* __restrict__ tval, int32_t* __restrict__ col,
-                                                   double* __restrict__ val, int* __restrict__ overflow) {
+                                                   double* __restrict__ val) {
     __shared__ int32_t keys[kWavesPerBlock][kRankMax];
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t r = int64_t(blockIdx.x) * kWavesPerBlock + w;
     if (r >= Rm.n_rows) return;
     const int n = Rm.len[r];
-    if (n > kRankMax) {
-        if (lane == 0) atomicOr(overflow, 1);
-        return;
-    }
+    const bool in_lds = n <= kRankMax;
+    auto key = [&](int j) -> int32_t { return in_lds ? keys[w][j] : tcol[sslot(Rm.sp, Rm.C, r, j)]; };
     int32_t mn = 0x7fffffff;
     for (int e = lane; e < n; e += kWave) {
-        keys[w][e] = tcol[sslot(Rm.sp, Rm.C, r, e)];
-        mn = min(mn, keys[w][e]);
+        const int32_t v = tcol[sslot(Rm.sp, Rm.C, r, e)];
+        if (in_lds) keys[w][e] = v;
+        mn = min(mn, v);
     }
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) mn = min(mn, __shfl_xor(mn, o));
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
     for (int e = lane; e < n; e += kWave) {
-        const int32_t v = keys[w][e];
+        const int32_t v = key(e);
         int rk = 0;
-        for (int j = 0; j < n; ++j) rk += keys[w][j] < v;
+        for (int j = 0; j < n; ++j) rk += key(j) < v;
         const int64_t src = sslot(Rm.sp, Rm.C, r, e), dst = sslot(Rm.sp, Rm.C, r, rk);
         col[dst] = v;
         for (int b = 0; b < BB; ++b) val[dst * BB + b] = tval[src * BB + b];
@@ -952,7 +953,7 @@ void transpose_values(const BMat<double>& P, BMat<double>& Rm, hipStream_t s) {
     fail(FR_EINTERNAL, "transpose: unsupported block shape");
 }
 
-BMat<double> transpose(const BMat<double>& P, int* errs, hipStream_t s) {
+BMat<double> transpose(const BMat<double>& P, hipStream_t s) {
     BMat<double> Rm;
     Rm.br = P.bc;
     Rm.bc = P.br;
@@ -976,7 +977,7 @@ BMat<double> transpose(const BMat<double>& P, int* errs, hipStream_t s) {
     if (P.br == BR_ && P.bc == BC_) {                                                                           \
         k_transpose_fill<BR_, BC_><<<g, 256, 0, s>>>(sv(*P.S), P.val, sv(*Rm.S), fillc.p, tcol.p, tval.p);      \
         FR_LAUNCH_CHECK();                                                                                      \
-        k_rank_rows<BR_ * BC_><<<gr, 256, 0, s>>>(sv(*Rm.S), tcol.p, tval.p, Rm.S->col, Rm.val, errs);          \
+        k_rank_rows<BR_ * BC_><<<gr, 256, 0, s>>>(sv(*Rm.S), tcol.p, tval.p, Rm.S->col, Rm.val);                \
         FR_LAUNCH_CHECK();                                                                                      \
         return Rm;                                                                                              \
     }
@@ -1218,7 +1219,7 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
                             const fr_amg_opts& o, bool keep, hipStream_t s) {
     H.lv.clear();
     H.refreshable = keep;
-    DBuf<int> errs;    // capacity overflows of the SpGEMM fills and transposes, read once at the end
+    DBuf<int> errs;    // capacity overflows of the SpGEMM fills, read once at the end
     errs.alloc(1, s);
     errs.zero(s);
     DBuf<double> Bf;   // near-null space of the current level (levels >= 1)
@@ -1260,7 +1261,7 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
                 ProfScope ps("setup_smooth_p", s, 0.0);
                 const double omega = 4.0 / (3.0 * L->lmax);
                 L->P = spgemm<1>(L->A, Pt, L->invd.p, omega, errs.p, s);
-                L->R = transpose(L->P, errs.p, s);
+                L->R = transpose(L->P, s);
             }
             {
                 ProfScope ps("setup_rap", s, 0.0);
@@ -1288,7 +1289,7 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
         if (o.precision == 32) make_f32(*H.lv[l], l + 1 == H.lv.size(), s);
         alloc_vectors(*H.lv[l], o.precision, s);
     }
-    if (download1(errs.p, s)) fail(FR_EINTERNAL, "amg setup: a row exceeded the SpGEMM / transpose LDS capacity");
+    if (download1(errs.p, s)) fail(FR_EINTERNAL, "amg setup: a row exceeded the SpGEMM LDS capacity");
 }
 
 // Same aggregates, tentative prolongators and sparsity; new values from the level-0 matrix

@@ -7,7 +7,9 @@
 #include <array>
 #include <cmath>
 #include <string>
-#include <unordered_set>
+#include <cstdint>
+#include <exception>
+#include <thread>
 
 #include "common.h"
 
@@ -19,15 +21,114 @@ struct Leaf {
     int64_t o[3];   // lower corner in finest-lattice units
 };
 
-struct LeafKey {
-    size_t operator()(const std::pair<int, std::array<int64_t, 3>>& k) const {
-        uint64_t h = 1469598103934665603ull ^ static_cast<uint64_t>(k.first);
-        for (int i = 0; i < 3; ++i) h = (h ^ static_cast<uint64_t>(k.second[i])) * 1099511628211ull;
-        return static_cast<size_t>(h);
+// Open-addressing hash set of 64-bit keys (linear probing, load <= 1/2).
+class KeySet {
+public:
+    explicit KeySet(size_t expect = 16) { rehash(std::max<size_t>(16, 2 * expect)); }
+    bool insert(uint64_t k) {
+        if (2 * (n_ + 1) > tab_.size()) rehash(2 * tab_.size());
+        return put(k);
     }
+    bool contains(uint64_t k) const {
+        for (size_t i = mix(k) & mask_;; i = (i + 1) & mask_) {
+            if (tab_[i] == kEmpty) return false;
+            if (tab_[i] == k) return true;
+        }
+    }
+    template <typename F>
+    void for_each(F f) const {
+        for (uint64_t v : tab_)
+            if (v != kEmpty) f(v);
+    }
+    size_t size() const { return n_; }
+
+private:
+    static constexpr uint64_t kEmpty = ~uint64_t(0);
+    static size_t mix(uint64_t k) {
+        k ^= k >> 33;
+        k *= 0xff51afd7ed558ccdull;
+        k ^= k >> 33;
+        return size_t(k);
+    }
+    bool put(uint64_t k) {
+        for (size_t i = mix(k) & mask_;; i = (i + 1) & mask_) {
+            if (tab_[i] == kEmpty) {
+                tab_[i] = k;
+                ++n_;
+                return true;
+            }
+            if (tab_[i] == k) return false;
+        }
+    }
+    void rehash(size_t cap) {
+        size_t c = 16;
+        while (c < cap) c <<= 1;
+        std::vector<uint64_t> old;
+        old.swap(tab_);
+        tab_.assign(c, kEmpty);
+        mask_ = c - 1;
+        n_ = 0;
+        for (uint64_t v : old)
+            if (v != kEmpty) put(v);
+    }
+    std::vector<uint64_t> tab_;
+    size_t mask_ = 0, n_ = 0;
 };
 
-using LeafSet = std::unordered_set<std::pair<int, std::array<int64_t, 3>>, LeafKey>;
+// lattice origin (each coordinate < 2^21) packed into one key
+inline uint64_t pack(const int64_t* o) {
+    return uint64_t(o[0]) | (uint64_t(o[1]) << 21) | (uint64_t(o[2]) << 42);
+}
+inline void unpack(uint64_t k, int64_t* o) {
+    o[0] = int64_t(k & 0x1FFFFF);
+    o[1] = int64_t((k >> 21) & 0x1FFFFF);
+    o[2] = int64_t((k >> 42) & 0x1FFFFF);
+}
+
+// Stable LSD radix sort of (key, value) pairs by key, 16-bit digits, as many passes as the
+// largest key needs.
+void radix_sort_pairs(std::vector<uint64_t>& key, std::vector<uint32_t>& val) {
+    const size_t n = key.size();
+    uint64_t mx = 0;
+    for (uint64_t k : key) mx = std::max(mx, k);
+    int bits = 0;
+    while (bits < 64 && (mx >> bits) != 0) ++bits;
+    std::vector<uint64_t> k2(n);
+    std::vector<uint32_t> v2(n);
+    std::vector<size_t> cnt(65537);
+    for (int shift = 0; shift < bits; shift += 16) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (size_t i = 0; i < n; ++i) cnt[((key[i] >> shift) & 0xFFFF) + 1]++;
+        for (size_t d = 0; d < 65536; ++d) cnt[d + 1] += cnt[d];
+        for (size_t i = 0; i < n; ++i) {
+            const size_t pos = cnt[(key[i] >> shift) & 0xFFFF]++;
+            k2[pos] = key[i];
+            v2[pos] = val[i];
+        }
+        key.swap(k2);
+        val.swap(v2);
+    }
+}
+
+// Runs f(begin, end, t) over [0, n) split into contiguous chunks, one per host thread.
+template <typename F>
+void parallel_ranges(int64_t n, F f) {
+    const int64_t hw = std::max<int64_t>(1, std::thread::hardware_concurrency());
+    const int64_t T = std::max<int64_t>(1, std::min<int64_t>({hw, 16, n / 4096 + 1}));
+    std::vector<std::thread> th;
+    std::vector<std::exception_ptr> err(static_cast<size_t>(T));
+    for (int64_t t = 0; t < T; ++t)
+        th.emplace_back([&, t]() {
+            try {
+                f(n * t / T, n * (t + 1) / T, int(t));
+            } catch (...) {
+                err[size_t(t)] = std::current_exception();
+            }
+        });
+    for (auto& x : th) x.join();
+    for (auto& e : err)
+        if (e) std::rethrow_exception(e);
+}
 
 // Distance from the box [a, b] to the crack (segment in 2d, disk in 3d).
 double crack_distance(const fr_mesh_desc& d, const double* a, const double* b) {
@@ -88,92 +189,97 @@ HostMesh build_mesh(const fr_mesh_desc& d) {
             for (int64_t j = 0; j < n1; ++j)
                 for (int64_t i = 0; i < n0; ++i) leaves.push_back(Leaf{0, {i, j, k}});
     } else {
-        // refine towards the crack
-        LeafSet set;
-        std::vector<Leaf> work;
+        // refined[l]: cells of level l that are split.  First the rule (split while the
+        // level is below L and the box is within refine_radius of the crack), then the 2:1
+        // closure level by level from the finest: every cell of level l needs the level-(l-1)
+        // cell around the centre of each same-size neighbour, so the level-(l-2) cell there
+        // is split (with its ancestors).  Cells of level l are never added while level l is
+        // scanned, so one sweep from the finest level down is the closure.
+        for (int k = 0; k < dim; ++k)
+            if (ext[k] >= (int64_t(1) << 21)) fail(FR_EINVAL, "mesh: more than 2^21 finest cells per axis");
+        std::vector<KeySet> refined(static_cast<size_t>(L));
         int64_t n0 = d.base[0], n1 = d.base[1], n2 = dim == 3 ? d.base[2] : 1;
+        struct Item { int level; int64_t o[3]; };
+        std::vector<Item> work;
         for (int64_t k = 0; k < n2; ++k)
             for (int64_t j = 0; j < n1; ++j)
-                for (int64_t i = 0; i < n0; ++i) work.push_back(Leaf{0, {i * S, j * S, k * S}});
-        auto box = [&](const Leaf& c, double* a, double* b) {
-            int64_t s = S >> c.level;
+                for (int64_t i = 0; i < n0; ++i) work.push_back(Item{0, {i * S, j * S, k * S}});
+        while (!work.empty()) {
+            Item c = work.back();
+            work.pop_back();
+            const int64_t s = S >> c.level;
+            double a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
             for (int q = 0; q < dim; ++q) {
                 a[q] = d.lo[q] + double(c.o[q]) * m.h_min;
                 b[q] = d.lo[q] + double(c.o[q] + s) * m.h_min;
             }
-        };
-        std::vector<Leaf> out;
-        while (!work.empty()) {
-            Leaf c = work.back();
-            work.pop_back();
-            double a[3], b[3];
-            box(c, a, b);
             if (c.level < L && crack_distance(d, a, b) <= d.refine_radius) {
-                int64_t s = (S >> c.level) / 2;
+                refined[size_t(c.level)].insert(pack(c.o));
                 for (int ch = 0; ch < (1 << dim); ++ch) {
-                    Leaf n{c.level + 1, {c.o[0], c.o[1], c.o[2]}};
-                    for (int q = 0; q < dim; ++q) n.o[q] += ((ch >> q) & 1) * s;
+                    Item n{c.level + 1, {c.o[0], c.o[1], c.o[2]}};
+                    for (int q = 0; q < dim; ++q) n.o[q] += ((ch >> q) & 1) * (s / 2);
                     work.push_back(n);
                 }
-            } else {
-                out.push_back(c);
             }
         }
-        for (auto& c : out) set.insert({c.level, {c.o[0], c.o[1], c.o[2]}});
-        // 2:1 balance across faces, edges and corners
-        auto find_leaf = [&](const int64_t* q, int max_level, int& lev, std::array<int64_t, 3>& org) -> bool {
-            for (int l = 0; l <= max_level; ++l) {
-                int64_t s = S >> l;
-                std::array<int64_t, 3> o{0, 0, 0};
-                for (int k = 0; k < dim; ++k) o[k] = (q[k] / s) * s;
-                if (set.count({l, o})) { lev = l; org = o; return true; }
+        // split the level-lv cell containing lattice point q, and its ancestors
+        auto split_around = [&](const int64_t* q, int lv) {
+            for (int l = lv; l >= 0; --l) {
+                const int64_t sz = S >> l;
+                int64_t o[3] = {0, 0, 0};
+                for (int k = 0; k < dim; ++k) o[k] = (q[k] / sz) * sz;
+                if (!refined[size_t(l)].insert(pack(o))) break;
             }
-            return false;
         };
-        bool changed = true;
-        while (changed) {
-            changed = false;
-            std::vector<std::pair<int, std::array<int64_t, 3>>> to_split;
-            for (const auto& e : set) {
-                int lev = e.first;
-                if (lev < 2) continue;
-                int64_t s = S >> lev;
-                int nd = 1;
-                for (int k = 0; k < dim; ++k) nd *= 3;
-                for (int dir = 0; dir < nd; ++dir) {
-                    int t = dir;
-                    int64_t q[3] = {0, 0, 0};
-                    bool self = true, inside = true;
-                    for (int k = 0; k < dim; ++k) {
-                        int o = t % 3 - 1;
-                        t /= 3;
-                        if (o != 0) self = false;
-                        // a lattice point strictly inside the neighbouring cell of the same size
-                        q[k] = e.second[k] + o * s + s / 2;
-                        if (s == 1) q[k] = e.second[k] + o * s;   // finest: use its corner
-                        if (q[k] < 0 || q[k] >= ext[k]) inside = false;
-                    }
-                    if (self || !inside) continue;
-                    int nl;
-                    std::array<int64_t, 3> no;
-                    if (find_leaf(q, lev, nl, no) && nl < lev - 1) to_split.push_back({nl, no});
-                }
-            }
-            std::sort(to_split.begin(), to_split.end());
-            to_split.erase(std::unique(to_split.begin(), to_split.end()), to_split.end());
-            for (auto& c : to_split) {
-                if (!set.erase(c)) continue;
-                int64_t s = (S >> c.first) / 2;
+        int nd = 1;
+        for (int k = 0; k < dim; ++k) nd *= 3;
+        for (int l = L; l >= 2; --l) {
+            const int64_t s = S >> l;
+            std::vector<uint64_t> parents;
+            parents.reserve(refined[size_t(l - 1)].size());
+            refined[size_t(l - 1)].for_each([&](uint64_t k) { parents.push_back(k); });
+            for (uint64_t pk : parents) {
+                int64_t po[3];
+                unpack(pk, po);
                 for (int ch = 0; ch < (1 << dim); ++ch) {
-                    std::array<int64_t, 3> o = c.second;
+                    int64_t o[3] = {po[0], po[1], po[2]};
                     for (int q = 0; q < dim; ++q) o[q] += ((ch >> q) & 1) * s;
-                    set.insert({c.first + 1, o});
+                    for (int dir = 0; dir < nd; ++dir) {
+                        int t = dir;
+                        int64_t q[3] = {0, 0, 0};
+                        bool self = true, inside = true;
+                        for (int k = 0; k < dim; ++k) {
+                            const int off = t % 3 - 1;
+                            t /= 3;
+                            if (off != 0) self = false;
+                            q[k] = o[k] + off * s + s / 2;   // inside the same-size neighbour
+                            if (q[k] < 0 || q[k] >= ext[k]) inside = false;
+                        }
+                        if (self || !inside) continue;
+                        split_around(q, l - 2);
+                    }
                 }
-                changed = true;
             }
         }
-        leaves.reserve(set.size());
-        for (auto& e : set) leaves.push_back(Leaf{e.first, {e.second[0], e.second[1], e.second[2]}});
+        // leaves: the cells of every level that are not split
+        for (int64_t k = 0; k < n2; ++k)
+            for (int64_t j = 0; j < n1; ++j)
+                for (int64_t i = 0; i < n0; ++i) {
+                    int64_t o[3] = {i * S, j * S, k * S};
+                    if (L == 0 || !refined[0].contains(pack(o))) leaves.push_back(Leaf{0, {o[0], o[1], o[2]}});
+                }
+        for (int l = 1; l <= L; ++l) {
+            const int64_t s = S >> l;
+            refined[size_t(l - 1)].for_each([&](uint64_t pk) {
+                int64_t po[3];
+                unpack(pk, po);
+                for (int ch = 0; ch < (1 << dim); ++ch) {
+                    int64_t o[3] = {po[0], po[1], po[2]};
+                    for (int q = 0; q < dim; ++q) o[q] += ((ch >> q) & 1) * s;
+                    if (l == L || !refined[size_t(l)].contains(pack(o))) leaves.push_back(Leaf{l, {o[0], o[1], o[2]}});
+                }
+            });
+        }
         // deterministic cell order: by lower corner (z, y, x), then level
         std::sort(leaves.begin(), leaves.end(), [&](const Leaf& a, const Leaf& b) {
             for (int k = dim - 1; k >= 0; --k)
@@ -218,19 +324,31 @@ HostMesh build_mesh(const fr_mesh_desc& d) {
             m.cell_h[size_t(c)] = m.h_min;
         }
     } else {
-        std::vector<int64_t> keys;
-        keys.reserve(size_t(m.n_cells) * nv);
-        for (const Leaf& lf : leaves) {
-            int64_t s = S >> lf.level;
+        // vertex keys of every cell, sorted with their positions: the distinct keys are the
+        // nodes (in key order), and each position learns its node id in the same sweep
+        const size_t nk = size_t(m.n_cells) * size_t(nv);
+        if (nk >= (size_t(1) << 32)) fail(FR_EINVAL, "mesh: too many cell vertices");
+        std::vector<uint64_t> skey(nk);
+        std::vector<uint32_t> spos(nk);
+        for (int64_t c = 0; c < m.n_cells; ++c) {
+            const Leaf& lf = leaves[size_t(c)];
+            const int64_t s = S >> lf.level;
             for (int a = 0; a < nv; ++a) {
                 int64_t q[3] = {lf.o[0], lf.o[1], lf.o[2]};
                 for (int k = 0; k < dim; ++k) q[k] += ((a >> k) & 1) * s;
-                keys.push_back(key_of(q));
+                skey[size_t(c) * nv + a] = uint64_t(key_of(q));
+                spos[size_t(c) * nv + a] = uint32_t(size_t(c) * nv + a);
             }
         }
-        std::vector<int64_t> uk(keys);
-        std::sort(uk.begin(), uk.end());
-        uk.erase(std::unique(uk.begin(), uk.end()), uk.end());
+        radix_sort_pairs(skey, spos);
+        std::vector<int64_t> uk;
+        uk.reserve(nk / 2 + 1);
+        for (size_t i = 0; i < nk; ++i) {
+            if (i == 0 || skey[i] != skey[i - 1]) uk.push_back(int64_t(skey[i]));
+            m.cells[spos[i]] = int32_t(uk.size() - 1);
+        }
+        skey = std::vector<uint64_t>();
+        spos = std::vector<uint32_t>();
         m.n_nodes = int64_t(uk.size());
         if (m.n_nodes >= (int64_t(1) << 31)) fail(FR_EINVAL, "mesh: too many nodes");
         m.coords.resize(size_t(m.n_nodes) * dim);
@@ -250,14 +368,19 @@ HostMesh build_mesh(const fr_mesh_desc& d) {
         };
         for (int64_t c = 0; c < m.n_cells; ++c) {
             const Leaf& lf = leaves[size_t(c)];
-            for (int a = 0; a < nv; ++a) m.cells[size_t(c) * nv + a] = int32_t(node_of(keys[size_t(c) * nv + a]));
             for (int k = 0; k < dim; ++k) m.cell_lo[size_t(c) * dim + k] = d.lo[k] + double(lf.o[k]) * m.h_min;
             m.cell_h[size_t(c)] = m.h_min * double(S >> lf.level);
         }
         // hanging nodes: edge midpoints (weights 1/2) and 3d face centres (weights 1/4) of
         // cells that are nodes of finer neighbours
-        std::vector<std::vector<std::pair<int64_t, double>>> hang(size_t(m.n_nodes));
+        std::vector<int32_t> hid(size_t(m.n_nodes), -1);           // node -> entry of `hang`
+        std::vector<std::vector<std::pair<int64_t, double>>> hang;
         std::vector<uint8_t> is_hang(size_t(m.n_nodes), 0);
+        auto set_hang = [&](int64_t n, std::vector<std::pair<int64_t, double>> ms) {
+            is_hang[size_t(n)] = 1;
+            hid[size_t(n)] = int32_t(hang.size());
+            hang.push_back(std::move(ms));
+        };
         for (int64_t c = 0; c < m.n_cells; ++c) {
             const Leaf& lf = leaves[size_t(c)];
             int64_t s = S >> lf.level;
@@ -272,10 +395,7 @@ HostMesh build_mesh(const fr_mesh_desc& d) {
                     for (int t = 0; t < dim; ++t) q[t] += ((a >> t) & 1) * s;
                     q[k] += s / 2;
                     int64_t n = node_of(key_of(q));
-                    if (n >= 0 && !is_hang[size_t(n)]) {
-                        is_hang[size_t(n)] = 1;
-                        hang[size_t(n)] = {{cv[a], 0.5}, {cv[b], 0.5}};
-                    }
+                    if (n >= 0 && !is_hang[size_t(n)]) set_hang(n, {{cv[a], 0.5}, {cv[b], 0.5}});
                 }
             if (dim == 3) {
                 for (int k = 0; k < 3; ++k)
@@ -284,11 +404,10 @@ HostMesh build_mesh(const fr_mesh_desc& d) {
                         q[k] = lf.o[k] + side * s;
                         int64_t n = node_of(key_of(q));
                         if (n >= 0 && !is_hang[size_t(n)]) {
-                            is_hang[size_t(n)] = 1;
                             std::vector<std::pair<int64_t, double>> ms;
                             for (int a = 0; a < nv; ++a)
                                 if (((a >> k) & 1) == side) ms.push_back({cv[a], 0.25});
-                            hang[size_t(n)] = ms;
+                            set_hang(n, std::move(ms));
                         }
                     }
             }
@@ -299,10 +418,10 @@ HostMesh build_mesh(const fr_mesh_desc& d) {
             for (int guard = 0; guard < 8; ++guard) {
                 bool again = false;
                 std::vector<std::pair<int64_t, double>> nx;
-                for (auto& mw : hang[size_t(n)]) {
+                for (auto& mw : hang[size_t(hid[size_t(n)])]) {
                     if (is_hang[size_t(mw.first)]) {
                         again = true;
-                        for (auto& m2 : hang[size_t(mw.first)]) nx.push_back({m2.first, mw.second * m2.second});
+                        for (auto& m2 : hang[size_t(hid[size_t(mw.first)])]) nx.push_back({m2.first, mw.second * m2.second});
                     } else {
                         nx.push_back(mw);
                     }
@@ -313,7 +432,7 @@ HostMesh build_mesh(const fr_mesh_desc& d) {
                     if (!mg.empty() && mg.back().first == e.first) mg.back().second += e.second;
                     else mg.push_back(e);
                 }
-                hang[size_t(n)] = mg;
+                hang[size_t(hid[size_t(n)])] = mg;
                 if (!again) break;
             }
         }
@@ -328,7 +447,7 @@ HostMesh build_mesh(const fr_mesh_desc& d) {
         m.con_ptr.assign(size_t(m.n_nodes) + 1, 0);
         for (int64_t n = 0; n < m.n_nodes; ++n) {
             if (is_hang[size_t(n)]) {
-                for (auto& mw : hang[size_t(n)]) {
+                for (auto& mw : hang[size_t(hid[size_t(n)])]) {
                     m.con_master.push_back(m.free_of_node[size_t(mw.first)]);
                     m.con_w.push_back(mw.second);
                 }
@@ -460,65 +579,118 @@ Pattern build_pattern(const HostMesh& m, int C) {
                     dep_w[static_cast<size_t>(fill[size_t(f)]++)] = m.con_w[size_t(j)];
                 }
     }
-    // per row: entries and sorted unique columns
-    std::vector<std::vector<int32_t>> cols(static_cast<size_t>(nf));
-    p.ent_ptr.assign(size_t(nf) + 1, 0);
+    // per row: assembly entries (cell, vertex, weight) ordered by (cell, vertex) and the
+    // sorted unique node columns; rows are independent, so host threads take row ranges and
+    // the pieces are concatenated in row order
     struct Ent { int32_t cell; uint8_t a; double w; };
-    std::vector<Ent> ents;
-    std::vector<Ent> tmp;
-    std::vector<int32_t> cand;
+    struct Part {
+        std::vector<Ent> ents;
+        std::vector<int32_t> n_ent, cols, n_col;
+        int max_row = 0;
+    };
+    const int64_t hw = std::max<int64_t>(1, std::thread::hardware_concurrency());
+    const int64_t T = std::max<int64_t>(1, std::min<int64_t>({hw, 16, nf / 4096 + 1}));
+    std::vector<Part> parts(static_cast<size_t>(T));
+    {
+        std::vector<std::thread> th;
+        std::vector<std::exception_ptr> err(static_cast<size_t>(T));
+        for (int64_t t = 0; t < T; ++t)
+            th.emplace_back([&, t]() {
+                try {
+                    Part& P = parts[size_t(t)];
+                    const int64_t f0 = nf * t / T, f1 = nf * (t + 1) / T;
+                    std::vector<Ent> tmp;
+                    std::vector<int32_t> cand;
+                    for (int64_t f = f0; f < f1; ++f) {
+                        tmp.clear();
+                        const int32_t node = m.node_of_free[size_t(f)];
+                        for (int32_t j = nc_ptr[size_t(node)]; j < nc_ptr[size_t(node) + 1]; ++j)
+                            tmp.push_back(Ent{nc_cell[size_t(j)], uint8_t(nc_a[size_t(j)]), 1.0});
+                        if (m.n_hanging > 0)
+                            for (int32_t j = dep_ptr[size_t(f)]; j < dep_ptr[size_t(f) + 1]; ++j) {
+                                const int32_t h = dep_node[size_t(j)];
+                                for (int32_t q = nc_ptr[size_t(h)]; q < nc_ptr[size_t(h) + 1]; ++q)
+                                    tmp.push_back(Ent{nc_cell[size_t(q)], uint8_t(nc_a[size_t(q)]), dep_w[size_t(j)]});
+                            }
+                        std::sort(tmp.begin(), tmp.end(), [](const Ent& x, const Ent& y) {
+                            return x.cell != y.cell ? x.cell < y.cell : x.a < y.a;
+                        });
+                        cand.clear();
+                        for (const Ent& e : tmp) {
+                            P.ents.push_back(e);
+                            for (int b = 0; b < nv; ++b) {
+                                const int32_t n = m.cells[size_t(e.cell) * nv + b];
+                                for (int32_t q = m.con_ptr[size_t(n)]; q < m.con_ptr[size_t(n) + 1]; ++q)
+                                    cand.push_back(m.con_master[size_t(q)]);
+                            }
+                        }
+                        std::sort(cand.begin(), cand.end());
+                        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+                        if (cand.size() > 254) fail(FR_EINTERNAL, "pattern: more than 254 node neighbours in a row");
+                        P.max_row = std::max(P.max_row, int(cand.size()));
+                        P.n_ent.push_back(int32_t(tmp.size()));
+                        P.n_col.push_back(int32_t(cand.size()));
+                        P.cols.insert(P.cols.end(), cand.begin(), cand.end());
+                    }
+                } catch (...) {
+                    err[size_t(t)] = std::current_exception();
+                }
+            });
+        for (auto& x : th) x.join();
+        for (auto& e : err)
+            if (e) std::rethrow_exception(e);
+    }
+    // concatenate: entry pointers, row column lists (col_ptr / col_all)
+    p.ent_ptr.assign(size_t(nf) + 1, 0);
+    std::vector<int64_t> col_ptr(size_t(nf) + 1, 0);
     int max_row = 0;
-    for (int64_t f = 0; f < nf; ++f) {
-        tmp.clear();
-        int32_t node = m.node_of_free[size_t(f)];
-        for (int32_t j = nc_ptr[size_t(node)]; j < nc_ptr[size_t(node) + 1]; ++j)
-            tmp.push_back(Ent{nc_cell[size_t(j)], uint8_t(nc_a[size_t(j)]), 1.0});
-        if (m.n_hanging > 0)
-            for (int32_t j = dep_ptr[size_t(f)]; j < dep_ptr[size_t(f) + 1]; ++j) {
-                int32_t h = dep_node[size_t(j)];
-                for (int32_t t = nc_ptr[size_t(h)]; t < nc_ptr[size_t(h) + 1]; ++t)
-                    tmp.push_back(Ent{nc_cell[size_t(t)], uint8_t(nc_a[size_t(t)]), dep_w[size_t(j)]});
+    {
+        int64_t f = 0;
+        for (const Part& P : parts) {
+            for (size_t r = 0; r < P.n_ent.size(); ++r, ++f) {
+                p.ent_ptr[size_t(f) + 1] = p.ent_ptr[size_t(f)] + P.n_ent[r];
+                col_ptr[size_t(f) + 1] = col_ptr[size_t(f)] + P.n_col[r];
             }
-        std::sort(tmp.begin(), tmp.end(), [](const Ent& x, const Ent& y) {
-            return x.cell != y.cell ? x.cell < y.cell : x.a < y.a;
-        });
-        cand.clear();
-        for (const Ent& e : tmp) {
-            ents.push_back(e);
-            for (int b = 0; b < nv; ++b) {
-                int32_t n = m.cells[size_t(e.cell) * nv + b];
-                for (int32_t t = m.con_ptr[size_t(n)]; t < m.con_ptr[size_t(n) + 1]; ++t) cand.push_back(m.con_master[size_t(t)]);
-            }
+            max_row = std::max(max_row, P.max_row);
         }
-        std::sort(cand.begin(), cand.end());
-        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
-        if (cand.size() > 254) fail(FR_EINTERNAL, "pattern: more than 254 node neighbours in a row");
-        max_row = std::max(max_row, int(cand.size()));
-        cols[size_t(f)] = cand;
-        p.ent_ptr[size_t(f) + 1] = int32_t(ents.size());
     }
     p.max_row = max_row;
-    const size_t n_ent = ents.size();
+    const size_t n_ent = size_t(p.ent_ptr[size_t(nf)]);
+    std::vector<Ent> ents(n_ent);
+    std::vector<int32_t> col_all(static_cast<size_t>(col_ptr[static_cast<size_t>(nf)]));
+    {
+        size_t eo = 0, co = 0;
+        for (Part& P : parts) {
+            std::copy(P.ents.begin(), P.ents.end(), ents.begin() + int64_t(eo));
+            std::copy(P.cols.begin(), P.cols.end(), col_all.begin() + int64_t(co));
+            eo += P.ents.size();
+            co += P.cols.size();
+            P = Part();
+        }
+    }
     p.ent_cell.resize(n_ent);
     p.ent_a.resize(n_ent);
     p.ent_w.resize(n_ent);
     p.ent_k.resize(n_ent * size_t(nv));
-    for (int64_t f = 0; f < nf; ++f) {
-        const auto& cf = cols[size_t(f)];
-        for (int32_t e = p.ent_ptr[size_t(f)]; e < p.ent_ptr[size_t(f) + 1]; ++e) {
-            const Ent& en = ents[size_t(e)];
-            p.ent_cell[size_t(e)] = en.cell;
-            p.ent_a[size_t(e)] = en.a;
-            p.ent_w[size_t(e)] = en.w;
-            for (int b = 0; b < nv; ++b) {
-                int32_t n = m.cells[size_t(en.cell) * nv + b];
-                int32_t fb = m.free_of_node[size_t(n)];
-                uint8_t k = 255;
-                if (fb >= 0) k = uint8_t(std::lower_bound(cf.begin(), cf.end(), fb) - cf.begin());
-                p.ent_k[size_t(e) * nv + b] = k;
+    parallel_ranges(nf, [&](int64_t f0, int64_t f1, int) {
+        for (int64_t f = f0; f < f1; ++f) {
+            const int32_t* cb = col_all.data() + col_ptr[size_t(f)];
+            const int32_t* ce = col_all.data() + col_ptr[size_t(f) + 1];
+            for (int32_t e = p.ent_ptr[size_t(f)]; e < p.ent_ptr[size_t(f) + 1]; ++e) {
+                const Ent& en = ents[size_t(e)];
+                p.ent_cell[size_t(e)] = en.cell;
+                p.ent_a[size_t(e)] = en.a;
+                p.ent_w[size_t(e)] = en.w;
+                for (int b = 0; b < nv; ++b) {
+                    const int32_t n = m.cells[size_t(en.cell) * nv + b];
+                    const int32_t fb = m.free_of_node[size_t(n)];
+                    uint8_t k = 255;
+                    if (fb >= 0) k = uint8_t(std::lower_bound(cb, ce, fb) - cb);
+                    p.ent_k[size_t(e) * nv + b] = k;
+                }
             }
         }
-    }
+    });
     // SELL-C layout (no row sorting: the node numbering already groups similar rows)
     p.n_slices = ceil_div(nf, C);
     p.slice_ptr.assign(size_t(p.n_slices) + 1, 0);
@@ -526,7 +698,8 @@ Pattern build_pattern(const HostMesh& m, int C) {
     int64_t off = 0;
     for (int64_t s = 0; s < p.n_slices; ++s) {
         int w = 0;
-        for (int64_t r = s * C; r < std::min<int64_t>(nf, (s + 1) * C); ++r) w = std::max(w, int(cols[size_t(r)].size()));
+        for (int64_t r = s * C; r < std::min<int64_t>(nf, (s + 1) * C); ++r)
+            w = std::max(w, int(col_ptr[size_t(r) + 1] - col_ptr[size_t(r)]));
         p.slice_ptr[size_t(s)] = int32_t(off);
         off += int64_t(w) * C;
         if (off >= (int64_t(1) << 31)) fail(FR_EINTERNAL, "pattern: more than 2^31 slots");
@@ -536,13 +709,14 @@ Pattern build_pattern(const HostMesh& m, int C) {
     p.col.assign(size_t(off), 0);
     int64_t nnz = 0;
     for (int64_t r = 0; r < nf; ++r) {
-        const auto& cf = cols[size_t(r)];
+        const int32_t* cf = col_all.data() + col_ptr[size_t(r)];
+        const int len = int(col_ptr[size_t(r) + 1] - col_ptr[size_t(r)]);
         int64_t s = r / C, lane = r % C;
         int w = (p.slice_ptr[size_t(s) + 1] - p.slice_ptr[size_t(s)]) / C;
-        p.row_len[size_t(r)] = int32_t(cf.size());
-        nnz += int64_t(cf.size());
+        p.row_len[size_t(r)] = int32_t(len);
+        nnz += int64_t(len);
         for (int k = 0; k < w; ++k)
-            p.col[size_t(p.slice_ptr[size_t(s)] + int64_t(k) * C + lane)] = k < int(cf.size()) ? cf[size_t(k)] : int32_t(r);
+            p.col[size_t(p.slice_ptr[size_t(s)] + int64_t(k) * C + lane)] = k < len ? cf[k] : int32_t(r);
     }
     // slots of padded lanes past the last row point at row 0 (any valid column)
     p.nnz = nnz;

@@ -142,7 +142,8 @@ def test_adaptive_octree_constraints():
     _check_conformity(m)
 
 
-@pytest.mark.parametrize("dim,n,levels,radius,half", [(2, 8, 3, 0.3, 0.5), (2, 16, 4, 0.1, 0.25), (3, 4, 2, 0.2, 0.4)])
+@pytest.mark.parametrize("dim,n,levels,radius,half", [(2, 8, 3, 0.3, 0.5), (2, 16, 4, 0.1, 0.25), (3, 4, 2, 0.2, 0.4),
+                                                       (2, 4, 7, 0.0, 0.3), (2, 6, 6, 0.02, 0.7), (3, 3, 3, 0.0, 0.5)])
 def test_library_adaptive_mesh_matches_oracle(dim, n, levels, radius, half):
     """The library's and the oracle's independent builders give the same nodes, cells and
     hanging-node weights."""
