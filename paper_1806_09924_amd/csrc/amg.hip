@@ -18,7 +18,6 @@
 namespace fr {
 namespace {
 
-constexpr int kHash = 1024;        // LDS hash slots per wave in the SpGEMM
 constexpr int kWavesPerBlock = 4;  // 256-thread blocks
 constexpr int kDenseMax = 4096;    // largest coarsest level inverted densely
 
@@ -396,11 +395,11 @@ struct SellV {
 SellV sv(const SellStruct& S) { return SellV{S.C, S.n_rows, S.slice_ptr, S.row_len, S.col}; }
 
 // Hashed SpGEMM symbolic phase.  A group of G lanes (G in {8,16,32,64}) owns one output
-// row and an LDS hash set of HS = 16 G slots; a wave holds 64/G rows.  The set of columns
-// is deterministic, the order of the table is not, so the fill kernel ranks the entries.
-template <int G>
+// row and an LDS hash set of HS slots (16 G, or 64 G for the rows that overflow that); a
+// wave holds 64/G rows.  The set of columns is deterministic, the order of the table is not,
+// so the fill kernel ranks the entries.
+template <int HS>
 __device__ __forceinline__ bool hash_insert(int32_t* tab, int32_t c, int& cnt) {
-    constexpr int HS = 16 * G;
     uint32_t h = hash32(uint32_t(c)) & (HS - 1);
     for (int probe = 0; probe < HS; ++probe) {
         const int32_t old = atomicCAS(&tab[h], -1, c);
@@ -419,10 +418,9 @@ __device__ __forceinline__ int group_sum(int v) {
 }
 
 // Builds the hash set of the columns of row r of A*B in this group's LDS table.
-template <int G>
+template <int G, int HS>
 __device__ void spgemm_row_set(const SellV& A, const SellV& B, int64_t r, int32_t* tab, int lg, int& added,
                                int* overflow) {
-    constexpr int HS = 16 * G;
     for (int i = lg; i < HS; i += G) tab[i] = -1;
     __syncthreads();
     if (r < A.n_rows) {
@@ -432,22 +430,22 @@ __device__ void spgemm_row_set(const SellV& A, const SellV& B, int64_t r, int32_
             const int lb = B.len[k];
             for (int kb = 0; kb < lb; ++kb) {
                 const int32_t c = B.col[sslot(B.sp, B.C, k, kb)];
-                if (!hash_insert<G>(tab, c, added)) { atomicOr(overflow, 1); break; }
+                if (!hash_insert<HS>(tab, c, added)) { atomicOr(overflow, 1); break; }
             }
         }
     }
     __syncthreads();
 }
 
-template <int G>
+template <int G, int HS>
 __global__ void __launch_bounds__(256) k_spgemm_count(SellV A, SellV B, int32_t* __restrict__ clen,
                                                       int* __restrict__ overflow) {
-    __shared__ int32_t tab[kWavesPerBlock][kHash];
-    constexpr int RPW = kWave / G, HS = 16 * G;
+    constexpr int RPW = kWave / G;
+    __shared__ int32_t tab[kWavesPerBlock][RPW * HS];
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, gi = lane / G, lg = lane % G;
     const int64_t r = (int64_t(blockIdx.x) * kWavesPerBlock + w) * RPW + gi;
     int added = 0;
-    spgemm_row_set<G>(A, B, r, &tab[w][gi * HS], lg, added, overflow);
+    spgemm_row_set<G, HS>(A, B, r, &tab[w][gi * HS], lg, added, overflow);
     const int tot = group_sum<G>(added);
     if (r < A.n_rows && lg == 0) {
         clen[r] = tot;
@@ -455,20 +453,20 @@ __global__ void __launch_bounds__(256) k_spgemm_count(SellV A, SellV B, int32_t*
     }
 }
 
-template <int G>
+template <int G, int HS>
 __global__ void __launch_bounds__(256) k_spgemm_fill(SellV A, SellV B, SellV Cm, int32_t* __restrict__ ccol,
                                                      int* __restrict__ overflow) {
-    __shared__ int32_t tab[kWavesPerBlock][kHash];
-    __shared__ int32_t lst[kWavesPerBlock][kHash];
-    __shared__ int32_t nl[kWavesPerBlock][kWave / G];
-    constexpr int RPW = kWave / G, HS = 16 * G;
+    constexpr int RPW = kWave / G;
+    __shared__ int32_t tab[kWavesPerBlock][RPW * HS];
+    __shared__ int32_t lst[kWavesPerBlock][RPW * HS];
+    __shared__ int32_t nl[kWavesPerBlock][RPW];
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, gi = lane / G, lg = lane % G;
     const int64_t r = (int64_t(blockIdx.x) * kWavesPerBlock + w) * RPW + gi;
     int32_t* mytab = &tab[w][gi * HS];
     int32_t* mylst = &lst[w][gi * HS];
     int added = 0;
     if (lg == 0) nl[w][gi] = 0;
-    spgemm_row_set<G>(A, B, r, mytab, lg, added, overflow);
+    spgemm_row_set<G, HS>(A, B, r, mytab, lg, added, overflow);
     for (int i = lg; i < HS; i += G) {
         const int32_t v = mytab[i];
         if (v >= 0) mylst[atomicAdd(&nl[w][gi], 1)] = v;
@@ -892,12 +890,12 @@ void spgemm_values(const BMat<double>& A, const BMat<double>& B, BMat<double>& C
 }
 #undef FR_SPGEMM_CASE
 
-template <int G>
+template <int G, int HS>
 void spgemm_symbolic(const BMat<double>& A, const BMat<double>& B, BMat<double>& Cm, int* ovf, hipStream_t s,
                      bool fill) {
     const int g = nblk(std::max<int64_t>(1, A.rows()), kWavesPerBlock * (kWave / G));
-    if (!fill) k_spgemm_count<G><<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), Cm.S->row_len, ovf);
-    else k_spgemm_fill<G><<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), sv(*Cm.S), Cm.S->col, ovf);
+    if (!fill) k_spgemm_count<G, HS><<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), Cm.S->row_len, ovf);
+    else k_spgemm_fill<G, HS><<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), sv(*Cm.S), Cm.S->col, ovf);
     FR_LAUNCH_CHECK();
 }
 
@@ -913,21 +911,30 @@ BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* 
     DBuf<int> ovf;
     ovf.alloc(1, s);
     ovf.zero(s);
-    // small hash sets first (8 rows per wave); a row that does not fit reruns with 64 lanes
-    spgemm_symbolic<8>(A, B, Cm, ovf.p, s, false);
+    // small hash sets first (8 rows per wave, 128 slots each); when a row does not fit, all
+    // rows rerun with a wave per row (1024 slots), then with 4096 slots
+    spgemm_symbolic<8, 128>(A, B, Cm, ovf.p, s, false);
     int over = 0;
     layout_from_lengths(*Cm.S, s, ovf.p, &over);
-    const bool small = over == 0;
-    if (!small) {
+    int tier = 0;
+    if (over) {
+        tier = 1;
         ovf.zero(s);
-        spgemm_symbolic<64>(A, B, Cm, ovf.p, s, false);
+        spgemm_symbolic<64, 1024>(A, B, Cm, ovf.p, s, false);
         layout_from_lengths(*Cm.S, s, ovf.p, &over);
-        if (over) fail(FR_EINTERNAL, "spgemm: row exceeds the LDS hash capacity");
+    }
+    if (over) {
+        tier = 2;
+        ovf.zero(s);
+        spgemm_symbolic<64, 4096>(A, B, Cm, ovf.p, s, false);
+        layout_from_lengths(*Cm.S, s, ovf.p, &over);
+        if (over) fail(FR_EINTERNAL, "spgemm: a row of the product has more than 3072 block columns");
     }
     Cm.S->own_col.alloc(size_t(std::max<int64_t>(1, Cm.S->n_slots)), s);
     Cm.S->col = Cm.S->own_col.p;
-    if (small) spgemm_symbolic<8>(A, B, Cm, errs, s, true);
-    else spgemm_symbolic<64>(A, B, Cm, errs, s, true);
+    if (tier == 0) spgemm_symbolic<8, 128>(A, B, Cm, errs, s, true);
+    else if (tier == 1) spgemm_symbolic<64, 1024>(A, B, Cm, errs, s, true);
+    else spgemm_symbolic<64, 4096>(A, B, Cm, errs, s, true);
     Cm.own_val.alloc(size_t(std::max<int64_t>(1, Cm.S->n_slots)) * Cm.br * Cm.bc, s);
     Cm.val = Cm.own_val.p;
     spgemm_values<MODE>(A, B, Cm, invd, omega, s);
