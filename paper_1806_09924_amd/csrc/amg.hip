@@ -417,12 +417,18 @@ __device__ __forceinline__ int group_sum(int v) {
     return v;
 }
 
+// LDS visibility among the lanes of one wave (each wave works on its own LDS slice)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Builds the hash set of the columns of row r of A*B in this group's LDS table.
 template <int G, int HS>
 __device__ void spgemm_row_set(const SellV& A, const SellV& B, int64_t r, int32_t* tab, int lg, int& added,
                                int* overflow) {
     for (int i = lg; i < HS; i += G) tab[i] = -1;
-    __syncthreads();
+    wave_sync();
     if (r < A.n_rows) {
         const int la = A.len[r];
         for (int ka = lg; ka < la; ka += G) {
@@ -434,7 +440,7 @@ __device__ void spgemm_row_set(const SellV& A, const SellV& B, int64_t r, int32_
             }
         }
     }
-    __syncthreads();
+    wave_sync();
 }
 
 template <int G, int HS>
@@ -471,7 +477,7 @@ __global__ void __launch_bounds__(256) k_spgemm_fill(SellV A, SellV B, SellV Cm,
         const int32_t v = mytab[i];
         if (v >= 0) mylst[atomicAdd(&nl[w][gi], 1)] = v;
     }
-    __syncthreads();
+    wave_sync();
     if (r >= A.n_rows) return;
     const int n = nl[w][gi];
     const int64_t s0 = r / Cm.C;
@@ -490,6 +496,57 @@ __global__ void __launch_bounds__(256) k_spgemm_fill(SellV A, SellV B, SellV Cm,
     for (int o = G / 2; o > 0; o >>= 1) f = max(f, __shfl_xor(f, o));
     if (f < 0) f = 0;
     for (int k = n + lg; k < width; k += G) ccol[sslot(Cm.sp, Cm.C, r, k)] = f;
+}
+
+// Symbolic phase of A B when every row of B has at most one block (a tentative prolongator):
+// the columns of row r are the distinct B columns of the rows A's row r touches.  G lanes
+// per row (G >= the longest row of A), lane g takes entry g; the group sorts its values by a
+// bitonic network over lanes, marks the first of each run of equal values and places it by a
+// prefix count.  fill == false: row lengths to clen; fill == true: sorted columns (padding
+// repeats the smallest) to ccol.
+template <int G>
+__global__ void __launch_bounds__(256) k_spgemm_single(SellV A, SellV B, SellV Cm, int32_t* __restrict__ clen,
+                                                       int32_t* __restrict__ ccol, int fill) {
+    constexpr int RPW = kWave / G;
+    constexpr int32_t kNone = 0x7fffffff;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, gi = lane / G, lg = lane % G;
+    const int64_t r = (int64_t(blockIdx.x) * kWavesPerBlock + w) * RPW + gi;
+    const bool row_ok = r < A.n_rows;
+    const int la = row_ok ? A.len[r] : 0;
+    int32_t v = kNone;
+    if (lg < la) {
+        const int64_t k = A.col[sslot(A.sp, A.C, r, lg)];
+        if (B.len[k] > 0) v = B.col[sslot(B.sp, B.C, k, 0)];
+    }
+    // ascending bitonic sort of the group's G values
+#pragma unroll
+    for (int k = 2; k <= G; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int32_t o = __shfl_xor(v, j);
+            const bool up = (lg & k) == 0, lower = (lg & j) == 0;
+            v = (lower == up) ? min(v, o) : max(v, o);
+        }
+    const int32_t prev = __shfl_up(v, 1);
+    const int first = (v != kNone && (lg == 0 || prev != v)) ? 1 : 0;
+    // inclusive prefix count of the run heads within the group
+    int pos = first;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+        const int t = __shfl_up(pos, o);
+        if (lg >= o) pos += t;
+    }
+    const int count = __shfl(pos, lane - lg + G - 1);
+    const int32_t mn = __shfl(v, lane - lg);
+    if (!row_ok) return;
+    if (!fill) {
+        if (lg == 0) clen[r] = count;
+        return;
+    }
+    if (first) ccol[sslot(Cm.sp, Cm.C, r, pos - 1)] = v;
+    const int64_t s0 = r / Cm.C;
+    const int width = (Cm.sp[s0 + 1] - Cm.sp[s0]) / Cm.C;
+    for (int k = count + lg; k < width; k += G) ccol[sslot(Cm.sp, Cm.C, r, k)] = count > 0 ? mn : 0;
 }
 
 __device__ __forceinline__ int find_sorted(const SellV& B, int64_t row, int32_t c) {
@@ -843,8 +900,10 @@ void spgemm_numeric(const BMat<double>& A, const BMat<double>& B, BMat<double>& 
                     hipStream_t s) {
     const int ml = Cm.S->max_len;
     const int64_t rows = std::max<int64_t>(1, A.rows());
-    // row merge in LDS when the output rows fit (16 lanes per row, 16 rows per block)
-    {
+    // row merge in LDS when the output rows fit (16 lanes per row, 16 rows per block) and the
+    // rows of B are long enough to keep its lanes busy; a tentative prolongator (one block
+    // per row) goes to the column-parallel kernel, whose lanes share the loads of A's row
+    if (B.S->max_len > 1) {
         constexpr int G = 16, RPB = kWavesPerBlock * (kWave / G), BB = BRA * BCB;
         int LC = 8;
         while (LC < ml) LC <<= 1;
@@ -911,6 +970,31 @@ BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* 
     DBuf<int> ovf;
     ovf.alloc(1, s);
     ovf.zero(s);
+    if (B.S->max_len <= 1 && A.S->max_len <= kWave) {
+        // B has one block per row: columns by lane ranking, no hash sets
+        int G = 8;
+        while (G < A.S->max_len) G <<= 1;
+        const int g = nblk(std::max<int64_t>(1, A.rows()), kWavesPerBlock * (kWave / G));
+#define FR_SINGLE(G_, FILL_)                                                                              \
+        k_spgemm_single<G_><<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), sv(*Cm.S), Cm.S->row_len, Cm.S->col, FILL_);
+#define FR_SINGLE_ALL(FILL_)                                                                              \
+        switch (G) {                                                                                      \
+            case 8: FR_SINGLE(8, FILL_) break;                                                            \
+            case 16: FR_SINGLE(16, FILL_) break;                                                          \
+            case 32: FR_SINGLE(32, FILL_) break;                                                          \
+            default: FR_SINGLE(64, FILL_) break;                                                          \
+        }                                                                                                 \
+        FR_LAUNCH_CHECK();
+        FR_SINGLE_ALL(0)
+        finish_struct(*Cm.S, s);
+        FR_SINGLE_ALL(1)
+#undef FR_SINGLE_ALL
+#undef FR_SINGLE
+        Cm.own_val.alloc(size_t(std::max<int64_t>(1, Cm.S->n_slots)) * Cm.br * Cm.bc, s);
+        Cm.val = Cm.own_val.p;
+        spgemm_values<MODE>(A, B, Cm, invd, omega, s);
+        return Cm;
+    }
     // small hash sets first (8 rows per wave, 128 slots each); when a row does not fit, all
     // rows rerun with a wave per row (1024 slots), then with 4096 slots
     spgemm_symbolic<8, 128>(A, B, Cm, ovf.p, s, false);
