@@ -100,6 +100,9 @@ typedef struct {
     double rtol;         /* stop when ||F - J du||_2 <= rtol ||F||_2 (true residual, FP64) */
     int restart;         /* Krylov basis size before a restart */
     int maxit;           /* total iteration cap */
+    int use_graphs;      /* nonzero: the two V-cycles are captured once per amg_setup as HIP graphs
+                            and replayed every iteration (one launch each instead of one per
+                            kernel); ignored while fracture_profile records */
 } fr_solve_opts;
 
 typedef struct {

@@ -40,7 +40,8 @@ class AmgOpts(ctypes.Structure):
 
 
 class SolveOpts(ctypes.Structure):
-    _fields_ = [("rtol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int)]
+    _fields_ = [("rtol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
+                ("use_graphs", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -158,8 +159,8 @@ def amg_opts(precision=64, theta=0.02, cheb_degree=2, cheb_ratio=12.0, coarse_ma
     return AmgOpts(precision, theta, cheb_degree, cheb_ratio, coarse_max, max_levels, reuse_u_block, refresh_phi)
 
 
-def solve_opts(rtol=1e-8, restart=100, maxit=500):
-    return SolveOpts(rtol, restart, maxit)
+def solve_opts(rtol=1e-8, restart=100, maxit=500, use_graphs=1):
+    return SolveOpts(rtol, restart, maxit, use_graphs)
 
 
 def newton_opts(tol=1e-8, max_it=30, ls_max=8):

@@ -601,7 +601,7 @@ fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double*
     if (ps != FR_OK) return ps;
     const fr_amg_opts ao = amg_opts ? *amg_opts : default_amg();
     if (check_amg(ao) != FR_OK) return FR_EINVAL;
-    fr_solve_opts so{1e-8, 100, 500};
+    fr_solve_opts so{1e-8, 100, 500, 1};
     if (solve_opts) so = *solve_opts;
     if (check_solve(so) != FR_OK) return FR_EINVAL;
     fr_newton_opts no{1e-8, 30, 8};

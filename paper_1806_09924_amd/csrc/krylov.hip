@@ -23,6 +23,9 @@ constexpr int kE = 4;                 // elements per thread in the vector sweep
 // the second Gram-Schmidt pass runs where the first cut |w| by more than this factor
 // (the orthogonality left is then at least 2^-10 u-level: about 1e-13)
 constexpr double kReorthEta = 1.0 / 1024.0;
+// the host waits for an iteration's convergence flags once some instance's residual estimate
+// is within this factor of its target
+constexpr double kSpecRatio = 64.0;
 constexpr int kChunk = 256 * kE;      // elements per block
 constexpr int kMaxM = 120;            // largest restart length
 
@@ -129,11 +132,11 @@ __global__ void __launch_bounds__(256) k_seg_resid(const double* __restrict__ F,
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// dst = src * scale[inst]; with an FP32 preconditioner also its input: the same values in
-// FP32, u part (solve index < n_u) to f_u, phi part to f_p.
+// dst = src * scale[inst]; also the preconditioner's input when it is staged: the same
+// values in FP32 (u part, solve index < n_u, to f_u; phi part to f_p) or in FP64 (d_copy).
 __global__ void __launch_bounds__(256) k_seg_scale(const double* __restrict__ src, double* __restrict__ dst,
                                                    const double* __restrict__ scale, Seg sg, float* __restrict__ f_u,
-                                                   float* __restrict__ f_p, int64_t n_u) {
+                                                   float* __restrict__ f_p, int64_t n_u, double* __restrict__ d_copy) {
     const int64_t s0 = sg.start[blockIdx.x];
     const int len = sg.len[blockIdx.x];
     const double a = scale[sg.inst[blockIdx.x]];
@@ -144,6 +147,7 @@ __global__ void __launch_bounds__(256) k_seg_scale(const double* __restrict__ sr
             const int64_t i = s0 + o;
             const double v = a * src[i];
             dst[i] = v;
+            if (d_copy) d_copy[i] = v;
             if (f_u) {
                 if (i < n_u) f_u[i] = float(v);
                 else f_p[i - n_u] = float(v);
@@ -286,6 +290,28 @@ __global__ void k_givens(int ni, int m, int j, State st) {
     st.scale[i] = (st.done[i] || !(nw > 0.0)) ? 0.0 : 1.0 / nw;
 }
 
+// The host's view of iteration j: whether every instance is done, and how far the running
+// ones still are from their targets.
+__global__ void k_summary(int ni, int m, int j, State st, IterSummary* out) {
+    __shared__ int all;
+    __shared__ double worst;
+    if (threadIdx.x == 0) { all = 1; worst = 0.0; }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ni; i += blockDim.x) {
+        if (st.done[i]) continue;
+        atomicAnd(&all, 0);
+        const double r = fabs(st.g[int64_t(i) * (m + 1) + j + 1]) / st.target[i];
+        // doubles compare as their bit patterns when non-negative (NaN: stays large)
+        atomicMax(reinterpret_cast<unsigned long long*>(&worst), __double_as_longlong(isfinite(r) ? r : 1e300));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out->all_done = all;
+        out->pad = 0;
+        out->ratio = worst;
+    }
+}
+
 // y = H^-1 g on the jused x jused upper triangle
 __global__ void k_backsolve(int ni, int m, State st) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -358,6 +384,11 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
     const int ni = sys.mesh->n_inst;
     const int m = std::max(1, std::min(o.restart, kMaxM));
     const bool z32 = amg.opts.precision == 32;
+    if (!ws.hsum) {
+        FR_HIP(hipHostMalloc(reinterpret_cast<void**>(&ws.hsum), 2 * sizeof(IterSummary), hipHostMallocDefault));
+        for (auto& e : ws.ev_sum) FR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ws.dsum.alloc(1, s);
+    }
     if (ws.n != n || ws.m != m || ws.n_inst != ni || ws.z32 != z32) {
         ws.n = n;
         ws.m = m;
@@ -402,10 +433,23 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
         st.need = ws.istate.p + 3 * ni;
     }
     const Seg sg{ws.seg_start.p, ws.seg_len.p, ws.seg_inst.p};
-    // FP32 preconditioner: the basis vectors are written in FP32 too, straight into the
-    // hierarchies' level-0 right-hand sides
-    float* f_u = z32 ? amg_input32(amg, 0) : nullptr;
-    float* f_p = z32 ? amg_input32(amg, 1) : nullptr;
+    // The preconditioner's argument is staged while the basis vector is written: for graph
+    // replay into the graphs' fixed input (FP32 or FP64); without graphs, with the FP32
+    // hierarchy, straight into its level-0 right-hand sides.
+    const bool graphs = o.use_graphs != 0 && !prof_enabled();
+    float* f_u = nullptr;
+    float* f_p = nullptr;
+    double* d_copy = nullptr;
+    if (graphs && z32) {
+        f_u = static_cast<float*>(amg_graph_input(amg));
+        f_p = f_u + sys.n_u;
+    } else if (graphs) {
+        d_copy = static_cast<double*>(amg_graph_input(amg));
+    } else if (z32) {
+        f_u = amg_input32(amg, 0);
+        f_p = amg_input32(amg, 1);
+    }
+    void* vout = graphs ? amg_graph_output(amg) : nullptr;
     const int nb = ws.nb;
     const int gi = int(ceil_div(ni, 64));
     double* part = ws.part.p;
@@ -449,13 +493,18 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
             all_done = all_done && dn[size_t(i)];
         }
         if (all_done || total >= o.maxit) break;
-        k_seg_scale<<<nb, 256, 0, s>>>(ws.w.p, ws.V.p, st.scale, sg, f_u, f_p, sys.n_u);
+        k_seg_scale<<<nb, 256, 0, s>>>(ws.w.p, ws.V.p, st.scale, sg, f_u, f_p, sys.n_u, d_copy);
         FR_LAUNCH_CHECK();
         int j = 0;
         for (; j < M && total < o.maxit; ++j) {
             if (j + 1 > ws.cap) grow_basis(ws, j, s);
             double* Vj = ws.V.p + int64_t(j) * n;
-            if (z32) {
+            if (graphs) {
+                // replayed V-cycles from the staged input; the product J z keeps z in the basis
+                amg_precondition_graph(amg, s);
+                if (z32) jspmv_copy(sys, static_cast<const float*>(vout), ws.w.p, ws.Z32.p + int64_t(j) * n, s);
+                else jspmv_copy(sys, static_cast<const double*>(vout), ws.w.p, ws.Z.p + int64_t(j) * n, s);
+            } else if (z32) {
                 float* Zj = ws.Z32.p + int64_t(j) * n;
                 amg_precondition32(amg, nullptr, Zj, s);   // input staged by k_seg_scale
                 jspmv(sys, Zj, ws.w.p, s);
@@ -498,13 +547,34 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
             }
             k_givens<<<gi, 64, 0, s>>>(ni, M, j, st);
             FR_LAUNCH_CHECK();
-            k_seg_scale<<<nb, 256, 0, s>>>(ws.w.p, ws.V.p + int64_t(j + 1) * n, st.scale, sg, f_u, f_p, sys.n_u);
+            k_seg_scale<<<nb, 256, 0, s>>>(ws.w.p, ws.V.p + int64_t(j + 1) * n, st.scale, sg, f_u, f_p, sys.n_u,
+                                           d_copy);
             FR_LAUNCH_CHECK();
+            // convergence readback without a round trip per iteration: the summary goes to a
+            // pinned ring; the host waits for it only when the previous iteration's summary
+            // (already on the host) leaves an instance within kSpecRatio of its target, and
+            // otherwise enqueues the next iteration at once.  An iteration run after every
+            // instance has finished changes nothing (finished instances are frozen).
+            const int slot = total & 1;
+            k_summary<<<1, 64, 0, s>>>(ni, M, j, st, ws.dsum.p);
+            FR_LAUNCH_CHECK();
+            FR_HIP(hipMemcpyAsync(&ws.hsum[slot], ws.dsum.p, sizeof(IterSummary), hipMemcpyDeviceToHost, s));
+            FR_HIP(hipEventRecord(ws.ev_sum[slot], s));
             ++total;
-            std::vector<int> d2 = download(st.done, size_t(ni), s);
-            bool all = true;
-            for (int i = 0; i < ni; ++i) all = all && d2[size_t(i)];
-            if (all) { ++j; break; }
+            bool wait = true;
+            if (j > 0) {
+                const hipError_t q = hipEventQuery(ws.ev_sum[slot ^ 1]);
+                if (q == hipSuccess) {
+                    const IterSummary& prev = ws.hsum[slot ^ 1];
+                    wait = prev.all_done || !(prev.ratio > kSpecRatio);
+                } else {
+                    (void)hipGetLastError();   // not ready: not an error
+                }
+            }
+            if (wait) {
+                FR_HIP(hipEventSynchronize(ws.ev_sum[slot]));
+                if (ws.hsum[slot].all_done) { ++j; break; }
+            }
         }
         k_backsolve<<<gi, 64, 0, s>>>(ni, M, st);
         FR_LAUNCH_CHECK();

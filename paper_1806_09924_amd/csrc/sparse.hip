@@ -164,7 +164,8 @@ template <int D, typename TX>
 __global__ void __launch_bounds__(256) k_jspmv(int64_t nf, int C, const int32_t* __restrict__ slice_ptr,
                                                const int32_t* __restrict__ col, const double* __restrict__ uu,
                                                const double* __restrict__ pu, const double* __restrict__ pp,
-                                               const TX* __restrict__ x, double* __restrict__ y) {
+                                               const TX* __restrict__ x, double* __restrict__ y,
+                                               TX* __restrict__ xcopy) {
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= nf) return;
     const int64_t s = r / C;
@@ -195,6 +196,11 @@ __global__ void __launch_bounds__(256) k_jspmv(int64_t nf, int C, const int32_t*
 #pragma unroll
     for (int i = 0; i < D; ++i) y[r * D + i] = au[i];
     y[D * nf + r] = ap;
+    if (xcopy) {   // the row's own entries of x, kept (the vector x is a scratch copy)
+#pragma unroll
+        for (int i = 0; i < D; ++i) xcopy[r * D + i] = x[r * D + i];
+        xcopy[D * nf + r] = xp[r];
+    }
 }
 
 // ---- scan ---------------------------------------------------------------------------------
@@ -518,7 +524,7 @@ void cheb_first(const T* invd, const T* b, T* d, T* x, T beta, int64_t n, hipStr
 }
 
 template <typename TX>
-static void jspmv_t(const DevSystem& sys, const TX* x, double* y, hipStream_t s) {
+static void jspmv_t(const DevSystem& sys, const TX* x, double* y, hipStream_t s, TX* xcopy = nullptr) {
     const SellStruct& S = *sys.Juu.S;
     const int g = nblk(S.n_rows, 256);
     const int D = sys.mesh->dim;
@@ -527,14 +533,22 @@ static void jspmv_t(const DevSystem& sys, const TX* x, double* y, hipStream_t s)
     std::snprintf(name, sizeof(name), "jspmv_d%d%s", D, sizeof(TX) == 4 ? "_x32" : "");
     ProfScope ps(name, s, bytes);
     if (D == 2)
-        k_jspmv<2, TX><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, sys.Juu.val, sys.Jpu.val, sys.Jpp.val, x, y);
+        k_jspmv<2, TX><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, sys.Juu.val, sys.Jpu.val, sys.Jpp.val, x, y,
+                                         xcopy);
     else
-        k_jspmv<3, TX><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, sys.Juu.val, sys.Jpu.val, sys.Jpp.val, x, y);
+        k_jspmv<3, TX><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, sys.Juu.val, sys.Jpu.val, sys.Jpp.val, x, y,
+                                         xcopy);
     FR_LAUNCH_CHECK();
 }
 
 void jspmv(const DevSystem& sys, const double* x, double* y, hipStream_t s) { jspmv_t<double>(sys, x, y, s); }
 void jspmv(const DevSystem& sys, const float* x, double* y, hipStream_t s) { jspmv_t<float>(sys, x, y, s); }
+void jspmv_copy(const DevSystem& sys, const double* x, double* y, double* xcopy, hipStream_t s) {
+    jspmv_t<double>(sys, x, y, s, xcopy);
+}
+void jspmv_copy(const DevSystem& sys, const float* x, double* y, float* xcopy, hipStream_t s) {
+    jspmv_t<float>(sys, x, y, s, xcopy);
+}
 
 void system_matvec(DevSystem& sys, const double* x, double* y) { jspmv(sys, x, y, sys.stream); }
 

@@ -125,6 +125,9 @@ void cheb_first(const T* invd, const T* b, T* d, T* x, T beta, int64_t n, hipStr
 // fused J-SpMV over the three blocks: y = J x (solve order); x may be FP32 (exactly widened)
 void jspmv(const DevSystem& sys, const double* x, double* y, hipStream_t s);
 void jspmv(const DevSystem& sys, const float* x, double* y, hipStream_t s);
+// the same, also copying x to xcopy
+void jspmv_copy(const DevSystem& sys, const double* x, double* y, double* xcopy, hipStream_t s);
+void jspmv_copy(const DevSystem& sys, const float* x, double* y, float* xcopy, hipStream_t s);
 
 // ---- AMG (amg.hip) ----------------------------------------------------------------------
 struct AmgLevel {
@@ -157,7 +160,20 @@ struct DevAmg {
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     DBuf<float> z32;                             // FP32 result staging of amg_precondition
+    // Replayable V-cycles: each block's cycle captured once per setup as a HIP graph that
+    // reads the fixed input vin and writes the fixed output vout (solve order, [u | phi], in
+    // the hierarchy's precision).  Destroyed at every setup.
+    DBuf<double> vin64, vout64;
+    DBuf<float> vin32, vout32;
+    hipGraphExec_t vgraph[2] = {nullptr, nullptr};
+    void drop_graphs() {
+        for (auto& g : vgraph)
+            if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+    }
     ~DevAmg() {
+        if (side) (void)hipStreamSynchronize(side);
+        if (stream) (void)hipStreamSynchronize(stream);
+        drop_graphs();
         // the phase-field hierarchy's buffers are freed on the side stream: before it goes
         for (auto& H : h) {
             H.lv.clear();
@@ -176,6 +192,12 @@ void amg_precondition(DevAmg& amg, const double* r, double* z, hipStream_t s);
 // level-0 right-hand sides, amg_input32(amg, 0) (u part) and amg_input32(amg, 1) (phi part).
 void amg_precondition32(DevAmg& amg, const double* r, float* z, hipStream_t s);
 float* amg_input32(DevAmg& amg, int blk);
+// Graph replay of the two V-cycles (captured on first use after a setup): the input is read
+// from amg_graph_input (the caller stages M^-1's argument there, in the hierarchy's precision,
+// solve order) and the result left in amg_graph_output.
+void amg_precondition_graph(DevAmg& amg, hipStream_t s);
+void* amg_graph_input(DevAmg& amg);
+void* amg_graph_output(DevAmg& amg);
 void amg_level_export(DevAmg& amg, int blk, int level, int which, int64_t& n_rows, int64_t& n_cols,
                       std::vector<int64_t>& rp, std::vector<int32_t>& ci, std::vector<double>& vv, hipStream_t s);
 void amg_info(DevAmg& amg, int blk, int level, int& n_levels, int64_t& rows, int& bsize, int64_t& nnzb,
@@ -184,9 +206,27 @@ void amg_info(DevAmg& amg, int blk, int level, int& n_levels, int64_t& rows, int
 // ---- Krylov (krylov.hip) ----------------------------------------------------------------
 constexpr int kInitBasis = 24;                   // initial Krylov basis capacity (vectors)
 
+// Per-iteration convergence summary read back asynchronously (pinned host ring).
+struct IterSummary {
+    int all_done;      // every instance converged or stopped
+    int pad;
+    double ratio;      // largest |residual estimate| / target over the running instances
+};
+
 struct DevKrylov {
     int64_t n = 0;
     int m = 0, n_inst = 0, nb = 0;
+    DBuf<IterSummary> dsum;                      // device summary of the last iteration
+    IterSummary* hsum = nullptr;                 // [2] pinned host ring
+    hipEvent_t ev_sum[2] = {nullptr, nullptr};
+    DevKrylov() = default;
+    DevKrylov(const DevKrylov&) = delete;
+    DevKrylov& operator=(const DevKrylov&) = delete;
+    ~DevKrylov() {
+        for (auto& e : ev_sum)
+            if (e) { (void)hipEventSynchronize(e); (void)hipEventDestroy(e); }
+        if (hsum) (void)hipHostFree(hsum);
+    }
     int cap = 0;                                 // vectors held in Z (V holds cap + 1)
     bool z32 = false;                            // Z kept in FP32 (FP32 preconditioner)
     DBuf<double> V, Z, w, part, state;
