@@ -314,10 +314,10 @@ __global__ void __launch_bounds__(128) k_jacobian(MeshView mv, Params prm0, cons
         double ue[NV][D], pe[NV], pte[NV];
 #pragma unroll
         for (int b = 0; b < NV; ++b) gather_node<D, HANG>(mv, mv.cells[int64_t(cell) * NV + b], u, phi, pt, ue[b], pe[b], pte[b]);
-        // per Gauss point: degradation, phi, stress and the reaction coefficient
-        double gq[NV], cphi[NV], pphi[NV], react[NV], sig[NV][D][D];
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
+        // Gauss-point fields: degradation, phi, stress, reaction coefficient.  In 2d they are
+        // kept for all points; in 3d (8 points x a 3x3 stress) keeping them spills registers,
+        // so each column b recomputes them point by point (same operations, same order).
+        auto qp_fields = [&](int q, double (&sg)[D][D], double& g_, double& cp_, double& pp_, double& re_) {
             double gu[D][D];
             double ph = 0.0, pq = 0.0;
 #pragma unroll
@@ -325,25 +325,31 @@ __global__ void __launch_bounds__(128) k_jacobian(MeshView mv, Params prm0, cons
 #pragma unroll
                 for (int k = 0; k < D; ++k) gu[c][k] = 0.0;
 #pragma unroll
-            for (int b = 0; b < NV; ++b) {
-                const double nb = shp<D>(q, b);
-                ph += nb * pe[b];
-                pq += nb * pte[b];
+            for (int b2 = 0; b2 < NV; ++b2) {
+                const double nb = shp<D>(q, b2);
+                ph += nb * pe[b2];
+                pq += nb * pte[b2];
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
-                    const double db = dshp<D>(q, b, k, ih);
+                    const double db = dshp<D>(q, b2, k, ih);
 #pragma unroll
-                    for (int c = 0; c < D; ++c) gu[c][k] += db * ue[b][c];
+                    for (int c = 0; c < D; ++c) gu[c][k] += db * ue[b2][c];
                 }
             }
-            double s, tr;
-            strain_stress<D>(gu, prm.mu, prm.lam, sig[q], s, tr);
-            gq[q] = (1.0 - prm.kappa) * pq * pq + prm.kappa;
-            cphi[q] = 2.0 * (1.0 - prm.kappa) * ph;
-            pphi[q] = 2.0 * prm.p * ph;
-            react[q] = (1.0 - prm.kappa) * s + 2.0 * prm.p * tr + prm.Gc / prm.eps;
-        }
+            double s_, tr;
+            strain_stress<D>(gu, prm.mu, prm.lam, sg, s_, tr);
+            g_ = (1.0 - prm.kappa) * pq * pq + prm.kappa;
+            cp_ = 2.0 * (1.0 - prm.kappa) * ph;
+            pp_ = 2.0 * prm.p * ph;
+            re_ = (1.0 - prm.kappa) * s_ + 2.0 * prm.p * tr + prm.Gc / prm.eps;
+        };
+        constexpr int NQ = D == 2 ? NV : 1;   // Gauss points whose fields are kept
+        double gq[NQ], cphi[NQ], pphi[NQ], react[NQ], sig[NQ][D][D];
+        if constexpr (D == 2) {
 #pragma unroll
+            for (int q = 0; q < NV; ++q) qp_fields(q, sig[q], gq[q], cphi[q], pphi[q], react[q]);
+        }
+#pragma unroll(D == 2 ? NV : 1)
         for (int b = 0; b < NV; ++b) {
             double kuu[D][D], kpu[D], kpp = 0.0;
 #pragma unroll
@@ -352,8 +358,21 @@ __global__ void __launch_bounds__(128) k_jacobian(MeshView mv, Params prm0, cons
 #pragma unroll
                 for (int d = 0; d < D; ++d) kuu[c][d] = 0.0;
             }
-#pragma unroll
+#pragma unroll(D == 2 ? NV : 2)
             for (int q = 0; q < NV; ++q) {
+                double sq[D][D], g, cp, pp, re;
+                if constexpr (D == 2) {
+                    g = gq[q];
+                    cp = cphi[q];
+                    pp = pphi[q];
+                    re = react[q];
+#pragma unroll
+                    for (int c = 0; c < D; ++c)
+#pragma unroll
+                        for (int k = 0; k < D; ++k) sq[c][k] = sig[q][c][k];
+                } else {
+                    qp_fields(q, sq, g, cp, pp, re);
+                }
                 const double na = shp<D>(q, a), nb = shp<D>(q, b);
                 double dna[D], dnb[D], dot = 0.0;
 #pragma unroll
@@ -362,7 +381,6 @@ __global__ void __launch_bounds__(128) k_jacobian(MeshView mv, Params prm0, cons
                     dnb[k] = dshp<D>(q, b, k, ih);
                     dot += dna[k] * dnb[k];
                 }
-                const double g = gq[q];
 #pragma unroll
                 for (int c = 0; c < D; ++c)
 #pragma unroll
@@ -372,10 +390,10 @@ __global__ void __launch_bounds__(128) k_jacobian(MeshView mv, Params prm0, cons
                 for (int d = 0; d < D; ++d) {
                     double t = 0.0;
 #pragma unroll
-                    for (int k = 0; k < D; ++k) t += sig[q][d][k] * dnb[k];
-                    kpu[d] += (cphi[q] * t + pphi[q] * dnb[d]) * na;
+                    for (int k = 0; k < D; ++k) t += sq[d][k] * dnb[k];
+                    kpu[d] += (cp * t + pp * dnb[d]) * na;
                 }
-                kpp += react[q] * nb * na + prm.Gc * prm.eps * dot;
+                kpp += re * nb * na + prm.Gc * prm.eps * dot;
             }
             const int kk = mv.ent_k[int64_t(e) * NV + b];
             if (kk != 255) {
