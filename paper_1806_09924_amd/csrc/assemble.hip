@@ -64,6 +64,8 @@ struct MeshView {
     const uint8_t* ent_a;
     const uint8_t* ent_k;
     const double* ent_w;
+    const int32_t* hang_ptr;       // masters' row positions for hanging vertices (hanging meshes)
+    const uint8_t* hang_k;
     int C;
     int64_t n_free;
     const int32_t* inst_of_free;   // nullptr for one instance
@@ -80,6 +82,7 @@ MeshView view(const DevMesh& m) {
     v.slice_ptr = m.graph->slice_ptr; v.row_len = m.graph->row_len; v.col = m.graph->col;
     v.ent_ptr = m.ent_ptr.p; v.ent_cell = m.ent_cell.p; v.ent_a = m.ent_a.p; v.ent_k = m.ent_k.p;
     v.ent_w = m.ent_w.p;
+    v.hang_ptr = m.hang_ptr.p; v.hang_k = m.hang_k.p;
     v.C = m.graph->C;
     v.n_free = m.n_free;
     v.inst_of_free = m.n_inst > 1 ? m.inst_of_free.p : nullptr;
@@ -142,7 +145,7 @@ __device__ __forceinline__ void strain_stress(const double (&gu)[D][D], double m
 }
 
 // ---- residual + lumped mass -------------------------------------------------------------
-template <int D, bool HANG>
+template <int D>
 __global__ void __launch_bounds__(256) k_residual(MeshView mv, Params prm0, const double* __restrict__ u,
                                                   const double* __restrict__ phi, const double* __restrict__ pt,
                                                   double* __restrict__ R, double* __restrict__ B) {
@@ -166,7 +169,7 @@ __global__ void __launch_bounds__(256) k_residual(MeshView mv, Params prm0, cons
         W *= w;
         double ue[NV][D], pe[NV], pte[NV];
 #pragma unroll
-        for (int b = 0; b < NV; ++b) gather_node<D, HANG>(mv, mv.cells[int64_t(cell) * NV + b], u, phi, pt, ue[b], pe[b], pte[b]);
+        for (int b = 0; b < NV; ++b) gather_node<D, false>(mv, mv.cells[int64_t(cell) * NV + b], u, phi, pt, ue[b], pe[b], pte[b]);
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             double gu[D][D], gp[D];
@@ -271,14 +274,9 @@ __device__ __forceinline__ int64_t slot_of(const MeshView& mv, int64_t f, int k)
     return int64_t(mv.slice_ptr[f / mv.C]) + int64_t(k) * mv.C + (f % mv.C);
 }
 
-template <int D>
-__device__ __forceinline__ int find_k(const MeshView& mv, int64_t f, int32_t g) {
-    const int len = mv.row_len[f];
-    for (int k = 0; k < len; ++k)
-        if (mv.col[slot_of<D>(mv, f, k)] == g) return k;
-    return -1;
-}
-
+// One thread per free row.  u, phi, pt hold every vertex's value (hanging ones filled); with
+// HANG the columns of hanging vertices are distributed to their masters, whose row positions
+// come from the pattern's hang_k table.
 template <int D, bool HANG>
 __global__ void __launch_bounds__(128) k_jacobian(MeshView mv, Params prm0, const double* __restrict__ u,
                                                   const double* __restrict__ phi, const double* __restrict__ phi_old,
@@ -293,6 +291,7 @@ __global__ void __launch_bounds__(128) k_jacobian(MeshView mv, Params prm0, cons
     const Params prm = row_params(mv, prm0, f);
     const int64_t sl = f / mv.C;
     const int width = (mv.slice_ptr[sl + 1] - mv.slice_ptr[sl]) / mv.C;
+    int32_t hc = HANG ? mv.hang_ptr[f] : 0;   // next master position of a hanging vertex
     for (int k = 0; k < width; ++k) {
         const int64_t s = slot_of<D>(mv, f, k);
 #pragma unroll
@@ -313,11 +312,24 @@ __global__ void __launch_bounds__(128) k_jacobian(MeshView mv, Params prm0, cons
         W *= w;
         double ue[NV][D], pe[NV], pte[NV];
 #pragma unroll
-        for (int b = 0; b < NV; ++b) gather_node<D, HANG>(mv, mv.cells[int64_t(cell) * NV + b], u, phi, pt, ue[b], pe[b], pte[b]);
-        // Gauss-point fields: degradation, phi, stress, reaction coefficient.  In 2d they are
-        // kept for all points; in 3d (8 points x a 3x3 stress) keeping them spills registers,
-        // so each column b recomputes them point by point (same operations, same order).
-        auto qp_fields = [&](int q, double (&sg)[D][D], double& g_, double& cp_, double& pp_, double& re_) {
+        for (int b = 0; b < NV; ++b) gather_node<D, false>(mv, mv.cells[int64_t(cell) * NV + b], u, phi, pt, ue[b], pe[b], pte[b]);
+        // Gauss-point fields folded with the row's vertex a, which is fixed for the entry:
+        //   Ga[q][k] = g_q dN_a/dx_k,  Sa[q] = N_a (cp_q sigma_q + pp_q I) (symmetric, packed),
+        //   ra[q] = N_a re_q.
+        // A column b then needs T[k][l] = sum_q Ga[q][k] dN_b/dx_l (which gives the u-u block),
+        // sum_q Sa[q] grad N_b (the phi-u row) and sum_q ra[q] N_b (the phi-phi reaction term).
+        constexpr int NS = D * (D + 1) / 2;
+        double Ga[NV][D], Sa[NV][NS], ra[NV];
+        double va[2][D], sa[D];
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            const bool am = (a >> m) & 1;
+            va[0][m] = am ? kGM : kGP;   // 1d factor of N_a at the abscissa of bit 0 / bit 1
+            va[1][m] = am ? kGP : kGM;
+            sa[m] = am ? ih : -ih;
+        }
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
             double gu[D][D];
             double ph = 0.0, pq = 0.0;
 #pragma unroll
@@ -336,65 +348,94 @@ __global__ void __launch_bounds__(128) k_jacobian(MeshView mv, Params prm0, cons
                     for (int c = 0; c < D; ++c) gu[c][k] += db * ue[b2][c];
                 }
             }
-            double s_, tr;
+            double sg[D][D], s_, tr;
             strain_stress<D>(gu, prm.mu, prm.lam, sg, s_, tr);
-            g_ = (1.0 - prm.kappa) * pq * pq + prm.kappa;
-            cp_ = 2.0 * (1.0 - prm.kappa) * ph;
-            pp_ = 2.0 * prm.p * ph;
-            re_ = (1.0 - prm.kappa) * s_ + 2.0 * prm.p * tr + prm.Gc / prm.eps;
-        };
-        constexpr int NQ = D == 2 ? NV : 1;   // Gauss points whose fields are kept
-        double gq[NQ], cphi[NQ], pphi[NQ], react[NQ], sig[NQ][D][D];
-        if constexpr (D == 2) {
+            const double g = (1.0 - prm.kappa) * pq * pq + prm.kappa;
+            const double cp = 2.0 * (1.0 - prm.kappa) * ph;
+            const double pp = 2.0 * prm.p * ph;
+            const double re = (1.0 - prm.kappa) * s_ + 2.0 * prm.p * tr + prm.Gc / prm.eps;
+            double na = 1.0;
 #pragma unroll
-            for (int q = 0; q < NV; ++q) qp_fields(q, sig[q], gq[q], cphi[q], pphi[q], react[q]);
+            for (int m = 0; m < D; ++m) na *= va[(q >> m) & 1][m];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                double dk = sa[k];
+#pragma unroll
+                for (int m = 0; m < D; ++m)
+                    if (m != k) dk *= va[(q >> m) & 1][m];
+                Ga[q][k] = g * dk;
+            }
+            int i = 0;
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+#pragma unroll
+                for (int k = c; k < D; ++k) Sa[q][i++] = na * (cp * sg[c][k] + (c == k ? pp : 0.0));
+            ra[q] = na * re;
         }
 #pragma unroll(D == 2 ? NV : 1)
         for (int b = 0; b < NV; ++b) {
-            double kuu[D][D], kpu[D], kpp = 0.0;
+            double vb[2][D], sb[D];
+#pragma unroll
+            for (int m = 0; m < D; ++m) {
+                const bool bm = (b >> m) & 1;
+                vb[0][m] = bm ? kGM : kGP;
+                vb[1][m] = bm ? kGP : kGM;
+                sb[m] = bm ? ih : -ih;
+            }
+            double T[D][D], kpu[D], kpp = 0.0;
 #pragma unroll
             for (int c = 0; c < D; ++c) {
                 kpu[c] = 0.0;
 #pragma unroll
-                for (int d = 0; d < D; ++d) kuu[c][d] = 0.0;
+                for (int d = 0; d < D; ++d) T[c][d] = 0.0;
             }
-#pragma unroll(D == 2 ? NV : 2)
+#pragma unroll
             for (int q = 0; q < NV; ++q) {
-                double sq[D][D], g, cp, pp, re;
-                if constexpr (D == 2) {
-                    g = gq[q];
-                    cp = cphi[q];
-                    pp = pphi[q];
-                    re = react[q];
+                double nb = 1.0, dnb[D];
 #pragma unroll
-                    for (int c = 0; c < D; ++c)
-#pragma unroll
-                        for (int k = 0; k < D; ++k) sq[c][k] = sig[q][c][k];
-                } else {
-                    qp_fields(q, sq, g, cp, pp, re);
-                }
-                const double na = shp<D>(q, a), nb = shp<D>(q, b);
-                double dna[D], dnb[D], dot = 0.0;
+                for (int m = 0; m < D; ++m) nb *= vb[(q >> m) & 1][m];
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
-                    dna[k] = dshp<D>(q, a, k, ih);
-                    dnb[k] = dshp<D>(q, b, k, ih);
-                    dot += dna[k] * dnb[k];
+                    double dk = sb[k];
+#pragma unroll
+                    for (int m = 0; m < D; ++m)
+                        if (m != k) dk *= vb[(q >> m) & 1][m];
+                    dnb[k] = dk;
                 }
 #pragma unroll
-                for (int c = 0; c < D; ++c)
+                for (int k = 0; k < D; ++k)
 #pragma unroll
-                    for (int d = 0; d < D; ++d)
-                        kuu[c][d] += g * (prm.mu * ((c == d ? dot : 0.0) + dnb[c] * dna[d]) + prm.lam * dnb[d] * dna[c]);
+                    for (int l = 0; l < D; ++l) T[k][l] += Ga[q][k] * dnb[l];
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
-                    double t = 0.0;
 #pragma unroll
-                    for (int k = 0; k < D; ++k) t += sq[d][k] * dnb[k];
-                    kpu[d] += (cp * t + pp * dnb[d]) * na;
+                    for (int k = 0; k < D; ++k) {
+                        const int lo = d < k ? d : k, hi = d < k ? k : d;
+                        kpu[d] += Sa[q][lo * D - lo * (lo - 1) / 2 + (hi - lo)] * dnb[k];
+                    }
                 }
-                kpp += re * nb * na + prm.Gc * prm.eps * dot;
+                kpp += ra[q] * nb;
             }
+            // Laplacian term: the 2-point rule is exact for Q1 gradient products, so
+            // sum_q grad N_a . grad N_b = ih^2 sum_k s_k 2 prod_{m != k} (2/3 or 1/3)
+            double lap = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                double t = (((a ^ b) >> k) & 1) ? -2.0 : 2.0;
+#pragma unroll
+                for (int m = 0; m < D; ++m)
+                    if (m != k) t *= (((a ^ b) >> m) & 1) ? (1.0 / 3.0) : (2.0 / 3.0);
+                lap += t;
+            }
+            kpp += prm.Gc * prm.eps * lap * ih * ih;
+            double trT = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) trT += T[k][k];
+            double kuu[D][D];
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+#pragma unroll
+                for (int d = 0; d < D; ++d) kuu[c][d] = prm.mu * ((c == d ? trT : 0.0) + T[d][c]) + prm.lam * T[c][d];
             const int kk = mv.ent_k[int64_t(e) * NV + b];
             if (kk != 255) {
                 const int64_t s = slot_of<D>(mv, f, kk);
@@ -408,8 +449,7 @@ __global__ void __launch_bounds__(128) k_jacobian(MeshView mv, Params prm0, cons
             } else if (HANG) {
                 const int32_t n = mv.cells[int64_t(cell) * NV + b];
                 for (int32_t j = mv.con_ptr[n]; j < mv.con_ptr[n + 1]; ++j) {
-                    const int k2 = find_k<D>(mv, f, mv.con_master[j]);
-                    if (k2 < 0) continue;
+                    const int k2 = mv.hang_k[hc++];
                     const double ww = W * mv.con_w[j];
                     const int64_t s = slot_of<D>(mv, f, k2);
 #pragma unroll
@@ -565,6 +605,36 @@ __global__ void k_fill_hanging(int64_t nn, int D, const int32_t* __restrict__ fr
     }
     for (int c = 0; c < D; ++c) u[n * D + c] = uu[c];
     phi[n] = pp;
+}
+
+// Nodal u, phi, phi~ with the hanging values interpolated from the free masters, so that the
+// element kernels gather every vertex directly (the user arrays are only read at free nodes).
+template <int D>
+__global__ void __launch_bounds__(256) k_nodal_fill(int64_t nn, const int32_t* __restrict__ free_of_node,
+                                                    const int32_t* __restrict__ node_of_free,
+                                                    const int32_t* __restrict__ con_ptr,
+                                                    const int32_t* __restrict__ con_master,
+                                                    const double* __restrict__ con_w, const double* __restrict__ u,
+                                                    const double* __restrict__ phi, const double* __restrict__ pt,
+                                                    double* __restrict__ uo, double* __restrict__ po,
+                                                    double* __restrict__ pto) {
+    const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    double uu[D], pp = 0.0, tt = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) uu[c] = 0.0;
+    for (int32_t j = con_ptr[n]; j < con_ptr[n + 1]; ++j) {
+        const int64_t src = node_of_free[con_master[j]];
+        const double w = con_w[j];
+#pragma unroll
+        for (int c = 0; c < D; ++c) uu[c] += w * u[src * D + c];
+        pp += w * phi[src];
+        if (pt) tt += w * pt[src];
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) uo[n * D + c] = uu[c];
+    po[n] = pp;
+    if (pt) pto[n] = tt;
 }
 
 // ---- functionals --------------------------------------------------------------------------
@@ -737,24 +807,46 @@ std::unique_ptr<DevMesh> mesh_create(const fr_mesh_desc* d, int n_inst, hipStrea
     m->ent_a.upload(p.ent_a, s);
     m->ent_k.upload(p.ent_k, s);
     m->ent_w.upload(p.ent_w, s);
+    if (!p.hang_k.empty()) {
+        m->hang_ptr.upload(p.hang_ptr, s);
+        m->hang_k.upload(p.hang_k, s);
+    }
     FR_HIP(hipStreamSynchronize(s));   // host vectors of the pattern stay alive in m
     return m;
 }
 
 static int blocks_for(int64_t n, int t) { return int(ceil_div(n, t)); }
 
+// Hanging meshes: fills sys.nodal and redirects u, phi, pt (pt stays null when null) to it.
+static void nodal_fill(DevSystem& sys, const double*& u, const double*& phi, const double*& pt) {
+    DevMesh& m = *sys.mesh;
+    const hipStream_t s = sys.stream;
+    const int64_t nn = m.n_nodes;
+    sys.nodal.reserve(size_t(nn) * size_t(m.dim + 2), s);
+    double* uo = sys.nodal.p;
+    double* po = uo + nn * m.dim;
+    double* pto = po + nn;
+    const int nb = blocks_for(nn, 256);
+    if (m.dim == 2)
+        k_nodal_fill<2><<<nb, 256, 0, s>>>(nn, m.free_of_node.p, m.node_of_free.p, m.con_ptr.p, m.con_master.p,
+                                           m.con_w.p, u, phi, pt, uo, po, pto);
+    else
+        k_nodal_fill<3><<<nb, 256, 0, s>>>(nn, m.free_of_node.p, m.node_of_free.p, m.con_ptr.p, m.con_master.p,
+                                           m.con_w.p, u, phi, pt, uo, po, pto);
+    FR_LAUNCH_CHECK();
+    u = uo;
+    phi = po;
+    if (pt) pt = pto;
+}
+
 void assemble_residual(DevSystem& sys, const double* u, const double* phi, const double* pt) {
     DevMesh& m = *sys.mesh;
     MeshView mv = view(sys);
     const hipStream_t s = sys.stream;
     const int nb = blocks_for(m.n_free, 256);
-    if (m.dim == 2) {
-        if (m.hanging) k_residual<2, true><<<nb, 256, 0, s>>>(mv, sys.prm, u, phi, pt, sys.R.p, sys.B.p);
-        else k_residual<2, false><<<nb, 256, 0, s>>>(mv, sys.prm, u, phi, pt, sys.R.p, sys.B.p);
-    } else {
-        if (m.hanging) k_residual<3, true><<<nb, 256, 0, s>>>(mv, sys.prm, u, phi, pt, sys.R.p, sys.B.p);
-        else k_residual<3, false><<<nb, 256, 0, s>>>(mv, sys.prm, u, phi, pt, sys.R.p, sys.B.p);
-    }
+    if (m.hanging) nodal_fill(sys, u, phi, pt);
+    if (m.dim == 2) k_residual<2><<<nb, 256, 0, s>>>(mv, sys.prm, u, phi, pt, sys.R.p, sys.B.p);
+    else k_residual<3><<<nb, 256, 0, s>>>(mv, sys.prm, u, phi, pt, sys.R.p, sys.B.p);
     FR_LAUNCH_CHECK();
     sys.have_residual = true;
 }
@@ -793,6 +885,7 @@ void assemble_jacobian(DevSystem& sys, const double* u, const double* phi, const
     MeshView mv = view(sys);
     const hipStream_t s = sys.stream;
     const int nb = blocks_for(m.n_free, 128);
+    if (m.hanging) nodal_fill(sys, u, phi, pt);
     if (m.dim == 2) {
         if (m.hanging)
             k_jacobian<2, true><<<nb, 128, 0, s>>>(mv, sys.prm, u, phi, phi_old, pt, sys.R.p, sys.active.p, sys.Juu.val,

@@ -691,6 +691,47 @@ Pattern build_pattern(const HostMesh& m, int C) {
             }
         }
     });
+    if (m.n_hanging > 0) {
+        // masters of hanging vertices: counted per row, then located in the row's columns
+        p.hang_ptr.assign(size_t(nf) + 1, 0);
+        parallel_ranges(nf, [&](int64_t f0, int64_t f1, int) {
+            for (int64_t f = f0; f < f1; ++f) {
+                int64_t c = 0;
+                for (int32_t e = p.ent_ptr[size_t(f)]; e < p.ent_ptr[size_t(f) + 1]; ++e)
+                    for (int b = 0; b < nv; ++b)
+                        if (p.ent_k[size_t(e) * nv + b] == 255) {
+                            const int32_t n = m.cells[size_t(p.ent_cell[size_t(e)]) * nv + b];
+                            c += m.con_ptr[size_t(n) + 1] - m.con_ptr[size_t(n)];
+                        }
+                p.hang_ptr[size_t(f) + 1] = int32_t(c);
+            }
+        });
+        int64_t tot = 0;
+        for (int64_t f = 0; f < nf; ++f) {
+            tot += p.hang_ptr[size_t(f) + 1];
+            if (tot >= (int64_t(1) << 31)) fail(FR_EINTERNAL, "pattern: more than 2^31 hanging-column entries");
+            p.hang_ptr[size_t(f) + 1] = int32_t(tot);
+        }
+        p.hang_k.resize(size_t(tot));
+        parallel_ranges(nf, [&](int64_t f0, int64_t f1, int) {
+            for (int64_t f = f0; f < f1; ++f) {
+                const int32_t* cb = col_all.data() + col_ptr[size_t(f)];
+                const int32_t* ce = col_all.data() + col_ptr[size_t(f) + 1];
+                size_t o = size_t(p.hang_ptr[size_t(f)]);
+                for (int32_t e = p.ent_ptr[size_t(f)]; e < p.ent_ptr[size_t(f) + 1]; ++e)
+                    for (int b = 0; b < nv; ++b) {
+                        if (p.ent_k[size_t(e) * nv + b] != 255) continue;
+                        const int32_t n = m.cells[size_t(p.ent_cell[size_t(e)]) * nv + b];
+                        for (int32_t j = m.con_ptr[size_t(n)]; j < m.con_ptr[size_t(n) + 1]; ++j) {
+                            const int32_t g = m.con_master[size_t(j)];
+                            const int32_t* it = std::lower_bound(cb, ce, g);
+                            if (it == ce || *it != g) fail(FR_EINTERNAL, "pattern: hanging master missing from its row");
+                            p.hang_k[o++] = uint8_t(it - cb);
+                        }
+                    }
+            }
+        });
+    }
     // SELL-C layout (no row sorting: the node numbering already groups similar rows)
     p.n_slices = ceil_div(nf, C);
     p.slice_ptr.assign(size_t(p.n_slices) + 1, 0);

@@ -45,6 +45,11 @@ struct Pattern {
     std::vector<uint8_t> ent_a;       // [n_ent] local vertex of the row node (or of its hanging dependent)
     std::vector<double> ent_w;        // [n_ent] weight of the row's basis function at that vertex
     std::vector<uint8_t> ent_k;       // [n_ent][nv] position of vertex b's node in the row, 255 = hanging
+    // Hanging vertices (ent_k == 255): row positions of their masters, in the order the row
+    // meets them (entries, then vertices b, then the vertex's constraint masters).  Empty
+    // without hanging nodes.
+    std::vector<int32_t> hang_ptr;    // [n_rows+1]
+    std::vector<uint8_t> hang_k;      // [hang_ptr[n_rows]]
 };
 
 HostMesh build_mesh(const fr_mesh_desc& d);

@@ -58,7 +58,8 @@ struct DevMesh {
     DBuf<uint8_t> dir_free;                      // Dirichlet flag per free node
     std::shared_ptr<SellStruct> graph;           // node graph (free x free)
     DBuf<int32_t> ent_ptr, ent_cell;
-    DBuf<uint8_t> ent_a, ent_k;
+    DBuf<uint8_t> ent_a, ent_k, hang_k;
+    DBuf<int32_t> hang_ptr;
     DBuf<double> ent_w;
 };
 
@@ -77,6 +78,7 @@ struct DevSystem {
     DBuf<uint8_t> active, active_prev, frozen;   // per free node
     DBuf<double> red;                            // reduction scratch
     DBuf<int32_t> ired;
+    DBuf<double> nodal;                          // hanging meshes: u, phi, phi~ with hanging values filled
     bool have_residual = false, have_active = false, have_jacobian = false;
     int64_t last_changes = 0;
     double last_min_margin = 0.0;
