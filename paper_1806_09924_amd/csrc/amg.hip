@@ -498,6 +498,70 @@ __global__ void __launch_bounds__(256) k_spgemm_fill(SellV A, SellV B, SellV Cm,
     for (int k = n + lg; k < width; k += G) ccol[sslot(Cm.sp, Cm.C, r, k)] = f;
 }
 
+// Symbolic phase for few, long rows over few columns (coarse levels): a workgroup per output
+// row marks the reached columns in an LDS bitmap (bitwise or, so the set does not depend on
+// the order of the marks), then counts them, or writes them in increasing order from
+// per-thread chunks of words placed by a prefix sum over the threads.  Padding slots repeat
+// the smallest column, as in the hashed kernels.
+template <bool FILL>
+__global__ void __launch_bounds__(256) k_spgemm_bitmap(SellV A, SellV B, SellV Cm, int32_t* __restrict__ clen,
+                                                       int32_t* __restrict__ ccol, int n_words) {
+    extern __shared__ uint32_t bits[];
+    __shared__ int32_t part[256];
+    __shared__ int32_t first_sh[256];
+    const int64_t r = blockIdx.x;
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int i = t; i < n_words; i += nt) bits[i] = 0u;
+    __syncthreads();
+    const int la = A.len[r];
+    for (int ka = 0; ka < la; ++ka) {
+        const int64_t k = A.col[sslot(A.sp, A.C, r, ka)];
+        const int lb = B.len[k];
+        for (int kb = t; kb < lb; kb += nt) {
+            const int32_t c = B.col[sslot(B.sp, B.C, k, kb)];
+            atomicOr(&bits[c >> 5], 1u << (c & 31));
+        }
+    }
+    __syncthreads();
+    const int per = (n_words + nt - 1) / nt;
+    const int w0 = min(n_words, t * per), w1 = min(n_words, w0 + per);
+    int cnt = 0, first = 0x7fffffff;
+    for (int w = w0; w < w1; ++w) {
+        const uint32_t m = bits[w];
+        if (m && first == 0x7fffffff) first = w * 32 + __builtin_ctz(m);
+        cnt += __builtin_popcount(m);
+    }
+    part[t] = cnt;
+    first_sh[t] = first;
+    __syncthreads();
+    // inclusive scan of the counts and minimum of the first columns (Hillis-Steele)
+    for (int o = 1; o < nt; o <<= 1) {
+        const int a = t >= o ? part[t - o] : 0;
+        const int f = t >= o ? first_sh[t - o] : 0x7fffffff;
+        __syncthreads();
+        part[t] += a;
+        first_sh[t] = min(first_sh[t], f);
+        __syncthreads();
+    }
+    const int total = part[nt - 1];
+    if (!FILL) {
+        if (t == 0) clen[r] = total;
+        return;
+    }
+    int pos = part[t] - cnt;
+    for (int w = w0; w < w1; ++w) {
+        uint32_t m = bits[w];
+        while (m) {
+            ccol[sslot(Cm.sp, Cm.C, r, pos++)] = w * 32 + __builtin_ctz(m);
+            m &= m - 1u;
+        }
+    }
+    const int32_t f = total > 0 ? first_sh[nt - 1] : 0;
+    const int64_t s0 = r / Cm.C;
+    const int width = (Cm.sp[s0 + 1] - Cm.sp[s0]) / Cm.C;
+    for (int k = total + t; k < width; k += nt) ccol[sslot(Cm.sp, Cm.C, r, k)] = f;
+}
+
 // Symbolic phase of A B when every row of B has at most one block (a tentative prolongator):
 // the columns of row r are the distinct B columns of the rows A's row r touches.  G lanes
 // per row (G >= the longest row of A), lane g takes entry g; the group sorts its values by a
@@ -828,7 +892,8 @@ __global__ void __launch_bounds__(256) k_spgemm_merge(SellV A, const double* __r
                                                       const double* __restrict__ bv, SellV Cm, double* __restrict__ cv,
                                                       const double* __restrict__ invd, double omega, int LC) {
     extern __shared__ double smem[];
-    constexpr int RPW = kWave / G, RPB = kWavesPerBlock * RPW, BB = BRA * BCB;
+    constexpr int RPW = kWave / G, BB = BRA * BCB;
+    const int RPB = int(blockDim.x / kWave) * RPW;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, gi = lane / G, lg = lane % G;
     const int slot_in_block = w * RPW + gi;
     double* acc = smem + size_t(slot_in_block) * LC * BB;
@@ -895,6 +960,67 @@ __global__ void __launch_bounds__(256) k_spgemm_merge(SellV A, const double* __r
     }
 }
 
+// Dense-row numeric phase for few, long output rows (coarse levels, where C has few block
+// columns): a workgroup owns one output row and accumulates it over all of C's columns in
+// LDS.  For every entry A_ik in turn the lanes walk row k of B (distinct columns, so no two
+// lanes add to one accumulator) and a barrier separates the entries, so the summation order
+// of every output block is A's column order, as in the row-merge kernel.
+template <int BRA, int BCA, int BCB, int MODE>
+__global__ void __launch_bounds__(256) k_spgemm_dense_row(SellV A, const double* __restrict__ av, SellV B,
+                                                          const double* __restrict__ bv, SellV Cm,
+                                                          double* __restrict__ cv, const double* __restrict__ invd,
+                                                          double omega, int n_cols) {
+    extern __shared__ double acc[];
+    constexpr int BB = BRA * BCB;
+    const int64_t r = blockIdx.x;
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int i = t; i < n_cols * BB; i += nt) acc[i] = 0.0;
+    __syncthreads();
+    const int la = A.len[r];
+    for (int ka = 0; ka < la; ++ka) {
+        const int64_t as = sslot(A.sp, A.C, r, ka);
+        const int64_t k = A.col[as];
+        double ab[BRA * BCA];
+        for (int e = 0; e < BRA * BCA; ++e) ab[e] = av[as * (BRA * BCA) + e];
+        const int lb = B.len[k];
+        for (int kb = t; kb < lb; kb += nt) {
+            const int64_t bs = sslot(B.sp, B.C, k, kb);
+            const int32_t c = B.col[bs];
+            const double* bb = bv + bs * (BCA * BCB);
+            for (int i = 0; i < BRA; ++i)
+                for (int j = 0; j < BCB; ++j) {
+                    double x = 0.0;
+                    for (int q = 0; q < BCA; ++q) x += ab[i * BCA + q] * bb[q * BCB + j];
+                    acc[c * BB + i * BCB + j] += x;
+                }
+        }
+        __syncthreads();
+    }
+    const int lc = Cm.len[r];
+    const int64_t s0 = r / Cm.C;
+    const int width = (Cm.sp[s0 + 1] - Cm.sp[s0]) / Cm.C;
+    for (int kc = t; kc < width; kc += nt) {
+        const int64_t cs = sslot(Cm.sp, Cm.C, r, kc);
+        if (kc < lc) {
+            const int32_t c = Cm.col[cs];
+            if (MODE == 1) {
+                const int kb = find_sorted(B, r, c);
+                for (int i = 0; i < BRA; ++i) {
+                    const double dsc = omega * invd[r * BRA + i];
+                    for (int j = 0; j < BCB; ++j) {
+                        const double own = kb >= 0 ? bv[sslot(B.sp, B.C, r, kb) * (BCA * BCB) + i * BCB + j] : 0.0;
+                        cv[cs * BB + i * BCB + j] = own - dsc * acc[c * BB + i * BCB + j];
+                    }
+                }
+            } else {
+                for (int e = 0; e < BB; ++e) cv[cs * BB + e] = acc[c * BB + e];
+            }
+        } else {
+            for (int e = 0; e < BB; ++e) cv[cs * BB + e] = 0.0;
+        }
+    }
+}
+
 template <int BRA, int BCA, int BCB, int MODE>
 void spgemm_numeric(const BMat<double>& A, const BMat<double>& B, BMat<double>& Cm, const double* invd, double omega,
                     hipStream_t s) {
@@ -904,12 +1030,32 @@ void spgemm_numeric(const BMat<double>& A, const BMat<double>& B, BMat<double>& 
     // rows of B are long enough to keep its lanes busy; a tentative prolongator (one block
     // per row) goes to the column-parallel kernel, whose lanes share the loads of A's row
     if (B.S->max_len > 1) {
-        constexpr int G = 16, RPB = kWavesPerBlock * (kWave / G), BB = BRA * BCB;
+        constexpr int BB = BRA * BCB;
+        constexpr size_t kLds = 64 * 1024;
+        // few long rows over few columns (coarse levels): a workgroup per row, dense in LDS
+        const int64_t nc = Cm.cols();
+        const int64_t avg_b = B.S->nnz / std::max<int64_t>(1, B.rows());
+        if (size_t(nc) * BB * sizeof(double) <= kLds && avg_b >= 64 && A.rows() > 0) {
+            k_spgemm_dense_row<BRA, BCA, BCB, MODE><<<int(A.rows()), 256, size_t(nc) * BB * sizeof(double), s>>>(
+                sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), Cm.val, invd, omega, int(nc));
+            FR_LAUNCH_CHECK();
+            return;
+        }
         int LC = 8;
         while (LC < ml) LC <<= 1;
-        const size_t lds = size_t(RPB) * LC * (BB * sizeof(double) + sizeof(int32_t));
-        if (ml <= 256 && lds <= 64 * 1024) {
-            k_spgemm_merge<BRA, BCA, BCB, MODE, G><<<nblk(rows, RPB), 256, lds, s>>>(
+        const size_t per_row = size_t(LC) * (BB * sizeof(double) + sizeof(int32_t));
+        constexpr int RPB16 = kWavesPerBlock * (kWave / 16);
+        if (ml <= 256 && RPB16 * per_row <= kLds) {
+            // 16 lanes per row, 16 rows per block
+            k_spgemm_merge<BRA, BCA, BCB, MODE, 16><<<nblk(rows, RPB16), 256, RPB16 * per_row, s>>>(
+                sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), Cm.val, invd, omega, LC);
+            FR_LAUNCH_CHECK();
+            return;
+        }
+        if (per_row <= kLds) {
+            // a wave per row: four rows per block when they fit, else one
+            const int wpb = kWavesPerBlock * per_row <= kLds ? kWavesPerBlock : 1;
+            k_spgemm_merge<BRA, BCA, BCB, MODE, kWave><<<nblk(rows, wpb), wpb * kWave, wpb * per_row, s>>>(
                 sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), Cm.val, invd, omega, LC);
             FR_LAUNCH_CHECK();
             return;
@@ -990,6 +1136,22 @@ BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* 
         FR_SINGLE_ALL(1)
 #undef FR_SINGLE_ALL
 #undef FR_SINGLE
+        Cm.own_val.alloc(size_t(std::max<int64_t>(1, Cm.S->n_slots)) * Cm.br * Cm.bc, s);
+        Cm.val = Cm.own_val.p;
+        spgemm_values<MODE>(A, B, Cm, invd, omega, s);
+        return Cm;
+    }
+    const int64_t avg_b = B.S->nnz / std::max<int64_t>(1, B.rows());
+    const int n_words = int(ceil_div(std::max<int64_t>(1, B.cols()), 32));
+    if (avg_b >= 64 && n_words <= 8192 && A.rows() > 0) {
+        // long rows of B over few columns: a workgroup per row with a column bitmap
+        const int g = int(A.rows());
+        const size_t lds = size_t(n_words) * sizeof(uint32_t);
+        k_spgemm_bitmap<false><<<g, 256, lds, s>>>(sv(*A.S), sv(*B.S), sv(*Cm.S), Cm.S->row_len, nullptr, n_words);
+        FR_LAUNCH_CHECK();
+        finish_struct(*Cm.S, s);
+        k_spgemm_bitmap<true><<<g, 256, lds, s>>>(sv(*A.S), sv(*B.S), sv(*Cm.S), nullptr, Cm.S->col, n_words);
+        FR_LAUNCH_CHECK();
         Cm.own_val.alloc(size_t(std::max<int64_t>(1, Cm.S->n_slots)) * Cm.br * Cm.bc, s);
         Cm.val = Cm.own_val.p;
         spgemm_values<MODE>(A, B, Cm, invd, omega, s);
