@@ -742,16 +742,18 @@ __global__ void __launch_bounds__(256) k_rank_rows(SellV Rm, const int32_t* __re
     }
 }
 
-// Values of R = P^T into an existing structure (one thread per row of R): entry (r, c) of R
-// is entry (c, r) of P, found by binary search in P's sorted row c.
-template <int BR, int BC>
-__global__ void k_transpose_values(SellV P, const double* __restrict__ pv, SellV Rm, double* __restrict__ rv) {
-    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+// Values of R = P^T into an existing structure (G lanes per row of R, over its entries):
+// entry (r, c) of R is entry (c, r) of P, found by binary search in P's sorted row c.
+template <int BR, int BC, int G>
+__global__ void __launch_bounds__(256) k_transpose_values(SellV P, const double* __restrict__ pv, SellV Rm,
+                                                          double* __restrict__ rv) {
+    const int64_t r = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / G;
+    const int lg = threadIdx.x % G;
     if (r >= Rm.n_rows) return;
     const int n = Rm.len[r];
     const int64_t s0 = r / Rm.C;
     const int width = (Rm.sp[s0 + 1] - Rm.sp[s0]) / Rm.C;
-    for (int k = 0; k < width; ++k) {
+    for (int k = lg; k < width; k += G) {
         const int64_t rs = sslot(Rm.sp, Rm.C, r, k);
         const int kp = k < n ? find_sorted(P, Rm.col[rs], int32_t(r)) : -1;
         const double* pb = kp >= 0 ? pv + sslot(P.sp, P.C, Rm.col[rs], kp) * (BR * BC) : nullptr;
@@ -960,6 +962,105 @@ __global__ void __launch_bounds__(256) k_spgemm_merge(SellV A, const double* __r
     }
 }
 
+__device__ __forceinline__ double read_lane(double x, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Numeric phase when every row of B has at most one block (B a tentative prolongator): entry
+// A_rk lands in column B.col[k] only.  A wave owns a row; lane j loads A's entry j of the
+// current chunk of 64 and forms its product block with row k_j of B; then every output
+// column (one per lane) adds, in A's column order, the products that land on it, read from
+// the owning lanes by readlane.
+template <int BRA, int BCA, int BCB, int MODE>
+__global__ void __launch_bounds__(256) k_spgemm_numeric_single(SellV A, const double* __restrict__ av, SellV B,
+                                                               const double* __restrict__ bv, SellV Cm,
+                                                               double* __restrict__ cv,
+                                                               const double* __restrict__ invd, double omega) {
+    constexpr int BB = BRA * BCB;
+    const int lane = threadIdx.x % kWave;
+    const int64_t r = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+    if (r >= Cm.n_rows) return;
+    const int la = A.len[r], lc = Cm.len[r];
+    const int64_t s0 = r / Cm.C;
+    const int width = (Cm.sp[s0 + 1] - Cm.sp[s0]) / Cm.C;
+    for (int kc0 = 0; kc0 < width; kc0 += kWave) {
+        const int kc = kc0 + lane;
+        const int64_t cs = kc < width ? sslot(Cm.sp, Cm.C, r, kc) : 0;
+        const int32_t c = kc < lc ? Cm.col[cs] : -1;
+        double acc[BB];
+#pragma unroll
+        for (int e = 0; e < BB; ++e) acc[e] = 0.0;
+        for (int j0 = 0; j0 < la; j0 += kWave) {
+            const int j = j0 + lane;
+            int32_t cj = -1;
+            double pj[BB];
+#pragma unroll
+            for (int e = 0; e < BB; ++e) pj[e] = 0.0;
+            if (j < la) {
+                const int64_t as = sslot(A.sp, A.C, r, j);
+                const int64_t k = A.col[as];
+                if (B.len[k] > 0) {
+                    const int64_t bs = sslot(B.sp, B.C, k, 0);
+                    cj = B.col[bs];
+                    const double* ab = av + as * (BRA * BCA);
+                    const double* bb = bv + bs * (BCA * BCB);
+#pragma unroll
+                    for (int i = 0; i < BRA; ++i)
+#pragma unroll
+                        for (int jj = 0; jj < BCB; ++jj) {
+                            double x = 0.0;
+#pragma unroll
+                            for (int q = 0; q < BCA; ++q) x += ab[i * BCA + q] * bb[q * BCB + jj];
+                            pj[i * BCB + jj] = x;
+                        }
+                }
+            }
+            const int nj = min(kWave, la - j0);
+            for (int t = 0; t < nj; ++t) {
+                const int32_t ct = __builtin_amdgcn_readlane(cj, t);
+                double pt[BB];
+#pragma unroll
+                for (int e = 0; e < BB; ++e) pt[e] = read_lane(pj[e], t);
+                if (ct == c) {
+#pragma unroll
+                    for (int e = 0; e < BB; ++e) acc[e] += pt[e];
+                }
+            }
+        }
+        if (kc < width) {
+            if (kc < lc) {
+                if (MODE == 1) {
+                    double ob[BB];
+#pragma unroll
+                    for (int e = 0; e < BB; ++e) ob[e] = 0.0;
+                    if (B.len[r] > 0) {
+                        const int64_t os = sslot(B.sp, B.C, r, 0);
+                        if (B.col[os] == c) {
+#pragma unroll
+                            for (int e = 0; e < BB; ++e) ob[e] = bv[os * BB + e];
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < BRA; ++i) {
+                        const double dsc = omega * invd[r * BRA + i];
+#pragma unroll
+                        for (int jj = 0; jj < BCB; ++jj)
+                            cv[cs * BB + i * BCB + jj] = ob[i * BCB + jj] - dsc * acc[i * BCB + jj];
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < BB; ++e) cv[cs * BB + e] = acc[e];
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < BB; ++e) cv[cs * BB + e] = 0.0;
+            }
+        }
+    }
+}
+
 // Dense-row numeric phase for few, long output rows (coarse levels, where C has few block
 // columns): a workgroup owns one output row and accumulates it over all of C's columns in
 // LDS.  For every entry A_ik in turn the lanes walk row k of B (distinct columns, so no two
@@ -1029,7 +1130,13 @@ void spgemm_numeric(const BMat<double>& A, const BMat<double>& B, BMat<double>& 
     // row merge in LDS when the output rows fit (16 lanes per row, 16 rows per block) and the
     // rows of B are long enough to keep its lanes busy; a tentative prolongator (one block
     // per row) goes to the column-parallel kernel, whose lanes share the loads of A's row
-    if (B.S->max_len > 1) {
+    if (B.S->max_len <= 1) {
+        k_spgemm_numeric_single<BRA, BCA, BCB, MODE><<<nblk(rows, kWavesPerBlock), 256, 0, s>>>(
+            sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), Cm.val, invd, omega);
+        FR_LAUNCH_CHECK();
+        return;
+    }
+    {
         constexpr int BB = BRA * BCB;
         constexpr size_t kLds = 64 * 1024;
         // few long rows over few columns (coarse levels): a workgroup per row, dense in LDS
@@ -1190,10 +1297,16 @@ BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* 
 void transpose_values(const BMat<double>& P, BMat<double>& Rm, hipStream_t s) {
     if (Rm.rows() != P.cols() || Rm.cols() != P.rows() || Rm.br != P.bc || Rm.bc != P.br)
         fail(FR_EINTERNAL, "transpose: shape mismatch");
-    const int g = nblk(std::max<int64_t>(1, Rm.rows()), 256);
+    // lanes per row of R from its mean length (coarse levels have few, long rows)
+    const int64_t avg = Rm.S->nnz / std::max<int64_t>(1, Rm.rows());
+    const int G = avg >= 48 ? 64 : (avg >= 6 ? 8 : 1);
+    const int g = nblk(std::max<int64_t>(1, Rm.rows()) * G, 256);
+#define FR_TV_G(BR_, BC_, G_) k_transpose_values<BR_, BC_, G_><<<g, 256, 0, s>>>(sv(*P.S), P.val, sv(*Rm.S), Rm.val);
 #define FR_TV_CASE(BR_, BC_)                                                                  \
     if (P.br == BR_ && P.bc == BC_) {                                                         \
-        k_transpose_values<BR_, BC_><<<g, 256, 0, s>>>(sv(*P.S), P.val, sv(*Rm.S), Rm.val);   \
+        if (G == 64) { FR_TV_G(BR_, BC_, 64) }                                                \
+        else if (G == 8) { FR_TV_G(BR_, BC_, 8) }                                             \
+        else { FR_TV_G(BR_, BC_, 1) }                                                         \
         FR_LAUNCH_CHECK();                                                                    \
         return;                                                                               \
     }
@@ -1203,6 +1316,7 @@ void transpose_values(const BMat<double>& P, BMat<double>& Rm, hipStream_t s) {
     FR_TV_CASE(3, 6)
     FR_TV_CASE(6, 6)
 #undef FR_TV_CASE
+#undef FR_TV_G
     fail(FR_EINTERNAL, "transpose: unsupported block shape");
 }
 
