@@ -1131,12 +1131,15 @@ void spgemm_numeric(const BMat<double>& A, const BMat<double>& B, BMat<double>& 
     // rows of B are long enough to keep its lanes busy; a tentative prolongator (one block
     // per row) goes to the column-parallel kernel, whose lanes share the loads of A's row
     if (B.S->max_len <= 1) {
-        k_spgemm_numeric_single<BRA, BCA, BCB, MODE><<<nblk(rows, kWavesPerBlock), 256, 0, s>>>(
-            sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), Cm.val, invd, omega);
-        FR_LAUNCH_CHECK();
-        return;
-    }
-    {
+        // B with one block per row: a wave per row when A's rows are long (3d, coarse
+        // levels); short rows take the column-parallel kernel below, several rows per wave
+        if (A.S->nnz >= 16 * rows) {
+            k_spgemm_numeric_single<BRA, BCA, BCB, MODE><<<nblk(rows, kWavesPerBlock), 256, 0, s>>>(
+                sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), Cm.val, invd, omega);
+            FR_LAUNCH_CHECK();
+            return;
+        }
+    } else {
         constexpr int BB = BRA * BCB;
         constexpr size_t kLds = 64 * 1024;
         // few long rows over few columns (coarse levels): a workgroup per row, dense in LDS

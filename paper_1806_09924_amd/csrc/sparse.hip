@@ -454,12 +454,14 @@ static void spmv_mode(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_
     const int br = A.br, bc = A.bc;
     const SellStruct& S = *A.S;
     if (S.n_rows == 0) return;
+    const int G = lanes_per_row(S);
+    // one profile scope per kernel instantiation (block shape, mode, lanes per row)
     char name[48];
-    std::snprintf(name, sizeof(name), "spmv_%s_%dx%d_m%d", sizeof(T) == 8 ? "f64" : "f32", br, bc, MODE);
+    if (G == 1) std::snprintf(name, sizeof(name), "spmv_%s_%dx%d_m%d", sizeof(T) == 8 ? "f64" : "f32", br, bc, MODE);
+    else std::snprintf(name, sizeof(name), "spmv_%s_%dx%d_m%d_g%d", sizeof(T) == 8 ? "f64" : "f32", br, bc, MODE, G);
     const double bytes = double(S.nnz) * (br * bc * sizeof(T) + 4) + double(S.n_cols) * bc * sizeof(T) +
                          double(S.n_rows) * br * sizeof(T) * (MODE == 0 ? 1 : 2);
     ProfScope ps(name, s, bytes);
-    const int G = lanes_per_row(S);
     const int gg = nblk(S.n_rows * G, 256);
 #define FR_SPMV_G(BR_, BC_, G_)                                                                      \
     k_spmv<T, BR_, BC_, MODE, G_><<<gg, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, x, b, y);
@@ -488,12 +490,14 @@ void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d
                hipStream_t s) {
     const SellStruct& S = *A.S;
     if (S.n_rows == 0) return;
+    const int G = lanes_per_row(S);
+    // one profile scope per kernel instantiation (block size, lanes per row)
     char name[48];
-    std::snprintf(name, sizeof(name), "cheb_%s_b%d", sizeof(T) == 8 ? "f64" : "f32", A.br);
+    if (G == 1) std::snprintf(name, sizeof(name), "cheb_%s_b%d", sizeof(T) == 8 ? "f64" : "f32", A.br);
+    else std::snprintf(name, sizeof(name), "cheb_%s_b%d_g%d", sizeof(T) == 8 ? "f64" : "f32", A.br, G);
     // matrix once, x gathered once, b, d, D^-1 read, d and x_new written
     const double bytes = double(S.nnz) * (A.br * A.bc * sizeof(T) + 4) + double(S.n_rows) * A.br * sizeof(T) * 6;
     ProfScope ps(name, s, bytes);
-    const int G = lanes_per_row(S);
     const int gg = nblk(S.n_rows * G, 256);
 #define FR_CHEB_G(B_, G_)                                                                            \
     k_cheb<T, B_, G_><<<gg, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, invd, x_old, b, d, x_new, \
