@@ -104,6 +104,12 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, int C, const int32
     const int lane = int(r - s * C);
     const int32_t p0 = slice_ptr[s];
     const int w = (slice_ptr[s + 1] - p0) / C;
+    // the row's b (mode 1) or y (mode 2) is loaded before the product, in flight with it
+    T own[BR];
+    if (MODE != 0 && (G == 1 || g == 0)) {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) own[i] = MODE == 1 ? b[r * BR + i] : y[r * BR + i];
+    }
     T acc[BR];
 #pragma unroll
     for (int i = 0; i < BR; ++i) acc[i] = T(0);
@@ -112,8 +118,8 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, int C, const int32
 #pragma unroll
     for (int i = 0; i < BR; ++i) {
         if (MODE == 0) y[r * BR + i] = acc[i];
-        else if (MODE == 1) y[r * BR + i] = b[r * BR + i] - acc[i];
-        else y[r * BR + i] += acc[i];
+        else if (MODE == 1) y[r * BR + i] = own[i] - acc[i];
+        else y[r * BR + i] = own[i] + acc[i];
     }
 }
 
@@ -133,6 +139,19 @@ __global__ void __launch_bounds__(256) k_cheb(int64_t n_rows, int C, const int32
     const int lane = int(r - s * C);
     const int32_t p0 = slice_ptr[s];
     const int w = (slice_ptr[s + 1] - p0) / C;
+    // the row's own vector entries are loaded before the product, so that they are in flight
+    // together with the matrix stream
+    T bv[B], dv[B], iv[B], xo[B];
+    if (G == 1 || g == 0) {
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            const int64_t e = r * B + i;
+            bv[i] = b[e];
+            dv[i] = alpha != T(0) ? d[e] : T(0);
+            iv[i] = invd[e];
+            xo[i] = x_old[e];
+        }
+    }
     T acc[B];
 #pragma unroll
     for (int i = 0; i < B; ++i) acc[i] = T(0);
@@ -141,10 +160,10 @@ __global__ void __launch_bounds__(256) k_cheb(int64_t n_rows, int C, const int32
 #pragma unroll
     for (int i = 0; i < B; ++i) {
         const int64_t e = r * B + i;
-        const T res = b[e] - acc[i];
-        const T dn = (alpha != T(0) ? alpha * d[e] : T(0)) + beta * invd[e] * res;
+        const T res = bv[i] - acc[i];
+        const T dn = (alpha != T(0) ? alpha * dv[i] : T(0)) + beta * iv[i] * res;
         d[e] = dn;
-        x_new[e] = x_old[e] + dn;
+        x_new[e] = xo[i] + dn;
     }
 }
 
