@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=512, help="cells per axis of the oracle's sample")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (reference for the HBM byte counters)")
-    ap.add_argument("--levels", action="store_true", help="print the AMG hierarchy of the first Newton step")
+    ap.add_argument("--levels", action="store_true", help="(kept for old command lines; the hierarchy is always reported)")
     return ap.parse_args()
 
 
@@ -233,16 +233,22 @@ def main():
         }
         if prof:
             out["fp32_amg"]["vcycle_ms_fp64"] = {k: v["ms"] for k, v in prof.items() if k.startswith("vcycle")}
-    if args.levels:
-        u.zero_()
-        phi.copy_(phi0)
-        S = B.System(mesh).assemble(prm, u, phi, phi0, phi0)
-        A = B.Amg(S, B.amg_opts(precision=64))
-        lv = {}
-        for blk, nm in ((0, "u"), (1, "phi")):
-            lv[nm] = [A.level_info(blk, l) for l in range(A.n_levels(blk))]
-        out["amg_levels"] = lv
-        del A, S
+    # the hierarchy of the first Newton step: level sizes and the launch shapes the tuner
+    # picked (SELL slice height, lanes per row) for each level's A, P, R
+    u.zero_()
+    phi.copy_(phi0)
+    S = B.System(mesh).assemble(prm, u, phi, phi0, phi0)
+    A = B.Amg(S, B.amg_opts(precision=64))
+    lv = {}
+    for blk, nm in ((0, "u"), (1, "phi")):
+        nl = A.n_levels(blk)
+        lv[nm] = []
+        for lev in range(nl):
+            d = A.level_info(blk, lev)
+            d["shape"] = {w: list(A.level_shape(blk, lev, i)) for i, w in enumerate("APR") if i == 0 or lev + 1 < nl}
+            lv[nm].append(d)
+    out["amg_levels"] = lv
+    del A, S
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

@@ -93,6 +93,13 @@ typedef struct {
                             that hierarchy's aggregates and sparsity and recomputes its values
                             (the Jacobian pattern never changes; masked entries stay as zeros);
                             fracture_newton does this from the second Newton iteration on. */
+    int autotune;        /* nonzero: the launch shape of every coarse-level smoother and transfer
+                            product (SELL slice height 64 or 1, lanes per row 1/4/16/64) is
+                            picked by timing the candidates on the level's matrix during the
+                            setup; choices are cached per process by (operation, block shape,
+                            log2 rows, mean row length) and reused by later setups.  Different
+                            lane counts sum a row in a different order, so results are
+                            reproducible for a given cache (amg_level_shape reports the choice). */
 } fr_amg_opts;
 
 /* FGMRES options (right preconditioned, x0 = 0). */
@@ -236,6 +243,15 @@ fr_status amg_setup(fr_system sys, const fr_amg_opts* opts /*host*/, fr_amg* amg
  * `level`: rows, block size, nnz blocks of A, lambda_max estimate. */
 fr_status amg_level_info(fr_amg amg, int block, int level, int* n_levels, int64_t* rows,
                          int* bsize, int64_t* nnz_blocks, double* lambda_max);
+
+/* Launch shape of level operator `which` (0 = A, 1 = P, 2 = R) of hierarchy `block`: SELL
+ * slice height and lanes per block row of its SpMV / Chebyshev kernels (host outputs,
+ * nullable). FR_EINVAL for a level out of range or an operator the level does not have. */
+fr_status amg_level_shape(fr_amg amg, int block, int level, int which, int* slice_height, int* lanes);
+
+/* Forgets the launch shapes the tuner has cached in this process (the next setups time
+ * their candidates again). */
+fr_status fracture_tune_clear(void);
 
 /* Level operator `which` (0 = A, 1 = P, 2 = R) of hierarchy `block` as scalar CSR, host
  * arrays, two-call protocol as fracture_system_csr. FP64 values. */

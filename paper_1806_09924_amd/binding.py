@@ -36,7 +36,7 @@ class Params(ctypes.Structure):
 class AmgOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("theta", ctypes.c_double), ("cheb_degree", ctypes.c_int),
                 ("cheb_ratio", ctypes.c_double), ("coarse_max", ctypes.c_int), ("max_levels", ctypes.c_int),
-                ("reuse_u_block", ctypes.c_int), ("refresh_phi", ctypes.c_int)]
+                ("reuse_u_block", ctypes.c_int), ("refresh_phi", ctypes.c_int), ("autotune", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -87,6 +87,9 @@ _SIGNATURES = {
     "fracture_system_csr": [_P, _I64P, _P, _P, _P, _P],
     "fracture_system_destroy": [_P],
     "amg_setup": [_P, ctypes.POINTER(AmgOpts), ctypes.POINTER(_P), _P],
+    "amg_level_shape": [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                        ctypes.POINTER(ctypes.c_int)],
+    "fracture_tune_clear": [],
     "amg_level_info": [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _I64P,
                        ctypes.POINTER(ctypes.c_int), _I64P, _DP],
     "amg_level_csr": [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I64P, _I64P, _I64P, _P, _P, _P, _P],
@@ -155,8 +158,9 @@ def params(E=1.0, nu=0.2, Gc=1.0, kappa=1e-10, eps=1.0 / 16, p=1e-3, c_pdas=1.0,
 
 
 def amg_opts(precision=64, theta=0.02, cheb_degree=2, cheb_ratio=12.0, coarse_max=96, max_levels=12,
-             reuse_u_block=1, refresh_phi=1):
-    return AmgOpts(precision, theta, cheb_degree, cheb_ratio, coarse_max, max_levels, reuse_u_block, refresh_phi)
+             reuse_u_block=1, refresh_phi=1, autotune=1):
+    return AmgOpts(precision, theta, cheb_degree, cheb_ratio, coarse_max, max_levels, reuse_u_block, refresh_phi,
+                   autotune)
 
 
 def solve_opts(rtol=1e-8, restart=100, maxit=500, use_graphs=1):
@@ -328,6 +332,12 @@ class Amg:
                                      ctypes.byref(nz), ctypes.byref(lm)))
         return dict(n_levels=nl.value, rows=rows.value, bsize=bs.value, nnz_blocks=nz.value, lambda_max=lm.value)
 
+    def level_shape(self, block, level, which):
+        """(SELL slice height, lanes per row) of operator which (0 A, 1 P, 2 R) on a level."""
+        c, g = ctypes.c_int(), ctypes.c_int()
+        _check(load().amg_level_shape(self.h, block, level, which, ctypes.byref(c), ctypes.byref(g)))
+        return c.value, g.value
+
     def n_levels(self, block):
         nl = ctypes.c_int()
         load().amg_level_info(self.h, block, 0, ctypes.byref(nl), None, None, None, None)
@@ -403,6 +413,11 @@ def trim_pool():
 
 def device_check():
     return load().fracture_device_check()
+
+
+def tune_clear():
+    """Forgets the launch shapes cached by the tuner in this process."""
+    _check(load().fracture_tune_clear())
 
 
 def profile(enable):

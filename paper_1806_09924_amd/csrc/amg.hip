@@ -1655,6 +1655,17 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
         ProfScope ps("setup_coarse", s, 0.0);
         coarse_inverse(H, s);
     }
+    if (o.autotune) {
+        // launch shapes of the smoothers and transfers below the finest level (level 0's
+        // matrix is the system's own)
+        ProfScope ps("setup_tune", s, 0.0);
+        for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
+            AmgLevel& L = *H.lv[l];
+            if (l > 0) tune_layout(L.A, 0, s);
+            tune_layout(L.R, 1, s);
+            tune_layout(L.P, 2, s);
+        }
+    }
     for (size_t l = 0; l < H.lv.size(); ++l) {
         if (o.precision == 32) make_f32(*H.lv[l], l + 1 == H.lv.size(), s);
         alloc_vectors(*H.lv[l], o.precision, s);
@@ -2021,6 +2032,16 @@ void amg_level_export(DevAmg& amg, int blk, int level, int which, int64_t& n_row
             }
             rp[size_t(r * br + i) + 1] = int64_t(ci.size());
         }
+}
+
+void amg_level_shape(DevAmg& amg, int blk, int level, int which, int& C, int& G) {
+    Hierarchy& H = amg.h[blk];
+    if (level < 0 || size_t(level) >= H.lv.size()) fail(FR_EINVAL, "amg_level_shape: level out of range");
+    AmgLevel& L = *H.lv[size_t(level)];
+    const BMat<double>* M = which == 0 ? &L.A : (which == 1 ? &L.P : &L.R);
+    if (!M->S) fail(FR_EINVAL, "amg_level_shape: operator absent on this level");
+    C = M->S->C;
+    G = launch_lanes(*M->S);
 }
 
 void amg_info(DevAmg& amg, int blk, int level, int& n_levels, int64_t& rows, int& bsize, int64_t& nnzb, double& lmax,

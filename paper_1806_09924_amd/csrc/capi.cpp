@@ -100,6 +100,7 @@ fr_amg_opts default_amg() {
     o.max_levels = 10;
     o.reuse_u_block = 1;
     o.refresh_phi = 1;
+    o.autotune = 1;
     return o;
 }
 
@@ -521,6 +522,26 @@ fr_status amg_level_info(fr_amg amg, int block, int level, int* n_levels, int64_
         if (bsize) *bsize = bs;
         if (nnz_blocks) *nnz_blocks = nz;
         if (lambda_max) *lambda_max = lm;
+        return FR_OK;
+    });
+}
+
+fr_status amg_level_shape(fr_amg amg, int block, int level, int which, int* slice_height, int* lanes) {
+    FR_REQUIRE(amg != nullptr, "amg_level_shape: NULL amg");
+    FR_REQUIRE(block == 0 || block == 1, "amg_level_shape: block must be 0 or 1");
+    FR_REQUIRE(which >= 0 && which <= 2, "amg_level_shape: which must be 0 (A), 1 (P) or 2 (R)");
+    return guard([&]() {
+        int C = 0, G = 0;
+        fr::amg_level_shape(amg->amg, block, level, which, C, G);
+        if (slice_height) *slice_height = C;
+        if (lanes) *lanes = G;
+        return FR_OK;
+    });
+}
+
+fr_status fracture_tune_clear(void) {
+    return guard([&]() {
+        fr::tune_clear();
         return FR_OK;
     });
 }

@@ -3,6 +3,9 @@
 // and small deterministic device primitives (scan, dot, casts).
 #include <algorithm>
 #include <cstdio>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "profile.h"
 #include "system.h"
@@ -468,19 +471,12 @@ void layout_from_lengths(SellStruct& S, hipStream_t s, const int* flag, int* fla
     FR_BLOCK_DISPATCH(6, 6, CALL)                                                                 \
     fail(FR_EINTERNAL, "spmv: unsupported block shape");
 
+int launch_lanes(const SellStruct& S) { return S.G > 0 ? S.G : lanes_per_row(S); }
+
 template <typename T, int MODE>
-static void spmv_mode(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_t s) {
+static void spmv_launch(const BMat<T>& A, int G, const T* x, const T* b, T* y, hipStream_t s) {
     const int br = A.br, bc = A.bc;
     const SellStruct& S = *A.S;
-    if (S.n_rows == 0) return;
-    const int G = lanes_per_row(S);
-    // one profile scope per kernel instantiation (block shape, mode, lanes per row)
-    char name[48];
-    if (G == 1) std::snprintf(name, sizeof(name), "spmv_%s_%dx%d_m%d", sizeof(T) == 8 ? "f64" : "f32", br, bc, MODE);
-    else std::snprintf(name, sizeof(name), "spmv_%s_%dx%d_m%d_g%d", sizeof(T) == 8 ? "f64" : "f32", br, bc, MODE, G);
-    const double bytes = double(S.nnz) * (br * bc * sizeof(T) + 4) + double(S.n_cols) * bc * sizeof(T) +
-                         double(S.n_rows) * br * sizeof(T) * (MODE == 0 ? 1 : 2);
-    ProfScope ps(name, s, bytes);
     const int gg = nblk(S.n_rows * G, 256);
 #define FR_SPMV_G(BR_, BC_, G_)                                                                      \
     k_spmv<T, BR_, BC_, MODE, G_><<<gg, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, x, b, y);
@@ -497,6 +493,22 @@ static void spmv_mode(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_
 #undef FR_SPMV_G
 }
 
+template <typename T, int MODE>
+static void spmv_mode(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_t s) {
+    const int br = A.br, bc = A.bc;
+    const SellStruct& S = *A.S;
+    if (S.n_rows == 0) return;
+    const int G = launch_lanes(S);
+    // one profile scope per kernel instantiation (block shape, mode, lanes per row)
+    char name[48];
+    if (G == 1) std::snprintf(name, sizeof(name), "spmv_%s_%dx%d_m%d", sizeof(T) == 8 ? "f64" : "f32", br, bc, MODE);
+    else std::snprintf(name, sizeof(name), "spmv_%s_%dx%d_m%d_g%d", sizeof(T) == 8 ? "f64" : "f32", br, bc, MODE, G);
+    const double bytes = double(S.nnz) * (br * bc * sizeof(T) + 4) + double(S.n_cols) * bc * sizeof(T) +
+                         double(S.n_rows) * br * sizeof(T) * (MODE == 0 ? 1 : 2);
+    ProfScope ps(name, s, bytes);
+    spmv_launch<T, MODE>(A, G, x, b, y, s);
+}
+
 template <typename T>
 void spmv(const BMat<T>& A, const T* x, T* y, hipStream_t s) { spmv_mode<T, 0>(A, x, nullptr, y, s); }
 template <typename T>
@@ -505,18 +517,9 @@ template <typename T>
 void spmv_add(const BMat<T>& A, const T* x, T* y, hipStream_t s) { spmv_mode<T, 2>(A, x, nullptr, y, s); }
 
 template <typename T>
-void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d, T* x_new, T alpha, T beta,
-               hipStream_t s) {
+static void cheb_launch(const BMat<T>& A, int G, const T* invd, const T* x_old, const T* b, T* d, T* x_new, T alpha,
+                        T beta, hipStream_t s) {
     const SellStruct& S = *A.S;
-    if (S.n_rows == 0) return;
-    const int G = lanes_per_row(S);
-    // one profile scope per kernel instantiation (block size, lanes per row)
-    char name[48];
-    if (G == 1) std::snprintf(name, sizeof(name), "cheb_%s_b%d", sizeof(T) == 8 ? "f64" : "f32", A.br);
-    else std::snprintf(name, sizeof(name), "cheb_%s_b%d_g%d", sizeof(T) == 8 ? "f64" : "f32", A.br, G);
-    // matrix once, x gathered once, b, d, D^-1 read, d and x_new written
-    const double bytes = double(S.nnz) * (A.br * A.bc * sizeof(T) + 4) + double(S.n_rows) * A.br * sizeof(T) * 6;
-    ProfScope ps(name, s, bytes);
     const int gg = nblk(S.n_rows * G, 256);
 #define FR_CHEB_G(B_, G_)                                                                            \
     k_cheb<T, B_, G_><<<gg, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, invd, x_old, b, d, x_new, \
@@ -538,6 +541,196 @@ void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d
 #undef FR_CHEB_CALL
 #undef FR_CHEB_G
     FR_LAUNCH_CHECK();
+}
+
+template <typename T>
+void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d, T* x_new, T alpha, T beta,
+               hipStream_t s) {
+    const SellStruct& S = *A.S;
+    if (S.n_rows == 0) return;
+    const int G = launch_lanes(S);
+    // one profile scope per kernel instantiation (block size, lanes per row)
+    char name[48];
+    if (G == 1) std::snprintf(name, sizeof(name), "cheb_%s_b%d", sizeof(T) == 8 ? "f64" : "f32", A.br);
+    else std::snprintf(name, sizeof(name), "cheb_%s_b%d_g%d", sizeof(T) == 8 ? "f64" : "f32", A.br, G);
+    // matrix once, x gathered once, b, d, D^-1 read, d and x_new written
+    const double bytes = double(S.nnz) * (A.br * A.bc * sizeof(T) + 4) + double(S.n_rows) * A.br * sizeof(T) * 6;
+    ProfScope ps(name, s, bytes);
+    cheb_launch<T>(A, G, invd, x_old, b, d, x_new, alpha, beta, s);
+}
+
+// ---- launch-shape tuner ---------------------------------------------------------------------
+// Copy of a block SELL matrix in another slice height (C = 1 stores each row contiguously, so
+// that the lanes of a row read consecutive slots); padding repeats the row's first column
+// with zero blocks.
+struct SellRef {
+    int C;
+    int64_t n_rows;
+    const int32_t* sp;
+    const int32_t* len;
+    const int32_t* col;
+};
+
+__device__ __forceinline__ int64_t slot_at(const SellRef& A, int64_t r, int k) {
+    return int64_t(A.sp[r / A.C]) + int64_t(k) * A.C + (r % A.C);
+}
+
+template <int BB>
+__global__ void k_relayout(SellRef A, const double* __restrict__ av, SellRef O, int32_t* __restrict__ ocol,
+                           double* __restrict__ ov) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= O.n_rows) return;
+    const int len = A.len[r];
+    const int64_t s0 = r / O.C;
+    const int width = (O.sp[s0 + 1] - O.sp[s0]) / O.C;
+    const int32_t c0 = len > 0 ? A.col[slot_at(A, r, 0)] : 0;
+    for (int k = 0; k < width; ++k) {
+        const int64_t os = slot_at(O, r, k);
+        if (k < len) {
+            const int64_t as = slot_at(A, r, k);
+            ocol[os] = A.col[as];
+            for (int e = 0; e < BB; ++e) ov[os * BB + e] = av[as * BB + e];
+        } else {
+            ocol[os] = c0;
+            for (int e = 0; e < BB; ++e) ov[os * BB + e] = 0.0;
+        }
+    }
+}
+
+BMat<double> relayout(const BMat<double>& A, int C, hipStream_t s) {
+    const SellStruct& S = *A.S;
+    BMat<double> O;
+    O.br = A.br;
+    O.bc = A.bc;
+    auto N = std::make_shared<SellStruct>();
+    N->C = C;
+    N->n_rows = S.n_rows;
+    N->n_cols = S.n_cols;
+    N->own_len.alloc(size_t(std::max<int64_t>(1, S.n_rows)), s);
+    N->row_len = N->own_len.p;
+    if (S.n_rows) FR_HIP(hipMemcpyAsync(N->row_len, S.row_len, size_t(S.n_rows) * sizeof(int32_t),
+                                        hipMemcpyDeviceToDevice, s));
+    layout_from_lengths(*N, s, nullptr, nullptr);
+    N->own_col.alloc(size_t(std::max<int64_t>(1, N->n_slots)), s);
+    N->col = N->own_col.p;
+    const int BB = A.br * A.bc;
+    O.own_val.alloc(size_t(std::max<int64_t>(1, N->n_slots)) * BB, s);
+    O.val = O.own_val.p;
+    const SellRef av{S.C, S.n_rows, S.slice_ptr, S.row_len, S.col};
+    const SellRef ov{N->C, N->n_rows, N->slice_ptr, N->row_len, N->col};
+    const int g = nblk(std::max<int64_t>(1, S.n_rows), 256);
+#define FR_RL(BB_) case BB_: k_relayout<BB_><<<g, 256, 0, s>>>(av, A.val, ov, N->col, O.val); break;
+    switch (BB) {
+        FR_RL(1) FR_RL(4) FR_RL(6) FR_RL(9) FR_RL(18) FR_RL(36)
+        default: fail(FR_EINTERNAL, "relayout: unsupported block shape");
+    }
+#undef FR_RL
+    FR_LAUNCH_CHECK();
+    O.S = N;
+    return O;
+}
+
+namespace {
+struct TuneKey {
+    int op, br, bc, lg_rows, avg_len;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(op, br, bc, lg_rows, avg_len) < std::tie(o.op, o.br, o.bc, o.lg_rows, o.avg_len);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune;   // -> (slice height, lanes per row)
+}  // namespace
+
+void tune_clear() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+}
+
+int tune_entries() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return int(g_tune.size());
+}
+
+// op 0: Chebyshev step (smoother of A), 1: y = M x (restriction), 2: y += M x (prolongation).
+// Candidates: slice height 64 with 1, 4, 16 lanes per row and contiguous rows (C = 1) with 4,
+// 16, 64 lanes.  Each is timed (one warm-up, best of three) on the matrix itself; the
+// heuristic shape is kept unless another is at least 5 % faster.  Choices are cached per
+// process by (op, block shape, log2 rows, mean row length), so later setups of similar
+// levels reuse them without timing.  Matrices with more than 2^20 rows keep one lane per row
+// in the given layout (their rows fill the chip either way).
+void tune_layout(BMat<double>& M, int op, hipStream_t s) {
+    SellStruct& S = *M.S;
+    if (S.n_rows == 0 || S.n_rows > (int64_t(1) << 20)) return;
+    const int64_t avg = S.nnz / S.n_rows;
+    int lg = 0;
+    while ((int64_t(1) << (lg + 1)) <= S.n_rows) ++lg;
+    const TuneKey key{op, M.br, M.bc, lg, int(avg)};
+    std::pair<int, int> choice{0, 0};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) choice = it->second;
+    }
+    if (choice.first == 0) {
+        const int64_t nr = S.n_rows * M.br, nc = S.n_cols * M.bc;
+        DBuf<double> x, b, d, y, iv;
+        x.alloc(size_t(std::max<int64_t>(1, nc)), s);
+        y.alloc(size_t(std::max<int64_t>(1, nr)), s);
+        x.zero(s);
+        y.zero(s);
+        if (op == 0) {
+            b.alloc(size_t(nr), s);
+            d.alloc(size_t(nr), s);
+            iv.alloc(size_t(nr), s);
+            b.zero(s);
+            d.zero(s);
+            iv.zero(s);
+        }
+        hipEvent_t e0, e1;
+        FR_HIP(hipEventCreate(&e0));
+        FR_HIP(hipEventCreate(&e1));
+        const std::pair<int, int> cands[] = {{S.C, 1}, {S.C, 4}, {S.C, 16}, {1, 4}, {1, 16}, {1, 64}};
+        const int G0 = lanes_per_row(S);
+        double best = 1e30, base = 1e30;
+        std::pair<int, int> pick{S.C, G0};
+        BMat<double> alt;
+        for (const auto& cg : cands) {
+            const BMat<double>* A = &M;
+            if (cg.first != S.C) {
+                if (alt.rows() == 0) alt = relayout(M, cg.first, s);
+                A = &alt;
+            }
+            auto run = [&]() {
+                if (op == 0) cheb_launch<double>(*A, cg.second, iv.p, x.p, b.p, d.p, y.p, 0.0, 1.0, s);
+                else if (op == 1) spmv_launch<double, 0>(*A, cg.second, x.p, nullptr, y.p, s);
+                else spmv_launch<double, 2>(*A, cg.second, x.p, nullptr, y.p, s);
+            };
+            run();
+            float t = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                FR_HIP(hipEventRecord(e0, s));
+                run();
+                FR_HIP(hipEventRecord(e1, s));
+                FR_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                FR_HIP(hipEventElapsedTime(&ms, e0, e1));
+                t = std::min(t, ms);
+            }
+            if (cg.first == S.C && cg.second == G0) base = t;
+            if (t < best) {
+                best = t;
+                pick = cg;
+            }
+        }
+        FR_HIP(hipEventDestroy(e0));
+        FR_HIP(hipEventDestroy(e1));
+        if (base < 1e30 && best > 0.95 * base) pick = {S.C, G0};
+        choice = pick;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune.emplace(key, choice);
+    }
+    if (choice.first != S.C) M = relayout(M, choice.first, s);
+    M.S->G = choice.second;
 }
 
 template <typename T>

@@ -26,6 +26,7 @@ struct SellStruct {
     int C = 64;
     int64_t n_rows = 0, n_cols = 0, n_slices = 0, n_slots = 0, nnz = 0;
     int max_len = 0;                // longest row (entries)
+    int G = 0;                      // lanes per row chosen by the launch-shape tuner (0: by row length)
     int32_t* slice_ptr = nullptr;   // [n_slices+1]
     int32_t* row_len = nullptr;     // [n_rows]
     int32_t* col = nullptr;         // [n_slots]
@@ -125,6 +126,15 @@ void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d
 template <typename T>
 void cheb_first(const T* invd, const T* b, T* d, T* x, T beta, int64_t n, hipStream_t s);
 // fused J-SpMV over the three blocks: y = J x (solve order); x may be FP32 (exactly widened)
+// Launch shape: lanes per row of the SpMV / Chebyshev kernels for a matrix.
+int launch_lanes(const SellStruct& S);
+// Same matrix in slice height C.
+BMat<double> relayout(const BMat<double>& A, int C, hipStream_t s);
+// Picks slice height and lanes per row for M by timing (op 0: smoother, 1: y = M x,
+// 2: y += M x); replaces M by its relayout when another slice height wins.  Process-wide cache.
+void tune_layout(BMat<double>& M, int op, hipStream_t s);
+void tune_clear();
+int tune_entries();
 void jspmv(const DevSystem& sys, const double* x, double* y, hipStream_t s);
 void jspmv(const DevSystem& sys, const float* x, double* y, hipStream_t s);
 // the same, also copying x to xcopy
@@ -204,6 +214,7 @@ void amg_level_export(DevAmg& amg, int blk, int level, int which, int64_t& n_row
                       std::vector<int64_t>& rp, std::vector<int32_t>& ci, std::vector<double>& vv, hipStream_t s);
 void amg_info(DevAmg& amg, int blk, int level, int& n_levels, int64_t& rows, int& bsize, int64_t& nnzb,
               double& lmax, hipStream_t s);
+void amg_level_shape(DevAmg& amg, int blk, int level, int which, int& C, int& G);
 
 // ---- Krylov (krylov.hip) ----------------------------------------------------------------
 constexpr int kInitBasis = 24;                   // initial Krylov basis capacity (vectors)

@@ -53,6 +53,8 @@ def test_argument_validation_before_device(lib):
     assert lib.fracture_solve(None, None, None, None, None, None) == B.FR_EINVAL
     assert lib.amg_setup(None, None, None, None) == B.FR_EINVAL
     assert lib.fracture_functionals(None, None, None, None, 0, None, None, None) == B.FR_EINVAL
+    assert lib.amg_level_shape(None, 0, 0, 0, None, None) == B.FR_EINVAL
+    assert lib.fracture_tune_clear() == B.FR_OK
 
 
 def test_host_only_mesh_is_rejected_by_device_calls(lib):

@@ -357,3 +357,44 @@ def test_graph_replay_matches_direct_launches(precision):
     d0, i0 = outs[0][0]
     for d, i in outs[1] + [(host(du), i0)]:
         assert np.array_equal(d, d0) and i == i0
+
+
+@pytest.mark.parametrize("dim,n", [(2, 256), (3, 32)])
+def test_autotuned_shapes_keep_the_operators(dim, n):
+    """The launch-shape tuner changes only layouts and lane counts: every level operator
+    exports the same CSR with and without it, every chosen shape is one of the candidates,
+    the finest level keeps the system's layout, a V-cycle agrees to rounding (other lane
+    counts sum rows in another order), and a second setup reuses the cached shapes."""
+    P = Problem(dim, 2.0, n)
+    S = _gpu_system(P)
+    B.tune_clear()
+    A0 = B.Amg(S, B.amg_opts(autotune=0))
+    A1 = B.Amg(S, B.amg_opts(autotune=1))
+    shapes = {}
+    for blk in (0, 1):
+        nl = A1.n_levels(blk)
+        assert nl == A0.n_levels(blk) and nl >= 3
+        for lev in range(nl):
+            for which in ((0, 1, 2) if lev + 1 < nl else (0,)):
+                (s0, r0, c0, v0), (s1, r1, c1, v1) = A0.level_csr(blk, lev, which), A1.level_csr(blk, lev, which)
+                assert s0 == s1 and np.array_equal(r0, r1) and np.array_equal(c0, c1) and np.array_equal(v0, v1)
+                C, G = A1.level_shape(blk, lev, which)
+                assert C in (1, 64) and G in (1, 4, 16, 64)
+                assert A0.level_shape(blk, lev, which)[0] == 64
+                shapes[(blk, lev, which)] = (C, G)
+        assert A1.level_shape(blk, 0, 0) == A0.level_shape(blk, 0, 0)
+    r = dev(np.random.default_rng(5).standard_normal(P.mesh.n_solve))
+    z0 = torch.empty_like(r)
+    z1 = torch.empty_like(r)
+    A0.apply(r, z0)
+    A1.apply(r, z1)
+    z0, z1 = host(z0), host(z1)
+    assert np.abs(z1 - z0).max() <= 1e-11 * np.abs(z0).max()
+    A2 = B.Amg(S, B.amg_opts(autotune=1))
+    for (blk, lev, which), cg in shapes.items():
+        assert A2.level_shape(blk, lev, which) == cg
+    z2 = torch.empty_like(r)
+    A2.apply(dev(host(r)), z2)
+    assert np.array_equal(host(z2), z1)
+    with pytest.raises(B.FractureError):
+        A1.level_shape(0, A1.n_levels(0) - 1, 1)
