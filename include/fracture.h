@@ -95,9 +95,10 @@ typedef struct {
                             fracture_newton does this from the second Newton iteration on. */
     int autotune;        /* nonzero: the launch shape of every coarse-level smoother and transfer
                             product (SELL slice height 64 or 1, lanes per row 1/4/16/64) is
-                            picked by timing the candidates on the level's matrix during the
-                            setup; choices are cached per process by (operation, block shape,
-                            log2 rows, mean row length) and reused by later setups.  Different
+                            picked by timing the candidates on the level's matrix, in the
+                            V-cycle's precision, during the setup; choices are cached per process
+                            by (operation, block shape, log2 rows, mean row length, precision)
+                            and reused by later setups.  Different
                             lane counts sum a row in a different order, so results are
                             reproducible for a given cache (amg_level_shape reports the choice). */
 } fr_amg_opts;

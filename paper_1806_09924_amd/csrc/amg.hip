@@ -1661,9 +1661,10 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
         ProfScope ps("setup_tune", s, 0.0);
         for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
             AmgLevel& L = *H.lv[l];
-            if (l > 0) tune_layout(L.A, 0, s);
-            tune_layout(L.R, 1, s);
-            tune_layout(L.P, 2, s);
+            const bool f32 = o.precision == 32;
+            if (l > 0) tune_layout(L.A, 0, f32, s);
+            tune_layout(L.R, 1, f32, s);
+            tune_layout(L.P, 2, f32, s);
         }
     }
     for (size_t l = 0; l < H.lv.size(); ++l) {

@@ -632,13 +632,90 @@ BMat<double> relayout(const BMat<double>& A, int C, hipStream_t s) {
 
 namespace {
 struct TuneKey {
-    int op, br, bc, lg_rows, avg_len;
+    int op, br, bc, lg_rows, avg_len, f32;
     bool operator<(const TuneKey& o) const {
-        return std::tie(op, br, bc, lg_rows, avg_len) < std::tie(o.op, o.br, o.bc, o.lg_rows, o.avg_len);
+        return std::tie(op, br, bc, lg_rows, avg_len, f32) < std::tie(o.op, o.br, o.bc, o.lg_rows, o.avg_len, o.f32);
     }
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<int, int>> g_tune;   // -> (slice height, lanes per row)
+
+// best of five timed launches (after one warm-up) of each candidate shape, in precision T
+template <typename T>
+std::pair<int, int> time_shapes(const BMat<double>& M, int op, hipStream_t s) {
+    const SellStruct& S = *M.S;
+    const int64_t nr = S.n_rows * M.br, nc = S.n_cols * M.bc;
+    DBuf<T> x, y, b, d, iv;
+    x.alloc(size_t(std::max<int64_t>(1, nc)), s);
+    y.alloc(size_t(std::max<int64_t>(1, nr)), s);
+    b.alloc(size_t(std::max<int64_t>(1, nr)), s);
+    d.alloc(size_t(std::max<int64_t>(1, nr)), s);
+    iv.alloc(size_t(std::max<int64_t>(1, nr)), s);
+    x.zero(s);
+    y.zero(s);
+    b.zero(s);
+    d.zero(s);
+    iv.zero(s);
+    // the matrix in both slice heights, values in precision T
+    BMat<double> alt;
+    DBuf<float> v32[2];
+    auto as_t = [&](const BMat<double>& A, int which) {
+        BMat<T> t;
+        t.br = A.br;
+        t.bc = A.bc;
+        t.S = A.S;
+        if constexpr (sizeof(T) == 8) {
+            t.val = A.val;
+        } else {
+            const int64_t n = A.S->n_slots * A.br * A.bc;
+            v32[which].alloc(size_t(std::max<int64_t>(1, n)), s);
+            cast_f64_f32(A.val, v32[which].p, n, s);
+            t.val = v32[which].p;
+        }
+        return t;
+    };
+    const BMat<T> m0 = as_t(M, 0);
+    BMat<T> m1;
+    hipEvent_t e0, e1;
+    FR_HIP(hipEventCreate(&e0));
+    FR_HIP(hipEventCreate(&e1));
+    const std::pair<int, int> cands[] = {{S.C, 1}, {S.C, 4}, {S.C, 16}, {1, 4}, {1, 16}, {1, 64}};
+    const int G0 = lanes_per_row(S);
+    double best = 1e30, base = 1e30;
+    std::pair<int, int> pick{S.C, G0};
+    for (const auto& cg : cands) {
+        if (cg.first != S.C && alt.rows() == 0) {
+            alt = relayout(M, cg.first, s);
+            m1 = as_t(alt, 1);
+        }
+        const BMat<T>& A = cg.first == S.C ? m0 : m1;
+        auto run = [&]() {
+            if (op == 0) cheb_launch<T>(A, cg.second, iv.p, x.p, b.p, d.p, y.p, T(0), T(1), s);
+            else if (op == 1) spmv_launch<T, 0>(A, cg.second, x.p, nullptr, y.p, s);
+            else spmv_launch<T, 2>(A, cg.second, x.p, nullptr, y.p, s);
+        };
+        run();
+        float t = 1e30f;
+        for (int rep = 0; rep < 5; ++rep) {
+            FR_HIP(hipEventRecord(e0, s));
+            run();
+            FR_HIP(hipEventRecord(e1, s));
+            FR_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            FR_HIP(hipEventElapsedTime(&ms, e0, e1));
+            t = std::min(t, ms);
+        }
+        if (cg.first == S.C && cg.second == G0) base = t;
+        if (t < best) {
+            best = t;
+            pick = cg;
+        }
+    }
+    FR_HIP(hipEventDestroy(e0));
+    FR_HIP(hipEventDestroy(e1));
+    if (base < 1e30 && best > 0.95 * base) pick = {S.C, G0};
+    return pick;
+}
 }  // namespace
 
 void tune_clear() {
@@ -651,20 +728,21 @@ int tune_entries() {
     return int(g_tune.size());
 }
 
-// op 0: Chebyshev step (smoother of A), 1: y = M x (restriction), 2: y += M x (prolongation).
-// Candidates: slice height 64 with 1, 4, 16 lanes per row and contiguous rows (C = 1) with 4,
-// 16, 64 lanes.  Each is timed (one warm-up, best of three) on the matrix itself; the
-// heuristic shape is kept unless another is at least 5 % faster.  Choices are cached per
-// process by (op, block shape, log2 rows, mean row length), so later setups of similar
-// levels reuse them without timing.  Matrices with more than 2^20 rows keep one lane per row
-// in the given layout (their rows fill the chip either way).
-void tune_layout(BMat<double>& M, int op, hipStream_t s) {
+// op 0: Chebyshev step (smoother of A), 1: y = M x (restriction), 2: y += M x (prolongation),
+// timed in the precision the V-cycle runs in (f32).  Candidates: slice height 64 with 1, 4,
+// 16 lanes per row and contiguous rows (C = 1) with 4, 16, 64 lanes.  Each is timed (one
+// warm-up, best of five) on the matrix itself; the heuristic shape is kept unless another
+// is at least 5 % faster.  Choices are cached per process by (op, block shape, log2 rows,
+// mean row length, precision), so later setups of similar levels reuse them without timing.
+// Matrices with more than 2^20 rows keep one lane per row in the given layout (their rows
+// fill the chip either way).
+void tune_layout(BMat<double>& M, int op, bool f32, hipStream_t s) {
     SellStruct& S = *M.S;
     if (S.n_rows == 0 || S.n_rows > (int64_t(1) << 20)) return;
     const int64_t avg = S.nnz / S.n_rows;
     int lg = 0;
     while ((int64_t(1) << (lg + 1)) <= S.n_rows) ++lg;
-    const TuneKey key{op, M.br, M.bc, lg, int(avg)};
+    const TuneKey key{op, M.br, M.bc, lg, int(avg), f32 ? 1 : 0};
     std::pair<int, int> choice{0, 0};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -672,60 +750,7 @@ void tune_layout(BMat<double>& M, int op, hipStream_t s) {
         if (it != g_tune.end()) choice = it->second;
     }
     if (choice.first == 0) {
-        const int64_t nr = S.n_rows * M.br, nc = S.n_cols * M.bc;
-        DBuf<double> x, b, d, y, iv;
-        x.alloc(size_t(std::max<int64_t>(1, nc)), s);
-        y.alloc(size_t(std::max<int64_t>(1, nr)), s);
-        x.zero(s);
-        y.zero(s);
-        if (op == 0) {
-            b.alloc(size_t(nr), s);
-            d.alloc(size_t(nr), s);
-            iv.alloc(size_t(nr), s);
-            b.zero(s);
-            d.zero(s);
-            iv.zero(s);
-        }
-        hipEvent_t e0, e1;
-        FR_HIP(hipEventCreate(&e0));
-        FR_HIP(hipEventCreate(&e1));
-        const std::pair<int, int> cands[] = {{S.C, 1}, {S.C, 4}, {S.C, 16}, {1, 4}, {1, 16}, {1, 64}};
-        const int G0 = lanes_per_row(S);
-        double best = 1e30, base = 1e30;
-        std::pair<int, int> pick{S.C, G0};
-        BMat<double> alt;
-        for (const auto& cg : cands) {
-            const BMat<double>* A = &M;
-            if (cg.first != S.C) {
-                if (alt.rows() == 0) alt = relayout(M, cg.first, s);
-                A = &alt;
-            }
-            auto run = [&]() {
-                if (op == 0) cheb_launch<double>(*A, cg.second, iv.p, x.p, b.p, d.p, y.p, 0.0, 1.0, s);
-                else if (op == 1) spmv_launch<double, 0>(*A, cg.second, x.p, nullptr, y.p, s);
-                else spmv_launch<double, 2>(*A, cg.second, x.p, nullptr, y.p, s);
-            };
-            run();
-            float t = 1e30f;
-            for (int rep = 0; rep < 3; ++rep) {
-                FR_HIP(hipEventRecord(e0, s));
-                run();
-                FR_HIP(hipEventRecord(e1, s));
-                FR_HIP(hipEventSynchronize(e1));
-                float ms = 0.f;
-                FR_HIP(hipEventElapsedTime(&ms, e0, e1));
-                t = std::min(t, ms);
-            }
-            if (cg.first == S.C && cg.second == G0) base = t;
-            if (t < best) {
-                best = t;
-                pick = cg;
-            }
-        }
-        FR_HIP(hipEventDestroy(e0));
-        FR_HIP(hipEventDestroy(e1));
-        if (base < 1e30 && best > 0.95 * base) pick = {S.C, G0};
-        choice = pick;
+        choice = f32 ? time_shapes<float>(M, op, s) : time_shapes<double>(M, op, s);
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune.emplace(key, choice);
     }

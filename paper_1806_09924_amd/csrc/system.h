@@ -131,8 +131,9 @@ int launch_lanes(const SellStruct& S);
 // Same matrix in slice height C.
 BMat<double> relayout(const BMat<double>& A, int C, hipStream_t s);
 // Picks slice height and lanes per row for M by timing (op 0: smoother, 1: y = M x,
-// 2: y += M x); replaces M by its relayout when another slice height wins.  Process-wide cache.
-void tune_layout(BMat<double>& M, int op, hipStream_t s);
+// 2: y += M x) in FP32 or FP64; replaces M by its relayout when another slice height wins.
+// Process-wide cache.
+void tune_layout(BMat<double>& M, int op, bool f32, hipStream_t s);
 void tune_clear();
 int tune_entries();
 void jspmv(const DevSystem& sys, const double* x, double* y, hipStream_t s);
