@@ -280,7 +280,11 @@ fr_status fracture_update(fr_mesh mesh, const double* du, double omega, double* 
 /* The Newton / active-set loop of one loading step (Section 3 algorithm): assemble,
  * active set, masked Jacobian, AMG setup, FGMRES, line search, stop test, with the cycle
  * freeze of alternating active-set entries. u and phi are updated in place (device).
- * amg_opts / solve_opts / newton_opts / stats: host.
+ * amg_opts / solve_opts / newton_opts / stats: host. prm and stats hold one entry per
+ * instance: on a batched mesh all instances iterate together (one assembly, setup and solve
+ * per iteration), each with its own line search and stop test; a finished instance takes no
+ * further update, and the loop ends when every instance has finished or max_it is reached
+ * (the return value is then the worst instance status). Timings are for the whole call.
  * The working storage (system, preconditioner, Krylov bases) stays with the mesh for the
  * next call, which recomputes all of it; calls on one mesh run one at a time. It is freed
  * by fracture_mesh_destroy, or by a call on another stream (the first stream must stay

@@ -108,3 +108,26 @@ def batched_instances(n_inst=48, seed=9924):
                             eps_factor=float(fac[i]), center=(float(xc[i]), float(yc[i]), 0.0),
                             newton="one_step"))
     return out
+
+
+# Section 4.2: influence of the finite domain size in 2d (crack half-length l0 = 1 in
+# [-L, L]^2 for domain sizes 10, 20, 40, 80).  The paper refines adaptively towards the crack;
+# the reading here: base cells of edge 1 (2L per axis), `levels` refinements of every cell
+# within `refine_radius` of the crack segment (2:1 balanced), eps = 2 h_min, p = 1e-3, and the
+# value extrapolated in h from the finest levels.  Exact (infinite-domain) TCV:
+# 2 pi p l0^2 (1 - nu^2) / E = 6.0319E-03.
+DOMAIN_STUDY_HALF_WIDTHS = (5.0, 10.0, 20.0, 40.0)
+DOMAIN_STUDY_LEVELS = (5, 6, 7)
+DOMAIN_STUDY_RADIUS = 4.0
+
+
+def domain_study(half_widths=DOMAIN_STUDY_HALF_WIDTHS, levels=DOMAIN_STUDY_LEVELS, refine_radius=DOMAIN_STUDY_RADIUS):
+    """Workloads of the domain-size study, domain-major, finest level last."""
+    out = []
+    for L in half_widths:
+        for k in levels:
+            out.append(Workload(f"domain{int(2 * L)}_lev{k}", 2, float(L), int(round(2 * L)), l0=1.0,
+                                levels=int(k), refine_radius=float(refine_radius), newton="loop",
+                                description=f"2d Sneddon l0=1 in [-{L:g},{L:g}]^2, base h=1, {k} levels "
+                                            f"within {refine_radius:g} of the crack, eps=2h_min"))
+    return out

@@ -381,15 +381,23 @@ def update(mesh, du, omega, u, phi):
 
 
 def newton(mesh, prm, u, phi, phi_old, phi_tilde, amg=None, solve=None, newton=None, raise_on_noconv=True):
-    st = NewtonStats()
-    status = load().fracture_newton(mesh.h, ctypes.byref(prm), _ptr(u), _ptr(phi), _ptr(phi_old), _ptr(phi_tilde),
+    """Newton / active-set loop; prm: one Params, or a list of one per instance of a batched
+    mesh.  Returns the stats dict (a list of them for a batched mesh)."""
+    ni = mesh.n_inst
+    plist = list(prm) if isinstance(prm, (list, tuple)) else [prm]
+    if len(plist) != ni:
+        raise ValueError(f"need {ni} parameter sets, got {len(plist)}")
+    arr = (Params * ni)(*plist)
+    st = (NewtonStats * ni)()
+    status = load().fracture_newton(mesh.h, arr, _ptr(u), _ptr(phi), _ptr(phi_old), _ptr(phi_tilde),
                                     ctypes.byref(amg if amg is not None else amg_opts()),
                                     ctypes.byref(solve if solve is not None else solve_opts()),
                                     ctypes.byref(newton if newton is not None else newton_opts()),
-                                    ctypes.byref(st), _stream())
+                                    st, _stream())
     if status != FR_OK and (raise_on_noconv or status != FR_ENOCONV):
         raise FractureError(status, last_error())
-    return {f: getattr(st, f) for f, _ in NewtonStats._fields_}
+    out = [{f: getattr(x, f) for f, _ in NewtonStats._fields_} for x in st]
+    return out[0] if ni == 1 else out
 
 
 def functionals(mesh, u, phi, cod_x=()):

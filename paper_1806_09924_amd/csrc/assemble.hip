@@ -580,6 +580,45 @@ __global__ void __launch_bounds__(256) k_norm_parts(int64_t nf, int D, const dou
     }
 }
 
+// Per instance of a batch (one workgroup each, rows in a fixed order): ||R~||^2 (Dirichlet
+// u rows and active phi rows left out), active phi rows, and rows whose active flag changed
+// in the last active-set update.
+__global__ void __launch_bounds__(256) k_inst_norms(int D, int64_t nf, const int64_t* __restrict__ off,
+                                                    const double* __restrict__ R, const uint8_t* __restrict__ dir,
+                                                    const uint8_t* __restrict__ active, const uint8_t* __restrict__ prev,
+                                                    double* __restrict__ out) {
+    __shared__ double sh[16];
+    const int i = blockIdx.x;
+    double r2 = 0.0, na = 0.0, nc = 0.0;
+    for (int64_t f = off[i] + threadIdx.x; f < off[i + 1]; f += blockDim.x) {
+        if (!dir[f])
+            for (int c = 0; c < D; ++c) r2 += R[f * D + c] * R[f * D + c];
+        if (!active[f]) r2 += R[D * nf + f] * R[D * nf + f];
+        else na += 1.0;
+        if (active[f] != prev[f]) nc += 1.0;
+    }
+    const double a = block_sum(r2, sh);
+    const double b = block_sum(na, sh);
+    const double c = block_sum(nc, sh);
+    if (threadIdx.x == 0) {
+        out[3 * i + 0] = a;
+        out[3 * i + 1] = b;
+        out[3 * i + 2] = c;
+    }
+}
+
+// u += omega_i du, phi += omega_i dphi at the free nodes of instance i
+__global__ void k_update_free_inst(int64_t nf, int D, const int32_t* __restrict__ node_of_free,
+                                   const int32_t* __restrict__ inst_of_free, const double* __restrict__ du,
+                                   const double* __restrict__ omega, double* __restrict__ u, double* __restrict__ phi) {
+    const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    const double w = omega[inst_of_free[f]];
+    const int64_t n = node_of_free[f];
+    for (int c = 0; c < D; ++c) u[n * D + c] += w * du[f * D + c];
+    phi[n] += w * du[D * nf + f];
+}
+
 // ---- update -----------------------------------------------------------------------------
 __global__ void k_update_free(int64_t nf, int D, const int32_t* __restrict__ node_of_free,
                               const double* __restrict__ du, double omega, double* __restrict__ u,
@@ -923,6 +962,38 @@ void system_norms(DevSystem& sys, const double* phi, const double* phi_old, doub
     if (norms) { norms[0] = std::sqrt(a); norms[1] = std::sqrt(b); }
     if (n_active) *n_active = int64_t(c + 0.5);
     if (min_margin) *min_margin = sys.last_min_margin;
+}
+
+void system_norms_inst(DevSystem& sys, std::vector<double>& rnorm, std::vector<int64_t>& n_active,
+                       std::vector<int64_t>& changes) {
+    DevMesh& m = *sys.mesh;
+    const hipStream_t s = sys.stream;
+    const int ni = m.n_inst;
+    if (sys.inst_off.p == nullptr) sys.inst_off.upload(m.host.free_off, s);
+    sys.red.reserve(size_t(3 * ni) + 16, s);
+    k_inst_norms<<<ni, 256, 0, s>>>(m.dim, m.n_free, sys.inst_off.p, sys.R.p, m.dir_free.p, sys.active.p,
+                                    sys.active_prev.p, sys.red.p);
+    FR_LAUNCH_CHECK();
+    auto part = download(sys.red.p, size_t(3 * ni), s);
+    rnorm.resize(size_t(ni));
+    n_active.resize(size_t(ni));
+    changes.resize(size_t(ni));
+    for (int i = 0; i < ni; ++i) {
+        rnorm[size_t(i)] = std::sqrt(part[size_t(3 * i)]);
+        n_active[size_t(i)] = int64_t(part[size_t(3 * i + 1)] + 0.5);
+        changes[size_t(i)] = int64_t(part[size_t(3 * i + 2)] + 0.5);
+    }
+}
+
+void mesh_update_inst(DevMesh& m, const double* du, const double* omega, double* u, double* phi, hipStream_t s) {
+    k_update_free_inst<<<blocks_for(m.n_free, 256), 256, 0, s>>>(m.n_free, m.dim, m.node_of_free.p, m.inst_of_free.p,
+                                                                 du, omega, u, phi);
+    FR_LAUNCH_CHECK();
+    if (m.hanging) {
+        k_fill_hanging<<<blocks_for(m.n_nodes, 256), 256, 0, s>>>(m.n_nodes, m.dim, m.free_of_node.p, m.node_of_free.p,
+                                                                   m.con_ptr.p, m.con_master.p, m.con_w.p, u, phi);
+        FR_LAUNCH_CHECK();
+    }
 }
 
 void mesh_update(DevMesh& m, const double* du, double omega, double* u, double* phi, hipStream_t s) {

@@ -1,5 +1,6 @@
 // C ABI of the fracture library: argument validation, handle lifetimes, error reporting and
 // the native Newton / active-set driver (Section 3 algorithm) over the device kernels.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -611,15 +612,142 @@ fr_status fracture_update(fr_mesh mesh, const double* du, double omega, double* 
     });
 }
 
+// Newton / active-set loop over a batch of independent instances (one disjoint-union system):
+// every iteration assembles, sets up and solves all instances together; the line search
+// halves each instance's step on its own (omega_i from its own residual norm), and an
+// instance whose active set is unchanged and whose residual is below tol x its initial one
+// is finished: its later updates get omega = 0.  Runs until every instance has finished.
+static fr_status newton_batch(NewtonWork& W, fr::DevMesh& m, const fr_params* prm, double* u, double* phi,
+                              const double* phi_old, const double* phi_tilde, const fr_amg_opts& ao,
+                              const fr_solve_opts& so, const fr_newton_opts& no, fr_newton_stats* stats,
+                              hipStream_t s) {
+    const int ni = m.n_inst;
+    fr_system_s* S = &W.S;
+    system_init(*S, m, s);
+    fr::DevSystem& sys = S->sys;
+    sys.prm_h.resize(size_t(ni));
+    for (int i = 0; i < ni; ++i) sys.prm_h[size_t(i)] = fr::make_params(prm[i]);
+    sys.prm = sys.prm_h[0];
+    sys.prm_d.upload(sys.prm_h, s);
+    fr_amg_s* A = &W.A;
+    const int64_t nn = m.n_nodes;
+    if (W.du.p == nullptr) W.du.alloc(size_t(sys.n_solve), s);
+    if (W.u_save.p == nullptr) W.u_save.alloc(size_t(nn) * m.dim, s);
+    if (W.p_save.p == nullptr) W.p_save.alloc(size_t(nn), s);
+    fr::DBuf<double> om_d;
+    om_d.alloc(size_t(ni), s);
+    std::vector<fr_newton_stats> ns(static_cast<size_t>(ni));
+    std::vector<fr_solve_stats> st(static_cast<size_t>(ni));
+    std::vector<double> r0, rk, nr;
+    std::vector<int64_t> n_act, chg;
+    std::vector<char> done(static_cast<size_t>(ni), 0), ok(static_cast<size_t>(ni), 0);
+    std::vector<double> om(static_cast<size_t>(ni), 0.0);
+    double t_asm = 0, t_setup = 0, t_solve = 0, t_other = 0;
+    {
+        EventTimer t(s);
+        fr::assemble_residual(sys, u, phi, phi_tilde);
+        fr::assemble_active(sys, phi, phi_old);
+        t_asm += t.stop();
+    }
+    fr::system_norms_inst(sys, r0, n_act, chg);
+    rk = r0;
+    for (int i = 0; i < ni; ++i) ns[size_t(i)].res0 = r0[size_t(i)];
+    int it = 0;
+    bool nan = false;
+    while (it < no.max_it) {
+        {
+            EventTimer t(s);
+            fr::assemble_jacobian(sys, u, phi, phi_old, phi_tilde);
+            t_asm += t.stop();
+        }
+        {
+            EventTimer t(s);
+            fr_amg_opts ao_it = ao;
+            ao_it.reuse_u_block = (it > 0 && ao.reuse_u_block) ? 1 : 0;
+            if (it == 0) A->amg.h[1].refreshable = false;
+            fr::amg_build(A->amg, sys, ao_it, s);
+            t_setup += t.stop();
+        }
+        {
+            EventTimer t(s);
+            const fr_status r = fr::fgmres(sys, A->amg, so, W.du.p, st.data(), S->kry, s);
+            t_solve += t.stop();
+            if (r == FR_ENAN) { nan = true; break; }
+        }
+        EventTimer t(s);
+        FR_HIP(hipMemcpyAsync(W.u_save.p, u, size_t(nn) * m.dim * 8, hipMemcpyDeviceToDevice, s));
+        FR_HIP(hipMemcpyAsync(W.p_save.p, phi, size_t(nn) * 8, hipMemcpyDeviceToDevice, s));
+        for (int i = 0; i < ni; ++i) {
+            ok[size_t(i)] = done[size_t(i)];
+            om[size_t(i)] = done[size_t(i)] ? 0.0 : 1.0;
+        }
+        for (int mm = 0; mm <= no.ls_max; ++mm) {
+            for (int i = 0; i < ni; ++i)
+                if (!ok[size_t(i)]) om[size_t(i)] = std::ldexp(1.0, -mm);
+            if (mm > 0) {
+                FR_HIP(hipMemcpyAsync(u, W.u_save.p, size_t(nn) * m.dim * 8, hipMemcpyDeviceToDevice, s));
+                FR_HIP(hipMemcpyAsync(phi, W.p_save.p, size_t(nn) * 8, hipMemcpyDeviceToDevice, s));
+            }
+            om_d.upload(om, s);
+            fr::mesh_update_inst(m, W.du.p, om_d.p, u, phi, s);
+            fr::assemble_residual(sys, u, phi, phi_tilde);
+            fr::system_norms_inst(sys, nr, n_act, chg);
+            bool all = true;
+            for (int i = 0; i < ni; ++i) {
+                if (!ok[size_t(i)] && nr[size_t(i)] < rk[size_t(i)]) ok[size_t(i)] = 1;
+                all = all && ok[size_t(i)];
+            }
+            if (all) break;
+        }
+        ++it;
+        if (it >= 2) fr::assemble_active_freeze(sys, phi, phi_old);
+        else fr::assemble_active(sys, phi, phi_old);
+        fr::system_norms_inst(sys, rk, n_act, chg);
+        t_other += t.stop();
+        bool all = true;
+        for (int i = 0; i < ni; ++i) {
+            fr_newton_stats& q = ns[size_t(i)];
+            if (!std::isfinite(rk[size_t(i)])) nan = true;
+            if (!done[size_t(i)]) {
+                q.iterations = it;
+                q.linear_iters += st[size_t(i)].iters;
+                if (chg[size_t(i)] == 0 && rk[size_t(i)] <= no.tol * r0[size_t(i)]) done[size_t(i)] = 1;
+            }
+            q.res = rk[size_t(i)];
+            q.n_active = n_act[size_t(i)];
+            all = all && done[size_t(i)];
+        }
+        if (nan || all) break;
+    }
+    fr_status worst = FR_OK;
+    for (int i = 0; i < ni; ++i) {
+        fr_newton_stats& q = ns[size_t(i)];
+        q.status = nan ? FR_ENAN : (done[size_t(i)] ? FR_OK : FR_ENOCONV);
+        q.t_assemble = t_asm;
+        q.t_setup = t_setup;
+        q.t_solve = t_solve;
+        q.t_other = t_other;
+        if (q.status != FR_OK && worst == FR_OK) worst = fr_status(q.status);
+        if (q.status == FR_ENAN) worst = FR_ENAN;
+    }
+    if (stats) std::copy(ns.begin(), ns.end(), stats);
+    FR_HIP(hipStreamSynchronize(s));
+    if (worst == FR_ENOCONV) set_err(worst, "newton: iteration limit reached for an instance");
+    if (worst == FR_ENAN) set_err(worst, "newton: non-finite residual");
+    return worst;
+}
+
 fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double* phi, const double* phi_old,
                           const double* phi_tilde, const fr_amg_opts* amg_opts, const fr_solve_opts* solve_opts,
                           const fr_newton_opts* newton_opts, fr_newton_stats* stats, void* stream) {
     FR_REQUIRE(mesh != nullptr && mesh->m, "newton: NULL mesh");
     FR_REQUIRE(mesh->m->on_device, "newton: host-only mesh");
-    FR_REQUIRE(mesh->m->n_inst == 1, "newton: batched meshes take single Newton steps (assemble/amg_setup/solve)");
     FR_REQUIRE(u && phi && phi_old && phi_tilde, "newton: NULL state array");
-    fr_status ps = check_params(prm);
-    if (ps != FR_OK) return ps;
+    FR_REQUIRE(prm != nullptr, "newton: NULL params");
+    for (int i = 0; i < mesh->m->n_inst; ++i) {
+        fr_status ps = check_params(prm + i);
+        if (ps != FR_OK) return ps;
+    }
     const fr_amg_opts ao = amg_opts ? *amg_opts : default_amg();
     if (check_amg(ao) != FR_OK) return FR_EINVAL;
     fr_solve_opts so{1e-8, 100, 500, 1};
@@ -643,6 +771,7 @@ fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double*
             mesh->nw->stream = s;
         }
         NewtonWork& W = *mesh->nw;
+        if (m.n_inst > 1) return newton_batch(W, m, prm, u, phi, phi_old, phi_tilde, ao, so, no, stats, s);
         fr_newton_stats ns{};
         fr_system_s* S = &W.S;
         system_init(*S, m, s);

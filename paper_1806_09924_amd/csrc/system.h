@@ -80,6 +80,7 @@ struct DevSystem {
     DBuf<double> red;                            // reduction scratch
     DBuf<int32_t> ired;
     DBuf<double> nodal;                          // hanging meshes: u, phi, phi~ with hanging values filled
+    DBuf<int64_t> inst_off;                      // batches: first free row of every instance
     bool have_residual = false, have_active = false, have_jacobian = false;
     int64_t last_changes = 0;
     double last_min_margin = 0.0;
@@ -96,6 +97,11 @@ void system_norms(DevSystem& sys, const double* phi, const double* phi_old, doub
                   int64_t* n_active, double* min_margin);
 void system_matvec(DevSystem& sys, const double* x, double* y);
 void mesh_update(DevMesh& m, const double* du, double omega, double* u, double* phi, hipStream_t s);
+// Batches: per-instance ||R~||, active phi rows and active-flag changes of the last update.
+void system_norms_inst(DevSystem& sys, std::vector<double>& rnorm, std::vector<int64_t>& n_active,
+                       std::vector<int64_t>& changes);
+// Batches: u += omega[i] du on instance i (omega: device, one per instance).
+void mesh_update_inst(DevMesh& m, const double* du, const double* omega, double* u, double* phi, hipStream_t s);
 void mesh_functionals(DevMesh& m, const double* u, const double* phi, const double* cod_x, int n_cod,
                       double* cod, double* tcv, hipStream_t s);
 
