@@ -969,30 +969,50 @@ __device__ __forceinline__ double read_lane(double x, int l) {
 }
 
 // Numeric phase when every row of B has at most one block (B a tentative prolongator): entry
-// A_rk lands in column B.col[k] only.  A wave owns a row; lane j loads A's entry j of the
-// current chunk of 64 and forms its product block with row k_j of B; then every output
-// column (one per lane) adds, in A's column order, the products that land on it, read from
-// the owning lanes by readlane.
-template <int BRA, int BCA, int BCB, int MODE>
+// A_rk lands in column B.col[k] only.  G lanes own a row; lane j loads A's entry j of the
+// current chunk of G and forms its product block with row k_j of B; then every output column
+// (one per lane) adds, in A's column order, the products that land on it, read from the
+// owning lanes (readlane for a whole wave, shuffles within smaller groups).  Every group
+// walks the same number of chunks (the wave's longest row), so the shuffles of a group
+// always read lanes of that group in the same step.
+template <int G>
+__device__ __forceinline__ double group_read(double x, int base, int t) {
+    if constexpr (G == kWave) return read_lane(x, t);
+    else return __shfl(x, base + t, kWave);
+}
+template <int G>
+__device__ __forceinline__ int32_t group_read(int32_t x, int base, int t) {
+    if constexpr (G == kWave) return __builtin_amdgcn_readlane(x, t);
+    else return __shfl(x, base + t, kWave);
+}
+
+template <int BRA, int BCA, int BCB, int MODE, int G>
 __global__ void __launch_bounds__(256) k_spgemm_numeric_single(SellV A, const double* __restrict__ av, SellV B,
                                                                const double* __restrict__ bv, SellV Cm,
                                                                double* __restrict__ cv,
                                                                const double* __restrict__ invd, double omega) {
-    constexpr int BB = BRA * BCB;
-    const int lane = threadIdx.x % kWave;
-    const int64_t r = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
-    if (r >= Cm.n_rows) return;
-    const int la = A.len[r], lc = Cm.len[r];
-    const int64_t s0 = r / Cm.C;
-    const int width = (Cm.sp[s0 + 1] - Cm.sp[s0]) / Cm.C;
-    for (int kc0 = 0; kc0 < width; kc0 += kWave) {
+    constexpr int BB = BRA * BCB, RPW = kWave / G;
+    const int wl = threadIdx.x % kWave, lane = wl % G, base = wl - lane;
+    const int64_t r = (int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave) * RPW + wl / G;
+    const bool live = r < Cm.n_rows;
+    const int la = live ? A.len[r] : 0, lc = live ? Cm.len[r] : 0;
+    const int64_t s0 = live ? r / Cm.C : 0;
+    const int width = live ? (Cm.sp[s0 + 1] - Cm.sp[s0]) / Cm.C : 0;
+    // loop bounds shared by the whole wave
+    int la_w = la, width_w = width;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        la_w = max(la_w, __shfl_xor(la_w, o, kWave));
+        width_w = max(width_w, __shfl_xor(width_w, o, kWave));
+    }
+    for (int kc0 = 0; kc0 < width_w; kc0 += G) {
         const int kc = kc0 + lane;
         const int64_t cs = kc < width ? sslot(Cm.sp, Cm.C, r, kc) : 0;
         const int32_t c = kc < lc ? Cm.col[cs] : -1;
         double acc[BB];
 #pragma unroll
         for (int e = 0; e < BB; ++e) acc[e] = 0.0;
-        for (int j0 = 0; j0 < la; j0 += kWave) {
+        for (int j0 = 0; j0 < la_w; j0 += G) {
             const int j = j0 + lane;
             int32_t cj = -1;
             double pj[BB];
@@ -1017,19 +1037,19 @@ __global__ void __launch_bounds__(256) k_spgemm_numeric_single(SellV A, const do
                         }
                 }
             }
-            const int nj = min(kWave, la - j0);
+            const int nj = min(G, la_w - j0);
             for (int t = 0; t < nj; ++t) {
-                const int32_t ct = __builtin_amdgcn_readlane(cj, t);
+                const int32_t ct = group_read<G>(cj, base, t);
                 double pt[BB];
 #pragma unroll
-                for (int e = 0; e < BB; ++e) pt[e] = read_lane(pj[e], t);
+                for (int e = 0; e < BB; ++e) pt[e] = group_read<G>(pj[e], base, t);
                 if (ct == c) {
 #pragma unroll
                     for (int e = 0; e < BB; ++e) acc[e] += pt[e];
                 }
             }
         }
-        if (kc < width) {
+        if (live && kc < width) {
             if (kc < lc) {
                 if (MODE == 1) {
                     double ob[BB];
@@ -1131,14 +1151,18 @@ void spgemm_numeric(const BMat<double>& A, const BMat<double>& B, BMat<double>& 
     // rows of B are long enough to keep its lanes busy; a tentative prolongator (one block
     // per row) goes to the column-parallel kernel, whose lanes share the loads of A's row
     if (B.S->max_len <= 1) {
-        // B with one block per row: a wave per row when A's rows are long (3d, coarse
-        // levels); short rows take the column-parallel kernel below, several rows per wave
-        if (A.S->nnz >= 16 * rows) {
-            k_spgemm_numeric_single<BRA, BCA, BCB, MODE><<<nblk(rows, kWavesPerBlock), 256, 0, s>>>(
-                sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), Cm.val, invd, omega);
-            FR_LAUNCH_CHECK();
-            return;
-        }
+        // B with one block per row: G lanes per row by A's mean row length (a wave for the
+        // long 3d / coarse rows, 16 or 8 lanes for 2d rows)
+        const int64_t avg_a = A.S->nnz / std::max<int64_t>(1, rows);
+#define FR_NSINGLE(G_)                                                                                 \
+    k_spgemm_numeric_single<BRA, BCA, BCB, MODE, G_><<<nblk(rows, kWavesPerBlock * (kWave / G_)), 256, 0, s>>>( \
+        sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), Cm.val, invd, omega);
+        if (avg_a >= 16) { FR_NSINGLE(64) }
+        else if (avg_a > 8) { FR_NSINGLE(16) }
+        else { FR_NSINGLE(8) }
+#undef FR_NSINGLE
+        FR_LAUNCH_CHECK();
+        return;
     } else {
         constexpr int BB = BRA * BCB;
         constexpr size_t kLds = 64 * 1024;
@@ -1154,6 +1178,14 @@ void spgemm_numeric(const BMat<double>& A, const BMat<double>& B, BMat<double>& 
         int LC = 8;
         while (LC < ml) LC <<= 1;
         const size_t per_row = size_t(LC) * (BB * sizeof(double) + sizeof(int32_t));
+        constexpr int RPB8 = kWavesPerBlock * (kWave / 8);
+        if (avg_b <= 8 && ml <= 128 && RPB8 * per_row <= kLds) {
+            // short rows of B (smoothed prolongators): 8 lanes per row, 32 rows per block
+            k_spgemm_merge<BRA, BCA, BCB, MODE, 8><<<nblk(rows, RPB8), 256, RPB8 * per_row, s>>>(
+                sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), Cm.val, invd, omega, LC);
+            FR_LAUNCH_CHECK();
+            return;
+        }
         constexpr int RPB16 = kWavesPerBlock * (kWave / 16);
         if (ml <= 256 && RPB16 * per_row <= kLds) {
             // 16 lanes per row, 16 rows per block
