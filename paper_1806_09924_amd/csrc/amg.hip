@@ -105,17 +105,29 @@ __global__ void k_mis_prop(int64_t n, int C, const int32_t* __restrict__ sp, con
     out[r] = m;
 }
 
-__global__ void __launch_bounds__(256) k_mis_update(int64_t n, const uint64_t* __restrict__ m2,
-                                                    uint8_t* __restrict__ state, uint64_t* __restrict__ key,
-                                                    int32_t* __restrict__ undecided) {
+// Second hop fused with the state update: m2 = max of m1 over the row and its strong
+// neighbours; an undecided row whose own key is that maximum becomes a root, one that sees a
+// root within two hops drops out.  (The first hop of the round has finished, and this kernel
+// reads only m1, so the rows' key and state can be updated in place.)
+__global__ void __launch_bounds__(256) k_mis_prop_update(int64_t n, int C, const int32_t* __restrict__ sp,
+                                                         const int32_t* __restrict__ len,
+                                                         const int32_t* __restrict__ col,
+                                                         const uint8_t* __restrict__ strong,
+                                                         const uint64_t* __restrict__ m1, uint8_t* __restrict__ state,
+                                                         uint64_t* __restrict__ key, int32_t* __restrict__ undecided) {
     __shared__ int sh[4];
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     int und = 0;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-        if (state[i] != 1) continue;
-        if (m2[i] == key[i]) {
+    if (i < n && state[i] == 1) {
+        uint64_t m2 = m1[i];
+        for (int k = 0; k < len[i]; ++k) {
+            const int64_t s = sslot(sp, C, i, k);
+            if (strong[s]) m2 = max(m2, m1[col[s]]);
+        }
+        if (m2 == key[i]) {
             state[i] = 2;
             key[i] = mis_key(2, i);
-        } else if ((m2[i] >> 62) == 2) {
+        } else if ((m2 >> 62) == 2) {
             state[i] = 0;
             key[i] = mis_key(0, i);
         } else {
@@ -1448,13 +1460,12 @@ static int64_t aggregate(const BMat<double>& A, const double* dnorm, double thet
     const int64_t n = S.n_rows;
     const int g = nblk(n, 256);
     DBuf<uint8_t> strong, isolated, state;
-    DBuf<uint64_t> key, m1, m2;
+    DBuf<uint64_t> key, m1;
     strong.alloc(size_t(std::max<int64_t>(1, S.n_slots)), s);
     isolated.alloc(size_t(n), s);
     state.alloc(size_t(n), s);
     key.alloc(size_t(n), s);
     m1.alloc(size_t(n), s);
-    m2.alloc(size_t(n), s);
     switch (A.br) {
         case 1: k_strength<1><<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.row_len, S.col, A.val, dnorm, theta, strong.p, isolated.p); break;
         case 2: k_strength<2><<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.row_len, S.col, A.val, dnorm, theta, strong.p, isolated.p); break;
@@ -1467,14 +1478,15 @@ static int64_t aggregate(const BMat<double>& A, const double* dnorm, double thet
     FR_LAUNCH_CHECK();
     DBuf<int32_t> und;
     und.alloc(1, s);
-    // rounds once decided are no-ops, so termination is checked every third round only
-    const int gu = int(std::min<int64_t>(1024, ceil_div(n, 256)));
+    // rounds once decided are no-ops: large levels check termination every round (a round
+    // costs more than the host round trip), small ones every third round
+    const int every = n >= (int64_t(1) << 18) ? 1 : 3;
     for (int round = 0; round < 240; ++round) {
         k_mis_prop<<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.row_len, S.col, strong.p, key.p, m1.p);
-        k_mis_prop<<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.row_len, S.col, strong.p, m1.p, m2.p);
-        const bool check = round % 3 == 2;
+        const bool check = round % every == every - 1;
         if (check) und.zero(s);
-        k_mis_update<<<gu, 256, 0, s>>>(n, m2.p, state.p, key.p, check ? und.p : nullptr);
+        k_mis_prop_update<<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.row_len, S.col, strong.p, m1.p, state.p, key.p,
+                                             check ? und.p : nullptr);
         FR_LAUNCH_CHECK();
         if (check && download1(und.p, s) == 0) break;
         if (round == 239) fail(FR_EINTERNAL, "aggregation: MIS(2) did not terminate");
