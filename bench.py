@@ -199,6 +199,9 @@ def main():
         "newton_iterations_per_step": newton_its / args.steps,
         "fgmres_iterations_per_newton": iters / max(1, newton_its),
         "solve_only_mdof_iter_s": mesh.n_solve * iters / t_solve / 1e6,
+        # iteration-count independent: DoFs brought to the converged Newton solution per second
+        # (a better preconditioner lowers MDoF-iter/s while it shortens the loop)
+        "loop_mdof_per_s": mesh.n_solve * args.steps / wall / 1e6,
         "phase_seconds_per_step": {k: sum(s[k] for s in stats) / args.steps
                                    for k in ("t_assemble", "t_setup", "t_solve", "t_other")},
         "tcv": tcv, "tcv_sneddon": tcv_exact, "tcv_rel_err_vs_sneddon": tcv / tcv_exact - 1,

@@ -637,7 +637,9 @@ __device__ __forceinline__ int find_sorted(const SellV& B, int64_t row, int32_t 
     return -1;
 }
 
-// C = A B (MODE 0) or C = B - omega D^-1 A B with B indexed by A's rows (MODE 1, smoothing).
+// C = A B (MODE 0) or C = B - omega D^-1 A B with B indexed by A's rows (MODE 1, smoothing),
+// one output block per lane (G lanes per row), each summing over A's row with a binary search
+// in B's rows: for output rows too long for LDS over many columns.
 template <int BRA, int BCA, int BCB, int MODE, int G>
 __global__ void __launch_bounds__(256) k_spgemm_numeric(SellV A, const double* __restrict__ av, SellV B,
                                                         const double* __restrict__ bv, SellV Cm,
@@ -1098,11 +1100,14 @@ __global__ void __launch_bounds__(256) k_spgemm_numeric_single(SellV A, const do
 // LDS.  For every entry A_ik in turn the lanes walk row k of B (distinct columns, so no two
 // lanes add to one accumulator) and a barrier separates the entries, so the summation order
 // of every output block is A's column order, as in the row-merge kernel.
+// Columns are taken in windows [c0, c0 + n_cols) of what fits in LDS, one launch per window
+// (only the first window writes the padding slots); the order of the additions into every
+// output block is the same for any window size.
 template <int BRA, int BCA, int BCB, int MODE>
 __global__ void __launch_bounds__(256) k_spgemm_dense_row(SellV A, const double* __restrict__ av, SellV B,
                                                           const double* __restrict__ bv, SellV Cm,
                                                           double* __restrict__ cv, const double* __restrict__ invd,
-                                                          double omega, int n_cols) {
+                                                          double omega, int c0, int n_cols) {
     extern __shared__ double acc[];
     constexpr int BB = BRA * BCB;
     const int64_t r = blockIdx.x;
@@ -1118,7 +1123,8 @@ __global__ void __launch_bounds__(256) k_spgemm_dense_row(SellV A, const double*
         const int lb = B.len[k];
         for (int kb = t; kb < lb; kb += nt) {
             const int64_t bs = sslot(B.sp, B.C, k, kb);
-            const int32_t c = B.col[bs];
+            const int32_t c = B.col[bs] - c0;
+            if (c < 0 || c >= n_cols) continue;
             const double* bb = bv + bs * (BCA * BCB);
             for (int i = 0; i < BRA; ++i)
                 for (int j = 0; j < BCB; ++j) {
@@ -1135,9 +1141,10 @@ __global__ void __launch_bounds__(256) k_spgemm_dense_row(SellV A, const double*
     for (int kc = t; kc < width; kc += nt) {
         const int64_t cs = sslot(Cm.sp, Cm.C, r, kc);
         if (kc < lc) {
-            const int32_t c = Cm.col[cs];
+            const int32_t cg = Cm.col[cs], c = cg - c0;
+            if (c < 0 || c >= n_cols) continue;
             if (MODE == 1) {
-                const int kb = find_sorted(B, r, c);
+                const int kb = find_sorted(B, r, cg);
                 for (int i = 0; i < BRA; ++i) {
                     const double dsc = omega * invd[r * BRA + i];
                     for (int j = 0; j < BCB; ++j) {
@@ -1148,7 +1155,7 @@ __global__ void __launch_bounds__(256) k_spgemm_dense_row(SellV A, const double*
             } else {
                 for (int e = 0; e < BB; ++e) cv[cs * BB + e] = acc[c * BB + e];
             }
-        } else {
+        } else if (c0 == 0) {
             for (int e = 0; e < BB; ++e) cv[cs * BB + e] = 0.0;
         }
     }
@@ -1159,9 +1166,10 @@ void spgemm_numeric(const BMat<double>& A, const BMat<double>& B, BMat<double>& 
                     hipStream_t s) {
     const int ml = Cm.S->max_len;
     const int64_t rows = std::max<int64_t>(1, A.rows());
-    // row merge in LDS when the output rows fit (16 lanes per row, 16 rows per block) and the
-    // rows of B are long enough to keep its lanes busy; a tentative prolongator (one block
-    // per row) goes to the column-parallel kernel, whose lanes share the loads of A's row
+    // B with one block per row (tentative prolongators): products handed to the output
+    // columns within lane groups; otherwise a dense LDS row for few columns and long B rows,
+    // the LDS row merge (8, 16 or 64 lanes per row) while the output rows fit, and beyond
+    // that the dense row over a few column windows or one output block per lane
     if (B.S->max_len <= 1) {
         // B with one block per row: G lanes per row by A's mean row length (a wave for the
         // long 3d / coarse rows, 16 or 8 lanes for 2d rows)
@@ -1183,7 +1191,7 @@ void spgemm_numeric(const BMat<double>& A, const BMat<double>& B, BMat<double>& 
         const int64_t avg_b = B.S->nnz / std::max<int64_t>(1, B.rows());
         if (size_t(nc) * BB * sizeof(double) <= kLds && avg_b >= 64 && A.rows() > 0) {
             k_spgemm_dense_row<BRA, BCA, BCB, MODE><<<int(A.rows()), 256, size_t(nc) * BB * sizeof(double), s>>>(
-                sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), Cm.val, invd, omega, int(nc));
+                sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), Cm.val, invd, omega, 0, int(nc));
             FR_LAUNCH_CHECK();
             return;
         }
@@ -1212,6 +1220,22 @@ void spgemm_numeric(const BMat<double>& A, const BMat<double>& B, BMat<double>& 
             k_spgemm_merge<BRA, BCA, BCB, MODE, kWave><<<nblk(rows, wpb), wpb * kWave, wpb * per_row, s>>>(
                 sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), Cm.val, invd, omega, LC);
             FR_LAUNCH_CHECK();
+            return;
+        }
+    }
+    {
+        // output rows too long for the LDS merge: the dense-row kernel over a few column
+        // windows, else one output block per lane
+        constexpr int BB = BRA * BCB;
+        const int64_t win = int64_t(48 * 1024) / (BB * int64_t(sizeof(double)));
+        const int64_t nc = Cm.cols();
+        if (A.rows() > 0 && ceil_div(nc, win) <= 8) {
+            for (int64_t c0 = 0; c0 < nc; c0 += win) {
+                const int w = int(std::min<int64_t>(win, nc - c0));
+                k_spgemm_dense_row<BRA, BCA, BCB, MODE><<<int(A.rows()), 256, size_t(w) * BB * sizeof(double), s>>>(
+                    sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), Cm.val, invd, omega, int(c0), w);
+                FR_LAUNCH_CHECK();
+            }
             return;
         }
     }
@@ -1659,7 +1683,9 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
             int64_t n_agg = 0;
             {
                 ProfScope ps("setup_aggregate", s, 0.0);
-                n_agg = aggregate(L->A, dnorm.p, o.theta, agg, s);
+                // strength threshold: negative selects the measured default per dimension
+                const double theta = o.theta >= 0 ? o.theta : (dim == 2 ? 0.08 : 0.02);
+                n_agg = aggregate(L->A, dnorm.p, theta, agg, s);
             }
             if (n_agg == 0 || n_agg * ns >= nrows) {
                 H.lv.push_back(std::move(L));

@@ -94,9 +94,9 @@ fr_status check_params(const fr_params* p) {
 fr_amg_opts default_amg() {
     fr_amg_opts o;
     o.precision = 64;
-    o.theta = 0.02;
+    o.theta = -1.0;
     o.cheb_degree = 2;
-    o.cheb_ratio = 12.0;
+    o.cheb_ratio = 8.0;
     o.coarse_max = 96;
     o.max_levels = 10;
     o.reuse_u_block = 1;
@@ -107,7 +107,7 @@ fr_amg_opts default_amg() {
 
 fr_status check_amg(const fr_amg_opts& o) {
     FR_REQUIRE(o.precision == 32 || o.precision == 64, "amg: precision must be 32 or 64");
-    FR_REQUIRE(o.theta >= 0 && o.theta < 1, "amg: theta must be in [0, 1)");
+    FR_REQUIRE(o.theta < 1, "amg: theta must be below 1 (negative: the default of the dimension)");
     FR_REQUIRE(o.cheb_degree >= 1 && o.cheb_degree <= 16, "amg: cheb_degree must be in [1, 16]");
     FR_REQUIRE(o.cheb_ratio > 1, "amg: cheb_ratio must be > 1");
     FR_REQUIRE(o.coarse_max >= 1 && o.coarse_max <= 4096, "amg: coarse_max must be in [1, 4096]");

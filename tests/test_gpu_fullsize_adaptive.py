@@ -184,8 +184,12 @@ def test_newton_fp64_and_fp32(big):
     assert np.abs(cu[inner]).max() <= 1e-7 * st["res0"]
     tau = big["oprm"].tau
     assert np.all(pg[S_] <= phi0[S_] + 2 * tau)
-    act = -cp / cm + (pg[S_] - phi0[S_]) - tau > 0
-    assert np.all(np.abs(pg[S_][act] - phi0[S_][act]) <= 1e-10)
+    margin = -cp / cm + (pg[S_] - phi0[S_]) - tau
+    # rows whose margin is within 1e-9 of the largest sit on the threshold of the active-set
+    # rule: either classification is correct to rounding, as in the active-set parity checks
+    act = margin > 1e-9 * np.abs(margin).max()
+    dev_a = np.abs(pg[S_][act] - phi0[S_][act])
+    assert np.all(dev_a <= 1e-10), (dev_a.max(), margin[act][np.argmax(dev_a)], np.abs(margin).max())
     if np.any(~act):
         assert np.abs(cp[~act]).max() <= 1e-7 * st["res0"]
     # functionals: the GPU reductions against the oracle's on the GPU fields, FP32 against
