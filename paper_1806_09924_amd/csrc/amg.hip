@@ -782,37 +782,6 @@ __global__ void k_power_init(int64_t n, double* __restrict__ x) {
     if (i < n) x[i] = 0.5 + double(hash32(uint32_t(i) ^ 0x9e3779b9u) & 0xffffu) / 65536.0;
 }
 
-__global__ void k_normalize(int64_t n, const double* __restrict__ nrm2, double* __restrict__ x) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) x[i] *= *nrm2 > 0.0 ? 1.0 / sqrt(*nrm2) : 0.0;
-}
-
-__global__ void k_normalize_copy(int64_t n, const double* __restrict__ t, const double* __restrict__ nrm2,
-                                 double* __restrict__ x) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) x[i] = t[i] * (*nrm2 > 0.0 ? 1.0 / sqrt(*nrm2) : 0.0);
-}
-
-__global__ void __launch_bounds__(256) k_mul_dot(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
-                                                 double* __restrict__ c, double* __restrict__ part) {
-    __shared__ double sh[16];
-    double acc = 0.0;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-        const double v = a[i] * b[i];
-        c[i] = v;
-        acc += v * v;
-    }
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-__global__ void __launch_bounds__(256) k_sum_parts1(const double* __restrict__ part, int n, double* __restrict__ out) {
-    __shared__ double sh[16];
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) *out = s;
-}
 
 // ---- dense coarsest level ------------------------------------------------------------------
 template <int B>
@@ -1430,33 +1399,29 @@ BMat<double> transpose(const BMat<double>& P, hipStream_t s) {
 
 // lambda_max(D^-1 A) by power iteration from a fixed pseudo-random start vector: with
 // ||x|| = 1, ||D^-1 A x|| approaches lambda_max from below.
+// Largest eigenvalue of D^-1 A by ten power steps from a fixed positive start vector.  The
+// iterates are not normalised between steps (D^-1 A has eigenvalues of order one, so ten
+// steps stay far inside the double range); the estimate is |x_10| / |x_9|.
 double lambda_max(const BMat<double>& A, const double* invd, hipStream_t s) {
     const int64_t n = A.rows() * A.br;
     if (n == 0) return 1.0;
-    DBuf<double> x, y, t, scr, nrm;
-    x.alloc(size_t(n), s);
-    y.alloc(size_t(n), s);
-    t.alloc(size_t(n), s);
+    DBuf<double> v[2], zero, scr_x, scr, nrm;
+    v[0].alloc(size_t(n), s);
+    v[1].alloc(size_t(n), s);
+    zero.alloc(size_t(n), s);
+    scr_x.alloc(size_t(n), s);
     scr.alloc(1024, s);
-    nrm.alloc(1, s);
-    k_power_init<<<nblk(n, 256), 256, 0, s>>>(n, x.p);
-    FR_LAUNCH_CHECK();
-    dev_dot(x.p, x.p, n, nrm.p, scr, s);
-    k_normalize<<<nblk(n, 256), 256, 0, s>>>(n, nrm.p, x.p);
+    nrm.alloc(2, s);
+    zero.zero(s);
+    k_power_init<<<nblk(n, 256), 256, 0, s>>>(n, v[0].p);
     FR_LAUNCH_CHECK();
     const int iters = 10;
-    const int gd = int(std::min<int64_t>(512, ceil_div(n, 256)));
-    for (int it = 0; it < iters; ++it) {
-        spmv(A, x.p, y.p, s);
-        k_mul_dot<<<gd, 256, 0, s>>>(n, invd, y.p, t.p, scr.p);   // t = D^-1 A x, partial |t|^2
-        FR_LAUNCH_CHECK();
-        k_sum_parts1<<<1, 256, 0, s>>>(scr.p, gd, nrm.p);
-        FR_LAUNCH_CHECK();
-        k_normalize_copy<<<nblk(n, 256), 256, 0, s>>>(n, t.p, nrm.p, x.p);
-        FR_LAUNCH_CHECK();
-    }
-    const double lam = std::sqrt(download1(nrm.p, s));
-    return lam > 0 ? lam : 1.0;
+    for (int it = 0; it < iters; ++it) diag_scaled_matvec(A, invd, v[it & 1].p, zero.p, v[(it + 1) & 1].p, scr_x.p, s);
+    dev_dot(v[iters & 1].p, v[iters & 1].p, n, nrm.p, scr, s);
+    dev_dot(v[(iters - 1) & 1].p, v[(iters - 1) & 1].p, n, nrm.p + 1, scr, s);
+    const auto h = download(nrm.p, 2, s);
+    const double lam = h[1] > 0 ? std::sqrt(h[0] / h[1]) : 0.0;
+    return lam > 0 && std::isfinite(lam) ? lam : 1.0;
 }
 
 }  // namespace

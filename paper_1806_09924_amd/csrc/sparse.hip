@@ -559,6 +559,13 @@ void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d
     cheb_launch<T>(A, G, invd, x_old, b, d, x_new, alpha, beta, s);
 }
 
+// y = D^-1 A x (the Chebyshev kernel with b = 0, alpha = 0, beta = -1; xn receives x + y)
+void diag_scaled_matvec(const BMat<double>& A, const double* invd, const double* x, const double* zero,
+                        double* y, double* xn, hipStream_t s) {
+    if (A.rows() == 0) return;
+    cheb_launch<double>(A, launch_lanes(*A.S), invd, x, zero, y, xn, 0.0, -1.0, s);
+}
+
 // ---- launch-shape tuner ---------------------------------------------------------------------
 // Copy of a block SELL matrix in another slice height (C = 1 stores each row contiguously, so
 // that the lanes of a row read consecutive slots); padding repeats the row's first column

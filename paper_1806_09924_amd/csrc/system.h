@@ -132,6 +132,9 @@ void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d
 template <typename T>
 void cheb_first(const T* invd, const T* b, T* d, T* x, T beta, int64_t n, hipStream_t s);
 // fused J-SpMV over the three blocks: y = J x (solve order); x may be FP32 (exactly widened)
+// y = D^-1 A x (zero: a zero vector of A's rows; xn: scratch of A's rows).
+void diag_scaled_matvec(const BMat<double>& A, const double* invd, const double* x, const double* zero,
+                        double* y, double* xn, hipStream_t s);
 // Launch shape: lanes per row of the SpMV / Chebyshev kernels for a matrix.
 int launch_lanes(const SellStruct& S);
 // Same matrix in slice height C.
