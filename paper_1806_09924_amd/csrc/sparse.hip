@@ -617,7 +617,19 @@ BMat<double> relayout(const BMat<double>& A, int C, hipStream_t s) {
     N->row_len = N->own_len.p;
     if (S.n_rows) FR_HIP(hipMemcpyAsync(N->row_len, S.row_len, size_t(S.n_rows) * sizeof(int32_t),
                                         hipMemcpyDeviceToDevice, s));
-    layout_from_lengths(*N, s, nullptr, nullptr);
+    if (C == 1) {
+        // one row per slice: the slice pointers are the row offsets and every statistic is
+        // the source's, so no host round trip is needed
+        N->n_slices = S.n_rows;
+        N->own_slice.alloc(size_t(S.n_rows) + 1, s);
+        N->slice_ptr = N->own_slice.p;
+        scan_exclusive_async(N->row_len, N->slice_ptr, S.n_rows, s);
+        N->n_slots = S.nnz;
+        N->nnz = S.nnz;
+        N->max_len = S.max_len;
+    } else {
+        layout_from_lengths(*N, s, nullptr, nullptr);
+    }
     N->own_col.alloc(size_t(std::max<int64_t>(1, N->n_slots)), s);
     N->col = N->own_col.p;
     const int BB = A.br * A.bc;
