@@ -1401,27 +1401,47 @@ BMat<double> transpose(const BMat<double>& P, hipStream_t s) {
 // ||x|| = 1, ||D^-1 A x|| approaches lambda_max from below.
 // Largest eigenvalue of D^-1 A by ten power steps from a fixed positive start vector.  The
 // iterates are not normalised between steps (D^-1 A has eigenvalues of order one, so ten
-// steps stay far inside the double range); the estimate is |x_10| / |x_9|.
-double lambda_max(const BMat<double>& A, const double* invd, hipStream_t s) {
-    const int64_t n = A.rows() * A.br;
-    if (n == 0) return 1.0;
+// steps stay far inside the double range); the estimate is |x_10| / |x_9|.  power_start
+// enqueues the steps on a stream and power_finish waits for the estimate, so that other work
+// can run in between (the buffers live in the PowerEst until then).
+struct PowerEst {
     DBuf<double> v[2], zero, scr_x, scr, nrm;
-    v[0].alloc(size_t(n), s);
-    v[1].alloc(size_t(n), s);
-    zero.alloc(size_t(n), s);
-    scr_x.alloc(size_t(n), s);
-    scr.alloc(1024, s);
-    nrm.alloc(2, s);
-    zero.zero(s);
-    k_power_init<<<nblk(n, 256), 256, 0, s>>>(n, v[0].p);
+    int64_t n = 0;
+    hipStream_t st = nullptr;
+};
+
+void power_start(PowerEst& pe, const BMat<double>& A, const double* invd, hipStream_t s) {
+    const int64_t n = A.rows() * A.br;
+    pe.n = n;
+    pe.st = s;
+    if (n == 0) return;
+    pe.v[0].alloc(size_t(n), s);
+    pe.v[1].alloc(size_t(n), s);
+    pe.zero.alloc(size_t(n), s);
+    pe.scr_x.alloc(size_t(n), s);
+    pe.scr.alloc(1024, s);
+    pe.nrm.alloc(2, s);
+    pe.zero.zero(s);
+    k_power_init<<<nblk(n, 256), 256, 0, s>>>(n, pe.v[0].p);
     FR_LAUNCH_CHECK();
     const int iters = 10;
-    for (int it = 0; it < iters; ++it) diag_scaled_matvec(A, invd, v[it & 1].p, zero.p, v[(it + 1) & 1].p, scr_x.p, s);
-    dev_dot(v[iters & 1].p, v[iters & 1].p, n, nrm.p, scr, s);
-    dev_dot(v[(iters - 1) & 1].p, v[(iters - 1) & 1].p, n, nrm.p + 1, scr, s);
-    const auto h = download(nrm.p, 2, s);
+    for (int it = 0; it < iters; ++it)
+        diag_scaled_matvec(A, invd, pe.v[it & 1].p, pe.zero.p, pe.v[(it + 1) & 1].p, pe.scr_x.p, s);
+    dev_dot(pe.v[iters & 1].p, pe.v[iters & 1].p, n, pe.nrm.p, pe.scr, s);
+    dev_dot(pe.v[(iters - 1) & 1].p, pe.v[(iters - 1) & 1].p, n, pe.nrm.p + 1, pe.scr, s);
+}
+
+double power_finish(PowerEst& pe) {
+    if (pe.n == 0) return 1.0;
+    const auto h = download(pe.nrm.p, 2, pe.st);
     const double lam = h[1] > 0 ? std::sqrt(h[0] / h[1]) : 0.0;
     return lam > 0 && std::isfinite(lam) ? lam : 1.0;
+}
+
+double lambda_max(const BMat<double>& A, const double* invd, hipStream_t s) {
+    PowerEst pe;
+    power_start(pe, A, invd, s);
+    return power_finish(pe);
 }
 
 }  // namespace
@@ -1618,10 +1638,18 @@ static void coarse_inverse(Hierarchy& H, hipStream_t s) {
 
 // `keep` stores the tentative prolongators and the products A P so that the values can later
 // be recomputed for a new matrix with the same sparsity (refresh_hierarchy).
+// The power iteration of a level runs on `aux` beside the aggregation and the tentative
+// prolongator (which do not need it) and is waited for before the prolongator smoothing.
 static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double* coords, int dim,
-                            const fr_amg_opts& o, bool keep, hipStream_t s) {
+                            const fr_amg_opts& o, bool keep, hipStream_t s, hipStream_t aux) {
     H.lv.clear();
     H.refreshable = keep;
+    struct Ev {
+        hipEvent_t e = nullptr;
+        Ev() { FR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming)); }
+        ~Ev() { if (e) (void)hipEventDestroy(e); }
+    } ev_holder;
+    const hipEvent_t ev_aux = ev_holder.e;
     DBuf<int> errs;    // capacity overflows of the SpGEMM fills, read once at the end
     errs.alloc(1, s);
     errs.zero(s);
@@ -1639,7 +1667,13 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
         {
             ProfScope ps("setup_lambda", s, 0.0);
             diag_info(L->A, L->invd, dnorm, s);
-            L->lmax = lambda_max(L->A, L->invd.p, s);
+        }
+        PowerEst pe;
+        {
+            FR_HIP(hipEventRecord(ev_aux, s));
+            FR_HIP(hipStreamWaitEvent(aux, ev_aux, 0));
+            ProfScope ps("setup_lambda", aux, 0.0);
+            power_start(pe, L->A, L->invd.p, aux);
         }
         const int64_t nrows = L->A.rows() * L->A.br;
         const bool last = nrows <= o.coarse_max || l + 1 >= o.max_levels;
@@ -1653,6 +1687,7 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
                 n_agg = aggregate(L->A, dnorm.p, theta, agg, s);
             }
             if (n_agg == 0 || n_agg * ns >= nrows) {
+                L->lmax = power_finish(pe);
                 H.lv.push_back(std::move(L));
                 break;   // coarsening stalled: this level is the coarsest
             }
@@ -1662,6 +1697,7 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
                 ProfScope ps("setup_tentative", s, 0.0);
                 Pt = tentative(L->A, agg, n_agg, ns, l == 0, coords, dim, Bf.p, Bc, s);
             }
+            L->lmax = power_finish(pe);
             {
                 ProfScope ps("setup_smooth_p", s, 0.0);
                 const double omega = 4.0 / (3.0 * L->lmax);
@@ -1683,6 +1719,7 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
             H.lv.push_back(std::move(L));
             continue;
         }
+        L->lmax = power_finish(pe);
         H.lv.push_back(std::move(L));
         break;
     }
@@ -1734,6 +1771,7 @@ static void refresh_hierarchy(Hierarchy& H, double* a0, const fr_amg_opts& o, hi
 static void ensure_side(DevAmg& amg) {
     if (amg.side) return;
     FR_HIP(hipStreamCreateWithFlags(&amg.side, hipStreamNonBlocking));
+    for (auto& a : amg.aux) FR_HIP(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
     FR_HIP(hipEventCreateWithFlags(&amg.ev_fork, hipEventDisableTiming));
     FR_HIP(hipEventCreateWithFlags(&amg.ev_join, hipEventDisableTiming));
 }
@@ -1775,7 +1813,8 @@ void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s)
             Ap.br = Ap.bc = 1;
             Ap.S = sys.Jpp.S;
             Ap.val = sys.Jpp.val;
-            build_hierarchy(amg.h[1], std::move(Ap), 1, m.coords_free.p, m.dim, o, o.refresh_phi != 0, side);
+            build_hierarchy(amg.h[1], std::move(Ap), 1, m.coords_free.p, m.dim, o, o.refresh_phi != 0, side,
+                            amg.aux[1]);
         }
     };
     auto u_setup = [&]() {
@@ -1783,7 +1822,7 @@ void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s)
         Au.br = Au.bc = m.dim;
         Au.S = sys.Juu.S;
         Au.val = sys.Juu.val;
-        build_hierarchy(amg.h[0], std::move(Au), m.dim == 2 ? 3 : 6, m.coords_free.p, m.dim, o, false, s);
+        build_hierarchy(amg.h[0], std::move(Au), m.dim == 2 ? 3 : 6, m.coords_free.p, m.dim, o, false, s, amg.aux[0]);
     };
     if (keep_u) {
         phi_setup();

@@ -559,7 +559,9 @@ void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d
     cheb_launch<T>(A, G, invd, x_old, b, d, x_new, alpha, beta, s);
 }
 
-// y = D^-1 A x (the Chebyshev kernel with b = 0, alpha = 0, beta = -1; xn receives x + y)
+// y = D^-1 A x (the Chebyshev kernel with b = 0, alpha = 0, beta = -1; xn receives x + y),
+// in the matrix's launch shape (a refreshed hierarchy's levels carry tuned shapes, so its
+// estimates can differ from the build's in the last bits)
 void diag_scaled_matvec(const BMat<double>& A, const double* invd, const double* x, const double* zero,
                         double* y, double* xn, hipStream_t s) {
     if (A.rows() == 0) return;

@@ -180,6 +180,7 @@ struct DevAmg {
     uint64_t sys_version = 0;
     // the phi V-cycle runs on a second stream (default priority) beside the u V-cycle
     hipStream_t side = nullptr;
+    hipStream_t aux[2] = {nullptr, nullptr};     // setup: power iterations of the u / phi hierarchy
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     DBuf<float> z32;                             // FP32 result staging of amg_precondition
     // Replayable V-cycles: each block's cycle captured once per setup as a HIP graph that
@@ -193,6 +194,8 @@ struct DevAmg {
             if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
     }
     ~DevAmg() {
+        for (auto a : aux)
+            if (a) (void)hipStreamSynchronize(a);
         if (side) (void)hipStreamSynchronize(side);
         if (stream) (void)hipStreamSynchronize(stream);
         drop_graphs();
@@ -202,9 +205,13 @@ struct DevAmg {
             H.dense_inv.release();
         }
         if (side) forget_stream(side);   // synchronises the side stream
+        for (auto a : aux)
+            if (a) forget_stream(a);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (side) (void)hipStreamDestroy(side);
+        for (auto a : aux)
+            if (a) (void)hipStreamDestroy(a);
     }
 };
 

@@ -342,21 +342,27 @@ def test_newton_reuses_working_storage_exactly():
 def test_graph_replay_matches_direct_launches(precision):
     """The V-cycles replayed from captured HIP graphs give bit-identical updates to the
     directly launched ones (same kernels, same order on each stream), over two solves with
-    one preconditioner and a rebuild in between (the graphs are captured again)."""
+    one preconditioner, and again after a second setup (a phase-field refresh: the graphs are
+    captured again).  The refreshed preconditioner itself may differ from the first in the
+    last bits (its lambda_max estimates use the tuned launch shapes), so the solutions before
+    and after it agree to the solver tolerance."""
     P = Problem(2, 2.0, 64)
     S = _gpu_system(P)
     A = B.Amg(S, B.amg_opts(precision=precision))
-    outs = {}
-    for graphs in (0, 1, 1):
+
+    def solve(graphs):
         du = torch.empty(P.mesh.n_solve, dtype=torch.float64, device="cuda")
         st = B.solve(S, A, du, B.solve_opts(rtol=1e-10, use_graphs=graphs))
-        outs.setdefault(graphs, []).append((host(du), st["iters"]))
+        return host(du), st["iters"]
+
+    first = [solve(g) for g in (0, 1, 1)]
     A.setup(B.amg_opts(precision=precision))
-    du = torch.empty(P.mesh.n_solve, dtype=torch.float64, device="cuda")
-    B.solve(S, A, du, B.solve_opts(rtol=1e-10, use_graphs=1))
-    d0, i0 = outs[0][0]
-    for d, i in outs[1] + [(host(du), i0)]:
-        assert np.array_equal(d, d0) and i == i0
+    second = [solve(g) for g in (1, 0, 1)]
+    for outs in (first, second):
+        d0, i0 = outs[0]
+        for d, i in outs[1:]:
+            assert np.array_equal(d, d0) and i == i0
+    assert np.abs(second[0][0] - first[0][0]).max() <= 1e-8 * np.abs(first[0][0]).max()
 
 
 @pytest.mark.parametrize("dim,n", [(2, 256), (3, 32)])
