@@ -98,7 +98,7 @@ template <typename T, int BR, int BC, int MODE, int G>
 __global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, int C, const int32_t* __restrict__ slice_ptr,
                                               const int32_t* __restrict__ col, const T* __restrict__ val,
                                               const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y) {
-    constexpr int U = BR * BC == 1 ? 8 : (BR * BC <= 4 ? 4 : 2);
+    constexpr int U = BR * BC == 1 ? 8 : 2;   // block rows: two entries in flight (measured fastest for 2x2)
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t r = t / G;
     const int g = int(t % G);
