@@ -840,6 +840,7 @@ std::unique_ptr<DevMesh> mesh_create(const fr_mesh_desc* d, int n_inst, hipStrea
     g->slice_ptr = g->own_slice.p;
     g->row_len = g->own_len.p;
     g->col = g->own_col.p;
+    make_col16(*g, s);
     m->graph = g;
     m->ent_ptr.upload(p.ent_ptr, s);
     m->ent_cell.upload(p.ent_cell, s);

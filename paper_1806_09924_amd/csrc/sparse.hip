@@ -13,18 +13,28 @@
 namespace fr {
 namespace {
 
-// acc += (row of A) x over the w slots of one SELL row starting at `slot` (stride C).  The
+// Column of a slot of row r: stored as an int32 index, or as an int16 offset from the row
+// (meshes whose node numbering keeps every neighbour within 32767 of the node: 2 bytes
+// instead of 4 per stored block on the finest level).
+__device__ __forceinline__ int64_t col_at(const int32_t* __restrict__ col, int64_t slot, int64_t) {
+    return col[slot];
+}
+__device__ __forceinline__ int64_t col_at(const int16_t* __restrict__ col, int64_t slot, int64_t r) {
+    return r + col[slot];
+}
+
+// acc += (row r of A) x over the w slots of the row starting at `slot` (stride C).  The
 // entries are taken U at a time with every load of a group issued before its products, so
 // a lane keeps several gathers in flight; the summation order stays entry by entry.
-template <typename T, int BR, int BC, int U>
-__device__ __forceinline__ void row_product(int w, int C, int64_t slot, const int32_t* __restrict__ col,
+template <typename T, int BR, int BC, int U, typename CI>
+__device__ __forceinline__ void row_product(int w, int C, int64_t slot, int64_t r, const CI* __restrict__ col,
                                             const T* __restrict__ val, const T* __restrict__ x, T* acc) {
     constexpr int BB = BR * BC;
     int k = 0;
     for (; k + U <= w; k += U, slot += int64_t(U) * C) {
         int64_t c[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) c[u] = col[slot + int64_t(u) * C];
+        for (int u = 0; u < U; ++u) c[u] = col_at(col, slot + int64_t(u) * C, r);
         T xv[U][BC];
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -43,7 +53,7 @@ __device__ __forceinline__ void row_product(int w, int C, int64_t slot, const in
                 for (int j = 0; j < BC; ++j) acc[i] += v[u][i * BC + j] * xv[u][j];
     }
     for (; k < w; ++k, slot += C) {
-        const int64_t c = col[slot];
+        const int64_t c = col_at(col, slot, r);
         const T* v = val + slot * BB;
         T xv[BC];
 #pragma unroll
@@ -58,16 +68,16 @@ __device__ __forceinline__ void row_product(int w, int C, int64_t slot, const in
 // With G > 1 lanes per row (small levels, long rows: few rows would leave most of the chip
 // idle), lane g of a group takes entries g, g+G, ... and the group combines its partial sums
 // by an xor butterfly, which leaves the same total on every lane of the group.
-template <typename T, int BR, int BC, int G, int U>
-__device__ __forceinline__ void row_product_g(int w, int C, int64_t slot0, int g, const int32_t* __restrict__ col,
+template <typename T, int BR, int BC, int G, int U, typename CI>
+__device__ __forceinline__ void row_product_g(int w, int C, int64_t slot0, int64_t r, int g, const CI* __restrict__ col,
                                               const T* __restrict__ val, const T* __restrict__ x, T* acc) {
     if constexpr (G == 1) {
-        row_product<T, BR, BC, U>(w, C, slot0, col, val, x, acc);
+        row_product<T, BR, BC, U>(w, C, slot0, r, col, val, x, acc);
     } else {
         constexpr int BB = BR * BC;
         for (int k = g; k < w; k += G) {
             const int64_t slot = slot0 + int64_t(k) * C;
-            const int64_t c = col[slot];
+            const int64_t c = col_at(col, slot, r);
             const T* v = val + slot * BB;
             T xv[BC];
 #pragma unroll
@@ -94,9 +104,9 @@ inline int lanes_per_row(const SellStruct& S) {
 }
 
 // MODE 0: y = A x; 1: y = b - A x; 2: y += A x
-template <typename T, int BR, int BC, int MODE, int G>
+template <typename T, int BR, int BC, int MODE, int G, typename CI>
 __global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, int C, const int32_t* __restrict__ slice_ptr,
-                                              const int32_t* __restrict__ col, const T* __restrict__ val,
+                                              const CI* __restrict__ col, const T* __restrict__ val,
                                               const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y) {
     constexpr int U = BR * BC == 1 ? 8 : 2;   // block rows: two entries in flight (measured fastest for 2x2)
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -116,7 +126,7 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, int C, const int32
     T acc[BR];
 #pragma unroll
     for (int i = 0; i < BR; ++i) acc[i] = T(0);
-    row_product_g<T, BR, BC, G, U>(w, C, int64_t(p0) + lane, g, col, val, x, acc);
+    row_product_g<T, BR, BC, G, U>(w, C, int64_t(p0) + lane, r, g, col, val, x, acc);
     if (g != 0) return;
 #pragma unroll
     for (int i = 0; i < BR; ++i) {
@@ -127,9 +137,9 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, int C, const int32
 }
 
 // Chebyshev step: r = b - A x_old; d = alpha d + beta D^-1 r; x_new = x_old + d
-template <typename T, int B, int G>
+template <typename T, int B, int G, typename CI>
 __global__ void __launch_bounds__(256) k_cheb(int64_t n_rows, int C, const int32_t* __restrict__ slice_ptr,
-                                              const int32_t* __restrict__ col, const T* __restrict__ val,
+                                              const CI* __restrict__ col, const T* __restrict__ val,
                                               const T* __restrict__ invd, const T* __restrict__ x_old,
                                               const T* __restrict__ b, T* __restrict__ d, T* __restrict__ x_new,
                                               T alpha, T beta) {
@@ -158,7 +168,7 @@ __global__ void __launch_bounds__(256) k_cheb(int64_t n_rows, int C, const int32
     T acc[B];
 #pragma unroll
     for (int i = 0; i < B; ++i) acc[i] = T(0);
-    row_product_g<T, B, B, G, U>(w, C, int64_t(p0) + lane, g, col, val, x_old, acc);
+    row_product_g<T, B, B, G, U>(w, C, int64_t(p0) + lane, r, g, col, val, x_old, acc);
     if (g != 0) return;
 #pragma unroll
     for (int i = 0; i < B; ++i) {
@@ -182,9 +192,9 @@ __global__ void k_cheb_first(int64_t n, const T* __restrict__ invd, const T* __r
 
 // y = J x over the coupled system (u rows: M_uu; phi rows: M_phiu and M_phiphi).  x is FP64,
 // or FP32 (widened exactly on load); the arithmetic is FP64.
-template <int D, typename TX>
+template <int D, typename TX, typename CI>
 __global__ void __launch_bounds__(256) k_jspmv(int64_t nf, int C, const int32_t* __restrict__ slice_ptr,
-                                               const int32_t* __restrict__ col, const double* __restrict__ uu,
+                                               const CI* __restrict__ col, const double* __restrict__ uu,
                                                const double* __restrict__ pu, const double* __restrict__ pp,
                                                const TX* __restrict__ x, double* __restrict__ y,
                                                TX* __restrict__ xcopy) {
@@ -200,7 +210,7 @@ __global__ void __launch_bounds__(256) k_jspmv(int64_t nf, int C, const int32_t*
     for (int i = 0; i < D; ++i) au[i] = 0.0;
     int64_t slot = int64_t(p0) + lane;
     for (int k = 0; k < w; ++k, slot += C) {
-        const int64_t c = col[slot];
+        const int64_t c = col_at(col, slot, r);
         double xu[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) xu[j] = double(x[c * D + j]);
@@ -479,10 +489,16 @@ static void spmv_launch(const BMat<T>& A, int G, const T* x, const T* b, T* y, h
     const SellStruct& S = *A.S;
     const int gg = nblk(S.n_rows * G, 256);
 #define FR_SPMV_G(BR_, BC_, G_)                                                                      \
-    k_spmv<T, BR_, BC_, MODE, G_><<<gg, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, x, b, y);
+    k_spmv<T, BR_, BC_, MODE, G_, int32_t><<<gg, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, x, b, y);
 #define FR_SPMV_CALL(BR_, BC_)                                                                       \
     switch (G) {                                                                                     \
-        case 1: FR_SPMV_G(BR_, BC_, 1) break;                                                        \
+        case 1:                                                                                      \
+            if (S.col16)                                                                             \
+                k_spmv<T, BR_, BC_, MODE, 1, int16_t><<<gg, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr,  \
+                                                                       S.col16, A.val, x, b, y);     \
+            else                                                                                     \
+                FR_SPMV_G(BR_, BC_, 1)                                                               \
+            break;                                                                                   \
         case 4: FR_SPMV_G(BR_, BC_, 4) break;                                                        \
         case 16: FR_SPMV_G(BR_, BC_, 16) break;                                                      \
         default: FR_SPMV_G(BR_, BC_, 64) break;                                                      \
@@ -503,7 +519,8 @@ static void spmv_mode(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_
     char name[48];
     if (G == 1) std::snprintf(name, sizeof(name), "spmv_%s_%dx%d_m%d", sizeof(T) == 8 ? "f64" : "f32", br, bc, MODE);
     else std::snprintf(name, sizeof(name), "spmv_%s_%dx%d_m%d_g%d", sizeof(T) == 8 ? "f64" : "f32", br, bc, MODE, G);
-    const double bytes = double(S.nnz) * (br * bc * sizeof(T) + 4) + double(S.n_cols) * bc * sizeof(T) +
+    const double ib = (S.col16 && G == 1) ? 2.0 : 4.0;   // index bytes per stored block
+    const double bytes = double(S.nnz) * (br * bc * sizeof(T) + ib) + double(S.n_cols) * bc * sizeof(T) +
                          double(S.n_rows) * br * sizeof(T) * (MODE == 0 ? 1 : 2);
     ProfScope ps(name, s, bytes);
     spmv_launch<T, MODE>(A, G, x, b, y, s);
@@ -522,11 +539,17 @@ static void cheb_launch(const BMat<T>& A, int G, const T* invd, const T* x_old, 
     const SellStruct& S = *A.S;
     const int gg = nblk(S.n_rows * G, 256);
 #define FR_CHEB_G(B_, G_)                                                                            \
-    k_cheb<T, B_, G_><<<gg, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, invd, x_old, b, d, x_new, \
-                                         alpha, beta);
+    k_cheb<T, B_, G_, int32_t><<<gg, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, A.val, invd, x_old, b, d, \
+                                                  x_new, alpha, beta);
 #define FR_CHEB_CALL(B_)                                                                             \
     switch (G) {                                                                                     \
-        case 1: FR_CHEB_G(B_, 1) break;                                                              \
+        case 1:                                                                                      \
+            if (S.col16)                                                                             \
+                k_cheb<T, B_, 1, int16_t><<<gg, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col16, A.val, invd, \
+                                                              x_old, b, d, x_new, alpha, beta);      \
+            else                                                                                     \
+                FR_CHEB_G(B_, 1)                                                                     \
+            break;                                                                                   \
         case 4: FR_CHEB_G(B_, 4) break;                                                              \
         case 16: FR_CHEB_G(B_, 16) break;                                                            \
         default: FR_CHEB_G(B_, 64) break;                                                            \
@@ -553,10 +576,49 @@ void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d
     char name[48];
     if (G == 1) std::snprintf(name, sizeof(name), "cheb_%s_b%d", sizeof(T) == 8 ? "f64" : "f32", A.br);
     else std::snprintf(name, sizeof(name), "cheb_%s_b%d_g%d", sizeof(T) == 8 ? "f64" : "f32", A.br, G);
-    // matrix once, x gathered once, b, d, D^-1 read, d and x_new written
-    const double bytes = double(S.nnz) * (A.br * A.bc * sizeof(T) + 4) + double(S.n_rows) * A.br * sizeof(T) * 6;
+    // matrix once (index bytes 2 with row offsets), x gathered once, b, d, D^-1 read, d and
+    // x_new written
+    const double ib = (S.col16 && G == 1) ? 2.0 : 4.0;
+    const double bytes = double(S.nnz) * (A.br * A.bc * sizeof(T) + ib) + double(S.n_rows) * A.br * sizeof(T) * 6;
     ProfScope ps(name, s, bytes);
     cheb_launch<T>(A, G, invd, x_old, b, d, x_new, alpha, beta, s);
+}
+
+// Row offsets of a SELL structure's columns as int16 (rows beyond n_rows in the last slice
+// get 0); *misfit is set when an offset does not fit.
+__global__ void k_col16(int64_t n_rows, int C, const int32_t* __restrict__ sp, const int32_t* __restrict__ col,
+                        int16_t* __restrict__ col16, int* __restrict__ misfit) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t n_pad = ((n_rows + C - 1) / C) * C;
+    if (r >= n_pad) return;
+    const int64_t s0 = r / C;
+    const int lane = int(r - s0 * C);
+    const int w = (sp[s0 + 1] - sp[s0]) / C;
+    bool bad = false;
+    for (int k = 0; k < w; ++k) {
+        const int64_t slot = int64_t(sp[s0]) + int64_t(k) * C + lane;
+        const int64_t off = r < n_rows ? int64_t(col[slot]) - r : 0;
+        bad = bad || off < -32768 || off > 32767;
+        col16[slot] = int16_t(bad ? 0 : off);
+    }
+    if (bad) atomicOr(misfit, 1);
+}
+
+void make_col16(SellStruct& S, hipStream_t s) {
+    if (S.n_rows == 0 || S.n_slots == 0) return;
+    S.own_col16.alloc(size_t(S.n_slots), s);
+    DBuf<int> misfit;
+    misfit.alloc(1, s);
+    misfit.zero(s);
+    const int64_t n_pad = ceil_div(S.n_rows, S.C) * S.C;
+    k_col16<<<nblk(n_pad, 256), 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, S.own_col16.p, misfit.p);
+    FR_LAUNCH_CHECK();
+    if (download1(misfit.p, s) == 0) {
+        S.col16 = S.own_col16.p;
+    } else {
+        S.own_col16.release();
+        S.col16 = nullptr;
+    }
 }
 
 // y = D^-1 A x (the Chebyshev kernel with b = 0, alpha = 0, beta = -1; xn receives x + y),
@@ -790,16 +852,22 @@ static void jspmv_t(const DevSystem& sys, const TX* x, double* y, hipStream_t s,
     const SellStruct& S = *sys.Juu.S;
     const int g = nblk(S.n_rows, 256);
     const int D = sys.mesh->dim;
-    const double bytes = double(S.nnz) * ((D * D + D + 1) * 8 + 4) + double(S.n_rows) * (D + 1) * (sizeof(TX) + 8);
+    const double ib = S.col16 ? 2.0 : 4.0;
+    const double bytes = double(S.nnz) * ((D * D + D + 1) * 8 + ib) + double(S.n_rows) * (D + 1) * (sizeof(TX) + 8);
     char name[32];
     std::snprintf(name, sizeof(name), "jspmv_d%d%s", D, sizeof(TX) == 4 ? "_x32" : "");
     ProfScope ps(name, s, bytes);
-    if (D == 2)
-        k_jspmv<2, TX><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, sys.Juu.val, sys.Jpu.val, sys.Jpp.val, x, y,
-                                         xcopy);
-    else
-        k_jspmv<3, TX><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, S.col, sys.Juu.val, sys.Jpu.val, sys.Jpp.val, x, y,
-                                         xcopy);
+#define FR_JSPMV(D_, CI_, COL_)                                                                        \
+    k_jspmv<D_, TX, CI_><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, COL_, sys.Juu.val, sys.Jpu.val, sys.Jpp.val, \
+                                           x, y, xcopy);
+    if (D == 2) {
+        if (S.col16) { FR_JSPMV(2, int16_t, S.col16) }
+        else { FR_JSPMV(2, int32_t, S.col) }
+    } else {
+        if (S.col16) { FR_JSPMV(3, int16_t, S.col16) }
+        else { FR_JSPMV(3, int32_t, S.col) }
+    }
+#undef FR_JSPMV
     FR_LAUNCH_CHECK();
 }
 

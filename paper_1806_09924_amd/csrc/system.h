@@ -30,7 +30,11 @@ struct SellStruct {
     int32_t* slice_ptr = nullptr;   // [n_slices+1]
     int32_t* row_len = nullptr;     // [n_rows]
     int32_t* col = nullptr;         // [n_slots]
+    // [n_slots] or null: the columns as int16 offsets from the row (slot's column - row), when
+    // all fit; the one-lane-per-row SpMV, Chebyshev and J-SpMV kernels then read these
+    int16_t* col16 = nullptr;
     DBuf<int32_t> own_slice, own_len, own_col;
+    DBuf<int16_t> own_col16;
 };
 
 template <typename T>
@@ -135,6 +139,8 @@ void cheb_first(const T* invd, const T* b, T* d, T* x, T beta, int64_t n, hipStr
 // y = D^-1 A x (zero: a zero vector of A's rows; xn: scratch of A's rows).
 void diag_scaled_matvec(const BMat<double>& A, const double* invd, const double* x, const double* zero,
                         double* y, double* xn, hipStream_t s);
+// Sets S.col16 (columns as int16 row offsets) when every offset fits.
+void make_col16(SellStruct& S, hipStream_t s);
 // Launch shape: lanes per row of the SpMV / Chebyshev kernels for a matrix.
 int launch_lanes(const SellStruct& S);
 // Same matrix in slice height C.
