@@ -130,6 +130,21 @@ def test_amg_hierarchy_algebra():
         assert all(b < a for a, b in zip(rows, rows[1:]))
 
 
+@pytest.mark.parametrize("theta", [-1.0, 0.05])
+def test_amg_hierarchy_algebra_3d(theta):
+    """3d: 3x3 fine blocks, 6x6 coarse blocks whose long Galerkin rows take the wave-per-row
+    merge, the dense-row products over column windows and the per-lane products; theta 0.05
+    coarsens slowly, so its coarse operators are the densest."""
+    P = Problem(3, 1.0, 24, l0=0.4)
+    S = _gpu_system(P)
+    A = B.Amg(S, B.amg_opts(precision=64, theta=theta))
+    o = _oracle_system(P)
+    nu = 3 * P.mesh.n_free
+    for blk, ref in ((0, o.Jm[:nu, :nu]), (1, o.Jm[nu:, nu:])):
+        assert A.n_levels(blk) >= 3
+        _galerkin_checks(A, blk, ref)
+
+
 def _galerkin_checks(A, blk, ref0):
     nl = A.n_levels(blk)
     shp, rp, ci, vv = A.level_csr(blk, 0, 0)
