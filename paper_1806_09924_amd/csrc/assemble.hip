@@ -292,14 +292,45 @@ __global__ void __launch_bounds__(128) k_jacobian(MeshView mv, Params prm0, cons
     const int64_t sl = f / mv.C;
     const int width = (mv.slice_ptr[sl + 1] - mv.slice_ptr[sl]) / mv.C;
     int32_t hc = HANG ? mv.hang_ptr[f] : 0;   // next master position of a hanging vertex
-    for (int k = 0; k < width; ++k) {
-        const int64_t s = slot_of<D>(mv, f, k);
+    // Rows of up to 128 slots record which slots they have written: a slot's first
+    // contribution is stored, later ones added, and the slots never written (padding) are
+    // zeroed at the end, so no slot is zeroed and then read back.  Longer rows zero first.
+    const bool track = width <= 128;
+    uint64_t touched[2] = {0u, 0u};
+    if (!track) {
+        for (int k = 0; k < width; ++k) {
+            const int64_t s = slot_of<D>(mv, f, k);
 #pragma unroll
-        for (int i = 0; i < DD; ++i) Juu[s * DD + i] = 0.0;
+            for (int i = 0; i < DD; ++i) Juu[s * DD + i] = 0.0;
 #pragma unroll
-        for (int i = 0; i < D; ++i) Jpu[s * D + i] = 0.0;
-        Jpp[s] = 0.0;
+            for (int i = 0; i < D; ++i) Jpu[s * D + i] = 0.0;
+            Jpp[s] = 0.0;
+        }
     }
+    // slot k += w * (kuu, kpu, kpp), or = on its first write
+    auto add_slot = [&](int k, double w, const double (&ku)[D][D], const double (&kp)[D], double kq) {
+        const int64_t s = slot_of<D>(mv, f, k);
+        const uint64_t bit = uint64_t(1) << (k & 63);
+        const bool first = track && !(touched[k >> 6] & bit);
+        if (track) touched[k >> 6] |= bit;
+        if (first) {
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+#pragma unroll
+                for (int d = 0; d < D; ++d) Juu[s * DD + c * D + d] = w * ku[c][d];
+#pragma unroll
+            for (int d = 0; d < D; ++d) Jpu[s * D + d] = w * kp[d];
+            Jpp[s] = w * kq;
+        } else {
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+#pragma unroll
+                for (int d = 0; d < D; ++d) Juu[s * DD + c * D + d] += w * ku[c][d];
+#pragma unroll
+            for (int d = 0; d < D; ++d) Jpu[s * D + d] += w * kp[d];
+            Jpp[s] += w * kq;
+        }
+    };
     for (int32_t e = mv.ent_ptr[f]; e < mv.ent_ptr[f + 1]; ++e) {
         const int32_t cell = mv.ent_cell[e];
         const int a = mv.ent_a[e];
@@ -438,29 +469,25 @@ __global__ void __launch_bounds__(128) k_jacobian(MeshView mv, Params prm0, cons
                 for (int d = 0; d < D; ++d) kuu[c][d] = prm.mu * ((c == d ? trT : 0.0) + T[d][c]) + prm.lam * T[c][d];
             const int kk = mv.ent_k[int64_t(e) * NV + b];
             if (kk != 255) {
-                const int64_t s = slot_of<D>(mv, f, kk);
-#pragma unroll
-                for (int c = 0; c < D; ++c)
-#pragma unroll
-                    for (int d = 0; d < D; ++d) Juu[s * DD + c * D + d] += W * kuu[c][d];
-#pragma unroll
-                for (int d = 0; d < D; ++d) Jpu[s * D + d] += W * kpu[d];
-                Jpp[s] += W * kpp;
+                add_slot(kk, W, kuu, kpu, kpp);
             } else if (HANG) {
                 const int32_t n = mv.cells[int64_t(cell) * NV + b];
                 for (int32_t j = mv.con_ptr[n]; j < mv.con_ptr[n + 1]; ++j) {
                     const int k2 = mv.hang_k[hc++];
-                    const double ww = W * mv.con_w[j];
-                    const int64_t s = slot_of<D>(mv, f, k2);
-#pragma unroll
-                    for (int c = 0; c < D; ++c)
-#pragma unroll
-                        for (int d = 0; d < D; ++d) Juu[s * DD + c * D + d] += ww * kuu[c][d];
-#pragma unroll
-                    for (int d = 0; d < D; ++d) Jpu[s * D + d] += ww * kpu[d];
-                    Jpp[s] += ww * kpp;
+                    add_slot(k2, W * mv.con_w[j], kuu, kpu, kpp);
                 }
             }
+        }
+    }
+    if (track) {
+        for (int k = 0; k < width; ++k) {
+            if (touched[k >> 6] & (uint64_t(1) << (k & 63))) continue;
+            const int64_t s = slot_of<D>(mv, f, k);
+#pragma unroll
+            for (int i = 0; i < DD; ++i) Juu[s * DD + i] = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) Jpu[s * D + i] = 0.0;
+            Jpp[s] = 0.0;
         }
     }
     // elimination of Dirichlet u DoFs (target u = 0) and active phi DoFs (target phi_old)
