@@ -66,6 +66,12 @@ struct MeshView {
     const double* ent_w;
     const int32_t* hang_ptr;       // masters' row positions for hanging vertices (hanging meshes)
     const uint8_t* hang_k;
+    // Rows with more than 2^d entries (masters of hanging nodes: their dependents' cells too)
+    // run in a second launch over this list, so that they do not hold up the waves of
+    // ordinary rows; pass 0 skips them, pass 1 takes them.
+    const int32_t* heavy;
+    int64_t n_heavy;
+    int pass;
     int C;
     int64_t n_free;
     const int32_t* inst_of_free;   // nullptr for one instance
@@ -83,6 +89,9 @@ MeshView view(const DevMesh& m) {
     v.ent_ptr = m.ent_ptr.p; v.ent_cell = m.ent_cell.p; v.ent_a = m.ent_a.p; v.ent_k = m.ent_k.p;
     v.ent_w = m.ent_w.p;
     v.hang_ptr = m.hang_ptr.p; v.hang_k = m.hang_k.p;
+    v.heavy = m.n_heavy > 0 ? m.heavy_rows.p : nullptr;
+    v.n_heavy = m.n_heavy;
+    v.pass = 0;
     v.C = m.graph->C;
     v.n_free = m.n_free;
     v.inst_of_free = m.n_inst > 1 ? m.inst_of_free.p : nullptr;
@@ -95,6 +104,16 @@ MeshView view(const DevSystem& sys) {
     MeshView v = view(*sys.mesh);
     v.prm_arr = sys.mesh->n_inst > 1 ? sys.prm_d.p : nullptr;
     return v;
+}
+
+// Row of this thread in the current pass, or -1.
+template <int NV>
+__device__ __forceinline__ int64_t pass_row(const MeshView& mv) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (mv.pass == 1) return t < mv.n_heavy ? int64_t(mv.heavy[t]) : -1;
+    if (t >= mv.n_free) return -1;
+    if (mv.heavy && mv.ent_ptr[t + 1] - mv.ent_ptr[t] > NV) return -1;
+    return t;
 }
 
 __device__ __forceinline__ Params row_params(const MeshView& mv, const Params& prm0, int64_t f) {
@@ -150,8 +169,8 @@ __global__ void __launch_bounds__(256) k_residual(MeshView mv, Params prm0, cons
                                                   const double* __restrict__ phi, const double* __restrict__ pt,
                                                   double* __restrict__ R, double* __restrict__ B) {
     constexpr int NV = 1 << D;
-    const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (f >= mv.n_free) return;
+    const int64_t f = pass_row<NV>(mv);
+    if (f < 0) return;
     const Params prm = row_params(mv, prm0, f);
     double ru[D];
 #pragma unroll
@@ -286,8 +305,8 @@ __global__ void __launch_bounds__(128) k_jacobian(MeshView mv, Params prm0, cons
                                                   double* __restrict__ F) {
     constexpr int NV = 1 << D;
     constexpr int DD = D * D;
-    const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (f >= mv.n_free) return;
+    const int64_t f = pass_row<NV>(mv);
+    if (f < 0) return;
     const Params prm = row_params(mv, prm0, f);
     const int64_t sl = f / mv.C;
     const int width = (mv.slice_ptr[sl + 1] - mv.slice_ptr[sl]) / mv.C;
@@ -878,6 +897,16 @@ std::unique_ptr<DevMesh> mesh_create(const fr_mesh_desc* d, int n_inst, hipStrea
         m->hang_ptr.upload(p.hang_ptr, s);
         m->hang_k.upload(p.hang_k, s);
     }
+    {
+        // rows with more entries than a cell has vertices (hanging-node masters)
+        std::vector<int32_t>& heavy = m->heavy_host;   // stays alive past the asynchronous upload
+        heavy.clear();
+        const int nv = 1 << h.dim;
+        for (int64_t f = 0; f < p.n_rows; ++f)
+            if (p.ent_ptr[size_t(f) + 1] - p.ent_ptr[size_t(f)] > nv) heavy.push_back(int32_t(f));
+        m->n_heavy = int64_t(heavy.size());
+        if (!heavy.empty()) m->heavy_rows.upload(heavy, s);
+    }
     FR_HIP(hipStreamSynchronize(s));   // host vectors of the pattern stay alive in m
     return m;
 }
@@ -912,8 +941,12 @@ void assemble_residual(DevSystem& sys, const double* u, const double* phi, const
     const hipStream_t s = sys.stream;
     const int nb = blocks_for(m.n_free, 256);
     if (m.hanging) nodal_fill(sys, u, phi, pt);
-    if (m.dim == 2) k_residual<2><<<nb, 256, 0, s>>>(mv, sys.prm, u, phi, pt, sys.R.p, sys.B.p);
-    else k_residual<3><<<nb, 256, 0, s>>>(mv, sys.prm, u, phi, pt, sys.R.p, sys.B.p);
+    for (int pass = 0; pass < (m.n_heavy > 0 ? 2 : 1); ++pass) {
+        mv.pass = pass;
+        const int g = pass == 0 ? nb : blocks_for(m.n_heavy, 256);
+        if (m.dim == 2) k_residual<2><<<g, 256, 0, s>>>(mv, sys.prm, u, phi, pt, sys.R.p, sys.B.p);
+        else k_residual<3><<<g, 256, 0, s>>>(mv, sys.prm, u, phi, pt, sys.R.p, sys.B.p);
+    }
     FR_LAUNCH_CHECK();
     sys.have_residual = true;
 }
@@ -951,22 +984,21 @@ void assemble_jacobian(DevSystem& sys, const double* u, const double* phi, const
     DevMesh& m = *sys.mesh;
     MeshView mv = view(sys);
     const hipStream_t s = sys.stream;
-    const int nb = blocks_for(m.n_free, 128);
     if (m.hanging) nodal_fill(sys, u, phi, pt);
-    if (m.dim == 2) {
-        if (m.hanging)
-            k_jacobian<2, true><<<nb, 128, 0, s>>>(mv, sys.prm, u, phi, phi_old, pt, sys.R.p, sys.active.p, sys.Juu.val,
-                                                   sys.Jpu.val, sys.Jpp.val, sys.F.p);
-        else
-            k_jacobian<2, false><<<nb, 128, 0, s>>>(mv, sys.prm, u, phi, phi_old, pt, sys.R.p, sys.active.p, sys.Juu.val,
-                                                    sys.Jpu.val, sys.Jpp.val, sys.F.p);
-    } else {
-        if (m.hanging)
-            k_jacobian<3, true><<<nb, 128, 0, s>>>(mv, sys.prm, u, phi, phi_old, pt, sys.R.p, sys.active.p, sys.Juu.val,
-                                                   sys.Jpu.val, sys.Jpp.val, sys.F.p);
-        else
-            k_jacobian<3, false><<<nb, 128, 0, s>>>(mv, sys.prm, u, phi, phi_old, pt, sys.R.p, sys.active.p, sys.Juu.val,
-                                                    sys.Jpu.val, sys.Jpp.val, sys.F.p);
+    for (int pass = 0; pass < (m.n_heavy > 0 ? 2 : 1); ++pass) {
+        mv.pass = pass;
+        const int nb = blocks_for(pass == 0 ? m.n_free : m.n_heavy, 128);
+#define FR_JAC(D_, H_)                                                                                  \
+    k_jacobian<D_, H_><<<nb, 128, 0, s>>>(mv, sys.prm, u, phi, phi_old, pt, sys.R.p, sys.active.p, sys.Juu.val, \
+                                          sys.Jpu.val, sys.Jpp.val, sys.F.p);
+        if (m.dim == 2) {
+            if (m.hanging) { FR_JAC(2, true) }
+            else { FR_JAC(2, false) }
+        } else {
+            if (m.hanging) { FR_JAC(3, true) }
+            else { FR_JAC(3, false) }
+        }
+#undef FR_JAC
     }
     FR_LAUNCH_CHECK();
     sys.have_jacobian = true;

@@ -65,6 +65,9 @@ struct DevMesh {
     DBuf<int32_t> ent_ptr, ent_cell;
     DBuf<uint8_t> ent_a, ent_k, hang_k;
     DBuf<int32_t> hang_ptr;
+    DBuf<int32_t> heavy_rows;                    // rows with more than 2^dim assembly entries
+    std::vector<int32_t> heavy_host;
+    int64_t n_heavy = 0;
     DBuf<double> ent_w;
 };
 
