@@ -20,7 +20,10 @@ dense LU for tiny meshes.  This is a different solver from the GPU's FGMRES + AM
 Newton loop (steps 1-6 with the stop rule "active set unchanged and residual < TOL"):
 line search omega in {1, 1/2, ..., 2^-8}, first omega with
 ||R~(U + omega dU)||_2 < ||R~(U)||_2 (else 2^-8); stop when A_k = A_{k-1} and
-||R~(U^k)||_2 <= tol ||R~(U^0)||_2, at most max_it iterations.  R~ is R with fixed rows
+||R~(U^k)||_2 <= max(tol ||R~(U^0)||_2, atol), at most max_it iterations.  The paper's
+rule compares R~ with an absolute TOL (atol); the relative part serves a step that starts
+far from equilibrium, the absolute part a step that starts at it (a later loading step at
+an unchanged load), whose R~(U^0) is already at rounding level.  R~ is R with fixed rows
 zeroed.  Cycle rule (the paper only says alternating indices are detected and
 constrained): a phi DoF whose membership flips twice within three consecutive iterates
 is frozen active for the rest of the loading step.
@@ -117,7 +120,7 @@ def newton_step_system(mesh, prm, u, phi, phi_old, phi_tilde):
 
 
 def newton_loop(mesh, prm, u0, phi0, phi_old, phi_tilde, tol=1e-8, max_it=30,
-                linear_solve=None, ls_max=8):
+                linear_solve=None, ls_max=8, atol=0.0):
     """Full Newton / active-set loop for one loading step (Section 3 algorithm)."""
     if linear_solve is None:
         linear_solve = lambda Jm, F: solve_block(mesh, Jm, F)
@@ -167,7 +170,7 @@ def newton_loop(mesh, prm, u0, phi0, phi_old, phi_tilde, tol=1e-8, max_it=30,
                         changed=int((new_active != active).sum())))
         same = np.array_equal(new_active, active)
         active = new_active
-        if same and rn <= tol * r0:
+        if same and rn <= max(tol * r0, atol):
             converged = True
             break
     return dict(u=u, phi=phi, U=U, active=active, iterations=it, converged=converged,
