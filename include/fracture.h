@@ -123,9 +123,12 @@ typedef struct {
 } fr_solve_stats;
 
 typedef struct {
-    double tol;          /* stop when the active set is unchanged and ||R~|| <= tol ||R~(U0)|| */
+    double tol;          /* stop when the active set is unchanged and ||R~|| <= max(tol ||R~(U0)||, atol) */
     int max_it;          /* Newton iteration cap */
     int ls_max;          /* line search tries omega = 1, 1/2, ..., 2^-ls_max */
+    double atol;         /* absolute floor of the stop test (>= 0; the algorithm of Section 3 states
+                            an absolute TOL): a loading step that starts at equilibrium has
+                            ||R~(U0)|| at rounding level, which the relative part cannot undercut */
 } fr_newton_opts;
 
 typedef struct {
@@ -297,6 +300,36 @@ fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double*
                           const fr_amg_opts* amg_opts, const fr_solve_opts* solve_opts,
                           const fr_newton_opts* newton_opts, fr_newton_stats* stats,
                           void* stream);
+
+/* ---- loading steps (Formulation 1, steps n = 1, 2, 3, ...) ------------------------ */
+
+/* phi_tilde = clip(phi1 + w (phi1 - phi2), 0, 1): the linear extrapolation in time of the
+ * phase field that convexifies Formulation 1 (Section 2), with phi1 = phi^{n-1}, phi2 =
+ * phi^{n-2} and w = (t_n - t_{n-1}) / (t_{n-1} - t_{n-2}); w = 0 copies phi1. Computed at the
+ * free nodes; a hanging node gets the interpolation of its masters' values (clipping and
+ * interpolation do not commute; the discrete field is fixed by its free values). The sum is
+ * product-then-add, without a fused multiply-add. phi1, phi2, phi_tilde: device [n_nodes];
+ * phi_tilde may alias neither input. Enqueued on `stream`; does not synchronise. */
+fr_status fracture_extrapolate(fr_mesh mesh, const double* phi1, const double* phi2, double w,
+                               double* phi_tilde, void* stream);
+
+/* Quasi-static loading steps n = 1 .. n_steps (Formulation 1 per step). Before step n:
+ * phi_old = phi^{n-1} (phi as it enters the step) and phi_tilde = fracture_extrapolate of
+ * (phi^{n-1}, phi^{n-2}) to t[n]; at the first step phi^{n-2} is phi_prev at t_prev when
+ * phi_prev is given, else phi_tilde = phi^0 (only one state is known). Then the Newton loop of
+ * fracture_newton with the parameters prm[(n-1) * n_inst + i] of instance i (the load
+ * schedule: p, and any other constant, may change per step), starting from the previous
+ * step's (u, phi). t: host [n_steps + 1], strictly increasing, t[0] the time of the state
+ * passed in. u, phi: device, updated in place (the state after the last step run). phi_prev:
+ * device [n_nodes] or NULL; t_prev < t[0]. stats: host [n_steps * n_inst] or NULL; tcv: host
+ * [n_steps * n_inst] or NULL, the TCV of every instance after every step (Section 4). The
+ * first step whose Newton loop fails ends the call with its status (its stats and tcv are
+ * written, later entries are not). Synchronises `stream`. */
+fr_status fracture_loading(fr_mesh mesh, const fr_params* prm, int n_steps, const double* t,
+                           double* u, double* phi, const double* phi_prev, double t_prev,
+                           const fr_amg_opts* amg_opts, const fr_solve_opts* solve_opts,
+                           const fr_newton_opts* newton_opts, fr_newton_stats* stats, double* tcv,
+                           void* stream);
 
 /* ---- functionals (Section 4) ------------------------------------------------------ */
 

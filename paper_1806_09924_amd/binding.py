@@ -49,7 +49,8 @@ class SolveStats(ctypes.Structure):
 
 
 class NewtonOpts(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_double), ("max_it", ctypes.c_int), ("ls_max", ctypes.c_int)]
+    _fields_ = [("tol", ctypes.c_double), ("max_it", ctypes.c_int), ("ls_max", ctypes.c_int),
+                ("atol", ctypes.c_double)]
 
 
 class NewtonStats(ctypes.Structure):
@@ -99,6 +100,10 @@ _SIGNATURES = {
     "fracture_update": [_P, _P, ctypes.c_double, _P, _P, _P],
     "fracture_newton": [_P, ctypes.POINTER(Params), _P, _P, _P, _P, ctypes.POINTER(AmgOpts),
                         ctypes.POINTER(SolveOpts), ctypes.POINTER(NewtonOpts), ctypes.POINTER(NewtonStats), _P],
+    "fracture_extrapolate": [_P, _P, _P, ctypes.c_double, _P, _P],
+    "fracture_loading": [_P, ctypes.POINTER(Params), ctypes.c_int, _DP, _P, _P, _P, ctypes.c_double,
+                         ctypes.POINTER(AmgOpts), ctypes.POINTER(SolveOpts), ctypes.POINTER(NewtonOpts),
+                         ctypes.POINTER(NewtonStats), _DP, _P],
     "fracture_functionals": [_P, _P, _P, _P, ctypes.c_int, _P, _P, _P],
     "fracture_profile": [ctypes.c_int],
     "fracture_profile_read": [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), _I64P, _DP, _DP],
@@ -167,8 +172,8 @@ def solve_opts(rtol=1e-8, restart=100, maxit=500, use_graphs=1):
     return SolveOpts(rtol, restart, maxit, use_graphs)
 
 
-def newton_opts(tol=1e-8, max_it=30, ls_max=8):
-    return NewtonOpts(tol, max_it, ls_max)
+def newton_opts(tol=1e-8, max_it=30, ls_max=8, atol=0.0):
+    return NewtonOpts(tol, max_it, ls_max, atol)
 
 
 def mesh_desc(dim, lo, hi, base, levels=0, refine_radius=0.0, crack_center=(0.0, 0.0, 0.0), crack_half_len=0.0):
@@ -398,6 +403,44 @@ def newton(mesh, prm, u, phi, phi_old, phi_tilde, amg=None, solve=None, newton=N
         raise FractureError(status, last_error())
     out = [{f: getattr(x, f) for f, _ in NewtonStats._fields_} for x in st]
     return out[0] if ni == 1 else out
+
+
+def extrapolate(mesh, phi1, phi2, w, out):
+    """out = clip(phi1 + w (phi1 - phi2), 0, 1) (device arrays of n_nodes)."""
+    _check(load().fracture_extrapolate(mesh.h, _ptr(phi1), _ptr(phi2), float(w), _ptr(out), _stream()))
+
+
+def loading(mesh, prm_steps, times, u, phi, phi_prev=None, t_prev=0.0, amg=None, solve=None, newton=None,
+            raise_on_noconv=True):
+    """Loading steps; prm_steps[n] is step n+1's Params (a list of one per instance on a batched
+    mesh), times[0] the time of (u, phi).  Returns (stats, tcv): stats[n] is a dict (a list of
+    them on a batched mesh), tcv an array [n_steps] ([n_steps, n_inst] batched)."""
+    ni = mesh.n_inst
+    ns = len(prm_steps)
+    flat = []
+    for p in prm_steps:
+        row = list(p) if isinstance(p, (list, tuple)) else [p]
+        if len(row) != ni:
+            raise ValueError(f"need {ni} parameter sets per step, got {len(row)}")
+        flat += row
+    t = np.ascontiguousarray(np.asarray(times, dtype=np.float64))
+    if t.shape != (ns + 1,):
+        raise ValueError(f"need {ns + 1} times, got {t.shape}")
+    arr = (Params * len(flat))(*flat)
+    st = (NewtonStats * len(flat))()
+    tcv = np.full(ns * ni, np.nan)
+    status = load().fracture_loading(mesh.h, arr, ns, t.ctypes.data_as(_DP), _ptr(u), _ptr(phi),
+                                     _ptr(phi_prev) if phi_prev is not None else None, float(t_prev),
+                                     ctypes.byref(amg if amg is not None else amg_opts()),
+                                     ctypes.byref(solve if solve is not None else solve_opts()),
+                                     ctypes.byref(newton if newton is not None else newton_opts()),
+                                     st, tcv.ctypes.data_as(_DP), _stream())
+    if status != FR_OK and (raise_on_noconv or status != FR_ENOCONV):
+        raise FractureError(status, last_error())
+    out = [{f: getattr(x, f) for f, _ in NewtonStats._fields_} for x in st]
+    if ni == 1:
+        return out, tcv
+    return [out[k * ni:(k + 1) * ni] for k in range(ns)], tcv.reshape(ns, ni)
 
 
 def functionals(mesh, u, phi, cod_x=()):

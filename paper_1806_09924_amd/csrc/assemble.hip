@@ -1056,6 +1056,47 @@ void mesh_update_inst(DevMesh& m, const double* du, const double* omega, double*
     }
 }
 
+// Linear extrapolation in time of the phase field (Formulation 1's phi_tilde):
+// clip(phi1 + w (phi1 - phi2), 0, 1) at every free node; a hanging node takes the
+// interpolation of its masters' extrapolated values, since the discrete field is fixed by its
+// free values and clipping does not commute with the interpolation.  No contraction into an
+// FMA, so the value is the plain product-then-sum.  A NaN input stays NaN.
+__device__ inline double extrap_clip(double a, double b, double w) {
+#pragma clang fp contract(off)
+    const double v = a + w * (a - b);
+    return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+}
+
+__global__ void __launch_bounds__(256) k_extrapolate(int64_t nn, const int32_t* __restrict__ free_of_node,
+                                                     const int32_t* __restrict__ node_of_free,
+                                                     const int32_t* __restrict__ con_ptr,
+                                                     const int32_t* __restrict__ con_master,
+                                                     const double* __restrict__ con_w,
+                                                     const double* __restrict__ p1, const double* __restrict__ p2,
+                                                     double w, double* __restrict__ out) {
+    const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    if (free_of_node == nullptr || free_of_node[n] >= 0) {
+        out[n] = extrap_clip(p1[n], p2[n], w);
+        return;
+    }
+    double v = 0.0;
+    for (int32_t j = con_ptr[n]; j < con_ptr[n + 1]; ++j) {
+        const int64_t src = node_of_free[con_master[j]];
+        v += con_w[j] * extrap_clip(p1[src], p2[src], w);
+    }
+    out[n] = v;
+}
+
+void extrapolate(DevMesh& m, const double* p1, const double* p2, double w, double* out, hipStream_t s) {
+    if (m.n_nodes == 0) return;
+    const bool h = m.hanging;
+    k_extrapolate<<<blocks_for(m.n_nodes, 256), 256, 0, s>>>(m.n_nodes, h ? m.free_of_node.p : nullptr,
+                                                             m.node_of_free.p, m.con_ptr.p, m.con_master.p,
+                                                             m.con_w.p, p1, p2, w, out);
+    FR_LAUNCH_CHECK();
+}
+
 void mesh_update(DevMesh& m, const double* du, double omega, double* u, double* phi, hipStream_t s) {
     k_update_free<<<blocks_for(m.n_free, 256), 256, 0, s>>>(m.n_free, m.dim, m.node_of_free.p, du, omega, u, phi);
     FR_LAUNCH_CHECK();

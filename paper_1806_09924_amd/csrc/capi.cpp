@@ -615,8 +615,8 @@ fr_status fracture_update(fr_mesh mesh, const double* du, double omega, double* 
 // Newton / active-set loop over a batch of independent instances (one disjoint-union system):
 // every iteration assembles, sets up and solves all instances together; the line search
 // halves each instance's step on its own (omega_i from its own residual norm), and an
-// instance whose active set is unchanged and whose residual is below tol x its initial one
-// is finished: its later updates get omega = 0.  Runs until every instance has finished.
+// instance whose active set is unchanged and whose residual is below max(tol x its initial
+// one, atol) is finished: its later updates get omega = 0.  Runs until every instance has finished.
 static fr_status newton_batch(NewtonWork& W, fr::DevMesh& m, const fr_params* prm, double* u, double* phi,
                               const double* phi_old, const double* phi_tilde, const fr_amg_opts& ao,
                               const fr_solve_opts& so, const fr_newton_opts& no, fr_newton_stats* stats,
@@ -711,7 +711,8 @@ static fr_status newton_batch(NewtonWork& W, fr::DevMesh& m, const fr_params* pr
             if (!done[size_t(i)]) {
                 q.iterations = it;
                 q.linear_iters += st[size_t(i)].iters;
-                if (chg[size_t(i)] == 0 && rk[size_t(i)] <= no.tol * r0[size_t(i)]) done[size_t(i)] = 1;
+                if (chg[size_t(i)] == 0 && rk[size_t(i)] <= std::max(no.tol * r0[size_t(i)], no.atol))
+                    done[size_t(i)] = 1;
             }
             q.res = rk[size_t(i)];
             q.n_active = n_act[size_t(i)];
@@ -737,6 +738,133 @@ static fr_status newton_batch(NewtonWork& W, fr::DevMesh& m, const fr_params* pr
     return worst;
 }
 
+// Options of a Newton loop with the library defaults for NULL pointers, validated.
+static fr_status newton_options(const fr_amg_opts* amg_opts, const fr_solve_opts* solve_opts,
+                                const fr_newton_opts* newton_opts, fr_amg_opts& ao, fr_solve_opts& so,
+                                fr_newton_opts& no) {
+    ao = amg_opts ? *amg_opts : default_amg();
+    if (check_amg(ao) != FR_OK) return FR_EINVAL;
+    so = fr_solve_opts{1e-8, 100, 500, 1};
+    if (solve_opts) so = *solve_opts;
+    if (check_solve(so) != FR_OK) return FR_EINVAL;
+    no = fr_newton_opts{1e-8, 30, 8, 0.0};
+    if (newton_opts) no = *newton_opts;
+    FR_REQUIRE(no.tol > 0 && no.atol >= 0 && std::isfinite(no.atol) && no.max_it >= 1 && no.ls_max >= 0 &&
+                   no.ls_max <= 60,
+               "newton: bad options");
+    return FR_OK;
+}
+
+// One Newton / active-set loop on a validated mesh and validated options (fracture_newton
+// and every step of fracture_loading).  Throws on HIP errors; the callers wrap it in guard().
+static fr_status newton_run(fr_mesh mesh, const fr_params* prm, double* u, double* phi, const double* phi_old,
+                            const double* phi_tilde, const fr_amg_opts& ao, const fr_solve_opts& so,
+                            const fr_newton_opts& no, fr_newton_stats* stats, hipStream_t s) {
+    fr::DevMesh& m = *mesh->m;
+    std::lock_guard<std::mutex> lk(mesh->newton_mu);
+    if (mesh->nw && mesh->nw->stream != s) {
+        // storage is freed on the stream it was allocated on
+        FR_HIP(hipStreamSynchronize(mesh->nw->stream));
+        mesh->nw.reset();
+    }
+    const bool fresh = !mesh->nw;
+    if (fresh) {
+        mesh->nw = std::make_unique<NewtonWork>();
+        mesh->nw->stream = s;
+    }
+    NewtonWork& W = *mesh->nw;
+    if (m.n_inst > 1) return newton_batch(W, m, prm, u, phi, phi_old, phi_tilde, ao, so, no, stats, s);
+    fr_newton_stats ns{};
+    fr_system_s* S = &W.S;
+    system_init(*S, m, s);
+    fr::DevSystem& sys = S->sys;
+    sys.prm = fr::make_params(*prm);
+    sys.prm_h = {sys.prm};
+    fr_amg_s* A = &W.A;
+    const int64_t nn = m.n_nodes;
+    fr::DBuf<double>& du = W.du;
+    fr::DBuf<double>& u_save = W.u_save;
+    fr::DBuf<double>& p_save = W.p_save;
+    if (du.p == nullptr) du.alloc(size_t(sys.n_solve), s);
+    if (u_save.p == nullptr) u_save.alloc(size_t(nn) * m.dim, s);
+    if (p_save.p == nullptr) p_save.alloc(size_t(nn), s);
+    double t_asm = 0, t_setup = 0, t_solve = 0, t_other = 0;
+    {
+        EventTimer t(s);
+        fr::assemble_residual(sys, u, phi, phi_tilde);
+        fr::assemble_active(sys, phi, phi_old);
+        t_asm += t.stop();
+    }
+    double nr[2];
+    fr::system_norms(sys, nullptr, nullptr, nr, nullptr, nullptr);
+    const double r0 = nr[0];
+    double rk = r0;
+    ns.res0 = r0;
+    int it = 0;
+    fr_status status = FR_ENOCONV;
+    while (it < no.max_it) {
+        {
+            EventTimer t(s);
+            fr::assemble_jacobian(sys, u, phi, phi_old, phi_tilde);
+            t_asm += t.stop();
+        }
+        {
+            EventTimer t(s);
+            fr_amg_opts ao_it = ao;
+            ao_it.reuse_u_block = (it > 0 && ao.reuse_u_block) ? 1 : 0;
+            // the first iteration of every call builds both hierarchies from scratch (the
+            // phase-field one keeps what a later refresh needs when refresh_phi is set)
+            if (it == 0) A->amg.h[1].refreshable = false;
+            fr::amg_build(A->amg, sys, ao_it, s);
+            t_setup += t.stop();
+        }
+        fr_solve_stats st{};
+        {
+            EventTimer t(s);
+            const fr_status r = fr::fgmres(sys, A->amg, so, du.p, &st, S->kry, s);
+            t_solve += t.stop();
+            ns.linear_iters += st.iters;
+            if (r == FR_ENAN) { status = FR_ENAN; break; }
+        }
+        EventTimer t(s);
+        // line search on ||R~|| with the current active set
+        FR_HIP(hipMemcpyAsync(u_save.p, u, size_t(nn) * m.dim * 8, hipMemcpyDeviceToDevice, s));
+        FR_HIP(hipMemcpyAsync(p_save.p, phi, size_t(nn) * 8, hipMemcpyDeviceToDevice, s));
+        for (int mm = 0; mm <= no.ls_max; ++mm) {
+            const double omega = std::ldexp(1.0, -mm);
+            if (mm > 0) {
+                FR_HIP(hipMemcpyAsync(u, u_save.p, size_t(nn) * m.dim * 8, hipMemcpyDeviceToDevice, s));
+                FR_HIP(hipMemcpyAsync(phi, p_save.p, size_t(nn) * 8, hipMemcpyDeviceToDevice, s));
+            }
+            fr::mesh_update(m, du.p, omega, u, phi, s);
+            fr::assemble_residual(sys, u, phi, phi_tilde);
+            fr::system_norms(sys, nullptr, nullptr, nr, nullptr, nullptr);
+            if (nr[0] < rk) break;
+        }
+        ++it;
+        if (it >= 2) fr::assemble_active_freeze(sys, phi, phi_old);
+        else fr::assemble_active(sys, phi, phi_old);
+        int64_t n_act = 0;
+        fr::system_norms(sys, nullptr, nullptr, nr, &n_act, nullptr);
+        rk = nr[0];
+        ns.n_active = n_act;
+        t_other += t.stop();
+        if (!std::isfinite(rk)) { status = FR_ENAN; break; }
+        if (sys.last_changes == 0 && rk <= std::max(no.tol * r0, no.atol)) { status = FR_OK; break; }
+    }
+    ns.iterations = it;
+    ns.res = rk;
+    ns.status = status;
+    ns.t_assemble = t_asm;
+    ns.t_setup = t_setup;
+    ns.t_solve = t_solve;
+    ns.t_other = t_other;
+    if (stats) *stats = ns;
+    FR_HIP(hipStreamSynchronize(s));
+    if (status == FR_ENOCONV) set_err(status, "newton: iteration limit reached");
+    return status;
+}
+
 fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double* phi, const double* phi_old,
                           const double* phi_tilde, const fr_amg_opts* amg_opts, const fr_solve_opts* solve_opts,
                           const fr_newton_opts* newton_opts, fr_newton_stats* stats, void* stream) {
@@ -748,119 +876,89 @@ fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double*
         fr_status ps = check_params(prm + i);
         if (ps != FR_OK) return ps;
     }
-    const fr_amg_opts ao = amg_opts ? *amg_opts : default_amg();
-    if (check_amg(ao) != FR_OK) return FR_EINVAL;
-    fr_solve_opts so{1e-8, 100, 500, 1};
-    if (solve_opts) so = *solve_opts;
-    if (check_solve(so) != FR_OK) return FR_EINVAL;
-    fr_newton_opts no{1e-8, 30, 8};
-    if (newton_opts) no = *newton_opts;
-    FR_REQUIRE(no.tol > 0 && no.max_it >= 1 && no.ls_max >= 0 && no.ls_max <= 60, "newton: bad options");
+    fr_amg_opts ao;
+    fr_solve_opts so;
+    fr_newton_opts no;
+    const fr_status os = newton_options(amg_opts, solve_opts, newton_opts, ao, so, no);
+    if (os != FR_OK) return os;
+    return guard([&]() {
+        return newton_run(mesh, prm, u, phi, phi_old, phi_tilde, ao, so, no, stats, fr::as_stream(stream));
+    });
+}
+
+fr_status fracture_extrapolate(fr_mesh mesh, const double* phi1, const double* phi2, double w, double* phi_tilde,
+                               void* stream) {
+    FR_REQUIRE(mesh != nullptr && mesh->m, "extrapolate: NULL mesh");
+    FR_REQUIRE(mesh->m->on_device, "extrapolate: host-only mesh");
+    FR_REQUIRE(phi1 && phi2 && phi_tilde, "extrapolate: NULL array");
+    FR_REQUIRE(std::isfinite(w), "extrapolate: w must be finite");
+    return guard([&]() {
+        fr::extrapolate(*mesh->m, phi1, phi2, w, phi_tilde, fr::as_stream(stream));
+        return FR_OK;
+    });
+}
+
+fr_status fracture_loading(fr_mesh mesh, const fr_params* prm, int n_steps, const double* t, double* u, double* phi,
+                           const double* phi_prev, double t_prev, const fr_amg_opts* amg_opts,
+                           const fr_solve_opts* solve_opts, const fr_newton_opts* newton_opts,
+                           fr_newton_stats* stats, double* tcv, void* stream) {
+    FR_REQUIRE(mesh != nullptr && mesh->m, "loading: NULL mesh");
+    FR_REQUIRE(mesh->m->on_device, "loading: host-only mesh");
+    FR_REQUIRE(u && phi, "loading: NULL state array");
+    FR_REQUIRE(prm != nullptr && t != nullptr, "loading: NULL params or times");
+    FR_REQUIRE(n_steps >= 1 && n_steps <= 100000, "loading: n_steps out of range");
+    const int ni = mesh->m->n_inst;
+    for (int k = 0; k < n_steps; ++k) {
+        FR_REQUIRE(std::isfinite(t[k]) && std::isfinite(t[k + 1]) && t[k + 1] > t[k],
+                   "loading: times must be finite and increasing");
+        for (int i = 0; i < ni; ++i) {
+            const fr_status ps = check_params(prm + size_t(k) * ni + i);
+            if (ps != FR_OK) return ps;
+        }
+    }
+    FR_REQUIRE(phi_prev == nullptr || (std::isfinite(t_prev) && t_prev < t[0]),
+               "loading: t_prev must be finite and before t[0]");
+    fr_amg_opts ao;
+    fr_solve_opts so;
+    fr_newton_opts no;
+    const fr_status os = newton_options(amg_opts, solve_opts, newton_opts, ao, so, no);
+    if (os != FR_OK) return os;
     return guard([&]() {
         hipStream_t s = fr::as_stream(stream);
         fr::DevMesh& m = *mesh->m;
-        std::lock_guard<std::mutex> lk(mesh->newton_mu);
-        if (mesh->nw && mesh->nw->stream != s) {
-            // storage is freed on the stream it was allocated on
-            FR_HIP(hipStreamSynchronize(mesh->nw->stream));
-            mesh->nw.reset();
+        const size_t nn = size_t(m.n_nodes);
+        // phi^{n-1} (phi_old of step n), phi^{n-2} and phi_tilde
+        fr::DBuf<double> cur, before, pt;
+        cur.alloc(nn, s);
+        pt.alloc(nn, s);
+        bool have_before = phi_prev != nullptr;
+        double t_before = t_prev;
+        if (have_before) {
+            before.alloc(nn, s);
+            FR_HIP(hipMemcpyAsync(before.p, phi_prev, nn * 8, hipMemcpyDeviceToDevice, s));
         }
-        const bool fresh = !mesh->nw;
-        if (fresh) {
-            mesh->nw = std::make_unique<NewtonWork>();
-            mesh->nw->stream = s;
+        fr_status worst = FR_OK;
+        for (int k = 0; k < n_steps; ++k) {
+            FR_HIP(hipMemcpyAsync(cur.p, phi, nn * 8, hipMemcpyDeviceToDevice, s));
+            const double w = have_before ? (t[k + 1] - t[k]) / (t[k] - t_before) : 0.0;
+            // w = 0 reproduces phi^{n-1} on the free nodes (and interpolates the hanging ones)
+            fr::extrapolate(m, cur.p, have_before ? before.p : cur.p, w, pt.p, s);
+            fr_newton_stats* st = stats ? stats + size_t(k) * ni : nullptr;
+            const fr_status r = newton_run(mesh, prm + size_t(k) * ni, u, phi, cur.p, pt.p, ao, so, no, st, s);
+            if (tcv) fr::mesh_functionals(m, u, phi, nullptr, 0, nullptr, tcv + size_t(k) * ni, s);
+            if (r != FR_OK) {
+                worst = r;
+                break;
+            }
+            if (!have_before) {
+                before.alloc(nn, s);
+                have_before = true;
+            }
+            std::swap(before, cur);
+            t_before = t[k];
         }
-        NewtonWork& W = *mesh->nw;
-        if (m.n_inst > 1) return newton_batch(W, m, prm, u, phi, phi_old, phi_tilde, ao, so, no, stats, s);
-        fr_newton_stats ns{};
-        fr_system_s* S = &W.S;
-        system_init(*S, m, s);
-        fr::DevSystem& sys = S->sys;
-        sys.prm = fr::make_params(*prm);
-        sys.prm_h = {sys.prm};
-        fr_amg_s* A = &W.A;
-        const int64_t nn = m.n_nodes;
-        fr::DBuf<double>& du = W.du;
-        fr::DBuf<double>& u_save = W.u_save;
-        fr::DBuf<double>& p_save = W.p_save;
-        if (du.p == nullptr) du.alloc(size_t(sys.n_solve), s);
-        if (u_save.p == nullptr) u_save.alloc(size_t(nn) * m.dim, s);
-        if (p_save.p == nullptr) p_save.alloc(size_t(nn), s);
-        double t_asm = 0, t_setup = 0, t_solve = 0, t_other = 0;
-        {
-            EventTimer t(s);
-            fr::assemble_residual(sys, u, phi, phi_tilde);
-            fr::assemble_active(sys, phi, phi_old);
-            t_asm += t.stop();
-        }
-        double nr[2];
-        fr::system_norms(sys, nullptr, nullptr, nr, nullptr, nullptr);
-        const double r0 = nr[0];
-        double rk = r0;
-        ns.res0 = r0;
-        int it = 0;
-        fr_status status = FR_ENOCONV;
-        while (it < no.max_it) {
-            {
-                EventTimer t(s);
-                fr::assemble_jacobian(sys, u, phi, phi_old, phi_tilde);
-                t_asm += t.stop();
-            }
-            {
-                EventTimer t(s);
-                fr_amg_opts ao_it = ao;
-                ao_it.reuse_u_block = (it > 0 && ao.reuse_u_block) ? 1 : 0;
-                // the first iteration of every call builds both hierarchies from scratch (the
-                // phase-field one keeps what a later refresh needs when refresh_phi is set)
-                if (it == 0) A->amg.h[1].refreshable = false;
-                fr::amg_build(A->amg, sys, ao_it, s);
-                t_setup += t.stop();
-            }
-            fr_solve_stats st{};
-            {
-                EventTimer t(s);
-                const fr_status r = fr::fgmres(sys, A->amg, so, du.p, &st, S->kry, s);
-                t_solve += t.stop();
-                ns.linear_iters += st.iters;
-                if (r == FR_ENAN) { status = FR_ENAN; break; }
-            }
-            EventTimer t(s);
-            // line search on ||R~|| with the current active set
-            FR_HIP(hipMemcpyAsync(u_save.p, u, size_t(nn) * m.dim * 8, hipMemcpyDeviceToDevice, s));
-            FR_HIP(hipMemcpyAsync(p_save.p, phi, size_t(nn) * 8, hipMemcpyDeviceToDevice, s));
-            for (int mm = 0; mm <= no.ls_max; ++mm) {
-                const double omega = std::ldexp(1.0, -mm);
-                if (mm > 0) {
-                    FR_HIP(hipMemcpyAsync(u, u_save.p, size_t(nn) * m.dim * 8, hipMemcpyDeviceToDevice, s));
-                    FR_HIP(hipMemcpyAsync(phi, p_save.p, size_t(nn) * 8, hipMemcpyDeviceToDevice, s));
-                }
-                fr::mesh_update(m, du.p, omega, u, phi, s);
-                fr::assemble_residual(sys, u, phi, phi_tilde);
-                fr::system_norms(sys, nullptr, nullptr, nr, nullptr, nullptr);
-                if (nr[0] < rk) break;
-            }
-            ++it;
-            if (it >= 2) fr::assemble_active_freeze(sys, phi, phi_old);
-            else fr::assemble_active(sys, phi, phi_old);
-            int64_t n_act = 0;
-            fr::system_norms(sys, nullptr, nullptr, nr, &n_act, nullptr);
-            rk = nr[0];
-            ns.n_active = n_act;
-            t_other += t.stop();
-            if (!std::isfinite(rk)) { status = FR_ENAN; break; }
-            if (sys.last_changes == 0 && rk <= no.tol * r0) { status = FR_OK; break; }
-        }
-        ns.iterations = it;
-        ns.res = rk;
-        ns.status = status;
-        ns.t_assemble = t_asm;
-        ns.t_setup = t_setup;
-        ns.t_solve = t_solve;
-        ns.t_other = t_other;
-        if (stats) *stats = ns;
         FR_HIP(hipStreamSynchronize(s));
-        if (status == FR_ENOCONV) set_err(status, "newton: iteration limit reached");
-        return status;
+        return worst;
     });
 }
 

@@ -104,6 +104,8 @@ void system_norms(DevSystem& sys, const double* phi, const double* phi_old, doub
                   int64_t* n_active, double* min_margin);
 void system_matvec(DevSystem& sys, const double* x, double* y);
 void mesh_update(DevMesh& m, const double* du, double omega, double* u, double* phi, hipStream_t s);
+// out = clip(p1 + w (p1 - p2), 0, 1) on the free nodes, hanging nodes interpolated from them.
+void extrapolate(DevMesh& m, const double* p1, const double* p2, double w, double* out, hipStream_t s);
 // Batches: per-instance ||R~||, active phi rows and active-flag changes of the last update.
 void system_norms_inst(DevSystem& sys, std::vector<double>& rnorm, std::vector<int64_t>& n_active,
                        std::vector<int64_t>& changes);

@@ -55,6 +55,11 @@ def test_argument_validation_before_device(lib):
     assert lib.fracture_functionals(None, None, None, None, 0, None, None, None) == B.FR_EINVAL
     assert lib.amg_level_shape(None, 0, 0, 0, None, None) == B.FR_EINVAL
     assert lib.fracture_tune_clear() == B.FR_OK
+    assert lib.fracture_extrapolate(None, None, None, ctypes.c_double(1.0), None, None) == B.FR_EINVAL
+    st = (B.NewtonStats * 1)()
+    t = (ctypes.c_double * 2)(0.0, 1.0)
+    assert lib.fracture_loading(None, ctypes.byref(p), 1, t, None, None, None, ctypes.c_double(0.0), None, None,
+                                None, st, None, None) == B.FR_EINVAL
 
 
 def test_host_only_mesh_is_rejected_by_device_calls(lib):
@@ -62,6 +67,14 @@ def test_host_only_mesh_is_rejected_by_device_calls(lib):
     p = B.params()
     sysh = ctypes.c_void_p()
     assert lib.fracture_assemble(m.h, ctypes.byref(p), None, None, None, None, 1, ctypes.byref(sysh), None) == B.FR_EINVAL
+    assert "host-only" in B.last_error()
+    t = (ctypes.c_double * 3)(0.0, 1.0, 1.0)
+    st = (B.NewtonStats * 2)()
+    prm2 = (B.Params * 2)(p, p)
+    assert lib.fracture_loading(m.h, prm2, 2, t, None, None, None, ctypes.c_double(0.0), None, None, None, st,
+                                None, None) == B.FR_EINVAL
+    assert "host-only" in B.last_error()
+    assert lib.fracture_extrapolate(m.h, None, None, ctypes.c_double(1.0), None, None) == B.FR_EINVAL
     assert "host-only" in B.last_error()
 
 
