@@ -5,6 +5,7 @@ solver or functional arithmetic of the method.  Both the oracle and the HIP path
 the arrays produced here, so that no floating-point tie in an input recipe can make the
 two sides see different problems.
 """
-from .sneddon import (Workload, WORKLOADS, crack_band_phi, random_state, batched_instances, domain_study)
+from .sneddon import (Workload, WORKLOADS, crack_band_phi, random_state, batched_instances, domain_study,
+                      cod_study)
 
-__all__ = ["Workload", "WORKLOADS", "crack_band_phi", "random_state", "batched_instances", "domain_study"]
+__all__ = ["Workload", "WORKLOADS", "crack_band_phi", "random_state", "batched_instances", "domain_study", "cod_study"]

@@ -131,3 +131,12 @@ def domain_study(half_widths=DOMAIN_STUDY_HALF_WIDTHS, levels=DOMAIN_STUDY_LEVEL
                                 description=f"2d Sneddon l0=1 in [-{L:g},{L:g}]^2, base h=1, {k} levels "
                                             f"within {refine_radius:g} of the crack, eps=2h_min"))
     return out
+
+
+# COD convergence study (Section 4.4): one domain, l0 = 1, base cells of edge 1, adaptive levels
+# within COD_STUDY_RADIUS of the crack against global meshes of the same h_min.
+COD_STUDY = dict(half_width=5.0, levels=(3, 4, 5, 6, 7), refine_radius=2.0)
+
+
+def cod_study():
+    return dict(COD_STUDY)

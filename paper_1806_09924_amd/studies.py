@@ -6,7 +6,12 @@ crack with l0 = 1.  For every domain the TCV is computed at several mesh levels 
 and extrapolated in h; the paper reports the extrapolated value's error against the exact
 6.0319E-03 as 5.6 %, 1.5 %, 0.5 % and 0.1 % for the domains 10x10 ... 80x80.
 
-Run as `python -m paper_1806_09924_amd.studies` (prints one JSON object).
+cod_convergence(): Section 4.4, the crack opening displacement on one domain under adaptive
+and under global refinement (eps = 2 h_min on every mesh), each family's reference value by
+Richardson extrapolation of its own three finest levels, and the observed orders of the errors
+against h and against the number of DoFs.
+
+Run as `python -m paper_1806_09924_amd.studies [domain|cod] [64|32]` (prints one JSON object).
 """
 import json
 import sys
@@ -69,11 +74,94 @@ def domain_size(workloads, precision=64, rtol=1e-8, exact=None):
                 n_dofs=int(3 * mesh.n_nodes), t_mesh=t_mesh, t_newton=t_newton, precision=precision)
 
 
+def richardson(values):
+    """Reference value and observed order from the last three entries of a sequence computed
+    on meshes whose h halves from one entry to the next: with C_h = C* + a h^q,
+    q = log2((C_2h - C_4h) / (C_h - C_2h)) and C* = C_h + (C_h - C_2h) / (2^q - 1)."""
+    c4, c2, c1 = (float(v) for v in values[-3:])
+    d_coarse, d_fine = c2 - c4, c1 - c2
+    if d_fine == 0.0 or d_coarse / d_fine <= 0.0:
+        raise ValueError("richardson: the last three values do not converge monotonically")
+    q = float(np.log2(d_coarse / d_fine))
+    return c1 + d_fine / (2.0 ** q - 1.0), q
+
+
+def _solve_family(descs, l0, xs, precision, rtol):
+    """One batched Newton loop over meshes of one family; COD at xs and DoFs per mesh."""
+    from inputs import crack_band_phi   # the workloads' initial crack field
+    mesh = B.Mesh(descs)
+    xyz = mesh.nodes()[0]
+    ni = len(descs)
+    inst = [mesh.instance(i) for i in range(ni)]
+    phi0 = np.zeros(mesh.n_nodes)
+    prms = []
+    for i, nd in enumerate(inst):
+        eps = 2.0 * nd["h_min"]
+        sl = slice(nd["node_offset"], nd["node_offset"] + nd["n_nodes"])
+        phi0[sl] = crack_band_phi(xyz[sl], l0, eps)
+        prms.append(B.params(eps=eps, kappa=1e-10, p=1e-3))
+    dev = torch.device("cuda")
+    p0 = torch.as_tensor(phi0, device=dev)
+    u = torch.zeros((mesh.n_nodes, 2), dtype=torch.float64, device=dev)
+    phi = p0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = B.newton(mesh, prms, u, phi, p0, p0, amg=B.amg_opts(precision=precision), solve=B.solve_opts(rtol=rtol))
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    cx = np.array([[[x] for x in xs]] * ni)
+    cod, _ = B.functionals(mesh, u, phi, cx)
+    for i in range(ni):
+        assert st[i]["status"] == 0, (i, st[i])
+    return dict(h=[nd["h_min"] for nd in inst], n_dofs=[3 * nd["n_nodes"] for nd in inst],
+                cod=np.asarray(cod).reshape(ni, len(xs)).T.tolist(), newton=[s["iterations"] for s in st],
+                t_newton=t)
+
+
+def _orders(h, n, err):
+    e = np.asarray(err, dtype=float)
+    return dict(vs_h=np.log2(e[:-1] / e[1:]).tolist(),
+                vs_dofs=(np.log(e[:-1] / e[1:]) / np.log(np.asarray(n[1:], float) / np.asarray(n[:-1], float))).tolist())
+
+
+def cod_convergence(half_width, levels, refine_radius, l0=1.0, xs=(0.0, 0.5), precision=64, rtol=1e-10):
+    """COD at the points xs along the crack (x_0 = xs, through the crack) under adaptive
+    refinement (base cells of edge 1, `levels` within refine_radius of the crack) and global
+    refinement of the same h_min, each with its Richardson reference from its three finest
+    levels (the global family stops one level short of the adaptive one: the finest global
+    mesh is the largest).  Returns the values, references, errors and observed orders."""
+    L = float(half_width)
+    n0 = int(round(2 * L))
+    ad = _solve_family([B.mesh_desc(2, -L, L, n0, levels=k, refine_radius=refine_radius, crack_half_len=l0)
+                        for k in levels], l0, xs, precision, rtol)
+    gl = _solve_family([B.mesh_desc(2, -L, L, n0 << k) for k in levels[:-1]], l0, xs, precision, rtol)
+    out = dict(domain=2 * L, l0=l0, xs=list(xs), refine_radius=refine_radius, adaptive=ad, global_=gl)
+    for fam in (ad, gl):
+        fam["reference"], fam["order_richardson"], fam["errors"], fam["orders"] = [], [], [], []
+        for k in range(len(xs)):
+            ref, q = richardson(fam["cod"][k])
+            err = [abs(c - ref) for c in fam["cod"][k]]
+            fam["reference"].append(ref)
+            fam["order_richardson"].append(q)
+            fam["errors"].append(err)
+            fam["orders"].append(_orders(fam["h"][:-1], fam["n_dofs"][:-1], err[:-1]))
+    return out
+
+
 def main(argv=None):
+    argv = list(argv or [])
+    which = argv.pop(0) if argv and argv[0] in ("domain", "cod") else "domain"
+    precision = int(argv[0]) if argv else 64
+    if which == "cod":
+        from inputs import cod_study
+        c = cod_study()
+        out = cod_convergence(c["half_width"], c["levels"], c["refine_radius"], precision=precision)
+        print(json.dumps(out))
+        return
     from inputs import domain_study
     ws = domain_study()
     exact = 2 * np.pi * 1e-3 * 1.0 ** 2 * (1 - 0.2 ** 2) / 1.0
-    out = domain_size(ws, precision=int(argv[0]) if argv else 64, exact=exact)
+    out = domain_size(ws, precision=precision, exact=exact)
     out["exact"] = exact
     print(json.dumps(out))
 
