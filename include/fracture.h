@@ -194,6 +194,31 @@ fr_status fracture_mesh_instance(fr_mesh mesh, int inst, int64_t* node_offset, i
                                  int64_t* free_offset, int64_t* n_free, int64_t* cell_offset,
                                  int64_t* n_cells, double* h_min);
 
+/* Refinement between loading steps: the mesh obtained from `mesh` (one instance) by splitting
+ * every cell c with flags[c] != 0 into 2^dim children, then splitting further until cells that
+ * share a point differ by at most one level (2:1 balance, as for fracture_mesh_create). The
+ * result has one more level than `mesh` when a cell of its finest level is flagged. It records
+ * where each of its nodes lies in `mesh`, for fracture_transfer. flags: host [n_cells] (e.g.
+ * from fracture_mark_crack). The new mesh is on the device when `mesh` is; it is independent
+ * of `mesh` except that fracture_transfer from `mesh` needs `mesh` alive. Synchronises. */
+fr_status fracture_mesh_refine(fr_mesh mesh, const uint8_t* flags, fr_mesh* out, void* stream);
+
+/* Interpolates nodal fields of `from` at the nodes of `to`, a mesh made from `from` by
+ * fracture_mesh_refine: dst[n][c] = value at node n of the Q1 function of `from` whose nodal
+ * values are src[.][c] (hanging vertices of `from` taken from their constraints). The spaces are
+ * nested, so the function is reproduced exactly (the solution transfer between loading steps).
+ * src: device [n_nodes(from)][ncomp], dst: device [n_nodes(to)][ncomp], 1 <= ncomp <= 16, no
+ * aliasing. Enqueued on `stream`. */
+fr_status fracture_transfer(fr_mesh from, fr_mesh to, const double* src, int ncomp, double* dst,
+                            void* stream);
+
+/* Crack-region marks (the refinement that keeps eps = 2h in the crack region, Section 3):
+ * flags[c] = 1 when cell c's edge exceeds h_target and phi is below phi_max at one of its
+ * vertices (hanging vertices from their constraints), else 0. phi: device [n_nodes]; flags:
+ * host [n_cells]; n_marked: host, optional. Synchronises `stream`. */
+fr_status fracture_mark_crack(fr_mesh mesh, const double* phi, double phi_max, double h_target,
+                              uint8_t* flags, int64_t* n_marked, void* stream);
+
 void fracture_mesh_destroy(fr_mesh mesh);
 
 /* ---- assembly --------------------------------------------------------------------- */

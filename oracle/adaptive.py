@@ -55,6 +55,12 @@ def adaptive(dim, lo, hi, n, levels, radius, center, half_len):
                 stack.append((lev + 1, tuple(o[k] + ch[k] * s // 2 for k in range(dim))))
         else:
             leaves.add((lev, o))
+    return mesh_from_leaves(dim, lo, hi, h_min, S, ext, balance(dim, S, ext, leaves))
+
+
+def balance(dim, S, ext, leaves):
+    """Splits leaves {(level, origin)} until cells sharing a point differ by at most one level."""
+    leaves = set(leaves)
 
     def leaf_at(point, max_level):
         for lev in range(max_level + 1):
@@ -88,7 +94,11 @@ def adaptive(dim, lo, hi, n, levels, radius, center, half_len):
                 for ch in itertools.product((0, 1), repeat=dim):
                     leaves.add((lev + 1, tuple(o[k] + ch[k] * s // 2 for k in range(dim))))
                 changed = True
+    return leaves
 
+
+def mesh_from_leaves(dim, lo, hi, h_min, S, ext, leaves):
+    """Nodes, cells, hanging constraints and Dirichlet flags of a balanced leaf set."""
     cells_l = sorted(leaves, key=lambda t: (tuple(reversed(t[1])), t[0]))
     nv = 1 << dim
     bits = np.array([[(a >> k) & 1 for k in range(dim)] for a in range(nv)])
@@ -165,4 +175,7 @@ def adaptive(dim, lo, hi, n, levels, radius, center, half_len):
                 rows.append(nd); cols.append(free_of[m]); vals.append(w)
     C = sp.csr_matrix((vals, (rows, cols)), shape=(n_nodes, len(free)))
     dirichlet = np.any((lattice == 0) | (lattice == ext), axis=1)
-    return Mesh(dim, coords, lattice, cells, cell_lo, cell_h, dirichlet, C, free, lo, hi)
+    m = Mesh(dim, coords, lattice, cells, cell_lo, cell_h, dirichlet, C, free, lo, hi)
+    m.S = S
+    m.leaves = cells_l
+    return m

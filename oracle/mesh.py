@@ -91,4 +91,7 @@ def uniform(dim, lo, hi, n):
     n_nodes = coords.shape[0]
     C = sp.identity(n_nodes, format="csr")
     free = np.arange(n_nodes)
-    return Mesh(dim, coords, lattice, cells, cell_lo, cell_h, dirichlet, C, free, lo, hi)
+    m = Mesh(dim, coords, lattice, cells, cell_lo, cell_h, dirichlet, C, free, lo, hi)
+    m.S = 1                                   # lattice units per base cell (no refinement)
+    m.leaves = [(0, tuple(int(v) for v in o)) for o in clat]
+    return m

@@ -101,6 +101,9 @@ _SIGNATURES = {
     "fracture_newton": [_P, ctypes.POINTER(Params), _P, _P, _P, _P, ctypes.POINTER(AmgOpts),
                         ctypes.POINTER(SolveOpts), ctypes.POINTER(NewtonOpts), ctypes.POINTER(NewtonStats), _P],
     "fracture_extrapolate": [_P, _P, _P, ctypes.c_double, _P, _P],
+    "fracture_mesh_refine": [_P, _P, ctypes.POINTER(_P), _P],
+    "fracture_transfer": [_P, _P, _P, ctypes.c_int, _P, _P],
+    "fracture_mark_crack": [_P, _P, ctypes.c_double, ctypes.c_double, _P, _I64P, _P],
     "fracture_loading": [_P, ctypes.POINTER(Params), ctypes.c_int, _DP, _P, _P, _P, ctypes.c_double,
                          ctypes.POINTER(AmgOpts), ctypes.POINTER(SolveOpts), ctypes.POINTER(NewtonOpts),
                          ctypes.POINTER(NewtonStats), _DP, _P],
@@ -193,11 +196,14 @@ def mesh_desc(dim, lo, hi, base, levels=0, refine_radius=0.0, crack_center=(0.0,
 class Mesh:
     """A mesh, or a batch of independent meshes when `desc` is a list of descriptors."""
 
-    def __init__(self, desc, host_only=False):
+    def __init__(self, desc, host_only=False, _handle=None):
         lib = load()
         h = _P()
         self.n_inst = 1
-        if isinstance(desc, (list, tuple)):
+        self.host_only = host_only
+        if _handle is not None:
+            h = _handle
+        elif isinstance(desc, (list, tuple)):
             arr = (MeshDesc * len(desc))(*desc)
             self.n_inst = len(desc)
             _check(lib.fracture_mesh_create_batch(arr, len(desc), ctypes.byref(h), _stream()))
@@ -255,10 +261,39 @@ class Mesh:
                                              w.ctypes.data_as(_P)))
         return ptr, mas, w
 
+    def refine(self, flags):
+        """The mesh with the flagged cells split (2:1 balanced); keeps this mesh alive for
+        transfers from it."""
+        f = np.ascontiguousarray(np.asarray(flags, dtype=np.uint8))
+        if f.shape != (self.n_cells,):
+            raise ValueError(f"need {self.n_cells} flags, got {f.shape}")
+        h = _P()
+        _check(load().fracture_mesh_refine(self.h, f.ctypes.data_as(_P), ctypes.byref(h),
+                                           None if self.host_only else _stream()))
+        out = Mesh(self.desc, host_only=self.host_only, _handle=h)
+        out.parent = self
+        return out
+
     def __del__(self):
         if getattr(self, "h", None) is not None and _lib is not None:
             _lib.fracture_mesh_destroy(self.h)
             self.h = None
+
+
+def transfer(src_mesh, dst_mesh, src, dst):
+    """Interpolates nodal fields (torch [n_nodes] or [n_nodes, ncomp]) of src_mesh onto the
+    nodes of dst_mesh, a refinement of it."""
+    ncomp = 1 if src.dim() == 1 else src.shape[1]
+    _check(load().fracture_transfer(src_mesh.h, dst_mesh.h, _ptr(src), ncomp, _ptr(dst), _stream()))
+
+
+def mark_crack(mesh, phi, phi_max, h_target):
+    """Crack-region marks: (flags uint8 [n_cells], count)."""
+    flags = np.zeros(mesh.n_cells, dtype=np.uint8)
+    n = ctypes.c_int64()
+    _check(load().fracture_mark_crack(mesh.h, _ptr(phi), float(phi_max), float(h_target), flags.ctypes.data_as(_P),
+                                      ctypes.byref(n), _stream()))
+    return flags, n.value
 
 
 class System:

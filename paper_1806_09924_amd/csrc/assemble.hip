@@ -831,8 +831,13 @@ __global__ void k_sum_rows(const double* __restrict__ part, int64_t n_part, int 
 // ---- host side --------------------------------------------------------------------------
 
 std::unique_ptr<DevMesh> mesh_create(const fr_mesh_desc* d, int n_inst, hipStream_t s, bool upload) {
+    return mesh_from_host(build_mesh_batch(d, n_inst), s, upload);
+}
+
+std::unique_ptr<DevMesh> mesh_from_host(HostMesh&& host, hipStream_t s, bool upload) {
     auto m = std::make_unique<DevMesh>();
-    m->host = build_mesh_batch(d, n_inst);
+    const int n_inst = host.n_inst;
+    m->host = std::move(host);
     m->n_inst = n_inst;
     m->pat = build_pattern(m->host, 64);
     const HostMesh& h = m->host;
@@ -1094,6 +1099,103 @@ void extrapolate(DevMesh& m, const double* p1, const double* p2, double w, doubl
     k_extrapolate<<<blocks_for(m.n_nodes, 256), 256, 0, s>>>(m.n_nodes, h ? m.free_of_node.p : nullptr,
                                                              m.node_of_free.p, m.con_ptr.p, m.con_master.p,
                                                              m.con_w.p, p1, p2, w, out);
+    FR_LAUNCH_CHECK();
+}
+
+// Nodal value of `src` at vertex n of the source mesh: the node's own value, or for a
+// hanging node the weighted values of its free masters.
+__device__ __forceinline__ double src_value(int32_t n, int c, int ncomp, const int32_t* __restrict__ con_ptr,
+                                            const int32_t* __restrict__ con_master,
+                                            const double* __restrict__ con_w,
+                                            const int32_t* __restrict__ node_of_free,
+                                            const double* __restrict__ src) {
+    if (con_ptr == nullptr) return src[int64_t(n) * ncomp + c];
+    double v = 0.0;
+    for (int32_t j = con_ptr[n]; j < con_ptr[n + 1]; ++j)
+        v += con_w[j] * src[int64_t(node_of_free[con_master[j]]) * ncomp + c];
+    return v;
+}
+
+// One thread per node of the refined mesh: the Q1 interpolant of the source cell that holds
+// the node, at the node's local coordinates (exact for a refinement: the spaces are nested).
+template <int D>
+__global__ void __launch_bounds__(256) k_transfer(int64_t nn, int ncomp, const int32_t* __restrict__ loc_cell,
+                                                  const double* __restrict__ loc_xi,
+                                                  const int32_t* __restrict__ cells,
+                                                  const int32_t* __restrict__ con_ptr,
+                                                  const int32_t* __restrict__ con_master,
+                                                  const double* __restrict__ con_w,
+                                                  const int32_t* __restrict__ node_of_free,
+                                                  const double* __restrict__ src, double* __restrict__ dst) {
+    constexpr int NV = 1 << D;
+    const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const int64_t cell = loc_cell[n];
+    double xi[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) xi[k] = loc_xi[n * D + k];
+    for (int c = 0; c < ncomp; ++c) {
+        double v = 0.0;
+#pragma unroll
+        for (int a = 0; a < NV; ++a) {
+            double w = 1.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) w *= ((a >> k) & 1) ? xi[k] : 1.0 - xi[k];
+            v += w * src_value(cells[cell * NV + a], c, ncomp, con_ptr, con_master, con_w, node_of_free, src);
+        }
+        dst[n * ncomp + c] = v;
+    }
+}
+
+void mesh_transfer(const DevMesh& from, const DevMesh& to, const double* src, int ncomp, double* dst,
+                   hipStream_t s) {
+    if (to.n_nodes == 0) return;
+    const bool h = from.hanging;
+    const int nb = blocks_for(to.n_nodes, 256);
+#define FR_TRANSFER(D_)                                                                                    \
+    k_transfer<D_><<<nb, 256, 0, s>>>(to.n_nodes, ncomp, to.parent_cell.p, to.parent_xi.p, from.cells.p,  \
+                                      h ? from.con_ptr.p : nullptr, from.con_master.p, from.con_w.p,      \
+                                      from.node_of_free.p, src, dst)
+    if (from.dim == 2) FR_TRANSFER(2);
+    else FR_TRANSFER(3);
+#undef FR_TRANSFER
+    FR_LAUNCH_CHECK();
+}
+
+// One thread per cell: the crack-region mark.
+template <int D>
+__global__ void __launch_bounds__(256) k_mark_crack(int64_t nc, const int32_t* __restrict__ cells,
+                                                    const double* __restrict__ cell_h,
+                                                    const int32_t* __restrict__ con_ptr,
+                                                    const int32_t* __restrict__ con_master,
+                                                    const double* __restrict__ con_w,
+                                                    const int32_t* __restrict__ node_of_free,
+                                                    const double* __restrict__ phi, double phi_max,
+                                                    double h_target, uint8_t* __restrict__ flags) {
+    constexpr int NV = 1 << D;
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    uint8_t f = 0;
+    if (cell_h[c] > h_target) {
+#pragma unroll
+        for (int a = 0; a < NV; ++a)
+            if (src_value(cells[c * NV + a], 0, 1, con_ptr, con_master, con_w, node_of_free, phi) < phi_max) f = 1;
+    }
+    flags[c] = f;
+}
+
+void mesh_mark_crack(const DevMesh& m, const double* phi, double phi_max, double h_target, uint8_t* flags_dev,
+                     hipStream_t s) {
+    if (m.n_cells == 0) return;
+    const bool h = m.hanging;
+    const int nb = blocks_for(m.n_cells, 256);
+#define FR_MARK(D_)                                                                                        \
+    k_mark_crack<D_><<<nb, 256, 0, s>>>(m.n_cells, m.cells.p, m.cell_h.p, h ? m.con_ptr.p : nullptr,       \
+                                        m.con_master.p, m.con_w.p, m.node_of_free.p, phi, phi_max,         \
+                                        h_target, flags_dev)
+    if (m.dim == 2) FR_MARK(2);
+    else FR_MARK(3);
+#undef FR_MARK
     FR_LAUNCH_CHECK();
 }
 

@@ -255,6 +255,69 @@ fr_status fracture_mesh_create_batch(const fr_mesh_desc* desc, int n_inst, fr_me
     });
 }
 
+fr_status fracture_mesh_refine(fr_mesh mesh, const uint8_t* flags, fr_mesh* out, void* stream) {
+    FR_REQUIRE(mesh != nullptr && mesh->m && flags != nullptr && out != nullptr, "mesh_refine: NULL argument");
+    FR_REQUIRE(mesh->m->n_inst == 1, "mesh_refine: batched meshes are not supported");
+    return guard([&]() {
+        const fr::DevMesh& old = *mesh->m;
+        if (old.on_device) {
+            const fr_status st = check_device();
+            if (st != FR_OK) return st;
+        }
+        hipStream_t s = fr::as_stream(stream);
+        std::vector<int32_t> loc_cell;
+        std::vector<double> loc_xi;
+        fr::HostMesh hm = fr::refine_mesh(old.host, flags, loc_cell, loc_xi);
+        auto h = std::make_unique<fr_mesh_s>();
+        h->m = fr::mesh_from_host(std::move(hm), s, old.on_device);
+        h->m->parent = &old;
+        h->m->parent_nodes = old.n_nodes;
+        if (old.on_device) {
+            h->m->parent_cell.upload(loc_cell, s);
+            h->m->parent_xi.upload(loc_xi, s);
+            FR_HIP(hipStreamSynchronize(s));        // the host tables above go out of scope
+        }
+        *out = h.release();
+        return FR_OK;
+    });
+}
+
+fr_status fracture_transfer(fr_mesh from, fr_mesh to, const double* src, int ncomp, double* dst, void* stream) {
+    FR_REQUIRE(from != nullptr && from->m && to != nullptr && to->m, "transfer: NULL mesh");
+    FR_REQUIRE(from->m->on_device && to->m->on_device, "transfer: host-only mesh");
+    FR_REQUIRE(to->m->parent == from->m.get() && to->m->parent_nodes == from->m->n_nodes,
+               "transfer: `to` was not made from `from` by fracture_mesh_refine");
+    FR_REQUIRE(src != nullptr && dst != nullptr && src != dst, "transfer: NULL or aliased arrays");
+    FR_REQUIRE(ncomp >= 1 && ncomp <= 16, "transfer: ncomp must be in [1, 16]");
+    return guard([&]() {
+        fr::mesh_transfer(*from->m, *to->m, src, ncomp, dst, fr::as_stream(stream));
+        return FR_OK;
+    });
+}
+
+fr_status fracture_mark_crack(fr_mesh mesh, const double* phi, double phi_max, double h_target, uint8_t* flags,
+                              int64_t* n_marked, void* stream) {
+    FR_REQUIRE(mesh != nullptr && mesh->m, "mark_crack: NULL mesh");
+    FR_REQUIRE(mesh->m->on_device, "mark_crack: host-only mesh");
+    FR_REQUIRE(phi != nullptr && flags != nullptr, "mark_crack: NULL array");
+    FR_REQUIRE(std::isfinite(phi_max) && std::isfinite(h_target) && h_target > 0, "mark_crack: bad thresholds");
+    return guard([&]() {
+        hipStream_t s = fr::as_stream(stream);
+        const fr::DevMesh& m = *mesh->m;
+        fr::DBuf<uint8_t> fd;
+        fd.alloc(size_t(m.n_cells), s);
+        fr::mesh_mark_crack(m, phi, phi_max, h_target, fd.p, s);
+        FR_HIP(hipMemcpyAsync(flags, fd.p, size_t(m.n_cells), hipMemcpyDeviceToHost, s));
+        FR_HIP(hipStreamSynchronize(s));
+        if (n_marked) {
+            int64_t k = 0;
+            for (int64_t c = 0; c < m.n_cells; ++c) k += flags[c] ? 1 : 0;
+            *n_marked = k;
+        }
+        return FR_OK;
+    });
+}
+
 fr_status fracture_mesh_instance(fr_mesh mesh, int inst, int64_t* node_offset, int64_t* n_nodes,
                                  int64_t* free_offset, int64_t* n_free, int64_t* cell_offset, int64_t* n_cells,
                                  double* h_min) {

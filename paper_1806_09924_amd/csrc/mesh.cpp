@@ -166,14 +166,18 @@ static void validate(const fr_mesh_desc& d) {
     if (d.levels > 0 && !(d.refine_radius >= 0)) fail(FR_EINVAL, "mesh: refine_radius must be >= 0");
 }
 
-HostMesh build_mesh(const fr_mesh_desc& d) {
+HostMesh build_mesh(const fr_mesh_desc& d, const RefineSeed* seed) {
     validate(d);
     HostMesh m;
     const int dim = d.dim;
     m.dim = dim;
     m.nv = 1 << dim;
     for (int k = 0; k < 3; ++k) { m.lo[k] = d.lo[k]; m.hi[k] = d.hi[k]; }
-    const int L = d.levels;
+    const int L = seed ? seed->L : d.levels;
+    if (L < 0 || L > 12) fail(FR_EINVAL, "mesh: levels must be in [0, 12]");
+    m.desc = d;
+    m.desc.levels = L;
+    m.levels = L;
     const int64_t S = int64_t(1) << L;                 // lattice units per base cell
     const double h_base = (d.hi[0] - d.lo[0]) / d.base[0];
     m.h_min = h_base / double(S);
@@ -201,9 +205,14 @@ HostMesh build_mesh(const fr_mesh_desc& d) {
         int64_t n0 = d.base[0], n1 = d.base[1], n2 = dim == 3 ? d.base[2] : 1;
         struct Item { int level; int64_t o[3]; };
         std::vector<Item> work;
-        for (int64_t k = 0; k < n2; ++k)
-            for (int64_t j = 0; j < n1; ++j)
-                for (int64_t i = 0; i < n0; ++i) work.push_back(Item{0, {i * S, j * S, k * S}});
+        if (seed) {
+            for (int l = 0; l < L && size_t(l) < seed->split.size(); ++l)
+                for (uint64_t k : seed->split[size_t(l)]) refined[size_t(l)].insert(k);
+        } else {
+            for (int64_t k = 0; k < n2; ++k)
+                for (int64_t j = 0; j < n1; ++j)
+                    for (int64_t i = 0; i < n0; ++i) work.push_back(Item{0, {i * S, j * S, k * S}});
+        }
         while (!work.empty()) {
             Item c = work.back();
             work.pop_back();
@@ -483,6 +492,92 @@ HostMesh build_mesh(const fr_mesh_desc& d) {
         }
         m.dirichlet[size_t(n)] = b ? 1 : 0;
     }
+    return m;
+}
+
+HostMesh refine_mesh(const HostMesh& old, const uint8_t* flags, std::vector<int32_t>& loc_cell,
+                     std::vector<double>& loc_xi) {
+    if (old.n_inst != 1) fail(FR_EINVAL, "mesh_refine: batched meshes are not supported");
+    const int dim = old.dim, nv = old.nv;
+    const int L0 = old.levels;
+    const int64_t nc = old.n_cells;
+    // level of every old cell from its edge in lattice units (vertex nv-1 minus vertex 0)
+    std::vector<int8_t> lev(static_cast<size_t>(nc));
+    bool grow = false;
+    for (int64_t c = 0; c < nc; ++c) {
+        const int64_t a = old.cells[size_t(c) * nv], b = old.cells[size_t(c) * nv + nv - 1];
+        const int64_t s = old.lattice[size_t(b) * dim] - old.lattice[size_t(a) * dim];
+        int l = L0;
+        for (int64_t t = s; t > 1; t >>= 1) --l;
+        if (l < 0 || (int64_t(1) << (L0 - l)) != s) fail(FR_EINTERNAL, "mesh_refine: cell edge is not a power of two");
+        lev[size_t(c)] = int8_t(l);
+        if (flags[c] && l == L0) grow = true;
+    }
+    const int L1 = L0 + (grow ? 1 : 0);
+    if (L1 > 12) fail(FR_EINVAL, "mesh_refine: more than 12 levels");
+    const int64_t f = grow ? 2 : 1;
+    const int64_t S1 = int64_t(1) << L1;
+    int64_t ext1[3] = {1, 1, 1};
+    for (int k = 0; k < dim; ++k) ext1[k] = int64_t(old.desc.base[k]) * S1;
+    for (int k = 0; k < dim; ++k)
+        if (ext1[k] >= (int64_t(1) << 21)) fail(FR_EINVAL, "mesh_refine: more than 2^21 finest cells per axis");
+    // split: every ancestor of an old leaf (the old tree) and every flagged leaf
+    std::vector<KeySet> split(static_cast<size_t>(std::max(L1, 1)));
+    for (int64_t c = 0; c < nc; ++c) {
+        const int l = lev[size_t(c)];
+        int64_t o[3] = {0, 0, 0};
+        const int64_t a = old.cells[size_t(c) * nv];
+        for (int k = 0; k < dim; ++k) o[k] = old.lattice[size_t(a) * dim + k] * f;
+        if (flags[c]) split[size_t(l)].insert(pack(o));
+        for (int j = l - 1; j >= 0; --j) {
+            const int64_t sz = S1 >> j;
+            int64_t po[3] = {0, 0, 0};
+            for (int k = 0; k < dim; ++k) po[k] = (o[k] / sz) * sz;
+            if (!split[size_t(j)].insert(pack(po))) break;
+        }
+    }
+    RefineSeed seed;
+    seed.L = L1;
+    seed.split.resize(size_t(L1));
+    for (int l = 0; l < L1; ++l) {
+        seed.split[size_t(l)].reserve(split[size_t(l)].size());
+        split[size_t(l)].for_each([&](uint64_t k) { seed.split[size_t(l)].push_back(k); });
+    }
+    HostMesh m = build_mesh(old.desc, &seed);
+    if (m.levels != L1) fail(FR_EINTERNAL, "mesh_refine: level count");
+    // locate every new node in an old cell: the old leaf of the finest level that contains it
+    std::vector<std::vector<std::pair<uint64_t, int32_t>>> byl(static_cast<size_t>(L0) + 1);
+    for (int64_t c = 0; c < nc; ++c) {
+        int64_t o[3] = {0, 0, 0};
+        const int64_t a = old.cells[size_t(c) * nv];
+        for (int k = 0; k < dim; ++k) o[k] = old.lattice[size_t(a) * dim + k] * f;
+        byl[size_t(lev[size_t(c)])].push_back({pack(o), int32_t(c)});
+    }
+    for (auto& v : byl) std::sort(v.begin(), v.end());
+    loc_cell.assign(size_t(m.n_nodes), -1);
+    loc_xi.assign(size_t(m.n_nodes) * dim, 0.0);
+    parallel_ranges(m.n_nodes, [&](int64_t b, int64_t e, int) {
+        for (int64_t n = b; n < e; ++n) {
+            const int64_t* q = &m.lattice[size_t(n) * dim];
+            for (int l = L0; l >= 0; --l) {
+                const int64_t sz = S1 >> l;
+                int64_t o[3] = {0, 0, 0};
+                for (int k = 0; k < dim; ++k) o[k] = std::min((q[k] / sz) * sz, ext1[k] - sz);
+                const auto& v = byl[size_t(l)];
+                auto it = std::lower_bound(v.begin(), v.end(), std::make_pair(pack(o), int32_t(-1)));
+                if (it == v.end() || it->first != pack(o)) continue;
+                loc_cell[size_t(n)] = it->second;
+                for (int k = 0; k < dim; ++k) loc_xi[size_t(n) * dim + k] = double(q[k] - o[k]) / double(sz);
+                break;
+            }
+        }
+    });
+    for (int64_t n = 0; n < m.n_nodes; ++n)
+        if (loc_cell[size_t(n)] < 0) fail(FR_EINTERNAL, "mesh_refine: a node of the refined mesh lies in no old cell");
+    m.node_off = {0, m.n_nodes};
+    m.cell_off = {0, m.n_cells};
+    m.free_off = {0, m.n_free};
+    m.inst_h_min = {m.h_min};
     return m;
 }
 

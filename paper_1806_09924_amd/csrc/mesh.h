@@ -2,6 +2,7 @@
 // node-centric assembly tables.
 #pragma once
 #include <cstdint>
+#include <array>
 #include <vector>
 
 #include "../../include/fracture.h"
@@ -29,6 +30,10 @@ struct HostMesh {
     int n_inst = 1;
     std::vector<int64_t> node_off, cell_off, free_off;   // [n_inst+1]
     std::vector<double> inst_h_min;                        // [n_inst]
+    // The descriptor this mesh was built from (one instance) and its number of levels (the
+    // lattice unit is the base cell edge / 2^levels); a refined mesh records its own.
+    fr_mesh_desc desc{};
+    int levels = 0;
 };
 
 // Node-graph pattern in SELL-C layout plus the tables of the node-centric assembly.
@@ -52,7 +57,21 @@ struct Pattern {
     std::vector<uint8_t> hang_k;      // [hang_ptr[n_rows]]
 };
 
-HostMesh build_mesh(const fr_mesh_desc& d);
+// Cells to split on top of a descriptor's base grid: every cell of level l whose lattice
+// origin is listed in split[l] is split (origins in units of the finest cell of a mesh with L
+// levels); the 2:1 closure then runs as for the descriptor's own rule, which the seed replaces.
+struct RefineSeed {
+    int L = 0;
+    std::vector<std::vector<uint64_t>> split;   // [L] packed origins (21 bits per axis) of split cells
+};
+
+HostMesh build_mesh(const fr_mesh_desc& d, const RefineSeed* seed = nullptr);
+
+// The mesh obtained from `old` (one instance) by splitting every cell c with flags[c] != 0,
+// then the 2:1 closure.  loc_cell[n] / loc_xi[n*dim + k]: a cell of `old` that contains node n
+// of the result and the node's local coordinates in it (in [0, 1]).
+HostMesh refine_mesh(const HostMesh& old, const uint8_t* flags, std::vector<int32_t>& loc_cell,
+                     std::vector<double>& loc_xi);
 // Disjoint union of n independent meshes of the same dimension.
 HostMesh build_mesh_batch(const fr_mesh_desc* d, int n);
 Pattern build_pattern(const HostMesh& m, int C);

@@ -69,9 +69,23 @@ struct DevMesh {
     std::vector<int32_t> heavy_host;
     int64_t n_heavy = 0;
     DBuf<double> ent_w;
+    // A mesh made by refine_mesh: where its nodes lie in the mesh it was made from.
+    const DevMesh* parent = nullptr;             // identity only (checked by transfers)
+    int64_t parent_nodes = 0;
+    DBuf<int32_t> parent_cell;                   // [n_nodes]
+    DBuf<double> parent_xi;                      // [n_nodes][dim]
 };
 
 std::unique_ptr<DevMesh> mesh_create(const fr_mesh_desc* d, int n_inst, hipStream_t s, bool upload);
+std::unique_ptr<DevMesh> mesh_from_host(HostMesh&& host, hipStream_t s, bool upload);
+// Nodal fields of `from` interpolated at the nodes of `to` (made from `from` by refine_mesh):
+// dst[n][c] = sum_a N_a(xi_n) src[vertex a of cell_n][c], hanging vertices of `from` taken from
+// their constraints.
+void mesh_transfer(const DevMesh& from, const DevMesh& to, const double* src, int ncomp, double* dst, hipStream_t s);
+// Crack-region marks: flag[c] = 1 when the cell's edge exceeds h_target and phi (hanging
+// vertices from their constraints) is below phi_max at one of its vertices.
+void mesh_mark_crack(const DevMesh& m, const double* phi, double phi_max, double h_target, uint8_t* flags_dev,
+                     hipStream_t s);
 
 // ---- assembled system -------------------------------------------------------------------
 struct DevSystem {

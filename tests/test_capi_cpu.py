@@ -167,6 +167,10 @@ def test_library_adaptive_mesh_matches_oracle(dim, n, levels, radius, half):
     m = B.Mesh(B.mesh_desc(dim, lo, hi, n, levels=levels, refine_radius=radius, crack_center=(0.0, 0.0, 0.0),
                            crack_half_len=half), host_only=True)
     om = adaptive.adaptive(dim, lo, hi, n, levels, radius, (0.0, 0.0, 0.0), half)
+    _same_mesh(m, om)
+
+
+def _same_mesh(m, om):
     xyz, lat, dirichlet, free = m.nodes()
     assert m.n_nodes == om.n_nodes and m.n_cells == om.n_cells and m.n_free == om.n_free
     key = lambda L: [tuple(r) for r in L]
@@ -186,3 +190,28 @@ def test_library_adaptive_mesh_matches_oracle(dim, n, levels, radius, half):
         row = Co.getrow(perm[nd])
         orc = sorted((tuple(om.lattice[om.free[c]]), v) for c, v in zip(row.indices, row.data))
         assert lib == orc
+
+
+@pytest.mark.parametrize("dim,n,levels,radius,half,frac", [(2, 4, 2, 0.3, 0.25, 0.2), (2, 6, 0, 0.0, 0.0, 0.3),
+                                                            (3, 2, 2, 0.1, 0.3, 0.15), (2, 8, 3, 0.3, 0.5, 0.05)])
+def test_library_refinement_matches_oracle(dim, n, levels, radius, half, frac):
+    """fracture_mesh_refine (the library's seeded builder and closure) against the oracle's
+    split-and-balance of the same marks, twice in a row; a finest cell is always marked, so the
+    level count grows."""
+    from oracle import adaptive, mesh as omesh, refine
+    lo, hi = -2.0, 2.0
+    m = B.Mesh(B.mesh_desc(dim, lo, hi, n, levels=levels, refine_radius=radius, crack_center=(0.0, 0.0, 0.0),
+                           crack_half_len=half), host_only=True)
+    om = (adaptive.adaptive(dim, lo, hi, n, levels, radius, (0.0, 0.0, 0.0), half) if levels > 0
+          else omesh.uniform(dim, lo, hi, n))
+    rng = np.random.default_rng(40 + dim + levels)
+    for _ in range(2):
+        _, clo, ch = m.cells()
+        assert np.allclose(clo, om.cell_lo, atol=1e-12) and np.allclose(ch, om.cell_h, atol=1e-12)
+        flags = (rng.random(m.n_cells) < frac).astype(np.uint8)
+        flags[np.argmin(ch)] = 1
+        m2 = m.refine(flags)
+        om2 = refine.refine(om, flags)
+        assert m2.h_min == pytest.approx(m.h_min / 2, rel=1e-15)
+        _same_mesh(m2, om2)
+        m, om = m2, om2
