@@ -310,7 +310,9 @@ fr_status fracture_update(fr_mesh mesh, const double* du, double omega, double* 
 
 /* The Newton / active-set loop of one loading step (Section 3 algorithm): assemble,
  * active set, masked Jacobian, AMG setup, FGMRES, line search, stop test, with the cycle
- * freeze of alternating active-set entries. u and phi are updated in place (device).
+ * freeze of alternating active-set entries. The line search scales the update of the DoFs that
+ * are not fixed; the fixed ones take their constraint values (Dirichlet u 0, active phi
+ * phi_old), so that the loop never stops with an active DoF off phi_old. u and phi are updated in place (device).
  * amg_opts / solve_opts / newton_opts / stats: host. prm and stats hold one entry per
  * instance: on a batched mesh all instances iterate together (one assembly, setup and solve
  * per iteration), each with its own line search and stop test; a finished instance takes no

@@ -18,8 +18,11 @@ each solved by sparse LU (scipy SuperLU as a library step), or the whole masked 
 dense LU for tiny meshes.  This is a different solver from the GPU's FGMRES + AMG.
 
 Newton loop (steps 1-6 with the stop rule "active set unchanged and residual < TOL"):
-line search omega in {1, 1/2, ..., 2^-8}, first omega with
-||R~(U + omega dU)||_2 < ||R~(U)||_2 (else 2^-8); stop when A_k = A_{k-1} and
+line search omega in {1, 1/2, ..., 2^-8} on the DoFs that are not fixed, first omega with
+||R~(U + omega dU)||_2 < ||R~(U)||_2 (else 2^-8); the fixed DoFs take their constraint values
+at every trial (0 for Dirichlet u, phi_old for active phi: the elimination of step 4 fixes
+them, and a damped step would leave an active DoF off phi_old while R~, which omits its row,
+reports convergence); stop when A_k = A_{k-1} and
 ||R~(U^k)||_2 <= max(tol ||R~(U^0)||_2, atol), at most max_it iterations.  The paper's
 rule compares R~ with an absolute TOL (atol); the relative part serves a step that starts
 far from equilibrium, the absolute part a step that starts at it (a later loading step at
@@ -64,6 +67,16 @@ def fixed_dofs(mesh, active, u, phi, phi_old):
     fixed[d * nf:] = active
     target[d * nf:] = np.where(active, phi_old[mesh.free] - phi[mesh.free], 0.0)
     return fixed, target
+
+
+def fixed_values(mesh, active, phi_old):
+    """Values the fixed solve-order DoFs take after an update: 0 for Dirichlet u DoFs and
+    phi_old for active phi DoFs (the elimination of step 4 fixes them there)."""
+    d = mesh.dim
+    nf = mesh.n_free
+    val = np.zeros((d + 1) * nf)
+    val[d * nf:] = np.where(active, phi_old[mesh.free], 0.0)
+    return val
 
 
 def mask_system(J, R, fixed, target):
@@ -146,15 +159,16 @@ def newton_loop(mesh, prm, u0, phi0, phi_old, phi_tilde, tol=1e-8, max_it=30,
         dU = linear_solve(Jm, F)
         rk = masked_residual_norm(R, fixed)
         omega = 2.0 ** -ls_max
+        fval = fixed_values(mesh, active, phi_old)
         for m in range(ls_max + 1):
             w = 2.0 ** -m
-            Ut = U + w * dU
+            Ut = np.where(fixed, fval, U + w * dU)
             ut, pt = fem.expand(mesh, Ut)
             Rt, _ = fem.residual(mesh, prm, ut, pt, phi_tilde)
             if masked_residual_norm(Rt, fixed) < rk:
                 omega = w
                 break
-        U = U + omega * dU
+        U = np.where(fixed, fval, U + omega * dU)
         u, phi = fem.expand(mesh, U)
         it += 1
         R, B = fem.residual(mesh, prm, u, phi, phi_tilde)

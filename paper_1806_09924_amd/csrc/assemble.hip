@@ -654,26 +654,39 @@ __global__ void __launch_bounds__(256) k_inst_norms(int D, int64_t nf, const int
 }
 
 // u += omega_i du, phi += omega_i dphi at the free nodes of instance i
-__global__ void k_update_free_inst(int64_t nf, int D, const int32_t* __restrict__ node_of_free,
-                                   const int32_t* __restrict__ inst_of_free, const double* __restrict__ du,
-                                   const double* __restrict__ omega, double* __restrict__ u, double* __restrict__ phi) {
-    const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (f >= nf) return;
-    const double w = omega[inst_of_free[f]];
-    const int64_t n = node_of_free[f];
-    for (int c = 0; c < D; ++c) u[n * D + c] += w * du[f * D + c];
-    phi[n] += w * du[D * nf + f];
+// ---- update -----------------------------------------------------------------------------
+// u += w du, phi += w du on free node f; with `fix` (the Newton loop) the DoFs that the
+// elimination fixes take their constraint values instead: Dirichlet u DoFs 0, active phi DoFs
+// phi_old, so that a damped step cannot leave an active DoF off phi_old.
+struct FixedDofs {
+    const uint8_t* dir;        // per free node, nullptr: no projection
+    const uint8_t* active;     // per free node
+    const double* phi_old;     // per node
+};
+
+__device__ __forceinline__ void update_node(int64_t f, int64_t nf, int D, int64_t n, const double* __restrict__ du,
+                                            double w, const FixedDofs& fix, double* __restrict__ u,
+                                            double* __restrict__ phi) {
+    const bool ud = fix.dir && fix.dir[f];
+    for (int c = 0; c < D; ++c) u[n * D + c] = ud ? 0.0 : u[n * D + c] + w * du[f * D + c];
+    phi[n] = (fix.dir && fix.active[f]) ? fix.phi_old[n] : phi[n] + w * du[D * nf + f];
 }
 
-// ---- update -----------------------------------------------------------------------------
+__global__ void k_update_free_inst(int64_t nf, int D, const int32_t* __restrict__ node_of_free,
+                                   const int32_t* __restrict__ inst_of_free, const double* __restrict__ du,
+                                   const double* __restrict__ omega, FixedDofs fix, double* __restrict__ u,
+                                   double* __restrict__ phi) {
+    const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    update_node(f, nf, D, node_of_free[f], du, omega[inst_of_free[f]], fix, u, phi);
+}
+
 __global__ void k_update_free(int64_t nf, int D, const int32_t* __restrict__ node_of_free,
-                              const double* __restrict__ du, double omega, double* __restrict__ u,
+                              const double* __restrict__ du, double omega, FixedDofs fix, double* __restrict__ u,
                               double* __restrict__ phi) {
     const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (f >= nf) return;
-    const int64_t n = node_of_free[f];
-    for (int c = 0; c < D; ++c) u[n * D + c] += omega * du[f * D + c];
-    phi[n] += omega * du[D * nf + f];
+    update_node(f, nf, D, node_of_free[f], du, omega, fix, u, phi);
 }
 
 __global__ void k_fill_hanging(int64_t nn, int D, const int32_t* __restrict__ free_of_node,
@@ -1050,9 +1063,11 @@ void system_norms_inst(DevSystem& sys, std::vector<double>& rnorm, std::vector<i
     }
 }
 
-void mesh_update_inst(DevMesh& m, const double* du, const double* omega, double* u, double* phi, hipStream_t s) {
+void mesh_update_inst(DevMesh& m, const double* du, const double* omega, double* u, double* phi, hipStream_t s,
+                      const uint8_t* active, const double* phi_old) {
+    const FixedDofs fix{active ? m.dir_free.p : nullptr, active, phi_old};
     k_update_free_inst<<<blocks_for(m.n_free, 256), 256, 0, s>>>(m.n_free, m.dim, m.node_of_free.p, m.inst_of_free.p,
-                                                                 du, omega, u, phi);
+                                                                 du, omega, fix, u, phi);
     FR_LAUNCH_CHECK();
     if (m.hanging) {
         k_fill_hanging<<<blocks_for(m.n_nodes, 256), 256, 0, s>>>(m.n_nodes, m.dim, m.free_of_node.p, m.node_of_free.p,
@@ -1199,8 +1214,11 @@ void mesh_mark_crack(const DevMesh& m, const double* phi, double phi_max, double
     FR_LAUNCH_CHECK();
 }
 
-void mesh_update(DevMesh& m, const double* du, double omega, double* u, double* phi, hipStream_t s) {
-    k_update_free<<<blocks_for(m.n_free, 256), 256, 0, s>>>(m.n_free, m.dim, m.node_of_free.p, du, omega, u, phi);
+void mesh_update(DevMesh& m, const double* du, double omega, double* u, double* phi, hipStream_t s,
+                 const uint8_t* active, const double* phi_old) {
+    const FixedDofs fix{active ? m.dir_free.p : nullptr, active, phi_old};
+    k_update_free<<<blocks_for(m.n_free, 256), 256, 0, s>>>(m.n_free, m.dim, m.node_of_free.p, du, omega, fix, u,
+                                                            phi);
     FR_LAUNCH_CHECK();
     if (m.hanging) {
         k_fill_hanging<<<blocks_for(m.n_nodes, 256), 256, 0, s>>>(m.n_nodes, m.dim, m.free_of_node.p, m.node_of_free.p,

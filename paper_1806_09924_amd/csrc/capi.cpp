@@ -752,7 +752,7 @@ static fr_status newton_batch(NewtonWork& W, fr::DevMesh& m, const fr_params* pr
                 FR_HIP(hipMemcpyAsync(phi, W.p_save.p, size_t(nn) * 8, hipMemcpyDeviceToDevice, s));
             }
             om_d.upload(om, s);
-            fr::mesh_update_inst(m, W.du.p, om_d.p, u, phi, s);
+            fr::mesh_update_inst(m, W.du.p, om_d.p, u, phi, s, sys.active.p, phi_old);
             fr::assemble_residual(sys, u, phi, phi_tilde);
             fr::system_norms_inst(sys, nr, n_act, chg);
             bool all = true;
@@ -890,7 +890,8 @@ static fr_status newton_run(fr_mesh mesh, const fr_params* prm, double* u, doubl
             if (r == FR_ENAN) { status = FR_ENAN; break; }
         }
         EventTimer t(s);
-        // line search on ||R~|| with the current active set
+        // line search on ||R~|| with the current active set; the fixed DoFs take their
+        // constraint values at every trial (Dirichlet u 0, active phi phi_old)
         FR_HIP(hipMemcpyAsync(u_save.p, u, size_t(nn) * m.dim * 8, hipMemcpyDeviceToDevice, s));
         FR_HIP(hipMemcpyAsync(p_save.p, phi, size_t(nn) * 8, hipMemcpyDeviceToDevice, s));
         for (int mm = 0; mm <= no.ls_max; ++mm) {
@@ -899,7 +900,7 @@ static fr_status newton_run(fr_mesh mesh, const fr_params* prm, double* u, doubl
                 FR_HIP(hipMemcpyAsync(u, u_save.p, size_t(nn) * m.dim * 8, hipMemcpyDeviceToDevice, s));
                 FR_HIP(hipMemcpyAsync(phi, p_save.p, size_t(nn) * 8, hipMemcpyDeviceToDevice, s));
             }
-            fr::mesh_update(m, du.p, omega, u, phi, s);
+            fr::mesh_update(m, du.p, omega, u, phi, s, sys.active.p, phi_old);
             fr::assemble_residual(sys, u, phi, phi_tilde);
             fr::system_norms(sys, nullptr, nullptr, nr, nullptr, nullptr);
             if (nr[0] < rk) break;

@@ -117,14 +117,19 @@ void assemble_jacobian(DevSystem& sys, const double* u, const double* phi, const
 void system_norms(DevSystem& sys, const double* phi, const double* phi_old, double* norms,
                   int64_t* n_active, double* min_margin);
 void system_matvec(DevSystem& sys, const double* x, double* y);
-void mesh_update(DevMesh& m, const double* du, double omega, double* u, double* phi, hipStream_t s);
+// u += omega du, phi += omega du on the free nodes (hanging nodes refilled).  With `active`
+// (per free node) the fixed DoFs take their constraint values instead: Dirichlet u 0, active
+// phi phi_old.
+void mesh_update(DevMesh& m, const double* du, double omega, double* u, double* phi, hipStream_t s,
+                 const uint8_t* active = nullptr, const double* phi_old = nullptr);
 // out = clip(p1 + w (p1 - p2), 0, 1) on the free nodes, hanging nodes interpolated from them.
 void extrapolate(DevMesh& m, const double* p1, const double* p2, double w, double* out, hipStream_t s);
 // Batches: per-instance ||R~||, active phi rows and active-flag changes of the last update.
 void system_norms_inst(DevSystem& sys, std::vector<double>& rnorm, std::vector<int64_t>& n_active,
                        std::vector<int64_t>& changes);
 // Batches: u += omega[i] du on instance i (omega: device, one per instance).
-void mesh_update_inst(DevMesh& m, const double* du, const double* omega, double* u, double* phi, hipStream_t s);
+void mesh_update_inst(DevMesh& m, const double* du, const double* omega, double* u, double* phi, hipStream_t s,
+                      const uint8_t* active = nullptr, const double* phi_old = nullptr);
 void mesh_functionals(DevMesh& m, const double* u, const double* phi, const double* cod_x, int n_cod,
                       double* cod, double* tcv, hipStream_t s);
 
