@@ -212,6 +212,15 @@ fr_status fracture_mesh_refine(fr_mesh mesh, const uint8_t* flags, fr_mesh* out,
 fr_status fracture_transfer(fr_mesh from, fr_mesh to, const double* src, int ncomp, double* dst,
                             void* stream);
 
+/* Gradient-jump indicator of the displacement (the estimator Section 3 adds to the crack-region
+ * refinement): eta2[c] = h_c / 24 * sum over the faces F of cell c of the integral over F of
+ * |jump of du/dn|^2 (all components; h_c the cell edge), integrated exactly by 2-point Gauss per
+ * face axis on the smaller of the two faces at a level change; boundary faces contribute
+ * nothing. u: device [n_nodes][dim] (hanging values from their constraints); eta2: device
+ * [n_cells] (one instance or a batch). The face-neighbour table is built on the first call and
+ * kept with the mesh. Enqueued on `stream` (the first call synchronises it). */
+fr_status fracture_kelly(fr_mesh mesh, const double* u, double* eta2, void* stream);
+
 /* Crack-region marks (the refinement that keeps eps = 2h in the crack region, Section 3):
  * flags[c] = 1 when cell c's edge exceeds h_target and phi is below phi_max at one of its
  * vertices (hanging vertices from their constraints), else 0. phi: device [n_nodes]; flags:

@@ -104,6 +104,7 @@ _SIGNATURES = {
     "fracture_mesh_refine": [_P, _P, ctypes.POINTER(_P), _P],
     "fracture_transfer": [_P, _P, _P, ctypes.c_int, _P, _P],
     "fracture_mark_crack": [_P, _P, ctypes.c_double, ctypes.c_double, _P, _I64P, _P],
+    "fracture_kelly": [_P, _P, _P, _P],
     "fracture_loading": [_P, ctypes.POINTER(Params), ctypes.c_int, _DP, _P, _P, _P, ctypes.c_double,
                          ctypes.POINTER(AmgOpts), ctypes.POINTER(SolveOpts), ctypes.POINTER(NewtonOpts),
                          ctypes.POINTER(NewtonStats), _DP, _P],
@@ -285,6 +286,11 @@ def transfer(src_mesh, dst_mesh, src, dst):
     nodes of dst_mesh, a refinement of it."""
     ncomp = 1 if src.dim() == 1 else src.shape[1]
     _check(load().fracture_transfer(src_mesh.h, dst_mesh.h, _ptr(src), ncomp, _ptr(dst), _stream()))
+
+
+def kelly(mesh, u, eta2):
+    """Gradient-jump indicator of u per cell into eta2 (torch [n_cells])."""
+    _check(load().fracture_kelly(mesh.h, _ptr(u), _ptr(eta2), _stream()))
 
 
 def mark_crack(mesh, phi, phi_max, h_target):

@@ -1177,6 +1177,124 @@ void mesh_transfer(const DevMesh& from, const DevMesh& to, const double* src, in
     FR_LAUNCH_CHECK();
 }
 
+// d u_comp / d x_k at local coordinates xi of a cell of edge h with nodal values un[a][comp].
+template <int D>
+__device__ __forceinline__ double cell_grad(const double (&un)[1 << D][D], int comp, int k, const double* xi,
+                                            double h) {
+    double g = 0.0;
+#pragma unroll
+    for (int a = 0; a < (1 << D); ++a) {
+        double w = ((a >> k) & 1) ? 1.0 : -1.0;
+#pragma unroll
+        for (int t = 0; t < D; ++t)
+            if (t != k) w *= ((a >> t) & 1) ? xi[t] : 1.0 - xi[t];
+        g += w * un[a][comp];
+    }
+    return g / h;
+}
+
+template <int D>
+__device__ __forceinline__ void cell_values(int64_t c, const int32_t* __restrict__ cells,
+                                            const int32_t* __restrict__ con_ptr,
+                                            const int32_t* __restrict__ con_master,
+                                            const double* __restrict__ con_w,
+                                            const int32_t* __restrict__ node_of_free, const double* __restrict__ u,
+                                            double (&un)[1 << D][D]) {
+#pragma unroll
+    for (int a = 0; a < (1 << D); ++a)
+#pragma unroll
+        for (int comp = 0; comp < D; ++comp)
+            un[a][comp] = src_value(cells[c * (1 << D) + a], comp, D, con_ptr, con_master, con_w, node_of_free, u);
+}
+
+// One thread per cell: the gradient-jump indicator (Kelly-type) of the displacement.
+template <int D>
+__global__ void __launch_bounds__(256) k_kelly(int64_t nc, const int32_t* __restrict__ cells,
+                                               const double* __restrict__ cell_lo, const double* __restrict__ cell_h,
+                                               const int32_t* __restrict__ fptr, const int32_t* __restrict__ fnbr,
+                                               const int32_t* __restrict__ con_ptr,
+                                               const int32_t* __restrict__ con_master,
+                                               const double* __restrict__ con_w,
+                                               const int32_t* __restrict__ node_of_free,
+                                               const double* __restrict__ u, double* __restrict__ eta2) {
+    constexpr int NV = 1 << D;
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    double uo[NV][D], un[NV][D];
+    cell_values<D>(c, cells, con_ptr, con_master, con_w, node_of_free, u, uo);
+    const double h = cell_h[c];
+    double lo[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) lo[k] = cell_lo[c * D + k];
+    double acc = 0.0;
+    for (int j = 0; j < 2 * D; ++j) {
+        const int k = j >> 1, side = j & 1;
+        const double xk = lo[k] + side * h;
+        for (int32_t e = fptr[c * 2 * D + j]; e < fptr[c * 2 * D + j + 1]; ++e) {
+            const int64_t n = fnbr[e];
+            cell_values<D>(n, cells, con_ptr, con_master, con_w, node_of_free, u, un);
+            const double hn = cell_h[n];
+            double lon[D];
+#pragma unroll
+            for (int t = 0; t < D; ++t) lon[t] = cell_lo[n * D + t];
+            // integrate over the smaller of the two faces
+            const bool finer = hn < h;
+            const double rh = finer ? hn : h;
+            double wq = 1.0;
+#pragma unroll
+            for (int t = 0; t < D - 1; ++t) wq *= 0.5 * rh;
+            for (int g = 0; g < (1 << (D - 1)); ++g) {
+                double x[D];
+                int b = 0;
+#pragma unroll
+                for (int t = 0; t < D; ++t) {
+                    if (t == k) {
+                        x[t] = xk;
+                        continue;
+                    }
+                    x[t] = (finer ? lon[t] : lo[t]) + rh * (((g >> b) & 1) ? kGP : kGM);
+                    ++b;
+                }
+                double xi_o[D], xi_n[D];
+#pragma unroll
+                for (int t = 0; t < D; ++t) {
+                    xi_o[t] = (x[t] - lo[t]) / h;
+                    xi_n[t] = (x[t] - lon[t]) / hn;
+                }
+                double jj = 0.0;
+#pragma unroll
+                for (int comp = 0; comp < D; ++comp) {
+                    const double d = cell_grad<D>(uo, comp, k, xi_o, h) - cell_grad<D>(un, comp, k, xi_n, hn);
+                    jj += d * d;
+                }
+                acc += wq * jj;
+            }
+        }
+    }
+    eta2[c] = h / 24.0 * acc;
+}
+
+void mesh_kelly(DevMesh& m, const double* u, double* eta2, hipStream_t s) {
+    if (m.n_cells == 0) return;
+    if (m.face_ptr.p == nullptr) {
+        std::vector<int32_t> ptr, nbr;
+        face_neighbors(m.host, ptr, nbr);
+        m.face_ptr.upload(ptr, s);
+        m.face_nbr.upload(nbr.empty() ? std::vector<int32_t>{0} : nbr, s);
+        FR_HIP(hipStreamSynchronize(s));          // the host tables go out of scope
+    }
+    const bool h = m.hanging;
+    const int nb = blocks_for(m.n_cells, 256);
+#define FR_KELLY(D_)                                                                                       \
+    k_kelly<D_><<<nb, 256, 0, s>>>(m.n_cells, m.cells.p, m.cell_lo.p, m.cell_h.p, m.face_ptr.p, m.face_nbr.p, \
+                                   h ? m.con_ptr.p : nullptr, m.con_master.p, m.con_w.p, m.node_of_free.p, u, \
+                                   eta2)
+    if (m.dim == 2) FR_KELLY(2);
+    else FR_KELLY(3);
+#undef FR_KELLY
+    FR_LAUNCH_CHECK();
+}
+
 // One thread per cell: the crack-region mark.
 template <int D>
 __global__ void __launch_bounds__(256) k_mark_crack(int64_t nc, const int32_t* __restrict__ cells,

@@ -295,6 +295,16 @@ fr_status fracture_transfer(fr_mesh from, fr_mesh to, const double* src, int nco
     });
 }
 
+fr_status fracture_kelly(fr_mesh mesh, const double* u, double* eta2, void* stream) {
+    FR_REQUIRE(mesh != nullptr && mesh->m, "kelly: NULL mesh");
+    FR_REQUIRE(mesh->m->on_device, "kelly: host-only mesh");
+    FR_REQUIRE(u != nullptr && eta2 != nullptr, "kelly: NULL array");
+    return guard([&]() {
+        fr::mesh_kelly(*mesh->m, u, eta2, fr::as_stream(stream));
+        return FR_OK;
+    });
+}
+
 fr_status fracture_mark_crack(fr_mesh mesh, const double* phi, double phi_max, double h_target, uint8_t* flags,
                               int64_t* n_marked, void* stream) {
     FR_REQUIRE(mesh != nullptr && mesh->m, "mark_crack: NULL mesh");

@@ -581,6 +581,90 @@ HostMesh refine_mesh(const HostMesh& old, const uint8_t* flags, std::vector<int3
     return m;
 }
 
+void face_neighbors(const HostMesh& m, std::vector<int32_t>& ptr, std::vector<int32_t>& nbr) {
+    const int dim = m.dim, nv = m.nv, nf = 2 * dim;
+    const int64_t nc = m.n_cells;
+    ptr.assign(size_t(nc) * nf + 1, 0);
+    nbr.clear();
+    // cells keyed by (instance, edge in lattice units, origin): the instances of a batch have
+    // their own lattices
+    std::vector<int32_t> inst(static_cast<size_t>(nc), 0);
+    for (int i = 0; i < m.n_inst; ++i)
+        for (int64_t c = m.cell_off.empty() ? 0 : m.cell_off[size_t(i)];
+             c < (m.cell_off.empty() ? nc : m.cell_off[size_t(i) + 1]); ++c)
+            inst[size_t(c)] = i;
+    auto key = [&](int i, int64_t s, const int64_t* o) {
+        int lg = 0;
+        while ((int64_t(1) << lg) < s) ++lg;
+        return std::make_pair((uint64_t(i) << 8) | uint64_t(lg), pack(o));
+    };
+    std::vector<std::pair<std::pair<uint64_t, uint64_t>, int32_t>> tab(static_cast<size_t>(nc));
+    std::vector<int64_t> edge(static_cast<size_t>(nc));
+    std::vector<std::array<int64_t, 3>> org(static_cast<size_t>(nc));
+    std::vector<std::array<int64_t, 3>> iext(static_cast<size_t>(m.n_inst), {0, 0, 0});
+    for (int64_t c = 0; c < nc; ++c) {
+        const int64_t a = m.cells[size_t(c) * nv], b = m.cells[size_t(c) * nv + nv - 1];
+        std::array<int64_t, 3> o{0, 0, 0};
+        for (int k = 0; k < dim; ++k) o[k] = m.lattice[size_t(a) * dim + k];
+        edge[size_t(c)] = m.lattice[size_t(b) * dim] - m.lattice[size_t(a) * dim];
+        org[size_t(c)] = o;
+        tab[size_t(c)] = {key(inst[size_t(c)], edge[size_t(c)], o.data()), int32_t(c)};
+        for (int k = 0; k < dim; ++k)
+            iext[size_t(inst[size_t(c)])][size_t(k)] =
+                std::max(iext[size_t(inst[size_t(c)])][size_t(k)], o[k] + edge[size_t(c)]);
+    }
+    std::sort(tab.begin(), tab.end());
+    auto find = [&](int i, int64_t s, const int64_t* o) -> int32_t {
+        const auto k = key(i, s, o);
+        auto it = std::lower_bound(tab.begin(), tab.end(), std::make_pair(k, int32_t(-1)));
+        return (it != tab.end() && it->first == k) ? it->second : -1;
+    };
+    for (int64_t c = 0; c < nc; ++c) {
+        const int i = inst[size_t(c)];
+        const int64_t s = edge[size_t(c)];
+        const auto& o = org[size_t(c)];
+        for (int j = 0; j < nf; ++j) {
+            const int k = j / 2, side = j % 2;
+            const int64_t q = side ? o[k] + s : o[k] - s;     // origin of a same-size neighbour
+            if (side ? (o[k] + s >= iext[size_t(i)][size_t(k)]) : (o[k] == 0)) {
+                ptr[size_t(c) * nf + j + 1] = int32_t(nbr.size());
+                continue;
+            }
+            int64_t on[3] = {o[0], o[1], o[2]};
+            on[k] = q;
+            int32_t n = find(i, s, on);
+            if (n >= 0) {
+                nbr.push_back(n);
+            } else {
+                // coarser: the cell of edge 2s that holds the same-size neighbour
+                int64_t oc[3] = {0, 0, 0};
+                for (int t = 0; t < dim; ++t) oc[t] = (on[t] / (2 * s)) * (2 * s);
+                n = find(i, 2 * s, oc);
+                if (n >= 0) {
+                    nbr.push_back(n);
+                } else {
+                    // finer: the 2^(dim-1) cells of edge s/2 along the face
+                    const int64_t h = s / 2;
+                    for (int sub = 0; sub < (1 << (dim - 1)); ++sub) {
+                        int64_t of[3] = {on[0], on[1], on[2]};
+                        of[k] = side ? q : q + h;
+                        int b = 0;
+                        for (int t = 0; t < dim; ++t) {
+                            if (t == k) continue;
+                            of[t] = o[t] + ((sub >> b) & 1) * h;
+                            ++b;
+                        }
+                        const int32_t f = h >= 1 ? find(i, h, of) : -1;
+                        if (f < 0) fail(FR_EINTERNAL, "kelly: face neighbour not found (mesh not 2:1 balanced?)");
+                        nbr.push_back(f);
+                    }
+                }
+            }
+            ptr[size_t(c) * nf + j + 1] = int32_t(nbr.size());
+        }
+    }
+}
+
 HostMesh build_mesh_batch(const fr_mesh_desc* d, int n) {
     if (n < 1) fail(FR_EINVAL, "mesh: need at least one instance");
     if (n == 1) {

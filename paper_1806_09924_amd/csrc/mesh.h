@@ -74,6 +74,12 @@ HostMesh refine_mesh(const HostMesh& old, const uint8_t* flags, std::vector<int3
                      std::vector<double>& loc_xi);
 // Disjoint union of n independent meshes of the same dimension.
 HostMesh build_mesh_batch(const fr_mesh_desc* d, int n);
+
+// Face neighbours of every cell (one instance or a batch): for face j = 2k + side (axis k,
+// side 0 = low, 1 = high) of cell c the cells across it are nbr[ptr[2 dim c + j] ..
+// ptr[2 dim c + j + 1]): none on the domain boundary, one of the same or the next coarser level,
+// or the 2^(dim-1) cells of the next finer level (2:1 balance).
+void face_neighbors(const HostMesh& m, std::vector<int32_t>& ptr, std::vector<int32_t>& nbr);
 Pattern build_pattern(const HostMesh& m, int C);
 
 }  // namespace fr

@@ -74,6 +74,8 @@ struct DevMesh {
     int64_t parent_nodes = 0;
     DBuf<int32_t> parent_cell;                   // [n_nodes]
     DBuf<double> parent_xi;                      // [n_nodes][dim]
+    // Face neighbours (built on first use by mesh_kelly)
+    DBuf<int32_t> face_ptr, face_nbr;
 };
 
 std::unique_ptr<DevMesh> mesh_create(const fr_mesh_desc* d, int n_inst, hipStream_t s, bool upload);
@@ -82,6 +84,10 @@ std::unique_ptr<DevMesh> mesh_from_host(HostMesh&& host, hipStream_t s, bool upl
 // dst[n][c] = sum_a N_a(xi_n) src[vertex a of cell_n][c], hanging vertices of `from` taken from
 // their constraints.
 void mesh_transfer(const DevMesh& from, const DevMesh& to, const double* src, int ncomp, double* dst, hipStream_t s);
+// Gradient-jump indicator of u: eta2[c] = h_c / 24 * sum over the faces of cell c of the
+// integral of |jump of du/dn|^2 (all components), 2-point Gauss per face axis on the smaller
+// of the two faces; boundary faces contribute nothing.
+void mesh_kelly(DevMesh& m, const double* u, double* eta2, hipStream_t s);
 // Crack-region marks: flag[c] = 1 when the cell's edge exceeds h_target and phi (hanging
 // vertices from their constraints) is below phi_max at one of its vertices.
 void mesh_mark_crack(const DevMesh& m, const double* phi, double phi_max, double h_target, uint8_t* flags_dev,

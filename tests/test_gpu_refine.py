@@ -1,5 +1,6 @@
-"""Refinement between loading steps on the GPU (fracture_mark_crack, fracture_mesh_refine,
-fracture_transfer) against the oracle: crack-region marks bit for bit, transferred fields, and
+"""Refinement between loading steps on the GPU (fracture_mark_crack, fracture_kelly,
+fracture_mesh_refine, fracture_transfer) against the oracle: crack-region marks bit for bit, the
+gradient-jump indicator, transferred fields, and
 the whole sequence of Section 3's algorithm on a small crack: refine the initial crack band until
 eps = 2h holds there, a loading step, marks from the solution, refinement, transfer of u, phi and
 the previous phase field, the next step on the new mesh.  At the benchmark's full size the
@@ -50,6 +51,28 @@ def test_transfer_and_marks_match_oracle():
         got = host(d_dst)
         want = oref.transfer(om, om2, src)[p2]
         assert np.abs(got - want).max() <= 1e-14 * max(1.0, np.abs(want).max())
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_kelly_matches_oracle(dim):
+    if dim == 2:
+        desc = B.mesh_desc(2, -1.0, 1.0, 4, levels=2, refine_radius=0.3, crack_center=(0.0, 0.0, 0.0),
+                           crack_half_len=0.25)
+        om = adaptive.adaptive(2, -1.0, 1.0, 4, 2, 0.3, (0.0, 0.0, 0.0), 0.25)
+    else:
+        desc = B.mesh_desc(3, -1.0, 1.0, 2, levels=2, refine_radius=0.1, crack_center=(0.0, 0.0, 0.0),
+                           crack_half_len=0.3)
+        om = adaptive.adaptive(3, -1.0, 1.0, 2, 2, 0.1, (0.0, 0.0, 0.0), 0.3)
+    m = B.Mesh(desc)
+    assert m.n_hanging > 0
+    p = _perm(m, om)
+    u = np.random.default_rng(31 + dim).standard_normal((om.n_nodes, dim))
+    eta = torch.empty(m.n_cells, dtype=torch.float64, device="cuda")
+    B.kelly(m, dev(u[p]), eta)
+    ref = oref.kelly(om, u)
+    _, clo, _ = m.cells()
+    assert np.allclose(clo, om.cell_lo, atol=1e-14)               # same cell order
+    assert np.abs(host(eta) - ref).max() <= 1e-12 * ref.max()
 
 
 def _check_step(st, tcv, r, m, om, p, prm, oprm, u, phi, phi_old, pt):
@@ -107,10 +130,24 @@ def test_loading_with_refinement_matches_oracle():
     st1, tcv1 = B.loading(m, prm[:1], [0.0, 1.0], u, phi, solve=so, newton=no)
     r1 = oload.loading(om, oprm[:1], [0.0, 1.0], np.zeros((om.n_nodes, 2)), phi0, atol=1e-12)[0]
     _check_step(st1[0], tcv1[0], r1, m, om, p, prm[0], oprm[0], u, phi, dev(phi0[p]), dev(phi0[p]))
-    # marks from the solution's phase field: cells of the widened band coarser than h_t / 2
+    # marks from the solution: cells of the widened band coarser than h_t / 2, and the cells with
+    # the largest gradient jumps of u (cut at a wide gap of the oracle's indicator near the top
+    # 5 %, so that rounding cannot move a cell across it)
     flags, n = B.mark_crack(m, phi, 0.5, h_t / 2)
     oflags = oref.mark_crack(om, r1["phi"], 0.5, h_t / 2)
     assert n > 0 and np.array_equal(flags, oflags)
+    oeta = oref.kelly(om, r1["u"])
+    srt = np.sort(oeta)[::-1]
+    k0, k1 = max(1, int(0.02 * om.n_cells)), int(0.08 * om.n_cells)
+    cut_at = k0 + int(np.argmax(srt[k0:k1] / srt[k0 + 1:k1 + 1]))
+    cut = np.sqrt(srt[cut_at] * srt[cut_at + 1])
+    assert srt[cut_at] / srt[cut_at + 1] > 1.001
+    eta = torch.empty(m.n_cells, dtype=torch.float64, device="cuda")
+    B.kelly(m, u, eta)
+    assert np.abs(host(eta) - oeta).max() <= 1e-6 * oeta.max()
+    flags = flags | (host(eta) > cut).astype(np.uint8)
+    oflags = oflags | (oeta > cut).astype(np.uint8)
+    assert np.array_equal(flags, oflags) and (oeta > cut).sum() == cut_at + 1
     m2, om2 = m.refine(flags), oref.refine(om, flags)
     p2 = _perm(m2, om2)
     u2 = torch.empty((m2.n_nodes, 2), dtype=torch.float64, device="cuda")
@@ -155,6 +192,10 @@ def test_refinement_and_transfer_at_full_size():
     d2 = torch.empty(m2.n_nodes, dtype=torch.float64, device="cuda")
     B.transfer(m, m2, dev(f(xyz)), d2)
     assert np.abs(host(d2) - f(xyz2)).max() <= 1e-13
+    # the gradient-jump indicator of a linear displacement vanishes, hanging faces included
+    eta = torch.empty(m2.n_cells, dtype=torch.float64, device="cuda")
+    B.kelly(m2, dev(np.stack([0.1 * xyz2[:, 0] - 0.2 * xyz2[:, 1], 0.3 * xyz2[:, 1] + 0.05], axis=1)), eta)
+    assert host(eta).max() <= 1e-26
     u = dev(np.zeros((m.n_nodes, 2)))
     phi = dev(phi0)
     st = B.newton(m, B.params(eps=eps, kappa=1e-10, p=1e-3), u, phi, dev(phi0), dev(phi0),

@@ -82,3 +82,31 @@ def test_crack_marks_against_a_direct_scan():
         want = m.cell_h[c] > h_t and min(phi[m.cells[c, a]] for a in range(4)) < 0.4
         assert bool(flags[c]) == want
     assert flags.any() and not flags.all()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_kelly_vanishes_for_linear_displacements(dim):
+    if dim == 2:
+        m = adaptive.adaptive(2, -1.0, 1.0, 4, 2, 0.3, (0.0, 0.0, 0.0), 0.25)
+    else:
+        m = adaptive.adaptive(3, -1.0, 1.0, 2, 2, 0.1, (0.0, 0.0, 0.0), 0.3)
+    assert m.n_free < m.n_nodes
+    A = np.random.default_rng(2).standard_normal((dim, dim))
+    u = m.coords @ A.T + 0.3
+    assert np.abs(refine.kelly(m, u)).max() <= 1e-24
+
+
+def test_kelly_closed_form_at_a_kink():
+    """u_0 = |x_0 - a| with a on a grid line: the normal derivative jumps by 2 across that line,
+    so the cells on either side have eta^2 = h/24 * 4 * h = h^2/6 and all others 0."""
+    n, L = 8, 1.0
+    m = omesh.uniform(2, -L, L, n)
+    h = 2 * L / n
+    a = -L + 3 * h
+    u = np.zeros((m.n_nodes, 2))
+    u[:, 0] = np.abs(m.coords[:, 0] - a)
+    eta2 = refine.kelly(m, u)
+    touch = (np.abs(m.cell_lo[:, 0] - a) < 1e-12) | (np.abs(m.cell_lo[:, 0] + h - a) < 1e-12)
+    assert touch.sum() == 2 * n
+    assert np.allclose(eta2[touch], h * h / 6.0, rtol=1e-13)
+    assert np.abs(eta2[~touch]).max() <= 1e-28
