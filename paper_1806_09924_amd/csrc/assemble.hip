@@ -6,6 +6,7 @@
 // Assembly is node-centric: one thread owns one free node (one block row of every matrix
 // and the matching residual entries), walks the cells that carry its basis function and
 // accumulates in a fixed order.  No atomics: results are bitwise reproducible.
+#include <atomic>
 #include <cmath>
 
 #include "system.h"
@@ -848,7 +849,9 @@ std::unique_ptr<DevMesh> mesh_create(const fr_mesh_desc* d, int n_inst, hipStrea
 }
 
 std::unique_ptr<DevMesh> mesh_from_host(HostMesh&& host, hipStream_t s, bool upload) {
+    static std::atomic<uint64_t> next_serial{1};
     auto m = std::make_unique<DevMesh>();
+    m->serial = next_serial.fetch_add(1);
     const int n_inst = host.n_inst;
     m->host = std::move(host);
     m->n_inst = n_inst;

@@ -270,7 +270,7 @@ fr_status fracture_mesh_refine(fr_mesh mesh, const uint8_t* flags, fr_mesh* out,
         fr::HostMesh hm = fr::refine_mesh(old.host, flags, loc_cell, loc_xi);
         auto h = std::make_unique<fr_mesh_s>();
         h->m = fr::mesh_from_host(std::move(hm), s, old.on_device);
-        h->m->parent = &old;
+        h->m->parent_serial = old.serial;
         h->m->parent_nodes = old.n_nodes;
         if (old.on_device) {
             h->m->parent_cell.upload(loc_cell, s);
@@ -285,7 +285,7 @@ fr_status fracture_mesh_refine(fr_mesh mesh, const uint8_t* flags, fr_mesh* out,
 fr_status fracture_transfer(fr_mesh from, fr_mesh to, const double* src, int ncomp, double* dst, void* stream) {
     FR_REQUIRE(from != nullptr && from->m && to != nullptr && to->m, "transfer: NULL mesh");
     FR_REQUIRE(from->m->on_device && to->m->on_device, "transfer: host-only mesh");
-    FR_REQUIRE(to->m->parent == from->m.get() && to->m->parent_nodes == from->m->n_nodes,
+    FR_REQUIRE(to->m->parent_serial == from->m->serial && to->m->parent_nodes == from->m->n_nodes,
                "transfer: `to` was not made from `from` by fracture_mesh_refine");
     FR_REQUIRE(src != nullptr && dst != nullptr && src != dst, "transfer: NULL or aliased arrays");
     FR_REQUIRE(ncomp >= 1 && ncomp <= 16, "transfer: ncomp must be in [1, 16]");

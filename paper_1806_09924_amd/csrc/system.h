@@ -69,8 +69,9 @@ struct DevMesh {
     std::vector<int32_t> heavy_host;
     int64_t n_heavy = 0;
     DBuf<double> ent_w;
+    uint64_t serial = 0;                         // unique per mesh in the process
     // A mesh made by refine_mesh: where its nodes lie in the mesh it was made from.
-    const DevMesh* parent = nullptr;             // identity only (checked by transfers)
+    uint64_t parent_serial = 0;                  // that mesh's serial (0: none)
     int64_t parent_nodes = 0;
     DBuf<int32_t> parent_cell;                   // [n_nodes]
     DBuf<double> parent_xi;                      // [n_nodes][dim]

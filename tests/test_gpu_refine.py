@@ -51,6 +51,12 @@ def test_transfer_and_marks_match_oracle():
         got = host(d_dst)
         want = oref.transfer(om, om2, src)[p2]
         assert np.abs(got - want).max() <= 1e-14 * max(1.0, np.abs(want).max())
+    # a transfer between meshes that are not parent and refinement is refused before any launch
+    other = B.Mesh(desc)
+    with pytest.raises(B.FractureError):
+        B.transfer(other, m2, dev(phi[p]), torch.empty(m2.n_nodes, dtype=torch.float64, device="cuda"))
+    with pytest.raises(B.FractureError):
+        B.transfer(m2, m, torch.zeros(m2.n_nodes, dtype=torch.float64, device="cuda"), dev(phi[p]))
 
 
 @pytest.mark.parametrize("dim", [2, 3])
