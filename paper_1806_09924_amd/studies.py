@@ -11,7 +11,11 @@ and under global refinement (eps = 2 h_min on every mesh), each family's referen
 Richardson extrapolation of its own three finest levels, and the observed orders of the errors
 against h and against the number of DoFs.
 
-Run as `python -m paper_1806_09924_amd.studies [domain|cod] [64|32]` (prints one JSON object).
+convergence_3d(): Section 4.3, the TCV of the 3d penny crack (l0 = 1, 10 x 10 x 10 domain) on
+adaptive meshes whose finest edge is 10 l0 / 2^ref, with eps = 2 x the finest cell's diameter
+(the eps column of the Fig. 3 table), against Sneddon's 5.12E-03.
+
+Run as `python -m paper_1806_09924_amd.studies [domain|cod|3d] [64|32]` (prints one JSON object).
 """
 import json
 import sys
@@ -109,8 +113,9 @@ def _solve_family(descs, l0, xs, precision, rtol):
     st = B.newton(mesh, prms, u, phi, p0, p0, amg=B.amg_opts(precision=precision), solve=B.solve_opts(rtol=rtol))
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    st = st if isinstance(st, list) else [st]
     cx = np.array([[[x] for x in xs]] * ni)
-    cod, _ = B.functionals(mesh, u, phi, cx)
+    cod, _ = B.functionals(mesh, u, phi, cx if ni > 1 else cx[0])
     for i in range(ni):
         assert st[i]["status"] == 0, (i, st[i])
     return dict(h=[nd["h_min"] for nd in inst], n_dofs=[3 * nd["n_nodes"] for nd in inst],
@@ -148,10 +153,56 @@ def cod_convergence(half_width, levels, refine_radius, l0=1.0, xs=(0.0, 0.5), pr
     return out
 
 
+def convergence_3d(refs=(7, 8, 9), refine_radius=0.4, precision=32, rtol=1e-8):
+    """One batched Newton loop over the refs' meshes: base 16^3 cells of edge 10/16 (ref 4),
+    ref - 4 levels within refine_radius of the crack disk, eps = 2 sqrt(3) h_min.  Returns per
+    ref the DoFs (4 per node), eps, TCV and the relative error against Sneddon's closed form."""
+    from inputs import crack_band_phi   # the workloads' initial crack field
+    descs = [B.mesh_desc(3, -5.0, 5.0, 16, levels=r - 4, refine_radius=refine_radius, crack_half_len=1.0)
+             for r in refs]
+    t0 = time.perf_counter()
+    mesh = B.Mesh(descs)
+    t_mesh = time.perf_counter() - t0
+    xyz = mesh.nodes()[0]
+    inst = [mesh.instance(i) for i in range(len(refs))]
+    phi0 = np.zeros(mesh.n_nodes)
+    prms, epss = [], []
+    for i, nd in enumerate(inst):
+        eps = 2.0 * np.sqrt(3.0) * nd["h_min"]
+        sl = slice(nd["node_offset"], nd["node_offset"] + nd["n_nodes"])
+        phi0[sl] = crack_band_phi(xyz[sl], 1.0, eps)
+        prms.append(B.params(eps=eps, kappa=1e-10, p=1e-3))
+        epss.append(eps)
+    dev = torch.device("cuda")
+    p0 = torch.as_tensor(phi0, device=dev)
+    u = torch.zeros((mesh.n_nodes, 3), dtype=torch.float64, device=dev)
+    phi = p0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = B.newton(mesh, prms, u, phi, p0, p0, amg=B.amg_opts(precision=precision), solve=B.solve_opts(rtol=rtol))
+    torch.cuda.synchronize()
+    t_newton = time.perf_counter() - t0
+    _, tcv = B.functionals(mesh, u, phi)
+    st = st if isinstance(st, list) else [st]          # one ref: the binding returns one dict
+    tcv = np.atleast_1d(tcv)
+    exact = 16.0 * 1e-3 * 1.0 ** 3 * (1 - 0.2 ** 2) / (3.0 * 1.0)
+    rows = []
+    for i, r in enumerate(refs):
+        assert st[i]["status"] == 0, (r, st[i])
+        rows.append(dict(ref=r, ten_l0_over_h=2 ** r,
+                         h_min=inst[i]["h_min"], n_dofs=4 * inst[i]["n_nodes"], eps=epss[i], tcv=float(tcv[i]),
+                         rel_error=float(tcv[i] / exact - 1), newton=st[i]["iterations"], fgmres=st[i]["linear_iters"]))
+    return dict(rows=rows, exact=exact, refine_radius=refine_radius, precision=precision, t_mesh=t_mesh,
+                t_newton=t_newton, n_dofs=int(4 * mesh.n_nodes))
+
+
 def main(argv=None):
     argv = list(argv or [])
-    which = argv.pop(0) if argv and argv[0] in ("domain", "cod") else "domain"
+    which = argv.pop(0) if argv and argv[0] in ("domain", "cod", "3d") else "domain"
     precision = int(argv[0]) if argv else 64
+    if which == "3d":
+        print(json.dumps(convergence_3d(precision=precision)))
+        return
     if which == "cod":
         from inputs import cod_study
         c = cod_study()
