@@ -218,7 +218,8 @@ fr_status fracture_transfer(fr_mesh from, fr_mesh to, const double* src, int nco
  * face axis on the smaller of the two faces at a level change; boundary faces contribute
  * nothing. u: device [n_nodes][dim] (hanging values from their constraints); eta2: device
  * [n_cells] (one instance or a batch). The face-neighbour table is built on the first call and
- * kept with the mesh. Enqueued on `stream` (the first call synchronises it). */
+ * kept with the mesh, so concurrent first calls on one mesh race. Enqueued on `stream` (the
+ * first call synchronises it). */
 fr_status fracture_kelly(fr_mesh mesh, const double* u, double* eta2, void* stream);
 
 /* Crack-region marks (the refinement that keeps eps = 2h in the crack region, Section 3):
