@@ -284,11 +284,11 @@ fr_status fracture_mesh_refine(fr_mesh mesh, const uint8_t* flags, fr_mesh* out,
 
 fr_status fracture_transfer(fr_mesh from, fr_mesh to, const double* src, int ncomp, double* dst, void* stream) {
     FR_REQUIRE(from != nullptr && from->m && to != nullptr && to->m, "transfer: NULL mesh");
-    FR_REQUIRE(from->m->on_device && to->m->on_device, "transfer: host-only mesh");
+    FR_REQUIRE(ncomp >= 1 && ncomp <= 16, "transfer: ncomp must be in [1, 16]");
     FR_REQUIRE(to->m->parent_serial == from->m->serial && to->m->parent_nodes == from->m->n_nodes,
                "transfer: `to` was not made from `from` by fracture_mesh_refine");
+    FR_REQUIRE(from->m->on_device && to->m->on_device, "transfer: host-only mesh");
     FR_REQUIRE(src != nullptr && dst != nullptr && src != dst, "transfer: NULL or aliased arrays");
-    FR_REQUIRE(ncomp >= 1 && ncomp <= 16, "transfer: ncomp must be in [1, 16]");
     return guard([&]() {
         fr::mesh_transfer(*from->m, *to->m, src, ncomp, dst, fr::as_stream(stream));
         return FR_OK;
@@ -308,9 +308,9 @@ fr_status fracture_kelly(fr_mesh mesh, const double* u, double* eta2, void* stre
 fr_status fracture_mark_crack(fr_mesh mesh, const double* phi, double phi_max, double h_target, uint8_t* flags,
                               int64_t* n_marked, void* stream) {
     FR_REQUIRE(mesh != nullptr && mesh->m, "mark_crack: NULL mesh");
+    FR_REQUIRE(std::isfinite(phi_max) && std::isfinite(h_target) && h_target > 0, "mark_crack: bad thresholds");
     FR_REQUIRE(mesh->m->on_device, "mark_crack: host-only mesh");
     FR_REQUIRE(phi != nullptr && flags != nullptr, "mark_crack: NULL array");
-    FR_REQUIRE(std::isfinite(phi_max) && std::isfinite(h_target) && h_target > 0, "mark_crack: bad thresholds");
     return guard([&]() {
         hipStream_t s = fr::as_stream(stream);
         const fr::DevMesh& m = *mesh->m;
@@ -977,8 +977,6 @@ fr_status fracture_loading(fr_mesh mesh, const fr_params* prm, int n_steps, cons
                            const fr_solve_opts* solve_opts, const fr_newton_opts* newton_opts,
                            fr_newton_stats* stats, double* tcv, void* stream) {
     FR_REQUIRE(mesh != nullptr && mesh->m, "loading: NULL mesh");
-    FR_REQUIRE(mesh->m->on_device, "loading: host-only mesh");
-    FR_REQUIRE(u && phi, "loading: NULL state array");
     FR_REQUIRE(prm != nullptr && t != nullptr, "loading: NULL params or times");
     FR_REQUIRE(n_steps >= 1 && n_steps <= 100000, "loading: n_steps out of range");
     const int ni = mesh->m->n_inst;
@@ -992,6 +990,8 @@ fr_status fracture_loading(fr_mesh mesh, const fr_params* prm, int n_steps, cons
     }
     FR_REQUIRE(phi_prev == nullptr || (std::isfinite(t_prev) && t_prev < t[0]),
                "loading: t_prev must be finite and before t[0]");
+    FR_REQUIRE(mesh->m->on_device, "loading: host-only mesh");
+    FR_REQUIRE(u && phi, "loading: NULL state array");
     fr_amg_opts ao;
     fr_solve_opts so;
     fr_newton_opts no;

@@ -68,7 +68,7 @@ def test_host_only_mesh_is_rejected_by_device_calls(lib):
     sysh = ctypes.c_void_p()
     assert lib.fracture_assemble(m.h, ctypes.byref(p), None, None, None, None, 1, ctypes.byref(sysh), None) == B.FR_EINVAL
     assert "host-only" in B.last_error()
-    t = (ctypes.c_double * 3)(0.0, 1.0, 1.0)
+    t = (ctypes.c_double * 3)(0.0, 1.0, 2.0)
     st = (B.NewtonStats * 2)()
     prm2 = (B.Params * 2)(p, p)
     assert lib.fracture_loading(m.h, prm2, 2, t, None, None, None, ctypes.c_double(0.0), None, None, None, st,
@@ -215,3 +215,41 @@ def test_library_refinement_matches_oracle(dim, n, levels, radius, half, frac):
         assert m2.h_min == pytest.approx(m.h_min / 2, rel=1e-15)
         _same_mesh(m2, om2)
         m, om = m2, om2
+
+
+def test_loading_refinement_argument_checks(lib):
+    """The loading and refinement entry points check their arguments before the device (a
+    host-only mesh stands in for any mesh here)."""
+    m = B.Mesh(B.mesh_desc(2, -1.0, 1.0, 4), host_only=True)
+    p = B.params()
+    st = (B.NewtonStats * 2)()
+    prm2 = (B.Params * 2)(p, p)
+    for times, n, msg in (((0.0, 1.0, 1.0), 2, "increasing"), ((0.0, 2.0, 1.0), 2, "increasing"),
+                          ((0.0, float("nan"), 2.0), 2, "finite"), ((0.0, 1.0, 2.0), 0, "n_steps")):
+        t = (ctypes.c_double * 3)(*times)
+        assert lib.fracture_loading(m.h, prm2, n, t, None, None, None, ctypes.c_double(0.0), None, None, None, st,
+                                    None, None) == B.FR_EINVAL
+        assert msg in B.last_error()
+    t = (ctypes.c_double * 3)(0.0, 1.0, 2.0)
+    bad = B.params(nu=0.7)
+    prm_bad = (B.Params * 2)(p, bad)
+    assert lib.fracture_loading(m.h, prm_bad, 2, t, None, None, None, ctypes.c_double(0.0), None, None, None, st,
+                                None, None) == B.FR_EINVAL
+    assert "nu" in B.last_error()
+    phi_prev = ctypes.c_void_p(8)     # never dereferenced: rejected first
+    assert lib.fracture_loading(m.h, prm2, 2, t, None, None, phi_prev, ctypes.c_double(0.5), None, None, None, st,
+                                None, None) == B.FR_EINVAL
+    assert "t_prev" in B.last_error()
+    # refinement of a host-only mesh works; a transfer needs the pair's lineage and ncomp in range
+    m2 = m.refine(np.ones(m.n_cells, dtype=np.uint8))
+    assert m2.n_cells == 4 * m.n_cells
+    assert lib.fracture_transfer(m.h, m2.h, None, 0, None, None) == B.FR_EINVAL
+    assert "ncomp" in B.last_error()
+    assert lib.fracture_transfer(m2.h, m.h, None, 1, None, None) == B.FR_EINVAL
+    assert "not made from" in B.last_error()
+    n = ctypes.c_int64()
+    assert lib.fracture_mark_crack(m.h, None, ctypes.c_double(0.5), ctypes.c_double(0.0), None, ctypes.byref(n),
+                                   None) == B.FR_EINVAL
+    assert "thresholds" in B.last_error()
+    with pytest.raises(ValueError):
+        m.refine(np.ones(m.n_cells + 1, dtype=np.uint8))
