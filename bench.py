@@ -121,6 +121,28 @@ def cpu_baseline(n_cpu, L_full, n_full, iters_per_newton):
                 seconds=wall, n_solve=m.n_solve)
 
 
+def stream_ceiling(dev, nbytes=2 << 30, reps=10):
+    """GB/s of a device copy (read + write counted) and of a read-only reduction over nbytes,
+    HIP events on the current stream, after two warm-up passes."""
+    import torch
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    res = {}
+    for name, fn, moved in (("copy_gbs", lambda: y.copy_(x), 2 * nbytes), ("read_gbs", lambda: x.sum(), nbytes)):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        res[name] = moved * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -217,6 +239,9 @@ def main():
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": counted_traffic(dom),
                            "bytes_per_launch": bytes_per, "avg_launch_ms": avg_ms, "launches": d["launches"]}
+        # what this device's HBM sustains for plain streams (context for frac; peak stays the
+        # published 8 TB/s)
+        out["roofline"]["measured_ceiling"] = stream_ceiling(dev)
         out["kernels"] = {k: {"launches": v["launches"], "ms_total": v["ms"],
                               "gbs": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 and v["bytes"] > 0 else None}
                           for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
