@@ -173,6 +173,13 @@ fr_status fracture_mesh_create_host(const fr_mesh_desc* desc, fr_mesh* out);
  * edge lengths. */
 fr_status fracture_mesh_cells(fr_mesh mesh, int32_t* cells, double* cell_lo, double* cell_h);
 
+/* Face neighbours, host CSR over (cell, face) for inspection (the table fracture_kelly uses):
+ * the cells across face j = 2k + side (axis k; side 0 low, 1 high) of cell c are
+ * nbr[ptr[2 dim c + j] .. ptr[2 dim c + j + 1]): none on the boundary, one of the same or the
+ * next coarser level, or the 2^(dim-1) cells of the next finer level. *n_entries is always
+ * set; ptr (2 dim n_cells + 1 entries) and nbr are nullable. Works on host-only meshes. */
+fr_status fracture_mesh_faces(fr_mesh mesh, int64_t* n_entries, int32_t* ptr, int32_t* nbr);
+
 /* Hanging-node conformity map, host CSR over nodes: value(node n) =
  * sum_j con_w[j] value(free node con_master[j]) for j in [con_ptr[n], con_ptr[n+1]);
  * a free node lists itself with weight 1. *n_entries is always set; arrays are nullable

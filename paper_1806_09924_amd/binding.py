@@ -105,6 +105,7 @@ _SIGNATURES = {
     "fracture_transfer": [_P, _P, _P, ctypes.c_int, _P, _P],
     "fracture_mark_crack": [_P, _P, ctypes.c_double, ctypes.c_double, _P, _I64P, _P],
     "fracture_kelly": [_P, _P, _P, _P],
+    "fracture_mesh_faces": [_P, _I64P, _P, _P],
     "fracture_loading": [_P, ctypes.POINTER(Params), ctypes.c_int, _DP, _P, _P, _P, ctypes.c_double,
                          ctypes.POINTER(AmgOpts), ctypes.POINTER(SolveOpts), ctypes.POINTER(NewtonOpts),
                          ctypes.POINTER(NewtonStats), _DP, _P],
@@ -250,6 +251,16 @@ class Mesh:
         _check(load().fracture_mesh_cells(self.h, cells.ctypes.data_as(_P), lo.ctypes.data_as(_P),
                                           h.ctypes.data_as(_P)))
         return cells, lo, h
+
+    def faces(self):
+        """(ptr [2 dim n_cells + 1], nbr): the cells across every face of every cell."""
+        lib = load()
+        n = ctypes.c_int64()
+        _check(lib.fracture_mesh_faces(self.h, ctypes.byref(n), None, None))
+        ptr = np.zeros(2 * self.dim * self.n_cells + 1, dtype=np.int32)
+        nbr = np.zeros(max(1, n.value), dtype=np.int32)
+        _check(lib.fracture_mesh_faces(self.h, ctypes.byref(n), ptr.ctypes.data_as(_P), nbr.ctypes.data_as(_P)))
+        return ptr, nbr[:n.value]
 
     def constraints(self):
         lib = load()

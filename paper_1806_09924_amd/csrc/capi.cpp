@@ -376,6 +376,18 @@ fr_status fracture_mesh_constraints(fr_mesh mesh, int64_t* n_entries, int32_t* c
     return FR_OK;
 }
 
+fr_status fracture_mesh_faces(fr_mesh mesh, int64_t* n_entries, int32_t* ptr, int32_t* nbr) {
+    FR_REQUIRE(mesh != nullptr && mesh->m && n_entries, "mesh_faces: NULL argument");
+    return guard([&]() {
+        std::vector<int32_t> p, n;
+        fr::face_neighbors(mesh->m->host, p, n);
+        *n_entries = int64_t(n.size());
+        if (ptr) std::memcpy(ptr, p.data(), p.size() * sizeof(int32_t));
+        if (nbr) std::memcpy(nbr, n.data(), n.size() * sizeof(int32_t));
+        return FR_OK;
+    });
+}
+
 fr_status fracture_mesh_info(fr_mesh mesh, int64_t* n_nodes, int64_t* n_cells, int64_t* n_free, int64_t* n_all,
                              int64_t* n_solve, int64_t* n_hanging, double* h_min, int64_t* nnz_node_graph) {
     FR_REQUIRE(mesh != nullptr && mesh->m, "mesh_info: NULL mesh");

@@ -253,3 +253,28 @@ def test_loading_refinement_argument_checks(lib):
     assert "thresholds" in B.last_error()
     with pytest.raises(ValueError):
         m.refine(np.ones(m.n_cells + 1, dtype=np.uint8))
+
+
+@pytest.mark.parametrize("dim,n,levels,radius,half", [(2, 4, 3, 0.3, 0.25), (3, 2, 2, 0.1, 0.3), (2, 5, 0, 0.0, 0.0)])
+def test_face_neighbours_against_a_brute_force_search(dim, n, levels, radius, half):
+    """The host face-neighbour table of the gradient-jump indicator: for every face of every
+    cell, exactly the cells whose box touches that face from the other side with an overlap of
+    positive measure (scan of all cells), on adaptive meshes and after a refinement."""
+    m = B.Mesh(B.mesh_desc(dim, -1.0, 1.0, n, levels=levels, refine_radius=radius, crack_center=(0.0, 0.0, 0.0),
+                           crack_half_len=half), host_only=True)
+    rng = np.random.default_rng(7)
+    for mesh in (m, m.refine((rng.random(m.n_cells) < 0.2).astype(np.uint8))):
+        _, lo, h = mesh.cells()
+        hi = lo + h[:, None]
+        ptr, nbr = mesh.faces()
+        tol = 1e-12
+        for c in range(mesh.n_cells):
+            for j in range(2 * dim):
+                k, side = divmod(j, 2)
+                plane = hi[c, k] if side else lo[c, k]
+                touch = np.abs((lo[:, k] if side else hi[:, k]) - plane) <= tol
+                for t in range(dim):
+                    if t != k:
+                        touch &= (np.minimum(hi[:, t], hi[c, t]) - np.maximum(lo[:, t], lo[c, t])) > tol
+                got = sorted(nbr[ptr[2 * dim * c + j]:ptr[2 * dim * c + j + 1]].tolist())
+                assert got == sorted(np.nonzero(touch)[0].tolist()), (c, j)
