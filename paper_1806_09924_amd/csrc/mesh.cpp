@@ -619,50 +619,58 @@ void face_neighbors(const HostMesh& m, std::vector<int32_t>& ptr, std::vector<in
         auto it = std::lower_bound(tab.begin(), tab.end(), std::make_pair(k, int32_t(-1)));
         return (it != tab.end() && it->first == k) ? it->second : -1;
     };
-    for (int64_t c = 0; c < nc; ++c) {
-        const int i = inst[size_t(c)];
-        const int64_t s = edge[size_t(c)];
-        const auto& o = org[size_t(c)];
-        for (int j = 0; j < nf; ++j) {
-            const int k = j / 2, side = j % 2;
-            const int64_t q = side ? o[k] + s : o[k] - s;     // origin of a same-size neighbour
-            if (side ? (o[k] + s >= iext[size_t(i)][size_t(k)]) : (o[k] == 0)) {
-                ptr[size_t(c) * nf + j + 1] = int32_t(nbr.size());
-                continue;
-            }
-            int64_t on[3] = {o[0], o[1], o[2]};
-            on[k] = q;
-            int32_t n = find(i, s, on);
-            if (n >= 0) {
-                nbr.push_back(n);
-            } else {
-                // coarser: the cell of edge 2s that holds the same-size neighbour
-                int64_t oc[3] = {0, 0, 0};
-                for (int t = 0; t < dim; ++t) oc[t] = (on[t] / (2 * s)) * (2 * s);
-                n = find(i, 2 * s, oc);
+    // cells in contiguous ranges, one per host thread; each range lists its neighbours in cell
+    // order and the ranges are joined in order, so the table equals a serial sweep's
+    std::vector<std::vector<int32_t>> part(16);
+    std::vector<int32_t> cnt(size_t(nc) * nf, 0);
+    parallel_ranges(nc, [&](int64_t cb, int64_t ce, int t) {
+        std::vector<int32_t>& out = part[size_t(t)];
+        for (int64_t c = cb; c < ce; ++c) {
+            const int i = inst[size_t(c)];
+            const int64_t s = edge[size_t(c)];
+            const auto& o = org[size_t(c)];
+            for (int j = 0; j < nf; ++j) {
+                const int k = j / 2, side = j % 2;
+                const int64_t q = side ? o[k] + s : o[k] - s;     // origin of a same-size neighbour
+                if (side ? (o[k] + s >= iext[size_t(i)][size_t(k)]) : (o[k] == 0)) continue;
+                const size_t before = out.size();
+                int64_t on[3] = {o[0], o[1], o[2]};
+                on[k] = q;
+                int32_t n = find(i, s, on);
                 if (n >= 0) {
-                    nbr.push_back(n);
+                    out.push_back(n);
                 } else {
-                    // finer: the 2^(dim-1) cells of edge s/2 along the face
-                    const int64_t h = s / 2;
-                    for (int sub = 0; sub < (1 << (dim - 1)); ++sub) {
-                        int64_t of[3] = {on[0], on[1], on[2]};
-                        of[k] = side ? q : q + h;
-                        int b = 0;
-                        for (int t = 0; t < dim; ++t) {
-                            if (t == k) continue;
-                            of[t] = o[t] + ((sub >> b) & 1) * h;
-                            ++b;
+                    // coarser: the cell of edge 2s that holds the same-size neighbour
+                    int64_t oc[3] = {0, 0, 0};
+                    for (int t = 0; t < dim; ++t) oc[t] = (on[t] / (2 * s)) * (2 * s);
+                    n = find(i, 2 * s, oc);
+                    if (n >= 0) {
+                        out.push_back(n);
+                    } else {
+                        // finer: the 2^(dim-1) cells of edge s/2 along the face
+                        const int64_t h = s / 2;
+                        for (int sub = 0; sub < (1 << (dim - 1)); ++sub) {
+                            int64_t of[3] = {on[0], on[1], on[2]};
+                            of[k] = side ? q : q + h;
+                            int b = 0;
+                            for (int t = 0; t < dim; ++t) {
+                                if (t == k) continue;
+                                of[t] = o[t] + ((sub >> b) & 1) * h;
+                                ++b;
+                            }
+                            const int32_t f = h >= 1 ? find(i, h, of) : -1;
+                            if (f < 0) fail(FR_EINTERNAL, "kelly: face neighbour not found (mesh not 2:1 balanced?)");
+                            out.push_back(f);
                         }
-                        const int32_t f = h >= 1 ? find(i, h, of) : -1;
-                        if (f < 0) fail(FR_EINTERNAL, "kelly: face neighbour not found (mesh not 2:1 balanced?)");
-                        nbr.push_back(f);
                     }
                 }
+                cnt[size_t(c) * nf + j] = int32_t(out.size() - before);
             }
-            ptr[size_t(c) * nf + j + 1] = int32_t(nbr.size());
         }
-    }
+    });
+    for (int64_t e = 0; e < nc * nf; ++e) ptr[size_t(e) + 1] = ptr[size_t(e)] + cnt[size_t(e)];
+    nbr.reserve(size_t(ptr[size_t(nc) * nf]));
+    for (auto& v : part) nbr.insert(nbr.end(), v.begin(), v.end());
 }
 
 HostMesh build_mesh_batch(const fr_mesh_desc* d, int n) {

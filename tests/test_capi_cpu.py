@@ -255,7 +255,8 @@ def test_loading_refinement_argument_checks(lib):
         m.refine(np.ones(m.n_cells + 1, dtype=np.uint8))
 
 
-@pytest.mark.parametrize("dim,n,levels,radius,half", [(2, 4, 3, 0.3, 0.25), (3, 2, 2, 0.1, 0.3), (2, 5, 0, 0.0, 0.0)])
+@pytest.mark.parametrize("dim,n,levels,radius,half", [(2, 4, 3, 0.3, 0.25), (3, 2, 2, 0.1, 0.3), (2, 5, 0, 0.0, 0.0),
+                                                       (2, 96, 0, 0.0, 0.0)])
 def test_face_neighbours_against_a_brute_force_search(dim, n, levels, radius, half):
     """The host face-neighbour table of the gradient-jump indicator: for every face of every
     cell, exactly the cells whose box touches that face from the other side with an overlap of
@@ -268,7 +269,9 @@ def test_face_neighbours_against_a_brute_force_search(dim, n, levels, radius, ha
         hi = lo + h[:, None]
         ptr, nbr = mesh.faces()
         tol = 1e-12
-        for c in range(mesh.n_cells):
+        # large meshes are built by several host threads; a sample of their cells is checked
+        cells = range(mesh.n_cells) if mesh.n_cells <= 4096 else rng.choice(mesh.n_cells, 600, replace=False)
+        for c in cells:
             for j in range(2 * dim):
                 k, side = divmod(j, 2)
                 plane = hi[c, k] if side else lo[c, k]
