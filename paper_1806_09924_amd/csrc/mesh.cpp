@@ -390,37 +390,56 @@ HostMesh build_mesh(const fr_mesh_desc& d, const RefineSeed* seed) {
             hid[size_t(n)] = int32_t(hang.size());
             hang.push_back(std::move(ms));
         };
-        for (int64_t c = 0; c < m.n_cells; ++c) {
-            const Leaf& lf = leaves[size_t(c)];
-            int64_t s = S >> lf.level;
-            if (s < 2) continue;
-            const int32_t* cv = &m.cells[size_t(c) * nv];
-            // edges: vertex pairs differing in one bit
-            for (int a = 0; a < nv; ++a)
-                for (int k = 0; k < dim; ++k) {
-                    if ((a >> k) & 1) continue;
-                    int b = a | (1 << k);
-                    int64_t q[3] = {lf.o[0], lf.o[1], lf.o[2]};
-                    for (int t = 0; t < dim; ++t) q[t] += ((a >> t) & 1) * s;
-                    q[k] += s / 2;
-                    int64_t n = node_of(key_of(q));
-                    if (n >= 0 && !is_hang[size_t(n)]) set_hang(n, {{cv[a], 0.5}, {cv[b], 0.5}});
-                }
-            if (dim == 3) {
-                for (int k = 0; k < 3; ++k)
-                    for (int side = 0; side < 2; ++side) {
-                        int64_t q[3] = {lf.o[0] + s / 2, lf.o[1] + s / 2, lf.o[2] + s / 2};
-                        q[k] = lf.o[k] + side * s;
-                        int64_t n = node_of(key_of(q));
-                        if (n >= 0 && !is_hang[size_t(n)]) {
-                            std::vector<std::pair<int64_t, double>> ms;
-                            for (int a = 0; a < nv; ++a)
-                                if (((a >> k) & 1) == side) ms.push_back({cv[a], 0.25});
-                            set_hang(n, std::move(ms));
-                        }
+        // The lookups run on host threads over contiguous cell ranges and list every node found
+        // with its masters; the lists are then recorded in cell order, the first cell that names
+        // a node giving its masters, exactly as a serial sweep would.
+        struct Cand {
+            int64_t n;
+            int nm;
+            int64_t mst[4];
+            double w;
+        };
+        std::vector<std::vector<Cand>> cand(16);
+        parallel_ranges(m.n_cells, [&](int64_t cb, int64_t ce, int th) {
+            std::vector<Cand>& out = cand[size_t(th)];
+            for (int64_t c = cb; c < ce; ++c) {
+                const Leaf& lf = leaves[size_t(c)];
+                const int64_t s = S >> lf.level;
+                if (s < 2) continue;
+                const int32_t* cv = &m.cells[size_t(c) * nv];
+                // edges: vertex pairs differing in one bit
+                for (int a = 0; a < nv; ++a)
+                    for (int k = 0; k < dim; ++k) {
+                        if ((a >> k) & 1) continue;
+                        const int b = a | (1 << k);
+                        int64_t q[3] = {lf.o[0], lf.o[1], lf.o[2]};
+                        for (int t = 0; t < dim; ++t) q[t] += ((a >> t) & 1) * s;
+                        q[k] += s / 2;
+                        const int64_t n = node_of(key_of(q));
+                        if (n >= 0) out.push_back(Cand{n, 2, {cv[a], cv[b], 0, 0}, 0.5});
                     }
+                if (dim == 3) {
+                    for (int k = 0; k < 3; ++k)
+                        for (int side = 0; side < 2; ++side) {
+                            int64_t q[3] = {lf.o[0] + s / 2, lf.o[1] + s / 2, lf.o[2] + s / 2};
+                            q[k] = lf.o[k] + side * s;
+                            const int64_t n = node_of(key_of(q));
+                            if (n < 0) continue;
+                            Cand cd{n, 0, {0, 0, 0, 0}, 0.25};
+                            for (int a = 0; a < nv; ++a)
+                                if (((a >> k) & 1) == side) cd.mst[cd.nm++] = cv[a];
+                            out.push_back(cd);
+                        }
+                }
             }
-        }
+        });
+        for (const auto& v : cand)
+            for (const Cand& cd : v) {
+                if (is_hang[size_t(cd.n)]) continue;
+                std::vector<std::pair<int64_t, double>> ms;
+                for (int j = 0; j < cd.nm; ++j) ms.push_back({cd.mst[j], cd.w});
+                set_hang(cd.n, std::move(ms));
+            }
         // resolve chains (a master that is itself hanging)
         for (int64_t n = 0; n < m.n_nodes; ++n) {
             if (!is_hang[size_t(n)]) continue;
