@@ -289,12 +289,22 @@ HostMesh build_mesh(const fr_mesh_desc& d, const RefineSeed* seed) {
                 }
             });
         }
-        // deterministic cell order: by lower corner (z, y, x), then level
-        std::sort(leaves.begin(), leaves.end(), [&](const Leaf& a, const Leaf& b) {
-            for (int k = dim - 1; k >= 0; --k)
-                if (a.o[k] != b.o[k]) return a.o[k] < b.o[k];
-            return a.level < b.level;
-        });
+        // deterministic cell order: by lower corner (z, y, x).  Leaves do not overlap, so no two
+        // share a lower corner, and the packed corner (z in the high bits) orders them.
+        {
+            std::vector<uint64_t> lk(leaves.size());
+            std::vector<uint32_t> li(leaves.size());
+            for (size_t i = 0; i < leaves.size(); ++i) {
+                lk[i] = pack(leaves[i].o);
+                li[i] = uint32_t(i);
+            }
+            radix_sort_pairs(lk, li);
+            for (size_t i = 1; i < lk.size(); ++i)
+                if (lk[i] == lk[i - 1]) fail(FR_EINTERNAL, "mesh: two leaves share a lower corner");
+            std::vector<Leaf> sorted(leaves.size());
+            for (size_t i = 0; i < leaves.size(); ++i) sorted[i] = leaves[li[i]];
+            leaves.swap(sorted);
+        }
     }
 
     // ---- nodes and cells ------------------------------------------------------------
