@@ -15,7 +15,13 @@ convergence_3d(): Section 4.3, the TCV of the 3d penny crack (l0 = 1, 10 x 10 x 
 adaptive meshes whose finest edge is 10 l0 / 2^ref, with eps = 2 x the finest cell's diameter
 (the eps column of the Fig. 3 table), against Sneddon's 5.12E-03.
 
-Run as `python -m paper_1806_09924_amd.studies [domain|cod|3d] [64|32]` (prints one JSON object).
+loading_refinement(): the algorithm around the Newton solve (Section 3) on one Sneddon mesh: a
+loading step at half the load, crack-region and gradient-jump marks, refinement, transfer of u,
+phi and the previous phase field, and the step at the full load on the refined mesh, each stage
+timed.
+
+Run as `python -m paper_1806_09924_amd.studies [domain|cod|3d|refine] [64|32]` (prints one JSON
+object).
 """
 import json
 import sys
@@ -196,10 +202,70 @@ def convergence_3d(refs=(7, 8, 9), refine_radius=0.4, precision=32, rtol=1e-8):
                 t_newton=t_newton, n_dofs=int(4 * mesh.n_nodes))
 
 
+def loading_refinement(n=2048, L=10.0, l0=0.25, kelly_fraction=0.01, precision=64):
+    """Two loading steps (p/2, then p) on the n x n Sneddon mesh with one refinement between them:
+    crack-region marks (phi < 1/2 on cells coarser than h/2) and the cells in the top
+    `kelly_fraction` of the gradient-jump indicator are split.  Returns per-stage seconds, the
+    Newton / FGMRES counts and TCV of both steps, and the mesh sizes."""
+    from inputs import crack_band_phi   # the workload's initial crack field
+    dev = torch.device("cuda")
+
+    def now():
+        torch.cuda.synchronize()
+        return time.perf_counter()
+
+    out = {}
+    t0 = now()
+    m = B.Mesh(B.mesh_desc(2, -L, L, n))
+    out["t_mesh"] = now() - t0
+    h = 2 * L / n
+    eps = 2 * h
+    phi0 = torch.as_tensor(crack_band_phi(m.nodes()[0], l0, eps), device=dev)
+    u = torch.zeros((m.n_nodes, 2), dtype=torch.float64, device=dev)
+    phi = phi0.clone()
+    prm = [B.params(eps=eps, kappa=1e-10, p=5e-4), B.params(eps=eps, kappa=1e-10, p=1e-3)]
+    amg, so, no = B.amg_opts(precision=precision), B.solve_opts(rtol=1e-8), B.newton_opts(atol=1e-13)
+    t0 = now()
+    st1, tcv1 = B.loading(m, prm[:1], [0.0, 1.0], u, phi, amg=amg, solve=so, newton=no)
+    out["t_step1"] = now() - t0
+    eta = torch.empty(m.n_cells, dtype=torch.float64, device=dev)
+    t0 = now()
+    B.kelly(m, u, eta)
+    crack, n_crack = B.mark_crack(m, phi, 0.5, h / 2)
+    e = eta.cpu().numpy()
+    flags = crack | (e > np.quantile(e, 1.0 - kelly_fraction)).astype(np.uint8)
+    out["t_mark"] = now() - t0
+    t0 = now()
+    m2 = m.refine(flags)
+    out["t_refine"] = now() - t0
+    u2 = torch.empty((m2.n_nodes, 2), dtype=torch.float64, device=dev)
+    phi2 = torch.empty(m2.n_nodes, dtype=torch.float64, device=dev)
+    prev2 = torch.empty(m2.n_nodes, dtype=torch.float64, device=dev)
+    t0 = now()
+    B.transfer(m, m2, u, u2)
+    B.transfer(m, m2, phi, phi2)
+    B.transfer(m, m2, phi0, prev2)
+    out["t_transfer"] = now() - t0
+    t0 = now()
+    st2, tcv2 = B.loading(m2, prm[1:], [1.0, 2.0], u2, phi2, phi_prev=prev2, t_prev=0.0, amg=amg, solve=so,
+                          newton=no)
+    out["t_step2"] = now() - t0
+    for s_ in st1 + st2:
+        assert s_["status"] == 0, s_
+    out.update(cells=[m.n_cells, m2.n_cells], n_solve=[m.n_solve, m2.n_solve], hanging=m2.n_hanging,
+               marked=int(flags.sum()), crack_marked=int(n_crack),
+               newton=[st1[0]["iterations"], st2[0]["iterations"]],
+               fgmres=[st1[0]["linear_iters"], st2[0]["linear_iters"]], tcv=[float(tcv1[0]), float(tcv2[0])])
+    return out
+
+
 def main(argv=None):
     argv = list(argv or [])
-    which = argv.pop(0) if argv and argv[0] in ("domain", "cod", "3d") else "domain"
+    which = argv.pop(0) if argv and argv[0] in ("domain", "cod", "3d", "refine") else "domain"
     precision = int(argv[0]) if argv else 64
+    if which == "refine":
+        print(json.dumps(loading_refinement(precision=precision)))
+        return
     if which == "3d":
         print(json.dumps(convergence_3d(precision=precision)))
         return
