@@ -214,3 +214,15 @@ def test_refinement_and_transfer_at_full_size():
     _, t1 = B.functionals(m, u, phi)
     _, t2 = B.functionals(m2, u2, phi2)
     assert abs(t2 / t1 - 1) <= 1e-12
+
+
+def test_loading_refinement_study_runs_end_to_end():
+    """studies.loading_refinement on a 256 x 256 mesh: both steps converge, the marks include the
+    crack region, refinement adds cells and hanging nodes, and TCV grows with the load."""
+    from paper_1806_09924_amd import studies
+    out = studies.loading_refinement(n=256, L=2.0, l0=0.25, kelly_fraction=0.02)
+    assert out["cells"][1] > out["cells"][0] and out["hanging"] > 0
+    assert out["marked"] >= out["crack_marked"] > 0
+    assert out["n_solve"][1] > out["n_solve"][0]
+    assert 0 < out["tcv"][0] < out["tcv"][1]
+    assert all(v >= 0 for k, v in out.items() if k.startswith("t_"))
