@@ -759,21 +759,29 @@ Pattern build_pattern(const HostMesh& m, int C) {
     const int nv = m.nv;
     const int64_t nn = m.n_nodes, nf = m.n_free;
     p.n_rows = nf;
-    // node -> cells adjacency
+    // node -> cells adjacency, filled by host threads with atomic counters: the order of a
+    // node's list is arbitrary, and every row below sorts its entries by (cell, vertex), which
+    // are unique, so the pattern does not depend on it
     std::vector<int32_t> nc_ptr(size_t(nn) + 1, 0);
-    for (int64_t c = 0; c < m.n_cells; ++c)
-        for (int a = 0; a < nv; ++a) nc_ptr[size_t(m.cells[size_t(c) * nv + a]) + 1]++;
+    parallel_ranges(m.n_cells, [&](int64_t c0, int64_t c1, int) {
+        for (int64_t c = c0; c < c1; ++c)
+            for (int a = 0; a < nv; ++a)
+                __atomic_fetch_add(&nc_ptr[size_t(m.cells[size_t(c) * nv + a]) + 1], 1, __ATOMIC_RELAXED);
+    });
     for (int64_t n = 0; n < nn; ++n) nc_ptr[size_t(n) + 1] += nc_ptr[size_t(n)];
     const size_t n_inc = size_t(nc_ptr[size_t(nn)]);
     std::vector<int32_t> nc_cell(n_inc), nc_a(n_inc);
     {
         std::vector<int32_t> fill(nc_ptr.begin(), nc_ptr.end() - 1);
-        for (int64_t c = 0; c < m.n_cells; ++c)
-            for (int a = 0; a < nv; ++a) {
-                int32_t n = m.cells[size_t(c) * nv + a];
-                nc_cell[static_cast<size_t>(fill[size_t(n)])] = int32_t(c);
-                nc_a[static_cast<size_t>(fill[size_t(n)]++)] = a;
-            }
+        parallel_ranges(m.n_cells, [&](int64_t c0, int64_t c1, int) {
+            for (int64_t c = c0; c < c1; ++c)
+                for (int a = 0; a < nv; ++a) {
+                    const int32_t n = m.cells[size_t(c) * nv + a];
+                    const int32_t pos = __atomic_fetch_add(&fill[size_t(n)], 1, __ATOMIC_RELAXED);
+                    nc_cell[size_t(pos)] = int32_t(c);
+                    nc_a[size_t(pos)] = a;
+                }
+        });
     }
     // master -> hanging dependents
     std::vector<int32_t> dep_ptr(size_t(nf) + 1, 0);
@@ -875,14 +883,20 @@ Pattern build_pattern(const HostMesh& m, int C) {
     std::vector<Ent> ents(n_ent);
     std::vector<int32_t> col_all(static_cast<size_t>(col_ptr[static_cast<size_t>(nf)]));
     {
-        size_t eo = 0, co = 0;
-        for (Part& P : parts) {
-            std::copy(P.ents.begin(), P.ents.end(), ents.begin() + int64_t(eo));
-            std::copy(P.cols.begin(), P.cols.end(), col_all.begin() + int64_t(co));
-            eo += P.ents.size();
-            co += P.cols.size();
-            P = Part();
+        // every part's pieces go to known offsets: one host thread per part
+        std::vector<size_t> eo(parts.size() + 1, 0), co(parts.size() + 1, 0);
+        for (size_t t = 0; t < parts.size(); ++t) {
+            eo[t + 1] = eo[t] + parts[t].ents.size();
+            co[t + 1] = co[t] + parts[t].cols.size();
         }
+        std::vector<std::thread> th;
+        for (size_t t = 0; t < parts.size(); ++t)
+            th.emplace_back([&, t]() {
+                std::copy(parts[t].ents.begin(), parts[t].ents.end(), ents.begin() + int64_t(eo[t]));
+                std::copy(parts[t].cols.begin(), parts[t].cols.end(), col_all.begin() + int64_t(co[t]));
+                parts[t] = Part();
+            });
+        for (auto& x : th) x.join();
     }
     p.ent_cell.resize(n_ent);
     p.ent_a.resize(n_ent);
