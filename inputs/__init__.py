@@ -7,5 +7,7 @@ two sides see different problems.
 """
 from .sneddon import (Workload, WORKLOADS, crack_band_phi, random_state, batched_instances, domain_study,
                       cod_study)
+from .cycle import alternating_case, ALTERNATING_SEED
 
-__all__ = ["Workload", "WORKLOADS", "crack_band_phi", "random_state", "batched_instances", "domain_study", "cod_study"]
+__all__ = ["Workload", "WORKLOADS", "crack_band_phi", "random_state", "batched_instances", "domain_study", "cod_study",
+           "alternating_case", "ALTERNATING_SEED"]

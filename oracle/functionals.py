@@ -15,7 +15,7 @@ Closed forms (Section 4, Sneddon):
   2d: TCV = 2 pi p l0^2 (1-nu^2)/E,  u_n(x) = 2 p l0 (1-nu^2)/E sqrt(1 - (x/l0)^2)
   3d: TCV = 16 p l0^3 (1-nu^2)/(3E), u_n(rho) = (4/pi) p l0 (1-nu^2)/E sqrt(1 - (rho/l0)^2)
 
-Pinned by tests/test_oracle_functionals.py: exact values for Q1-representable fields
+Pinned by tests/test_oracle_basics.py: exact values for Q1-representable fields
 (u = e_0, phi linear in x_0 gives TCV = |B| / (hi - lo); COD of u = e_last, phi linear
 in the last axis), the paper's printed value 6.0319E-03 of the 2d closed form, the
 integral of 2 u_n reproducing TCV (2d and 3d).

@@ -4,8 +4,8 @@ The paper only names "Lame coefficients" mu_s, lambda_s and gives E=1, nu=0.2 (S
 Reading: the standard isotropic relations; in 2d the problem is plane strain, which is
 the setting in which Sneddon's forms carry the factor (1 - nu^2)/E (Section 4).
 
-Pinned by: tests/test_oracle_material.py (nu recovered from lambda/(2(lambda+mu)),
-E recovered from mu(3 lambda + 2 mu)/(lambda + mu)).
+Pinned by tests/test_oracle_basics.py (test_lame_relations: nu recovered from
+lambda/(2(lambda+mu)) and E from mu(3 lambda + 2 mu)/(lambda + mu); test_appendix_constants).
 """
 from dataclasses import dataclass
 

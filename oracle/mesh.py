@@ -15,8 +15,9 @@ A mesh is described by
 
 Uniform meshes number nodes lexicographically (x fastest), cells likewise.
 
-Pinned by: tests/test_oracle_mesh.py (Table 1 DoF counts 3 (2^(k+3)+1)^2, node and cell
-counts, vertex coordinates consistent with cell corners).
+Pinned by tests/test_oracle_basics.py (test_table1_dof_counts: the Table 1 DoF counts
+3 (2^(k+3)+1)^2; test_uniform_mesh_geometry: node and cell counts, vertex coordinates
+consistent with cell corners).
 """
 import numpy as np
 import scipy.sparse as sp

@@ -29,11 +29,17 @@ far from equilibrium, the absolute part a step that starts at it (a later loadin
 an unchanged load), whose R~(U^0) is already at rounding level.  R~ is R with fixed rows
 zeroed.  Cycle rule (the paper only says alternating indices are detected and
 constrained): a phi DoF whose membership flips twice within three consecutive iterates
-is frozen active for the rest of the loading step.
+is frozen active for the rest of the loading step.  Status at the iteration cap: "cycle"
+when the residual part of the stop test is met and only the active set still changes,
+else "noconv".
 
 Pinned by tests/test_oracle_newton.py: dense LU of the full masked J against the block
 forward substitution; KKT conditions at the Newton fixed point; brute-force enumeration of
-all active sets of the linearised problem on a tiny mesh.
+all active sets of the linearised problem on a tiny mesh; the cycle rule on every
+membership sequence of three iterates (only in-out-in and out-in-out freeze, frozen DoFs
+stay active), and on a seeded problem whose iterates alternate: without the rule the loop
+cycles to the cap with a converged residual, with it the two alternating DoFs are frozen and
+the loop stops.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -94,6 +100,20 @@ def mask_system(J, R, fixed, target):
     return Jm, F
 
 
+def alternating(a_before, a_prev, a_new):
+    """DoFs whose membership flips twice over three consecutive iterates: in, out, in or
+    out, in, out (the alternating active-set indices Section 3 detects)."""
+    return (a_before != a_prev) & (a_prev != a_new)
+
+
+def freeze(a_before, a_prev, a_new, frozen):
+    """Cycle rule of Section 3 (alternating indices are constrained): every alternating DoF
+    joins `frozen` for the rest of the loading step, and frozen DoFs are active.  Returns the
+    new (active, frozen) pair; the inputs are not modified."""
+    frozen = frozen | alternating(a_before, a_prev, a_new)
+    return a_new | frozen, frozen
+
+
 def masked_residual_norm(R, fixed):
     return float(np.linalg.norm(np.where(fixed, 0.0, R)))
 
@@ -133,8 +153,9 @@ def newton_step_system(mesh, prm, u, phi, phi_old, phi_tilde):
 
 
 def newton_loop(mesh, prm, u0, phi0, phi_old, phi_tilde, tol=1e-8, max_it=30,
-                linear_solve=None, ls_max=8, atol=0.0):
-    """Full Newton / active-set loop for one loading step (Section 3 algorithm)."""
+                linear_solve=None, ls_max=8, atol=0.0, freeze_cycles=True):
+    """Full Newton / active-set loop for one loading step (Section 3 algorithm).
+    freeze_cycles=False leaves the cycle rule out (the library's diagnostic option)."""
     if linear_solve is None:
         linear_solve = lambda Jm, F: solve_block(mesh, Jm, F)
     d = mesh.dim
@@ -173,19 +194,22 @@ def newton_loop(mesh, prm, u0, phi0, phi_old, phi_tilde, tol=1e-8, max_it=30,
         it += 1
         R, B = fem.residual(mesh, prm, u, phi, phi_tilde)
         new_active, _ = active_set(mesh, prm, R, B, phi, phi_old)
-        if len(history) >= 2:
-            a2, a1 = history[-2], history[-1]
-            flips = (a2 != a1) & (a1 != new_active)
-            frozen |= flips
-        new_active |= frozen
+        if freeze_cycles and len(history) >= 2:
+            new_active, frozen = freeze(history[-2], history[-1], new_active, frozen)
+        else:
+            new_active = new_active | frozen
         fixed, target = fixed_dofs(mesh, new_active, u, phi, phi_old)
         rn = masked_residual_norm(R, fixed)
         log.append(dict(it=it, omega=omega, res=rn, n_active=int(new_active.sum()),
                         changed=int((new_active != active).sum())))
         same = np.array_equal(new_active, active)
         active = new_active
-        if same and rn <= max(tol * r0, atol):
+        res_ok = rn <= max(tol * r0, atol)
+        if same and res_ok:
             converged = True
             break
+    # the iteration cap: a loop held back only by a still-changing active set is a cycle the
+    # freeze did not resolve, anything else is plain non-convergence
+    status = "ok" if converged else ("cycle" if res_ok else "noconv")
     return dict(u=u, phi=phi, U=U, active=active, iterations=it, converged=converged,
-                r0=r0, log=log, frozen=frozen)
+                r0=r0, res=rn if it else r0, log=log, frozen=frozen, status=status)

@@ -8,8 +8,8 @@ Vertex numbering: vertex a has bit k of a set when it sits at +1 along axis k
 (lexicographic, x fastest).  Gauss point q uses the same bit pattern for the sign of
 +-1/sqrt(3).
 
-Pinned by: tests/test_oracle_q1.py (partition of unity, nodal interpolation of linear
-functions, textbook mass and Laplacian element matrices).
+Pinned by tests/test_oracle_basics.py (test_partition_of_unity_and_linear_reproduction,
+test_textbook_mass_and_laplacian_2d / _3d: textbook mass and Laplacian element matrices).
 """
 import numpy as np
 

@@ -143,3 +143,57 @@ def test_sneddon_tcv_band_and_h_convergence():
         assert 0.5 < cod0 / ofun.sneddon_cod(2, 1e-3, 0.25, 1.0, 0.2, 1.0 / n) < 1.5
     assert 0.0 < errs[1] < 0.4
     assert abs(errs[1]) < 0.75 * abs(errs[0])
+
+
+def test_cycle_rule_on_membership_sequences():
+    """Section 3 constrains alternating active-set indices: of the eight membership
+    sequences over three iterates exactly in-out-in and out-in-out alternate; frozen DoFs are
+    active from then on, whatever the later decisions."""
+    seqs = np.array(list(itertools.product([False, True], repeat=3)))
+    a0, a1, a2 = seqs[:, 0], seqs[:, 1], seqs[:, 2]
+    flagged = newton.alternating(a0, a1, a2)
+    expect = np.array([(x != y) and (y != z) for x, y, z in seqs])
+    assert flagged.sum() == 2
+    assert np.array_equal(flagged, expect)
+    assert set(map(tuple, seqs[flagged].astype(int))) == {(1, 0, 1), (0, 1, 0)}
+    none = np.zeros(8, dtype=bool)
+    act, frz = newton.freeze(a0, a1, a2, none)
+    assert np.array_equal(frz, flagged)
+    assert np.array_equal(act, a2 | flagged)          # out-in-out ends active, not inactive
+    assert act[np.where((seqs == [0, 1, 0]).all(1))[0][0]]
+    # a DoF frozen earlier stays frozen and active even when every later decision is "out"
+    earlier = np.zeros(8, dtype=bool)
+    earlier[0] = True                                  # the out-out-out sequence
+    act, frz = newton.freeze(a0, a1, a2, earlier)
+    assert frz[0] and act[0]
+    assert np.array_equal(frz, flagged | earlier)
+    # the inputs are left alone
+    assert not none.any()
+
+
+def _alternating_problem():
+    from inputs import alternating_case
+    c = alternating_case()
+    m = omesh.uniform(2, -c["L"], c["L"], c["n"])
+    assert np.array_equal(m.dirichlet, c["boundary"])
+    prm = Params(E=c["E"], nu=c["nu"], Gc=c["Gc"], kappa=c["kappa"], eps=c["eps"], p=c["p"])
+    return m, prm, c
+
+
+def test_cycle_rule_stops_an_alternating_active_set():
+    m, prm, c = _alternating_problem()
+    args = (m, prm, c["u0"], c["phi0"], c["phi_old"], c["phi_tilde"])
+    out = newton.newton_loop(*args, tol=1e-8, max_it=20)
+    assert out["status"] == "ok" and out["converged"]
+    assert out["iterations"] == 4
+    assert np.array_equal(np.nonzero(out["frozen"])[0], [0, 1])
+    assert out["active"][[0, 1]].all()
+    # without the rule the same loop alternates until the cap with a converged residual
+    raw = newton.newton_loop(*args, tol=1e-8, max_it=20, freeze_cycles=False)
+    assert raw["status"] == "cycle" and not raw["converged"]
+    assert raw["iterations"] == 20
+    assert raw["res"] <= 1e-8 * raw["r0"]
+    assert all(e["changed"] > 0 for e in raw["log"][-6:])
+    # a periodic orbit of the active set (period 3 here: DoFs 0 and 1 leave and re-enter)
+    acts = [e["n_active"] for e in raw["log"][-6:]]
+    assert acts[:3] == acts[3:] and len(set(acts)) == 3
