@@ -92,10 +92,10 @@ def counted_traffic(kernel):
     return float(t.group(1)) if cur and cur.startswith(h.group(3)) else None
 
 
-def cpu_baseline(n_cpu, L_full, n_full, iters_per_newton):
-    """The FP64 oracle (one exact Newton step: residual, active set, masked Jacobian, block
-    forward substitution by sparse LU) on a square of the benchmark mesh with the same h,
-    eps and crack, timed on this host."""
+def cpu_baseline(n_cpu, L_full, n_full):
+    """The FP64 oracle as it stands (one exact Newton step: residual, active set, masked Jacobian,
+    block forward substitution by sparse LU) on a square of the benchmark mesh with the same h,
+    eps and crack, timed on this host.  value = N_solve of the sample / seconds of the step."""
     import numpy as np
     from oracle import mesh as omesh, newton as onewton
     from oracle.material import Params as OParams
@@ -112,13 +112,18 @@ def cpu_baseline(n_cpu, L_full, n_full, iters_per_newton):
     t1, c1 = time.perf_counter(), time.process_time()
     wall = t1 - t0
     cores = max(1, int(round((c1 - c0) / wall)))
-    value = m.n_solve * iters_per_newton / wall / 1e6
-    return dict(value=value, unit="MDoF-iter/s", cores=cores, kind="oracle",
-                sample=(f"one exact Newton step (assembly + active set + masked Jacobian + sparse-LU block "
-                        f"forward substitution) on [-{L:g},{L:g}]^2 with {n_cpu}^2 cells, the benchmark's h, eps "
-                        f"and crack: N_solve={m.n_solve}, {wall:.2f} s; value = N_solve x the GPU's FGMRES "
-                        f"iterations per Newton step ({iters_per_newton:.1f}) / time"),
-                seconds=wall, n_solve=m.n_solve)
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return dict(value=m.n_solve / wall / 1e6, unit="MDoF/s (exact Newton steps)", cores=cores, kind="oracle",
+                nproc=os.cpu_count(), usable_cores=usable, seconds_per_newton_step=wall, n_solve=m.n_solve,
+                sample=(f"one exact Newton step (assembly + active set + masked Jacobian + sparse-LU block forward "
+                        f"substitution; numpy/scipy, SuperLU single-threaded) on [-{L:g},{L:g}]^2 with {n_cpu}^2 "
+                        f"cells, the benchmark's h, eps and crack: N_solve={m.n_solve}, {wall:.2f} s; value = "
+                        f"N_solve / seconds per exact Newton step (compare newton_step_mdof_per_s)"),
+                full_size=(f"not reached: the {n_full}^2 step (16x the sample's DoFs; sparse-LU fill grows faster "
+                           f"than the DoFs) is not attempted within the bench's few-minute budget"))
 
 
 def stream_ceiling(dev, nbytes=2 << 30, reps=10):
@@ -203,7 +208,9 @@ def main():
 
     # the timed run records no events; the per-kernel table comes from a second, profiled run
     wall, stats, _ = run(64, args.steps, args.warmup, False)
-    prof = {} if args.no_profile else run(64, args.steps, 0, True)[2]
+    prof, pstats = {}, []
+    if not args.no_profile:
+        _, pstats, prof = run(64, args.steps, 0, True)
     iters = sum(s["linear_iters"] for s in stats)
     t_solve = sum(s["t_solve"] for s in stats)
     newton_its = sum(s["iterations"] for s in stats)
@@ -224,6 +231,9 @@ def main():
         # iteration-count independent: DoFs brought to the converged Newton solution per second
         # (a better preconditioner lowers MDoF-iter/s while it shortens the loop)
         "loop_mdof_per_s": mesh.n_solve * args.steps / wall / 1e6,
+        # N_solve per second of Newton steps (assembly, setup, solve, line search): the unit of
+        # the oracle's cpu_baseline
+        "newton_step_mdof_per_s": mesh.n_solve * newton_its / wall / 1e6,
         "phase_seconds_per_step": {k: sum(s[k] for s in stats) / args.steps
                                    for k in ("t_assemble", "t_setup", "t_solve", "t_other")},
         "tcv": tcv, "tcv_sneddon": tcv_exact, "tcv_rel_err_vs_sneddon": tcv / tcv_exact - 1,
@@ -239,6 +249,24 @@ def main():
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": counted_traffic(dom),
                            "bytes_per_launch": bytes_per, "avg_launch_ms": avg_ms, "launches": d["launches"]}
+        # the whole FGMRES iteration and the V-cycle pair: algorithmic bytes of every solve-phase
+        # kernel (smoothers, transfers and coarse products of both hierarchies; J-SpMV;
+        # Gram-Schmidt) per iteration of the profiled run, over the timed run's FGMRES time per
+        # iteration and over the V-cycle window (the two cycles run on two streams at once: the
+        # longer of the two per-cycle times)
+        p_iters = sum(s_["linear_iters"] for s_ in pstats)
+        vc_names = [k for k in kern if k.startswith(("cheb_", "spmv_"))]
+        vc_bytes = sum(kern[k]["bytes"] for k in vc_names) / p_iters
+        it_bytes = sum(v["bytes"] for v in kern.values()) / p_iters
+        vc_ms = max(prof[k]["ms"] / prof[k]["launches"] for k in ("vcycle_u", "vcycle_phi") if k in prof)
+        it_ms = 1e3 * t_solve / iters
+        out["roofline"]["vcycle"] = {"bytes_per_iteration": vc_bytes, "ms_per_iteration": vc_ms,
+                                     "achieved": vc_bytes / (vc_ms * 1e-3) / 1e9,
+                                     "frac": vc_bytes / (vc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                     "kernels": sorted(vc_names)}
+        out["roofline"]["iteration"] = {"bytes_per_iteration": it_bytes, "ms_per_iteration": it_ms,
+                                        "achieved": it_bytes / (it_ms * 1e-3) / 1e9,
+                                        "frac": it_bytes / (it_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         # what this device's HBM sustains for plain streams (context for frac; peak stays the
         # published 8 TB/s)
         out["roofline"]["measured_ceiling"] = stream_ceiling(dev)
@@ -286,7 +314,7 @@ def main():
         out["copy_calibration_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
     if not args.no_cpu:
         log("oracle timing on the host")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_n, L, n, out["fgmres_iterations_per_newton"])
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, L, n)
     print(json.dumps(out), flush=True)
 
 

@@ -58,7 +58,8 @@ typedef struct fr_amg_s* fr_amg;
  * levels = 0: uniform mesh of base[0] x ... cells. levels > 0: every cell whose box comes
  * within refine_radius of the crack (2d: segment |x - c_x| <= crack_half_len on the line
  * y = c_y; 3d: disk of radius crack_half_len in the plane z = c_z) is split, `levels`
- * times, followed by 2:1 balancing across faces (Section 3 adaptive meshes). */
+ * times, followed by 2:1 balancing: cells that share a point (a vertex, edge or face) differ by
+ * at most one level (Section 3 adaptive meshes). */
 typedef struct {
     int dim;                 /* 2 or 3 */
     double lo[3], hi[3];
@@ -129,6 +130,9 @@ typedef struct {
     double atol;         /* absolute floor of the stop test (>= 0; the algorithm of Section 3 states
                             an absolute TOL): a loading step that starts at equilibrium has
                             ||R~(U0)|| at rounding level, which the relative part cannot undercut */
+    int no_cycle_freeze; /* nonzero leaves out the cycle rule (a diagnostic: Section 3 detects and
+                            constrains alternating active-set indices; with this set a loop whose
+                            active set alternates runs to max_it and returns FR_ECYCLE) */
 } fr_newton_opts;
 
 typedef struct {
@@ -136,8 +140,11 @@ typedef struct {
     int linear_iters;    /* sum of FGMRES iterations */
     double res0, res;    /* ||R~(U0)|| and ||R~|| at exit */
     int64_t n_active;    /* active phi DoFs at exit */
-    int status;
+    int status;          /* fr_status of this instance (see fracture_newton) */
     double t_assemble, t_setup, t_solve, t_other;  /* seconds, HIP-event timed */
+    int64_t n_frozen;    /* phi DoFs frozen active by the cycle rule */
+    int linear_noconv;   /* Newton iterations whose FGMRES solve stopped at maxit above rtol */
+    int linear_status;   /* worst fr_solve_stats.status of the instance's FGMRES solves */
 } fr_newton_stats;
 
 /* Flags of fracture_assemble. */
@@ -157,9 +164,12 @@ fr_status fracture_mesh_info(fr_mesh mesh, int64_t* n_nodes, int64_t* n_cells, i
                              int64_t* n_all, int64_t* n_solve, int64_t* n_hanging,
                              double* h_min, int64_t* nnz_node_graph);
 
-/* Host outputs: xyz[n_nodes*dim] node coordinates; lattice (nullable) integer coordinates
- * in units of the finest cell edge; dirichlet (nullable) 1 for boundary nodes;
- * free_index (nullable) solve-order node index or -1 for hanging nodes. */
+/* The nodes of the Q1 space of Section 3 (cell vertices of the uniform or adaptive mesh; the
+ * initial crack of Section 4 and every nodal field are given at them). Host outputs:
+ * xyz[n_nodes*dim] node coordinates; lattice (nullable) integer coordinates
+ * in units of the finest cell edge; dirichlet (nullable) 1 for boundary nodes (u = 0 on the
+ * outer boundary, Section 2); free_index (nullable) solve-order node index or -1 for hanging
+ * nodes. */
 fr_status fracture_mesh_nodes(fr_mesh mesh, double* xyz, int64_t* lattice, uint8_t* dirichlet,
                               int32_t* free_index);
 
@@ -251,11 +261,13 @@ fr_status fracture_assemble(fr_mesh mesh, const fr_params* prm /*host*/, const d
                             const double* phi, const double* phi_old, const double* phi_tilde,
                             unsigned flags, fr_system* sys, void* stream);
 
-/* Host outputs: norms[0] = ||R~||_2 (R with Dirichlet u rows and active phi rows
- * zeroed), norms[1] = ||F||_2 (masked right-hand side, if assembled);
+/* The quantities of the stop test of the Section 3 algorithm (active set unchanged and the
+ * residual below TOL). Host outputs: norms[0] = ||R~||_2 (R with Dirichlet u rows and active
+ * phi rows zeroed), norms[1] = ||F||_2 (masked right-hand side, if assembled);
  * n_active = |A|; active_changes = entries that changed in the last FR_ACTIVE_SET;
  * min_margin = min_i |lambda_i + c(phi_i - phi_old,i) - tau| (distance of the closest
- * decision to the threshold). Synchronises `stream`. Any pointer may be NULL. */
+ * decision to the threshold). Synchronises `stream`. Any pointer may be NULL. Returns
+ * FR_ENAN (outputs still written) when a norm is not finite. */
 fr_status fracture_residual_norms(fr_system sys, double* norms, int64_t* n_active,
                                   int64_t* active_changes, double* min_margin, void* stream);
 
@@ -285,7 +297,8 @@ void fracture_system_destroy(fr_system sys);
  * Jacobian (strength graph, MIS-2 aggregation, tentative prolongator from the rigid-body
  * modes (u) or constants (phi), damped-Jacobi prolongator smoothing, Galerkin R A P),
  * Chebyshev smoothers and a dense coarsest-level inverse. *amg == NULL creates it,
- * otherwise it is rebuilt in place. The host synchronises `stream` between levels. */
+ * otherwise it is rebuilt in place. The host synchronises `stream` between levels.
+ * FR_ENAN (nothing built) when the Jacobian or F holds a non-finite value. */
 fr_status amg_setup(fr_system sys, const fr_amg_opts* opts /*host*/, fr_amg* amg, void* stream);
 
 /* Host outputs for hierarchy `block` (0 = u, 1 = phi): number of levels, and for level
@@ -313,11 +326,17 @@ fr_status amg_apply(fr_amg amg, const double* r, double* z, void* stream);
 
 void amg_destroy(fr_amg amg);
 
-/* Solves J du = F (masked system) by FGMRES with the AMG preconditioner. du: device,
+/* Solves J du = F (masked system): the linear solve of Section 3 ("Linear iterative
+ * solution": GMRES preconditioned by the block-diagonal P^-1, one AMG V-cycle per block) as
+ * right-preconditioned restarted FGMRES from du = 0, to the true FP64 relative residual
+ * ||F - J du|| <= rtol ||F|| (1e-8, the tolerance of the solver study of Table 1). du: device,
  * n_solve. stats: host, one per instance (nullable); each instance stops on its own
  * relative residual, the return value is the worst instance status. Synchronises `stream`
- * once per iteration (one flag per instance). FR_ENOCONV is returned with du and stats
- * filled when maxit is reached. */
+ * once per iteration (one flag per instance). Statuses: FR_ENOCONV with du and stats filled
+ * (the last iterate) when maxit is reached; FR_ENAN when F (or the iterate) is not finite;
+ * FR_EBREAKDOWN when the Arnoldi process yields a non-finite value from finite inputs (e.g. an
+ * FP32 hierarchy whose values overflow), or a zero Arnoldi norm while the true residual is
+ * still above the target: the instance stops and du keeps the update of the finite columns. */
 fr_status fracture_solve(fr_system sys, fr_amg amg, const fr_solve_opts* opts /*host*/,
                          double* du, fr_solve_stats* stats, void* stream);
 
@@ -326,15 +345,31 @@ fr_status fracture_update(fr_mesh mesh, const double* du, double omega, double* 
                           void* stream);
 
 /* The Newton / active-set loop of one loading step (Section 3 algorithm): assemble,
- * active set, masked Jacobian, AMG setup, FGMRES, line search, stop test, with the cycle
- * freeze of alternating active-set entries. The line search scales the update of the DoFs that
+ * active set, masked Jacobian, AMG setup, FGMRES, line search, stop test (active set unchanged
+ * and ||R~|| <= max(tol ||R~(U0)||, atol)), with the cycle rule of Section 3 (detect and
+ * constrain alternating active-set indices): from the third iterate on, a phi DoF whose
+ * membership flipped twice over three consecutive iterates (in-out-in or out-in-out) is frozen
+ * active for the rest of the call. The line search scales the update of the DoFs that
  * are not fixed; the fixed ones take their constraint values (Dirichlet u 0, active phi
  * phi_old), so that the loop never stops with an active DoF off phi_old. u and phi are updated in place (device).
  * amg_opts / solve_opts / newton_opts / stats: host. prm and stats hold one entry per
  * instance: on a batched mesh all instances iterate together (one assembly, setup and solve
  * per iteration), each with its own line search and stop test; a finished instance takes no
- * further update, and the loop ends when every instance has finished or max_it is reached
- * (the return value is then the worst instance status). Timings are for the whole call.
+ * further update, and the loop ends when every instance has finished or failed, or max_it is
+ * reached. Status per instance (stats[i].status; the return value is the worst of them, in
+ * the order FR_OK < FR_ENOCONV < FR_ECYCLE < FR_EBREAKDOWN < FR_ENAN):
+ *   FR_OK        the stop test was met and every FGMRES solve reached rtol;
+ *   FR_ENOCONV   max_it reached with ||R~|| above the stop test, or the stop test met while
+ *                some FGMRES solve stopped at maxit above rtol (stats.linear_noconv counts
+ *                them; each such step was still taken, guarded by the line search);
+ *   FR_ECYCLE    max_it reached with the residual part of the stop test met and only the
+ *                active set still changing (the cycle rule did not settle it);
+ *   FR_EBREAKDOWN an FGMRES breakdown; the instance stops with the state before that step;
+ *   FR_ENAN      a non-finite residual (e.g. non-finite input); no Jacobian, preconditioner or
+ *                solve is built from it. On a batch only that instance stops (its u and phi
+ *                are left as they are); its rows are set to identity rows with zero right-hand
+ *                side, so the other instances go on unaffected.
+ * Outputs (u, phi, stats) always hold the last iterate. Timings are for the whole call.
  * The working storage (system, preconditioner, Krylov bases) stays with the mesh for the
  * next call, which recomputes all of it; calls on one mesh run one at a time. It is freed
  * by fracture_mesh_destroy, or by a call on another stream (the first stream must stay
@@ -344,6 +379,12 @@ fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double*
                           const fr_amg_opts* amg_opts, const fr_solve_opts* solve_opts,
                           const fr_newton_opts* newton_opts, fr_newton_stats* stats,
                           void* stream);
+
+/* Device copies of the active set and of the DoFs frozen by the cycle rule at the end of the
+ * last fracture_newton (or fracture_loading step) on this mesh: active, frozen: device
+ * [n_free] bytes of 0/1 (either may be NULL). FR_EINVAL before any Newton loop ran on the
+ * mesh. Enqueued on `stream` (the loop's stream or one ordered after it). */
+fr_status fracture_newton_masks(fr_mesh mesh, uint8_t* active, uint8_t* frozen, void* stream);
 
 /* ---- loading steps (Formulation 1, steps n = 1, 2, 3, ...) ------------------------ */
 
@@ -400,6 +441,20 @@ fr_status fracture_profile(int enable);
 fr_status fracture_profile_read(int i, const char** name, int64_t* launches, double* ms, double* bytes);
 
 /* ---- misc ------------------------------------------------------------------------- */
+
+/* Device memory from the caller's allocator (e.g. a PyTorch caching allocator): every device
+ * allocation the library makes after this call goes through alloc(bytes, device, stream, ctx),
+ * which returns a device pointer of at least `bytes` bytes usable in stream order on `stream`
+ * (NULL: the call fails with FR_ENOMEM), and the block goes back through
+ * dealloc(ptr, bytes, device, stream, ctx) when the library frees it, with the stream its last
+ * use was ordered on (the stream it was allocated on). Blocks from the caller's allocator are not
+ * cached by the library. Both NULL restores the library's own pool. Blocks remember the allocator
+ * that made them, so objects created before a change stay valid; the functions and ctx must stay
+ * callable until every block they made is freed. Both must be thread safe (the library may
+ * allocate from two host threads during a setup). FR_EINVAL if exactly one is NULL. */
+typedef void* (*fr_alloc_fn)(size_t bytes, int device, void* stream, void* ctx);
+typedef void (*fr_free_fn)(void* ptr, size_t bytes, int device, void* stream, void* ctx);
+fr_status fracture_set_allocator(fr_alloc_fn alloc, fr_free_fn dealloc, void* ctx);
 
 /* Device memory of every object comes from a stream-ordered pool per device, and memory an
  * object gives up is cached for later allocations on the same stream (repeated calls of

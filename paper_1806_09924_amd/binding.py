@@ -50,14 +50,15 @@ class SolveStats(ctypes.Structure):
 
 class NewtonOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_it", ctypes.c_int), ("ls_max", ctypes.c_int),
-                ("atol", ctypes.c_double)]
+                ("atol", ctypes.c_double), ("no_cycle_freeze", ctypes.c_int)]
 
 
 class NewtonStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("linear_iters", ctypes.c_int), ("res0", ctypes.c_double),
                 ("res", ctypes.c_double), ("n_active", ctypes.c_int64), ("status", ctypes.c_int),
                 ("t_assemble", ctypes.c_double), ("t_setup", ctypes.c_double), ("t_solve", ctypes.c_double),
-                ("t_other", ctypes.c_double)]
+                ("t_other", ctypes.c_double), ("n_frozen", ctypes.c_int64), ("linear_noconv", ctypes.c_int),
+                ("linear_status", ctypes.c_int)]
 
 
 class FractureError(RuntimeError):
@@ -69,6 +70,8 @@ class FractureError(RuntimeError):
 _P = ctypes.c_void_p
 _I64P = ctypes.POINTER(ctypes.c_int64)
 _DP = ctypes.POINTER(ctypes.c_double)
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p)
 
 _SIGNATURES = {
     "fracture_mesh_create": [ctypes.POINTER(MeshDesc), ctypes.POINTER(_P), _P],
@@ -101,6 +104,7 @@ _SIGNATURES = {
     "fracture_newton": [_P, ctypes.POINTER(Params), _P, _P, _P, _P, ctypes.POINTER(AmgOpts),
                         ctypes.POINTER(SolveOpts), ctypes.POINTER(NewtonOpts), ctypes.POINTER(NewtonStats), _P],
     "fracture_extrapolate": [_P, _P, _P, ctypes.c_double, _P, _P],
+    "fracture_newton_masks": [_P, _P, _P, _P],
     "fracture_mesh_refine": [_P, _P, ctypes.POINTER(_P), _P],
     "fracture_transfer": [_P, _P, _P, ctypes.c_int, _P, _P],
     "fracture_mark_crack": [_P, _P, ctypes.c_double, ctypes.c_double, _P, _I64P, _P],
@@ -115,6 +119,7 @@ _SIGNATURES = {
     "fracture_last_error": [],
     "fracture_device_check": [],
     "fracture_trim_pool": [],
+    "fracture_set_allocator": [_ALLOC_FN, _FREE_FN, _P],
     "fracture_version": [],
 }
 _VOID = {"fracture_mesh_destroy", "fracture_system_destroy", "amg_destroy"}
@@ -177,8 +182,12 @@ def solve_opts(rtol=1e-8, restart=100, maxit=500, use_graphs=1):
     return SolveOpts(rtol, restart, maxit, use_graphs)
 
 
-def newton_opts(tol=1e-8, max_it=30, ls_max=8, atol=0.0):
-    return NewtonOpts(tol, max_it, ls_max, atol)
+def newton_opts(tol=1e-8, max_it=30, ls_max=8, atol=0.0, no_cycle_freeze=0):
+    return NewtonOpts(tol, max_it, ls_max, atol, no_cycle_freeze)
+
+
+# statuses of a solve or Newton loop that leave valid outputs (the last iterate) behind
+SOLVER_STATUSES = (FR_ENOCONV, FR_ECYCLE, FR_EBREAKDOWN, FR_ENAN)
 
 
 def mesh_desc(dim, lo, hi, base, levels=0, refine_radius=0.0, crack_center=(0.0, 0.0, 0.0), crack_half_len=0.0):
@@ -421,13 +430,15 @@ class Amg:
             self.h = None
 
 
-def solve(system, amg, du, opts=None, raise_on_noconv=True):
-    """FGMRES; returns the stats dict (a list of them for a batched mesh)."""
+def solve(system, amg, du, opts=None, raise_on_noconv=True, raise_on_status=True):
+    """FGMRES; returns the stats dict (a list of them for a batched mesh).  raise_on_status=False
+    returns the stats (with their status) for every solver status instead of raising."""
     ni = system.mesh.n_inst
     st = (SolveStats * ni)()
     o = opts if opts is not None else solve_opts()
     status = load().fracture_solve(system.h, amg.h, ctypes.byref(o), _ptr(du), st, _stream())
-    if status != FR_OK and (raise_on_noconv or status != FR_ENOCONV):
+    quiet = (not raise_on_status and status in SOLVER_STATUSES) or (not raise_on_noconv and status == FR_ENOCONV)
+    if status != FR_OK and not quiet:
         raise FractureError(status, last_error())
     out = [dict(iters=s.iters, relres=s.relres, status=s.status) for s in st]
     return out[0] if ni == 1 else out
@@ -437,9 +448,11 @@ def update(mesh, du, omega, u, phi):
     _check(load().fracture_update(mesh.h, _ptr(du), float(omega), _ptr(u), _ptr(phi), _stream()))
 
 
-def newton(mesh, prm, u, phi, phi_old, phi_tilde, amg=None, solve=None, newton=None, raise_on_noconv=True):
+def newton(mesh, prm, u, phi, phi_old, phi_tilde, amg=None, solve=None, newton=None, raise_on_noconv=True,
+           raise_on_status=True):
     """Newton / active-set loop; prm: one Params, or a list of one per instance of a batched
-    mesh.  Returns the stats dict (a list of them for a batched mesh)."""
+    mesh.  Returns the stats dict (a list of them for a batched mesh).  raise_on_status=False
+    returns the stats for every solver status (FR_ENOCONV, FR_ECYCLE, FR_EBREAKDOWN, FR_ENAN)."""
     ni = mesh.n_inst
     plist = list(prm) if isinstance(prm, (list, tuple)) else [prm]
     if len(plist) != ni:
@@ -451,10 +464,19 @@ def newton(mesh, prm, u, phi, phi_old, phi_tilde, amg=None, solve=None, newton=N
                                     ctypes.byref(solve if solve is not None else solve_opts()),
                                     ctypes.byref(newton if newton is not None else newton_opts()),
                                     st, _stream())
-    if status != FR_OK and (raise_on_noconv or status != FR_ENOCONV):
+    quiet = (not raise_on_status and status in SOLVER_STATUSES) or (not raise_on_noconv and status == FR_ENOCONV)
+    if status != FR_OK and not quiet:
         raise FractureError(status, last_error())
     out = [{f: getattr(x, f) for f, _ in NewtonStats._fields_} for x in st]
     return out[0] if ni == 1 else out
+
+
+def newton_masks(mesh):
+    """(active, frozen): uint8 device tensors [n_free] of the last Newton loop on the mesh."""
+    act = torch.empty(mesh.n_free, dtype=torch.uint8, device="cuda")
+    frz = torch.empty(mesh.n_free, dtype=torch.uint8, device="cuda")
+    _check(load().fracture_newton_masks(mesh.h, _ptr(act, torch.uint8), _ptr(frz, torch.uint8), _stream()))
+    return act, frz
 
 
 def extrapolate(mesh, phi1, phi2, w, out):
@@ -508,6 +530,32 @@ def functionals(mesh, u, phi, cod_x=()):
     if ni == 1:
         return cod[:n], float(tcv[0])
     return cod[:ni * n].reshape(ni, n), tcv
+
+
+def _torch_alloc(nbytes, device, stream, ctx):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), int(device), int(stream or 0))
+    except Exception:   # out of memory: the library reports FR_ENOMEM
+        return None
+
+
+def _torch_free(ptr, nbytes, device, stream, ctx):
+    torch.cuda.caching_allocator_delete(ptr)
+
+
+# kept alive for the life of the process: blocks made through them may outlive any setting
+_TORCH_HOOKS = (_ALLOC_FN(_torch_alloc), _FREE_FN(_torch_free))
+
+
+def set_allocator(kind):
+    """kind="torch": the library's device memory comes from PyTorch's caching allocator (on the
+    stream of each allocation); kind=None: the library's own pool again."""
+    if kind == "torch":
+        _check(load().fracture_set_allocator(_TORCH_HOOKS[0], _TORCH_HOOKS[1], None))
+    elif kind is None:
+        _check(load().fracture_set_allocator(_ALLOC_FN(), _FREE_FN(), None))
+    else:
+        raise ValueError("kind must be 'torch' or None")
 
 
 def trim_pool():

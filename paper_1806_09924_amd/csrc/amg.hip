@@ -1405,7 +1405,7 @@ BMat<double> transpose(const BMat<double>& P, hipStream_t s) {
 // enqueues the steps on a stream and power_finish waits for the estimate, so that other work
 // can run in between (the buffers live in the PowerEst until then).
 struct PowerEst {
-    DBuf<double> v[2], zero, scr_x, scr, nrm;
+    DBuf<double> v[2], scr, nrm;
     int64_t n = 0;
     hipStream_t st = nullptr;
 };
@@ -1417,16 +1417,13 @@ void power_start(PowerEst& pe, const BMat<double>& A, const double* invd, hipStr
     if (n == 0) return;
     pe.v[0].alloc(size_t(n), s);
     pe.v[1].alloc(size_t(n), s);
-    pe.zero.alloc(size_t(n), s);
-    pe.scr_x.alloc(size_t(n), s);
     pe.scr.alloc(1024, s);
     pe.nrm.alloc(2, s);
-    pe.zero.zero(s);
     k_power_init<<<nblk(n, 256), 256, 0, s>>>(n, pe.v[0].p);
     FR_LAUNCH_CHECK();
     const int iters = 10;
     for (int it = 0; it < iters; ++it)
-        diag_scaled_matvec(A, invd, pe.v[it & 1].p, pe.zero.p, pe.v[(it + 1) & 1].p, pe.scr_x.p, s);
+        diag_scaled_matvec(A, invd, pe.v[it & 1].p, pe.v[(it + 1) & 1].p, s);
     dev_dot(pe.v[iters & 1].p, pe.v[iters & 1].p, n, pe.nrm.p, pe.scr, s);
     dev_dot(pe.v[(iters - 1) & 1].p, pe.v[(iters - 1) & 1].p, n, pe.nrm.p + 1, pe.scr, s);
 }

@@ -679,7 +679,9 @@ __global__ void k_update_free_inst(int64_t nf, int D, const int32_t* __restrict_
                                    double* __restrict__ phi) {
     const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (f >= nf) return;
-    update_node(f, nf, D, node_of_free[f], du, omega[inst_of_free[f]], fix, u, phi);
+    const double w = omega[inst_of_free[f]];
+    if (w == 0.0) return;   // finished or failed instance: left exactly as it is
+    update_node(f, nf, D, node_of_free[f], du, w, fix, u, phi);
 }
 
 __global__ void k_update_free(int64_t nf, int D, const int32_t* __restrict__ node_of_free,
@@ -838,6 +840,57 @@ __global__ void k_sum_rows(const double* __restrict__ part, int64_t n_part, int 
     for (int64_t i = threadIdx.x; i < n_part; i += blockDim.x) acc += part[int64_t(r) * stride_row + i * stride_elem];
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) out[r] = s;
+}
+
+// ---- failed instances of a batch, flag counts, finiteness -----------------------------------
+// Rows of the instances flagged in `bad` become identity rows with a zero right-hand side (and
+// residual), so that their non-finite values stay out of the preconditioner and the solve of
+// the other instances (which never couple to them); their increment is then zero.
+template <int D>
+__global__ void __launch_bounds__(256) k_neutralize(int64_t nf, const int32_t* __restrict__ inst_of_free,
+                                                    const int* __restrict__ bad, const int32_t* __restrict__ slice_ptr,
+                                                    const int32_t* __restrict__ row_len, const int32_t* __restrict__ col,
+                                                    int C, double* __restrict__ Juu, double* __restrict__ Jpu,
+                                                    double* __restrict__ Jpp, double* __restrict__ F,
+                                                    double* __restrict__ R) {
+    const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (f >= nf || !bad[inst_of_free[f]]) return;
+    const int64_t base = int64_t(slice_ptr[f / C]) + (f % C);
+    const int len = row_len[f];
+    for (int k = 0; k < len; ++k) {
+        const int64_t slot = base + int64_t(k) * C;
+        const double one = col[slot] == f ? 1.0 : 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+#pragma unroll
+            for (int b = 0; b < D; ++b) Juu[slot * D * D + a * D + b] = a == b ? one : 0.0;
+            Jpu[slot * D + a] = 0.0;
+        }
+        Jpp[slot] = one;
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        F[f * D + c] = 0.0;
+        R[f * D + c] = 0.0;
+    }
+    F[D * nf + f] = 0.0;
+    R[D * nf + f] = 0.0;
+}
+
+// cnt[instance] += number of nonzero flags (cnt zeroed by the caller)
+__global__ void __launch_bounds__(256) k_count_flags(int64_t nf, const int32_t* __restrict__ inst_of_free,
+                                                     const uint8_t* __restrict__ flags,
+                                                     unsigned long long* __restrict__ cnt) {
+    const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (f < nf && flags[f]) atomicAdd(&cnt[inst_of_free ? inst_of_free[f] : 0], 1ull);
+}
+
+// *flag = 1 when any of x[0..n) is not finite (flag zeroed by the caller)
+__global__ void __launch_bounds__(256) k_nonfinite(const double* __restrict__ x, int64_t n, int* __restrict__ flag) {
+    bool bad = false;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        bad = bad || !isfinite(x[i]);
+    if (bad) atomicOr(flag, 1);
 }
 
 }  // namespace
@@ -1064,6 +1117,50 @@ void system_norms_inst(DevSystem& sys, std::vector<double>& rnorm, std::vector<i
         n_active[size_t(i)] = int64_t(part[size_t(3 * i + 1)] + 0.5);
         changes[size_t(i)] = int64_t(part[size_t(3 * i + 2)] + 0.5);
     }
+}
+
+void system_neutralize(DevSystem& sys, const int* bad_dev) {
+    DevMesh& m = *sys.mesh;
+    if (m.n_inst < 2) fail(FR_EINTERNAL, "system_neutralize: batched meshes only");
+    const SellStruct& S = *m.graph;
+    const int nb = blocks_for(m.n_free, 256);
+    const hipStream_t s = sys.stream;
+    if (m.dim == 2)
+        k_neutralize<2><<<nb, 256, 0, s>>>(m.n_free, m.inst_of_free.p, bad_dev, S.slice_ptr, S.row_len, S.col, S.C,
+                                           sys.Juu.val, sys.Jpu.val, sys.Jpp.val, sys.F.p, sys.R.p);
+    else
+        k_neutralize<3><<<nb, 256, 0, s>>>(m.n_free, m.inst_of_free.p, bad_dev, S.slice_ptr, S.row_len, S.col, S.C,
+                                           sys.Juu.val, sys.Jpu.val, sys.Jpp.val, sys.F.p, sys.R.p);
+    FR_LAUNCH_CHECK();
+}
+
+std::vector<int64_t> count_flags_inst(DevSystem& sys, const uint8_t* flags) {
+    DevMesh& m = *sys.mesh;
+    const hipStream_t s = sys.stream;
+    DBuf<unsigned long long> cnt;
+    cnt.alloc(size_t(m.n_inst), s);
+    cnt.zero(s);
+    k_count_flags<<<blocks_for(std::max<int64_t>(1, m.n_free), 256), 256, 0, s>>>(
+        m.n_free, m.n_inst > 1 ? m.inst_of_free.p : nullptr, flags, cnt.p);
+    FR_LAUNCH_CHECK();
+    auto h = download(cnt.p, size_t(m.n_inst), s);
+    return std::vector<int64_t>(h.begin(), h.end());
+}
+
+bool system_all_finite(const DevSystem& sys, hipStream_t s) {
+    DBuf<int> flag;
+    flag.alloc(1, s);
+    flag.zero(s);
+    const int64_t slots = sys.mesh->graph->n_slots;
+    const int D = sys.mesh->dim;
+    const struct { const double* p; int64_t n; } arrays[] = {
+        {sys.Juu.val, slots * D * D}, {sys.Jpu.val, slots * D}, {sys.Jpp.val, slots}, {sys.F.p, sys.n_solve}};
+    for (const auto& a : arrays) {
+        const int g = int(std::min<int64_t>(4096, std::max<int64_t>(1, blocks_for(a.n, 256))));
+        k_nonfinite<<<g, 256, 0, s>>>(a.p, a.n, flag.p);
+        FR_LAUNCH_CHECK();
+    }
+    return download1(flag.p, s) == 0;
 }
 
 void mesh_update_inst(DevMesh& m, const double* du, const double* omega, double* u, double* phi, hipStream_t s,

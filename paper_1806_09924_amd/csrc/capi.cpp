@@ -32,6 +32,7 @@ struct NewtonWork {
     fr_system_s S;
     fr_amg_s A;
     fr::DBuf<double> du, u_save, p_save;
+    bool ran = false;                            // a loop has run: S holds its final active set
 };
 
 struct fr_mesh_s {
@@ -203,6 +204,14 @@ fr_status fracture_profile_read(int i, const char** name, int64_t* launches, dou
 }
 
 const char* fracture_version(void) { return "fracture-gfx950 0.1"; }
+
+fr_status fracture_set_allocator(fr_alloc_fn alloc, fr_free_fn dealloc, void* ctx) {
+    FR_REQUIRE((alloc == nullptr) == (dealloc == nullptr), "set_allocator: give both functions or neither");
+    return guard([&]() {
+        fr::set_allocator(alloc, dealloc, ctx);
+        return FR_OK;
+    });
+}
 
 fr_status fracture_trim_pool(void) {
     return guard([&]() {
@@ -473,6 +482,8 @@ fr_status fracture_residual_norms(fr_system sys, double* norms, int64_t* n_activ
         fr::system_norms(sys->sys, nullptr, nullptr, nr, n_active, min_margin);
         if (norms) { norms[0] = nr[0]; norms[1] = nr[1]; }
         if (active_changes) *active_changes = sys->sys.last_changes;
+        if (!std::isfinite(nr[0]) || !std::isfinite(nr[1]))
+            return set_err(FR_ENAN, "residual_norms: non-finite residual or right-hand side");
         return FR_OK;
     });
 }
@@ -581,6 +592,9 @@ fr_status amg_setup(fr_system sys, const fr_amg_opts* opts, fr_amg* amg, void* s
     if (*amg && (*amg)->amg.sys && (*amg)->amg.sys != &sys->sys) return set_err(FR_EINVAL, "amg_setup: preconditioner belongs to another system");
     return guard([&]() {
         hipStream_t s = fr::as_stream(stream);
+        // a non-finite value would flow through the aggregation and the dense coarse inverse
+        if (!fr::system_all_finite(sys->sys, s))
+            return set_err(FR_ENAN, "amg_setup: the Jacobian or right-hand side holds a non-finite value");
         std::unique_ptr<fr_amg_s> created;
         fr_amg_s* A = *amg;
         if (!A) {
@@ -682,7 +696,8 @@ fr_status fracture_solve(fr_system sys, fr_amg amg, const fr_solve_opts* opts, d
     return guard([&]() {
         const fr_status r = fr::fgmres(sys->sys, amg->amg, *opts, du, stats, sys->kry, fr::as_stream(stream));
         if (r == FR_ENOCONV) set_err(r, "solve: iteration limit reached");
-        if (r == FR_ENAN) set_err(r, "solve: non-finite value in the Krylov iteration");
+        if (r == FR_ENAN) set_err(r, "solve: non-finite right-hand side or iterate");
+        if (r == FR_EBREAKDOWN) set_err(r, "solve: Krylov breakdown (non-finite or zero Arnoldi norm)");
         return r;
     });
 }
@@ -697,20 +712,36 @@ fr_status fracture_update(fr_mesh mesh, const double* du, double omega, double* 
     });
 }
 
+// Message of a failed Newton loop.
+static std::string newton_message(fr_status st, const char* who) {
+    const std::string w(who);
+    switch (st) {
+        case FR_ENOCONV: return "newton: " + w + " reached max_it above the stop test, or an FGMRES solve stopped at maxit";
+        case FR_ECYCLE: return "newton: " + w + " reached max_it with a converged residual and a still changing active set";
+        case FR_EBREAKDOWN: return "newton: FGMRES breakdown in " + w;
+        case FR_ENAN: return "newton: non-finite residual in " + w;
+        default: return "newton: failed";
+    }
+}
+
 // Newton / active-set loop over a batch of independent instances (one disjoint-union system):
 // every iteration assembles, sets up and solves all instances together; the line search
 // halves each instance's step on its own (omega_i from its own residual norm), and an
 // instance whose active set is unchanged and whose residual is below max(tol x its initial
-// one, atol) is finished: its later updates get omega = 0.  Runs until every instance has finished.
+// one, atol) is finished: its later updates get omega = 0.  An instance whose residual turns
+// non-finite, or whose linear solve breaks down, has failed: it takes no further step and its
+// rows are replaced by identity rows with zero right-hand side from then on, so that the
+// others go on unaffected.  Runs until every instance has finished or failed, or max_it.
 static fr_status newton_batch(NewtonWork& W, fr::DevMesh& m, const fr_params* prm, double* u, double* phi,
                               const double* phi_old, const double* phi_tilde, const fr_amg_opts& ao,
                               const fr_solve_opts& so, const fr_newton_opts& no, fr_newton_stats* stats,
                               hipStream_t s) {
     const int ni = m.n_inst;
+    const size_t nis = static_cast<size_t>(ni);
     fr_system_s* S = &W.S;
     system_init(*S, m, s);
     fr::DevSystem& sys = S->sys;
-    sys.prm_h.resize(size_t(ni));
+    sys.prm_h.resize(nis);
     for (int i = 0; i < ni; ++i) sys.prm_h[size_t(i)] = fr::make_params(prm[i]);
     sys.prm = sys.prm_h[0];
     sys.prm_d.upload(sys.prm_h, s);
@@ -720,13 +751,17 @@ static fr_status newton_batch(NewtonWork& W, fr::DevMesh& m, const fr_params* pr
     if (W.u_save.p == nullptr) W.u_save.alloc(size_t(nn) * m.dim, s);
     if (W.p_save.p == nullptr) W.p_save.alloc(size_t(nn), s);
     fr::DBuf<double> om_d;
-    om_d.alloc(size_t(ni), s);
-    std::vector<fr_newton_stats> ns(static_cast<size_t>(ni));
-    std::vector<fr_solve_stats> st(static_cast<size_t>(ni));
+    om_d.alloc(nis, s);
+    fr::DBuf<int> bad_d;
+    std::vector<fr_newton_stats> ns(nis);
+    std::vector<fr_solve_stats> st(nis);
     std::vector<double> r0, rk, nr;
     std::vector<int64_t> n_act, chg;
-    std::vector<char> done(static_cast<size_t>(ni), 0), ok(static_cast<size_t>(ni), 0);
-    std::vector<double> om(static_cast<size_t>(ni), 0.0);
+    std::vector<char> done(nis, 0), ok(nis, 0);
+    std::vector<fr_status> failed(nis, FR_OK), lin_worst(nis, FR_OK);
+    std::vector<int> lin_noconv(nis, 0);
+    std::vector<double> om(nis, 0.0);
+    auto live = [&](int i) { return !done[size_t(i)] && failed[size_t(i)] == FR_OK; };
     double t_asm = 0, t_setup = 0, t_solve = 0, t_other = 0;
     {
         EventTimer t(s);
@@ -736,13 +771,29 @@ static fr_status newton_batch(NewtonWork& W, fr::DevMesh& m, const fr_params* pr
     }
     fr::system_norms_inst(sys, r0, n_act, chg);
     rk = r0;
-    for (int i = 0; i < ni; ++i) ns[size_t(i)].res0 = r0[size_t(i)];
+    for (int i = 0; i < ni; ++i) {
+        ns[size_t(i)].res0 = r0[size_t(i)];
+        ns[size_t(i)].res = r0[size_t(i)];
+        ns[size_t(i)].n_active = n_act[size_t(i)];
+        if (!std::isfinite(r0[size_t(i)])) failed[size_t(i)] = FR_ENAN;
+    }
     int it = 0;
-    bool nan = false;
     while (it < no.max_it) {
+        bool any_live = false, any_failed = false;
+        for (int i = 0; i < ni; ++i) {
+            any_live = any_live || live(i);
+            any_failed = any_failed || failed[size_t(i)] != FR_OK;
+        }
+        if (!any_live) break;
         {
             EventTimer t(s);
             fr::assemble_jacobian(sys, u, phi, phi_old, phi_tilde);
+            if (any_failed) {
+                std::vector<int> bad(nis);
+                for (int i = 0; i < ni; ++i) bad[size_t(i)] = failed[size_t(i)] != FR_OK;
+                bad_d.upload(bad, s);
+                fr::system_neutralize(sys, bad_d.p);
+            }
             t_asm += t.stop();
         }
         {
@@ -755,16 +806,25 @@ static fr_status newton_batch(NewtonWork& W, fr::DevMesh& m, const fr_params* pr
         }
         {
             EventTimer t(s);
-            const fr_status r = fr::fgmres(sys, A->amg, so, W.du.p, st.data(), S->kry, s);
+            (void)fr::fgmres(sys, A->amg, so, W.du.p, st.data(), S->kry, s);
             t_solve += t.stop();
-            if (r == FR_ENAN) { nan = true; break; }
+        }
+        for (int i = 0; i < ni; ++i) {
+            if (!live(i)) continue;
+            const fr_status si = fr_status(st[size_t(i)].status);
+            ns[size_t(i)].linear_iters += st[size_t(i)].iters;
+            lin_worst[size_t(i)] = fr::worse_status(lin_worst[size_t(i)], si);
+            if (si == FR_ENAN || si == FR_EBREAKDOWN) failed[size_t(i)] = si;   // no step from this solve
+            else if (si == FR_ENOCONV) ++lin_noconv[size_t(i)];
         }
         EventTimer t(s);
         FR_HIP(hipMemcpyAsync(W.u_save.p, u, size_t(nn) * m.dim * 8, hipMemcpyDeviceToDevice, s));
         FR_HIP(hipMemcpyAsync(W.p_save.p, phi, size_t(nn) * 8, hipMemcpyDeviceToDevice, s));
+        std::vector<char> stepped(nis, 0);
         for (int i = 0; i < ni; ++i) {
-            ok[size_t(i)] = done[size_t(i)];
-            om[size_t(i)] = done[size_t(i)] ? 0.0 : 1.0;
+            stepped[size_t(i)] = live(i);
+            ok[size_t(i)] = !live(i);
+            om[size_t(i)] = live(i) ? 1.0 : 0.0;
         }
         for (int mm = 0; mm <= no.ls_max; ++mm) {
             for (int i = 0; i < ni; ++i)
@@ -785,41 +845,43 @@ static fr_status newton_batch(NewtonWork& W, fr::DevMesh& m, const fr_params* pr
             if (all) break;
         }
         ++it;
-        if (it >= 2) fr::assemble_active_freeze(sys, phi, phi_old);
+        if (it >= 2 && !no.no_cycle_freeze) fr::assemble_active_freeze(sys, phi, phi_old);
         else fr::assemble_active(sys, phi, phi_old);
         fr::system_norms_inst(sys, rk, n_act, chg);
         t_other += t.stop();
-        bool all = true;
         for (int i = 0; i < ni; ++i) {
             fr_newton_stats& q = ns[size_t(i)];
-            if (!std::isfinite(rk[size_t(i)])) nan = true;
-            if (!done[size_t(i)]) {
-                q.iterations = it;
-                q.linear_iters += st[size_t(i)].iters;
-                if (chg[size_t(i)] == 0 && rk[size_t(i)] <= std::max(no.tol * r0[size_t(i)], no.atol))
-                    done[size_t(i)] = 1;
-            }
+            if (!stepped[size_t(i)]) continue;
+            q.iterations = it;
             q.res = rk[size_t(i)];
             q.n_active = n_act[size_t(i)];
-            all = all && done[size_t(i)];
+            if (!std::isfinite(rk[size_t(i)])) failed[size_t(i)] = FR_ENAN;
+            else if (chg[size_t(i)] == 0 && rk[size_t(i)] <= std::max(no.tol * r0[size_t(i)], no.atol))
+                done[size_t(i)] = 1;
         }
-        if (nan || all) break;
     }
+    const std::vector<int64_t> nfz = it >= 2 ? fr::count_flags_inst(sys, sys.frozen.p) : std::vector<int64_t>(nis, 0);
     fr_status worst = FR_OK;
     for (int i = 0; i < ni; ++i) {
         fr_newton_stats& q = ns[size_t(i)];
-        q.status = nan ? FR_ENAN : (done[size_t(i)] ? FR_OK : FR_ENOCONV);
+        fr_status si;
+        if (failed[size_t(i)] != FR_OK) si = failed[size_t(i)];
+        else if (done[size_t(i)]) si = lin_noconv[size_t(i)] ? FR_ENOCONV : FR_OK;
+        else si = q.res <= std::max(no.tol * r0[size_t(i)], no.atol) ? FR_ECYCLE : FR_ENOCONV;
+        q.status = si;
+        q.n_frozen = nfz[size_t(i)];
+        q.linear_noconv = lin_noconv[size_t(i)];
+        q.linear_status = lin_worst[size_t(i)];
         q.t_assemble = t_asm;
         q.t_setup = t_setup;
         q.t_solve = t_solve;
         q.t_other = t_other;
-        if (q.status != FR_OK && worst == FR_OK) worst = fr_status(q.status);
-        if (q.status == FR_ENAN) worst = FR_ENAN;
+        worst = fr::worse_status(worst, si);
     }
     if (stats) std::copy(ns.begin(), ns.end(), stats);
     FR_HIP(hipStreamSynchronize(s));
-    if (worst == FR_ENOCONV) set_err(worst, "newton: iteration limit reached for an instance");
-    if (worst == FR_ENAN) set_err(worst, "newton: non-finite residual");
+    W.ran = true;
+    if (worst != FR_OK) set_err(worst, newton_message(worst, "an instance"));
     return worst;
 }
 
@@ -832,7 +894,7 @@ static fr_status newton_options(const fr_amg_opts* amg_opts, const fr_solve_opts
     so = fr_solve_opts{1e-8, 100, 500, 1};
     if (solve_opts) so = *solve_opts;
     if (check_solve(so) != FR_OK) return FR_EINVAL;
-    no = fr_newton_opts{1e-8, 30, 8, 0.0};
+    no = fr_newton_opts{1e-8, 30, 8, 0.0, 0};
     if (newton_opts) no = *newton_opts;
     FR_REQUIRE(no.tol > 0 && no.atol >= 0 && std::isfinite(no.atol) && no.max_it >= 1 && no.ls_max >= 0 &&
                    no.ls_max <= 60,
@@ -881,13 +943,18 @@ static fr_status newton_run(fr_mesh mesh, const fr_params* prm, double* u, doubl
         t_asm += t.stop();
     }
     double nr[2];
-    fr::system_norms(sys, nullptr, nullptr, nr, nullptr, nullptr);
+    int64_t n_act = 0;
+    fr::system_norms(sys, nullptr, nullptr, nr, &n_act, nullptr);
     const double r0 = nr[0];
     double rk = r0;
     ns.res0 = r0;
-    int it = 0;
-    fr_status status = FR_ENOCONV;
-    while (it < no.max_it) {
+    ns.n_active = n_act;
+    int it = 0, lin_noconv = 0;
+    fr_status lin_worst = FR_OK;
+    // FR_ENAN / FR_EBREAKDOWN end the loop; nothing is built from a non-finite residual
+    fr_status failed = std::isfinite(r0) ? FR_OK : FR_ENAN;
+    bool converged = false;
+    while (failed == FR_OK && it < no.max_it) {
         {
             EventTimer t(s);
             fr::assemble_jacobian(sys, u, phi, phi_old, phi_tilde);
@@ -909,7 +976,12 @@ static fr_status newton_run(fr_mesh mesh, const fr_params* prm, double* u, doubl
             const fr_status r = fr::fgmres(sys, A->amg, so, du.p, &st, S->kry, s);
             t_solve += t.stop();
             ns.linear_iters += st.iters;
-            if (r == FR_ENAN) { status = FR_ENAN; break; }
+            lin_worst = fr::worse_status(lin_worst, r);
+            if (r == FR_ENAN || r == FR_EBREAKDOWN) {   // no step from this solve
+                failed = r;
+                break;
+            }
+            if (r == FR_ENOCONV) ++lin_noconv;
         }
         EventTimer t(s);
         // line search on ||R~|| with the current active set; the fixed DoFs take their
@@ -928,26 +1000,42 @@ static fr_status newton_run(fr_mesh mesh, const fr_params* prm, double* u, doubl
             if (nr[0] < rk) break;
         }
         ++it;
-        if (it >= 2) fr::assemble_active_freeze(sys, phi, phi_old);
+        // the cycle rule: from the third iterate on, alternating phi DoFs are frozen active
+        if (it >= 2 && !no.no_cycle_freeze) fr::assemble_active_freeze(sys, phi, phi_old);
         else fr::assemble_active(sys, phi, phi_old);
-        int64_t n_act = 0;
         fr::system_norms(sys, nullptr, nullptr, nr, &n_act, nullptr);
         rk = nr[0];
         ns.n_active = n_act;
         t_other += t.stop();
-        if (!std::isfinite(rk)) { status = FR_ENAN; break; }
-        if (sys.last_changes == 0 && rk <= std::max(no.tol * r0, no.atol)) { status = FR_OK; break; }
+        if (!std::isfinite(rk)) {
+            failed = FR_ENAN;
+            break;
+        }
+        if (sys.last_changes == 0 && rk <= std::max(no.tol * r0, no.atol)) {
+            converged = true;
+            break;
+        }
     }
+    fr_status status;
+    if (failed != FR_OK) status = failed;
+    else if (converged) status = lin_noconv ? FR_ENOCONV : FR_OK;
+    // the iteration cap: a loop held back only by a still-changing active set is a cycle the
+    // rule did not settle, anything else is plain non-convergence
+    else status = rk <= std::max(no.tol * r0, no.atol) ? FR_ECYCLE : FR_ENOCONV;
     ns.iterations = it;
     ns.res = rk;
     ns.status = status;
+    ns.n_frozen = it >= 2 ? fr::count_flags_inst(sys, sys.frozen.p)[0] : 0;
+    ns.linear_noconv = lin_noconv;
+    ns.linear_status = lin_worst;
     ns.t_assemble = t_asm;
     ns.t_setup = t_setup;
     ns.t_solve = t_solve;
     ns.t_other = t_other;
     if (stats) *stats = ns;
     FR_HIP(hipStreamSynchronize(s));
-    if (status == FR_ENOCONV) set_err(status, "newton: iteration limit reached");
+    W.ran = true;
+    if (status != FR_OK) set_err(status, newton_message(status, "the loop"));
     return status;
 }
 
@@ -969,6 +1057,21 @@ fr_status fracture_newton(fr_mesh mesh, const fr_params* prm, double* u, double*
     if (os != FR_OK) return os;
     return guard([&]() {
         return newton_run(mesh, prm, u, phi, phi_old, phi_tilde, ao, so, no, stats, fr::as_stream(stream));
+    });
+}
+
+fr_status fracture_newton_masks(fr_mesh mesh, uint8_t* active, uint8_t* frozen, void* stream) {
+    FR_REQUIRE(mesh != nullptr && mesh->m, "newton_masks: NULL mesh");
+    FR_REQUIRE(mesh->m->on_device, "newton_masks: host-only mesh");
+    std::lock_guard<std::mutex> lk(mesh->newton_mu);
+    FR_REQUIRE(mesh->nw && mesh->nw->ran, "newton_masks: no Newton loop has run on this mesh");
+    return guard([&]() {
+        hipStream_t s = fr::as_stream(stream);
+        const fr::DevSystem& S = mesh->nw->S.sys;
+        const size_t nf = size_t(mesh->m->n_free);
+        if (active) FR_HIP(hipMemcpyAsync(active, S.active.p, nf, hipMemcpyDeviceToDevice, s));
+        if (frozen) FR_HIP(hipMemcpyAsync(frozen, S.frozen.p, nf, hipMemcpyDeviceToDevice, s));
+        return FR_OK;
     });
 }
 

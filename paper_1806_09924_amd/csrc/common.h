@@ -21,6 +21,20 @@ struct Error : std::runtime_error {
 
 [[noreturn]] inline void fail(fr_status s, const std::string& m) { throw Error(s, m); }
 
+// The worse of two statuses (what a call over several instances or steps returns):
+// FR_OK < FR_ENOCONV < FR_ECYCLE < FR_EBREAKDOWN < FR_ENAN < every argument / device error.
+inline int status_rank(fr_status s) {
+    switch (s) {
+        case FR_OK: return 0;
+        case FR_ENOCONV: return 1;
+        case FR_ECYCLE: return 2;
+        case FR_EBREAKDOWN: return 3;
+        case FR_ENAN: return 4;
+        default: return 5;
+    }
+}
+inline fr_status worse_status(fr_status a, fr_status b) { return status_rank(b) > status_rank(a) ? b : a; }
+
 #define FR_HIP(call)                                                                   \
     do {                                                                               \
         hipError_t e_ = (call);                                                        \
@@ -43,6 +57,8 @@ void* dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void* p, hipStream_t s);
 void trim_pool();
 void forget_stream(hipStream_t s);
+// Installs the caller's allocator (both NULL: the library's pool again).
+void set_allocator(fr_alloc_fn alloc, fr_free_fn dealloc, void* ctx);
 
 // Stream-ordered device buffer.  Released on the stream it was allocated on.
 template <typename T>

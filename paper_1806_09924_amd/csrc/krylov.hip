@@ -216,8 +216,11 @@ struct State {
     double* beta2;   // [ni] squared residual norm
     int* done;       // [ni] converged (or stopped) in this cycle
     int* jused;      // [ni] Krylov columns used by the instance in this cycle
-    int* bad;        // [ni] non-finite value seen
+    int* bad;        // [ni] non-finite residual (the right-hand side or the iterate)
     int* need;       // [ni] the second Gram-Schmidt pass is applied in this iteration
+    int* brk;        // [ni] breakdown: non-finite Arnoldi quantities, or a zero Arnoldi norm
+                     //      whose cycle left the true residual above the target
+    int* zhit;       // [ni] the last cycle ended on a zero Arnoldi norm
 };
 
 // Classical Gram-Schmidt with the second pass only where it is needed: after one pass the
@@ -235,7 +238,9 @@ __global__ void k_reorth_decide(int ni, int m, int nv, State st, double eta2) {
     st.need[i] = (!st.done[i] && !(after >= eta2 * before)) ? 1 : 0;   // NaN -> second pass
 }
 
-// new cycle: g = (beta, 0, ...), scale = 1/beta, done when beta <= target
+// new cycle: g = (beta, 0, ...), scale = 1/beta, done when beta <= target.  A previous cycle
+// that ended on a zero Arnoldi norm (an invariant Krylov space) without reaching the target is a
+// breakdown: the next cycle would rebuild the same space.
 __global__ void k_cycle_start(int ni, int m, State st) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ni) return;
@@ -244,7 +249,9 @@ __global__ void k_cycle_start(int ni, int m, State st) {
     st.g[int64_t(i) * (m + 1)] = beta;
     const bool fin = isfinite(beta);
     if (!fin) st.bad[i] = 1;
-    const bool dn = !fin || beta <= st.target[i];
+    if (fin && st.zhit[i] && !(beta <= st.target[i])) st.brk[i] = 1;
+    st.zhit[i] = 0;
+    const bool dn = !fin || st.brk[i] || beta <= st.target[i];
     st.done[i] = dn ? 1 : 0;
     st.jused[i] = 0;
     st.scale[i] = (!dn && beta > 0.0) ? 1.0 / beta : 0.0;
@@ -267,6 +274,17 @@ __global__ void k_givens(int ni, int m, int j, State st) {
     double* H = st.H + int64_t(i) * (m + 1) * m;
     for (int k = 0; k <= j; ++k) h[k] += h2[k];
     const double nw = sqrt(st.nrm2[i]);
+    bool fin_col = isfinite(nw);
+    for (int k = 0; k <= j; ++k) fin_col = fin_col && isfinite(h[k]);
+    if (!fin_col) {
+        // breakdown with finite inputs (e.g. a preconditioner that overflowed): the column is
+        // dropped, so the update uses the j finite columns before it
+        st.brk[i] = 1;
+        st.done[i] = 1;
+        st.jused[i] = j;
+        st.scale[i] = 0.0;
+        return;
+    }
     h[j + 1] = nw;
     for (int k = 0; k < j; ++k) {
         const double a = h[k], b = h[k + 1];
@@ -282,11 +300,12 @@ __global__ void k_givens(int ni, int m, int j, State st) {
     g[j] = cs[j] * g[j];
     for (int k = 0; k <= j; ++k) H[int64_t(j) * (m + 1) + k] = h[k];
     st.jused[i] = j + 1;
-    const bool fin = isfinite(nw) && isfinite(g[j + 1]);
-    if (!fin) st.bad[i] = 1;
+    const bool fin = isfinite(g[j + 1]);
+    if (!fin) st.brk[i] = 1;
     const bool conv = fabs(g[j + 1]) <= st.target[i];
-    const bool brk = !(nw > 0.0);      // invariant subspace: the solution is in the basis
-    if (!fin || conv || brk || j + 1 == m) st.done[i] = 1;
+    const bool inv = !(nw > 0.0);      // invariant subspace: the solution is in the basis
+    if (inv) st.zhit[i] = 1;           // unless the true residual says otherwise (next cycle)
+    if (!fin || conv || inv || j + 1 == m) st.done[i] = 1;
     st.scale[i] = (st.done[i] || !(nw > 0.0)) ? 0.0 : 1.0 / nw;
 }
 
@@ -409,7 +428,7 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
         ws.part.alloc(size_t(ws.nb) * (kMaxM + 2) + 64, s);
         const size_t per = size_t(2 * (m + 2) + 1 + (m + 1) * m + 2 * m + (m + 1) + m + 3);
         ws.state.alloc(per * size_t(ni), s);
-        ws.istate.alloc(size_t(4 * ni), s);
+        ws.istate.alloc(size_t(6 * ni), s);
     }
     const int M = ws.m;
     State st;
@@ -431,6 +450,8 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
         st.jused = ws.istate.p + ni;
         st.bad = ws.istate.p + 2 * ni;
         st.need = ws.istate.p + 3 * ni;
+        st.brk = ws.istate.p + 4 * ni;
+        st.zhit = ws.istate.p + 5 * ni;
     }
     const Seg sg{ws.seg_start.p, ws.seg_len.p, ws.seg_inst.p};
     // The preconditioner's argument is staged while the basis vector is written: for graph
@@ -453,7 +474,7 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
     const int nb = ws.nb;
     const int gi = int(ceil_div(ni, 64));
     double* part = ws.part.p;
-    FR_HIP(hipMemsetAsync(ws.istate.p, 0, size_t(4 * ni) * sizeof(int), s));
+    FR_HIP(hipMemsetAsync(ws.istate.p, 0, size_t(6 * ni) * sizeof(int), s));
 
     // ||F_i||, targets
     k_seg_resid<<<nb, 256, 0, s>>>(sys.F.p, ws.w.p, 1, sg, part);
@@ -589,24 +610,23 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
             else k_seg_combine<double><<<nb, 256, 0, s>>>(ws.Z.p, n, jmax, st.y, M, du, sg);
             FR_LAUNCH_CHECK();
         }
-        std::vector<int> bad = download(st.bad, size_t(ni), s);
-        bool any_bad = false;
-        for (int b : bad) any_bad = any_bad || b;
-        if (any_bad) break;
+        // instances with a non-finite residual or a breakdown are marked done by the next
+        // cycle start; the others go on
     }
     std::vector<int> bad = download(st.bad, size_t(ni), s);
+    std::vector<int> brk = download(st.brk, size_t(ni), s);
     fr_status worst = FR_OK;
     for (int i = 0; i < ni; ++i) {
         fr_status si = FR_OK;
         if (bad[size_t(i)]) si = FR_ENAN;
+        else if (brk[size_t(i)]) si = FR_EBREAKDOWN;
         else if (!(relres[size_t(i)] <= o.rtol)) si = FR_ENOCONV;
         if (stats) {
             stats[i].iters = iters[size_t(i)];
             stats[i].relres = relres[size_t(i)];
             stats[i].status = si;
         }
-        if (si == FR_ENAN) worst = FR_ENAN;
-        else if (si == FR_ENOCONV && worst == FR_OK) worst = FR_ENOCONV;
+        worst = worse_status(worst, si);
     }
     return worst;
 }

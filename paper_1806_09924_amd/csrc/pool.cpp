@@ -1,12 +1,17 @@
 // Device memory for the library.
 //
-// Blocks come from a library-owned stream-ordered pool per device whose release threshold
+// By default blocks come from a library-owned stream-ordered pool per device whose release threshold
 // is unbounded, and a freed block goes to a cache keyed by (device, stream, size) from
 // which a later allocation on the same stream takes it back without any runtime call.  In
 // a steady state (every Newton call of a loading step allocates the same sizes) setup and
 // solve then make no allocation calls at all; the runtime's own free path can stall the
 // host for a whole device drain.  Reuse on the stream of the free is safe by stream order,
 // the same contract as the stream-ordered allocator's.
+//
+// A caller may install an allocator of its own (fracture_set_allocator, e.g. PyTorch's caching
+// allocator): new blocks then come from it and go back to it when freed, with the stream of
+// the free; the library keeps no cache of them.  Every block remembers the allocator that made
+// it, so changing the allocator while objects are alive is safe.
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -19,12 +24,25 @@ namespace {
 
 constexpr int kMaxDevices = 64;
 
+struct Hook {
+    fr_alloc_fn alloc = nullptr;
+    fr_free_fn dealloc = nullptr;
+    void* ctx = nullptr;
+};
+
+struct Block {
+    size_t bytes = 0;
+    int dev = 0;
+    Hook hook;                 // the caller's allocator that made it (alloc == nullptr: the pool)
+};
+
 struct Cache {
     std::mutex mu;
     hipMemPool_t pool[kMaxDevices] = {};
-    // (device, stream) -> size -> cached blocks
+    Hook hook;                 // installed allocator (alloc == nullptr: the library's pool)
+    // (device, stream) -> size -> cached blocks (pool blocks only)
     std::map<std::pair<int, hipStream_t>, std::multimap<size_t, void*>> free_blocks;
-    std::unordered_map<void*, std::pair<size_t, int>> size_of;   // every block we made: bytes, device
+    std::unordered_map<void*, Block> blocks;   // every block handed out
 };
 
 Cache& cache() {
@@ -71,7 +89,7 @@ void release_locked(Cache& c, int dev, bool s_only, hipStream_t s) {
         }
         for (auto& kv : it->second) {
             (void)hipFreeAsync(kv.second, nullptr);
-            c.size_of.erase(kv.second);
+            c.blocks.erase(kv.second);
         }
         it = c.free_blocks.erase(it);
     }
@@ -84,6 +102,19 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
     const int dev = current_device();
     const size_t rb = round_bytes(bytes);
     hipMemPool_t pool = nullptr;
+    Hook hook;
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        hook = c.hook;
+    }
+    if (hook.alloc) {
+        // the caller's allocator, called without the lock held
+        void* p = hook.alloc(rb, dev, reinterpret_cast<void*>(s), hook.ctx);
+        if (!p) fail(FR_ENOMEM, std::string("installed allocator returned NULL for ") + std::to_string(rb) + " bytes");
+        std::lock_guard<std::mutex> lk(c.mu);
+        c.blocks[p] = Block{rb, dev, hook};
+        return p;
+    }
     {
         std::lock_guard<std::mutex> lk(c.mu);
         auto fb = c.free_blocks.find({dev, s});
@@ -117,20 +148,35 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
              std::string("device allocation of ") + std::to_string(rb) + " bytes: " + hipGetErrorString(e));
     }
     std::lock_guard<std::mutex> lk(c.mu);
-    c.size_of[p] = {rb, dev};
+    c.blocks[p] = Block{rb, dev, Hook{}};
     return p;
 }
 
 void dev_free(void* p, hipStream_t s) {
     if (!p) return;
     Cache& c = cache();
-    std::lock_guard<std::mutex> lk(c.mu);
-    auto it = c.size_of.find(p);
-    if (it == c.size_of.end()) {
-        (void)hipFreeAsync(p, s);
-        return;
+    Block b;
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        auto it = c.blocks.find(p);
+        if (it == c.blocks.end()) {
+            (void)hipFreeAsync(p, s);
+            return;
+        }
+        if (!it->second.hook.alloc) {
+            c.free_blocks[{it->second.dev, s}].insert({it->second.bytes, p});
+            return;
+        }
+        b = it->second;
+        c.blocks.erase(it);
     }
-    c.free_blocks[{it->second.second, s}].insert({it->second.first, p});
+    b.hook.dealloc(p, b.bytes, b.dev, reinterpret_cast<void*>(s), b.hook.ctx);
+}
+
+void set_allocator(fr_alloc_fn alloc, fr_free_fn dealloc, void* ctx) {
+    Cache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.hook = Hook{alloc, dealloc, ctx};
 }
 
 void forget_stream(hipStream_t s) {

@@ -134,7 +134,16 @@ void extrapolate(DevMesh& m, const double* p1, const double* p2, double w, doubl
 // Batches: per-instance ||R~||, active phi rows and active-flag changes of the last update.
 void system_norms_inst(DevSystem& sys, std::vector<double>& rnorm, std::vector<int64_t>& n_active,
                        std::vector<int64_t>& changes);
-// Batches: u += omega[i] du on instance i (omega: device, one per instance).
+// Batches: the rows of every instance i with bad_dev[i] != 0 (device, one int per instance)
+// become identity rows with zero right-hand side and residual (their increments are then 0
+// and their non-finite values stay out of the other instances' preconditioner and solve).
+void system_neutralize(DevSystem& sys, const int* bad_dev);
+// Per-instance count of nonzero entries of a per-free-node flag array (synchronises).
+std::vector<int64_t> count_flags_inst(DevSystem& sys, const uint8_t* flags);
+// Whether every value of the three Jacobian blocks and of F is finite (synchronises s).
+bool system_all_finite(const DevSystem& sys, hipStream_t s);
+// Batches: u += omega[i] du on instance i (omega: device, one per instance); instances with
+// omega[i] == 0 are not touched.
 void mesh_update_inst(DevMesh& m, const double* du, const double* omega, double* u, double* phi, hipStream_t s,
                       const uint8_t* active = nullptr, const double* phi_old = nullptr);
 void mesh_functionals(DevMesh& m, const double* u, const double* phi, const double* cod_x, int n_cod,
@@ -167,9 +176,8 @@ void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d
 template <typename T>
 void cheb_first(const T* invd, const T* b, T* d, T* x, T beta, int64_t n, hipStream_t s);
 // fused J-SpMV over the three blocks: y = J x (solve order); x may be FP32 (exactly widened)
-// y = D^-1 A x (zero: a zero vector of A's rows; xn: scratch of A's rows).
-void diag_scaled_matvec(const BMat<double>& A, const double* invd, const double* x, const double* zero,
-                        double* y, double* xn, hipStream_t s);
+// y = D^-1 A x (the power iteration of the smoother bounds; its own kernel, k_power_step).
+void diag_scaled_matvec(const BMat<double>& A, const double* invd, const double* x, double* y, hipStream_t s);
 // Sets S.col16 (columns as int16 row offsets) when every offset fits.
 void make_col16(SellStruct& S, hipStream_t s);
 // Launch shape: lanes per row of the SpMV / Chebyshev kernels for a matrix.

@@ -62,6 +62,22 @@ def test_argument_validation_before_device(lib):
                                 None, st, None, None) == B.FR_EINVAL
 
 
+def test_error_contract_arguments(lib):
+    """Argument checks of the calls of the error contract, before any device work."""
+    # an allocator needs both functions (or neither, which restores the built-in pool)
+    assert lib.fracture_set_allocator(B._TORCH_HOOKS[0], B._FREE_FN(), None) == B.FR_EINVAL
+    assert "both" in B.last_error()
+    assert lib.fracture_set_allocator(B._ALLOC_FN(), B._TORCH_HOOKS[1], None) == B.FR_EINVAL
+    assert lib.fracture_set_allocator(B._ALLOC_FN(), B._FREE_FN(), None) == B.FR_OK
+    assert lib.fracture_newton_masks(None, None, None, None) == B.FR_EINVAL
+    m = B.Mesh(B.mesh_desc(2, -1.0, 1.0, 4), host_only=True)
+    assert lib.fracture_newton_masks(m.h, None, None, None) == B.FR_EINVAL
+    # newton options reach the library in full (the cycle-rule switch is the last field)
+    o = B.newton_opts(no_cycle_freeze=1)
+    assert ctypes.sizeof(o) == ctypes.sizeof(ctypes.c_double) * 2 + ctypes.sizeof(ctypes.c_int) * 4
+    assert o.no_cycle_freeze == 1
+
+
 def test_host_only_mesh_is_rejected_by_device_calls(lib):
     m = B.Mesh(B.mesh_desc(2, -1.0, 1.0, 4), host_only=True)
     p = B.params()
