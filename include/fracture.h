@@ -426,6 +426,20 @@ fr_status fracture_functionals(fr_mesh mesh, const double* u, const double* phi,
                                const double* cod_x, int n_cod, double* cod, double* tcv,
                                void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the same results as fracture_functionals, bit for bit (same
+ * kernels, same summation order), with no allocation of any kind. Its device buffers (the
+ * sample abscissae, per-block partial sums and reduced values) are slices of one fixed array of
+ * 524288 doubles (4 MiB) that every device the library runs on holds for the life of the
+ * process. Limit: n_inst * n_cod * (dim - 1) + (1 + ceil(c / 256)) * max(1, n_cod) <= 524288,
+ * c the cell count of the largest instance (a 2048 x 2048 mesh allows n_cod <= 31); larger calls
+ * return FR_EINVAL before any device work. Calls that overlap on one device share the array and
+ * race: issue them one at a time per device. Same arguments and synchronisation as
+ * fracture_functionals. */
+fr_status fracture_functionals_noalloc(fr_mesh mesh, const double* u, const double* phi,
+                                       const double* cod_x, int n_cod, double* cod, double* tcv,
+                                       void* stream);
+
 /* ---- kernel timing ---------------------------------------------------------------- */
 
 /* enable != 0 starts recording a HIP event pair on the launch stream around every launch

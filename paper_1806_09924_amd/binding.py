@@ -114,6 +114,7 @@ _SIGNATURES = {
                          ctypes.POINTER(AmgOpts), ctypes.POINTER(SolveOpts), ctypes.POINTER(NewtonOpts),
                          ctypes.POINTER(NewtonStats), _DP, _P],
     "fracture_functionals": [_P, _P, _P, _P, ctypes.c_int, _P, _P, _P],
+    "fracture_functionals_noalloc": [_P, _P, _P, _P, ctypes.c_int, _P, _P, _P],
     "fracture_profile": [ctypes.c_int],
     "fracture_profile_read": [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), _I64P, _DP, _DP],
     "fracture_last_error": [],
@@ -517,16 +518,18 @@ def loading(mesh, prm_steps, times, u, phi, phi_prev=None, t_prev=0.0, amg=None,
     return [out[k * ni:(k + 1) * ni] for k in range(ns)], tcv.reshape(ns, ni)
 
 
-def functionals(mesh, u, phi, cod_x=()):
+def functionals(mesh, u, phi, cod_x=(), noalloc=False):
     """(cod, tcv). One mesh: cod_x [n_cod][dim-1] -> cod [n_cod], tcv float. Batched mesh:
-    cod_x [n_inst][n_cod][dim-1] -> cod [n_inst][n_cod], tcv [n_inst]."""
+    cod_x [n_inst][n_cod][dim-1] -> cod [n_inst][n_cod], tcv [n_inst].  noalloc: the entry
+    point that allocates nothing (fixed per-device scratch)."""
     ni = mesh.n_inst
     cod_x = np.ascontiguousarray(np.asarray(cod_x, dtype=np.float64).reshape(ni, -1, mesh.dim - 1))
     n = cod_x.shape[1]
     cod = np.zeros(max(1, ni * n))
     tcv = np.zeros(ni)
-    _check(load().fracture_functionals(mesh.h, _ptr(u), _ptr(phi), cod_x.ctypes.data_as(_P) if n else None, n,
-                                       cod.ctypes.data_as(_P) if n else None, tcv.ctypes.data_as(_P), _stream()))
+    fn = load().fracture_functionals_noalloc if noalloc else load().fracture_functionals
+    _check(fn(mesh.h, _ptr(u), _ptr(phi), cod_x.ctypes.data_as(_P) if n else None, n,
+              cod.ctypes.data_as(_P) if n else None, tcv.ctypes.data_as(_P), _stream()))
     if ni == 1:
         return cod[:n], float(tcv[0])
     return cod[:ni * n].reshape(ni, n), tcv

@@ -8,6 +8,7 @@
 // accumulates in a fixed order.  No atomics: results are bitwise reproducible.
 #include <atomic>
 #include <cmath>
+#include <mutex>
 
 #include "system.h"
 
@@ -1445,54 +1446,123 @@ void mesh_update(DevMesh& m, const double* du, double omega, double* u, double* 
     }
 }
 
-void mesh_functionals(DevMesh& m, const double* u, const double* phi, const double* cod_x, int n_cod, double* cod,
-                      double* tcv, hipStream_t s) {
+// TCV and COD of every instance with the caller's device buffers: xs (the sample abscissae,
+// already on the device), part (at least blocks x max(1, n_cod) doubles for the largest
+// instance) and out (max(1, n_cod) doubles).  Results go straight into the host arrays.
+static void functionals_into(DevMesh& m, const double* u, const double* phi, const double* xs, int n_cod,
+                             double* cod, double* tcv, double* part, double* out, hipStream_t s) {
     MeshView mv = view(m);
     const HostMesh& hm = m.host;
     const int D1 = m.dim - 1;
-    DBuf<double> part, out, xs;
-    const int nb_max = blocks_for(std::max<int64_t>(1, m.n_cells), 256);
-    part.alloc(size_t(nb_max) * size_t(std::max(1, n_cod)), s);
-    out.alloc(size_t(std::max(1, n_cod)), s);
-    if (n_cod > 0) {
-        xs.alloc(size_t(m.n_inst) * n_cod * D1, s);
-        xs.upload(cod_x, size_t(m.n_inst) * n_cod * D1, s);
-    }
     // one reduction per instance over its cell range (instances never share cells)
     for (int i = 0; i < m.n_inst; ++i) {
         const int64_t c0 = hm.cell_off[size_t(i)], c1 = hm.cell_off[size_t(i) + 1];
         const int nb = blocks_for(std::max<int64_t>(1, c1 - c0), 256);
         if (tcv) {
             if (m.dim == 2) {
-                if (m.hanging) k_tcv<2, true><<<nb, 256, 0, s>>>(c0, c1, mv, u, phi, part.p);
-                else k_tcv<2, false><<<nb, 256, 0, s>>>(c0, c1, mv, u, phi, part.p);
+                if (m.hanging) k_tcv<2, true><<<nb, 256, 0, s>>>(c0, c1, mv, u, phi, part);
+                else k_tcv<2, false><<<nb, 256, 0, s>>>(c0, c1, mv, u, phi, part);
             } else {
-                if (m.hanging) k_tcv<3, true><<<nb, 256, 0, s>>>(c0, c1, mv, u, phi, part.p);
-                else k_tcv<3, false><<<nb, 256, 0, s>>>(c0, c1, mv, u, phi, part.p);
+                if (m.hanging) k_tcv<3, true><<<nb, 256, 0, s>>>(c0, c1, mv, u, phi, part);
+                else k_tcv<3, false><<<nb, 256, 0, s>>>(c0, c1, mv, u, phi, part);
             }
             FR_LAUNCH_CHECK();
-            k_sum_rows<<<1, 256, 0, s>>>(part.p, nb, 1, 0, 1, out.p);
+            k_sum_rows<<<1, 256, 0, s>>>(part, nb, 1, 0, 1, out);
             FR_LAUNCH_CHECK();
-            tcv[i] = download1(out.p, s);
+            FR_HIP(hipMemcpyAsync(tcv + i, out, sizeof(double), hipMemcpyDeviceToHost, s));
+            FR_HIP(hipStreamSynchronize(s));
         }
         if (cod && n_cod > 0) {
             dim3 grid(nb, n_cod);
-            const double* xi = xs.p + size_t(i) * n_cod * D1;
+            const double* xi = xs + size_t(i) * n_cod * D1;
             if (m.dim == 2) {
-                if (m.hanging) k_cod<2, true><<<grid, 256, 0, s>>>(c0, c1, mv, u, phi, xi, part.p);
-                else k_cod<2, false><<<grid, 256, 0, s>>>(c0, c1, mv, u, phi, xi, part.p);
+                if (m.hanging) k_cod<2, true><<<grid, 256, 0, s>>>(c0, c1, mv, u, phi, xi, part);
+                else k_cod<2, false><<<grid, 256, 0, s>>>(c0, c1, mv, u, phi, xi, part);
             } else {
-                if (m.hanging) k_cod<3, true><<<grid, 256, 0, s>>>(c0, c1, mv, u, phi, xi, part.p);
-                else k_cod<3, false><<<grid, 256, 0, s>>>(c0, c1, mv, u, phi, xi, part.p);
+                if (m.hanging) k_cod<3, true><<<grid, 256, 0, s>>>(c0, c1, mv, u, phi, xi, part);
+                else k_cod<3, false><<<grid, 256, 0, s>>>(c0, c1, mv, u, phi, xi, part);
             }
             FR_LAUNCH_CHECK();
-            k_sum_rows<<<n_cod, 256, 0, s>>>(part.p, nb, n_cod, nb, 1, out.p);
+            k_sum_rows<<<n_cod, 256, 0, s>>>(part, nb, n_cod, nb, 1, out);
             FR_LAUNCH_CHECK();
-            auto h = download(out.p, size_t(n_cod), s);
-            for (int k = 0; k < n_cod; ++k) cod[size_t(i) * n_cod + k] = h[size_t(k)];
+            FR_HIP(hipMemcpyAsync(cod + size_t(i) * n_cod, out, size_t(n_cod) * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+            FR_HIP(hipStreamSynchronize(s));
         }
     }
     FR_HIP(hipStreamSynchronize(s));
+}
+
+// Partial-sum blocks of the largest instance (the reductions of every instance reuse them).
+static int64_t functionals_blocks(const DevMesh& m) {
+    int64_t nb = 1;
+    for (int i = 0; i < m.n_inst; ++i) {
+        const int64_t nc = m.host.cell_off[size_t(i) + 1] - m.host.cell_off[size_t(i)];
+        nb = std::max<int64_t>(nb, blocks_for(std::max<int64_t>(1, nc), 256));
+    }
+    return nb;
+}
+
+void mesh_functionals(DevMesh& m, const double* u, const double* phi, const double* cod_x, int n_cod, double* cod,
+                      double* tcv, hipStream_t s) {
+    const int D1 = m.dim - 1;
+    DBuf<double> part, out, xs;
+    part.alloc(size_t(functionals_blocks(m)) * size_t(std::max(1, n_cod)), s);
+    out.alloc(size_t(std::max(1, n_cod)), s);
+    if (n_cod > 0) {
+        xs.alloc(size_t(m.n_inst) * n_cod * D1, s);
+        xs.upload(cod_x, size_t(m.n_inst) * n_cod * D1, s);
+    }
+    functionals_into(m, u, phi, xs.p, n_cod, cod, tcv, part.p, out.p, s);
+}
+
+}  // namespace fr
+
+// ---- functionals without allocation -------------------------------------------------------
+// Device memory of fracture_functionals_noalloc: the sample abscissae, the per-block partial
+// sums and the reduced values live in this fixed array (each device holds its own copy for the
+// life of the process).  Host code reaches it only through the address hipGetSymbolAddress
+// returns for the current device.
+static __device__ __align__(256) double scratch[fr::kFunctionalsScratchDoubles];
+
+namespace fr {
+
+int64_t functionals_scratch_need(const DevMesh& m, int n_cod) {
+    const int64_t nc = std::max(1, n_cod);
+    return int64_t(m.n_inst) * n_cod * (m.dim - 1) + nc + functionals_blocks(m) * nc;
+}
+
+// The current device's address of `scratch`, looked up once per device (with it current).
+static double* functionals_scratch() {
+    static std::mutex mu;
+    static void* addr[kMaxScratchDevices] = {};
+    int dev = 0;
+    FR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices) fail(FR_EDEVICE, "functionals_noalloc: device ordinal out of range");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();
+            fail(FR_EDEVICE, std::string("functionals_noalloc: hipGetSymbolAddress failed: ") + hipGetErrorString(e));
+        }
+        addr[dev] = p;
+    }
+    return static_cast<double*>(addr[dev]);
+}
+
+void mesh_functionals_noalloc(DevMesh& m, const double* u, const double* phi, const double* cod_x, int n_cod,
+                              double* cod, double* tcv, hipStream_t s) {
+    if (functionals_scratch_need(m, n_cod) > int64_t(kFunctionalsScratchDoubles))
+        fail(FR_EINVAL, "functionals_noalloc: mesh and n_cod need more than the fixed scratch");
+    double* base = functionals_scratch();
+    const int64_t nx = int64_t(m.n_inst) * n_cod * (m.dim - 1);
+    double* xs = base;
+    double* out = base + nx;
+    double* part = out + std::max(1, n_cod);
+    if (nx > 0) FR_HIP(hipMemcpyAsync(xs, cod_x, size_t(nx) * sizeof(double), hipMemcpyHostToDevice, s));
+    functionals_into(m, u, phi, xs, n_cod, cod, tcv, part, out, s);
 }
 
 }  // namespace fr

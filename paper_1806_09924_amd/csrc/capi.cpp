@@ -1163,4 +1163,19 @@ fr_status fracture_functionals(fr_mesh mesh, const double* u, const double* phi,
     });
 }
 
+fr_status fracture_functionals_noalloc(fr_mesh mesh, const double* u, const double* phi, const double* cod_x,
+                                       int n_cod, double* cod, double* tcv, void* stream) {
+    FR_REQUIRE(mesh != nullptr && mesh->m && u && phi, "functionals_noalloc: NULL argument");
+    FR_REQUIRE(mesh->m->on_device, "functionals_noalloc: host-only mesh");
+    FR_REQUIRE(n_cod >= 0 && n_cod <= 65535, "functionals_noalloc: n_cod out of range");
+    FR_REQUIRE(n_cod == 0 || (cod_x && cod), "functionals_noalloc: cod_x and cod required when n_cod > 0");
+    FR_REQUIRE(fr::functionals_scratch_need(*mesh->m, n_cod) <= int64_t(fr::kFunctionalsScratchDoubles),
+               "functionals_noalloc: n_inst * n_cod * (dim - 1) + (1 + ceil(largest instance's cells / 256)) * "
+               "max(1, n_cod) exceeds the 524288 doubles of the fixed scratch");
+    return guard([&]() {
+        fr::mesh_functionals_noalloc(*mesh->m, u, phi, cod_x, n_cod, cod, tcv, fr::as_stream(stream));
+        return FR_OK;
+    });
+}
+
 }  // extern "C"

@@ -148,6 +148,14 @@ void mesh_update_inst(DevMesh& m, const double* du, const double* omega, double*
                       const uint8_t* active = nullptr, const double* phi_old = nullptr);
 void mesh_functionals(DevMesh& m, const double* u, const double* phi, const double* cod_x, int n_cod,
                       double* cod, double* tcv, hipStream_t s);
+// The same results with no allocation: every device buffer is a slice of a fixed per-device
+// array of kFunctionalsScratchDoubles doubles (FR_EINVAL when the call needs more, see
+// functionals_scratch_need).  Calls that overlap on one device share that array and race.
+constexpr size_t kFunctionalsScratchDoubles = size_t(1) << 19;   // 4 MiB per device
+constexpr int kMaxScratchDevices = 64;
+int64_t functionals_scratch_need(const DevMesh& m, int n_cod);
+void mesh_functionals_noalloc(DevMesh& m, const double* u, const double* phi, const double* cod_x, int n_cod,
+                              double* cod, double* tcv, hipStream_t s);
 
 // ---- generic device primitives (sparse.hip) ---------------------------------------------
 // out[0..n] exclusive scan of in[0..n-1]; returns the total (synchronises).
