@@ -1784,13 +1784,8 @@ void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s)
                             amg.opts.coarse_max == o.coarse_max && amg.opts.max_levels == o.max_levels;
     const bool refresh_phi = o.refresh_phi && amg.sys == &sys && !amg.h[1].lv.empty() && amg.h[1].refreshable &&
                              same_shape && amg.h[1].lv[0]->A.S == sys.Jpp.S;
-    // the graphs replay the old hierarchy's buffers and coefficients: drop them first (after
-    // the last replay has run)
-    if (amg.vgraph[0] || amg.vgraph[1]) {
-        if (amg.side) FR_HIP(hipStreamSynchronize(amg.side));
-        FR_HIP(hipStreamSynchronize(s));
-        amg.drop_graphs();
-    }
+    // graphs captured over the old hierarchy's buffers and coefficients are stale from here on
+    ++amg.epoch;
     amg.sys = &sys;
     amg.opts = o;
     amg.stream = s;
@@ -1998,74 +1993,44 @@ void amg_precondition32(DevAmg& amg, const double* r, float* z, hipStream_t s) {
     precondition<float>(amg, r, z, s);
 }
 
-// Captures block blk's V-cycle (input vin + off, output vout + off) on stream st.
-template <typename T>
-static hipGraphExec_t capture_vcycle(DevAmg& amg, int blk, const T* vin, T* vout, hipStream_t st) {
-    Hierarchy& H = amg.h[blk];
-    hipGraph_t g = nullptr;
-    FR_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    try {
-        vcycle<T>(H, 0, vin, amg.opts, st, vout);
-    } catch (...) {
-        (void)hipStreamEndCapture(st, &g);
-        if (g) (void)hipGraphDestroy(g);
-        throw;
-    }
-    FR_HIP(hipStreamEndCapture(st, &g));
-    hipGraphExec_t ex = nullptr;
-    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    FR_HIP(e);
-    return ex;
-}
-
 void* amg_graph_input(DevAmg& amg) {
     const int64_t n = std::max<int64_t>(1, amg.sys->n_solve);
     if (amg.opts.precision == 32) {
-        if (amg.vin32.n < size_t(n)) { amg.drop_graphs(); amg.vin32.reserve(size_t(n), amg.stream); }
+        if (amg.vin32.n < size_t(n)) { ++amg.epoch; amg.vin32.reserve(size_t(n), amg.stream); }
         return amg.vin32.p;
     }
-    if (amg.vin64.n < size_t(n)) { amg.drop_graphs(); amg.vin64.reserve(size_t(n), amg.stream); }
+    if (amg.vin64.n < size_t(n)) { ++amg.epoch; amg.vin64.reserve(size_t(n), amg.stream); }
     return amg.vin64.p;
 }
 
 void* amg_graph_output(DevAmg& amg) {
     const int64_t n = std::max<int64_t>(1, amg.sys->n_solve);
     if (amg.opts.precision == 32) {
-        if (amg.vout32.n < size_t(n)) { amg.drop_graphs(); amg.vout32.reserve(size_t(n), amg.stream); }
+        if (amg.vout32.n < size_t(n)) { ++amg.epoch; amg.vout32.reserve(size_t(n), amg.stream); }
         return amg.vout32.p;
     }
-    if (amg.vout64.n < size_t(n)) { amg.drop_graphs(); amg.vout64.reserve(size_t(n), amg.stream); }
+    if (amg.vout64.n < size_t(n)) { ++amg.epoch; amg.vout64.reserve(size_t(n), amg.stream); }
     return amg.vout64.p;
 }
 
-void amg_precondition_graph(DevAmg& amg, hipStream_t s) {
-    if (prof_enabled()) fail(FR_EINTERNAL, "amg_precondition_graph: kernel timing needs direct launches");
+void amg_precondition_staged(DevAmg& amg, hipStream_t s) {
     ensure_side(amg);
     DevSystem& sys = *amg.sys;
     const int64_t off[2] = {0, sys.n_u};
     void* vin = amg_graph_input(amg);
     void* vout = amg_graph_output(amg);
-    if (!amg.vgraph[0] || !amg.vgraph[1]) {
-        // the buffers' allocations must have completed before the capture records uses;
-        // both cycles are captured on the side stream (a created stream: the caller's may be
-        // the legacy default stream, which cannot be captured)
-        FR_HIP(hipStreamSynchronize(s));
-        amg.drop_graphs();
-        for (int blk = 0; blk <= 1; ++blk) {
-            const hipStream_t st = amg.side;
-            if (amg.opts.precision == 32)
-                amg.vgraph[blk] = capture_vcycle<float>(amg, blk, static_cast<float*>(vin) + off[blk],
-                                                        static_cast<float*>(vout) + off[blk], st);
-            else
-                amg.vgraph[blk] = capture_vcycle<double>(amg, blk, static_cast<double*>(vin) + off[blk],
-                                                         static_cast<double*>(vout) + off[blk], st);
-        }
-    }
     FR_HIP(hipEventRecord(amg.ev_fork, s));
     FR_HIP(hipStreamWaitEvent(amg.side, amg.ev_fork, 0));
-    FR_HIP(hipGraphLaunch(amg.vgraph[0], s));
-    FR_HIP(hipGraphLaunch(amg.vgraph[1], amg.side));
+    for (int blk = 0; blk <= 1; ++blk) {
+        const hipStream_t st = blk == 1 ? amg.side : s;
+        ProfScope ps(blk == 0 ? "vcycle_u" : "vcycle_phi", st, 0.0);
+        if (amg.opts.precision == 32)
+            vcycle<float>(amg.h[blk], 0, static_cast<float*>(vin) + off[blk], amg.opts, st,
+                          static_cast<float*>(vout) + off[blk]);
+        else
+            vcycle<double>(amg.h[blk], 0, static_cast<double*>(vin) + off[blk], amg.opts, st,
+                           static_cast<double*>(vout) + off[blk]);
+    }
     FR_HIP(hipEventRecord(amg.ev_join, amg.side));
     FR_HIP(hipStreamWaitEvent(s, amg.ev_join, 0));
 }

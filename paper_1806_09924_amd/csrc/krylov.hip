@@ -9,6 +9,12 @@
 // multi-vector dot sweep, one fused update + dot sweep, one update + norm sweep.  Givens
 // rotations, the convergence test and the back substitution run on the device, one thread
 // per instance; the host reads one flag word per instance per iteration to stop.
+//
+// The Krylov index j of the current cycle lives on the device (State::j): every kernel of an
+// Arnoldi step reads it there (basis pointers, vector counts, the Givens column), and the step's
+// last kernel advances it.  An Arnoldi step is therefore the same launch sequence for every j,
+// and with use_graphs it is captured once per preconditioner setup (both V-cycles, J z,
+// Gram-Schmidt, rotations, summary) as one HIP graph that the host replays once per iteration.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -38,10 +44,11 @@ struct Seg {
 // part[v * nb + g] = sum over segment g of V_v[i] w[i] (v < nv), and with `self` also
 // part[nv * nb + g] = sum of w[i]^2.  Segments of an instance whose flag in `need` is 0 are
 // skipped (need may be null); the grid may be smaller than the segment count.
-__global__ void __launch_bounds__(256) k_seg_dots(const double* __restrict__ V, int64_t n, int nv,
+__global__ void __launch_bounds__(256) k_seg_dots(const double* __restrict__ V, int64_t n, const int* __restrict__ jp,
                                                   const double* __restrict__ w, Seg sg, int nb,
                                                   double* __restrict__ part, const int* __restrict__ need, int self) {
     __shared__ double sh[kMaxM + 8][4];
+    const int nv = *jp + 1;   // V_0 .. V_j
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int rows = nv + (self ? 1 : 0);
     for (int g = blockIdx.x; g < nb; g += gridDim.x) {
@@ -82,12 +89,13 @@ __global__ void __launch_bounds__(256) k_seg_dots(const double* __restrict__ V, 
 // w -= sum_k c_inst[k] V_k; part[g] = sum of the new w^2 over segment g.  Segments of an
 // instance whose flag in `need` is 0 are skipped (need may be null); the grid may be
 // smaller than the segment count.
-__global__ void __launch_bounds__(256) k_seg_update_norm(const double* __restrict__ V, int64_t n, int nv,
-                                                         const double* __restrict__ c, int cstride,
-                                                         double* __restrict__ w, Seg sg, int nb,
+__global__ void __launch_bounds__(256) k_seg_update_norm(const double* __restrict__ V, int64_t n,
+                                                         const int* __restrict__ jp, const double* __restrict__ c,
+                                                         int cstride, double* __restrict__ w, Seg sg, int nb,
                                                          double* __restrict__ part, const int* __restrict__ need) {
     __shared__ double sh[16];
     __shared__ double cs[kMaxM + 8];
+    const int nv = *jp + 1;
     for (int g = blockIdx.x; g < nb; g += gridDim.x) {
         if (need && !need[sg.inst[g]]) continue;
         const int64_t s0 = sg.start[g];
@@ -132,11 +140,14 @@ __global__ void __launch_bounds__(256) k_seg_resid(const double* __restrict__ F,
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// dst = src * scale[inst]; also the preconditioner's input when it is staged: the same
-// values in FP32 (u part, solve index < n_u, to f_u; phi part to f_p) or in FP64 (d_copy).
+// dst = src * scale[inst] (with jp: dst + (*jp + 1) n, the next basis vector); also the
+// preconditioner's input when it is staged: the same values in FP32 (u part, solve index < n_u,
+// to f_u; phi part to f_p) or in FP64 (d_copy).
 __global__ void __launch_bounds__(256) k_seg_scale(const double* __restrict__ src, double* __restrict__ dst,
+                                                   const int* __restrict__ jp, int64_t n,
                                                    const double* __restrict__ scale, Seg sg, float* __restrict__ f_u,
                                                    float* __restrict__ f_p, int64_t n_u, double* __restrict__ d_copy) {
+    if (jp) dst += int64_t(*jp + 1) * n;
     const int64_t s0 = sg.start[blockIdx.x];
     const int len = sg.len[blockIdx.x];
     const double a = scale[sg.inst[blockIdx.x]];
@@ -179,15 +190,18 @@ __global__ void __launch_bounds__(256) k_seg_combine(const TZ* __restrict__ Z, i
 }
 
 // out[inst * stride + v] = sum of part[v * nb + b] over the blocks of the instance (only
-// for instances whose flag in `only` is set, when given).  Four independent partial sums
-// per thread keep several loads in flight; the order is fixed.
+// for instances whose flag in `only` is set, when given; with jp only for v < *jp + 1 + extra,
+// the grid covering the largest count).  Four independent partial sums per thread keep several
+// loads in flight; the order is fixed.
 constexpr int kReduceT = 512;
 __global__ void __launch_bounds__(kReduceT) k_seg_reduce(const double* __restrict__ part, int nb,
                                                          const int32_t* __restrict__ bptr, double* __restrict__ out,
-                                                         int stride, const int* __restrict__ only = nullptr) {
+                                                         int stride, const int* __restrict__ only = nullptr,
+                                                         const int* __restrict__ jp = nullptr, int extra = 0) {
     __shared__ double sh[16];
     const int v = blockIdx.x, inst = blockIdx.y;
     if (only && !only[inst]) return;
+    if (jp && v >= *jp + 1 + extra) return;
     const double* p = part + int64_t(v) * nb;
     const int b1 = bptr[inst + 1];
     double a[4] = {0.0, 0.0, 0.0, 0.0};
@@ -221,6 +235,7 @@ struct State {
     int* brk;        // [ni] breakdown: non-finite Arnoldi quantities, or a zero Arnoldi norm
                      //      whose cycle left the true residual above the target
     int* zhit;       // [ni] the last cycle ended on a zero Arnoldi norm
+    int* j;          // [1] Krylov index of the next Arnoldi step in the current cycle
 };
 
 // Classical Gram-Schmidt with the second pass only where it is needed: after one pass the
@@ -228,9 +243,10 @@ struct State {
 // |w_before| / |w_after|, so the pass is repeated where the norm dropped below eta times its
 // value before (h1[nv] holds |w_before|^2, nrm2 |w_after|^2).  h2 is cleared everywhere;
 // the second pass fills it where it runs.
-__global__ void k_reorth_decide(int ni, int m, int nv, State st, double eta2) {
+__global__ void k_reorth_decide(int ni, int m, State st, double eta2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ni) return;
+    const int nv = *st.j + 1;
     double* h2 = st.h2 + int64_t(i) * (m + 2);
     for (int k = 0; k <= nv; ++k) h2[k] = 0.0;
     const double before = st.h1[int64_t(i) * (m + 2) + nv];
@@ -259,9 +275,10 @@ __global__ void k_cycle_start(int ni, int m, State st) {
 
 // Hessenberg column j: combine the two passes, apply the previous rotations, make the new
 // one, update g, test convergence.  Instances already done are left untouched.
-__global__ void k_givens(int ni, int m, int j, State st) {
+__global__ void k_givens(int ni, int m, State st) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ni) return;
+    const int j = *st.j;
     if (st.done[i]) {
         st.scale[i] = 0.0;
         return;
@@ -310,10 +327,12 @@ __global__ void k_givens(int ni, int m, int j, State st) {
 }
 
 // The host's view of iteration j: whether every instance is done, and how far the running
-// ones still are from their targets.
-__global__ void k_summary(int ni, int m, int j, State st, IterSummary* out) {
+// ones still are from their targets, written to out[j & 1] (the host reads the two slots
+// alternately); then the step's Krylov index advances.
+__global__ void k_summary(int ni, int m, State st, IterSummary* out) {
     __shared__ int all;
     __shared__ double worst;
+    const int j = *st.j;
     if (threadIdx.x == 0) { all = 1; worst = 0.0; }
     __syncthreads();
     for (int i = threadIdx.x; i < ni; i += blockDim.x) {
@@ -325,10 +344,16 @@ __global__ void k_summary(int ni, int m, int j, State st, IterSummary* out) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        out->all_done = all;
-        out->pad = 0;
-        out->ratio = worst;
+        IterSummary& o = out[j & 1];
+        o.all_done = all;
+        o.pad = 0;
+        o.ratio = worst;
+        *st.j = j + 1;
     }
+}
+
+__global__ void k_set_int(int* p, int v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
 // y = H^-1 g on the jused x jused upper triangle
@@ -397,6 +422,127 @@ static void grow_basis(DevKrylov& ws, int j, hipStream_t s) {
     ws.cap = cap;
 }
 
+// Everything one Arnoldi step needs; the step itself reads the Krylov index from the device.
+struct StepCtx {
+    DevSystem* sys;
+    DevAmg* amg;
+    DevKrylov* ws;
+    State st;
+    Seg sg;
+    int ni, M;
+    int64_t n;
+    bool z32, staged;          // staged: the preconditioner runs from / to the fixed staged buffers
+    float* f_u;
+    float* f_p;
+    double* d_copy;            // staging targets of k_seg_scale (null: none)
+    void* vout;                // staged preconditioner output
+};
+
+// One Arnoldi step at the device's Krylov index j: z = M^-1 v_j (kept as Z_j), w = J z, CGS2
+// against V_0..V_j, the Hessenberg column and its rotations, v_{j+1} = w / |w| (and the next
+// staged preconditioner input), the summary of the step, j + 1.  j_host is used only for the
+// unstaged preconditioner call (direct launches); a staged step is the same launch sequence for
+// every j, so it can be captured.
+static void arnoldi_step(const StepCtx& c, int j_host, hipStream_t s) {
+    DevSystem& sys = *c.sys;
+    DevKrylov& ws = *c.ws;
+    const State& st = c.st;
+    const int64_t n = c.n;
+    const int nb = ws.nb;
+    const int ni = c.ni;
+    const int gi = int(ceil_div(ni, 64));
+    if (c.staged) {
+        // both V-cycles from the staged input; the product J z copies z into Z_j as it reads it
+        amg_precondition_staged(*c.amg, s);
+        if (c.z32) jspmv_copy(sys, static_cast<const float*>(c.vout), ws.w.p, ws.Z32.p, st.j, n, s);
+        else jspmv_copy(sys, static_cast<const double*>(c.vout), ws.w.p, ws.Z.p, st.j, n, s);
+    } else if (c.z32) {
+        float* Zj = ws.Z32.p + int64_t(j_host) * n;
+        amg_precondition32(*c.amg, nullptr, Zj, s);   // input staged by k_seg_scale
+        jspmv(sys, Zj, ws.w.p, s);
+    } else {
+        double* Zj = ws.Z.p + int64_t(j_host) * n;
+        amg_precondition(*c.amg, ws.V.p + int64_t(j_host) * n, Zj, s);
+        jspmv(sys, Zj, ws.w.p, s);
+    }
+    // Gram-Schmidt reductions cover the largest vector count of the current basis; rows past
+    // the step's own count return at once
+    const int rows = ws.cap + 2;
+    const int nv_h = j_host + 1;   // for the profile's byte counts only
+    const double md_bytes = double(nv_h + 1) * double(n) * 8.0;
+    const double up_bytes = double(nv_h + 2) * double(n) * 8.0;
+    const int gc = std::min(nb, 1024);   // grid of the conditional second pass
+    double* part = ws.part.p;
+    const int M = c.M;
+    {
+        ProfScope ps("gs_multidot", s, md_bytes);
+        k_seg_dots<<<nb, 256, 0, s>>>(ws.V.p, n, st.j, ws.w.p, c.sg, nb, part, nullptr, 1);
+        FR_LAUNCH_CHECK();
+    }
+    k_seg_reduce<<<dim3(rows, ni), kReduceT, 0, s>>>(part, nb, ws.seg_bptr.p, st.h1, M + 2, nullptr, st.j, 1);
+    FR_LAUNCH_CHECK();
+    {
+        ProfScope ps("gs_update", s, up_bytes);
+        k_seg_update_norm<<<nb, 256, 0, s>>>(ws.V.p, n, st.j, st.h1, M + 2, ws.w.p, c.sg, nb, part, nullptr);
+        FR_LAUNCH_CHECK();
+    }
+    k_seg_reduce<<<dim3(1, ni), kReduceT, 0, s>>>(part, nb, ws.seg_bptr.p, st.nrm2, 1);
+    FR_LAUNCH_CHECK();
+    k_reorth_decide<<<gi, 64, 0, s>>>(ni, M, st, kReorthEta * kReorthEta);
+    FR_LAUNCH_CHECK();
+    {
+        // the bytes depend on how many instances need the pass (a device decision)
+        ProfScope ps("gs_second_pass", s, 0.0);
+        k_seg_dots<<<gc, 256, 0, s>>>(ws.V.p, n, st.j, ws.w.p, c.sg, nb, part, st.need, 0);
+        FR_LAUNCH_CHECK();
+        k_seg_reduce<<<dim3(rows, ni), kReduceT, 0, s>>>(part, nb, ws.seg_bptr.p, st.h2, M + 2, st.need, st.j, 0);
+        FR_LAUNCH_CHECK();
+        k_seg_update_norm<<<gc, 256, 0, s>>>(ws.V.p, n, st.j, st.h2, M + 2, ws.w.p, c.sg, nb, part, st.need);
+        FR_LAUNCH_CHECK();
+        k_seg_reduce<<<dim3(1, ni), kReduceT, 0, s>>>(part, nb, ws.seg_bptr.p, st.nrm2, 1, st.need);
+        FR_LAUNCH_CHECK();
+    }
+    k_givens<<<gi, 64, 0, s>>>(ni, M, st);
+    FR_LAUNCH_CHECK();
+    k_seg_scale<<<nb, 256, 0, s>>>(ws.w.p, ws.V.p, st.j, n, st.scale, c.sg, c.f_u, c.f_p, sys.n_u, c.d_copy);
+    FR_LAUNCH_CHECK();
+    k_summary<<<1, 64, 0, s>>>(ni, M, st, ws.dsum.p);
+    FR_LAUNCH_CHECK();
+    FR_HIP(hipMemcpyAsync(ws.hsum, ws.dsum.p, 2 * sizeof(IterSummary), hipMemcpyDeviceToHost, s));
+}
+
+// The captured Arnoldi step of the current preconditioner, basis capacity and workspace
+// (captured again when any of them changed).  The capture runs on a stream of the workspace (the
+// caller's may be the legacy default stream, which cannot be captured) after s has drained, so
+// that every buffer it records exists.
+static hipGraphExec_t step_graph(const StepCtx& c, hipStream_t s) {
+    DevKrylov& ws = *c.ws;
+    const IterKey key{c.sys, c.amg, c.amg->epoch, ws.cap, ws.V.p, c.z32 ? static_cast<void*>(ws.Z32.p)
+                                                                          : static_cast<void*>(ws.Z.p)};
+    if (ws.step_exec && ws.step_key == key) return ws.step_exec;
+    FR_HIP(hipStreamSynchronize(s));
+    ws.drop_step();
+    if (!ws.cstream) FR_HIP(hipStreamCreateWithFlags(&ws.cstream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    FR_HIP(hipStreamBeginCapture(ws.cstream, hipStreamCaptureModeThreadLocal));
+    try {
+        arnoldi_step(c, 0, ws.cstream);
+    } catch (...) {
+        (void)hipStreamEndCapture(ws.cstream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    FR_HIP(hipStreamEndCapture(ws.cstream, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    FR_HIP(e);
+    ws.step_exec = ex;
+    ws.step_key = key;
+    ++ws.captures;
+    return ex;
+}
+
 fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du, fr_solve_stats* stats,
                  DevKrylov& ws, hipStream_t s) {
     const int64_t n = sys.n_solve;
@@ -406,7 +552,7 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
     if (!ws.hsum) {
         FR_HIP(hipHostMalloc(reinterpret_cast<void**>(&ws.hsum), 2 * sizeof(IterSummary), hipHostMallocDefault));
         for (auto& e : ws.ev_sum) FR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        ws.dsum.alloc(1, s);
+        ws.dsum.alloc(2, s);
     }
     if (ws.n != n || ws.m != m || ws.n_inst != ni || ws.z32 != z32) {
         ws.n = n;
@@ -428,7 +574,7 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
         ws.part.alloc(size_t(ws.nb) * (kMaxM + 2) + 64, s);
         const size_t per = size_t(2 * (m + 2) + 1 + (m + 1) * m + 2 * m + (m + 1) + m + 3);
         ws.state.alloc(per * size_t(ni), s);
-        ws.istate.alloc(size_t(6 * ni), s);
+        ws.istate.alloc(size_t(6 * ni) + 1, s);
     }
     const int M = ws.m;
     State st;
@@ -452,29 +598,28 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
         st.need = ws.istate.p + 3 * ni;
         st.brk = ws.istate.p + 4 * ni;
         st.zhit = ws.istate.p + 5 * ni;
+        st.j = ws.istate.p + 6 * ni;
     }
     const Seg sg{ws.seg_start.p, ws.seg_len.p, ws.seg_inst.p};
-    // The preconditioner's argument is staged while the basis vector is written: for graph
-    // replay into the graphs' fixed input (FP32 or FP64); without graphs, with the FP32
-    // hierarchy, straight into its level-0 right-hand sides.
+    // The preconditioner's argument is staged while the basis vector is written: with graphs
+    // into the fixed staged input (FP32 or FP64); without graphs, with the FP32 hierarchy,
+    // straight into its level-0 right-hand sides.
     const bool graphs = o.use_graphs != 0 && !prof_enabled();
-    float* f_u = nullptr;
-    float* f_p = nullptr;
-    double* d_copy = nullptr;
+    StepCtx c{&sys, &amg, &ws, st, sg, ni, M, n, z32, graphs, nullptr, nullptr, nullptr, nullptr};
     if (graphs && z32) {
-        f_u = static_cast<float*>(amg_graph_input(amg));
-        f_p = f_u + sys.n_u;
+        c.f_u = static_cast<float*>(amg_graph_input(amg));
+        c.f_p = c.f_u + sys.n_u;
     } else if (graphs) {
-        d_copy = static_cast<double*>(amg_graph_input(amg));
+        c.d_copy = static_cast<double*>(amg_graph_input(amg));
     } else if (z32) {
-        f_u = amg_input32(amg, 0);
-        f_p = amg_input32(amg, 1);
+        c.f_u = amg_input32(amg, 0);
+        c.f_p = amg_input32(amg, 1);
     }
-    void* vout = graphs ? amg_graph_output(amg) : nullptr;
+    if (graphs) c.vout = amg_graph_output(amg);
     const int nb = ws.nb;
     const int gi = int(ceil_div(ni, 64));
     double* part = ws.part.p;
-    FR_HIP(hipMemsetAsync(ws.istate.p, 0, size_t(6 * ni) * sizeof(int), s));
+    FR_HIP(hipMemsetAsync(ws.istate.p, 0, (size_t(6 * ni) + 1) * sizeof(int), s));
 
     // ||F_i||, targets
     k_seg_resid<<<nb, 256, 0, s>>>(sys.F.p, ws.w.p, 1, sg, part);
@@ -514,72 +659,22 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
             all_done = all_done && dn[size_t(i)];
         }
         if (all_done || total >= o.maxit) break;
-        k_seg_scale<<<nb, 256, 0, s>>>(ws.w.p, ws.V.p, st.scale, sg, f_u, f_p, sys.n_u, d_copy);
+        k_seg_scale<<<nb, 256, 0, s>>>(ws.w.p, ws.V.p, nullptr, n, st.scale, sg, c.f_u, c.f_p, sys.n_u, c.d_copy);
+        FR_LAUNCH_CHECK();
+        k_set_int<<<1, 64, 0, s>>>(st.j, 0);
         FR_LAUNCH_CHECK();
         int j = 0;
         for (; j < M && total < o.maxit; ++j) {
             if (j + 1 > ws.cap) grow_basis(ws, j, s);
-            double* Vj = ws.V.p + int64_t(j) * n;
-            if (graphs) {
-                // replayed V-cycles from the staged input; the product J z keeps z in the basis
-                amg_precondition_graph(amg, s);
-                if (z32) jspmv_copy(sys, static_cast<const float*>(vout), ws.w.p, ws.Z32.p + int64_t(j) * n, s);
-                else jspmv_copy(sys, static_cast<const double*>(vout), ws.w.p, ws.Z.p + int64_t(j) * n, s);
-            } else if (z32) {
-                float* Zj = ws.Z32.p + int64_t(j) * n;
-                amg_precondition32(amg, nullptr, Zj, s);   // input staged by k_seg_scale
-                jspmv(sys, Zj, ws.w.p, s);
-            } else {
-                double* Zj = ws.Z.p + int64_t(j) * n;
-                amg_precondition(amg, Vj, Zj, s);
-                jspmv(sys, Zj, ws.w.p, s);
-            }
-            const int nv = j + 1;
-            const double md_bytes = double(nv + 1) * double(n) * 8.0;
-            const double up_bytes = double(nv + 2) * double(n) * 8.0;
-            const int gc = std::min(nb, 1024);   // grid of the conditional second pass
-            {
-                ProfScope ps("gs_multidot", s, md_bytes);
-                k_seg_dots<<<nb, 256, 0, s>>>(ws.V.p, n, nv, ws.w.p, sg, nb, part, nullptr, 1);
-                FR_LAUNCH_CHECK();
-            }
-            k_seg_reduce<<<dim3(nv + 1, ni), kReduceT, 0, s>>>(part, nb, ws.seg_bptr.p, st.h1, M + 2);
-            FR_LAUNCH_CHECK();
-            {
-                ProfScope ps("gs_update", s, up_bytes);
-                k_seg_update_norm<<<nb, 256, 0, s>>>(ws.V.p, n, nv, st.h1, M + 2, ws.w.p, sg, nb, part, nullptr);
-                FR_LAUNCH_CHECK();
-            }
-            k_seg_reduce<<<dim3(1, ni), kReduceT, 0, s>>>(part, nb, ws.seg_bptr.p, st.nrm2, 1);
-            FR_LAUNCH_CHECK();
-            k_reorth_decide<<<gi, 64, 0, s>>>(ni, M, nv, st, kReorthEta * kReorthEta);
-            FR_LAUNCH_CHECK();
-            {
-                // the bytes depend on how many instances need the pass (a device decision)
-                ProfScope ps("gs_second_pass", s, 0.0);
-                k_seg_dots<<<gc, 256, 0, s>>>(ws.V.p, n, nv, ws.w.p, sg, nb, part, st.need, 0);
-                FR_LAUNCH_CHECK();
-                k_seg_reduce<<<dim3(nv, ni), kReduceT, 0, s>>>(part, nb, ws.seg_bptr.p, st.h2, M + 2, st.need);
-                FR_LAUNCH_CHECK();
-                k_seg_update_norm<<<gc, 256, 0, s>>>(ws.V.p, n, nv, st.h2, M + 2, ws.w.p, sg, nb, part, st.need);
-                FR_LAUNCH_CHECK();
-                k_seg_reduce<<<dim3(1, ni), kReduceT, 0, s>>>(part, nb, ws.seg_bptr.p, st.nrm2, 1, st.need);
-                FR_LAUNCH_CHECK();
-            }
-            k_givens<<<gi, 64, 0, s>>>(ni, M, j, st);
-            FR_LAUNCH_CHECK();
-            k_seg_scale<<<nb, 256, 0, s>>>(ws.w.p, ws.V.p + int64_t(j + 1) * n, st.scale, sg, f_u, f_p, sys.n_u,
-                                           d_copy);
-            FR_LAUNCH_CHECK();
-            // convergence readback without a round trip per iteration: the summary goes to a
-            // pinned ring; the host waits for it only when the previous iteration's summary
-            // (already on the host) leaves an instance within kSpecRatio of its target, and
-            // otherwise enqueues the next iteration at once.  An iteration run after every
-            // instance has finished changes nothing (finished instances are frozen).
-            const int slot = total & 1;
-            k_summary<<<1, 64, 0, s>>>(ni, M, j, st, ws.dsum.p);
-            FR_LAUNCH_CHECK();
-            FR_HIP(hipMemcpyAsync(&ws.hsum[slot], ws.dsum.p, sizeof(IterSummary), hipMemcpyDeviceToHost, s));
+            if (graphs) FR_HIP(hipGraphLaunch(step_graph(c, s), s));
+            else arnoldi_step(c, j, s);
+            // convergence readback without a round trip per iteration: the summary of step j
+            // lands in slot j & 1 of a pinned ring; the host waits for it only when the
+            // previous step's summary (already on the host) leaves an instance within
+            // kSpecRatio of its target, and otherwise enqueues the next step at once.  A step
+            // run after every instance has finished changes nothing (finished instances are
+            // frozen).
+            const int slot = j & 1;
             FR_HIP(hipEventRecord(ws.ev_sum[slot], s));
             ++total;
             bool wait = true;
@@ -613,6 +708,7 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
         // instances with a non-finite residual or a breakdown are marked done by the next
         // cycle start; the others go on
     }
+    ws.last_iters = total;
     std::vector<int> bad = download(st.bad, size_t(ni), s);
     std::vector<int> brk = download(st.brk, size_t(ni), s);
     fr_status worst = FR_OK;

@@ -224,7 +224,8 @@ __global__ void __launch_bounds__(256) k_jspmv(int64_t nf, int C, const int32_t*
                                                const CI* __restrict__ col, const double* __restrict__ uu,
                                                const double* __restrict__ pu, const double* __restrict__ pp,
                                                const TX* __restrict__ x, double* __restrict__ y,
-                                               TX* __restrict__ xcopy) {
+                                               TX* __restrict__ xcopy, const int* __restrict__ jp,
+                                               int64_t xstride) {
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= nf) return;
     const int64_t s = r / C;
@@ -256,9 +257,10 @@ __global__ void __launch_bounds__(256) k_jspmv(int64_t nf, int C, const int32_t*
     for (int i = 0; i < D; ++i) y[r * D + i] = au[i];
     y[D * nf + r] = ap;
     if (xcopy) {   // the row's own entries of x, kept (the vector x is a scratch copy)
+        TX* xc = jp ? xcopy + int64_t(*jp) * xstride : xcopy;   // Z_j of the device's Krylov index
 #pragma unroll
-        for (int i = 0; i < D; ++i) xcopy[r * D + i] = x[r * D + i];
-        xcopy[D * nf + r] = xp[r];
+        for (int i = 0; i < D; ++i) xc[r * D + i] = x[r * D + i];
+        xc[D * nf + r] = xp[r];
     }
 }
 
@@ -900,7 +902,8 @@ void cheb_first(const T* invd, const T* b, T* d, T* x, T beta, int64_t n, hipStr
 }
 
 template <typename TX>
-static void jspmv_t(const DevSystem& sys, const TX* x, double* y, hipStream_t s, TX* xcopy = nullptr) {
+static void jspmv_t(const DevSystem& sys, const TX* x, double* y, hipStream_t s, TX* xcopy = nullptr,
+                    const int* jp = nullptr, int64_t xstride = 0) {
     const SellStruct& S = *sys.Juu.S;
     const int g = nblk(S.n_rows, 256);
     const int D = sys.mesh->dim;
@@ -911,7 +914,7 @@ static void jspmv_t(const DevSystem& sys, const TX* x, double* y, hipStream_t s,
     ProfScope ps(name, s, bytes);
 #define FR_JSPMV(D_, CI_, COL_)                                                                        \
     k_jspmv<D_, TX, CI_><<<g, 256, 0, s>>>(S.n_rows, S.C, S.slice_ptr, COL_, sys.Juu.val, sys.Jpu.val, sys.Jpp.val, \
-                                           x, y, xcopy);
+                                           x, y, xcopy, jp, xstride);
     if (D == 2) {
         if (S.col16) { FR_JSPMV(2, int16_t, S.col16) }
         else { FR_JSPMV(2, int32_t, S.col) }
@@ -925,11 +928,13 @@ static void jspmv_t(const DevSystem& sys, const TX* x, double* y, hipStream_t s,
 
 void jspmv(const DevSystem& sys, const double* x, double* y, hipStream_t s) { jspmv_t<double>(sys, x, y, s); }
 void jspmv(const DevSystem& sys, const float* x, double* y, hipStream_t s) { jspmv_t<float>(sys, x, y, s); }
-void jspmv_copy(const DevSystem& sys, const double* x, double* y, double* xcopy, hipStream_t s) {
-    jspmv_t<double>(sys, x, y, s, xcopy);
+void jspmv_copy(const DevSystem& sys, const double* x, double* y, double* xcopy, const int* jp, int64_t xstride,
+                hipStream_t s) {
+    jspmv_t<double>(sys, x, y, s, xcopy, jp, xstride);
 }
-void jspmv_copy(const DevSystem& sys, const float* x, double* y, float* xcopy, hipStream_t s) {
-    jspmv_t<float>(sys, x, y, s, xcopy);
+void jspmv_copy(const DevSystem& sys, const float* x, double* y, float* xcopy, const int* jp, int64_t xstride,
+                hipStream_t s) {
+    jspmv_t<float>(sys, x, y, s, xcopy, jp, xstride);
 }
 
 void system_matvec(DevSystem& sys, const double* x, double* y) { jspmv(sys, x, y, sys.stream); }

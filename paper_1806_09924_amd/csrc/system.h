@@ -200,9 +200,11 @@ void tune_clear();
 int tune_entries();
 void jspmv(const DevSystem& sys, const double* x, double* y, hipStream_t s);
 void jspmv(const DevSystem& sys, const float* x, double* y, hipStream_t s);
-// the same, also copying x to xcopy
-void jspmv_copy(const DevSystem& sys, const double* x, double* y, double* xcopy, hipStream_t s);
-void jspmv_copy(const DevSystem& sys, const float* x, double* y, float* xcopy, hipStream_t s);
+// the same, also copying x to xcopy + (*jp) xstride (the Krylov basis slot of the device's index)
+void jspmv_copy(const DevSystem& sys, const double* x, double* y, double* xcopy, const int* jp, int64_t xstride,
+                hipStream_t s);
+void jspmv_copy(const DevSystem& sys, const float* x, double* y, float* xcopy, const int* jp, int64_t xstride,
+                hipStream_t s);
 
 // ---- AMG (amg.hip) ----------------------------------------------------------------------
 struct AmgLevel {
@@ -236,22 +238,17 @@ struct DevAmg {
     hipStream_t aux[2] = {nullptr, nullptr};     // setup: power iterations of the u / phi hierarchy
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     DBuf<float> z32;                             // FP32 result staging of amg_precondition
-    // Replayable V-cycles: each block's cycle captured once per setup as a HIP graph that
-    // reads the fixed input vin and writes the fixed output vout (solve order, [u | phi], in
-    // the hierarchy's precision).  Destroyed at every setup.
+    // Staged preconditioner input and output (solve order, [u | phi], in the hierarchy's
+    // precision) of amg_precondition_staged, the form a captured FGMRES iteration uses; epoch
+    // counts the setups and buffer changes after which such a capture is stale.
     DBuf<double> vin64, vout64;
     DBuf<float> vin32, vout32;
-    hipGraphExec_t vgraph[2] = {nullptr, nullptr};
-    void drop_graphs() {
-        for (auto& g : vgraph)
-            if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
-    }
+    uint64_t epoch = 0;
     ~DevAmg() {
         for (auto a : aux)
             if (a) (void)hipStreamSynchronize(a);
         if (side) (void)hipStreamSynchronize(side);
         if (stream) (void)hipStreamSynchronize(stream);
-        drop_graphs();
         // the phase-field hierarchy's buffers are freed on the side stream: before it goes
         for (auto& H : h) {
             H.lv.clear();
@@ -274,10 +271,10 @@ void amg_precondition(DevAmg& amg, const double* r, double* z, hipStream_t s);
 // level-0 right-hand sides, amg_input32(amg, 0) (u part) and amg_input32(amg, 1) (phi part).
 void amg_precondition32(DevAmg& amg, const double* r, float* z, hipStream_t s);
 float* amg_input32(DevAmg& amg, int blk);
-// Graph replay of the two V-cycles (captured on first use after a setup): the input is read
-// from amg_graph_input (the caller stages M^-1's argument there, in the hierarchy's precision,
-// solve order) and the result left in amg_graph_output.
-void amg_precondition_graph(DevAmg& amg, hipStream_t s);
+// The two V-cycles (u on s, phi on the side stream) from the staged input amg_graph_input
+// (the caller stages M^-1's argument there, in the hierarchy's precision, solve order) to the
+// staged output amg_graph_output; fixed buffers, so the launches can be captured in a graph.
+void amg_precondition_staged(DevAmg& amg, hipStream_t s);
 void* amg_graph_input(DevAmg& amg);
 void* amg_graph_output(DevAmg& amg);
 void amg_level_export(DevAmg& amg, int blk, int level, int which, int64_t& n_rows, int64_t& n_cols,
@@ -296,12 +293,35 @@ struct IterSummary {
     double ratio;      // largest |residual estimate| / target over the running instances
 };
 
+// What a captured Arnoldi step depends on: the system, the preconditioner and its setup epoch,
+// the basis capacity and the bases' addresses.
+struct IterKey {
+    const void* sys = nullptr;
+    const void* amg = nullptr;
+    uint64_t epoch = 0;
+    int cap = 0;
+    const void* V = nullptr;
+    const void* Z = nullptr;
+    bool operator==(const IterKey& o) const {
+        return sys == o.sys && amg == o.amg && epoch == o.epoch && cap == o.cap && V == o.V && Z == o.Z;
+    }
+};
+
 struct DevKrylov {
     int64_t n = 0;
     int m = 0, n_inst = 0, nb = 0;
-    DBuf<IterSummary> dsum;                      // device summary of the last iteration
+    DBuf<IterSummary> dsum;                      // [2] device summaries (slot j & 1)
     IterSummary* hsum = nullptr;                 // [2] pinned host ring
     hipEvent_t ev_sum[2] = {nullptr, nullptr};
+    // the captured Arnoldi step (use_graphs) and the stream it is captured on
+    hipGraphExec_t step_exec = nullptr;
+    IterKey step_key;
+    hipStream_t cstream = nullptr;
+    int64_t captures = 0;                        // captures made (one per preconditioner setup)
+    int last_iters = 0;                          // Arnoldi steps of the last solve
+    void drop_step() {
+        if (step_exec) { (void)hipGraphExecDestroy(step_exec); step_exec = nullptr; }
+    }
     DevKrylov() = default;
     DevKrylov(const DevKrylov&) = delete;
     DevKrylov& operator=(const DevKrylov&) = delete;
@@ -309,6 +329,8 @@ struct DevKrylov {
         for (auto& e : ev_sum)
             if (e) { (void)hipEventSynchronize(e); (void)hipEventDestroy(e); }
         if (hsum) (void)hipHostFree(hsum);
+        drop_step();
+        if (cstream) (void)hipStreamDestroy(cstream);
     }
     int cap = 0;                                 // vectors held in Z (V holds cap + 1)
     bool z32 = false;                            // Z kept in FP32 (FP32 preconditioner)
