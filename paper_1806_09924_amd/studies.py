@@ -20,8 +20,11 @@ loading step at half the load, crack-region and gradient-jump marks, refinement,
 phi and the previous phase field, and the step at the full load on the refined mesh, each stage
 timed.
 
-Run as `python -m paper_1806_09924_amd.studies [domain|cod|3d|refine] [64|32]` (prints one JSON
-object).
+launch_cost(): milliseconds per FGMRES iteration with the captured Arnoldi step and with direct
+launches, on a launch-bound 50 k-DoF mesh and on the 48-instance batch.
+
+Run as `python -m paper_1806_09924_amd.studies [domain|cod|3d|refine|launch] [64|32]` (prints one
+JSON object).
 """
 import json
 import sys
@@ -159,10 +162,16 @@ def cod_convergence(half_width, levels, refine_radius, l0=1.0, xs=(0.0, 0.5), pr
     return out
 
 
-def convergence_3d(refs=(7, 8, 9), refine_radius=0.4, precision=32, rtol=1e-8):
-    """One batched Newton loop over the refs' meshes: base 16^3 cells of edge 10/16 (ref 4),
-    ref - 4 levels within refine_radius of the crack disk, eps = 2 sqrt(3) h_min.  Returns per
-    ref the DoFs (4 per node), eps, TCV and the relative error against Sneddon's closed form."""
+def convergence_3d(refs=(7, 8, 9), refine_radius=0.4, precision=32, rtol=1e-8, steps=1):
+    """The refs' meshes in one batch: base 16^3 cells of edge 10/16 (ref 4), ref - 4 levels within
+    refine_radius of the crack disk, eps = 2 sqrt(3) h_min.  steps = 1: one Newton loop from the
+    sharp initial crack (phi_tilde = phi_old = phi_0).  steps > 1: that many quasi-static loading
+    steps at the constant pressure (fracture_loading: phi_old the previous step's phase field,
+    phi_tilde extrapolated in time), the phase field relaxing from the sharp initial band to its
+    stationary profile; the later steps start at equilibrium, so their Newton stop test has the
+    absolute floor 1e-8 x the smallest first-step residual.  Returns per ref the DoFs (4 per
+    node), eps, the TCV after every step, and the final TCV's relative error against Sneddon's
+    closed form."""
     from inputs import crack_band_phi   # the workloads' initial crack field
     descs = [B.mesh_desc(3, -5.0, 5.0, 16, levels=r - 4, refine_radius=refine_radius, crack_half_len=1.0)
              for r in refs]
@@ -183,23 +192,36 @@ def convergence_3d(refs=(7, 8, 9), refine_radius=0.4, precision=32, rtol=1e-8):
     p0 = torch.as_tensor(phi0, device=dev)
     u = torch.zeros((mesh.n_nodes, 3), dtype=torch.float64, device=dev)
     phi = p0.clone()
+    amg, sol = B.amg_opts(precision=precision), B.solve_opts(rtol=rtol)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = B.newton(mesh, prms, u, phi, p0, p0, amg=B.amg_opts(precision=precision), solve=B.solve_opts(rtol=rtol))
+    one = lambda x: x if isinstance(x, list) else [x]  # one ref: the binding returns one dict
+    st1, tcv1 = B.loading(mesh, [prms], [0.0, 1.0], u, phi, amg=amg, solve=sol)
+    stats = [one(st1[0])]
+    tcvs = [np.atleast_1d(tcv1)[:len(refs)] if len(refs) > 1 else np.atleast_1d(tcv1)]
+    if steps > 1:
+        atol = 1e-8 * min(s["res0"] for s in stats[0])
+        st, tcv = B.loading(mesh, [prms] * (steps - 1), np.arange(1.0, steps + 1.0), u, phi, phi_prev=p0,
+                            t_prev=0.0, amg=amg, solve=sol, newton=B.newton_opts(atol=atol))
+        tcv = np.asarray(tcv).reshape(steps - 1, len(refs))
+        for k in range(steps - 1):
+            stats.append(one(st[k]))
+            tcvs.append(tcv[k])
     torch.cuda.synchronize()
     t_newton = time.perf_counter() - t0
-    _, tcv = B.functionals(mesh, u, phi)
-    st = st if isinstance(st, list) else [st]          # one ref: the binding returns one dict
-    tcv = np.atleast_1d(tcv)
     exact = 16.0 * 1e-3 * 1.0 ** 3 * (1 - 0.2 ** 2) / (3.0 * 1.0)
     rows = []
     for i, r in enumerate(refs):
-        assert st[i]["status"] == 0, (r, st[i])
+        for k in range(len(stats)):
+            assert stats[k][i]["status"] == 0, (r, k, stats[k][i])
+        t_steps = [float(np.asarray(t).reshape(-1)[i]) for t in tcvs]
         rows.append(dict(ref=r, ten_l0_over_h=2 ** r,
-                         h_min=inst[i]["h_min"], n_dofs=4 * inst[i]["n_nodes"], eps=epss[i], tcv=float(tcv[i]),
-                         rel_error=float(tcv[i] / exact - 1), newton=st[i]["iterations"], fgmres=st[i]["linear_iters"]))
-    return dict(rows=rows, exact=exact, refine_radius=refine_radius, precision=precision, t_mesh=t_mesh,
-                t_newton=t_newton, n_dofs=int(4 * mesh.n_nodes))
+                         h_min=inst[i]["h_min"], n_dofs=4 * inst[i]["n_nodes"], eps=epss[i], tcv=t_steps[-1],
+                         tcv_steps=t_steps, rel_error=float(t_steps[-1] / exact - 1),
+                         rel_error_first_step=float(t_steps[0] / exact - 1),
+                         newton=[s[i]["iterations"] for s in stats], fgmres=[s[i]["linear_iters"] for s in stats]))
+    return dict(rows=rows, exact=exact, refine_radius=refine_radius, precision=precision, steps=steps,
+                t_mesh=t_mesh, t_newton=t_newton, n_dofs=int(4 * mesh.n_nodes))
 
 
 def loading_refinement(n=2048, L=10.0, l0=0.25, kelly_fraction=0.01, precision=64):
@@ -259,15 +281,75 @@ def loading_refinement(n=2048, L=10.0, l0=0.25, kelly_fraction=0.01, precision=6
     return out
 
 
+def launch_cost(repeats=5, batch=True):
+    """Time per FGMRES iteration with the captured Arnoldi step (one graph launch per iteration)
+    and with direct launches, on the 128 x 128 mesh of [-2, 2]^2 (50 k DoFs: launch bound) and on
+    the 48-instance batch of the batched studies (46.8 M DoFs): one Newton step's solve to 1e-8,
+    FP64 hierarchy, repeated; wall and host CPU milliseconds per iteration (the best repeat;
+    the first graph solve after a setup, which captures the step, is reported apart)."""
+    from inputs import crack_band_phi, batched_instances
+
+    def measure(mesh, prm, phi0):
+        u = torch.zeros((mesh.n_nodes, mesh.dim), dtype=torch.float64, device="cuda")
+        phi = torch.as_tensor(phi0, dtype=torch.float64, device="cuda")
+        S = B.System(mesh).assemble(prm, u, phi, phi, phi)
+        A = B.Amg(S)
+        du = torch.empty(mesh.n_solve, dtype=torch.float64, device="cuda")
+        row = {"n_solve": mesh.n_solve}
+        for g in (0, 1):
+            best = None
+            for r in range(repeats + 1):
+                if g == 1 and r == 0:
+                    A.setup()            # a fresh setup: the first graph solve captures the step
+                torch.cuda.synchronize()
+                c0, t0 = time.process_time(), time.perf_counter()
+                st = B.solve(S, A, du, B.solve_opts(use_graphs=g))
+                torch.cuda.synchronize()
+                t1, c1 = time.perf_counter(), time.process_time()
+                its = st["iters"] if isinstance(st, dict) else max(x["iters"] for x in st)
+                cur = (1e3 * (t1 - t0) / its, 1e3 * (c1 - c0) / its, its)
+                if g == 1 and r == 0:
+                    row["graph_first_solve_ms"] = 1e3 * (t1 - t0)
+                    continue
+                if best is None or cur[0] < best[0]:
+                    best = cur
+            key = "graph" if g else "direct"
+            row[key] = {"wall_ms_per_iter": best[0], "host_cpu_ms_per_iter": best[1], "iters": best[2]}
+        return row
+
+    out = {}
+    L, n = 2.0, 128
+    m = B.Mesh(B.mesh_desc(2, -L, L, n))
+    eps = 2 * 2 * L / n
+    out["sneddon2d_128"] = measure(m, B.params(eps=eps), crack_band_phi(m.nodes()[0], 0.25, eps))
+    if batch:
+        ws = batched_instances()
+        descs = [B.mesh_desc(2, -w.L, w.L, w.n) for w in ws]
+        bm = B.Mesh(descs)
+        xyz = bm.nodes()[0]
+        phis = []
+        for i, w in enumerate(ws):
+            nd = bm.instance(i)
+            phis.append(crack_band_phi(xyz[nd["node_offset"]:nd["node_offset"] + nd["n_nodes"]], w.l0, w.eps,
+                                       (w.center[0], w.center[1], 0.0)))
+        out["batch48"] = measure(bm, [B.params(**w.params()) for w in ws], np.concatenate(phis))
+    return out
+
+
 def main(argv=None):
     argv = list(argv or [])
-    which = argv.pop(0) if argv and argv[0] in ("domain", "cod", "3d", "refine") else "domain"
+    which = argv.pop(0) if argv and argv[0] in ("domain", "cod", "3d", "refine", "launch") else "domain"
     precision = int(argv[0]) if argv else 64
+    if which == "launch":
+        print(json.dumps(launch_cost()))
+        return
     if which == "refine":
         print(json.dumps(loading_refinement(precision=precision)))
         return
     if which == "3d":
-        print(json.dumps(convergence_3d(precision=precision)))
+        refs = tuple(int(r) for r in argv[1].split(",")) if len(argv) > 1 else (7, 8, 9)
+        steps = int(argv[2]) if len(argv) > 2 else 1
+        print(json.dumps(convergence_3d(refs=refs, precision=precision, steps=steps)))
         return
     if which == "cod":
         from inputs import cod_study

@@ -131,3 +131,68 @@ def test_fullsize_newton_loop_kkt_and_functionals(big):
     assert abs(cod[0] / ofun.cod(om, ug, pg, xs[0]) - 1) <= 1e-12
     exact = ofun.sneddon_tcv(2, 1e-3, L0, 1.0, 0.2)
     assert abs(tcv / exact - 1) <= 0.10
+
+
+def _full_residual(om, oprm, u, phi, pt, chunk=1 << 19):
+    """The oracle's uncondensed residual and lumped mass over every cell, in cell chunks."""
+    Ru = np.zeros((om.n_nodes, 2))
+    Rp = np.zeros(om.n_nodes)
+    mass = np.zeros(om.n_nodes)
+    for c0 in range(0, om.n_cells, chunk):
+        a, b, c = fem.residual_all(om, oprm, u, phi, pt, cells_idx=np.arange(c0, min(om.n_cells, c0 + chunk)))
+        Ru += a
+        Rp += b
+        mass += c
+    return Ru, Rp, mass
+
+
+def _masked_norm(om, Ru, Rp, active):
+    """||R~||: R with the Dirichlet u rows and the active phi rows zeroed (uniform mesh: every
+    node is free)."""
+    ru = np.where(om.dirichlet[:, None], 0.0, Ru)
+    rp = np.where(active, 0.0, Rp)
+    return float(np.sqrt((ru ** 2).sum() + (rp ** 2).sum()))
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_fullsize_newton_full_residual(big, precision):
+    """The whole residual vector of the GPU's Newton solution, evaluated by the oracle over all
+    4.2 M cells: the stop test of the Section 3 algorithm holds for it, with the active set the
+    library ends with (and which the oracle's own decision reproduces away from the threshold)."""
+    m, om, oprm = big["mesh"], big["om"], big["oprm"]
+    phi0 = big["phi0"]
+    u0 = np.zeros((om.n_nodes, 2))
+    if "res0" not in big:
+        Ru0, Rp0, mass0 = _full_residual(om, oprm, u0, phi0, phi0)
+        act0 = -Rp0 / mass0 - oprm.tau > 0.0
+        big["res0"] = _masked_norm(om, Ru0, Rp0, act0)
+    u = torch.zeros((om.n_nodes, 2), dtype=torch.float64, device="cuda")
+    phi = dev(phi0)
+    st = B.newton(m, big["prm"], u, phi, dev(phi0), dev(phi0), amg=B.amg_opts(precision=precision))
+    assert st["status"] == B.FR_OK
+    act = host(B.newton_masks(m)[0]).astype(bool)
+    ug, pg = host(u), host(phi)
+    Ru, Rp, mass = _full_residual(om, oprm, ug, pg, phi0)
+    margin = -Rp / mass + (pg - phi0) - oprm.tau
+    differ = (margin > 0) != act
+    assert not np.any(differ & (np.abs(margin) > 1e-9 * np.abs(margin).max())), np.nonzero(differ)[0][:10]
+    res = _masked_norm(om, Ru, Rp, act)
+    print(f"fp{precision}: oracle ||R~|| {res:.3e}, library {st['res']:.3e}, res0 {big['res0']:.3e}")
+    # the library's residual vector at the same state, entry by entry
+    S = B.System(m).assemble(big["prm"], u, phi, dev(phi0), dev(phi0), flags=B.FR_RESIDUAL)
+    Rg = host(S.vectors()[0])
+    nf = om.n_free
+    du_ = np.where(om.dirichlet[:, None], 0.0, Rg[:2 * nf].reshape(-1, 2) - Ru)
+    dp_ = np.where(act, 0.0, Rg[2 * nf:] - Rp)
+    diff = float(np.sqrt((du_ ** 2).sum() + (dp_ ** 2).sum()))
+    iu, ip = np.unravel_index(np.abs(du_).argmax(), du_.shape)[0], np.abs(dp_).argmax()
+    print(f"  ||R~_lib - R~_oracle|| {diff:.3e}; largest u-row diff {np.abs(du_).max():.3e} at node {iu} "
+          f"(R {Ru[iu]}), phi-row {np.abs(dp_).max():.3e} at node {ip} (R {Rp[ip]:.3e}, phi {pg[ip]:.6f}, "
+          f"phi0 {phi0[ip]}, active {act[ip]}); ||R~_lib|| {_masked_norm(om, Rg[:2 * nf].reshape(-1, 2), Rg[2 * nf:], act):.3e}")
+    # same initial residual as the library's (both sides decide A_0 in FP64 from complete rows)
+    assert abs(st["res0"] / big["res0"] - 1.0) <= 1e-10
+    assert res <= 1e-8 * big["res0"]
+    # the library's own norm of the final residual: 1e8 times below the residual's initial size
+    # the two assemblies' rounding differs visibly (measured about 20 % of it), so the two
+    # evaluations are compared on the scale of the stop tolerance
+    assert abs(res - st["res"]) <= 0.5e-8 * big["res0"]
