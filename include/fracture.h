@@ -105,6 +105,11 @@ typedef struct {
                             and reused by later setups.  Different
                             lane counts sum a row in a different order, so results are
                             reproducible for a given cache (amg_level_shape reports the choice). */
+    int fine_matrix_free; /* nonzero: on a uniform 2d mesh (one instance) the finest displacement level's
+                            smoother and residual, and the displacement rows of the J-SpMV in
+                            fracture_solve, apply M_uu matrix-free from phi_tilde (the same masked
+                            operator as the stored blocks, summed in another order: equal up to
+                            rounding); other meshes use the stored blocks either way */
 } fr_amg_opts;
 
 /* FGMRES options (right preconditioned, x0 = 0). */

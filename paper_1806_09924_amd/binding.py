@@ -36,7 +36,8 @@ class Params(ctypes.Structure):
 class AmgOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("theta", ctypes.c_double), ("cheb_degree", ctypes.c_int),
                 ("cheb_ratio", ctypes.c_double), ("coarse_max", ctypes.c_int), ("max_levels", ctypes.c_int),
-                ("reuse_u_block", ctypes.c_int), ("refresh_phi", ctypes.c_int), ("autotune", ctypes.c_int)]
+                ("reuse_u_block", ctypes.c_int), ("refresh_phi", ctypes.c_int), ("autotune", ctypes.c_int),
+                ("fine_matrix_free", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -174,9 +175,9 @@ def params(E=1.0, nu=0.2, Gc=1.0, kappa=1e-10, eps=1.0 / 16, p=1e-3, c_pdas=1.0,
 
 
 def amg_opts(precision=64, theta=-1.0, cheb_degree=2, cheb_ratio=8.0, coarse_max=96, max_levels=12,
-             reuse_u_block=1, refresh_phi=1, autotune=1):
+             reuse_u_block=1, refresh_phi=1, autotune=1, fine_matrix_free=1):
     return AmgOpts(precision, theta, cheb_degree, cheb_ratio, coarse_max, max_levels, reuse_u_block, refresh_phi,
-                   autotune)
+                   autotune, fine_matrix_free)
 
 
 def solve_opts(rtol=1e-8, restart=100, maxit=500, use_graphs=1):

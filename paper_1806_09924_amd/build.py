@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfracture.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["mesh.cpp", "profile.cpp", "pool.cpp", "assemble.hip", "sparse.hip", "amg.hip", "krylov.hip", "capi.cpp"]
+SOURCES = ["mesh.cpp", "profile.cpp", "pool.cpp", "assemble.hip", "sparse.hip", "mfree.hip", "amg.hip", "krylov.hip",
+           "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

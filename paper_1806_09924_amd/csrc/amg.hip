@@ -7,6 +7,7 @@
 // Chebyshev smoother and a dense inverse of the coarsest operator.  Every kernel
 // accumulates in a fixed order, so the hierarchy is bitwise reproducible.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <exception>
 #include <thread>
@@ -1785,11 +1786,12 @@ void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s)
     const bool refresh_phi = o.refresh_phi && amg.sys == &sys && !amg.h[1].lv.empty() && amg.h[1].refreshable &&
                              same_shape && amg.h[1].lv[0]->A.S == sys.Jpp.S;
     // graphs captured over the old hierarchy's buffers and coefficients are stale from here on
-    ++amg.epoch;
+    amg.epoch = next_epoch();
     amg.sys = &sys;
     amg.opts = o;
     amg.stream = s;
     ensure_side(amg);
+    amg.h[1].mf = nullptr;
     DevMesh& m = *sys.mesh;
     // fork: the side stream follows everything enqueued on s so far (the Jacobian, and
     // every earlier use of the buffers that the phase-field setup frees)
@@ -1844,6 +1846,8 @@ void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s)
     FR_HIP(hipEventRecord(amg.ev_join, side));
     FR_HIP(hipStreamWaitEvent(s, amg.ev_join, 0));
     amg.sys_version = sys.version;
+    // the fine displacement level applies M_uu matrix-free where the mesh allows it
+    amg.h[0].mf = (o.fine_matrix_free && sys.mf.valid) ? &sys.mf : nullptr;
 }
 
 // ---- V-cycle ---------------------------------------------------------------------------------
@@ -1892,7 +1896,7 @@ struct LevelOps<float> {
 // given (the last step writes there).
 template <typename T>
 static T* chebyshev(const AmgLevel& Lc, AmgLevel& L, const T* b, bool from_zero, T* x, T* other, int degree,
-                    double ratio, hipStream_t s, T* out = nullptr) {
+                    double ratio, hipStream_t s, T* out = nullptr, const MfState* mf = nullptr) {
     using O = LevelOps<T>;
     const double hi = 1.1 * Lc.lmax, lo = hi / ratio;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
@@ -1904,14 +1908,16 @@ static T* chebyshev(const AmgLevel& Lc, AmgLevel& L, const T* b, bool from_zero,
         if (degree == 1 && out) return out;
     } else {
         T* dst = (degree == 1 && out) ? out : other;
-        cheb_step<T>(O::A(Lc), O::invd(Lc), x, b, d, dst, T(0), T(1.0 / theta), s);
+        if (mf) mf_cheb_step<T>(*mf, O::invd(Lc), x, b, d, dst, T(0), T(1.0 / theta), s);
+        else cheb_step<T>(O::A(Lc), O::invd(Lc), x, b, d, dst, T(0), T(1.0 / theta), s);
         if (dst == out) return out;
         std::swap(x, other);
     }
     for (int k = 1; k < degree; ++k) {
         const double rn = 1.0 / (2.0 * sigma - rho);
         T* dst = (k + 1 == degree && out) ? out : other;
-        cheb_step<T>(O::A(Lc), O::invd(Lc), x, b, d, dst, T(rn * rho), T(2.0 * rn / delta), s);
+        if (mf) mf_cheb_step<T>(*mf, O::invd(Lc), x, b, d, dst, T(rn * rho), T(2.0 * rn / delta), s);
+        else cheb_step<T>(O::A(Lc), O::invd(Lc), x, b, d, dst, T(rn * rho), T(2.0 * rn / delta), s);
         rho = rn;
         if (dst == out) return out;
         std::swap(x, other);
@@ -1936,14 +1942,17 @@ static T* vcycle(Hierarchy& H, size_t l, const T* b, const fr_amg_opts& o, hipSt
         // large coarsest level: a longer smoothing sweep stands in for the exact solve
         return chebyshev<T>(L, L, b, true, O::x0(L), O::x1(L), 4 * o.cheb_degree, o.cheb_ratio, s, out);
     }
-    T* x = chebyshev<T>(L, L, b, true, O::x0(L), O::x1(L), o.cheb_degree, o.cheb_ratio, s);
+    // the fine displacement level of a uniform 2d mesh applies M_uu matrix-free
+    const MfState* mf = (l == 0 && H.mf && H.mf->valid) ? H.mf : nullptr;
+    T* x = chebyshev<T>(L, L, b, true, O::x0(L), O::x1(L), o.cheb_degree, o.cheb_ratio, s, nullptr, mf);
     T* other = (x == O::x0(L)) ? O::x1(L) : O::x0(L);
-    spmv_residual<T>(O::A(L), x, b, O::r(L), s);
+    if (mf) mf_residual<T>(*mf, x, b, O::r(L), s);
+    else spmv_residual<T>(O::A(L), x, b, O::r(L), s);
     AmgLevel& Ln = *H.lv[l + 1];
     spmv<T>(O::R(L), O::r(L), O::b(Ln), s);
     T* xc = vcycle<T>(H, l + 1, O::b(Ln), o, s);
     spmv_add<T>(O::P(L), xc, x, s);
-    return chebyshev<T>(L, L, b, false, x, other, o.cheb_degree, o.cheb_ratio, s, out);
+    return chebyshev<T>(L, L, b, false, x, other, o.cheb_degree, o.cheb_ratio, s, out, mf);
 }
 
 // z = M^-1 r with M^-1 = diag(V-cycle(M_uu), V-cycle(M_phiphi)).  The phi block's cycle
@@ -1993,23 +2002,28 @@ void amg_precondition32(DevAmg& amg, const double* r, float* z, hipStream_t s) {
     precondition<float>(amg, r, z, s);
 }
 
+uint64_t next_epoch() {
+    static std::atomic<uint64_t> e{0};
+    return ++e;
+}
+
 void* amg_graph_input(DevAmg& amg) {
     const int64_t n = std::max<int64_t>(1, amg.sys->n_solve);
     if (amg.opts.precision == 32) {
-        if (amg.vin32.n < size_t(n)) { ++amg.epoch; amg.vin32.reserve(size_t(n), amg.stream); }
+        if (amg.vin32.n < size_t(n)) { amg.epoch = next_epoch(); amg.vin32.reserve(size_t(n), amg.stream); }
         return amg.vin32.p;
     }
-    if (amg.vin64.n < size_t(n)) { ++amg.epoch; amg.vin64.reserve(size_t(n), amg.stream); }
+    if (amg.vin64.n < size_t(n)) { amg.epoch = next_epoch(); amg.vin64.reserve(size_t(n), amg.stream); }
     return amg.vin64.p;
 }
 
 void* amg_graph_output(DevAmg& amg) {
     const int64_t n = std::max<int64_t>(1, amg.sys->n_solve);
     if (amg.opts.precision == 32) {
-        if (amg.vout32.n < size_t(n)) { ++amg.epoch; amg.vout32.reserve(size_t(n), amg.stream); }
+        if (amg.vout32.n < size_t(n)) { amg.epoch = next_epoch(); amg.vout32.reserve(size_t(n), amg.stream); }
         return amg.vout32.p;
     }
-    if (amg.vout64.n < size_t(n)) { ++amg.epoch; amg.vout64.reserve(size_t(n), amg.stream); }
+    if (amg.vout64.n < size_t(n)) { amg.epoch = next_epoch(); amg.vout64.reserve(size_t(n), amg.stream); }
     return amg.vout64.p;
 }
 

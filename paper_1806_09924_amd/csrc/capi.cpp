@@ -103,6 +103,7 @@ fr_amg_opts default_amg() {
     o.reuse_u_block = 1;
     o.refresh_phi = 1;
     o.autotune = 1;
+    o.fine_matrix_free = 1;
     return o;
 }
 

@@ -420,6 +420,7 @@ static void grow_basis(DevKrylov& ws, int j, hipStream_t s) {
     grow_keep(ws.Z, size_t(j) * n, size_t(cap) * n, s);
     grow_keep(ws.Z32, size_t(j) * n, size_t(cap) * n, s);
     ws.cap = cap;
+    ws.layout = next_epoch();
 }
 
 // Everything one Arnoldi step needs; the step itself reads the Krylov index from the device.
@@ -436,7 +437,18 @@ struct StepCtx {
     float* f_p;
     double* d_copy;            // staging targets of k_seg_scale (null: none)
     void* vout;                // staged preconditioner output
+    bool mf;                   // J x with the displacement rows matrix-free
 };
+
+// y = J x, x also copied to xcopy + (*jp) n when xcopy is given; the displacement rows
+// matrix-free where the preconditioner's fine level is (uniform 2d meshes), else from the
+// stored blocks.
+template <typename TX>
+static void jmul(const StepCtx& c, const TX* x, double* y, TX* xcopy, const int* jp, hipStream_t s) {
+    if (c.mf) mf_jspmv<TX>(*c.sys, x, y, xcopy, jp, c.n, s);
+    else if (xcopy) jspmv_copy(*c.sys, x, y, xcopy, jp, c.n, s);
+    else jspmv(*c.sys, x, y, s);
+}
 
 // One Arnoldi step at the device's Krylov index j: z = M^-1 v_j (kept as Z_j), w = J z, CGS2
 // against V_0..V_j, the Hessenberg column and its rotations, v_{j+1} = w / |w| (and the next
@@ -454,16 +466,16 @@ static void arnoldi_step(const StepCtx& c, int j_host, hipStream_t s) {
     if (c.staged) {
         // both V-cycles from the staged input; the product J z copies z into Z_j as it reads it
         amg_precondition_staged(*c.amg, s);
-        if (c.z32) jspmv_copy(sys, static_cast<const float*>(c.vout), ws.w.p, ws.Z32.p, st.j, n, s);
-        else jspmv_copy(sys, static_cast<const double*>(c.vout), ws.w.p, ws.Z.p, st.j, n, s);
+        if (c.z32) jmul(c, static_cast<const float*>(c.vout), ws.w.p, ws.Z32.p, st.j, s);
+        else jmul(c, static_cast<const double*>(c.vout), ws.w.p, ws.Z.p, st.j, s);
     } else if (c.z32) {
         float* Zj = ws.Z32.p + int64_t(j_host) * n;
         amg_precondition32(*c.amg, nullptr, Zj, s);   // input staged by k_seg_scale
-        jspmv(sys, Zj, ws.w.p, s);
+        jmul<float>(c, Zj, ws.w.p, nullptr, nullptr, s);
     } else {
         double* Zj = ws.Z.p + int64_t(j_host) * n;
         amg_precondition(*c.amg, ws.V.p + int64_t(j_host) * n, Zj, s);
-        jspmv(sys, Zj, ws.w.p, s);
+        jmul<double>(c, Zj, ws.w.p, nullptr, nullptr, s);
     }
     // Gram-Schmidt reductions cover the largest vector count of the current basis; rows past
     // the step's own count return at once
@@ -517,8 +529,7 @@ static void arnoldi_step(const StepCtx& c, int j_host, hipStream_t s) {
 // that every buffer it records exists.
 static hipGraphExec_t step_graph(const StepCtx& c, hipStream_t s) {
     DevKrylov& ws = *c.ws;
-    const IterKey key{c.sys, c.amg, c.amg->epoch, ws.cap, ws.V.p, c.z32 ? static_cast<void*>(ws.Z32.p)
-                                                                          : static_cast<void*>(ws.Z.p)};
+    const IterKey key{c.sys, c.sys->version, c.amg->epoch, ws.layout};
     if (ws.step_exec && ws.step_key == key) return ws.step_exec;
     FR_HIP(hipStreamSynchronize(s));
     ws.drop_step();
@@ -575,6 +586,7 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
         const size_t per = size_t(2 * (m + 2) + 1 + (m + 1) * m + 2 * m + (m + 1) + m + 3);
         ws.state.alloc(per * size_t(ni), s);
         ws.istate.alloc(size_t(6 * ni) + 1, s);
+        ws.layout = next_epoch();
     }
     const int M = ws.m;
     State st;
@@ -605,7 +617,8 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
     // into the fixed staged input (FP32 or FP64); without graphs, with the FP32 hierarchy,
     // straight into its level-0 right-hand sides.
     const bool graphs = o.use_graphs != 0 && !prof_enabled();
-    StepCtx c{&sys, &amg, &ws, st, sg, ni, M, n, z32, graphs, nullptr, nullptr, nullptr, nullptr};
+    StepCtx c{&sys, &amg, &ws, st, sg, ni, M, n, z32, graphs, nullptr, nullptr, nullptr, nullptr,
+              amg.h[0].mf != nullptr};
     if (graphs && z32) {
         c.f_u = static_cast<float*>(amg_graph_input(amg));
         c.f_p = c.f_u + sys.n_u;
@@ -642,7 +655,7 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
     bool first = true;
     while (true) {
         // r = F - J x per instance, its norm, the new cycle
-        if (!first) jspmv(sys, du, ws.w.p, s);
+        if (!first) jmul<double>(c, du, ws.w.p, nullptr, nullptr, s);
         k_seg_resid<<<nb, 256, 0, s>>>(sys.F.p, ws.w.p, first ? 1 : 0, sg, part);
         FR_LAUNCH_CHECK();
         k_seg_reduce<<<dim3(1, ni), kReduceT, 0, s>>>(part, nb, ws.seg_bptr.p, st.beta2, 1);

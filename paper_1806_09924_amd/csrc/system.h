@@ -94,6 +94,18 @@ void mesh_kelly(DevMesh& m, const double* u, double* eta2, hipStream_t s);
 void mesh_mark_crack(const DevMesh& m, const double* phi, double phi_max, double h_target, uint8_t* flags_dev,
                      hipStream_t s);
 
+// ---- matrix-free displacement block on uniform 2d meshes (mfree.hip) ---------------------
+struct MfGrid {
+    int64_t nx = 0, ny = 0, n1 = 0, n_nodes = 0;   // cells per axis, nodes per row, nodes
+    double mu = 0, lam = 0, kappa = 0;
+};
+struct MfState {
+    bool valid = false;                          // the system's mesh allows it and phi_tilde is copied
+    MfGrid grid;
+    DBuf<double> pt;                             // phi_tilde of the last Jacobian assembly, all nodes
+    DBuf<float> pt32;                            // the same in FP32 (the FP32 hierarchy's smoother)
+};
+
 // ---- assembled system -------------------------------------------------------------------
 struct DevSystem {
     DevMesh* mesh = nullptr;
@@ -113,7 +125,23 @@ struct DevSystem {
     int64_t last_changes = 0;
     double last_min_margin = 0.0;
     uint64_t version = 0;                        // bumped at every Jacobian assembly
+    MfState mf;                                  // matrix-free M_uu (uniform 2d meshes)
 };
+
+// Matrix-free M_uu (Section 3's displacement block) on uniform 2d single-instance meshes: the
+// masked operator the assembly stores, applied from phi_tilde and the vector alone.
+bool mf_eligible(const DevMesh& m);
+// Copies phi_tilde (all nodes) for the matrix-free operator; sys.mf.valid tells whether it applies.
+void mf_prepare(DevSystem& sys, const double* pt, hipStream_t s);
+template <typename T>
+void mf_cheb_step(const MfState& mf, const T* invd, const T* x_old, const T* b, T* d, T* x_new, T alpha, T beta,
+                  hipStream_t s);
+template <typename T>
+void mf_residual(const MfState& mf, const T* x, const T* b, T* y, hipStream_t s);
+// y = J x with the displacement rows matrix-free (x FP64 or FP32), xcopy as for jspmv_copy
+template <typename TX>
+void mf_jspmv(const DevSystem& sys, const TX* x, double* y, TX* xcopy, const int* jp, int64_t xstride,
+              hipStream_t s);
 
 void assemble_residual(DevSystem& sys, const double* u, const double* phi, const double* pt);
 void assemble_active(DevSystem& sys, const double* phi, const double* phi_old);
@@ -225,6 +253,7 @@ struct Hierarchy {
     DBuf<double> dense_inv;                      // coarsest A^-1, row-major
     int64_t n_coarse = 0;
     bool refreshable = false;                    // Pt and AP kept on every level but the last
+    const MfState* mf = nullptr;                 // level 0 applied matrix-free (the u block of a uniform 2d mesh)
 };
 
 struct DevAmg {
@@ -239,8 +268,10 @@ struct DevAmg {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     DBuf<float> z32;                             // FP32 result staging of amg_precondition
     // Staged preconditioner input and output (solve order, [u | phi], in the hierarchy's
-    // precision) of amg_precondition_staged, the form a captured FGMRES iteration uses; epoch
-    // counts the setups and buffer changes after which such a capture is stale.
+    // precision) of amg_precondition_staged, the form a captured FGMRES iteration uses.  epoch
+    // is renewed (process-wide unique, next_epoch) at every setup and buffer change after which
+    // such a capture is stale: a preconditioner made at the address of a destroyed one never
+    // matches the old one's captures.
     DBuf<double> vin64, vout64;
     DBuf<float> vin32, vout32;
     uint64_t epoch = 0;
@@ -293,17 +324,19 @@ struct IterSummary {
     double ratio;      // largest |residual estimate| / target over the running instances
 };
 
-// What a captured Arnoldi step depends on: the system, the preconditioner and its setup epoch,
-// the basis capacity and the bases' addresses.
+// Process-wide unique serial numbers (never 0) for the epochs of captured work.
+uint64_t next_epoch();
+
+// What a captured Arnoldi step depends on: the system and its Jacobian assembly, the
+// preconditioner's setup epoch and the workspace layout (renewed whenever the Krylov buffers are
+// reallocated or grown).
 struct IterKey {
     const void* sys = nullptr;
-    const void* amg = nullptr;
-    uint64_t epoch = 0;
-    int cap = 0;
-    const void* V = nullptr;
-    const void* Z = nullptr;
+    uint64_t sys_version = 0;                    // the Jacobian assembly (parameters captured by value)
+    uint64_t amg_epoch = 0;
+    uint64_t layout = 0;
     bool operator==(const IterKey& o) const {
-        return sys == o.sys && amg == o.amg && epoch == o.epoch && cap == o.cap && V == o.V && Z == o.Z;
+        return sys == o.sys && sys_version == o.sys_version && amg_epoch == o.amg_epoch && layout == o.layout;
     }
 };
 
@@ -318,6 +351,7 @@ struct DevKrylov {
     IterKey step_key;
     hipStream_t cstream = nullptr;
     int64_t captures = 0;                        // captures made (one per preconditioner setup)
+    uint64_t layout = 0;                         // renewed (next_epoch) whenever V, Z, w, part, state move
     int last_iters = 0;                          // Arnoldi steps of the last solve
     void drop_step() {
         if (step_exec) { (void)hipGraphExecDestroy(step_exec); step_exec = nullptr; }

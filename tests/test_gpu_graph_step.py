@@ -64,3 +64,24 @@ def test_graph_step_bitwise_batch_and_newton():
     assert [s["linear_iters"] for s in st0] == [s["linear_iters"] for s in st1]
     assert [s["status"] for s in st1] == [B.FR_OK] * 3
     assert np.array_equal(u0, u1) and np.array_equal(p0, p1)
+
+
+def test_graph_step_fresh_preconditioner_on_the_same_system():
+    """A preconditioner made on a system after an earlier one was destroyed (it typically takes
+    the same address): its solves must capture their own step, not replay the earlier one's
+    (whose hierarchy buffers are gone).  Replay against direct launches, bit for bit."""
+    import gc
+    P = Problem(2, 2.0, 64)
+    u, phi, po, pt = P.dstate()
+    S = B.System(P.mesh).assemble(P.prm, u, phi, po, pt)
+    for prec in (64, 32, 64):
+        A = B.Amg(S, B.amg_opts(precision=prec))
+        out = {}
+        for g in (1, 0):
+            du = torch.empty(P.mesh.n_solve, dtype=torch.float64, device="cuda")
+            st = B.solve(S, A, du, B.solve_opts(use_graphs=g, rtol=1e-10))
+            out[g] = (st["iters"], host(du))
+        assert out[0][0] == out[1][0]
+        assert np.array_equal(out[0][1], out[1][1])
+        del A
+        gc.collect()
