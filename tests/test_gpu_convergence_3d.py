@@ -1,9 +1,12 @@
-"""The 3d penny-crack convergence of Fig. 3 (Section 4.3) on one GPU, refs 7-9 in one batch: the
-eps column of the table is reproduced exactly (2 x the finest cell's diameter), the errors
-against Sneddon's TCV shrink monotonically, and ref 9 is within 10 % of it.  The table's
-values converge from above and these from below: the initial crack field is built in the
-paper's earlier work, which the paper does not restate, so the sign of the eps error is a
-reading gap (the Newton solves themselves are parity-checked against the oracle elsewhere)."""
+"""The 3d penny-crack convergence of Fig. 3 (Section 4.3) on one GPU under the quasi-static
+reading of Sneddon's test: loading steps at the constant pressure until the phase field is
+stationary (the first step sees the sharp initial band in its degradation and pressure terms;
+the later ones relax it to the regularised profile).  Refs 7-9 in one batch and ref 10 alone:
+the eps column of the table is reproduced (2 x the finest cell's diameter), the errors against
+Sneddon's TCV are positive and shrink with eps as the table's do, and every ref's TCV is within
+3 % of the table's value (measured: -2.2 %, -1.6 %, -1.4 %, -1.3 %; errors +32.0 / +11.7 /
++3.5 / +0.4 % against the table's +35.0 / +13.4 / +5.0 / +1.8 %).  A single Newton loop from the
+sharp band (the first step) converges from below instead (-14.7 ... -5.5 %)."""
 import os
 
 import numpy as np
@@ -14,6 +17,7 @@ from paper_1806_09924_amd import studies
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fig3_table.txt")
+STEPS = 6
 
 
 def _table():
@@ -27,17 +31,28 @@ def _table():
     return rows
 
 
-def test_convergence_3d_refs_7_to_9():
-    tab = _table()
-    out = studies.convergence_3d((7, 8, 9), refine_radius=0.4, precision=32)
-    assert abs(out["exact"] / 5.12e-3 - 1) < 1e-12
-    errs = []
-    for r in out["rows"]:
+def _check_rows(rows, tab):
+    for r in rows:
         t = tab[r["ref"]]
         assert r["ten_l0_over_h"] == t["ten_l0_over_h"]
         assert abs(r["eps"] / t["eps"] - 1) < 1e-4
-        errs.append(abs(r["rel_error"]))
-    assert errs[0] > errs[1] > errs[2]
-    assert errs[2] <= 0.10
-    # the finest mesh is of the table's size
-    assert abs(out["rows"][-1]["n_dofs"] / tab[9]["dofs"] - 1) <= 0.05
+        assert abs(r["tcv"] / t["tcv"] - 1) <= 0.03, (r["ref"], r["tcv"], t["tcv"])
+        assert r["rel_error"] > 0                              # from above, as the table
+        assert r["rel_error_first_step"] < 0                   # the sharp band alone: from below
+        ts = r["tcv_steps"]
+        assert abs(ts[-1] / ts[-2] - 1) <= 1e-8                # stationary
+
+
+def test_convergence_3d_quasistatic_refs_7_to_10():
+    tab = _table()
+    out = studies.convergence_3d((7, 8, 9), refine_radius=0.4, precision=32, steps=STEPS)
+    assert abs(out["exact"] / 5.12e-3 - 1) < 1e-12
+    rows = out["rows"]
+    _check_rows(rows, tab)
+    # the finest mesh of the batch is of the table's size
+    assert abs(rows[-1]["n_dofs"] / tab[9]["dofs"] - 1) <= 0.05
+    out10 = studies.convergence_3d((10,), refine_radius=0.4, precision=32, steps=STEPS)
+    _check_rows(out10["rows"], tab)
+    errs = [r["rel_error"] for r in rows + out10["rows"]]
+    assert all(a > b for a, b in zip(errs, errs[1:]))
+    assert errs[-1] <= 0.02
