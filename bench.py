@@ -43,7 +43,8 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-PROFILE_OF = {"cheb_f64_b2": "cheb_f64_b2_sneddon2d_2048.md"}
+PROFILE_OF = {"cheb_f64_b2": "cheb_f64_b2_sneddon2d_2048.md", "cheb_f64_b2_i16": "cheb_f64_b2_sneddon2d_2048.md",
+              "mf_cheb_f64": "mf_cheb_f64_sneddon2d_2048.md"}
 
 
 def kernel_digest(src_text, kernel):

@@ -10,6 +10,7 @@
 #include <atomic>
 #include <cmath>
 #include <exception>
+#include <string>
 #include <thread>
 #include <type_traits>
 
@@ -1639,7 +1640,13 @@ static void coarse_inverse(Hierarchy& H, hipStream_t s) {
 // The power iteration of a level runs on `aux` beside the aggregation and the tentative
 // prolongator (which do not need it) and is waited for before the prolongator smoothing.
 static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double* coords, int dim,
-                            const fr_amg_opts& o, bool keep, hipStream_t s, hipStream_t aux) {
+                            const fr_amg_opts& o, bool keep, hipStream_t s, hipStream_t aux, const char* tag) {
+    // profile names of the setup phases, per hierarchy (u / phi)
+    const std::string t(tag);
+    const std::string nm_lambda = "setup_lambda_" + t, nm_agg = "setup_aggregate_" + t,
+                      nm_tent = "setup_tentative_" + t, nm_smooth = "setup_smooth_p_" + t, nm_rap = "setup_rap_" + t,
+                      nm_coarse = "setup_coarse_" + t, nm_tune = "setup_tune_" + t, nm_all = "setup_hierarchy_" + t;
+    ProfScope ps_all(nm_all.c_str(), s, 0.0);
     H.lv.clear();
     H.refreshable = keep;
     struct Ev {
@@ -1663,14 +1670,14 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
         L->A.own_val = std::move(A.own_val);
         DBuf<double> dnorm;
         {
-            ProfScope ps("setup_lambda", s, 0.0);
+            ProfScope ps(nm_lambda.c_str(), s, 0.0);
             diag_info(L->A, L->invd, dnorm, s);
         }
         PowerEst pe;
         {
             FR_HIP(hipEventRecord(ev_aux, s));
             FR_HIP(hipStreamWaitEvent(aux, ev_aux, 0));
-            ProfScope ps("setup_lambda", aux, 0.0);
+            ProfScope ps(nm_lambda.c_str(), aux, 0.0);
             power_start(pe, L->A, L->invd.p, aux);
         }
         const int64_t nrows = L->A.rows() * L->A.br;
@@ -1679,7 +1686,7 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
             DBuf<int32_t> agg;
             int64_t n_agg = 0;
             {
-                ProfScope ps("setup_aggregate", s, 0.0);
+                ProfScope ps(nm_agg.c_str(), s, 0.0);
                 // strength threshold: negative selects the measured default per dimension
                 const double theta = o.theta >= 0 ? o.theta : (dim == 2 ? 0.08 : 0.02);
                 n_agg = aggregate(L->A, dnorm.p, theta, agg, s);
@@ -1692,18 +1699,18 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
             DBuf<double> Bc;
             BMat<double> Pt, AP, Ac;
             {
-                ProfScope ps("setup_tentative", s, 0.0);
+                ProfScope ps(nm_tent.c_str(), s, 0.0);
                 Pt = tentative(L->A, agg, n_agg, ns, l == 0, coords, dim, Bf.p, Bc, s);
             }
             L->lmax = power_finish(pe);
             {
-                ProfScope ps("setup_smooth_p", s, 0.0);
+                ProfScope ps(nm_smooth.c_str(), s, 0.0);
                 const double omega = 4.0 / (3.0 * L->lmax);
                 L->P = spgemm<1>(L->A, Pt, L->invd.p, omega, errs.p, s);
                 L->R = transpose(L->P, s);
             }
             {
-                ProfScope ps("setup_rap", s, 0.0);
+                ProfScope ps(nm_rap.c_str(), s, 0.0);
                 AP = spgemm<0>(L->A, L->P, nullptr, 0.0, errs.p, s);
                 Ac = spgemm<0>(L->R, AP, nullptr, 0.0, errs.p, s);
             }
@@ -1722,13 +1729,13 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
         break;
     }
     {
-        ProfScope ps("setup_coarse", s, 0.0);
+        ProfScope ps(nm_coarse.c_str(), s, 0.0);
         coarse_inverse(H, s);
     }
     if (o.autotune) {
         // launch shapes of the smoothers and transfers below the finest level (level 0's
         // matrix is the system's own)
-        ProfScope ps("setup_tune", s, 0.0);
+        ProfScope ps(nm_tune.c_str(), s, 0.0);
         for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
             AmgLevel& L = *H.lv[l];
             const bool f32 = o.precision == 32;
@@ -1808,7 +1815,7 @@ void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s)
             Ap.S = sys.Jpp.S;
             Ap.val = sys.Jpp.val;
             build_hierarchy(amg.h[1], std::move(Ap), 1, m.coords_free.p, m.dim, o, o.refresh_phi != 0, side,
-                            amg.aux[1]);
+                            amg.aux[1], "phi");
         }
     };
     auto u_setup = [&]() {
@@ -1816,7 +1823,8 @@ void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s)
         Au.br = Au.bc = m.dim;
         Au.S = sys.Juu.S;
         Au.val = sys.Juu.val;
-        build_hierarchy(amg.h[0], std::move(Au), m.dim == 2 ? 3 : 6, m.coords_free.p, m.dim, o, false, s, amg.aux[0]);
+        build_hierarchy(amg.h[0], std::move(Au), m.dim == 2 ? 3 : 6, m.coords_free.p, m.dim, o, false, s, amg.aux[0],
+                        "u");
     };
     if (keep_u) {
         phi_setup();

@@ -53,9 +53,9 @@ static_assert(kCX * kCY == 256, "one cell per thread");
 // and phi_tilde of the patch (zero outside the mesh), in LDS.
 template <typename TA>
 struct Patch {
-    TA x[kPY][kPX][2];
+    TA x[2][kPY][kPX];                           // component-major: consecutive lanes, consecutive words
     TA p[kPY][kPX];
-    TA c[kCY][kCX][4][2];                        // cell contributions to vertex a, component c
+    TA c[4][2][kCY][kCX];                        // cell contributions to vertex a, component c
 };
 
 template <typename TA, typename TX, typename TP>
@@ -68,59 +68,87 @@ __device__ __forceinline__ void load_patch(const MfGrid& g, const TP* __restrict
         const bool interior = bi > 0 && bj > 0 && bi < g.nx && bj < g.ny;
         const int64_t nb = bi + bj * g.n1;
         P.p[py][px] = in ? TA(pt[nb]) : TA(0);
-        P.x[py][px][0] = interior ? TA(x[2 * nb]) : TA(0);
-        P.x[py][px][1] = interior ? TA(x[2 * nb + 1]) : TA(0);
+        P.x[0][py][px] = interior ? TA(x[2 * nb]) : TA(0);
+        P.x[1][py][px] = interior ? TA(x[2 * nb + 1]) : TA(0);
     }
 }
 
 // Thread t's cell (i0 - 1 + t % kCX, j0 - 1 + t / kCX): its contributions to its four vertices,
 // sum over the Gauss points of g_q sigma_q(x) grad N_a(q) (zero for a cell outside the mesh).
+// The tensor-product structure of Q1 with 2 x 2 Gauss points is used: with f(b, q) = kP when the
+// vertex and the Gauss point lie on the same side of the axis (else kM),
+//   d/dxi of the x at Gauss point q  = (f(0, q_y) (x_1 - x_0) + f(1, q_y) (x_3 - x_2)) / 2,
+//   d/deta                            = (f(0, q_x) (x_2 - x_0) + f(1, q_x) (x_3 - x_1)) / 2,
+// and the vertex contributions need only the stresses summed along one axis:
+//   c_(a, comp) = s_x(a) X_comp[a_y] + s_y(a) Y_comp[a_x],
+//   X_comp[a_y] = (f(a_y, 0) Sx_comp[0] + f(a_y, 1) Sx_comp[1]) / 2, Sx_comp[q_y] = sum over q_x
+//   of sigma[comp][0], and Y the same along the other axis with sigma[comp][1].
 template <typename TA>
 __device__ __forceinline__ void cell_contrib(const MfGrid& g, int64_t i0, int64_t j0, Patch<TA>& P) {
     const int cx = threadIdx.x % kCX, cy = threadIdx.x / kCX;
     const int64_t ci = i0 - 1 + cx, cj = j0 - 1 + cy;
-    TA acc[4][2];
+    TA out[4][2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) acc[a][0] = acc[a][1] = TA(0);
+    for (int a = 0; a < 4; ++a) out[a][0] = out[a][1] = TA(0);
     if (ci >= 0 && cj >= 0 && ci < g.nx && cj < g.ny) {
         const TA mu = TA(g.mu), lam = TA(g.lam), kap = TA(g.kappa), omk = TA(1.0 - g.kappa);
-        TA xv[4][2], pv[4];
+        const TA fP = TA(kP), fM = TA(kM), half = TA(0.5);
+        // vertex values: b = 0 (lower left), 1 (lower right), 2 (upper left), 3 (upper right)
+        TA xv[2][4], pv[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             pv[b] = P.p[cy + (b >> 1)][cx + (b & 1)];
-            xv[b][0] = P.x[cy + (b >> 1)][cx + (b & 1)][0];
-            xv[b][1] = P.x[cy + (b >> 1)][cx + (b & 1)][1];
+            xv[0][b] = P.x[0][cy + (b >> 1)][cx + (b & 1)];
+            xv[1][b] = P.x[1][cy + (b >> 1)][cx + (b & 1)];
         }
+        // reference gradients: Hx[comp][q_y] = d x_comp / dxi, Hy[comp][q_x] = d x_comp / deta
+        TA Hx[2][2], Hy[2][2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const TA dx0 = xv[c][1] - xv[c][0], dx1 = xv[c][3] - xv[c][2];
+            const TA dy0 = xv[c][2] - xv[c][0], dy1 = xv[c][3] - xv[c][1];
+            Hx[c][0] = half * (fP * dx0 + fM * dx1);
+            Hx[c][1] = half * (fM * dx0 + fP * dx1);
+            Hy[c][0] = half * (fP * dy0 + fM * dy1);
+            Hy[c][1] = half * (fM * dy0 + fP * dy1);
+        }
+        // phi_tilde at the Gauss points: along x in both vertex rows, then along y
+        TA pr[2][2];
+#pragma unroll
+        for (int by = 0; by < 2; ++by) {
+            pr[by][0] = fP * pv[2 * by] + fM * pv[2 * by + 1];
+            pr[by][1] = fM * pv[2 * by] + fP * pv[2 * by + 1];
+        }
+        TA Sx[2][2] = {{TA(0), TA(0)}, {TA(0), TA(0)}}, Sy[2][2] = {{TA(0), TA(0)}, {TA(0), TA(0)}};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            TA ph = TA(0);
-#pragma unroll
-            for (int b = 0; b < 4; ++b) ph += TA(nq(q, b)) * pv[b];
+            const int qx = q & 1, qy = q >> 1;
+            const TA ph = qy ? fM * pr[0][qx] + fP * pr[1][qx] : fP * pr[0][qx] + fM * pr[1][qx];
             const TA gg = omk * ph * ph + kap;
-            TA H[2][2] = {{TA(0), TA(0)}, {TA(0), TA(0)}};
+            const TA h00 = Hx[0][qy], h01 = Hy[0][qx], h10 = Hx[1][qy], h11 = Hy[1][qx];
+            const TA tr = h00 + h11;
+            const TA s00 = gg * (TA(2) * mu * h00 + lam * tr);
+            const TA s11 = gg * (TA(2) * mu * h11 + lam * tr);
+            const TA s01 = gg * (mu * (h01 + h10));
+            Sx[0][qy] += s00;                    // sigma[0][0]
+            Sx[1][qy] += s01;                    // sigma[1][0]
+            Sy[0][qx] += s01;                    // sigma[0][1]
+            Sy[1][qx] += s11;                    // sigma[1][1]
+        }
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
-#pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    H[0][k] += xv[b][0] * TA(gq(q, b, k));
-                    H[1][k] += xv[b][1] * TA(gq(q, b, k));
-                }
-            const TA tr = H[0][0] + H[1][1];
-            const TA s00 = gg * (TA(2) * mu * H[0][0] + lam * tr);
-            const TA s11 = gg * (TA(2) * mu * H[1][1] + lam * tr);
-            const TA s01 = gg * (mu * (H[0][1] + H[1][0]));
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const TA ga0 = TA(gq(q, a, 0)), ga1 = TA(gq(q, a, 1));
-                acc[a][0] += s00 * ga0 + s01 * ga1;
-                acc[a][1] += s01 * ga0 + s11 * ga1;
-            }
+        for (int c = 0; c < 2; ++c) {
+            const TA X0 = half * (fP * Sx[c][0] + fM * Sx[c][1]), X1 = half * (fM * Sx[c][0] + fP * Sx[c][1]);
+            const TA Y0 = half * (fP * Sy[c][0] + fM * Sy[c][1]), Y1 = half * (fM * Sy[c][0] + fP * Sy[c][1]);
+            out[0][c] = -X0 - Y0;                // a = (0, 0)
+            out[1][c] = X0 - Y1;                 // a = (1, 0)
+            out[2][c] = -X1 + Y0;                // a = (0, 1)
+            out[3][c] = X1 + Y1;                 // a = (1, 1)
         }
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        P.c[cy][cx][a][0] = acc[a][0];
-        P.c[cy][cx][a][1] = acc[a][1];
+        P.c[a][0][cy][cx] = out[a][0];
+        P.c[a][1][cy][cx] = out[a][1];
     }
 }
 
@@ -168,7 +196,7 @@ __device__ __forceinline__ void node_row(const MfGrid& g, int64_t i, int64_t j, 
     }
 #pragma unroll
     for (int c = 0; c < 2; ++c)
-        y[c] = ((P.c[ty + 1][tx + 1][0][c] + P.c[ty + 1][tx][1][c]) + P.c[ty][tx + 1][2][c]) + P.c[ty][tx][3][c];
+        y[c] = ((P.c[0][c][ty + 1][tx + 1] + P.c[1][c][ty + 1][tx]) + P.c[2][c][ty][tx + 1]) + P.c[3][c][ty][tx];
 }
 
 // Tile origin of this workgroup and the node of this thread (valid: inside the tile and mesh).

@@ -546,7 +546,9 @@ static void spmv_mode(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_
     const int G = launch_lanes(S);
     // one profile scope per kernel instantiation (block shape, mode, lanes per row)
     char name[48];
-    if (G == 1) std::snprintf(name, sizeof(name), "spmv_%s_%dx%d_m%d", sizeof(T) == 8 ? "f64" : "f32", br, bc, MODE);
+    // one name per kernel instantiation (int16 column offsets are a separate one)
+    if (G == 1) std::snprintf(name, sizeof(name), "spmv_%s_%dx%d_m%d%s", sizeof(T) == 8 ? "f64" : "f32", br, bc, MODE,
+                              S.col16 ? "_i16" : "");
     else std::snprintf(name, sizeof(name), "spmv_%s_%dx%d_m%d_g%d", sizeof(T) == 8 ? "f64" : "f32", br, bc, MODE, G);
     const double ib = (S.col16 && G == 1) ? 2.0 : 4.0;   // index bytes per stored block
     const double bytes = double(S.nnz) * (br * bc * sizeof(T) + ib) + double(S.n_cols) * bc * sizeof(T) +
@@ -603,7 +605,8 @@ void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d
     const int G = launch_lanes(S);
     // one profile scope per kernel instantiation (block size, lanes per row)
     char name[48];
-    if (G == 1) std::snprintf(name, sizeof(name), "cheb_%s_b%d", sizeof(T) == 8 ? "f64" : "f32", A.br);
+    if (G == 1) std::snprintf(name, sizeof(name), "cheb_%s_b%d%s", sizeof(T) == 8 ? "f64" : "f32", A.br,
+                              S.col16 ? "_i16" : "");
     else std::snprintf(name, sizeof(name), "cheb_%s_b%d_g%d", sizeof(T) == 8 ? "f64" : "f32", A.br, G);
     // matrix once (index bytes 2 with row offsets), x gathered once, b, d, D^-1 read, d and
     // x_new written
