@@ -105,11 +105,15 @@ typedef struct {
                             and reused by later setups.  Different
                             lane counts sum a row in a different order, so results are
                             reproducible for a given cache (amg_level_shape reports the choice). */
-    int fine_matrix_free; /* nonzero: on a uniform 2d mesh (one instance) the finest displacement level's
+    int fine_matrix_free; /* bit mask, on a uniform 2d mesh (one instance); other meshes use the
+                            stored blocks either way.  Bit 0 (1): the finest displacement level's
                             smoother and residual, and the displacement rows of the J-SpMV in
-                            fracture_solve, apply M_uu matrix-free from phi_tilde (the same masked
-                            operator as the stored blocks, summed in another order: equal up to
-                            rounding); other meshes use the stored blocks either way */
+                            fracture_solve, apply M_uu matrix-free from phi_tilde.  Bit 1 (2): the
+                            finest phase-field level's smoother and residual apply the masked
+                            M_phiphi from the assembly's u and active set, and (with bit 0) the
+                            phase-field rows of the J-SpMV apply M_phiu and M_phiphi from its u,
+                            phi and active set.  The same masked operators as the stored blocks,
+                            summed in another order: equal up to rounding.  Default 3. */
 } fr_amg_opts;
 
 /* FGMRES options (right preconditioned, x0 = 0). */
@@ -286,6 +290,15 @@ fr_status fracture_set_active(fr_system sys, const uint8_t* active, void* stream
 
 /* y = J x with the masked Jacobian (device vectors of n_solve entries). */
 fr_status fracture_matvec(fr_system sys, const double* x, double* y, void* stream);
+
+/* y = J x as fracture_solve applies it on a uniform 2d mesh (one instance): the same masked
+ * Jacobian (Section 3: the blocks of equations E22ATW and E33ATW, active phase-field rows and
+ * columns and Dirichlet displacement rows and columns eliminated, diagonals kept) computed
+ * cell by cell from the last assembly's state instead of read from the stored blocks, equal to
+ * fracture_matvec up to rounding.  rows = 1: the displacement rows matrix-free, the phase-field
+ * rows from the stored blocks; rows = 3: every row matrix-free.  FR_EINVAL on other meshes
+ * (see fine_matrix_free) or another `rows`. */
+fr_status fracture_matvec_free(fr_system sys, int rows, const double* x, double* y, void* stream);
 
 /* Masked Jacobian as scalar CSR in solve order, host arrays: row_ptr[n_solve+1],
  * col[nnz], val[nnz] with nnz from a first call with col == NULL (it sets *nnz).

@@ -89,6 +89,7 @@ _SIGNATURES = {
     "fracture_system_vectors": [_P, _P, _P, _P, _P, _P],
     "fracture_set_active": [_P, _P, _P],
     "fracture_matvec": [_P, _P, _P, _P],
+    "fracture_matvec_free": [_P, ctypes.c_int, _P, _P, _P],
     "fracture_system_csr": [_P, _I64P, _P, _P, _P, _P],
     "fracture_system_destroy": [_P],
     "amg_setup": [_P, ctypes.POINTER(AmgOpts), ctypes.POINTER(_P), _P],
@@ -175,7 +176,7 @@ def params(E=1.0, nu=0.2, Gc=1.0, kappa=1e-10, eps=1.0 / 16, p=1e-3, c_pdas=1.0,
 
 
 def amg_opts(precision=64, theta=-1.0, cheb_degree=2, cheb_ratio=8.0, coarse_max=96, max_levels=12,
-             reuse_u_block=1, refresh_phi=1, autotune=1, fine_matrix_free=1):
+             reuse_u_block=1, refresh_phi=1, autotune=1, fine_matrix_free=3):
     return AmgOpts(precision, theta, cheb_degree, cheb_ratio, coarse_max, max_levels, reuse_u_block, refresh_phi,
                    autotune, fine_matrix_free)
 
@@ -362,6 +363,9 @@ class System:
 
     def matvec(self, x, y):
         _check(load().fracture_matvec(self.h, _ptr(x), _ptr(y), _stream()))
+
+    def matvec_free(self, x, y, rows=3):
+        _check(load().fracture_matvec_free(self.h, rows, _ptr(x), _ptr(y), _stream()))
 
     def csr(self):
         lib = load()

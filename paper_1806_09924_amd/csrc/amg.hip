@@ -1854,8 +1854,11 @@ void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s)
     FR_HIP(hipEventRecord(amg.ev_join, side));
     FR_HIP(hipStreamWaitEvent(s, amg.ev_join, 0));
     amg.sys_version = sys.version;
-    // the fine displacement level applies M_uu matrix-free where the mesh allows it
-    amg.h[0].mf = (o.fine_matrix_free && sys.mf.valid) ? &sys.mf : nullptr;
+    // the fine levels apply M_uu (bit 0) and M_phiphi (bit 1) matrix-free where the mesh allows it
+    amg.h[0].blk = 0;
+    amg.h[1].blk = 1;
+    amg.h[0].mf = ((o.fine_matrix_free & 1) && sys.mf.valid) ? &sys.mf : nullptr;
+    amg.h[1].mf = ((o.fine_matrix_free & 2) && sys.mf.valid) ? &sys.mf : nullptr;
 }
 
 // ---- V-cycle ---------------------------------------------------------------------------------
@@ -1904,7 +1907,7 @@ struct LevelOps<float> {
 // given (the last step writes there).
 template <typename T>
 static T* chebyshev(const AmgLevel& Lc, AmgLevel& L, const T* b, bool from_zero, T* x, T* other, int degree,
-                    double ratio, hipStream_t s, T* out = nullptr, const MfState* mf = nullptr) {
+                    double ratio, hipStream_t s, T* out = nullptr, const MfState* mf = nullptr, int blk = 0) {
     using O = LevelOps<T>;
     const double hi = 1.1 * Lc.lmax, lo = hi / ratio;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
@@ -1916,7 +1919,7 @@ static T* chebyshev(const AmgLevel& Lc, AmgLevel& L, const T* b, bool from_zero,
         if (degree == 1 && out) return out;
     } else {
         T* dst = (degree == 1 && out) ? out : other;
-        if (mf) mf_cheb_step<T>(*mf, O::invd(Lc), x, b, d, dst, T(0), T(1.0 / theta), s);
+        if (mf) mf_cheb_step<T>(*mf, blk, O::invd(Lc), x, b, d, dst, T(0), T(1.0 / theta), s);
         else cheb_step<T>(O::A(Lc), O::invd(Lc), x, b, d, dst, T(0), T(1.0 / theta), s);
         if (dst == out) return out;
         std::swap(x, other);
@@ -1924,7 +1927,7 @@ static T* chebyshev(const AmgLevel& Lc, AmgLevel& L, const T* b, bool from_zero,
     for (int k = 1; k < degree; ++k) {
         const double rn = 1.0 / (2.0 * sigma - rho);
         T* dst = (k + 1 == degree && out) ? out : other;
-        if (mf) mf_cheb_step<T>(*mf, O::invd(Lc), x, b, d, dst, T(rn * rho), T(2.0 * rn / delta), s);
+        if (mf) mf_cheb_step<T>(*mf, blk, O::invd(Lc), x, b, d, dst, T(rn * rho), T(2.0 * rn / delta), s);
         else cheb_step<T>(O::A(Lc), O::invd(Lc), x, b, d, dst, T(rn * rho), T(2.0 * rn / delta), s);
         rho = rn;
         if (dst == out) return out;
@@ -1950,17 +1953,17 @@ static T* vcycle(Hierarchy& H, size_t l, const T* b, const fr_amg_opts& o, hipSt
         // large coarsest level: a longer smoothing sweep stands in for the exact solve
         return chebyshev<T>(L, L, b, true, O::x0(L), O::x1(L), 4 * o.cheb_degree, o.cheb_ratio, s, out);
     }
-    // the fine displacement level of a uniform 2d mesh applies M_uu matrix-free
+    // the fine level of a uniform 2d mesh applies its block (M_uu or M_phiphi) matrix-free
     const MfState* mf = (l == 0 && H.mf && H.mf->valid) ? H.mf : nullptr;
-    T* x = chebyshev<T>(L, L, b, true, O::x0(L), O::x1(L), o.cheb_degree, o.cheb_ratio, s, nullptr, mf);
+    T* x = chebyshev<T>(L, L, b, true, O::x0(L), O::x1(L), o.cheb_degree, o.cheb_ratio, s, nullptr, mf, H.blk);
     T* other = (x == O::x0(L)) ? O::x1(L) : O::x0(L);
-    if (mf) mf_residual<T>(*mf, x, b, O::r(L), s);
+    if (mf) mf_residual<T>(*mf, H.blk, x, b, O::r(L), s);
     else spmv_residual<T>(O::A(L), x, b, O::r(L), s);
     AmgLevel& Ln = *H.lv[l + 1];
     spmv<T>(O::R(L), O::r(L), O::b(Ln), s);
     T* xc = vcycle<T>(H, l + 1, O::b(Ln), o, s);
     spmv_add<T>(O::P(L), xc, x, s);
-    return chebyshev<T>(L, L, b, false, x, other, o.cheb_degree, o.cheb_ratio, s, out, mf);
+    return chebyshev<T>(L, L, b, false, x, other, o.cheb_degree, o.cheb_ratio, s, out, mf, H.blk);
 }
 
 // z = M^-1 r with M^-1 = diag(V-cycle(M_uu), V-cycle(M_phiphi)).  The phi block's cycle

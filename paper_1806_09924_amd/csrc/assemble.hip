@@ -1078,7 +1078,7 @@ void assemble_jacobian(DevSystem& sys, const double* u, const double* phi, const
     FR_LAUNCH_CHECK();
     sys.have_jacobian = true;
     sys.version++;
-    mf_prepare(sys, pt, s);
+    mf_prepare(sys, u, phi, pt, s);
 }
 
 void system_norms(DevSystem& sys, const double* phi, const double* phi_old, double* norms, int64_t* n_active,

@@ -103,7 +103,7 @@ fr_amg_opts default_amg() {
     o.reuse_u_block = 1;
     o.refresh_phi = 1;
     o.autotune = 1;
-    o.fine_matrix_free = 1;
+    o.fine_matrix_free = 3;
     return o;
 }
 
@@ -114,6 +114,7 @@ fr_status check_amg(const fr_amg_opts& o) {
     FR_REQUIRE(o.cheb_ratio > 1, "amg: cheb_ratio must be > 1");
     FR_REQUIRE(o.coarse_max >= 1 && o.coarse_max <= 4096, "amg: coarse_max must be in [1, 4096]");
     FR_REQUIRE(o.max_levels >= 1 && o.max_levels <= 30, "amg: max_levels must be in [1, 30]");
+    FR_REQUIRE(o.fine_matrix_free >= 0 && o.fine_matrix_free <= 3, "amg: fine_matrix_free must be in [0, 3]");
     return FR_OK;
 }
 
@@ -519,6 +520,17 @@ fr_status fracture_matvec(fr_system sys, const double* x, double* y, void* strea
     FR_REQUIRE(sys->sys.have_jacobian, "matvec: no Jacobian assembled");
     return guard([&]() {
         fr::jspmv(sys->sys, x, y, fr::as_stream(stream));
+        return FR_OK;
+    });
+}
+
+fr_status fracture_matvec_free(fr_system sys, int rows, const double* x, double* y, void* stream) {
+    FR_REQUIRE(sys != nullptr && x != nullptr && y != nullptr, "matvec_free: NULL argument");
+    FR_REQUIRE(rows == 1 || rows == 3, "matvec_free: rows must be 1 or 3");
+    FR_REQUIRE(sys->sys.have_jacobian, "matvec_free: no Jacobian assembled");
+    FR_REQUIRE(sys->sys.mf.valid, "matvec_free: the mesh is not a uniform 2d single-instance mesh");
+    return guard([&]() {
+        fr::mf_jspmv<double>(sys->sys, rows == 3, x, y, nullptr, nullptr, 0, fr::as_stream(stream));
         return FR_OK;
     });
 }

@@ -438,14 +438,15 @@ struct StepCtx {
     double* d_copy;            // staging targets of k_seg_scale (null: none)
     void* vout;                // staged preconditioner output
     bool mf;                   // J x with the displacement rows matrix-free
+    bool mf_phi;               // and the phase-field rows too
 };
 
 // y = J x, x also copied to xcopy + (*jp) n when xcopy is given; the displacement rows
-// matrix-free where the preconditioner's fine level is (uniform 2d meshes), else from the
-// stored blocks.
+// matrix-free where the preconditioner's fine displacement level is (uniform 2d meshes), the
+// phase-field rows too where its fine phase-field level is as well, else from the stored blocks.
 template <typename TX>
 static void jmul(const StepCtx& c, const TX* x, double* y, TX* xcopy, const int* jp, hipStream_t s) {
-    if (c.mf) mf_jspmv<TX>(*c.sys, x, y, xcopy, jp, c.n, s);
+    if (c.mf) mf_jspmv<TX>(*c.sys, c.mf_phi, x, y, xcopy, jp, c.n, s);
     else if (xcopy) jspmv_copy(*c.sys, x, y, xcopy, jp, c.n, s);
     else jspmv(*c.sys, x, y, s);
 }
@@ -618,7 +619,7 @@ fr_status fgmres(DevSystem& sys, DevAmg& amg, const fr_solve_opts& o, double* du
     // straight into its level-0 right-hand sides.
     const bool graphs = o.use_graphs != 0 && !prof_enabled();
     StepCtx c{&sys, &amg, &ws, st, sg, ni, M, n, z32, graphs, nullptr, nullptr, nullptr, nullptr,
-              amg.h[0].mf != nullptr};
+              amg.h[0].mf != nullptr, amg.h[0].mf != nullptr && amg.h[1].mf != nullptr};
     if (graphs && z32) {
         c.f_u = static_cast<float*>(amg_graph_input(amg));
         c.f_p = c.f_u + sys.n_u;

@@ -94,16 +94,22 @@ void mesh_kelly(DevMesh& m, const double* u, double* eta2, hipStream_t s);
 void mesh_mark_crack(const DevMesh& m, const double* phi, double phi_max, double h_target, uint8_t* flags_dev,
                      hipStream_t s);
 
-// ---- matrix-free displacement block on uniform 2d meshes (mfree.hip) ---------------------
+// ---- matrix-free fine-level operators on uniform 2d meshes (mfree.hip) --------------------
 struct MfGrid {
     int64_t nx = 0, ny = 0, n1 = 0, n_nodes = 0;   // cells per axis, nodes per row, nodes
     double mu = 0, lam = 0, kappa = 0;
+    double h = 0, p = 0, Gc = 0, eps = 0;          // cell edge, pressure, G_c, epsilon
 };
 struct MfState {
-    bool valid = false;                          // the system's mesh allows it and phi_tilde is copied
+    bool valid = false;                          // the system's mesh allows it and the state is copied
     MfGrid grid;
     DBuf<double> pt;                             // phi_tilde of the last Jacobian assembly, all nodes
     DBuf<float> pt32;                            // the same in FP32 (the FP32 hierarchy's smoother)
+    DBuf<double> us, ps;                         // u (node-major) and phi of that assembly
+    DBuf<float> us32;
+    DBuf<uint8_t> act;                           // its active set (per node)
+    DBuf<double> dpp;                            // diagonal of M_phiphi (kept for active rows)
+    DBuf<float> dpp32;
 };
 
 // ---- assembled system -------------------------------------------------------------------
@@ -125,22 +131,25 @@ struct DevSystem {
     int64_t last_changes = 0;
     double last_min_margin = 0.0;
     uint64_t version = 0;                        // bumped at every Jacobian assembly
-    MfState mf;                                  // matrix-free M_uu (uniform 2d meshes)
+    MfState mf;                                  // matrix-free fine-level blocks (uniform 2d meshes)
 };
 
-// Matrix-free M_uu (Section 3's displacement block) on uniform 2d single-instance meshes: the
-// masked operator the assembly stores, applied from phi_tilde and the vector alone.
+// Matrix-free fine-level blocks (Section 3's M_uu and M_phiphi, and the phase-field rows
+// M_phiu, M_phiphi of the J-SpMV) on uniform 2d single-instance meshes: the masked operators
+// the assembly stores, applied from the assembly's state (phi_tilde, u, phi, active set) and
+// the vector alone.  blk 0: M_uu, 1: M_phiphi.
 bool mf_eligible(const DevMesh& m);
-// Copies phi_tilde (all nodes) for the matrix-free operator; sys.mf.valid tells whether it applies.
-void mf_prepare(DevSystem& sys, const double* pt, hipStream_t s);
+// Copies the state for the matrix-free operators; sys.mf.valid tells whether they apply.
+void mf_prepare(DevSystem& sys, const double* u, const double* phi, const double* pt, hipStream_t s);
 template <typename T>
-void mf_cheb_step(const MfState& mf, const T* invd, const T* x_old, const T* b, T* d, T* x_new, T alpha, T beta,
-                  hipStream_t s);
+void mf_cheb_step(const MfState& mf, int blk, const T* invd, const T* x_old, const T* b, T* d, T* x_new, T alpha,
+                  T beta, hipStream_t s);
 template <typename T>
-void mf_residual(const MfState& mf, const T* x, const T* b, T* y, hipStream_t s);
-// y = J x with the displacement rows matrix-free (x FP64 or FP32), xcopy as for jspmv_copy
+void mf_residual(const MfState& mf, int blk, const T* x, const T* b, T* y, hipStream_t s);
+// y = J x with the displacement rows matrix-free, and the phase-field rows too when `phi_rows`
+// (x FP64 or FP32), xcopy as for jspmv_copy
 template <typename TX>
-void mf_jspmv(const DevSystem& sys, const TX* x, double* y, TX* xcopy, const int* jp, int64_t xstride,
+void mf_jspmv(const DevSystem& sys, bool phi_rows, const TX* x, double* y, TX* xcopy, const int* jp, int64_t xstride,
               hipStream_t s);
 
 void assemble_residual(DevSystem& sys, const double* u, const double* phi, const double* pt);
@@ -220,6 +229,7 @@ void make_col16(SellStruct& S, hipStream_t s);
 int launch_lanes(const SellStruct& S);
 // Same matrix in slice height C.
 BMat<double> relayout(const BMat<double>& A, int C, hipStream_t s);
+
 // Picks slice height and lanes per row for M by timing (op 0: smoother, 1: y = M x,
 // 2: y += M x) in FP32 or FP64; replaces M by its relayout when another slice height wins.
 // Process-wide cache.
@@ -253,7 +263,8 @@ struct Hierarchy {
     DBuf<double> dense_inv;                      // coarsest A^-1, row-major
     int64_t n_coarse = 0;
     bool refreshable = false;                    // Pt and AP kept on every level but the last
-    const MfState* mf = nullptr;                 // level 0 applied matrix-free (the u block of a uniform 2d mesh)
+    const MfState* mf = nullptr;                 // level 0 applied matrix-free (uniform 2d meshes)
+    int blk = 0;                                 // 0: the u block's hierarchy, 1: the phi block's
 };
 
 struct DevAmg {

@@ -74,6 +74,7 @@ def test_error_contract_arguments(lib):
     assert lib.fracture_newton_masks(m.h, None, None, None) == B.FR_EINVAL
     assert lib.fracture_functionals_noalloc(None, None, None, None, 0, None, None, None) == B.FR_EINVAL
     assert lib.fracture_functionals_noalloc(m.h, None, None, None, 0, None, None, None) == B.FR_EINVAL
+    assert lib.fracture_matvec_free(None, 3, None, None, None) == B.FR_EINVAL
     # newton options reach the library in full (the cycle-rule switch is the last field)
     o = B.newton_opts(no_cycle_freeze=1)
     assert ctypes.sizeof(o) == ctypes.sizeof(ctypes.c_double) * 2 + ctypes.sizeof(ctypes.c_int) * 4
