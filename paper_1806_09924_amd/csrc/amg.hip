@@ -1399,20 +1399,20 @@ BMat<double> transpose(const BMat<double>& P, hipStream_t s) {
     fail(FR_EINTERNAL, "transpose: unsupported block shape");
 }
 
-// lambda_max(D^-1 A) by power iteration from a fixed pseudo-random start vector: with
-// ||x|| = 1, ||D^-1 A x|| approaches lambda_max from below.
 // Largest eigenvalue of D^-1 A by ten power steps from a fixed positive start vector.  The
 // iterates are not normalised between steps (D^-1 A has eigenvalues of order one, so ten
 // steps stay far inside the double range); the estimate is |x_10| / |x_9|.  power_start
 // enqueues the steps on a stream and power_finish waits for the estimate, so that other work
-// can run in between (the buffers live in the PowerEst until then).
+// can run in between (the buffers live in the PowerEst until then).  With `mf` the steps apply
+// the fine level's block matrix-free (the same operator up to rounding, fewer bytes).
 struct PowerEst {
     DBuf<double> v[2], scr, nrm;
     int64_t n = 0;
     hipStream_t st = nullptr;
 };
 
-void power_start(PowerEst& pe, const BMat<double>& A, const double* invd, hipStream_t s) {
+void power_start(PowerEst& pe, const BMat<double>& A, const double* invd, hipStream_t s, const MfState* mf = nullptr,
+                 int blk = 0) {
     const int64_t n = A.rows() * A.br;
     pe.n = n;
     pe.st = s;
@@ -1424,8 +1424,10 @@ void power_start(PowerEst& pe, const BMat<double>& A, const double* invd, hipStr
     k_power_init<<<nblk(n, 256), 256, 0, s>>>(n, pe.v[0].p);
     FR_LAUNCH_CHECK();
     const int iters = 10;
-    for (int it = 0; it < iters; ++it)
-        diag_scaled_matvec(A, invd, pe.v[it & 1].p, pe.v[(it + 1) & 1].p, s);
+    for (int it = 0; it < iters; ++it) {
+        if (mf) mf_power_step(*mf, blk, invd, pe.v[it & 1].p, pe.v[(it + 1) & 1].p, s);
+        else diag_scaled_matvec(A, invd, pe.v[it & 1].p, pe.v[(it + 1) & 1].p, s);
+    }
     dev_dot(pe.v[iters & 1].p, pe.v[iters & 1].p, n, pe.nrm.p, pe.scr, s);
     dev_dot(pe.v[(iters - 1) & 1].p, pe.v[(iters - 1) & 1].p, n, pe.nrm.p + 1, pe.scr, s);
 }
@@ -1437,9 +1439,10 @@ double power_finish(PowerEst& pe) {
     return lam > 0 && std::isfinite(lam) ? lam : 1.0;
 }
 
-double lambda_max(const BMat<double>& A, const double* invd, hipStream_t s) {
+double lambda_max(const BMat<double>& A, const double* invd, hipStream_t s, const MfState* mf = nullptr,
+                  int blk = 0) {
     PowerEst pe;
-    power_start(pe, A, invd, s);
+    power_start(pe, A, invd, s, mf, blk);
     return power_finish(pe);
 }
 
@@ -1640,7 +1643,8 @@ static void coarse_inverse(Hierarchy& H, hipStream_t s) {
 // The power iteration of a level runs on `aux` beside the aggregation and the tentative
 // prolongator (which do not need it) and is waited for before the prolongator smoothing.
 static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double* coords, int dim,
-                            const fr_amg_opts& o, bool keep, hipStream_t s, hipStream_t aux, const char* tag) {
+                            const fr_amg_opts& o, bool keep, hipStream_t s, hipStream_t aux, const char* tag,
+                            const MfState* mf0 = nullptr, int blk = 0) {
     // profile names of the setup phases, per hierarchy (u / phi)
     const std::string t(tag);
     const std::string nm_lambda = "setup_lambda_" + t, nm_agg = "setup_aggregate_" + t,
@@ -1678,7 +1682,7 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
             FR_HIP(hipEventRecord(ev_aux, s));
             FR_HIP(hipStreamWaitEvent(aux, ev_aux, 0));
             ProfScope ps(nm_lambda.c_str(), aux, 0.0);
-            power_start(pe, L->A, L->invd.p, aux);
+            power_start(pe, L->A, L->invd.p, aux, l == 0 ? mf0 : nullptr, blk);
         }
         const int64_t nrows = L->A.rows() * L->A.br;
         const bool last = nrows <= o.coarse_max || l + 1 >= o.max_levels;
@@ -1753,14 +1757,15 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
 
 // Same aggregates, tentative prolongators and sparsity; new values from the level-0 matrix
 // at a0 (whose structure is the one the hierarchy was built on).
-static void refresh_hierarchy(Hierarchy& H, double* a0, const fr_amg_opts& o, hipStream_t s) {
+static void refresh_hierarchy(Hierarchy& H, double* a0, const fr_amg_opts& o, hipStream_t s,
+                              const MfState* mf0 = nullptr, int blk = 0) {
     const size_t nl = H.lv.size();
     H.lv[0]->A.val = a0;
     for (size_t l = 0; l < nl; ++l) {
         AmgLevel& L = *H.lv[l];
         DBuf<double> dnorm;
         diag_info(L.A, L.invd, dnorm, s);
-        L.lmax = lambda_max(L.A, L.invd.p, s);
+        L.lmax = lambda_max(L.A, L.invd.p, s, l == 0 ? mf0 : nullptr, blk);
         if (l + 1 == nl) break;
         const double omega = 4.0 / (3.0 * L.lmax);
         spgemm_values<1>(L.A, L.Pt, L.P, L.invd.p, omega, s);
@@ -1805,17 +1810,20 @@ void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s)
     FR_HIP(hipEventRecord(amg.ev_fork, s));
     FR_HIP(hipStreamWaitEvent(amg.side, amg.ev_fork, 0));
     const hipStream_t side = amg.side;
-    auto phi_setup = [&amg, &sys, &m, o, refresh_phi, side]() {
+    // the fine levels' power steps apply the blocks matrix-free where the V-cycle will
+    const MfState* mf_u = ((o.fine_matrix_free & 1) && sys.mf.valid) ? &sys.mf : nullptr;
+    const MfState* mf_p = ((o.fine_matrix_free & 2) && sys.mf.valid) ? &sys.mf : nullptr;
+    auto phi_setup = [&amg, &sys, &m, o, refresh_phi, side, mf_p]() {
         if (refresh_phi) {
             ProfScope ps("setup_refresh_phi", side, 0.0);
-            refresh_hierarchy(amg.h[1], sys.Jpp.val, o, side);
+            refresh_hierarchy(amg.h[1], sys.Jpp.val, o, side, mf_p, 1);
         } else {
             BMat<double> Ap;
             Ap.br = Ap.bc = 1;
             Ap.S = sys.Jpp.S;
             Ap.val = sys.Jpp.val;
             build_hierarchy(amg.h[1], std::move(Ap), 1, m.coords_free.p, m.dim, o, o.refresh_phi != 0, side,
-                            amg.aux[1], "phi");
+                            amg.aux[1], "phi", mf_p, 1);
         }
     };
     auto u_setup = [&]() {
@@ -1824,7 +1832,7 @@ void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s)
         Au.S = sys.Juu.S;
         Au.val = sys.Juu.val;
         build_hierarchy(amg.h[0], std::move(Au), m.dim == 2 ? 3 : 6, m.coords_free.p, m.dim, o, false, s, amg.aux[0],
-                        "u");
+                        "u", mf_u, 0);
     };
     if (keep_u) {
         phi_setup();

@@ -17,10 +17,13 @@
 // FP64 vector rate.  The phase-field rows are applied the same way from the assembly's u and
 // phi and its active set (below).
 //
-// A workgroup works on a 31 x 7 tile of nodes (lexicographic numbering, x fastest): it reads the
-// tile's patch of x and of the state once into LDS, computes each of the 32 x 8 cells around the
-// tile once (one thread per cell: the Gauss-point quantities and the contributions to the cell's
-// four vertices), and every node sums the contributions of its four cells.
+// Each wave streams up a strip of node columns (lexicographic numbering, x fastest): one lane per
+// node column, one node row after the other.  A lane reads its node of the row (coalesced across
+// the wave), takes its right neighbour's values by a lane shuffle, computes the cell above-right
+// of its node (the Gauss-point quantities and the contributions to the cell's four vertices), and
+// sums its node's row from its own cell, the left lane's cell (shuffled) and the two cells of the
+// row below (kept from the previous step).  No LDS and no barrier: the next row's loads are
+// issued before the current row's arithmetic, so they are in flight while it runs.
 #include "profile.h"
 #include "system.h"
 
@@ -31,180 +34,111 @@ namespace {
 constexpr double kP = 0.78867513459481288225;
 constexpr double kM = 0.21132486540518711775;
 
-// N_b at Gauss point q (bit k of b / q: upper side along axis k)
-__device__ __forceinline__ constexpr double nq(int q, int b) {
-    return ((b & 1) == (q & 1) ? kP : kM) * (((b >> 1) & 1) == ((q >> 1) & 1) ? kP : kM);
-}
-
-// dN_b / dxi_k at Gauss point q on the reference square [-1, 1]^2
+// dN_b / dxi_k at Gauss point q on the reference square [-1, 1]^2 (bit k of b / q: upper side
+// along axis k)
 __device__ __forceinline__ constexpr double gq(int q, int b, int k) {
     const int o = 1 - k;   // the other axis
     return (((b >> k) & 1) ? 0.5 : -0.5) * (((b >> o) & 1) == ((q >> o) & 1) ? kP : kM);
 }
 
-// Tiles: a workgroup of 256 threads owns the nodes i0 .. i0 + 30 of rows j0 .. j0 + 6 (31 x 7)
-// and computes, one thread per cell, the 32 x 8 cells around them (the node tile grown by one
-// cell to the left and below) from the 33 x 9 patch of nodes it reads once into LDS.  Each cell
-// leaves the contributions to its four vertices in LDS; a node sums those of its four cells.
-constexpr int kTX = 31, kTY = 7;                 // nodes per tile
-constexpr int kCX = kTX + 1, kCY = kTY + 1;      // cells per tile (kCX * kCY = 256 threads)
-constexpr int kPX = kTX + 2, kPY = kTY + 2;      // patch nodes per tile
-static_assert(kCX * kCY == 256, "one cell per thread");
+// ---- cells ------------------------------------------------------------------------------------
+// Vertex values in registers, vertex b = 0 (lower left), 1 (lower right), 2 (upper left), 3 (upper
+// right).  The tensor-product structure of Q1 with 2 x 2 Gauss points is used: with f(b, q) = kP
+// when the vertex and the Gauss point lie on the same side of the axis (else kM),
+//   d/dxi of x at Gauss point q  = (f(0, q_y) (x_1 - x_0) + f(1, q_y) (x_3 - x_2)) / 2,
+//   d/deta                       = (f(0, q_x) (x_2 - x_0) + f(1, q_x) (x_3 - x_1)) / 2,
+// and a sum over q of N_a(q) v_q or of grad N_a(q) . s_q factors along the two axes.
 
-// x of the patch (zero on the boundary: the eliminated Dirichlet columns, and outside the mesh)
-// and phi_tilde of the patch (zero outside the mesh), in LDS.
+// Reference gradients of a vertex field: Hx[comp][q_y] = d/dxi, Hy[comp][q_x] = d/deta.
 template <typename TA>
-struct Patch {
-    TA x[2][kPY][kPX];                           // component-major: consecutive lanes, consecutive words
-    TA p[kPY][kPX];
-    TA c[4][2][kCY][kCX];                        // cell contributions to vertex a, component c
-};
-
-template <typename TA, typename TX, typename TP>
-__device__ __forceinline__ void load_patch(const MfGrid& g, const TP* __restrict__ pt, const TX* __restrict__ x,
-                                           int64_t i0, int64_t j0, Patch<TA>& P) {
-    for (int t = threadIdx.x; t < kPX * kPY; t += blockDim.x) {
-        const int px = t % kPX, py = t / kPX;
-        const int64_t bi = i0 - 1 + px, bj = j0 - 1 + py;
-        const bool in = bi >= 0 && bj >= 0 && bi <= g.nx && bj <= g.ny;
-        const bool interior = bi > 0 && bj > 0 && bi < g.nx && bj < g.ny;
-        const int64_t nb = bi + bj * g.n1;
-        P.p[py][px] = in ? TA(pt[nb]) : TA(0);
-        P.x[0][py][px] = interior ? TA(x[2 * nb]) : TA(0);
-        P.x[1][py][px] = interior ? TA(x[2 * nb + 1]) : TA(0);
+__device__ __forceinline__ void ref_grad(const TA (&v)[2][4], TA (&Hx)[2][2], TA (&Hy)[2][2]) {
+    const TA fP = TA(kP), fM = TA(kM), half = TA(0.5);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const TA dx0 = v[c][1] - v[c][0], dx1 = v[c][3] - v[c][2];
+        const TA dy0 = v[c][2] - v[c][0], dy1 = v[c][3] - v[c][1];
+        Hx[c][0] = half * (fP * dx0 + fM * dx1);
+        Hx[c][1] = half * (fM * dx0 + fP * dx1);
+        Hy[c][0] = half * (fP * dy0 + fM * dy1);
+        Hy[c][1] = half * (fM * dy0 + fP * dy1);
     }
 }
 
-// Thread t's cell (i0 - 1 + t % kCX, j0 - 1 + t / kCX): its contributions to its four vertices,
-// sum over the Gauss points of g_q sigma_q(x) grad N_a(q) (zero for a cell outside the mesh).
-// The tensor-product structure of Q1 with 2 x 2 Gauss points is used: with f(b, q) = kP when the
-// vertex and the Gauss point lie on the same side of the axis (else kM),
-//   d/dxi of the x at Gauss point q  = (f(0, q_y) (x_1 - x_0) + f(1, q_y) (x_3 - x_2)) / 2,
-//   d/deta                            = (f(0, q_x) (x_2 - x_0) + f(1, q_x) (x_3 - x_1)) / 2,
-// and the vertex contributions need only the stresses summed along one axis:
-//   c_(a, comp) = s_x(a) X_comp[a_y] + s_y(a) Y_comp[a_x],
-//   X_comp[a_y] = (f(a_y, 0) Sx_comp[0] + f(a_y, 1) Sx_comp[1]) / 2, Sx_comp[q_y] = sum over q_x
-//   of sigma[comp][0], and Y the same along the other axis with sigma[comp][1].
+// A vertex scalar along x in both vertex rows: r[b_y][q_x] (then along y per Gauss point).
 template <typename TA>
-__device__ __forceinline__ void cell_contrib(const MfGrid& g, int64_t i0, int64_t j0, Patch<TA>& P) {
-    const int cx = threadIdx.x % kCX, cy = threadIdx.x / kCX;
-    const int64_t ci = i0 - 1 + cx, cj = j0 - 1 + cy;
-    TA out[4][2];
+__device__ __forceinline__ void along_x(const TA (&v)[4], TA (&r)[2][2]) {
+    const TA fP = TA(kP), fM = TA(kM);
 #pragma unroll
-    for (int a = 0; a < 4; ++a) out[a][0] = out[a][1] = TA(0);
-    if (ci >= 0 && cj >= 0 && ci < g.nx && cj < g.ny) {
-        const TA mu = TA(g.mu), lam = TA(g.lam), kap = TA(g.kappa), omk = TA(1.0 - g.kappa);
-        const TA fP = TA(kP), fM = TA(kM), half = TA(0.5);
-        // vertex values: b = 0 (lower left), 1 (lower right), 2 (upper left), 3 (upper right)
-        TA xv[2][4], pv[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            pv[b] = P.p[cy + (b >> 1)][cx + (b & 1)];
-            xv[0][b] = P.x[0][cy + (b >> 1)][cx + (b & 1)];
-            xv[1][b] = P.x[1][cy + (b >> 1)][cx + (b & 1)];
-        }
-        // reference gradients: Hx[comp][q_y] = d x_comp / dxi, Hy[comp][q_x] = d x_comp / deta
-        TA Hx[2][2], Hy[2][2];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const TA dx0 = xv[c][1] - xv[c][0], dx1 = xv[c][3] - xv[c][2];
-            const TA dy0 = xv[c][2] - xv[c][0], dy1 = xv[c][3] - xv[c][1];
-            Hx[c][0] = half * (fP * dx0 + fM * dx1);
-            Hx[c][1] = half * (fM * dx0 + fP * dx1);
-            Hy[c][0] = half * (fP * dy0 + fM * dy1);
-            Hy[c][1] = half * (fM * dy0 + fP * dy1);
-        }
-        // phi_tilde at the Gauss points: along x in both vertex rows, then along y
-        TA pr[2][2];
-#pragma unroll
-        for (int by = 0; by < 2; ++by) {
-            pr[by][0] = fP * pv[2 * by] + fM * pv[2 * by + 1];
-            pr[by][1] = fM * pv[2 * by] + fP * pv[2 * by + 1];
-        }
-        TA Sx[2][2] = {{TA(0), TA(0)}, {TA(0), TA(0)}}, Sy[2][2] = {{TA(0), TA(0)}, {TA(0), TA(0)}};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int qx = q & 1, qy = q >> 1;
-            const TA ph = qy ? fM * pr[0][qx] + fP * pr[1][qx] : fP * pr[0][qx] + fM * pr[1][qx];
-            const TA gg = omk * ph * ph + kap;
-            const TA h00 = Hx[0][qy], h01 = Hy[0][qx], h10 = Hx[1][qy], h11 = Hy[1][qx];
-            const TA tr = h00 + h11;
-            const TA s00 = gg * (TA(2) * mu * h00 + lam * tr);
-            const TA s11 = gg * (TA(2) * mu * h11 + lam * tr);
-            const TA s01 = gg * (mu * (h01 + h10));
-            Sx[0][qy] += s00;                    // sigma[0][0]
-            Sx[1][qy] += s01;                    // sigma[1][0]
-            Sy[0][qx] += s01;                    // sigma[0][1]
-            Sy[1][qx] += s11;                    // sigma[1][1]
-        }
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const TA X0 = half * (fP * Sx[c][0] + fM * Sx[c][1]), X1 = half * (fM * Sx[c][0] + fP * Sx[c][1]);
-            const TA Y0 = half * (fP * Sy[c][0] + fM * Sy[c][1]), Y1 = half * (fM * Sy[c][0] + fP * Sy[c][1]);
-            out[0][c] = -X0 - Y0;                // a = (0, 0)
-            out[1][c] = X0 - Y1;                 // a = (1, 0)
-            out[2][c] = -X1 + Y0;                // a = (0, 1)
-            out[3][c] = X1 + Y1;                 // a = (1, 1)
-        }
+    for (int by = 0; by < 2; ++by) {
+        r[by][0] = fP * v[2 * by] + fM * v[2 * by + 1];
+        r[by][1] = fM * v[2 * by] + fP * v[2 * by + 1];
     }
+}
+template <typename TA>
+__device__ __forceinline__ TA at_q(const TA (&r)[2][2], int qx, int qy) {
+    const TA fP = TA(kP), fM = TA(kM);
+    return qy ? fM * r[0][qx] + fP * r[1][qx] : fP * r[0][qx] + fM * r[1][qx];
+}
+
+// Displacement block: a cell's contributions to its vertices' rows of M_uu x (Hx, Hy: the
+// reference gradients of x, zero at the Dirichlet nodes), sum over the Gauss points of
+// g_q sigma_q(x) grad N_a(q), and the Gauss-point degradations g_q = (1 - kappa) phi_tilde_q^2 + kappa.  The vertex contributions need only the
+// stresses summed along one axis: c_(a, comp) = s_x(a) X_comp[a_y] + s_y(a) Y_comp[a_x],
+// X_comp[a_y] = (f(a_y, 0) Sx_comp[0] + f(a_y, 1) Sx_comp[1]) / 2, Sx_comp[q_y] = sum over q_x of
+// sigma[comp][0], and Y the same along the other axis with sigma[comp][1].
+template <typename TA>
+__device__ __forceinline__ void cell_u(const MfGrid& g, const TA (&Hx)[2][2], const TA (&Hy)[2][2], const TA (&pv)[4],
+                                       TA (&out)[4][2], TA (&gg)[4]) {
+    const TA mu = TA(g.mu), lam = TA(g.lam), kap = TA(g.kappa), omk = TA(1.0 - g.kappa);
+    const TA fP = TA(kP), fM = TA(kM), half = TA(0.5);
+    TA pr[2][2];
+    along_x<TA>(pv, pr);
+    TA Sx[2][2] = {{TA(0), TA(0)}, {TA(0), TA(0)}}, Sy[2][2] = {{TA(0), TA(0)}, {TA(0), TA(0)}};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int qx = q & 1, qy = q >> 1;
+        const TA ph = at_q<TA>(pr, qx, qy);
+        gg[q] = omk * ph * ph + kap;
+        const TA h00 = Hx[0][qy], h01 = Hy[0][qx], h10 = Hx[1][qy], h11 = Hy[1][qx];
+        const TA tr = h00 + h11;
+        const TA s00 = gg[q] * (TA(2) * mu * h00 + lam * tr);
+        const TA s11 = gg[q] * (TA(2) * mu * h11 + lam * tr);
+        const TA s01 = gg[q] * (mu * (h01 + h10));
+        Sx[0][qy] += s00;                    // sigma[0][0]
+        Sx[1][qy] += s01;                    // sigma[1][0]
+        Sy[0][qx] += s01;                    // sigma[0][1]
+        Sy[1][qx] += s11;                    // sigma[1][1]
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const TA X0 = half * (fP * Sx[c][0] + fM * Sx[c][1]), X1 = half * (fM * Sx[c][0] + fP * Sx[c][1]);
+        const TA Y0 = half * (fP * Sy[c][0] + fM * Sy[c][1]), Y1 = half * (fM * Sy[c][0] + fP * Sy[c][1]);
+        out[0][c] = -X0 - Y0;                // a = (0, 0)
+        out[1][c] = X0 - Y1;                 // a = (1, 0)
+        out[2][c] = -X1 + Y0;                // a = (0, 1)
+        out[3][c] = X1 + Y1;                 // a = (1, 1)
+    }
+}
+
+// A cell's part of the original diagonal entries of its vertices' two rows (what a Dirichlet row
+// keeps): sum over q of g_q (mu (|grad N_a|^2 + (d_c N_a)^2) + lambda (d_c N_a)^2).
+template <typename TA>
+__device__ __forceinline__ void cell_u_diag(const MfGrid& g, const TA (&gg)[4], TA (&dg)[4][2]) {
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        P.c[a][0][cy][cx] = out[a][0];
-        P.c[a][1][cy][cx] = out[a][1];
-    }
-}
-
-// Original diagonal entries of a Dirichlet node's two rows (the node of thread tile position
-// (tx, ty)): sum over its cells of g_q (mu (|grad N_a|^2 + (d_c N_a)^2) + lambda (d_c N_a)^2).
-template <typename TA>
-__device__ __forceinline__ void dirichlet_diag(const MfGrid& g, int64_t i, int64_t j, int tx, int ty,
-                                               const Patch<TA>& P, TA dg[2]) {
-    const TA mu = TA(g.mu), lam = TA(g.lam), kap = TA(g.kappa), omk = TA(1.0 - g.kappa);
-    dg[0] = dg[1] = TA(0);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int ex = e & 1, ey = e >> 1;       // cell to the lower-left (0) ... upper-right (3)
-        const int64_t ci = i - 1 + ex, cj = j - 1 + ey;
-        if (ci < 0 || cj < 0 || ci >= g.nx || cj >= g.ny) continue;
-        const int a = (1 - ex) + 2 * (1 - ey);  // the node's vertex in that cell
-        const int cx = tx + ex, cy = ty + ey;    // the cell's patch position
+        dg[a][0] = dg[a][1] = TA(0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            TA ph = TA(0);
-#pragma unroll
-            for (int b = 0; b < 4; ++b) ph += TA(nq(q, b)) * P.p[cy + (b >> 1)][cx + (b & 1)];
-            const TA gg = omk * ph * ph + kap;
-            const TA ga0 = TA(gq(q, a, 0)), ga1 = TA(gq(q, a, 1));
-            const TA nn = ga0 * ga0 + ga1 * ga1;
-            dg[0] += gg * (mu * (nn + ga0 * ga0) + lam * ga0 * ga0);
-            dg[1] += gg * (mu * (nn + ga1 * ga1) + lam * ga1 * ga1);
+            const double ga0 = gq(q, a, 0), ga1 = gq(q, a, 1), nn = ga0 * ga0 + ga1 * ga1;
+            dg[a][0] += gg[q] * TA(g.mu * (nn + ga0 * ga0) + g.lam * ga0 * ga0);
+            dg[a][1] += gg[q] * TA(g.mu * (nn + ga1 * ga1) + g.lam * ga1 * ga1);
         }
     }
 }
 
-// The masked M_uu row of the tile node at (tx, ty) (tx < kTX, ty < kTY) from the cells' LDS
-// contributions: vertex 0 of the cell at (tx+1, ty+1), 1 of (tx, ty+1), 2 of (tx+1, ty), 3 of
-// (tx, ty).  A Dirichlet row is its diagonal entry times x_r.
-template <typename TA, typename TX>
-__device__ __forceinline__ void node_row(const MfGrid& g, int64_t i, int64_t j, int64_t r, int tx, int ty,
-                                         const Patch<TA>& P, const TX* __restrict__ x, TA y[2]) {
-    const bool dir = i == 0 || j == 0 || i == g.nx || j == g.ny;
-    if (dir) {
-        TA dg[2];
-        dirichlet_diag<TA>(g, i, j, tx, ty, P, dg);
-        y[0] = dg[0] * TA(x[2 * r]);
-        y[1] = dg[1] * TA(x[2 * r + 1]);
-        return;
-    }
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-        y[c] = ((P.c[0][c][ty + 1][tx + 1] + P.c[1][c][ty + 1][tx]) + P.c[2][c][ty][tx + 1]) + P.c[3][c][ty][tx];
-}
-
-// ---- phase-field rows ------------------------------------------------------------------------
-// The phase-field rows of the masked Jacobian at the assembly's state (u_s, phi_s).  Per Gauss
-// point q of a cell, with the reference gradients G of u_s and H of x_u, the stress in reference
-// units sigma^ = 2 mu sym G + lambda tr G I, and w|J| = h^2 / 4 (the h factors of the physical
+// Phase-field rows of the masked Jacobian at the assembly's state (u_s, phi_s).  Per Gauss point
+// q, with the reference gradients G of u_s and H of x_u, the stress in reference units
+// sigma^ = 2 mu sym G + lambda tr G I, and w|J| = h^2 / 4 (the h factors of the physical
 // gradients leave or become explicit):
 //   M_phiphi x_phi:  x_phi(q) ((1 - kappa) sigma^ : sym G + h p tr G + (h^2 / 4) G_c / eps) N_a(q)
 //                    + G_c eps grad^ x_phi(q) . grad^ N_a(q),
@@ -212,185 +146,250 @@ __device__ __forceinline__ void node_row(const MfGrid& g, int64_t i, int64_t j, 
 // with x_phi zero at active nodes (their columns are eliminated), x_u zero at Dirichlet nodes,
 // and an active row replaced by its diagonal entry times x_phi.  The gradient term is the Q1
 // stiffness matrix of the reference square (2/3 on the diagonal, -1/6 along an edge, -1/3
-// across), which the 2-point rule integrates exactly.
-template <typename TA>
-struct PPatch {
-    TA u[2][kPY][kPX];                           // u_s (every node of the mesh, zero outside)
-    TA x[kPY][kPX];                              // x_phi (zero at active nodes and outside)
-    TA c[4][kCY][kCX];                           // cell contributions to vertex a
-};
-
-template <typename TA, typename TX, typename TU>
-__device__ __forceinline__ void load_ppatch(const MfGrid& g, const TU* __restrict__ us, const uint8_t* __restrict__ act,
-                                            const TX* __restrict__ xp, int64_t i0, int64_t j0, PPatch<TA>& F) {
-    for (int t = threadIdx.x; t < kPX * kPY; t += blockDim.x) {
-        const int px = t % kPX, py = t / kPX;
-        const int64_t bi = i0 - 1 + px, bj = j0 - 1 + py;
-        const bool in = bi >= 0 && bj >= 0 && bi <= g.nx && bj <= g.ny;
-        const int64_t nb = bi + bj * g.n1;
-        F.u[0][py][px] = in ? TA(us[2 * nb]) : TA(0);
-        F.u[1][py][px] = in ? TA(us[2 * nb + 1]) : TA(0);
-        F.x[py][px] = (in && act[nb] == 0) ? TA(xp[nb]) : TA(0);
-    }
-}
-
-// Thread t's cell: its contributions to the phase-field rows of its four vertices (M_phiphi
-// x_phi, plus M_phiu x_u when JPU, from the x_u patch xu and the phi_s patch ps).
+// across), which the 2-point rule integrates exactly.  JPU adds the M_phiu part (Hx, Hy: the
+// reference gradients of x_u; pv: phi_s).
 template <typename TA, bool JPU>
-__device__ __forceinline__ void phi_cell(const MfGrid& g, int64_t i0, int64_t j0, PPatch<TA>& F,
-                                         const TA (*xu)[kPY][kPX], const TA (*ps)[kPX]) {
-    const int cx = threadIdx.x % kCX, cy = threadIdx.x / kCX;
-    const int64_t ci = i0 - 1 + cx, cj = j0 - 1 + cy;
-    TA out[4];
+__device__ __forceinline__ void cell_phi(const MfGrid& g, const TA (&uv)[2][4], const TA (&xv)[4], const TA (&Hx)[2][2],
+                                         const TA (&Hy)[2][2], const TA (&pv)[4], TA (&out)[4]) {
+    const TA mu = TA(g.mu), lam = TA(g.lam), omk = TA(1.0 - g.kappa);
+    const TA hp = TA(g.h * g.p), gh = TA(0.25 * g.h * g.h * g.Gc / g.eps), ge = TA(g.Gc * g.eps);
+    const TA fP = TA(kP), fM = TA(kM);
+    TA Gx[2][2], Gy[2][2], xr[2][2];
+    ref_grad<TA>(uv, Gx, Gy);
+    along_x<TA>(xv, xr);
+    TA pr[2][2];
+    if constexpr (JPU) along_x<TA>(pv, pr);
+    TA v[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) out[a] = TA(0);
-    if (ci >= 0 && cj >= 0 && ci < g.nx && cj < g.ny) {
-        const TA mu = TA(g.mu), lam = TA(g.lam), omk = TA(1.0 - g.kappa);
-        const TA hp = TA(g.h * g.p), gh = TA(0.25 * g.h * g.h * g.Gc / g.eps), ge = TA(g.Gc * g.eps);
-        const TA fP = TA(kP), fM = TA(kM), half = TA(0.5);
-        TA uv[2][4], xv[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            uv[0][b] = F.u[0][cy + (b >> 1)][cx + (b & 1)];
-            uv[1][b] = F.u[1][cy + (b >> 1)][cx + (b & 1)];
-            xv[b] = F.x[cy + (b >> 1)][cx + (b & 1)];
-        }
-        // reference gradients of u_s: Gx[comp][q_y] = d/dxi, Gy[comp][q_x] = d/deta
-        TA Gx[2][2], Gy[2][2];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const TA dx0 = uv[c][1] - uv[c][0], dx1 = uv[c][3] - uv[c][2];
-            const TA dy0 = uv[c][2] - uv[c][0], dy1 = uv[c][3] - uv[c][1];
-            Gx[c][0] = half * (fP * dx0 + fM * dx1);
-            Gx[c][1] = half * (fM * dx0 + fP * dx1);
-            Gy[c][0] = half * (fP * dy0 + fM * dy1);
-            Gy[c][1] = half * (fM * dy0 + fP * dy1);
-        }
-        // x_phi along x in both vertex rows (then along y per Gauss point)
-        TA xr[2][2];
-#pragma unroll
-        for (int by = 0; by < 2; ++by) {
-            xr[by][0] = fP * xv[2 * by] + fM * xv[2 * by + 1];
-            xr[by][1] = fM * xv[2 * by] + fP * xv[2 * by + 1];
-        }
-        TA Hx[2][2], Hy[2][2], pr[2][2];
+    for (int q = 0; q < 4; ++q) {
+        const int qx = q & 1, qy = q >> 1;
+        const TA X = at_q<TA>(xr, qx, qy);
+        const TA g00 = Gx[0][qy], g11 = Gy[1][qx], g01 = Gy[0][qx] + Gx[1][qy];   // g01: twice sym G[0][1]
+        const TA tr = g00 + g11;
+        const TA s00 = TA(2) * mu * g00 + lam * tr, s11 = TA(2) * mu * g11 + lam * tr, s01 = mu * g01;
+        const TA se = s00 * g00 + s11 * g11 + s01 * g01;                          // sigma^ : sym G
+        TA vq = (omk * se + hp * tr + gh) * X;
         if constexpr (JPU) {
-            TA wv[2][4], pv[4];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                wv[0][b] = xu[0][cy + (b >> 1)][cx + (b & 1)];
-                wv[1][b] = xu[1][cy + (b >> 1)][cx + (b & 1)];
-                pv[b] = ps[cy + (b >> 1)][cx + (b & 1)];
-            }
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const TA dx0 = wv[c][1] - wv[c][0], dx1 = wv[c][3] - wv[c][2];
-                const TA dy0 = wv[c][2] - wv[c][0], dy1 = wv[c][3] - wv[c][1];
-                Hx[c][0] = half * (fP * dx0 + fM * dx1);
-                Hx[c][1] = half * (fM * dx0 + fP * dx1);
-                Hy[c][0] = half * (fP * dy0 + fM * dy1);
-                Hy[c][1] = half * (fM * dy0 + fP * dy1);
-            }
-#pragma unroll
-            for (int by = 0; by < 2; ++by) {
-                pr[by][0] = fP * pv[2 * by] + fM * pv[2 * by + 1];
-                pr[by][1] = fM * pv[2 * by] + fP * pv[2 * by + 1];
-            }
+            const TA ph = at_q<TA>(pr, qx, qy);
+            const TA h00 = Hx[0][qy], h11 = Hy[1][qx], h01 = Hy[0][qx] + Hx[1][qy];
+            const TA sh = s00 * h00 + s11 * h11 + s01 * h01;                      // sigma^ : H
+            vq += ph * (TA(2) * omk * sh + hp * (h00 + h11));
         }
-        TA v[4];
+        v[q] = vq;
+    }
+    // sum over q of N_a(q) v_q, N_a(q) = f(a_x, q_x) f(a_y, q_y): along x, then along y
+    TA V[2][2];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int qx = q & 1, qy = q >> 1;
-            const TA X = qy ? fM * xr[0][qx] + fP * xr[1][qx] : fP * xr[0][qx] + fM * xr[1][qx];
-            const TA g00 = Gx[0][qy], g11 = Gy[1][qx], g01 = Gy[0][qx] + Gx[1][qy];   // g01: twice sym G[0][1]
-            const TA tr = g00 + g11;
-            const TA s00 = TA(2) * mu * g00 + lam * tr, s11 = TA(2) * mu * g11 + lam * tr, s01 = mu * g01;
-            const TA se = s00 * g00 + s11 * g11 + s01 * g01;                          // sigma^ : sym G
-            TA vq = (omk * se + hp * tr + gh) * X;
-            if constexpr (JPU) {
-                const TA ph = qy ? fM * pr[0][qx] + fP * pr[1][qx] : fP * pr[0][qx] + fM * pr[1][qx];
-                const TA h00 = Hx[0][qy], h11 = Hy[1][qx], h01 = Hy[0][qx] + Hx[1][qy];
-                const TA sh = s00 * h00 + s11 * h11 + s01 * h01;                      // sigma^ : H
-                vq += ph * (TA(2) * omk * sh + hp * (h00 + h11));
-            }
-            v[q] = vq;
-        }
-        // sum over q of N_a(q) v_q, N_a(q) = f(a_x, q_x) f(a_y, q_y): along x, then along y
-        TA V[2][2];
+    for (int qy = 0; qy < 2; ++qy) {
+        V[qy][0] = fP * v[2 * qy] + fM * v[2 * qy + 1];
+        V[qy][1] = fM * v[2 * qy] + fP * v[2 * qy + 1];
+    }
+    const TA k0 = TA(2.0 / 3.0), k1 = TA(1.0 / 6.0), k3 = TA(1.0 / 3.0);
 #pragma unroll
-        for (int qy = 0; qy < 2; ++qy) {
-            V[qy][0] = fP * v[2 * qy] + fM * v[2 * qy + 1];
-            V[qy][1] = fM * v[2 * qy] + fP * v[2 * qy + 1];
-        }
-        const TA k0 = TA(2.0 / 3.0), k1 = TA(1.0 / 6.0), k3 = TA(1.0 / 3.0);
+    for (int a = 0; a < 4; ++a) {
+        const int ax = a & 1, ay = a >> 1;
+        const TA m = ay ? fM * V[0][ax] + fP * V[1][ax] : fP * V[0][ax] + fM * V[1][ax];
+        out[a] = m + ge * (k0 * xv[a] - k1 * (xv[a ^ 1] + xv[a ^ 2]) - k3 * xv[a ^ 3]);
+    }
+}
+
+// ---- wave strips ------------------------------------------------------------------------------
+// A wave's lanes take the node columns s*kSW - 1 .. s*kSW + 62 of strip s; lane l computes the cell
+// whose lower-left vertex is its node (lanes 0..62) and writes its node's rows (lanes 1..kSW), for
+// the node rows of band b, [b*kBand, (b+1)*kBand).  Lane 0's cell feeds lane 1, lane 63's node
+// is the right vertex of lane 62's cell.
+constexpr int kWaveLanes = 64;
+constexpr int kSW = kWaveLanes - 2;              // node columns a wave writes
+constexpr int kBand = 16;                        // node rows a wave writes
+
+struct WaveStrip {
+    int64_t col, j0, j1;                         // the lane's node column; node rows written [j0, j1)
+    int lane;
+    bool valid, writer;
+    bool col_in, col_int;                        // column inside the mesh / not on its left or right edge
+};
+
+__device__ __forceinline__ int64_t n_strips(const MfGrid& g) { return (g.n1 + kSW - 1) / kSW; }
+__device__ __forceinline__ int64_t n_bands(const MfGrid& g) { return (g.ny + kBand) / kBand; }
+
+__device__ __forceinline__ WaveStrip wave_strip(const MfGrid& g) {
+    WaveStrip w;
+    w.lane = int(threadIdx.x % kWaveLanes);
+    const int64_t wv = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWaveLanes;
+    const int64_t ns = n_strips(g);
+    w.valid = wv < ns * n_bands(g);
+    const int64_t s = wv % ns, b = wv / ns;
+    w.col = s * kSW - 1 + w.lane;
+    w.j0 = b * kBand;
+    w.j1 = w.j0 + kBand < g.ny + 1 ? w.j0 + kBand : g.ny + 1;
+    w.col_in = w.col >= 0 && w.col <= g.nx;
+    w.col_int = w.col > 0 && w.col < g.nx;
+    w.writer = w.valid && w.lane >= 1 && w.lane <= kSW && w.col <= g.nx;
+    return w;
+}
+
+// the value of the lane to the right / left (the wave's last / first lane gets its own)
+template <typename TA>
+__device__ __forceinline__ TA from_right(TA v) { return __shfl_down(v, 1, kWaveLanes); }
+template <typename TA>
+__device__ __forceinline__ TA from_left(TA v) { return __shfl_up(v, 1, kWaveLanes); }
+
+__device__ __forceinline__ bool cell_at(const MfGrid& g, const WaveStrip& w, int64_t j) {
+    return w.lane < kWaveLanes - 1 && w.col >= 0 && w.col < g.nx && j >= 0 && j < g.ny;
+}
+__device__ __forceinline__ bool row_in(const MfGrid& g, int64_t j) { return j >= 0 && j <= g.ny; }
+__device__ __forceinline__ bool dirichlet(const MfGrid& g, int64_t i, int64_t j) {
+    return i == 0 || j == 0 || i == g.nx || j == g.ny;
+}
+
+// The displacement rows of a cell row: each lane's cell (Hx, Hy from masked_grad; the Dirichlet
+// vertices' contributions replaced by their diagonal parts), then this lane's node of
+// the bottom row: ((own cell + left cell) + own cell below + left cell below), the last two
+// carried in c2 / c3 from the previous row.  Returns, for the Dirichlet node, the sum of the
+// diagonal parts (the caller multiplies by x).
+// Reference gradients over this lane's cell of x_u masked at the Dirichlet nodes (rows j, j + 1).
+template <typename TA>
+__device__ __forceinline__ void masked_grad(const MfGrid& g, const WaveStrip& w, int64_t j, const TA (&xB)[2],
+                                            const TA (&xT)[2], TA (&Hx)[2][2], TA (&Hy)[2][2]) {
+    const bool iB = w.col_int && j > 0 && j < g.ny, iT = w.col_int && j + 1 > 0 && j + 1 < g.ny;
+    TA xv[2][4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int ax = a & 1, ay = a >> 1;
-            const TA m = ay ? fM * V[0][ax] + fP * V[1][ax] : fP * V[0][ax] + fM * V[1][ax];
-            out[a] = m + ge * (k0 * xv[a] - k1 * (xv[a ^ 1] + xv[a ^ 2]) - k3 * xv[a ^ 3]);
+    for (int c = 0; c < 2; ++c) {
+        xv[c][0] = iB ? xB[c] : TA(0);
+        xv[c][2] = iT ? xT[c] : TA(0);
+        xv[c][1] = from_right(xv[c][0]);
+        xv[c][3] = from_right(xv[c][2]);
+    }
+    ref_grad<TA>(xv, Hx, Hy);
+}
+
+template <typename TA>
+__device__ __forceinline__ void u_rows(const MfGrid& g, const WaveStrip& w, int64_t j, const TA (&Hx)[2][2],
+                                       const TA (&Hy)[2][2], TA pB, TA pT, TA (&c2)[2], TA (&c3)[2], TA (&y)[2]) {
+    TA pv[4];
+    pv[0] = pB;
+    pv[2] = pT;
+    pv[1] = from_right(pB);
+    pv[3] = from_right(pT);
+    TA out[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) out[a][0] = out[a][1] = TA(0);
+    if (cell_at(g, w, j)) {
+        TA gg[4];
+        cell_u<TA>(g, Hx, Hy, pv, out, gg);
+        if (w.col == 0 || w.col == g.nx - 1 || j == 0 || j == g.ny - 1) {
+            TA dg[4][2];
+            cell_u_diag<TA>(g, gg, dg);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+                if (dirichlet(g, w.col + (a & 1), j + (a >> 1))) {
+                    out[a][0] = dg[a][0];
+                    out[a][1] = dg[a][1];
+                }
         }
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a) F.c[a][cy][cx] = out[a];
+    for (int c = 0; c < 2; ++c) {
+        const TA c1 = from_left(out[1][c]), c3n = from_left(out[3][c]);
+        y[c] = ((out[0][c] + c1) + c2[c]) + c3[c];
+        c2[c] = out[2][c];
+        c3[c] = c3n;
+    }
 }
 
-// The phase-field row of the tile node at (tx, ty) from its four cells' contributions.
-template <typename TA>
-__device__ __forceinline__ TA phi_row(const PPatch<TA>& F, int tx, int ty) {
-    return ((F.c[0][ty + 1][tx + 1] + F.c[1][ty + 1][tx]) + F.c[2][ty][tx + 1]) + F.c[3][ty][tx];
-}
-
-// Tile origin of this workgroup and the node of this thread (valid: inside the tile and mesh).
-struct TileNode {
-    int64_t i0, j0, i, j, r;
-    int tx, ty;
-    bool valid;
-};
-
-__device__ __forceinline__ TileNode tile_node(const MfGrid& g) {
-    TileNode t;
-    t.i0 = int64_t(blockIdx.x) * kTX;
-    t.j0 = int64_t(blockIdx.y) * kTY;
-    t.tx = threadIdx.x % kCX;
-    t.ty = threadIdx.x / kCX;
-    t.i = t.i0 + t.tx;
-    t.j = t.j0 + t.ty;
-    t.valid = t.tx < kTX && t.ty < kTY && t.i <= g.nx && t.j <= g.ny;
-    t.r = t.i + t.j * g.n1;
-    return t;
+// The phase-field rows of a cell row, as u_rows (JPU: with M_phiu x_u from the gradients Hx, Hy
+// of masked_grad and phi_s).
+template <typename TA, bool JPU>
+__device__ __forceinline__ TA phi_rows(const MfGrid& g, const WaveStrip& w, int64_t j, const TA (&uB)[2],
+                                       const TA (&uT)[2], TA xB, TA xT, const TA (&Hx)[2][2], const TA (&Hy)[2][2],
+                                       TA psB, TA psT, TA& c2, TA& c3) {
+    TA uv[2][4], xv[4], pv[4];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        uv[c][0] = uB[c];
+        uv[c][2] = uT[c];
+        uv[c][1] = from_right(uB[c]);
+        uv[c][3] = from_right(uT[c]);
+    }
+    xv[0] = xB;
+    xv[2] = xT;
+    xv[1] = from_right(xB);
+    xv[3] = from_right(xT);
+    if constexpr (JPU) {
+        pv[0] = psB;
+        pv[2] = psT;
+        pv[1] = from_right(psB);
+        pv[3] = from_right(psT);
+    }
+    TA out[4] = {TA(0), TA(0), TA(0), TA(0)};
+    if (cell_at(g, w, j)) cell_phi<TA, JPU>(g, uv, xv, Hx, Hy, pv, out);
+    const TA c1 = from_left(out[1]), c3n = from_left(out[3]);
+    const TA y = ((out[0] + c1) + c2) + c3;
+    c2 = out[2];
+    c3 = c3n;
+    return y;
 }
 
 // Chebyshev step of the fine displacement level: r = b - M_uu x_old; d = alpha d + beta D^-1 r;
-// x_new = x_old + d (the assembled kernel's update, same order of the update terms).
-template <typename T>
+// x_new = x_old + d (the assembled kernel's update, same order of the update terms).  POW: a
+// power step of the smoother bounds instead, d = D^-1 M_uu x_old (b and x_new untouched).
+template <typename T, bool POW = false>
 __global__ void __launch_bounds__(256) k_mf_cheb(MfGrid g, const T* __restrict__ pt, const T* __restrict__ invd,
                                                  const T* __restrict__ x_old, const T* __restrict__ b,
                                                  T* __restrict__ d, T* __restrict__ x_new, T alpha, T beta) {
-    __shared__ Patch<T> P;
-    const TileNode t = tile_node(g);
-    T bv[2], dv[2], iv[2], xo[2];
-    if (t.valid) {
+    const WaveStrip w = wave_strip(g);
+    if (!w.valid) return;
+    auto ld = [&](int64_t j, T& p, T (&x)[2]) {
+        const bool in = w.col_in && row_in(g, j);
+        const int64_t r = w.col + j * g.n1;
+        p = in ? pt[r] : T(0);
+        x[0] = in ? x_old[2 * r] : T(0);
+        x[1] = in ? x_old[2 * r + 1] : T(0);
+    };
+    T pB, pT, xB[2], xT[2], c2[2] = {T(0), T(0)}, c3[2] = {T(0), T(0)};
+    ld(w.j0 - 1, pB, xB);
+    ld(w.j0, pT, xT);
+    for (int64_t j = w.j0 - 1; j < w.j1; ++j) {
+        T pN, xN[2];
+        ld(j + 2, pN, xN);
+        const bool wr = w.writer && j >= w.j0;
+        const int64_t r = w.col + j * g.n1;
+        T bv[2] = {T(0), T(0)}, dv[2] = {T(0), T(0)}, iv[2] = {T(0), T(0)};
+        if (wr) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if (!POW) {
+                    bv[c] = b[2 * r + c];
+                    dv[c] = alpha != T(0) ? d[2 * r + c] : T(0);
+                }
+                iv[c] = invd[2 * r + c];
+            }
+        }
+        T y[2], Hx[2][2], Hy[2][2];
+        masked_grad<T>(g, w, j, xB, xT, Hx, Hy);
+        u_rows<T>(g, w, j, Hx, Hy, pB, pT, c2, c3, y);
+        if (wr) {
+            const bool dir = dirichlet(g, w.col, j);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const T yc = dir ? y[c] * xB[c] : y[c];
+                if (POW) {
+                    d[2 * r + c] = iv[c] * yc;
+                } else {
+                    const T res = bv[c] - yc;
+                    const T dn = (alpha != T(0) ? alpha * dv[c] : T(0)) + beta * iv[c] * res;
+                    d[2 * r + c] = dn;
+                    x_new[2 * r + c] = xB[c] + dn;
+                }
+            }
+        }
+        pB = pT;
+        pT = pN;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            bv[c] = b[2 * t.r + c];
-            dv[c] = alpha != T(0) ? d[2 * t.r + c] : T(0);
-            iv[c] = invd[2 * t.r + c];
-            xo[c] = x_old[2 * t.r + c];
+            xB[c] = xT[c];
+            xT[c] = xN[c];
         }
-    }
-    load_patch<T, T, T>(g, pt, x_old, t.i0, t.j0, P);
-    __syncthreads();
-    cell_contrib<T>(g, t.i0, t.j0, P);
-    __syncthreads();
-    if (!t.valid) return;
-    T y[2];
-    node_row<T, T>(g, t.i, t.j, t.r, t.tx, t.ty, P, x_old, y);
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const T res = bv[c] - y[c];
-        const T dn = (alpha != T(0) ? alpha * dv[c] : T(0)) + beta * iv[c] * res;
-        d[2 * t.r + c] = dn;
-        x_new[2 * t.r + c] = xo[c] + dn;
     }
 }
 
@@ -398,51 +397,105 @@ __global__ void __launch_bounds__(256) k_mf_cheb(MfGrid g, const T* __restrict__
 template <typename T>
 __global__ void __launch_bounds__(256) k_mf_residual(MfGrid g, const T* __restrict__ pt, const T* __restrict__ x,
                                                      const T* __restrict__ b, T* __restrict__ y) {
-    __shared__ Patch<T> P;
-    const TileNode t = tile_node(g);
-    T bv[2];
-    if (t.valid) {
-        bv[0] = b[2 * t.r];
-        bv[1] = b[2 * t.r + 1];
+    const WaveStrip w = wave_strip(g);
+    if (!w.valid) return;
+    auto ld = [&](int64_t j, T& p, T (&v)[2]) {
+        const bool in = w.col_in && row_in(g, j);
+        const int64_t r = w.col + j * g.n1;
+        p = in ? pt[r] : T(0);
+        v[0] = in ? x[2 * r] : T(0);
+        v[1] = in ? x[2 * r + 1] : T(0);
+    };
+    T pB, pT, xB[2], xT[2], c2[2] = {T(0), T(0)}, c3[2] = {T(0), T(0)};
+    ld(w.j0 - 1, pB, xB);
+    ld(w.j0, pT, xT);
+    for (int64_t j = w.j0 - 1; j < w.j1; ++j) {
+        T pN, xN[2];
+        ld(j + 2, pN, xN);
+        const bool wr = w.writer && j >= w.j0;
+        const int64_t r = w.col + j * g.n1;
+        T bv[2];
+        if (wr) {
+            bv[0] = b[2 * r];
+            bv[1] = b[2 * r + 1];
+        }
+        T acc[2], Hx[2][2], Hy[2][2];
+        masked_grad<T>(g, w, j, xB, xT, Hx, Hy);
+        u_rows<T>(g, w, j, Hx, Hy, pB, pT, c2, c3, acc);
+        if (wr) {
+            const bool dir = dirichlet(g, w.col, j);
+            y[2 * r] = bv[0] - (dir ? acc[0] * xB[0] : acc[0]);
+            y[2 * r + 1] = bv[1] - (dir ? acc[1] * xB[1] : acc[1]);
+        }
+        pB = pT;
+        pT = pN;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            xB[c] = xT[c];
+            xT[c] = xN[c];
+        }
     }
-    load_patch<T, T, T>(g, pt, x, t.i0, t.j0, P);
-    __syncthreads();
-    cell_contrib<T>(g, t.i0, t.j0, P);
-    __syncthreads();
-    if (!t.valid) return;
-    T acc[2];
-    node_row<T, T>(g, t.i, t.j, t.r, t.tx, t.ty, P, x, acc);
-    y[2 * t.r] = bv[0] - acc[0];
-    y[2 * t.r + 1] = bv[1] - acc[1];
 }
 
-// Chebyshev step of the fine phase-field level (M_phiphi, masked), as k_mf_cheb.
-template <typename T>
+// Chebyshev step of the fine phase-field level (M_phiphi, masked), as k_mf_cheb (POW: a power
+// step, d = D^-1 M_phiphi x_old).
+template <typename T, bool POW = false>
 __global__ void __launch_bounds__(256) k_mf_pcheb(MfGrid g, const T* __restrict__ us, const uint8_t* __restrict__ act,
                                                   const T* __restrict__ dpp, const T* __restrict__ invd,
                                                   const T* __restrict__ x_old, const T* __restrict__ b,
                                                   T* __restrict__ d, T* __restrict__ x_new, T alpha, T beta) {
-    __shared__ PPatch<T> F;
-    const TileNode t = tile_node(g);
-    T bv = T(0), dv = T(0), iv = T(0), xo = T(0);
-    bool on = false;
-    if (t.valid) {
-        bv = b[t.r];
-        dv = alpha != T(0) ? d[t.r] : T(0);
-        iv = invd[t.r];
-        xo = x_old[t.r];
-        on = act[t.r] != 0;
+    const WaveStrip w = wave_strip(g);
+    if (!w.valid) return;
+    // u_s, x (raw), and x masked at active nodes
+    auto ld = [&](int64_t j, T (&u)[2], T& x, T& xm) {
+        const bool in = w.col_in && row_in(g, j);
+        const int64_t r = w.col + j * g.n1;
+        u[0] = in ? us[2 * r] : T(0);
+        u[1] = in ? us[2 * r + 1] : T(0);
+        x = in ? x_old[r] : T(0);
+        xm = (in && act[r] == 0) ? x : T(0);
+    };
+    T uB[2], uT[2], xB, xT, mB, mT, c2 = T(0), c3 = T(0);
+    ld(w.j0 - 1, uB, xB, mB);
+    ld(w.j0, uT, xT, mT);
+    const T none[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
+    for (int64_t j = w.j0 - 1; j < w.j1; ++j) {
+        T uN[2], xN, mN;
+        ld(j + 2, uN, xN, mN);
+        const bool wr = w.writer && j >= w.j0;
+        const int64_t r = w.col + j * g.n1;
+        T bv = T(0), dv = T(0), iv = T(0), dg = T(0);
+        bool on = false;
+        if (wr) {
+            if (!POW) {
+                bv = b[r];
+                dv = alpha != T(0) ? d[r] : T(0);
+            }
+            iv = invd[r];
+            on = act[r] != 0;
+            if (on) dg = dpp[r];
+        }
+        const T y = phi_rows<T, false>(g, w, j, uB, uT, mB, mT, none, none, T(0), T(0), c2, c3);
+        if (wr) {
+            const T ay = on ? dg * xB : y;
+            if (POW) {
+                d[r] = iv * ay;
+            } else {
+                const T res = bv - ay;
+                const T dn = (alpha != T(0) ? alpha * dv : T(0)) + beta * iv * res;
+                d[r] = dn;
+                x_new[r] = xB + dn;
+            }
+        }
+        uB[0] = uT[0];
+        uB[1] = uT[1];
+        uT[0] = uN[0];
+        uT[1] = uN[1];
+        xB = xT;
+        xT = xN;
+        mB = mT;
+        mT = mN;
     }
-    load_ppatch<T, T, T>(g, us, act, x_old, t.i0, t.j0, F);
-    __syncthreads();
-    phi_cell<T, false>(g, t.i0, t.j0, F, nullptr, nullptr);
-    __syncthreads();
-    if (!t.valid) return;
-    const T y = on ? dpp[t.r] * xo : phi_row<T>(F, t.tx, t.ty);
-    const T res = bv - y;
-    const T dn = (alpha != T(0) ? alpha * dv : T(0)) + beta * iv * res;
-    d[t.r] = dn;
-    x_new[t.r] = xo + dn;
 }
 
 // y = b - M_phiphi x on the fine phase-field level
@@ -451,120 +504,135 @@ __global__ void __launch_bounds__(256) k_mf_presidual(MfGrid g, const T* __restr
                                                       const uint8_t* __restrict__ act, const T* __restrict__ dpp,
                                                       const T* __restrict__ x, const T* __restrict__ b,
                                                       T* __restrict__ y) {
-    __shared__ PPatch<T> F;
-    const TileNode t = tile_node(g);
-    T bv = T(0), xo = T(0);
-    bool on = false;
-    if (t.valid) {
-        bv = b[t.r];
-        xo = x[t.r];
-        on = act[t.r] != 0;
-    }
-    load_ppatch<T, T, T>(g, us, act, x, t.i0, t.j0, F);
-    __syncthreads();
-    phi_cell<T, false>(g, t.i0, t.j0, F, nullptr, nullptr);
-    __syncthreads();
-    if (!t.valid) return;
-    y[t.r] = bv - (on ? dpp[t.r] * xo : phi_row<T>(F, t.tx, t.ty));
-}
-
-// y = J x with every row matrix-free: the displacement rows as in k_jspmv_mf, the phase-field
-// rows M_phiu x_u + M_phiphi x_phi from u_s, phi_s and the active set (FP64 arithmetic, x FP64
-// or FP32 widened exactly); xcopy (optional) receives the row's own entries of x at *jp.
-template <typename TX>
-__global__ void __launch_bounds__(256) k_jspmv_mf_all(MfGrid g, const double* __restrict__ pt,
-                                                      const double* __restrict__ us, const double* __restrict__ ps,
-                                                      const uint8_t* __restrict__ act, const double* __restrict__ dpp,
-                                                      const TX* __restrict__ x, double* __restrict__ y,
-                                                      TX* __restrict__ xcopy, const int* __restrict__ jp,
-                                                      int64_t xstride) {
-    __shared__ Patch<double> P;
-    __shared__ PPatch<double> F;
-    __shared__ double S[kPY][kPX];
-    const TileNode t = tile_node(g);
-    const int64_t nf = g.n_nodes;
-    const TX* xp = x + 2 * nf;
-    for (int k = threadIdx.x; k < kPX * kPY; k += blockDim.x) {
-        const int px = k % kPX, py = k / kPX;
-        const int64_t bi = t.i0 - 1 + px, bj = t.j0 - 1 + py;
-        const bool in = bi >= 0 && bj >= 0 && bi <= g.nx && bj <= g.ny;
-        const bool interior = bi > 0 && bj > 0 && bi < g.nx && bj < g.ny;
-        const int64_t nb = bi + bj * g.n1;
-        P.p[py][px] = in ? pt[nb] : 0.0;
-        P.x[0][py][px] = interior ? double(x[2 * nb]) : 0.0;
-        P.x[1][py][px] = interior ? double(x[2 * nb + 1]) : 0.0;
-        F.u[0][py][px] = in ? us[2 * nb] : 0.0;
-        F.u[1][py][px] = in ? us[2 * nb + 1] : 0.0;
-        F.x[py][px] = (in && act[nb] == 0) ? double(xp[nb]) : 0.0;
-        S[py][px] = in ? ps[nb] : 0.0;
-    }
-    __syncthreads();
-    cell_contrib<double>(g, t.i0, t.j0, P);
-    phi_cell<double, true>(g, t.i0, t.j0, F, P.x, S);
-    __syncthreads();
-    if (!t.valid) return;
-    const int64_t r = t.r;
-    double yu[2];
-    node_row<double, TX>(g, t.i, t.j, r, t.tx, t.ty, P, x, yu);
-    y[2 * r] = yu[0];
-    y[2 * r + 1] = yu[1];
-    y[2 * nf + r] = act[r] != 0 ? dpp[r] * double(xp[r]) : phi_row<double>(F, t.tx, t.ty);
-    if (xcopy) {
-        TX* xc = jp ? xcopy + int64_t(*jp) * xstride : xcopy;
-        xc[2 * r] = x[2 * r];
-        xc[2 * r + 1] = x[2 * r + 1];
-        xc[2 * nf + r] = xp[r];
-    }
-}
-
-// y = J x over the coupled system with the displacement rows matrix-free (FP64 arithmetic; x
-// FP64 or FP32 widened exactly) and the phase-field rows M_phiu x_u + M_phiphi x_phi from the
-// stored blocks; xcopy (optional) receives the row's own entries of x at the Krylov slot *jp.
-template <typename TX, typename CI>
-__global__ void __launch_bounds__(256) k_jspmv_mf(MfGrid g, const double* __restrict__ pt, int C,
-                                                  const int32_t* __restrict__ slice_ptr, const CI* __restrict__ col,
-                                                  const double* __restrict__ pu, const double* __restrict__ pp,
-                                                  const TX* __restrict__ x, double* __restrict__ y,
-                                                  TX* __restrict__ xcopy, const int* __restrict__ jp,
-                                                  int64_t xstride) {
-    __shared__ Patch<double> P;
-    const TileNode t = tile_node(g);
-    const int64_t nf = g.n_nodes;
-    const TX* xp = x + 2 * nf;
-    double ap = 0.0;
-    if (t.valid) {
-        const int64_t r = t.r;
-        const int64_t s = r / C;
-        const int lane = int(r - s * C);
-        const int32_t p0 = slice_ptr[s];
-        const int w = (slice_ptr[s + 1] - p0) / C;
-        int64_t slot = int64_t(p0) + lane;
-        for (int k = 0; k < w; ++k, slot += C) {
-            const int64_t c = sizeof(CI) == 2 ? r + int64_t(col[slot]) : int64_t(col[slot]);
-            const double xu0 = double(x[2 * c]), xu1 = double(x[2 * c + 1]);
-            const double xph = double(xp[c]);
-            const double* vp = pu + slot * 2;
-            ap += vp[0] * xu0;
-            ap += vp[1] * xu1;
-            ap += pp[slot] * xph;
+    const WaveStrip w = wave_strip(g);
+    if (!w.valid) return;
+    auto ld = [&](int64_t j, T (&u)[2], T& v, T& vm) {
+        const bool in = w.col_in && row_in(g, j);
+        const int64_t r = w.col + j * g.n1;
+        u[0] = in ? us[2 * r] : T(0);
+        u[1] = in ? us[2 * r + 1] : T(0);
+        v = in ? x[r] : T(0);
+        vm = (in && act[r] == 0) ? v : T(0);
+    };
+    T uB[2], uT[2], xB, xT, mB, mT, c2 = T(0), c3 = T(0);
+    ld(w.j0 - 1, uB, xB, mB);
+    ld(w.j0, uT, xT, mT);
+    const T none[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
+    for (int64_t j = w.j0 - 1; j < w.j1; ++j) {
+        T uN[2], xN, mN;
+        ld(j + 2, uN, xN, mN);
+        const bool wr = w.writer && j >= w.j0;
+        const int64_t r = w.col + j * g.n1;
+        T bv = T(0), dg = T(0);
+        bool on = false;
+        if (wr) {
+            bv = b[r];
+            on = act[r] != 0;
+            if (on) dg = dpp[r];
         }
+        const T acc = phi_rows<T, false>(g, w, j, uB, uT, mB, mT, none, none, T(0), T(0), c2, c3);
+        if (wr) y[r] = bv - (on ? dg * xB : acc);
+        uB[0] = uT[0];
+        uB[1] = uT[1];
+        uT[0] = uN[0];
+        uT[1] = uN[1];
+        xB = xT;
+        xT = xN;
+        mB = mT;
+        mT = mN;
     }
-    load_patch<double, TX, double>(g, pt, x, t.i0, t.j0, P);
-    __syncthreads();
-    cell_contrib<double>(g, t.i0, t.j0, P);
-    __syncthreads();
-    if (!t.valid) return;
-    const int64_t r = t.r;
-    double yu[2];
-    node_row<double, TX>(g, t.i, t.j, r, t.tx, t.ty, P, x, yu);
-    y[2 * r] = yu[0];
-    y[2 * r + 1] = yu[1];
-    y[2 * nf + r] = ap;
-    if (xcopy) {
-        TX* xc = jp ? xcopy + int64_t(*jp) * xstride : xcopy;
-        xc[2 * r] = x[2 * r];
-        xc[2 * r + 1] = x[2 * r + 1];
-        xc[2 * nf + r] = xp[r];
+}
+
+// y = J x over the coupled system, by rows (FP64 arithmetic; x FP64 or FP32 widened exactly).
+// PART 0: the displacement rows matrix-free and the phase-field rows from the stored blocks (SELL
+// slots of the node graph); 1: the displacement rows matrix-free; 2: the phase-field rows
+// M_phiu x_u + M_phiphi x_phi matrix-free (from u_s, phi_s and the active set).  Parts 1 and 2
+// together make the whole product in two launches, each with half the live registers of one.
+// xcopy (optional) receives the written rows' own entries of x at the Krylov slot *jp.
+template <typename TX, int PART, typename CI>
+__global__ void __launch_bounds__(256) k_jspmv_mf(MfGrid g, const double* __restrict__ pt,
+                                                  const double* __restrict__ us, const double* __restrict__ ps,
+                                                  const uint8_t* __restrict__ act, const double* __restrict__ dpp,
+                                                  int C, const int32_t* __restrict__ slice_ptr,
+                                                  const CI* __restrict__ col, const double* __restrict__ pu,
+                                                  const double* __restrict__ pp, const TX* __restrict__ x,
+                                                  double* __restrict__ y, TX* __restrict__ xcopy,
+                                                  const int* __restrict__ jp, int64_t xstride) {
+    constexpr bool U = PART != 2, PH = PART == 2;
+    const WaveStrip w = wave_strip(g);
+    if (!w.valid) return;
+    const int64_t nf = g.n_nodes;
+    const TX* xp = x + 2 * nf;
+    struct Row {
+        double p, x[2], xm, u[2], s;             // phi_tilde, x_u (raw), x_phi (masked), u_s, phi_s
+    };
+    auto ld = [&](int64_t j, Row& v) {
+        const bool in = w.col_in && row_in(g, j);
+        const int64_t r = w.col + j * g.n1;
+        v.x[0] = in ? double(x[2 * r]) : 0.0;
+        v.x[1] = in ? double(x[2 * r + 1]) : 0.0;
+        if constexpr (U) v.p = in ? pt[r] : 0.0;
+        if constexpr (PH) {
+            v.xm = (in && act[r] == 0) ? double(xp[r]) : 0.0;
+            v.u[0] = in ? us[2 * r] : 0.0;
+            v.u[1] = in ? us[2 * r + 1] : 0.0;
+            v.s = in ? ps[r] : 0.0;
+        }
+    };
+    Row B, T;
+    ld(w.j0 - 1, B);
+    ld(w.j0, T);
+    double c2[2] = {0.0, 0.0}, c3[2] = {0.0, 0.0};
+    for (int64_t j = w.j0 - 1; j < w.j1; ++j) {
+        Row N;
+        ld(j + 2, N);
+        const bool wr = w.writer && j >= w.j0;
+        const int64_t r = w.col + j * g.n1;
+        TX xo = TX(0);
+        if (wr && PH) xo = xp[r];
+        double Hx[2][2], Hy[2][2];
+        masked_grad<double>(g, w, j, B.x, T.x, Hx, Hy);
+        if constexpr (U) {
+            double yu[2];
+            u_rows<double>(g, w, j, Hx, Hy, B.p, T.p, c2, c3, yu);
+            if (wr) {
+                const bool dir = dirichlet(g, w.col, j);
+                y[2 * r] = dir ? yu[0] * B.x[0] : yu[0];
+                y[2 * r + 1] = dir ? yu[1] * B.x[1] : yu[1];
+                if (xcopy) {
+                    TX* xc = jp ? xcopy + int64_t(*jp) * xstride : xcopy;
+                    xc[2 * r] = x[2 * r];
+                    xc[2 * r + 1] = x[2 * r + 1];
+                }
+            }
+        }
+        if constexpr (PART == 0) {
+            if (wr) {
+                const int64_t sl = r / C;
+                const int lane = int(r - sl * C);
+                const int32_t p0 = slice_ptr[sl];
+                const int wd = (slice_ptr[sl + 1] - p0) / C;
+                int64_t slot = int64_t(p0) + lane;
+                double ap = 0.0;
+                for (int k = 0; k < wd; ++k, slot += C) {
+                    const int64_t c = sizeof(CI) == 2 ? r + int64_t(col[slot]) : int64_t(col[slot]);
+                    ap += pu[slot * 2] * double(x[2 * c]);
+                    ap += pu[slot * 2 + 1] * double(x[2 * c + 1]);
+                    ap += pp[slot] * double(xp[c]);
+                }
+                y[2 * nf + r] = ap;
+                if (xcopy) (jp ? xcopy + int64_t(*jp) * xstride : xcopy)[2 * nf + r] = xp[r];
+            }
+        }
+        if constexpr (PH) {
+            const double yp = phi_rows<double, true>(g, w, j, B.u, T.u, B.xm, T.xm, Hx, Hy, B.s, T.s, c2[0], c3[0]);
+            if (wr) {
+                y[2 * nf + r] = act[r] != 0 ? dpp[r] * double(xo) : yp;
+                if (xcopy) (jp ? xcopy + int64_t(*jp) * xstride : xcopy)[2 * nf + r] = xo;
+            }
+        }
+        B = T;
+        T = N;
     }
 }
 
@@ -598,7 +666,9 @@ __global__ void k_diag_pp(int64_t n, int C, const int32_t* __restrict__ sp, cons
 
 int grid_for(int64_t n) { return int((n + 255) / 256); }
 
-dim3 tiles(const MfGrid& g) { return dim3(unsigned((g.n1 + kTX - 1) / kTX), unsigned((g.ny + 1 + kTY - 1) / kTY)); }
+// workgroups of four waves over the strips x bands of the mesh
+int64_t strip_waves(const MfGrid& g) { return ((g.n1 + kSW - 1) / kSW) * ((g.ny + kBand) / kBand); }
+dim3 tiles(const MfGrid& g) { return dim3(unsigned((strip_waves(g) + 3) / 4)); }
 
 }  // namespace
 
@@ -623,7 +693,7 @@ void mf_prepare(DevSystem& sys, const double* u, const double* phi, const double
     g.Gc = sys.prm.Gc;
     g.eps = sys.prm.eps;
     if (g.n1 * (g.ny + 1) != m.n_nodes || m.n_free != m.n_nodes) return;
-    if ((g.n1 + kTX - 1) / kTX > 65535 || (g.ny + kTY) / kTY > 65535) return;   // tile grid limits
+    if ((strip_waves(g) + 3) / 4 >= (int64_t(1) << 31)) return;   // grid limit
     const int64_t n = m.n_nodes;
     MfState& f = sys.mf;
     f.pt.reserve(size_t(n), s);
@@ -690,6 +760,16 @@ void mf_cheb_step(const MfState& mf, int blk, const T* invd, const T* x_old, con
     FR_LAUNCH_CHECK();
 }
 
+void mf_power_step(const MfState& mf, int blk, const double* invd, const double* x, double* y, hipStream_t s) {
+    const MfGrid& g = mf.grid;
+    if (blk == 0)
+        k_mf_cheb<double, true><<<tiles(g), 256, 0, s>>>(g, mf.pt.p, invd, x, nullptr, y, nullptr, 0.0, 0.0);
+    else
+        k_mf_pcheb<double, true><<<tiles(g), 256, 0, s>>>(g, mf.us.p, mf.act.p, mf.dpp.p, invd, x, nullptr, y,
+                                                          nullptr, 0.0, 0.0);
+    FR_LAUNCH_CHECK();
+}
+
 template <typename T>
 void mf_residual(const MfState& mf, int blk, const T* x, const T* b, T* y, hipStream_t s) {
     const MfGrid& g = mf.grid;
@@ -713,26 +793,37 @@ void mf_jspmv(const DevSystem& sys, bool phi_rows, const TX* x, double* y, TX* x
     const dim3 gr = tiles(mf.grid);
     const bool x64 = sizeof(TX) == 8;
     const double nn = double(mf.grid.n_nodes);
+    const SellStruct& S = *sys.Juu.S;
     if (phi_rows) {
-        // phi_tilde, u_s, phi_s, the active flag and x read, y (and the copy of x) written
-        const double bytes = nn * (8 + 16 + 8 + 1 + 3 * sizeof(TX) + 24) + (xcopy ? nn * 3 * sizeof(TX) : 0.0);
-        ProfScope ps(x64 ? "jspmv_mf_all_d2" : "jspmv_mf_all_d2_x32", s, bytes);
-        k_jspmv_mf_all<TX><<<gr, 256, 0, s>>>(mf.grid, mf.pt.p, mf.us.p, mf.ps.p, mf.act.p, mf.dpp.p, x, y, xcopy, jp,
-                                               xstride);
+        // displacement rows: phi_tilde, x_u read, y_u (and the copy of x_u) written; phase-field
+        // rows: u_s, phi_s, the active flag, x_u, x_phi read, y_phi (and the copy) written
+        const double bu = nn * (8 + 2 * sizeof(TX) + 16) + (xcopy ? nn * 2 * sizeof(TX) : 0.0);
+        const double bp = nn * (16 + 8 + 1 + 3 * sizeof(TX) + 8) + (xcopy ? nn * sizeof(TX) : 0.0);
+        {
+            ProfScope ps(x64 ? "jspmv_mf_u_d2" : "jspmv_mf_u_d2_x32", s, bu);
+            k_jspmv_mf<TX, 1, int32_t><<<gr, 256, 0, s>>>(mf.grid, mf.pt.p, nullptr, nullptr, nullptr, nullptr, S.C,
+                                                          S.slice_ptr, S.col, nullptr, nullptr, x, y, xcopy, jp,
+                                                          xstride);
+            FR_LAUNCH_CHECK();
+        }
+        ProfScope ps(x64 ? "jspmv_mf_phi_d2" : "jspmv_mf_phi_d2_x32", s, bp);
+        k_jspmv_mf<TX, 2, int32_t><<<gr, 256, 0, s>>>(mf.grid, nullptr, mf.us.p, mf.ps.p, mf.act.p, mf.dpp.p, S.C,
+                                                      S.slice_ptr, S.col, nullptr, nullptr, x, y, xcopy, jp, xstride);
         FR_LAUNCH_CHECK();
         return;
     }
-    const SellStruct& S = *sys.Juu.S;
     const double ib = S.col16 ? 2.0 : 4.0;
     const double bytes = double(S.nnz) * (3 * 8 + ib) + double(S.n_rows) * (3 * (sizeof(TX) + 8) + 8) +
                          (xcopy ? double(S.n_rows) * 3 * sizeof(TX) : 0.0);
     ProfScope ps(x64 ? "jspmv_mf_d2" : "jspmv_mf_d2_x32", s, bytes);
     if (S.col16)
-        k_jspmv_mf<TX, int16_t><<<gr, 256, 0, s>>>(mf.grid, mf.pt.p, S.C, S.slice_ptr, S.col16, sys.Jpu.val,
-                                                   sys.Jpp.val, x, y, xcopy, jp, xstride);
+        k_jspmv_mf<TX, 0, int16_t><<<gr, 256, 0, s>>>(mf.grid, mf.pt.p, nullptr, nullptr, nullptr, nullptr, S.C,
+                                                          S.slice_ptr, S.col16, sys.Jpu.val, sys.Jpp.val, x, y, xcopy,
+                                                          jp, xstride);
     else
-        k_jspmv_mf<TX, int32_t><<<gr, 256, 0, s>>>(mf.grid, mf.pt.p, S.C, S.slice_ptr, S.col, sys.Jpu.val,
-                                                   sys.Jpp.val, x, y, xcopy, jp, xstride);
+        k_jspmv_mf<TX, 0, int32_t><<<gr, 256, 0, s>>>(mf.grid, mf.pt.p, nullptr, nullptr, nullptr, nullptr, S.C,
+                                                          S.slice_ptr, S.col, sys.Jpu.val, sys.Jpp.val, x, y, xcopy,
+                                                          jp, xstride);
     FR_LAUNCH_CHECK();
 }
 

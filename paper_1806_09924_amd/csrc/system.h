@@ -146,6 +146,8 @@ void mf_cheb_step(const MfState& mf, int blk, const T* invd, const T* x_old, con
                   T beta, hipStream_t s);
 template <typename T>
 void mf_residual(const MfState& mf, int blk, const T* x, const T* b, T* y, hipStream_t s);
+// y = D^-1 A x with the block's fine operator matrix-free (a power step of the smoother bounds)
+void mf_power_step(const MfState& mf, int blk, const double* invd, const double* x, double* y, hipStream_t s);
 // y = J x with the displacement rows matrix-free, and the phase-field rows too when `phi_rows`
 // (x FP64 or FP32), xcopy as for jspmv_copy
 template <typename TX>
