@@ -287,6 +287,9 @@ def main():
             "speedup_whole_step": (wall / args.steps) / (w32 / args.steps),
             "speedup_time_to_solution": t_solve / ts32,
             "vcycle_ms": {k: v["ms"] for k, v in p32.items() if k.startswith("vcycle")},
+            "kernels": {k: {"launches": v["launches"], "ms_total": v["ms"],
+                            "gbs": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 and v["bytes"] > 0 else None}
+                        for k, v in sorted(p32.items(), key=lambda kv: -kv[1]["ms"]) if not k.startswith("setup_")},
         }
         if prof:
             out["fp32_amg"]["vcycle_ms_fp64"] = {k: v["ms"] for k, v in prof.items() if k.startswith("vcycle")}

@@ -819,7 +819,7 @@ std::pair<int, int> time_shapes(const BMat<double>& M, int op, hipStream_t s) {
     hipEvent_t e0, e1;
     FR_HIP(hipEventCreate(&e0));
     FR_HIP(hipEventCreate(&e1));
-    const std::pair<int, int> cands[] = {{S.C, 1}, {S.C, 4}, {S.C, 16}, {1, 4}, {1, 16}, {1, 64}};
+    const std::pair<int, int> cands[] = {{S.C, 1}, {S.C, 4}, {S.C, 16}, {1, 1}, {1, 4}, {1, 16}, {1, 64}};
     const int G0 = lanes_per_row(S);
     double best = 1e30, base = 1e30;
     std::pair<int, int> pick{S.C, G0};
@@ -870,15 +870,15 @@ int tune_entries() {
 
 // op 0: Chebyshev step (smoother of A), 1: y = M x (restriction), 2: y += M x (prolongation),
 // timed in the precision the V-cycle runs in (f32).  Candidates: slice height 64 with 1, 4,
-// 16 lanes per row and contiguous rows (C = 1) with 4, 16, 64 lanes.  Each is timed (one
+// 16 lanes per row and contiguous rows (C = 1) with 1, 4, 16, 64 lanes.  Each is timed (one
 // warm-up, best of five) on the matrix itself; the heuristic shape is kept unless another
 // is at least 5 % faster.  Choices are cached per process by (op, block shape, log2 rows,
 // mean row length, precision), so later setups of similar levels reuse them without timing.
-// Matrices with more than 2^20 rows keep one lane per row in the given layout (their rows
-// fill the chip either way).
+// Large operators are tuned too: the finest prolongator's rows (1 to ~5 blocks) pad a slice
+// of 64 to its longest row, which contiguous rows avoid.
 void tune_layout(BMat<double>& M, int op, bool f32, hipStream_t s) {
     SellStruct& S = *M.S;
-    if (S.n_rows == 0 || S.n_rows > (int64_t(1) << 20)) return;
+    if (S.n_rows == 0) return;
     const int64_t avg = S.nnz / S.n_rows;
     int lg = 0;
     while ((int64_t(1) << (lg + 1)) <= S.n_rows) ++lg;
