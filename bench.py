@@ -44,7 +44,7 @@ def log(msg):
 
 
 PROFILE_OF = {"cheb_f64_b2": "cheb_f64_b2_sneddon2d_2048.md", "cheb_f64_b2_i16": "cheb_f64_b2_sneddon2d_2048.md",
-              "mf_cheb_f64": "mf_cheb_f64_sneddon2d_2048.md"}
+              "mf_cheb_f64": "mf_cheb_f64_sneddon2d_2048.md", "mf_pcheb_f64": "mf_pcheb_f64_sneddon2d_2048.md"}
 
 
 def kernel_digest(src_text, kernel):
