@@ -256,7 +256,7 @@ def main():
         # iteration and over the V-cycle window (the two cycles run on two streams at once: the
         # longer of the two per-cycle times)
         p_iters = sum(s_["linear_iters"] for s_ in pstats)
-        vc_names = [k for k in kern if k.startswith(("cheb_", "spmv_"))]
+        vc_names = [k for k in kern if k.startswith(("cheb_", "spmv_", "mf_"))]
         vc_bytes = sum(kern[k]["bytes"] for k in vc_names) / p_iters
         it_bytes = sum(v["bytes"] for v in kern.values()) / p_iters
         vc_ms = max(prof[k]["ms"] / prof[k]["launches"] for k in ("vcycle_u", "vcycle_phi") if k in prof)

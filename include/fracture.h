@@ -112,8 +112,12 @@ typedef struct {
                             finest phase-field level's smoother and residual apply the masked
                             M_phiphi from the assembly's u and active set, and (with bit 0) the
                             phase-field rows of the J-SpMV apply M_phiu and M_phiphi from its u,
-                            phi and active set.  The same masked operators as the stored blocks,
-                            summed in another order: equal up to rounding.  Default 3. */
+                            phi and active set.  Bit 2 (4, with bit 0): the finest displacement
+                            level's prolongation and restriction apply P = (I - omega D^-1 M_uu) P_t
+                            and P^T = P_t^T (I - omega M_uu D^-1) from the aggregation (per node its
+                            aggregate, per aggregate the tentative prolongator's R^-1 and centroid)
+                            instead of the stored P and R.  The same operators as the stored
+                            blocks, summed in another order: equal up to rounding.  Default 7. */
 } fr_amg_opts;
 
 /* FGMRES options (right preconditioned, x0 = 0). */

@@ -252,7 +252,7 @@ template <int BR, int NS, bool LEVEL0>
 __global__ void k_tentative(int64_t na, const int32_t* __restrict__ aptr, const int32_t* __restrict__ anodes,
                             const double* __restrict__ coords, int dim, const double* __restrict__ Bf,
                             int C, const int32_t* __restrict__ psp, double* __restrict__ pval,
-                            double* __restrict__ Bc) {
+                            double* __restrict__ Bc, double* __restrict__ ainfo) {
     const int64_t a = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (a >= na) return;
     const int32_t b0 = aptr[a], b1 = aptr[a + 1];
@@ -357,6 +357,17 @@ __global__ void k_tentative(int64_t na, const int32_t* __restrict__ aptr, const 
                 for (int k = 0; k < NS; ++k) s += v[k] * Ri[k][j];
                 q[c * NS + j] = s;
             }
+        }
+    }
+    // the aggregate's factors of the tentative rows (R^-1 and the centroid), for the matrix-free
+    // transfers of the finest 2d displacement level
+    if constexpr (LEVEL0 && NS == 3) {
+        if (ainfo) {
+            double* o = ainfo + a * kAggInfo;
+            for (int i = 0; i < NS; ++i)
+                for (int j = 0; j < NS; ++j) o[i * NS + j] = Ri[i][j];
+            o[9] = xc[0];
+            o[10] = xc[1];
         }
     }
     // coarse near-null space: R T (T maps centred to global rotations at level 0)
@@ -1527,7 +1538,8 @@ static int64_t aggregate(const BMat<double>& A, const double* dnorm, double thet
 
 // Tentative prolongator (one block per aggregated row) and the coarse near-null space.
 static BMat<double> tentative(const BMat<double>& A, const DBuf<int32_t>& agg, int64_t n_agg, int ns, bool level0,
-                              const double* coords, int dim, const double* Bf, DBuf<double>& Bc, hipStream_t s) {
+                              const double* coords, int dim, const double* Bf, DBuf<double>& Bc, hipStream_t s,
+                              AggTransfer* keep = nullptr) {
     const int64_t n = A.rows();
     const int br = A.br;
     BMat<double> P;
@@ -1557,28 +1569,38 @@ static BMat<double> tentative(const BMat<double>& A, const DBuf<int32_t>& agg, i
     k_agg_sort<<<nblk(n_agg, 256), 256, 0, s>>>(n_agg, ptr.p, nodes.p);
     FR_LAUNCH_CHECK();
     Bc.alloc(size_t(std::max<int64_t>(1, n_agg)) * ns * ns, s);
+    double* ainfo = nullptr;
+    if (keep) {
+        keep->n_agg = n_agg;
+        keep->info.alloc(size_t(std::max<int64_t>(1, n_agg)) * kAggInfo, s);
+        ainfo = keep->info.p;
+    }
     const int g = nblk(n_agg, 64);
     const int C = P.S->C;
     // level 0 builds the near-null space from coordinates; coarser levels read the R
     // factors of the level above, which must exist
     if (!level0 && Bf == nullptr) fail(FR_EINTERNAL, "tentative: coarse level without a near-null space");
     if (level0 && br == 2 && ns == 3)
-        k_tentative<2, 3, true><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p);
+        k_tentative<2, 3, true><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p, ainfo);
     else if (level0 && br == 3 && ns == 6)
-        k_tentative<3, 6, true><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p);
+        k_tentative<3, 6, true><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p, ainfo);
     else if (level0 && br == 1 && ns == 1)
-        k_tentative<1, 1, true><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p);
+        k_tentative<1, 1, true><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p, ainfo);
     else if (level0)
         fail(FR_EINTERNAL, "tentative: unsupported level-0 block shape");
     else if (br == 1 && ns == 1)
-        k_tentative<1, 1, false><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p);
+        k_tentative<1, 1, false><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p, ainfo);
     else if (br == 3 && ns == 3)
-        k_tentative<3, 3, false><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p);
+        k_tentative<3, 3, false><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p, ainfo);
     else if (br == 6 && ns == 6)
-        k_tentative<6, 6, false><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p);
+        k_tentative<6, 6, false><<<g, 64, 0, s>>>(n_agg, ptr.p, nodes.p, coords, dim, Bf, C, P.S->slice_ptr, P.val, Bc.p, ainfo);
     else
         fail(FR_EINTERNAL, "tentative: unsupported block shape");
     FR_LAUNCH_CHECK();
+    if (keep) {
+        keep->aptr = std::move(ptr);
+        keep->anodes = std::move(nodes);
+    }
     return P;
 }
 
@@ -1702,11 +1724,26 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
             }
             DBuf<double> Bc;
             BMat<double> Pt, AP, Ac;
+            // the finest displacement level of a uniform 2d mesh keeps its aggregation for the
+            // matrix-free transfers
+            const bool mt = l == 0 && mf0 && blk == 0 && dim == 2 && ns == 3 && (o.fine_matrix_free & 4);
+            if (mt) L->mt = std::make_unique<AggTransfer>();
             {
                 ProfScope ps(nm_tent.c_str(), s, 0.0);
-                Pt = tentative(L->A, agg, n_agg, ns, l == 0, coords, dim, Bf.p, Bc, s);
+                Pt = tentative(L->A, agg, n_agg, ns, l == 0, coords, dim, Bf.p, Bc, s, L->mt.get());
             }
             L->lmax = power_finish(pe);
+            if (mt) {
+                L->mt->agg = std::move(agg);
+                L->mt->omega = 4.0 / (3.0 * L->lmax);
+                L->mt->w.alloc(size_t(std::max<int64_t>(1, n_agg)) * 3, s);
+                if (o.precision == 32) {
+                    const int64_t ni = n_agg * kAggInfo;
+                    L->mt->info32.alloc(size_t(std::max<int64_t>(1, ni)), s);
+                    cast_f64_f32(L->mt->info.p, L->mt->info32.p, ni, s);
+                    L->mt->w32.alloc(size_t(std::max<int64_t>(1, n_agg)) * 3, s);
+                }
+            }
             {
                 ProfScope ps(nm_smooth.c_str(), s, 0.0);
                 const double omega = 4.0 / (3.0 * L->lmax);
@@ -1968,9 +2005,14 @@ static T* vcycle(Hierarchy& H, size_t l, const T* b, const fr_amg_opts& o, hipSt
     if (mf) mf_residual<T>(*mf, H.blk, x, b, O::r(L), s);
     else spmv_residual<T>(O::A(L), x, b, O::r(L), s);
     AmgLevel& Ln = *H.lv[l + 1];
-    spmv<T>(O::R(L), O::r(L), O::b(Ln), s);
+    // the finest displacement level's transfers matrix-free where its aggregation was kept (the
+    // smoother's d is free between the two smoothings: the restriction's scratch)
+    const AggTransfer* mt = (mf && L.mt) ? L.mt.get() : nullptr;
+    if (mt) mf_restrict<T>(*mf, *mt, O::invd(L), O::r(L), O::d(L), O::b(Ln), s);
+    else spmv<T>(O::R(L), O::r(L), O::b(Ln), s);
     T* xc = vcycle<T>(H, l + 1, O::b(Ln), o, s);
-    spmv_add<T>(O::P(L), xc, x, s);
+    if (mt) mf_prolong<T>(*mf, *mt, O::invd(L), xc, x, s);
+    else spmv_add<T>(O::P(L), xc, x, s);
     return chebyshev<T>(L, L, b, false, x, other, o.cheb_degree, o.cheb_ratio, s, out, mf, H.blk);
 }
 

@@ -636,6 +636,170 @@ __global__ void __launch_bounds__(256) k_jspmv_mf(MfGrid g, const double* __rest
     }
 }
 
+// ---- matrix-free transfers of the finest displacement level ------------------------------------
+// P = (I - omega D^-1 M_uu) P_t with P_t's row of node i, aggregate a: B_i R_a^-1, B_i = [[1, 0,
+// -(y_i - yc_a)], [0, 1, x_i - xc_a]] (the rigid-body modes about the aggregate's centroid).  So
+// P_t x_c at node i is B_i w_a with w_a = R_a^-1 x_c,a, and P^T r = P_t^T (r - omega M_uu D^-1 r)
+// (M_uu symmetric) sums B_i^T s_i over the aggregate's nodes and multiplies by R_a^-T.  The node
+// coordinates are the mesh's (x0 + i h, y0 + j h).
+
+// w_a = R_a^-1 x_c,a
+template <typename T>
+__global__ void k_agg_w(int64_t na, const T* __restrict__ info, const T* __restrict__ xc, T* __restrict__ w) {
+    const int64_t a = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (a >= na) return;
+    const T* R = info + a * kAggInfo;
+    const T x0 = xc[3 * a], x1 = xc[3 * a + 1], x2 = xc[3 * a + 2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w[3 * a + k] = (R[3 * k] * x0 + R[3 * k + 1] * x1) + R[3 * k + 2] * x2;
+}
+
+// P_t x_c at node (i, j) of aggregate a (negative: none): B_i w_a
+template <typename T>
+__device__ __forceinline__ void tent_value(const MfGrid& g, int32_t a, const T* __restrict__ info,
+                                           const T* __restrict__ w, int64_t i, int64_t j, T (&z)[2]) {
+    if (a < 0) {
+        z[0] = z[1] = T(0);
+        return;
+    }
+    const T dx = T(g.x0 + double(i) * g.h) - info[int64_t(a) * kAggInfo + 9];
+    const T dy = T(g.y0 + double(j) * g.h) - info[int64_t(a) * kAggInfo + 10];
+    const T w2 = w[3 * int64_t(a) + 2];
+    z[0] = w[3 * int64_t(a)] - dy * w2;
+    z[1] = w[3 * int64_t(a) + 1] + dx * w2;
+}
+
+// x += z - omega D^-1 M_uu z with z = P_t x_c (computed per node from the aggregate's w)
+template <typename T>
+__global__ void __launch_bounds__(256) k_mf_prolong(MfGrid g, const T* __restrict__ pt, const T* __restrict__ invd,
+                                                    const int32_t* __restrict__ agg, const T* __restrict__ info,
+                                                    const T* __restrict__ w, T omega, T* __restrict__ x) {
+    const WaveStrip ws = wave_strip(g);
+    if (!ws.valid) return;
+    // two-stage row loads: a row's aggregate indices one step ahead of its gathers
+    auto ld_agg = [&](int64_t j) -> int32_t {
+        return (ws.col_in && row_in(g, j)) ? agg[ws.col + j * g.n1] : -1;
+    };
+    auto ld = [&](int64_t j, int32_t a, T& p, T (&z)[2]) {
+        const bool in = ws.col_in && row_in(g, j);
+        p = in ? pt[ws.col + j * g.n1] : T(0);
+        tent_value<T>(g, in ? a : -1, info, w, ws.col, j, z);
+    };
+    T pB, pT, zB[2], zT[2], c2[2] = {T(0), T(0)}, c3[2] = {T(0), T(0)};
+    ld(ws.j0 - 1, ld_agg(ws.j0 - 1), pB, zB);
+    ld(ws.j0, ld_agg(ws.j0), pT, zT);
+    int32_t aN = ld_agg(ws.j0 + 1);
+    for (int64_t j = ws.j0 - 1; j < ws.j1; ++j) {
+        const int32_t aNN = ld_agg(j + 3);
+        T pN, zN[2];
+        ld(j + 2, aN, pN, zN);
+        aN = aNN;
+        const bool wr = ws.writer && j >= ws.j0;
+        const int64_t r = ws.col + j * g.n1;
+        T xo[2] = {T(0), T(0)}, iv[2] = {T(0), T(0)};
+        if (wr) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                xo[c] = x[2 * r + c];
+                iv[c] = invd[2 * r + c];
+            }
+        }
+        T y[2], Hx[2][2], Hy[2][2];
+        masked_grad<T>(g, ws, j, zB, zT, Hx, Hy);
+        u_rows<T>(g, ws, j, Hx, Hy, pB, pT, c2, c3, y);
+        if (wr) {
+            const bool dir = dirichlet(g, ws.col, j);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const T az = dir ? y[c] * zB[c] : y[c];
+                x[2 * r + c] = xo[c] + (zB[c] - omega * iv[c] * az);
+            }
+        }
+        pB = pT;
+        pT = pN;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            zB[c] = zT[c];
+            zT[c] = zN[c];
+        }
+    }
+}
+
+// s = r - omega M_uu D^-1 r
+template <typename T>
+__global__ void __launch_bounds__(256) k_mf_restrict(MfGrid g, const T* __restrict__ pt, const T* __restrict__ invd,
+                                                     const T* __restrict__ r_in, T omega, T* __restrict__ s_out) {
+    const WaveStrip ws = wave_strip(g);
+    if (!ws.valid) return;
+    auto ld = [&](int64_t j, T& p, T (&v)[2]) {
+        const bool in = ws.col_in && row_in(g, j);
+        const int64_t r = ws.col + j * g.n1;
+        p = in ? pt[r] : T(0);
+        v[0] = in ? invd[2 * r] * r_in[2 * r] : T(0);
+        v[1] = in ? invd[2 * r + 1] * r_in[2 * r + 1] : T(0);
+    };
+    T pB, pT, vB[2], vT[2], c2[2] = {T(0), T(0)}, c3[2] = {T(0), T(0)};
+    ld(ws.j0 - 1, pB, vB);
+    ld(ws.j0, pT, vT);
+    for (int64_t j = ws.j0 - 1; j < ws.j1; ++j) {
+        T pN, vN[2];
+        ld(j + 2, pN, vN);
+        const bool wr = ws.writer && j >= ws.j0;
+        const int64_t r = ws.col + j * g.n1;
+        T ro[2] = {T(0), T(0)};
+        if (wr) {
+            ro[0] = r_in[2 * r];
+            ro[1] = r_in[2 * r + 1];
+        }
+        T y[2], Hx[2][2], Hy[2][2];
+        masked_grad<T>(g, ws, j, vB, vT, Hx, Hy);
+        u_rows<T>(g, ws, j, Hx, Hy, pB, pT, c2, c3, y);
+        if (wr) {
+            const bool dir = dirichlet(g, ws.col, j);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) s_out[2 * r + c] = ro[c] - omega * (dir ? y[c] * vB[c] : y[c]);
+        }
+        pB = pT;
+        pT = pN;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            vB[c] = vT[c];
+            vT[c] = vN[c];
+        }
+    }
+}
+
+// b_c,a = R_a^-T sum over the aggregate's nodes of B_i^T s_i: 16 lanes per aggregate, lane g
+// takes members g, g + 16, ... (in increasing node order), the group sums by an xor butterfly
+constexpr int kAggLanes = 16;
+template <typename T>
+__global__ void __launch_bounds__(256) k_agg_restrict(MfGrid g, int64_t na, const int32_t* __restrict__ aptr,
+                                                      const int32_t* __restrict__ anodes, const T* __restrict__ info,
+                                                      const T* __restrict__ s, T* __restrict__ bc) {
+    const int64_t a = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kAggLanes;
+    const int lg = int(threadIdx.x % kAggLanes);
+    if (a >= na) return;   // whole groups leave together
+    const T* R = info + a * kAggInfo;
+    const T xc = R[9], yc = R[10];
+    T t0 = T(0), t1 = T(0), t2 = T(0);
+    for (int32_t m = aptr[a] + lg; m < aptr[a + 1]; m += kAggLanes) {
+        const int32_t node = anodes[m];
+        const int32_t j = node / int32_t(g.n1), i = node - j * int32_t(g.n1);
+        const T dx = T(g.x0 + double(i) * g.h) - xc, dy = T(g.y0 + double(j) * g.h) - yc;
+        const T s0 = s[2 * int64_t(node)], s1 = s[2 * int64_t(node) + 1];
+        t0 += s0;
+        t1 += s1;
+        t2 += -dy * s0 + dx * s1;
+    }
+#pragma unroll
+    for (int o = kAggLanes / 2; o > 0; o >>= 1) {
+        t0 += __shfl_xor(t0, o, kAggLanes);
+        t1 += __shfl_xor(t1, o, kAggLanes);
+        t2 += __shfl_xor(t2, o, kAggLanes);
+    }
+    if (lg < 3) bc[3 * a + lg] = (R[lg] * t0 + R[3 + lg] * t1) + R[6 + lg] * t2;
+}
+
 __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) b[i] = float(a[i]);
@@ -692,6 +856,8 @@ void mf_prepare(DevSystem& sys, const double* u, const double* phi, const double
     g.p = sys.prm.p;
     g.Gc = sys.prm.Gc;
     g.eps = sys.prm.eps;
+    g.x0 = m.host.desc.lo[0];
+    g.y0 = m.host.desc.lo[1];
     if (g.n1 * (g.ny + 1) != m.n_nodes || m.n_free != m.n_nodes) return;
     if ((strip_waves(g) + 3) / 4 >= (int64_t(1) << 31)) return;   // grid limit
     const int64_t n = m.n_nodes;
@@ -771,6 +937,50 @@ void mf_power_step(const MfState& mf, int blk, const double* invd, const double*
 }
 
 template <typename T>
+static const T* agg_info(const AggTransfer& t);
+template <>
+const double* agg_info<double>(const AggTransfer& t) { return t.info.p; }
+template <>
+const float* agg_info<float>(const AggTransfer& t) { return t.info32.p; }
+template <typename T>
+static T* agg_w(const AggTransfer& t);
+template <>
+double* agg_w<double>(const AggTransfer& t) { return t.w.p; }
+template <>
+float* agg_w<float>(const AggTransfer& t) { return t.w32.p; }
+
+template <typename T>
+void mf_prolong(const MfState& mf, const AggTransfer& t, const T* invd, const T* xc, T* x, hipStream_t st) {
+    const MfGrid& g = mf.grid;
+    const bool f64 = sizeof(T) == 8;
+    // w: the coarse vector and the aggregates' factors read, w written; then per node the
+    // aggregate index, phi_tilde, D^-1 and x (read and written), w and the factors gathered (cached)
+    const double bytes = double(t.n_agg) * sizeof(T) * (3 + kAggInfo + 3) +
+                         double(g.n_nodes) * (4 + sizeof(T) * (1 + 2 + 4));
+    ProfScope ps(f64 ? "mf_prolong_f64" : "mf_prolong_f32", st, bytes);
+    if (t.n_agg) k_agg_w<T><<<grid_for(t.n_agg), 256, 0, st>>>(t.n_agg, agg_info<T>(t), xc, agg_w<T>(t));
+    k_mf_prolong<T><<<tiles(g), 256, 0, st>>>(g, mf_pt<T>(mf), invd, t.agg.p, agg_info<T>(t), agg_w<T>(t),
+                                               T(t.omega), x);
+    FR_LAUNCH_CHECK();
+}
+
+template <typename T>
+void mf_restrict(const MfState& mf, const AggTransfer& t, const T* invd, const T* r, T* s, T* bc, hipStream_t st) {
+    const MfGrid& g = mf.grid;
+    const bool f64 = sizeof(T) == 8;
+    // per node phi_tilde, D^-1, r read, s written; then s, the member list read and the
+    // aggregates' factors read, b_c written
+    const double bytes = double(g.n_nodes) * (sizeof(T) * (1 + 2 + 2 + 2) + sizeof(T) * 2 + 4) +
+                         double(t.n_agg) * (sizeof(T) * (kAggInfo + 3) + 4);
+    ProfScope ps(f64 ? "mf_restrict_f64" : "mf_restrict_f32", st, bytes);
+    k_mf_restrict<T><<<tiles(g), 256, 0, st>>>(g, mf_pt<T>(mf), invd, r, T(t.omega), s);
+    if (t.n_agg)
+        k_agg_restrict<T><<<grid_for(t.n_agg * kAggLanes), 256, 0, st>>>(g, t.n_agg, t.aptr.p, t.anodes.p,
+                                                                         agg_info<T>(t), s, bc);
+    FR_LAUNCH_CHECK();
+}
+
+template <typename T>
 void mf_residual(const MfState& mf, int blk, const T* x, const T* b, T* y, hipStream_t s) {
     const MfGrid& g = mf.grid;
     const bool f64 = sizeof(T) == 8;
@@ -832,6 +1042,12 @@ template void mf_cheb_step<double>(const MfState&, int, const double*, const dou
 template void mf_cheb_step<float>(const MfState&, int, const float*, const float*, const float*, float*, float*,
                                   float, float, hipStream_t);
 template void mf_residual<double>(const MfState&, int, const double*, const double*, double*, hipStream_t);
+template void mf_prolong<double>(const MfState&, const AggTransfer&, const double*, const double*, double*, hipStream_t);
+template void mf_prolong<float>(const MfState&, const AggTransfer&, const float*, const float*, float*, hipStream_t);
+template void mf_restrict<double>(const MfState&, const AggTransfer&, const double*, const double*, double*, double*,
+                                  hipStream_t);
+template void mf_restrict<float>(const MfState&, const AggTransfer&, const float*, const float*, float*, float*,
+                                 hipStream_t);
 template void mf_residual<float>(const MfState&, int, const float*, const float*, float*, hipStream_t);
 template void mf_jspmv<double>(const DevSystem&, bool, const double*, double*, double*, const int*, int64_t,
                                hipStream_t);

@@ -900,7 +900,10 @@ void tune_layout(BMat<double>& M, int op, bool f32, hipStream_t s) {
 
 template <typename T>
 void cheb_first(const T* invd, const T* b, T* d, T* x, T beta, int64_t n, hipStream_t s) {
-    if (n) k_cheb_first<T><<<nblk(n, 256), 256, 0, s>>>(n, invd, b, d, x, beta);
+    if (n == 0) return;
+    // D^-1 and b read, d and x written
+    ProfScope ps(sizeof(T) == 8 ? "cheb_first_f64" : "cheb_first_f32", s, double(n) * sizeof(T) * 4);
+    k_cheb_first<T><<<nblk(n, 256), 256, 0, s>>>(n, invd, b, d, x, beta);
     FR_LAUNCH_CHECK();
 }
 

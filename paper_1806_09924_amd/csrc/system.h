@@ -94,11 +94,14 @@ void mesh_kelly(DevMesh& m, const double* u, double* eta2, hipStream_t s);
 void mesh_mark_crack(const DevMesh& m, const double* phi, double phi_max, double h_target, uint8_t* flags_dev,
                      hipStream_t s);
 
+struct AggTransfer;
+
 // ---- matrix-free fine-level operators on uniform 2d meshes (mfree.hip) --------------------
 struct MfGrid {
     int64_t nx = 0, ny = 0, n1 = 0, n_nodes = 0;   // cells per axis, nodes per row, nodes
     double mu = 0, lam = 0, kappa = 0;
     double h = 0, p = 0, Gc = 0, eps = 0;          // cell edge, pressure, G_c, epsilon
+    double x0 = 0, y0 = 0;                         // lower-left corner (node (i, j) at x0 + i h, y0 + j h)
 };
 struct MfState {
     bool valid = false;                          // the system's mesh allows it and the state is copied
@@ -148,6 +151,13 @@ template <typename T>
 void mf_residual(const MfState& mf, int blk, const T* x, const T* b, T* y, hipStream_t s);
 // y = D^-1 A x with the block's fine operator matrix-free (a power step of the smoother bounds)
 void mf_power_step(const MfState& mf, int blk, const double* invd, const double* x, double* y, hipStream_t s);
+// The finest displacement level's transfers matrix-free, P = (I - omega D^-1 M_uu) P_t:
+// x += P x_c (xc on the aggregates), and b_c = P^T r = P_t^T (r - omega M_uu D^-1 r) (s: a
+// scratch vector of the fine level's size).
+template <typename T>
+void mf_prolong(const MfState& mf, const AggTransfer& t, const T* invd, const T* xc, T* x, hipStream_t st);
+template <typename T>
+void mf_restrict(const MfState& mf, const AggTransfer& t, const T* invd, const T* r, T* s, T* bc, hipStream_t st);
 // y = J x with the displacement rows matrix-free, and the phase-field rows too when `phi_rows`
 // (x FP64 or FP32), xcopy as for jspmv_copy
 template <typename TX>
@@ -247,8 +257,24 @@ void jspmv_copy(const DevSystem& sys, const float* x, double* y, float* xcopy, c
                 hipStream_t s);
 
 // ---- AMG (amg.hip) ----------------------------------------------------------------------
+// The finest displacement level's aggregation, kept so that the V-cycle can apply its
+// transfers matrix-free (uniform 2d meshes): per node its aggregate, per aggregate its member
+// nodes and the factors of the tentative prolongator (rows B_i R_a^-1, B_i the rigid-body modes
+// of node i about the aggregate's centroid): R_a^-1 (3 x 3, row-major) and the centroid (2).
+constexpr int kAggInfo = 11;
+struct AggTransfer {
+    int64_t n_agg = 0;
+    double omega = 0;                            // the prolongator smoothing weight 4 / (3 lambda_max)
+    DBuf<int32_t> agg, aptr, anodes;
+    DBuf<double> info;                           // n_agg x kAggInfo
+    DBuf<float> info32;
+    DBuf<double> w;                              // n_agg x 3 scratch (R_a^-1 x_c)
+    DBuf<float> w32;
+};
+
 struct AmgLevel {
     BMat<double> A, P, R;
+    std::unique_ptr<AggTransfer> mt;             // level 0 of the u hierarchy on uniform 2d meshes
     BMat<double> Pt, AP;                         // kept for a numeric-only refresh
     BMat<float> A32, P32, R32;
     DBuf<double> invd;

@@ -1,8 +1,9 @@
-"""The matrix-free fine-level blocks on uniform 2d meshes (fine_matrix_free, bit 0: M_uu from
+"""The matrix-free fine-level operators on uniform 2d meshes (fine_matrix_free, bit 0: M_uu from
 phi_tilde; bit 1: the masked M_phiphi, and with bit 0 the phase-field rows of the J-SpMV, from the
-assembly's u, phi and active set; default both) equal the stored (masked) blocks up to rounding,
-in the smoothers, the fine-level residuals and the J-SpMV; the FGMRES solve and the Newton loop
-reach the same results with the same iteration counts either way."""
+assembly's u, phi and active set; bit 2: the finest displacement level's prolongation and
+restriction from the aggregation; default all) equal the stored (masked) operators up to
+rounding, in the smoothers, the fine-level residuals, the transfers and the J-SpMV; the FGMRES
+solve and the Newton loop reach the same results with the same iteration counts either way."""
 import numpy as np
 import pytest
 import torch
@@ -35,7 +36,7 @@ def _rect_system(L, nx, ny, seed=11):
     return mesh, prm, state
 
 
-@pytest.mark.parametrize("mf", [1, 2, 3])
+@pytest.mark.parametrize("mf", [1, 2, 3, 5, 7])
 @pytest.mark.parametrize("precision", [64, 32])
 @pytest.mark.parametrize("shape", [(2.0, 128, 128), (1.0, 40, 24)])
 def test_matrix_free_fine_level_matches_stored_blocks(shape, precision, mf):
@@ -103,7 +104,7 @@ def test_matrix_free_jspmv_equals_stored(case):
 def test_matrix_free_newton_loop_config1():
     P = Problem(2, 2.0, 128)
     out = []
-    for mf in (0, 3):
+    for mf in (0, 7):
         u, phi, po, pt = P.dstate()
         st = B.newton(P.mesh, P.prm, u, phi, po, pt, amg=B.amg_opts(fine_matrix_free=mf))
         out.append((st, host(u), host(phi)))
