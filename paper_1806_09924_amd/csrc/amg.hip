@@ -1317,12 +1317,23 @@ BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* 
         spgemm_values<MODE>(A, B, Cm, invd, omega, s);
         return Cm;
     }
-    // small hash sets first (8 rows per wave, 128 slots each); when a row does not fit, all
-    // rows rerun with a wave per row (1024 slots), then with 4096 slots
-    spgemm_symbolic<8, 128>(A, B, Cm, ovf.p, s, false);
+    // small hash sets first (8 rows per wave: 32 slots for the short rows of the finest level's
+    // A P, else 128); when a row does not fit, all rows rerun with the next size (128 slots, a
+    // wave per row with 1024 slots, then 4096 slots)
     int over = 0;
-    layout_from_lengths(*Cm.S, s, ovf.p, &over);
     int tier = 0;
+    const bool short_rows = int64_t(A.S->max_len) * B.S->max_len <= 96;
+    if (short_rows) {
+        tier = -1;
+        spgemm_symbolic<8, 32>(A, B, Cm, ovf.p, s, false);
+        layout_from_lengths(*Cm.S, s, ovf.p, &over);
+    }
+    if (!short_rows || over) {
+        tier = 0;
+        ovf.zero(s);
+        spgemm_symbolic<8, 128>(A, B, Cm, ovf.p, s, false);
+        layout_from_lengths(*Cm.S, s, ovf.p, &over);
+    }
     if (over) {
         tier = 1;
         ovf.zero(s);
@@ -1338,7 +1349,8 @@ BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* 
     }
     Cm.S->own_col.alloc(size_t(std::max<int64_t>(1, Cm.S->n_slots)), s);
     Cm.S->col = Cm.S->own_col.p;
-    if (tier == 0) spgemm_symbolic<8, 128>(A, B, Cm, errs, s, true);
+    if (tier == -1) spgemm_symbolic<8, 32>(A, B, Cm, errs, s, true);
+    else if (tier == 0) spgemm_symbolic<8, 128>(A, B, Cm, errs, s, true);
     else if (tier == 1) spgemm_symbolic<64, 1024>(A, B, Cm, errs, s, true);
     else spgemm_symbolic<64, 4096>(A, B, Cm, errs, s, true);
     Cm.own_val.alloc(size_t(std::max<int64_t>(1, Cm.S->n_slots)) * Cm.br * Cm.bc, s);
