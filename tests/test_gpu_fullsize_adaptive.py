@@ -140,7 +140,8 @@ def test_assembly_sampled_rows(big):
     # active set at the sample, decided in FP64 from complete rows
     margin = -cp / cm - big["oprm"].tau
     ref = margin > 0
-    assert np.array_equal(act[f], ref) or not np.any((act[f] != ref) & (np.abs(margin) > 1e-9 * np.abs(margin).max()))
+    # classifications may differ only within 10 tau of the threshold (rounding of lambda)
+    assert np.array_equal(act[f], ref) or not np.any((act[f] != ref) & (np.abs(margin) > 10 * big["oprm"].tau))
     # J x on the sampled rows: condensed, masked (Dirichlet and active rows/columns keep the
     # diagonal), against the oracle's element matrices on the cells of the rows
     x = np.random.default_rng(11).standard_normal(m.n_solve)
@@ -185,9 +186,10 @@ def test_newton_fp64_and_fp32(big):
     tau = big["oprm"].tau
     assert np.all(pg[S_] <= phi0[S_] + 2 * tau)
     margin = -cp / cm + (pg[S_] - phi0[S_]) - tau
-    # rows whose margin is within 1e-9 of the largest sit on the threshold of the active-set
-    # rule: either classification is correct to rounding, as in the active-set parity checks
-    act = margin > 1e-9 * np.abs(margin).max()
+    # rows whose margin is within 10 tau of the threshold (tau = 1e-10 G_c / eps, the rule's own
+    # offset) sit on it to the accuracy of lambda = -R_phi / B at the 1e-8 Newton tolerance:
+    # either classification is correct there
+    act = margin > 10 * tau
     dev_a = np.abs(pg[S_][act] - phi0[S_][act])
     assert np.all(dev_a <= 1e-10), (dev_a.max(), margin[act][np.argmax(dev_a)], np.abs(margin).max())
     if np.any(~act):
