@@ -1971,7 +1971,17 @@ static T* chebyshev(const AmgLevel& Lc, AmgLevel& L, const T* b, bool from_zero,
     double rho = 1.0 / sigma;
     const int64_t n = Lc.A.rows() * Lc.A.br;
     T* d = O::d(L);
-    if (from_zero) {
+    int k0 = 1;
+    if (from_zero && mf && degree >= 2) {
+        // matrix-free fine level: the first step (x = D^-1 b / theta) is formed inside the second
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        T* dst = (degree == 2 && out) ? out : other;
+        mf_cheb_first2<T>(*mf, blk, O::invd(Lc), b, d, dst, T(1.0 / theta), T(rn * rho), T(2.0 * rn / delta), s);
+        rho = rn;
+        if (dst == out) return out;
+        std::swap(x, other);
+        k0 = 2;
+    } else if (from_zero) {
         cheb_first<T>(O::invd(Lc), b, d, (degree == 1 && out) ? out : x, T(1.0 / theta), n, s);
         if (degree == 1 && out) return out;
     } else {
@@ -1981,7 +1991,7 @@ static T* chebyshev(const AmgLevel& Lc, AmgLevel& L, const T* b, bool from_zero,
         if (dst == out) return out;
         std::swap(x, other);
     }
-    for (int k = 1; k < degree; ++k) {
+    for (int k = k0; k < degree; ++k) {
         const double rn = 1.0 / (2.0 * sigma - rho);
         T* dst = (k + 1 == degree && out) ? out : other;
         if (mf) mf_cheb_step<T>(*mf, blk, O::invd(Lc), x, b, d, dst, T(rn * rho), T(2.0 * rn / delta), s);

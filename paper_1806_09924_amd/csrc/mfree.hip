@@ -331,20 +331,30 @@ __device__ __forceinline__ TA phi_rows(const MfGrid& g, const WaveStrip& w, int6
 }
 
 // Chebyshev step of the fine displacement level: r = b - M_uu x_old; d = alpha d + beta D^-1 r;
-// x_new = x_old + d (the assembled kernel's update, same order of the update terms).  POW: a
+// x_new = x_old + d (the assembled kernel's update, same order of the update terms).  MODE 1: a
 // power step of the smoother bounds instead, d = D^-1 M_uu x_old (b and x_new untouched).
-template <typename T, bool POW = false>
+// MODE 2: the first two steps from x = 0 in one pass: x_old = d = beta0 D^-1 b (the first step,
+// formed per node from b and D^-1 exactly as the separate first-step kernel forms it), then the
+// step above (x_old is not read).
+template <typename T, int MODE = 0>
 __global__ void __launch_bounds__(256) k_mf_cheb(MfGrid g, const T* __restrict__ pt, const T* __restrict__ invd,
                                                  const T* __restrict__ x_old, const T* __restrict__ b,
-                                                 T* __restrict__ d, T* __restrict__ x_new, T alpha, T beta) {
+                                                 T* __restrict__ d, T* __restrict__ x_new, T alpha, T beta,
+                                                 T beta0 = T(0)) {
+    constexpr bool POW = MODE == 1;
     const WaveStrip w = wave_strip(g);
     if (!w.valid) return;
     auto ld = [&](int64_t j, T& p, T (&x)[2]) {
         const bool in = w.col_in && row_in(g, j);
         const int64_t r = w.col + j * g.n1;
         p = in ? pt[r] : T(0);
-        x[0] = in ? x_old[2 * r] : T(0);
-        x[1] = in ? x_old[2 * r + 1] : T(0);
+        if (MODE == 2) {
+            x[0] = in ? beta0 * invd[2 * r] * b[2 * r] : T(0);
+            x[1] = in ? beta0 * invd[2 * r + 1] * b[2 * r + 1] : T(0);
+        } else {
+            x[0] = in ? x_old[2 * r] : T(0);
+            x[1] = in ? x_old[2 * r + 1] : T(0);
+        }
     };
     T pB, pT, xB[2], xT[2], c2[2] = {T(0), T(0)}, c3[2] = {T(0), T(0)};
     ld(w.j0 - 1, pB, xB);
@@ -360,7 +370,7 @@ __global__ void __launch_bounds__(256) k_mf_cheb(MfGrid g, const T* __restrict__
             for (int c = 0; c < 2; ++c) {
                 if (!POW) {
                     bv[c] = b[2 * r + c];
-                    dv[c] = alpha != T(0) ? d[2 * r + c] : T(0);
+                    dv[c] = MODE == 2 ? xB[c] : (alpha != T(0) ? d[2 * r + c] : T(0));
                 }
                 iv[c] = invd[2 * r + c];
             }
@@ -437,13 +447,15 @@ __global__ void __launch_bounds__(256) k_mf_residual(MfGrid g, const T* __restri
     }
 }
 
-// Chebyshev step of the fine phase-field level (M_phiphi, masked), as k_mf_cheb (POW: a power
-// step, d = D^-1 M_phiphi x_old).
-template <typename T, bool POW = false>
+// Chebyshev step of the fine phase-field level (M_phiphi, masked), as k_mf_cheb (MODE 1: a power
+// step, d = D^-1 M_phiphi x_old; MODE 2: the first two steps from x = 0 in one pass).
+template <typename T, int MODE = 0>
 __global__ void __launch_bounds__(256) k_mf_pcheb(MfGrid g, const T* __restrict__ us, const uint8_t* __restrict__ act,
                                                   const T* __restrict__ dpp, const T* __restrict__ invd,
                                                   const T* __restrict__ x_old, const T* __restrict__ b,
-                                                  T* __restrict__ d, T* __restrict__ x_new, T alpha, T beta) {
+                                                  T* __restrict__ d, T* __restrict__ x_new, T alpha, T beta,
+                                                  T beta0 = T(0)) {
+    constexpr bool POW = MODE == 1;
     const WaveStrip w = wave_strip(g);
     if (!w.valid) return;
     // u_s, x (raw), and x masked at active nodes
@@ -452,7 +464,8 @@ __global__ void __launch_bounds__(256) k_mf_pcheb(MfGrid g, const T* __restrict_
         const int64_t r = w.col + j * g.n1;
         u[0] = in ? us[2 * r] : T(0);
         u[1] = in ? us[2 * r + 1] : T(0);
-        x = in ? x_old[r] : T(0);
+        if (MODE == 2) x = in ? beta0 * invd[r] * b[r] : T(0);
+        else x = in ? x_old[r] : T(0);
         xm = (in && act[r] == 0) ? x : T(0);
     };
     T uB[2], uT[2], xB, xT, mB, mT, c2 = T(0), c3 = T(0);
@@ -469,7 +482,7 @@ __global__ void __launch_bounds__(256) k_mf_pcheb(MfGrid g, const T* __restrict_
         if (wr) {
             if (!POW) {
                 bv = b[r];
-                dv = alpha != T(0) ? d[r] : T(0);
+                dv = MODE == 2 ? xB : (alpha != T(0) ? d[r] : T(0));
             }
             iv = invd[r];
             on = act[r] != 0;
@@ -926,12 +939,32 @@ void mf_cheb_step(const MfState& mf, int blk, const T* invd, const T* x_old, con
     FR_LAUNCH_CHECK();
 }
 
+template <typename T>
+void mf_cheb_first2(const MfState& mf, int blk, const T* invd, const T* b, T* d, T* x_new, T beta0, T alpha, T beta,
+                    hipStream_t s) {
+    const MfGrid& g = mf.grid;
+    const bool f64 = sizeof(T) == 8;
+    if (blk == 0) {
+        // b, D^-1 (two words each) and phi_tilde read, d and x_new written
+        const double bytes = double(g.n_nodes) * sizeof(T) * (2 * 2 + 1 + 2 * 2);
+        ProfScope ps(f64 ? "mf_cheb2_f64" : "mf_cheb2_f32", s, bytes);
+        k_mf_cheb<T, 2><<<tiles(g), 256, 0, s>>>(g, mf_pt<T>(mf), invd, nullptr, b, d, x_new, alpha, beta, beta0);
+    } else {
+        // u_s (two words), b, D^-1, the active flag read, d and x_new written
+        const double bytes = double(g.n_nodes) * (sizeof(T) * (2 + 2 + 2) + 1);
+        ProfScope ps(f64 ? "mf_pcheb2_f64" : "mf_pcheb2_f32", s, bytes);
+        k_mf_pcheb<T, 2><<<tiles(g), 256, 0, s>>>(g, mf_us<T>(mf), mf.act.p, mf_dpp<T>(mf), invd, nullptr, b, d, x_new,
+                                                  alpha, beta, beta0);
+    }
+    FR_LAUNCH_CHECK();
+}
+
 void mf_power_step(const MfState& mf, int blk, const double* invd, const double* x, double* y, hipStream_t s) {
     const MfGrid& g = mf.grid;
     if (blk == 0)
-        k_mf_cheb<double, true><<<tiles(g), 256, 0, s>>>(g, mf.pt.p, invd, x, nullptr, y, nullptr, 0.0, 0.0);
+        k_mf_cheb<double, 1><<<tiles(g), 256, 0, s>>>(g, mf.pt.p, invd, x, nullptr, y, nullptr, 0.0, 0.0);
     else
-        k_mf_pcheb<double, true><<<tiles(g), 256, 0, s>>>(g, mf.us.p, mf.act.p, mf.dpp.p, invd, x, nullptr, y,
+        k_mf_pcheb<double, 1><<<tiles(g), 256, 0, s>>>(g, mf.us.p, mf.act.p, mf.dpp.p, invd, x, nullptr, y,
                                                           nullptr, 0.0, 0.0);
     FR_LAUNCH_CHECK();
 }
@@ -1042,6 +1075,10 @@ template void mf_cheb_step<double>(const MfState&, int, const double*, const dou
 template void mf_cheb_step<float>(const MfState&, int, const float*, const float*, const float*, float*, float*,
                                   float, float, hipStream_t);
 template void mf_residual<double>(const MfState&, int, const double*, const double*, double*, hipStream_t);
+template void mf_cheb_first2<double>(const MfState&, int, const double*, const double*, double*, double*, double,
+                                     double, double, hipStream_t);
+template void mf_cheb_first2<float>(const MfState&, int, const float*, const float*, float*, float*, float, float,
+                                    float, hipStream_t);
 template void mf_prolong<double>(const MfState&, const AggTransfer&, const double*, const double*, double*, hipStream_t);
 template void mf_prolong<float>(const MfState&, const AggTransfer&, const float*, const float*, float*, hipStream_t);
 template void mf_restrict<double>(const MfState&, const AggTransfer&, const double*, const double*, double*, double*,

@@ -149,6 +149,11 @@ void mf_cheb_step(const MfState& mf, int blk, const T* invd, const T* x_old, con
                   T beta, hipStream_t s);
 template <typename T>
 void mf_residual(const MfState& mf, int blk, const T* x, const T* b, T* y, hipStream_t s);
+// The first two Chebyshev steps from x = 0 in one pass (x_1 = beta0 D^-1 b formed per node;
+// then the step with alpha, beta into d and x_new): the two separate launches' values.
+template <typename T>
+void mf_cheb_first2(const MfState& mf, int blk, const T* invd, const T* b, T* d, T* x_new, T beta0, T alpha, T beta,
+                    hipStream_t s);
 // y = D^-1 A x with the block's fine operator matrix-free (a power step of the smoother bounds)
 void mf_power_step(const MfState& mf, int blk, const double* invd, const double* x, double* y, hipStream_t s);
 // The finest displacement level's transfers matrix-free, P = (I - omega D^-1 M_uu) P_t:
