@@ -344,33 +344,46 @@ __global__ void __launch_bounds__(256) k_mf_cheb(MfGrid g, const T* __restrict__
     constexpr bool POW = MODE == 1;
     const WaveStrip w = wave_strip(g);
     if (!w.valid) return;
-    auto ld = [&](int64_t j, T& p, T (&x)[2]) {
+    // MODE 2 keeps each row's b and D^-1 from its load (the row is written two steps later)
+    auto ld = [&](int64_t j, T& p, T (&x)[2], T (&bb)[2], T (&ii)[2]) {
         const bool in = w.col_in && row_in(g, j);
         const int64_t r = w.col + j * g.n1;
         p = in ? pt[r] : T(0);
         if (MODE == 2) {
-            x[0] = in ? beta0 * invd[2 * r] * b[2 * r] : T(0);
-            x[1] = in ? beta0 * invd[2 * r + 1] * b[2 * r + 1] : T(0);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                bb[c] = in ? b[2 * r + c] : T(0);
+                ii[c] = in ? invd[2 * r + c] : T(0);
+                x[c] = beta0 * ii[c] * bb[c];
+            }
         } else {
             x[0] = in ? x_old[2 * r] : T(0);
             x[1] = in ? x_old[2 * r + 1] : T(0);
         }
     };
     T pB, pT, xB[2], xT[2], c2[2] = {T(0), T(0)}, c3[2] = {T(0), T(0)};
-    ld(w.j0 - 1, pB, xB);
-    ld(w.j0, pT, xT);
+    T bB[2], bT[2], iB[2], iT[2];
+    ld(w.j0 - 1, pB, xB, bB, iB);
+    ld(w.j0, pT, xT, bT, iT);
     for (int64_t j = w.j0 - 1; j < w.j1; ++j) {
-        T pN, xN[2];
-        ld(j + 2, pN, xN);
+        T pN, xN[2], bN[2], iN[2];
+        ld(j + 2, pN, xN, bN, iN);
         const bool wr = w.writer && j >= w.j0;
         const int64_t r = w.col + j * g.n1;
         T bv[2] = {T(0), T(0)}, dv[2] = {T(0), T(0)}, iv[2] = {T(0), T(0)};
-        if (wr) {
+        if (MODE == 2) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                bv[c] = bB[c];
+                dv[c] = xB[c];
+                iv[c] = iB[c];
+            }
+        } else if (wr) {
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 if (!POW) {
                     bv[c] = b[2 * r + c];
-                    dv[c] = MODE == 2 ? xB[c] : (alpha != T(0) ? d[2 * r + c] : T(0));
+                    dv[c] = alpha != T(0) ? d[2 * r + c] : T(0);
                 }
                 iv[c] = invd[2 * r + c];
             }
@@ -399,6 +412,12 @@ __global__ void __launch_bounds__(256) k_mf_cheb(MfGrid g, const T* __restrict__
         for (int c = 0; c < 2; ++c) {
             xB[c] = xT[c];
             xT[c] = xN[c];
+            if (MODE == 2) {
+                bB[c] = bT[c];
+                bT[c] = bN[c];
+                iB[c] = iT[c];
+                iT[c] = iN[c];
+            }
         }
     }
 }
@@ -459,32 +478,45 @@ __global__ void __launch_bounds__(256) k_mf_pcheb(MfGrid g, const T* __restrict_
     const WaveStrip w = wave_strip(g);
     if (!w.valid) return;
     // u_s, x (raw), and x masked at active nodes
-    auto ld = [&](int64_t j, T (&u)[2], T& x, T& xm) {
+    // MODE 2 keeps each row's b and D^-1 from its load (the row is written two steps later)
+    auto ld = [&](int64_t j, T (&u)[2], T& x, T& xm, T& bb, T& ii) {
         const bool in = w.col_in && row_in(g, j);
         const int64_t r = w.col + j * g.n1;
         u[0] = in ? us[2 * r] : T(0);
         u[1] = in ? us[2 * r + 1] : T(0);
-        if (MODE == 2) x = in ? beta0 * invd[r] * b[r] : T(0);
-        else x = in ? x_old[r] : T(0);
+        if (MODE == 2) {
+            bb = in ? b[r] : T(0);
+            ii = in ? invd[r] : T(0);
+            x = beta0 * ii * bb;
+        } else {
+            x = in ? x_old[r] : T(0);
+        }
         xm = (in && act[r] == 0) ? x : T(0);
     };
     T uB[2], uT[2], xB, xT, mB, mT, c2 = T(0), c3 = T(0);
-    ld(w.j0 - 1, uB, xB, mB);
-    ld(w.j0, uT, xT, mT);
+    T bB = T(0), bT = T(0), iB = T(0), iT = T(0);
+    ld(w.j0 - 1, uB, xB, mB, bB, iB);
+    ld(w.j0, uT, xT, mT, bT, iT);
     const T none[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
     for (int64_t j = w.j0 - 1; j < w.j1; ++j) {
-        T uN[2], xN, mN;
-        ld(j + 2, uN, xN, mN);
+        T uN[2], xN, mN, bN = T(0), iN = T(0);
+        ld(j + 2, uN, xN, mN, bN, iN);
         const bool wr = w.writer && j >= w.j0;
         const int64_t r = w.col + j * g.n1;
         T bv = T(0), dv = T(0), iv = T(0), dg = T(0);
         bool on = false;
         if (wr) {
-            if (!POW) {
-                bv = b[r];
-                dv = MODE == 2 ? xB : (alpha != T(0) ? d[r] : T(0));
+            if (MODE == 2) {
+                bv = bB;
+                dv = xB;
+                iv = iB;
+            } else {
+                if (!POW) {
+                    bv = b[r];
+                    dv = alpha != T(0) ? d[r] : T(0);
+                }
+                iv = invd[r];
             }
-            iv = invd[r];
             on = act[r] != 0;
             if (on) dg = dpp[r];
         }
@@ -508,6 +540,10 @@ __global__ void __launch_bounds__(256) k_mf_pcheb(MfGrid g, const T* __restrict_
         xT = xN;
         mB = mT;
         mT = mN;
+        bB = bT;
+        bT = bN;
+        iB = iT;
+        iT = iN;
     }
 }
 
