@@ -35,6 +35,9 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=512, help="cells per axis of the oracle's sample")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--tune-load", metavar="PATH",
+                    help="launch shapes saved by --tune-save: used instead of timing candidates")
+    ap.add_argument("--tune-save", metavar="PATH", help="write the tuner's launch shapes at the end")
     ap.add_argument("--levels", action="store_true", help="(kept for old command lines; the hierarchy is always reported)")
     return ap.parse_args()
 
@@ -43,8 +46,9 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-PROFILE_OF = {"cheb_f64_b2": "cheb_f64_b2_sneddon2d_2048.md", "cheb_f64_b2_i16": "cheb_f64_b2_sneddon2d_2048.md",
-              "mf_cheb_f64": "mf_cheb_f64_sneddon2d_2048.md", "mf_pcheb_f64": "mf_pcheb_f64_sneddon2d_2048.md"}
+PROFILE_OF = {"cheb_f64_b2_l0": "cheb_f64_b2_sneddon2d_2048.md", "cheb_f64_b2_i16_l0": "cheb_f64_b2_sneddon2d_2048.md",
+              "mf_cheb_f64": "mf_cheb_f64_sneddon2d_2048.md", "mf_pcheb_f64": "mf_pcheb_f64_sneddon2d_2048.md",
+              "cheb_f64_b3_g16_l1": "cheb_f64_b3_g16_l1_sneddon2d_2048.md"}
 
 
 def kernel_digest(src_text, kernel):
@@ -163,6 +167,10 @@ def main():
     from inputs import crack_band_phi
 
     torch.cuda.set_device(0)
+    if args.tune_load:
+        # the counter runs take the shapes of the traced run: timing under collection can pick others
+        with open(args.tune_load) as f:
+            B.tune_load(f.read())
     L, n, l0 = 10.0, args.n, 0.25
     h = 2 * L / n
     eps = 2 * h
@@ -316,6 +324,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
+    if args.tune_save:
+        with open(args.tune_save, "w") as f:
+            f.write(B.tune_table())
     if not args.no_cpu:
         log("oracle timing on the host")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, L, n)

@@ -337,6 +337,22 @@ fr_status amg_level_shape(fr_amg amg, int block, int level, int which, int* slic
  * their candidates again). */
 fr_status fracture_tune_clear(void);
 
+/* The tuner's cached launch shapes as text, one line per entry, eight integers: operation
+ * (0 Chebyshev step, 1 restriction, 2 prolongation), block rows, block columns, floor(log2
+ * rows), mean stored blocks per row, FP32 flag, then the chosen slice height (1 or 64) and
+ * lanes per row (1, 4, 16, 64).  Two-call protocol: *len receives the text's length without
+ * its terminating NUL; with buf non-NULL the text and the NUL are copied when cap > *len, and
+ * FR_EINVAL is returned (nothing copied) otherwise.  A table saved from one process and
+ * imported into another before its setups makes that process use the same shapes without
+ * timing them (deterministic kernels across runs, no tuning cost). */
+fr_status fracture_tune_export(char* buf, size_t cap, size_t* len);
+
+/* Adds the entries of a table in the format above to this process's cache (an entry replaces
+ * a cached choice with the same key; blank lines are skipped).  The whole text is checked
+ * first: FR_EINVAL, with the cache unchanged, for a line that is not eight integers or holds
+ * a value out of range. */
+fr_status fracture_tune_import(const char* text);
+
 /* Level operator `which` (0 = A, 1 = P, 2 = R) of hierarchy `block` as scalar CSR, host
  * arrays, two-call protocol as fracture_system_csr. FP64 values. */
 fr_status amg_level_csr(fr_amg amg, int block, int level, int which, int64_t* n_rows,

@@ -96,6 +96,8 @@ _SIGNATURES = {
     "amg_level_shape": [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                         ctypes.POINTER(ctypes.c_int)],
     "fracture_tune_clear": [],
+    "fracture_tune_export": [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+    "fracture_tune_import": [ctypes.c_char_p],
     "amg_level_info": [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _I64P,
                        ctypes.POINTER(ctypes.c_int), _I64P, _DP],
     "amg_level_csr": [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I64P, _I64P, _I64P, _P, _P, _P, _P],
@@ -577,6 +579,22 @@ def device_check():
 def tune_clear():
     """Forgets the launch shapes cached by the tuner in this process."""
     _check(load().fracture_tune_clear())
+
+
+def tune_table():
+    """The tuner's cached launch shapes as text (one line per entry: op, block rows, block
+    columns, floor(log2 rows), mean blocks per row, FP32 flag, slice height, lanes per row)."""
+    lib = load()
+    n = ctypes.c_size_t(0)
+    _check(lib.fracture_tune_export(None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(lib.fracture_tune_export(buf, n.value + 1, ctypes.byref(n)))
+    return buf.value.decode()
+
+
+def tune_load(text):
+    """Adds a table written by tune_table to this process's cache (same-key entries replaced)."""
+    _check(load().fracture_tune_import(text.encode()))
 
 
 def profile(enable):

@@ -1964,7 +1964,8 @@ struct LevelOps<float> {
 // given (the last step writes there).
 template <typename T>
 static T* chebyshev(const AmgLevel& Lc, AmgLevel& L, const T* b, bool from_zero, T* x, T* other, int degree,
-                    double ratio, hipStream_t s, T* out = nullptr, const MfState* mf = nullptr, int blk = 0) {
+                    double ratio, hipStream_t s, T* out = nullptr, const MfState* mf = nullptr, int blk = 0,
+                    int lvl = -1) {
     using O = LevelOps<T>;
     const double hi = 1.1 * Lc.lmax, lo = hi / ratio;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
@@ -1982,12 +1983,12 @@ static T* chebyshev(const AmgLevel& Lc, AmgLevel& L, const T* b, bool from_zero,
         std::swap(x, other);
         k0 = 2;
     } else if (from_zero) {
-        cheb_first<T>(O::invd(Lc), b, d, (degree == 1 && out) ? out : x, T(1.0 / theta), n, s);
+        cheb_first<T>(O::invd(Lc), b, d, (degree == 1 && out) ? out : x, T(1.0 / theta), n, s, lvl);
         if (degree == 1 && out) return out;
     } else {
         T* dst = (degree == 1 && out) ? out : other;
         if (mf) mf_cheb_step<T>(*mf, blk, O::invd(Lc), x, b, d, dst, T(0), T(1.0 / theta), s);
-        else cheb_step<T>(O::A(Lc), O::invd(Lc), x, b, d, dst, T(0), T(1.0 / theta), s);
+        else cheb_step<T>(O::A(Lc), O::invd(Lc), x, b, d, dst, T(0), T(1.0 / theta), s, lvl);
         if (dst == out) return out;
         std::swap(x, other);
     }
@@ -1995,7 +1996,7 @@ static T* chebyshev(const AmgLevel& Lc, AmgLevel& L, const T* b, bool from_zero,
         const double rn = 1.0 / (2.0 * sigma - rho);
         T* dst = (k + 1 == degree && out) ? out : other;
         if (mf) mf_cheb_step<T>(*mf, blk, O::invd(Lc), x, b, d, dst, T(rn * rho), T(2.0 * rn / delta), s);
-        else cheb_step<T>(O::A(Lc), O::invd(Lc), x, b, d, dst, T(rn * rho), T(2.0 * rn / delta), s);
+        else cheb_step<T>(O::A(Lc), O::invd(Lc), x, b, d, dst, T(rn * rho), T(2.0 * rn / delta), s, lvl);
         rho = rn;
         if (dst == out) return out;
         std::swap(x, other);
@@ -2018,24 +2019,26 @@ static T* vcycle(Hierarchy& H, size_t l, const T* b, const fr_amg_opts& o, hipSt
             return x;
         }
         // large coarsest level: a longer smoothing sweep stands in for the exact solve
-        return chebyshev<T>(L, L, b, true, O::x0(L), O::x1(L), 4 * o.cheb_degree, o.cheb_ratio, s, out);
+        return chebyshev<T>(L, L, b, true, O::x0(L), O::x1(L), 4 * o.cheb_degree, o.cheb_ratio, s, out, nullptr, 0,
+                            int(l));
     }
     // the fine level of a uniform 2d mesh applies its block (M_uu or M_phiphi) matrix-free
     const MfState* mf = (l == 0 && H.mf && H.mf->valid) ? H.mf : nullptr;
-    T* x = chebyshev<T>(L, L, b, true, O::x0(L), O::x1(L), o.cheb_degree, o.cheb_ratio, s, nullptr, mf, H.blk);
+    const int lv = int(l);
+    T* x = chebyshev<T>(L, L, b, true, O::x0(L), O::x1(L), o.cheb_degree, o.cheb_ratio, s, nullptr, mf, H.blk, lv);
     T* other = (x == O::x0(L)) ? O::x1(L) : O::x0(L);
     if (mf) mf_residual<T>(*mf, H.blk, x, b, O::r(L), s);
-    else spmv_residual<T>(O::A(L), x, b, O::r(L), s);
+    else spmv_residual<T>(O::A(L), x, b, O::r(L), s, lv);
     AmgLevel& Ln = *H.lv[l + 1];
     // the finest displacement level's transfers matrix-free where its aggregation was kept (the
     // smoother's d is free between the two smoothings: the restriction's scratch)
     const AggTransfer* mt = (mf && L.mt) ? L.mt.get() : nullptr;
     if (mt) mf_restrict<T>(*mf, *mt, O::invd(L), O::r(L), O::d(L), O::b(Ln), s);
-    else spmv<T>(O::R(L), O::r(L), O::b(Ln), s);
+    else spmv<T>(O::R(L), O::r(L), O::b(Ln), s, lv);
     T* xc = vcycle<T>(H, l + 1, O::b(Ln), o, s);
     if (mt) mf_prolong<T>(*mf, *mt, O::invd(L), xc, x, s);
-    else spmv_add<T>(O::P(L), xc, x, s);
-    return chebyshev<T>(L, L, b, false, x, other, o.cheb_degree, o.cheb_ratio, s, out, mf, H.blk);
+    else spmv_add<T>(O::P(L), xc, x, s, lv);
+    return chebyshev<T>(L, L, b, false, x, other, o.cheb_degree, o.cheb_ratio, s, out, mf, H.blk, lv);
 }
 
 // z = M^-1 r with M^-1 = diag(V-cycle(M_uu), V-cycle(M_phiphi)).  The phi block's cycle

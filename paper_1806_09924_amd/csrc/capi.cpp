@@ -659,6 +659,27 @@ fr_status fracture_tune_clear(void) {
     });
 }
 
+fr_status fracture_tune_export(char* buf, size_t cap, size_t* len) {
+    FR_REQUIRE(len != nullptr, "fracture_tune_export: NULL len");
+    return guard([&]() {
+        const std::string t = fr::tune_export();
+        *len = t.size();
+        if (buf == nullptr) return FR_OK;
+        FR_REQUIRE(cap > t.size(), "fracture_tune_export: buffer of " + std::to_string(cap) + " bytes, the table needs " +
+                                       std::to_string(t.size() + 1));
+        std::memcpy(buf, t.c_str(), t.size() + 1);
+        return FR_OK;
+    });
+}
+
+fr_status fracture_tune_import(const char* text) {
+    FR_REQUIRE(text != nullptr, "fracture_tune_import: NULL text");
+    return guard([&]() {
+        fr::tune_import(text);
+        return FR_OK;
+    });
+}
+
 fr_status amg_level_csr(fr_amg amg, int block, int level, int which, int64_t* n_rows, int64_t* n_cols, int64_t* nnz,
                         int64_t* row_ptr, int32_t* col, double* val, void* stream) {
     FR_REQUIRE(amg != nullptr && nnz != nullptr, "amg_level_csr: NULL argument");

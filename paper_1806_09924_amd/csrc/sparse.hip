@@ -3,9 +3,12 @@
 // and small deterministic device primitives (scan, dot, casts).
 #include <algorithm>
 #include <cstdio>
+#include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
+#include <vector>
 
 #include "profile.h"
 #include "system.h"
@@ -538,8 +541,16 @@ static void spmv_launch(const BMat<T>& A, int G, const T* x, const T* b, T* y, h
 #undef FR_SPMV_G
 }
 
+// Profile names: one per kernel instantiation, with the hierarchy level when the caller gives it
+// ("_l<level>"), so that a level's launches are told apart from another's of the same kernel.
+static void level_suffix(char* name, size_t cap, int level) {
+    if (level < 0) return;
+    const size_t n = std::strlen(name);
+    if (n < cap) std::snprintf(name + n, cap - n, "_l%d", level);
+}
+
 template <typename T, int MODE>
-static void spmv_mode(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_t s) {
+static void spmv_mode(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_t s, int level) {
     const int br = A.br, bc = A.bc;
     const SellStruct& S = *A.S;
     if (S.n_rows == 0) return;
@@ -550,6 +561,7 @@ static void spmv_mode(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_
     if (G == 1) std::snprintf(name, sizeof(name), "spmv_%s_%dx%d_m%d%s", sizeof(T) == 8 ? "f64" : "f32", br, bc, MODE,
                               S.col16 ? "_i16" : "");
     else std::snprintf(name, sizeof(name), "spmv_%s_%dx%d_m%d_g%d", sizeof(T) == 8 ? "f64" : "f32", br, bc, MODE, G);
+    level_suffix(name, sizeof(name), level);
     const double ib = (S.col16 && G == 1) ? 2.0 : 4.0;   // index bytes per stored block
     const double bytes = double(S.nnz) * (br * bc * sizeof(T) + ib) + double(S.n_cols) * bc * sizeof(T) +
                          double(S.n_rows) * br * sizeof(T) * (MODE == 0 ? 1 : 2);
@@ -558,11 +570,17 @@ static void spmv_mode(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_
 }
 
 template <typename T>
-void spmv(const BMat<T>& A, const T* x, T* y, hipStream_t s) { spmv_mode<T, 0>(A, x, nullptr, y, s); }
+void spmv(const BMat<T>& A, const T* x, T* y, hipStream_t s, int level) {
+    spmv_mode<T, 0>(A, x, nullptr, y, s, level);
+}
 template <typename T>
-void spmv_residual(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_t s) { spmv_mode<T, 1>(A, x, b, y, s); }
+void spmv_residual(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_t s, int level) {
+    spmv_mode<T, 1>(A, x, b, y, s, level);
+}
 template <typename T>
-void spmv_add(const BMat<T>& A, const T* x, T* y, hipStream_t s) { spmv_mode<T, 2>(A, x, nullptr, y, s); }
+void spmv_add(const BMat<T>& A, const T* x, T* y, hipStream_t s, int level) {
+    spmv_mode<T, 2>(A, x, nullptr, y, s, level);
+}
 
 template <typename T>
 static void cheb_launch(const BMat<T>& A, int G, const T* invd, const T* x_old, const T* b, T* d, T* x_new, T alpha,
@@ -599,7 +617,7 @@ static void cheb_launch(const BMat<T>& A, int G, const T* invd, const T* x_old, 
 
 template <typename T>
 void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d, T* x_new, T alpha, T beta,
-               hipStream_t s) {
+               hipStream_t s, int level) {
     const SellStruct& S = *A.S;
     if (S.n_rows == 0) return;
     const int G = launch_lanes(S);
@@ -608,6 +626,7 @@ void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d
     if (G == 1) std::snprintf(name, sizeof(name), "cheb_%s_b%d%s", sizeof(T) == 8 ? "f64" : "f32", A.br,
                               S.col16 ? "_i16" : "");
     else std::snprintf(name, sizeof(name), "cheb_%s_b%d_g%d", sizeof(T) == 8 ? "f64" : "f32", A.br, G);
+    level_suffix(name, sizeof(name), level);
     // matrix once (index bytes 2 with row offsets), x gathered once, b, d, D^-1 read, d and
     // x_new written
     const double ib = (S.col16 && G == 1) ? 2.0 : 4.0;
@@ -868,6 +887,50 @@ int tune_entries() {
     return int(g_tune.size());
 }
 
+// One line per cached choice: "op br bc lg_rows avg_len f32 C G".
+std::string tune_export() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::string out;
+    char line[96];
+    for (const auto& [k, v] : g_tune) {
+        std::snprintf(line, sizeof(line), "%d %d %d %d %d %d %d %d\n", k.op, k.br, k.bc, k.lg_rows, k.avg_len, k.f32,
+                      v.first, v.second);
+        out += line;
+    }
+    return out;
+}
+
+// Parses the whole text before it touches the cache, so a malformed table changes nothing.
+// Entries replace cached choices with the same key.
+void tune_import(const char* text) {
+    std::vector<std::pair<TuneKey, std::pair<int, int>>> rows;
+    const char* p = text;
+    int line_no = 0;
+    while (*p) {
+        const char* e = std::strchr(p, '\n');
+        const size_t n = e ? size_t(e - p) : std::strlen(p);
+        std::string line(p, n);
+        p += n + (e ? 1 : 0);
+        ++line_no;
+        if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+        TuneKey k{};
+        int C = 0, G = 0, used = 0;
+        const int got = std::sscanf(line.c_str(), "%d %d %d %d %d %d %d %d %n", &k.op, &k.br, &k.bc, &k.lg_rows,
+                                    &k.avg_len, &k.f32, &C, &G, &used);
+        if (got != 8 || line.find_first_not_of(" \t\r", size_t(used)) != std::string::npos)
+            fail(FR_EINVAL, "tune table line " + std::to_string(line_no) + ": expected 8 integers");
+        if (k.op < 0 || k.op > 2 || k.br < 1 || k.br > 6 || k.bc < 1 || k.bc > 6 || k.lg_rows < 0 || k.lg_rows > 62 ||
+            k.avg_len < 0 || (k.f32 != 0 && k.f32 != 1))
+            fail(FR_EINVAL, "tune table line " + std::to_string(line_no) + ": key out of range");
+        if ((C != 1 && C != kWave) || (G != 1 && G != 4 && G != 16 && G != 64))
+            fail(FR_EINVAL, "tune table line " + std::to_string(line_no) + ": slice height must be 1 or " +
+                                std::to_string(kWave) + ", lanes per row 1, 4, 16 or 64");
+        rows.push_back({k, {C, G}});
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& r : rows) g_tune[r.first] = r.second;
+}
+
 // op 0: Chebyshev step (smoother of A), 1: y = M x (restriction), 2: y += M x (prolongation),
 // timed in the precision the V-cycle runs in (f32).  Candidates: slice height 64 with 1, 4,
 // 16 lanes per row and contiguous rows (C = 1) with 1, 4, 16, 64 lanes.  Each is timed (one
@@ -899,10 +962,13 @@ void tune_layout(BMat<double>& M, int op, bool f32, hipStream_t s) {
 }
 
 template <typename T>
-void cheb_first(const T* invd, const T* b, T* d, T* x, T beta, int64_t n, hipStream_t s) {
+void cheb_first(const T* invd, const T* b, T* d, T* x, T beta, int64_t n, hipStream_t s, int level) {
     if (n == 0) return;
     // D^-1 and b read, d and x written
-    ProfScope ps(sizeof(T) == 8 ? "cheb_first_f64" : "cheb_first_f32", s, double(n) * sizeof(T) * 4);
+    char name[48];
+    std::snprintf(name, sizeof(name), "cheb_first_%s", sizeof(T) == 8 ? "f64" : "f32");
+    level_suffix(name, sizeof(name), level);
+    ProfScope ps(name, s, double(n) * sizeof(T) * 4);
     k_cheb_first<T><<<nblk(n, 256), 256, 0, s>>>(n, invd, b, d, x, beta);
     FR_LAUNCH_CHECK();
 }
@@ -945,17 +1011,17 @@ void jspmv_copy(const DevSystem& sys, const float* x, double* y, float* xcopy, c
 
 void system_matvec(DevSystem& sys, const double* x, double* y) { jspmv(sys, x, y, sys.stream); }
 
-template void spmv<double>(const BMat<double>&, const double*, double*, hipStream_t);
-template void spmv<float>(const BMat<float>&, const float*, float*, hipStream_t);
-template void spmv_residual<double>(const BMat<double>&, const double*, const double*, double*, hipStream_t);
-template void spmv_residual<float>(const BMat<float>&, const float*, const float*, float*, hipStream_t);
-template void spmv_add<double>(const BMat<double>&, const double*, double*, hipStream_t);
-template void spmv_add<float>(const BMat<float>&, const float*, float*, hipStream_t);
+template void spmv<double>(const BMat<double>&, const double*, double*, hipStream_t, int);
+template void spmv<float>(const BMat<float>&, const float*, float*, hipStream_t, int);
+template void spmv_residual<double>(const BMat<double>&, const double*, const double*, double*, hipStream_t, int);
+template void spmv_residual<float>(const BMat<float>&, const float*, const float*, float*, hipStream_t, int);
+template void spmv_add<double>(const BMat<double>&, const double*, double*, hipStream_t, int);
+template void spmv_add<float>(const BMat<float>&, const float*, float*, hipStream_t, int);
 template void cheb_step<double>(const BMat<double>&, const double*, const double*, const double*, double*, double*,
-                                double, double, hipStream_t);
+                                double, double, hipStream_t, int);
 template void cheb_step<float>(const BMat<float>&, const float*, const float*, const float*, float*, float*, float,
-                               float, hipStream_t);
-template void cheb_first<double>(const double*, const double*, double*, double*, double, int64_t, hipStream_t);
-template void cheb_first<float>(const float*, const float*, float*, float*, float, int64_t, hipStream_t);
+                               float, hipStream_t, int);
+template void cheb_first<double>(const double*, const double*, double*, double*, double, int64_t, hipStream_t, int);
+template void cheb_first<float>(const float*, const float*, float*, float*, float, int64_t, hipStream_t, int);
 
 }  // namespace fr

@@ -227,16 +227,16 @@ void layout_from_lengths(SellStruct& S, hipStream_t s, const int* flag = nullptr
 void scan_exclusive_async(const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
 
 template <typename T>
-void spmv(const BMat<T>& A, const T* x, T* y, hipStream_t s);                 // y = A x
+void spmv(const BMat<T>& A, const T* x, T* y, hipStream_t s, int level = -1);   // y = A x
 template <typename T>
-void spmv_residual(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_t s);  // y = b - A x
+void spmv_residual(const BMat<T>& A, const T* x, const T* b, T* y, hipStream_t s, int level = -1);  // y = b - A x
 template <typename T>
-void spmv_add(const BMat<T>& A, const T* x, T* y, hipStream_t s);             // y += A x
+void spmv_add(const BMat<T>& A, const T* x, T* y, hipStream_t s, int level = -1);   // y += A x
 template <typename T>
 void cheb_step(const BMat<T>& A, const T* invd, const T* x_old, const T* b, T* d, T* x_new,
-               T alpha, T beta, hipStream_t s);
+               T alpha, T beta, hipStream_t s, int level = -1);
 template <typename T>
-void cheb_first(const T* invd, const T* b, T* d, T* x, T beta, int64_t n, hipStream_t s);
+void cheb_first(const T* invd, const T* b, T* d, T* x, T beta, int64_t n, hipStream_t s, int level = -1);
 // fused J-SpMV over the three blocks: y = J x (solve order); x may be FP32 (exactly widened)
 // y = D^-1 A x (the power iteration of the smoother bounds; its own kernel, k_power_step).
 void diag_scaled_matvec(const BMat<double>& A, const double* invd, const double* x, double* y, hipStream_t s);
@@ -253,6 +253,8 @@ BMat<double> relayout(const BMat<double>& A, int C, hipStream_t s);
 void tune_layout(BMat<double>& M, int op, bool f32, hipStream_t s);
 void tune_clear();
 int tune_entries();
+std::string tune_export();
+void tune_import(const char* text);
 void jspmv(const DevSystem& sys, const double* x, double* y, hipStream_t s);
 void jspmv(const DevSystem& sys, const float* x, double* y, hipStream_t s);
 // the same, also copying x to xcopy + (*jp) xstride (the Krylov basis slot of the device's index)

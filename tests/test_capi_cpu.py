@@ -300,3 +300,35 @@ def test_face_neighbours_against_a_brute_force_search(dim, n, levels, radius, ha
                         touch &= (np.minimum(hi[:, t], hi[c, t]) - np.maximum(lo[:, t], lo[c, t])) > tol
                 got = sorted(nbr[ptr[2 * dim * c + j]:ptr[2 * dim * c + j + 1]].tolist())
                 assert got == sorted(np.nonzero(touch)[0].tolist()), (c, j)
+
+
+def test_tune_table_round_trip_and_rejects(lib):
+    """The tuner's cache as text: imported entries come back out unchanged, a malformed table
+    is rejected as a whole (the cache keeps its entries), short buffers are refused."""
+    B.tune_clear()
+    assert B.tune_table() == ""
+    table = "0 3 3 20 9 0 64 16\n1 2 2 13 5 1 1 4\n"
+    B.tune_load(table + "\n")
+    assert sorted(B.tune_table().splitlines()) == sorted(table.splitlines())
+    # a later entry with the same key replaces the cached one
+    B.tune_load("0 3 3 20 9 0 1 64\n")
+    assert "0 3 3 20 9 0 1 64" in B.tune_table().splitlines()
+    before = B.tune_table()
+    for bad in ("0 3 3 20 9 0 64\n",            # seven integers
+                "0 3 3 20 9 0 64 16 5\n",       # nine
+                "3 3 3 20 9 0 64 16\n",         # no operation 3
+                "0 3 3 20 9 0 32 16\n",         # slice height 32
+                "0 3 3 20 9 0 64 8\n",          # 8 lanes per row
+                "0 3 3 20 9 2 64 16\n",         # precision flag 2
+                "1 2 2 13 6 1 1 4\nx\n"):       # a good line then a bad one: nothing taken
+        assert lib.fracture_tune_import(bad.encode()) == B.FR_EINVAL, bad
+        assert "tune table line" in B.last_error()
+        assert B.tune_table() == before
+    assert lib.fracture_tune_import(None) == B.FR_EINVAL
+    n = ctypes.c_size_t(0)
+    assert lib.fracture_tune_export(None, 0, None) == B.FR_EINVAL
+    assert lib.fracture_tune_export(None, 0, ctypes.byref(n)) == B.FR_OK and n.value == len(before)
+    buf = ctypes.create_string_buffer(n.value)
+    assert lib.fracture_tune_export(buf, n.value, ctypes.byref(n)) == B.FR_EINVAL   # no room for the NUL
+    B.tune_clear()
+    assert B.tune_table() == ""

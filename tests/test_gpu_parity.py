@@ -419,3 +419,16 @@ def test_autotuned_shapes_keep_the_operators(dim, n):
     assert np.array_equal(host(z2), z1)
     with pytest.raises(B.FractureError):
         A1.level_shape(0, A1.n_levels(0) - 1, 1)
+    # the cache as text: cleared, then loaded from the table, a setup takes the same shapes
+    # without timing and gives the same V-cycle bit for bit
+    table = B.tune_table()
+    assert len(table.splitlines()) >= 3
+    B.tune_clear()
+    B.tune_load(table)
+    assert B.tune_table() == table
+    A3 = B.Amg(S, B.amg_opts(autotune=1))
+    for (blk, lev, which), cg in shapes.items():
+        assert A3.level_shape(blk, lev, which) == cg
+    z3 = torch.empty_like(r)
+    A3.apply(dev(host(r)), z3)
+    assert np.array_equal(host(z3), z1)
