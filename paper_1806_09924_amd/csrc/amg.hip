@@ -94,17 +94,47 @@ __global__ void k_mis_init(int64_t n, const uint8_t* __restrict__ isolated, uint
     key[i] = mis_key(st, i);
 }
 
-__global__ void k_mis_prop(int64_t n, int C, const int32_t* __restrict__ sp, const int32_t* __restrict__ len,
-                           const int32_t* __restrict__ col, const uint8_t* __restrict__ strong,
-                           const uint64_t* __restrict__ in, uint64_t* __restrict__ out) {
+// m = max(m, in[c]) over the strong slots of row r.  Every slot of the row's slice is visited:
+// padding slots are never strong and their columns are valid indices, so each chunk's column,
+// flag and gathered value are loaded before any test and the gathers are in flight together.
+__device__ __forceinline__ uint64_t strong_max(const int32_t* __restrict__ sp, int C, int64_t r,
+                                               const int32_t* __restrict__ col, const uint8_t* __restrict__ strong,
+                                               const uint64_t* __restrict__ in, uint64_t m) {
+    constexpr int U = 4;
+    const int64_t s0 = r / C;
+    const int64_t base = int64_t(sp[s0]) + (r - s0 * C);
+    const int w = (sp[s0 + 1] - sp[s0]) / C;
+    int k = 0;
+    for (; k + U <= w; k += U) {
+        int32_t c[U];
+        uint8_t st[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t sl = base + int64_t(k + u) * C;
+            c[u] = col[sl];
+            st[u] = strong[sl];
+        }
+        uint64_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = in[c[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (st[u]) m = max(m, v[u]);
+    }
+    for (; k < w; ++k) {
+        const int64_t sl = base + int64_t(k) * C;
+        const uint64_t v = in[col[sl]];
+        if (strong[sl]) m = max(m, v);
+    }
+    return m;
+}
+
+__global__ void k_mis_prop(int64_t n, int C, const int32_t* __restrict__ sp, const int32_t* __restrict__ col,
+                           const uint8_t* __restrict__ strong, const uint64_t* __restrict__ in,
+                           uint64_t* __restrict__ out) {
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    uint64_t m = in[r];
-    for (int k = 0; k < len[r]; ++k) {
-        const int64_t s = sslot(sp, C, r, k);
-        if (strong[s]) m = max(m, in[col[s]]);
-    }
-    out[r] = m;
+    out[r] = strong_max(sp, C, r, col, strong, in, in[r]);
 }
 
 // Second hop fused with the state update: m2 = max of m1 over the row and its strong
@@ -112,7 +142,6 @@ __global__ void k_mis_prop(int64_t n, int C, const int32_t* __restrict__ sp, con
 // root within two hops drops out.  (The first hop of the round has finished, and this kernel
 // reads only m1, so the rows' key and state can be updated in place.)
 __global__ void __launch_bounds__(256) k_mis_prop_update(int64_t n, int C, const int32_t* __restrict__ sp,
-                                                         const int32_t* __restrict__ len,
                                                          const int32_t* __restrict__ col,
                                                          const uint8_t* __restrict__ strong,
                                                          const uint64_t* __restrict__ m1, uint8_t* __restrict__ state,
@@ -121,11 +150,7 @@ __global__ void __launch_bounds__(256) k_mis_prop_update(int64_t n, int C, const
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     int und = 0;
     if (i < n && state[i] == 1) {
-        uint64_t m2 = m1[i];
-        for (int k = 0; k < len[i]; ++k) {
-            const int64_t s = sslot(sp, C, i, k);
-            if (strong[s]) m2 = max(m2, m1[col[s]]);
-        }
+        const uint64_t m2 = strong_max(sp, C, i, col, strong, m1, m1[i]);
         if (m2 == key[i]) {
             state[i] = 2;
             key[i] = mis_key(2, i);
@@ -1516,10 +1541,10 @@ static int64_t aggregate(const BMat<double>& A, const double* dnorm, double thet
     // costs more than the host round trip), small ones every third round
     const int every = n >= (int64_t(1) << 18) ? 1 : 3;
     for (int round = 0; round < 240; ++round) {
-        k_mis_prop<<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.row_len, S.col, strong.p, key.p, m1.p);
+        k_mis_prop<<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.col, strong.p, key.p, m1.p);
         const bool check = round % every == every - 1;
         if (check) und.zero(s);
-        k_mis_prop_update<<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.row_len, S.col, strong.p, m1.p, state.p, key.p,
+        k_mis_prop_update<<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.col, strong.p, m1.p, state.p, key.p,
                                              check ? und.p : nullptr);
         FR_LAUNCH_CHECK();
         if (check && download1(und.p, s) == 0) break;
