@@ -931,34 +931,55 @@ __global__ void __launch_bounds__(256) k_spgemm_merge(SellV A, const double* __r
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
     const int la = A.len[r];
-    for (int ka = 0; ka < la; ++ka) {
-        const int64_t as = sslot(A.sp, A.C, r, ka);
-        const int64_t k = A.col[as];
-        double ab[BRA * BCA];
-        for (int e = 0; e < BRA * BCA; ++e) ab[e] = av[as * (BRA * BCA) + e];
-        const int lb = B.len[k];
-        for (int kb = lg; kb < lb; kb += G) {
-            const int64_t bs = sslot(B.sp, B.C, k, kb);
-            const int32_t c = B.col[bs];
-            int lo = 0, hi = lc - 1, p = -1;
-            while (lo <= hi) {
-                const int mid = (lo + hi) >> 1;
-                const int32_t v = cols[mid];
-                if (v == c) { p = mid; break; }
-                if (v < c) lo = mid + 1;
-                else hi = mid - 1;
-            }
-            if (p < 0) continue;
-            const double* bb = bv + bs * (BCA * BCB);
-            for (int i = 0; i < BRA; ++i)
-                for (int j = 0; j < BCB; ++j) {
-                    double t = 0.0;
-                    for (int q = 0; q < BCA; ++q) t += ab[i * BCA + q] * bb[q * BCB + j];
-                    acc[p * BB + i * BCB + j] += t;
-                }
+    const int base = lane - lg;   // the group's first lane in the wave
+    for (int j0 = 0; j0 < la; j0 += G) {
+        // lane lg loads A's entry j0 + lg (its block, and where row k of B starts and how long
+        // it is), so the loads of up to G entries are in flight together; the group then takes
+        // the entries in column order from the lane that holds each
+        const int ja = j0 + lg;
+        double abj[BRA * BCA];
+        int32_t lbj = 0, b0lo = 0, b0hi = 0;
+        for (int e = 0; e < BRA * BCA; ++e) abj[e] = 0.0;
+        if (ja < la) {
+            const int64_t as = sslot(A.sp, A.C, r, ja);
+            const int64_t k = A.col[as];
+            for (int e = 0; e < BRA * BCA; ++e) abj[e] = av[as * (BRA * BCA) + e];
+            lbj = B.len[k];
+            const int64_t b0 = sslot(B.sp, B.C, k, 0);
+            b0lo = int32_t(uint32_t(uint64_t(b0)));
+            b0hi = int32_t(uint32_t(uint64_t(b0) >> 32));
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        const int nj = min(G, la - j0);
+        for (int tj = 0; tj < nj; ++tj) {
+            const int src = base + tj;
+            const int lb = __shfl(lbj, src, kWave);
+            const int64_t b0 = int64_t((uint64_t(uint32_t(__shfl(b0hi, src, kWave))) << 32) |
+                                       uint64_t(uint32_t(__shfl(b0lo, src, kWave))));
+            double ab[BRA * BCA];
+            for (int e = 0; e < BRA * BCA; ++e) ab[e] = __shfl(abj[e], src, kWave);
+            for (int kb = lg; kb < lb; kb += G) {
+                const int64_t bs = b0 + int64_t(kb) * B.C;
+                const int32_t c = B.col[bs];
+                int lo = 0, hi = lc - 1, p = -1;
+                while (lo <= hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const int32_t v = cols[mid];
+                    if (v == c) { p = mid; break; }
+                    if (v < c) lo = mid + 1;
+                    else hi = mid - 1;
+                }
+                if (p < 0) continue;
+                const double* bb = bv + bs * (BCA * BCB);
+                for (int i = 0; i < BRA; ++i)
+                    for (int j = 0; j < BCB; ++j) {
+                        double t = 0.0;
+                        for (int q = 0; q < BCA; ++q) t += ab[i * BCA + q] * bb[q * BCB + j];
+                        acc[p * BB + i * BCB + j] += t;
+                    }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
     }
     const int64_t s0 = r / Cm.C;
     const int width = (Cm.sp[s0 + 1] - Cm.sp[s0]) / Cm.C;
