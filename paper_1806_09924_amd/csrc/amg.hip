@@ -481,14 +481,23 @@ __device__ void spgemm_row_set(const SellV& A, const SellV& B, int64_t r, int32_
     wave_sync();
     if (r < A.n_rows) {
         const int la = A.len[r];
-        for (int ka = lg; ka < la; ka += G) {
+        bool full = false;
+        for (int ka = lg; ka < la && !full; ka += G) {
             const int64_t k = A.col[sslot(A.sp, A.C, r, ka)];
             const int lb = B.len[k];
-            for (int kb = 0; kb < lb; ++kb) {
-                const int32_t c = B.col[sslot(B.sp, B.C, k, kb)];
-                if (!hash_insert<HS>(tab, c, added)) { atomicOr(overflow, 1); break; }
+            const int64_t b0 = sslot(B.sp, B.C, k, 0);
+            // B's columns U at a time, all loaded before they are inserted
+            constexpr int U = 4;
+            for (int kb = 0; kb < lb && !full; kb += U) {
+                int32_t c[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) c[u] = kb + u < lb ? B.col[b0 + int64_t(kb + u) * B.C] : -1;
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (c[u] >= 0 && !full && !hash_insert<HS>(tab, c[u], added)) full = true;
             }
         }
+        if (full) atomicOr(overflow, 1);
     }
     wave_sync();
 }
