@@ -14,6 +14,8 @@
 #include <thread>
 #include <type_traits>
 
+#include <hipcub/hipcub.hpp>
+
 #include "profile.h"
 #include "system.h"
 
@@ -737,72 +739,6 @@ __global__ void __launch_bounds__(256) k_spgemm_numeric(SellV A, const double* _
 }
 
 // ---- transpose -------------------------------------------------------------------------------
-__global__ void k_col_count(SellV P, int32_t* __restrict__ cnt) {
-    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= P.n_rows) return;
-    for (int k = 0; k < P.len[r]; ++k) atomicAdd(&cnt[P.col[sslot(P.sp, P.C, r, k)]], 1);
-}
-
-template <int BR, int BC>
-__global__ void k_transpose_fill(SellV P, const double* __restrict__ pv, SellV Rm, int32_t* __restrict__ fillc,
-                                 int32_t* __restrict__ rcol, double* __restrict__ rv) {
-    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= P.n_rows) return;
-    for (int k = 0; k < P.len[r]; ++k) {
-        const int64_t ps = sslot(P.sp, P.C, r, k);
-        const int32_t c = P.col[ps];
-        const int pos = atomicAdd(&fillc[c], 1);
-        const int64_t rs = sslot(Rm.sp, Rm.C, c, pos);
-        rcol[rs] = int32_t(r);
-        for (int i = 0; i < BR; ++i)
-            for (int j = 0; j < BC; ++j) rv[rs * (BR * BC) + j * BR + i] = pv[ps * (BR * BC) + i * BC + j];
-    }
-}
-
-// One wave per row: order the row's (unique) columns by rank and move the blocks from the
-// unsorted staging arrays into place; padding repeats the smallest column with zero blocks.
-// Rows of up to kRankMax entries rank against a copy of their keys in LDS, longer ones
-// against the staging array itself.
-constexpr int kRankMax = 1024;
-
-template <int BB>
-__global__ void __launch_bounds__(256) k_rank_rows(SellV Rm, const int32_t* __restrict__ tcol,
-                                                   const double* __restrict__ tval, int32_t* __restrict__ col,
-                                                   double* __restrict__ val) {
-    __shared__ int32_t keys[kWavesPerBlock][kRankMax];
-    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t r = int64_t(blockIdx.x) * kWavesPerBlock + w;
-    if (r >= Rm.n_rows) return;
-    const int n = Rm.len[r];
-    const bool in_lds = n <= kRankMax;
-    auto key = [&](int j) -> int32_t { return in_lds ? keys[w][j] : tcol[sslot(Rm.sp, Rm.C, r, j)]; };
-    int32_t mn = 0x7fffffff;
-    for (int e = lane; e < n; e += kWave) {
-        const int32_t v = tcol[sslot(Rm.sp, Rm.C, r, e)];
-        if (in_lds) keys[w][e] = v;
-        mn = min(mn, v);
-    }
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) mn = min(mn, __shfl_xor(mn, o));
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    for (int e = lane; e < n; e += kWave) {
-        const int32_t v = key(e);
-        int rk = 0;
-        for (int j = 0; j < n; ++j) rk += key(j) < v;
-        const int64_t src = sslot(Rm.sp, Rm.C, r, e), dst = sslot(Rm.sp, Rm.C, r, rk);
-        col[dst] = v;
-        for (int b = 0; b < BB; ++b) val[dst * BB + b] = tval[src * BB + b];
-    }
-    const int64_t s0 = r / Rm.C;
-    const int width = (Rm.sp[s0 + 1] - Rm.sp[s0]) / Rm.C;
-    for (int k = n + lane; k < width; k += kWave) {
-        const int64_t s = sslot(Rm.sp, Rm.C, r, k);
-        col[s] = n > 0 ? mn : 0;
-        for (int b = 0; b < BB; ++b) val[s * BB + b] = 0.0;
-    }
-}
-
 // Values of R = P^T into an existing structure (G lanes per row of R, over its entries):
 // entry (r, c) of R is entry (c, r) of P, found by binary search in P's sorted row c.
 template <int BR, int BC, int G>
@@ -820,6 +756,74 @@ __global__ void __launch_bounds__(256) k_transpose_values(SellV P, const double*
         const double* pb = kp >= 0 ? pv + sslot(P.sp, P.C, Rm.col[rs], kp) * (BR * BC) : nullptr;
         for (int i = 0; i < BR; ++i)
             for (int j = 0; j < BC; ++j) rv[rs * (BR * BC) + j * BR + i] = pb ? pb[i * BC + j] : 0.0;
+    }
+}
+
+// Transpose by a stable sort of P's entries by column: the entries listed in row order (key:
+// the column; value: the row in the high word, the slot in the low word), sorted, are R's
+// entries row by row with the columns (P's rows) ascending, so they are placed without
+// atomics and without a per-row ranking.
+__global__ void k_tr_entries(SellV P, const int32_t* __restrict__ roff, uint32_t* __restrict__ key,
+                             uint64_t* __restrict__ ent) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= P.n_rows) return;
+    const int n = P.len[r];
+    const int64_t b = roff[r];
+    for (int k = 0; k < n; ++k) {
+        const int64_t ps = sslot(P.sp, P.C, r, k);
+        key[b + k] = uint32_t(P.col[ps]);
+        ent[b + k] = (uint64_t(uint32_t(r)) << 32) | uint64_t(uint32_t(ps));
+    }
+}
+
+// Row a of R holds the sorted entries [start[a], start[a] + len[a]) (lower bounds in the
+// sorted keys)
+__global__ void k_tr_bounds(const uint32_t* __restrict__ key, int64_t nnz, int64_t n_rows, int32_t* __restrict__ start,
+                            int32_t* __restrict__ len) {
+    const int64_t a = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (a >= n_rows) return;
+    auto lower = [&](uint32_t v) {
+        int64_t lo = 0, hi = nnz;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (key[mid] < v) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+    const int64_t b = lower(uint32_t(a)), e = lower(uint32_t(a) + 1u);
+    start[a] = int32_t(b);
+    len[a] = int32_t(e - b);
+}
+
+template <int BR, int BC>
+__global__ void k_tr_place(const uint32_t* __restrict__ key, const uint64_t* __restrict__ ent, int64_t nnz,
+                           const int32_t* __restrict__ start, const double* __restrict__ pv, SellV Rm,
+                           int32_t* __restrict__ rcol, double* __restrict__ rv) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= nnz) return;
+    const int64_t a = key[t];
+    const uint64_t e = ent[t];
+    const int64_t ps = int64_t(uint32_t(e));
+    const int64_t rs = sslot(Rm.sp, Rm.C, a, int(t - start[a]));
+    rcol[rs] = int32_t(e >> 32);
+    for (int i = 0; i < BR; ++i)
+        for (int j = 0; j < BC; ++j) rv[rs * (BR * BC) + j * BR + i] = pv[ps * (BR * BC) + i * BC + j];
+}
+
+// padding slots of R's rows repeat the row's smallest column (0 in an empty row) with zero blocks
+__global__ void k_tr_pad(const uint64_t* __restrict__ ent, const int32_t* __restrict__ start, SellV Rm,
+                         int32_t* __restrict__ rcol, double* __restrict__ rv, int bb) {
+    const int64_t a = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (a >= Rm.n_rows) return;
+    const int n = Rm.len[a];
+    const int64_t s0 = a / Rm.C;
+    const int width = (Rm.sp[s0 + 1] - Rm.sp[s0]) / Rm.C;
+    const int32_t f = n > 0 ? int32_t(ent[start[a]] >> 32) : 0;
+    for (int k = n; k < width; ++k) {
+        const int64_t rs = sslot(Rm.sp, Rm.C, a, k);
+        rcol[rs] = f;
+        for (int b = 0; b < bb; ++b) rv[rs * bb + b] = 0.0;
     }
 }
 
@@ -1441,32 +1445,60 @@ void transpose_values(const BMat<double>& P, BMat<double>& Rm, hipStream_t s) {
 }
 
 BMat<double> transpose(const BMat<double>& P, hipStream_t s) {
+    const SellStruct& PS = *P.S;
+    if (PS.n_rows >= (int64_t(1) << 31) || PS.n_slots >= (int64_t(1) << 31) || PS.nnz >= (int64_t(1) << 31))
+        fail(FR_EINTERNAL, "transpose: more than 2^31 rows, slots or entries");
     BMat<double> Rm;
     Rm.br = P.bc;
     Rm.bc = P.br;
     Rm.S = new_struct(P.cols(), P.rows(), s);
-    FR_HIP(hipMemsetAsync(Rm.S->row_len, 0, size_t(std::max<int64_t>(1, P.cols())) * sizeof(int32_t), s));
-    k_col_count<<<nblk(P.rows(), 256), 256, 0, s>>>(sv(*P.S), Rm.S->row_len);
-    FR_LAUNCH_CHECK();
+    const int64_t nnz = PS.nnz, nr = P.cols();
+    const size_t ne = size_t(std::max<int64_t>(1, nnz));
+    DBuf<int32_t> roff, start;
+    DBuf<uint32_t> key[2];
+    DBuf<uint64_t> ent[2];
+    roff.alloc(size_t(P.rows()) + 1, s);
+    scan_exclusive_async(PS.row_len, roff.p, P.rows(), s);
+    for (int i = 0; i < 2; ++i) {
+        key[i].alloc(ne, s);
+        ent[i].alloc(ne, s);
+    }
+    if (P.rows() > 0) {
+        k_tr_entries<<<nblk(P.rows(), 256), 256, 0, s>>>(sv(PS), roff.p, key[0].p, ent[0].p);
+        FR_LAUNCH_CHECK();
+    }
+    // keys below the number of R's rows: only their bits are sorted
+    int bits = 1;
+    while (bits < 32 && (int64_t(1) << bits) < nr) ++bits;
+    size_t tmp_bytes = 0;
+    FR_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, key[0].p, key[1].p, ent[0].p, ent[1].p, int(nnz), 0,
+                                             bits, s));
+    DBuf<char> tmp;
+    tmp.alloc(std::max<size_t>(1, tmp_bytes), s);
+    if (nnz > 0)
+        FR_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tmp_bytes, key[0].p, key[1].p, ent[0].p, ent[1].p, int(nnz), 0,
+                                                 bits, s));
+    start.alloc(size_t(std::max<int64_t>(1, nr)), s);
+    if (nr > 0) {
+        k_tr_bounds<<<nblk(nr, 256), 256, 0, s>>>(key[1].p, nnz, nr, start.p, Rm.S->row_len);
+        FR_LAUNCH_CHECK();
+    }
     finish_struct(*Rm.S, s);
     const size_t nvals = size_t(std::max<int64_t>(1, Rm.S->n_slots)) * Rm.br * Rm.bc;
     Rm.own_val.alloc(nvals, s);
     Rm.val = Rm.own_val.p;
-    DBuf<int32_t> fillc, tcol;
-    DBuf<double> tval;
-    fillc.alloc(size_t(std::max<int64_t>(1, P.cols())), s);
-    fillc.zero(s);
-    tcol.alloc(size_t(std::max<int64_t>(1, Rm.S->n_slots)), s);
-    tval.alloc(nvals, s);
-    const int g = nblk(P.rows(), 256);
-    const int gr = nblk(Rm.rows(), kWavesPerBlock);
-#define FR_TR_CASE(BR_, BC_)                                                                                    \
-    if (P.br == BR_ && P.bc == BC_) {                                                                           \
-        k_transpose_fill<BR_, BC_><<<g, 256, 0, s>>>(sv(*P.S), P.val, sv(*Rm.S), fillc.p, tcol.p, tval.p);      \
-        FR_LAUNCH_CHECK();                                                                                      \
-        k_rank_rows<BR_ * BC_><<<gr, 256, 0, s>>>(sv(*Rm.S), tcol.p, tval.p, Rm.S->col, Rm.val);                \
-        FR_LAUNCH_CHECK();                                                                                      \
-        return Rm;                                                                                              \
+#define FR_TR_CASE(BR_, BC_)                                                                                     \
+    if (P.br == BR_ && P.bc == BC_) {                                                                            \
+        if (nnz > 0) {                                                                                           \
+            k_tr_place<BR_, BC_><<<nblk(nnz, 256), 256, 0, s>>>(key[1].p, ent[1].p, nnz, start.p, P.val, sv(*Rm.S), \
+                                                                Rm.S->col, Rm.val);                              \
+            FR_LAUNCH_CHECK();                                                                                   \
+        }                                                                                                        \
+        if (nr > 0) {                                                                                            \
+            k_tr_pad<<<nblk(nr, 256), 256, 0, s>>>(ent[1].p, start.p, sv(*Rm.S), Rm.S->col, Rm.val, BR_ * BC_);  \
+            FR_LAUNCH_CHECK();                                                                                   \
+        }                                                                                                        \
+        return Rm;                                                                                               \
     }
     FR_TR_CASE(1, 1)
     FR_TR_CASE(2, 3)
