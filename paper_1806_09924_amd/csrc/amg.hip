@@ -230,30 +230,14 @@ __global__ void k_orphan_assign(int64_t n, const int32_t* __restrict__ flag, con
     if (i < n && flag[i]) agg[i] = base + rank[i];
 }
 
-__global__ void k_agg_count(int64_t n, const int32_t* __restrict__ agg, int32_t* __restrict__ cnt) {
+// Aggregate member lists by a stable sort of the nodes by aggregate (nodes of no aggregate
+// take the key n_agg and sort last): each list comes out in increasing node order.
+__global__ void k_agg_keys(int64_t n, const int32_t* __restrict__ agg, int64_t n_agg, uint32_t* __restrict__ key,
+                           int32_t* __restrict__ node) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n && agg[i] >= 0) atomicAdd(&cnt[agg[i]], 1);
-}
-
-__global__ void k_agg_fill(int64_t n, const int32_t* __restrict__ agg, const int32_t* __restrict__ ptr,
-                           int32_t* __restrict__ fillc, int32_t* __restrict__ nodes) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n && agg[i] >= 0) {
-        const int32_t p = atomicAdd(&fillc[agg[i]], 1);
-        nodes[ptr[agg[i]] + p] = int32_t(i);
-    }
-}
-
-__global__ void k_agg_sort(int64_t na, const int32_t* __restrict__ ptr, int32_t* __restrict__ nodes) {
-    const int64_t a = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (a >= na) return;
-    const int32_t b = ptr[a], e = ptr[a + 1];
-    for (int32_t i = b + 1; i < e; ++i) {
-        const int32_t v = nodes[i];
-        int32_t j = i - 1;
-        while (j >= b && nodes[j] > v) { nodes[j + 1] = nodes[j]; --j; }
-        nodes[j + 1] = v;
-    }
+    if (i >= n) return;
+    key[i] = uint32_t(agg[i] >= 0 ? agg[i] : n_agg);
+    node[i] = int32_t(i);
 }
 
 // ---- tentative prolongator ----------------------------------------------------------------
@@ -623,15 +607,28 @@ __global__ void __launch_bounds__(256) k_spgemm_bitmap(SellV A, SellV B, SellV C
     for (int k = total + t; k < width; k += nt) ccol[sslot(Cm.sp, Cm.C, r, k)] = f;
 }
 
+// Where the one block of each row of B sits (bslot, -1 for an empty row) and its column
+// (bcol, -1): the one-block-per-row products then reach B's block in one step from A's column.
+__global__ void k_single_index(SellV B, int64_t* __restrict__ bslot, int32_t* __restrict__ bcol) {
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= B.n_rows) return;
+    const bool has = B.len[k] > 0;
+    const int64_t bs = has ? sslot(B.sp, B.C, k, 0) : -1;
+    bslot[k] = bs;
+    bcol[k] = has ? B.col[bs] : -1;
+}
+
 // Symbolic phase of A B when every row of B has at most one block (a tentative prolongator):
-// the columns of row r are the distinct B columns of the rows A's row r touches.  G lanes
+// the columns of row r are the distinct B columns of the rows A's row r touches (bcol[k]: the
+// column of B's row k, -1 when the row is empty).  G lanes
 // per row (G >= the longest row of A), lane g takes entry g; the group sorts its values by a
 // bitonic network over lanes, marks the first of each run of equal values and places it by a
 // prefix count.  fill == false: row lengths to clen; fill == true: sorted columns (padding
 // repeats the smallest) to ccol.
 template <int G>
-__global__ void __launch_bounds__(256) k_spgemm_single(SellV A, SellV B, SellV Cm, int32_t* __restrict__ clen,
-                                                       int32_t* __restrict__ ccol, int fill) {
+__global__ void __launch_bounds__(256) k_spgemm_single(SellV A, const int32_t* __restrict__ bcol, SellV Cm,
+                                                       int32_t* __restrict__ clen, int32_t* __restrict__ ccol,
+                                                       int fill) {
     constexpr int RPW = kWave / G;
     constexpr int32_t kNone = 0x7fffffff;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, gi = lane / G, lg = lane % G;
@@ -640,8 +637,8 @@ __global__ void __launch_bounds__(256) k_spgemm_single(SellV A, SellV B, SellV C
     const int la = row_ok ? A.len[r] : 0;
     int32_t v = kNone;
     if (lg < la) {
-        const int64_t k = A.col[sslot(A.sp, A.C, r, lg)];
-        if (B.len[k] > 0) v = B.col[sslot(B.sp, B.C, k, 0)];
+        const int32_t c = bcol[A.col[sslot(A.sp, A.C, r, lg)]];
+        if (c >= 0) v = c;
     }
     // ascending bitonic sort of the group's G values
 #pragma unroll
@@ -776,8 +773,9 @@ __global__ void k_tr_entries(SellV P, const int32_t* __restrict__ roff, uint32_t
     }
 }
 
-// Row a of R holds the sorted entries [start[a], start[a] + len[a]) (lower bounds in the
-// sorted keys)
+// Lower bounds in sorted keys: start[a] = the first position whose key is >= a, and len[a]
+// (when asked for) the number of keys equal to a.  Row a of R holds the sorted entries
+// [start[a], start[a] + len[a]).
 __global__ void k_tr_bounds(const uint32_t* __restrict__ key, int64_t nnz, int64_t n_rows, int32_t* __restrict__ start,
                             int32_t* __restrict__ len) {
     const int64_t a = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -793,7 +791,7 @@ __global__ void k_tr_bounds(const uint32_t* __restrict__ key, int64_t nnz, int64
     };
     const int64_t b = lower(uint32_t(a)), e = lower(uint32_t(a) + 1u);
     start[a] = int32_t(b);
-    len[a] = int32_t(e - b);
+    if (len) len[a] = int32_t(e - b);
 }
 
 template <int BR, int BC>
@@ -1042,7 +1040,9 @@ __device__ __forceinline__ int32_t group_read(int32_t x, int base, int t) {
 }
 
 template <int BRA, int BCA, int BCB, int MODE, int G>
-__global__ void __launch_bounds__(256) k_spgemm_numeric_single(SellV A, const double* __restrict__ av, SellV B,
+__global__ void __launch_bounds__(256) k_spgemm_numeric_single(SellV A, const double* __restrict__ av,
+                                                               const int64_t* __restrict__ bslot,
+                                                               const int32_t* __restrict__ bcol,
                                                                const double* __restrict__ bv, SellV Cm,
                                                                double* __restrict__ cv,
                                                                const double* __restrict__ invd, double omega) {
@@ -1076,9 +1076,9 @@ __global__ void __launch_bounds__(256) k_spgemm_numeric_single(SellV A, const do
             if (j < la) {
                 const int64_t as = sslot(A.sp, A.C, r, j);
                 const int64_t k = A.col[as];
-                if (B.len[k] > 0) {
-                    const int64_t bs = sslot(B.sp, B.C, k, 0);
-                    cj = B.col[bs];
+                const int64_t bs = bslot[k];
+                if (bs >= 0) {
+                    cj = bcol[k];
                     const double* ab = av + as * (BRA * BCA);
                     const double* bb = bv + bs * (BCA * BCB);
 #pragma unroll
@@ -1110,9 +1110,9 @@ __global__ void __launch_bounds__(256) k_spgemm_numeric_single(SellV A, const do
                     double ob[BB];
 #pragma unroll
                     for (int e = 0; e < BB; ++e) ob[e] = 0.0;
-                    if (B.len[r] > 0) {
-                        const int64_t os = sslot(B.sp, B.C, r, 0);
-                        if (B.col[os] == c) {
+                    const int64_t os = bslot[r];
+                    if (os >= 0) {
+                        if (bcol[r] == c) {
 #pragma unroll
                             for (int e = 0; e < BB; ++e) ob[e] = bv[os * BB + e];
                         }
@@ -1202,6 +1202,15 @@ __global__ void __launch_bounds__(256) k_spgemm_dense_row(SellV A, const double*
     }
 }
 
+static void single_index(const BMat<double>& B, DBuf<int64_t>& bslot, DBuf<int32_t>& bcol, hipStream_t s) {
+    const int64_t nb = B.rows();
+    bslot.alloc(size_t(std::max<int64_t>(1, nb)), s);
+    bcol.alloc(size_t(std::max<int64_t>(1, nb)), s);
+    if (nb == 0) return;
+    k_single_index<<<nblk(nb, 256), 256, 0, s>>>(sv(*B.S), bslot.p, bcol.p);
+    FR_LAUNCH_CHECK();
+}
+
 template <int BRA, int BCA, int BCB, int MODE>
 void spgemm_numeric(const BMat<double>& A, const BMat<double>& B, BMat<double>& Cm, const double* invd, double omega,
                     hipStream_t s) {
@@ -1215,9 +1224,12 @@ void spgemm_numeric(const BMat<double>& A, const BMat<double>& B, BMat<double>& 
         // B with one block per row: G lanes per row by A's mean row length (a wave for the
         // long 3d / coarse rows, 16 or 8 lanes for 2d rows)
         const int64_t avg_a = A.S->nnz / std::max<int64_t>(1, rows);
+        DBuf<int64_t> bslot;
+        DBuf<int32_t> bcol;
+        single_index(B, bslot, bcol, s);
 #define FR_NSINGLE(G_)                                                                                 \
     k_spgemm_numeric_single<BRA, BCA, BCB, MODE, G_><<<nblk(rows, kWavesPerBlock * (kWave / G_)), 256, 0, s>>>( \
-        sv(*A.S), A.val, sv(*B.S), B.val, sv(*Cm.S), Cm.val, invd, omega);
+        sv(*A.S), A.val, bslot.p, bcol.p, B.val, sv(*Cm.S), Cm.val, invd, omega);
         if (avg_a >= 16) { FR_NSINGLE(64) }
         else if (avg_a > 8) { FR_NSINGLE(16) }
         else { FR_NSINGLE(8) }
@@ -1337,11 +1349,14 @@ BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* 
     ovf.zero(s);
     if (B.S->max_len <= 1 && A.S->max_len <= kWave) {
         // B has one block per row: columns by lane ranking, no hash sets
+        DBuf<int64_t> bslot;
+        DBuf<int32_t> bcol;
+        single_index(B, bslot, bcol, s);
         int G = 8;
         while (G < A.S->max_len) G <<= 1;
         const int g = nblk(std::max<int64_t>(1, A.rows()), kWavesPerBlock * (kWave / G));
 #define FR_SINGLE(G_, FILL_)                                                                              \
-        k_spgemm_single<G_><<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), sv(*Cm.S), Cm.S->row_len, Cm.S->col, FILL_);
+        k_spgemm_single<G_><<<g, 256, 0, s>>>(sv(*A.S), bcol.p, sv(*Cm.S), Cm.S->row_len, Cm.S->col, FILL_);
 #define FR_SINGLE_ALL(FILL_)                                                                              \
         switch (G) {                                                                                      \
             case 8: FR_SINGLE(8, FILL_) break;                                                            \
@@ -1652,20 +1667,31 @@ static BMat<double> tentative(const BMat<double>& A, const DBuf<int32_t>& agg, i
     P.val = P.own_val.p;
     k_ptent_cols<<<nblk(n, 256), 256, 0, s>>>(n, P.S->C, P.S->slice_ptr, agg.p, P.S->col, P.val, br * ns);
     FR_LAUNCH_CHECK();
-    // aggregate member lists
-    DBuf<int32_t> cnt, ptr, fillc, nodes;
-    cnt.alloc(size_t(n_agg) + 1, s);
+    // aggregate member lists: nodes[ptr[a] .. ptr[a + 1]) are aggregate a's, ascending
+    if (n >= (int64_t(1) << 31)) fail(FR_EINTERNAL, "tentative: more than 2^31 rows");
+    DBuf<int32_t> ptr, nodes, node_in;
+    DBuf<uint32_t> key[2];
+    const size_t nn = size_t(std::max<int64_t>(1, n));
     ptr.alloc(size_t(n_agg) + 1, s);
-    fillc.alloc(size_t(n_agg) + 1, s);
-    nodes.alloc(size_t(std::max<int64_t>(1, n)), s);
-    cnt.zero(s);
-    fillc.zero(s);
-    k_agg_count<<<nblk(n, 256), 256, 0, s>>>(n, agg.p, cnt.p);
-    FR_LAUNCH_CHECK();
-    scan_exclusive_async(cnt.p, ptr.p, n_agg, s);
-    k_agg_fill<<<nblk(n, 256), 256, 0, s>>>(n, agg.p, ptr.p, fillc.p, nodes.p);
-    FR_LAUNCH_CHECK();
-    k_agg_sort<<<nblk(n_agg, 256), 256, 0, s>>>(n_agg, ptr.p, nodes.p);
+    nodes.alloc(nn, s);
+    node_in.alloc(nn, s);
+    key[0].alloc(nn, s);
+    key[1].alloc(nn, s);
+    if (n > 0) {
+        k_agg_keys<<<nblk(n, 256), 256, 0, s>>>(n, agg.p, n_agg, key[0].p, node_in.p);
+        FR_LAUNCH_CHECK();
+    }
+    int bits = 1;
+    while (bits < 32 && (int64_t(1) << bits) <= n_agg) ++bits;
+    size_t tmp_bytes = 0;
+    FR_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, key[0].p, key[1].p, node_in.p, nodes.p, int(n), 0,
+                                             bits, s));
+    DBuf<char> tmp;
+    tmp.alloc(std::max<size_t>(1, tmp_bytes), s);
+    if (n > 0)
+        FR_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tmp_bytes, key[0].p, key[1].p, node_in.p, nodes.p, int(n), 0,
+                                                 bits, s));
+    k_tr_bounds<<<nblk(n_agg + 1, 256), 256, 0, s>>>(key[1].p, n, n_agg + 1, ptr.p, nullptr);
     FR_LAUNCH_CHECK();
     Bc.alloc(size_t(std::max<int64_t>(1, n_agg)) * ns * ns, s);
     double* ainfo = nullptr;
