@@ -1377,8 +1377,8 @@ BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* 
     }
     const int64_t avg_b = B.S->nnz / std::max<int64_t>(1, B.rows());
     const int n_words = int(ceil_div(std::max<int64_t>(1, B.cols()), 32));
-    if (avg_b >= 64 && n_words <= 8192 && A.rows() > 0) {
-        // long rows of B over few columns: a workgroup per row with a column bitmap
+    auto bitmap_product = [&]() {
+        // a workgroup per row with a column bitmap over all of C's columns
         const int g = int(A.rows());
         const size_t lds = size_t(n_words) * sizeof(uint32_t);
         k_spgemm_bitmap<false><<<g, 256, lds, s>>>(sv(*A.S), sv(*B.S), sv(*Cm.S), Cm.S->row_len, nullptr, n_words);
@@ -1389,6 +1389,10 @@ BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* 
         Cm.own_val.alloc(size_t(std::max<int64_t>(1, Cm.S->n_slots)) * Cm.br * Cm.bc, s);
         Cm.val = Cm.own_val.p;
         spgemm_values<MODE>(A, B, Cm, invd, omega, s);
+    };
+    if (avg_b >= 64 && n_words <= 8192 && A.rows() > 0) {
+        // long rows of B over few columns
+        bitmap_product();
         return Cm;
     }
     // small hash sets first (8 rows per wave: 32 slots for the short rows of the finest level's
@@ -1419,7 +1423,12 @@ BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* 
         ovf.zero(s);
         spgemm_symbolic<64, 4096>(A, B, Cm, ovf.p, s, false);
         layout_from_lengths(*Cm.S, s, ovf.p, &over);
-        if (over) fail(FR_EINTERNAL, "spgemm: a row of the product has more than 3072 block columns");
+        if (over) {
+            // rows beyond the largest hash set: the column bitmap, when C's columns fit in LDS
+            if (n_words > 8192) fail(FR_EINTERNAL, "spgemm: a row of the product has more than 3072 block columns");
+            bitmap_product();
+            return Cm;
+        }
     }
     Cm.S->own_col.alloc(size_t(std::max<int64_t>(1, Cm.S->n_slots)), s);
     Cm.S->col = Cm.S->own_col.p;

@@ -56,3 +56,30 @@ def test_convergence_3d_quasistatic_refs_7_to_10():
     errs = [r["rel_error"] for r in rows + out10["rows"]]
     assert all(a > b for a, b in zip(errs, errs[1:]))
     assert errs[-1] <= 0.02
+
+
+def test_convergence_3d_ref_11_at_the_table_size():
+    """Ref 11 (h_min = 10/2048) with the refinement radius cut to 0.12 so that the mesh has the
+    table's size (34.8 M DoFs against 30.3 M; radius 0.4 would need about 4x that, beyond one
+    GPU's memory for the 3d hierarchy).  The eps column and the table's TCV within 3 % hold and
+    the phase field is stationary; the error against Sneddon is -1.3 % here, below the table's
+    +0.72 %: with the mesh coarsened 0.12 away from the crack the far field's discretisation
+    error (which lowers the TCV) outweighs the eps error at this size (ref 10 with radius 0.4:
+    +0.4 %).  The device pool is handed back at the end."""
+    tab = _table()
+    try:
+        out = studies.convergence_3d((11,), refine_radius=0.12, precision=32, steps=STEPS)
+        (r,) = out["rows"]
+        t = tab[11]
+        assert r["ten_l0_over_h"] == t["ten_l0_over_h"]
+        assert abs(r["eps"] / t["eps"] - 1) < 1e-4
+        assert abs(r["n_dofs"] / t["dofs"] - 1) <= 0.20
+        assert abs(r["tcv"] / t["tcv"] - 1) <= 0.03, (r["tcv"], t["tcv"])
+        assert abs(r["rel_error"]) <= 0.02
+        ts = r["tcv_steps"]
+        assert abs(ts[-1] / ts[-2] - 1) <= 1e-8
+    finally:
+        import gc
+        from paper_1806_09924_amd import binding as B
+        gc.collect()
+        B.trim_pool()
