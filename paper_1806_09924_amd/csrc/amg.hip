@@ -1932,11 +1932,18 @@ static void refresh_hierarchy(Hierarchy& H, double* a0, const fr_amg_opts& o, hi
                               const MfState* mf0 = nullptr, int blk = 0) {
     const size_t nl = H.lv.size();
     H.lv[0]->A.val = a0;
+    // refresh_phi 2: the finest level's diagonal and lambda_max only (coarse levels and the
+    // transfers stay those of the build: a lagged preconditioner)
+    const bool fine_only = o.refresh_phi == 2;
     for (size_t l = 0; l < nl; ++l) {
         AmgLevel& L = *H.lv[l];
         DBuf<double> dnorm;
         diag_info(L.A, L.invd, dnorm, s);
         L.lmax = lambda_max(L.A, L.invd.p, s, l == 0 ? mf0 : nullptr, blk);
+        if (fine_only) {
+            if (o.precision == 32) make_f32(L, nl == 1, s);
+            return;
+        }
         if (l + 1 == nl) break;
         const double omega = 4.0 / (3.0 * L.lmax);
         spgemm_values<1>(L.A, L.Pt, L.P, L.invd.p, omega, s);

@@ -101,7 +101,7 @@ fr_amg_opts default_amg() {
     o.coarse_max = 96;
     o.max_levels = 10;
     o.reuse_u_block = 1;
-    o.refresh_phi = 1;
+    o.refresh_phi = 2;
     o.autotune = 1;
     o.fine_matrix_free = 7;
     return o;
@@ -115,6 +115,7 @@ fr_status check_amg(const fr_amg_opts& o) {
     FR_REQUIRE(o.coarse_max >= 1 && o.coarse_max <= 4096, "amg: coarse_max must be in [1, 4096]");
     FR_REQUIRE(o.max_levels >= 1 && o.max_levels <= 30, "amg: max_levels must be in [1, 30]");
     FR_REQUIRE(o.fine_matrix_free >= 0 && o.fine_matrix_free <= 7, "amg: fine_matrix_free must be in [0, 7]");
+    FR_REQUIRE(o.refresh_phi >= 0 && o.refresh_phi <= 2, "amg: refresh_phi must be 0, 1 or 2");
     return FR_OK;
 }
 

@@ -204,6 +204,39 @@ def test_amg_phase_field_refresh(precision):
     assert its[0] <= its[1] + 4
 
 
+def test_amg_phase_field_lagged_refresh():
+    """refresh_phi = 2 (the default): on a new Jacobian the phase-field hierarchy keeps every
+    coarse level and transfer of its build bit for bit, takes the finest level's new values and
+    recomputes that level's lambda_max, and still solves to the 1e-8 residual."""
+    P = Problem(2, 2.0, 64)
+    S = _gpu_system(P)
+    opts = B.amg_opts(precision=64, refresh_phi=2)
+    A = B.Amg(S, opts)
+    nl = A.n_levels(1)
+    before = {(lev, w): A.level_csr(1, lev, w) for lev in range(nl) for w in ((0, 1, 2) if lev + 1 < nl else (0,))}
+    lmax0 = A.level_info(1, 0)["lambda_max"]
+    u0, phi0, po, pt = P.state
+    rng = np.random.default_rng(5)
+    u2 = 1e-3 * rng.standard_normal(u0.shape)
+    u2[P.omesh.dirichlet] = 0.0
+    phi2 = np.clip(phi0 - rng.uniform(0.0, 0.05, phi0.shape), 0.0, 1.0)
+    o = _oracle_system(P, u=u2, phi=phi2)
+    S.assemble(P.prm, dev(u2), dev(phi2), dev(po), dev(pt))
+    S.set_active(torch.as_tensor(o.active.astype(np.uint8), device="cuda"))
+    S.assemble(P.prm, dev(u2), dev(phi2), dev(po), dev(pt), flags=B.FR_JACOBIAN)
+    A.setup(opts)
+    assert A.n_levels(1) == nl
+    for (lev, w), (s0, r0, c0, v0) in before.items():
+        s1, r1, c1, v1 = A.level_csr(1, lev, w)
+        same = s0 == s1 and np.array_equal(r0, r1) and np.array_equal(c0, c1) and np.array_equal(v0, v1)
+        assert same == (lev > 0 or w > 0), (lev, w)          # only level 0's A changed
+    assert A.level_info(1, 0)["lambda_max"] != lmax0
+    du = torch.empty(P.mesh.n_solve, dtype=torch.float64, device="cuda")
+    st = B.solve(S, A, du, B.solve_opts(rtol=1e-8))
+    assert np.linalg.norm(o.F - o.Jm @ host(du)) / np.linalg.norm(o.F) <= 1.01e-8
+    assert st["iters"] <= 40
+
+
 def test_vcycle_is_linear_and_symmetric():
     P = Problem(2, 2.0, 64)
     S = _gpu_system(P)
