@@ -10,6 +10,7 @@
 #include <atomic>
 #include <cmath>
 #include <exception>
+#include <functional>
 #include <string>
 #include <thread>
 #include <type_traits>
@@ -1600,7 +1601,10 @@ static void diag_info(const BMat<double>& A, DBuf<double>& invd, DBuf<double>& d
 }
 
 // Aggregation of the block rows of A; returns the number of aggregates, agg[n] (-1 = none).
-static int64_t aggregate(const BMat<double>& A, const double* dnorm, double theta, DBuf<int32_t>& agg, hipStream_t s) {
+// `before_wait` (may be empty) is called once, after the first round is enqueued and before
+// the host first waits for the stream: work the caller enqueues there overlaps the rounds.
+static int64_t aggregate(const BMat<double>& A, const double* dnorm, double theta, DBuf<int32_t>& agg, hipStream_t s,
+                         const std::function<void()>& before_wait = {}) {
     const SellStruct& S = *A.S;
     const int64_t n = S.n_rows;
     const int g = nblk(n, 256);
@@ -1633,6 +1637,7 @@ static int64_t aggregate(const BMat<double>& A, const double* dnorm, double thet
         k_mis_prop_update<<<g, 256, 0, s>>>(n, S.C, S.slice_ptr, S.col, strong.p, m1.p, state.p, key.p,
                                              check ? und.p : nullptr);
         FR_LAUNCH_CHECK();
+        if (check && before_wait && round + 1 == every) before_wait();
         if (check && download1(und.p, s) == 0) break;
         if (round == 239) fail(FR_EINTERNAL, "aggregation: MIS(2) did not terminate");
     }
@@ -1833,15 +1838,21 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
             ProfScope ps(nm_lambda.c_str(), s, 0.0);
             diag_info(L->A, L->invd, dnorm, s);
         }
+        // the power iteration waits for the diagonal only; its launches are enqueued on `aux`
+        // while the first aggregation round runs, so the stream is not idle meanwhile
         PowerEst pe;
-        {
-            FR_HIP(hipEventRecord(ev_aux, s));
+        FR_HIP(hipEventRecord(ev_aux, s));
+        bool power_started = false;
+        auto start_power = [&]() {
+            if (power_started) return;
+            power_started = true;
             FR_HIP(hipStreamWaitEvent(aux, ev_aux, 0));
             ProfScope ps(nm_lambda.c_str(), aux, 0.0);
             power_start(pe, L->A, L->invd.p, aux, l == 0 ? mf0 : nullptr, blk);
-        }
+        };
         const int64_t nrows = L->A.rows() * L->A.br;
         const bool last = nrows <= o.coarse_max || l + 1 >= o.max_levels;
+        if (last) start_power();
         if (!last) {
             DBuf<int32_t> agg;
             int64_t n_agg = 0;
@@ -1849,8 +1860,9 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
                 ProfScope ps(nm_agg.c_str(), s, 0.0);
                 // strength threshold: negative selects the measured default per dimension
                 const double theta = o.theta >= 0 ? o.theta : (dim == 2 ? 0.08 : 0.02);
-                n_agg = aggregate(L->A, dnorm.p, theta, agg, s);
+                n_agg = aggregate(L->A, dnorm.p, theta, agg, s, start_power);
             }
+            start_power();   // aggregation without a host wait in its rounds
             if (n_agg == 0 || n_agg * ns >= nrows) {
                 L->lmax = power_finish(pe);
                 H.lv.push_back(std::move(L));
