@@ -100,12 +100,17 @@ struct DBuf {
     }
 };
 
+// Waits until everything enqueued on s so far has finished, by polling an event: the setup
+// reads many small results back (sizes, counts), and a blocking synchronise can take tens of
+// microseconds to wake the host after the device is done.
+void stream_wait(hipStream_t s);
+
 template <typename T>
 std::vector<T> download(const T* d, size_t n, hipStream_t s) {
     std::vector<T> h(n);
     if (n) {
         FR_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
-        FR_HIP(hipStreamSynchronize(s));
+        stream_wait(s);
     }
     return h;
 }
@@ -114,7 +119,7 @@ template <typename T>
 T download1(const T* d, hipStream_t s) {
     T v{};
     FR_HIP(hipMemcpyAsync(&v, d, sizeof(T), hipMemcpyDeviceToHost, s));
-    FR_HIP(hipStreamSynchronize(s));
+    stream_wait(s);
     return v;
 }
 

@@ -179,6 +179,29 @@ void set_allocator(fr_alloc_fn alloc, fr_free_fn dealloc, void* ctx) {
     c.hook = Hook{alloc, dealloc, ctx};
 }
 
+namespace {
+// one event per host thread (the phase-field setup runs in a thread of its own)
+struct WaitEvent {
+    hipEvent_t e = nullptr;
+    ~WaitEvent() {
+        if (e) (void)hipEventDestroy(e);
+    }
+};
+}  // namespace
+
+void stream_wait(hipStream_t s) {
+    thread_local WaitEvent w;
+    if (!w.e) FR_HIP(hipEventCreateWithFlags(&w.e, hipEventDisableTiming));
+    FR_HIP(hipEventRecord(w.e, s));
+    for (;;) {
+        const hipError_t q = hipEventQuery(w.e);
+        if (q == hipSuccess) break;
+        if (q != hipErrorNotReady) FR_HIP(q);
+    }
+    // the not-ready answers must not linger as the thread's last error (launch checks read it)
+    (void)hipGetLastError();
+}
+
 void forget_stream(hipStream_t s) {
     Cache& c = cache();
     int dev = 0;
