@@ -780,26 +780,25 @@ __global__ void __launch_bounds__(256) k_mf_restrict(MfGrid g, const T* __restri
                                                      const T* __restrict__ r_in, T omega, T* __restrict__ s_out) {
     const WaveStrip ws = wave_strip(g);
     if (!ws.valid) return;
-    auto ld = [&](int64_t j, T& p, T (&v)[2]) {
+    // per row: phi_tilde, r and D^-1 r (r is kept for the row's output, not loaded again)
+    auto ld = [&](int64_t j, T& p, T (&rr)[2], T (&v)[2]) {
         const bool in = ws.col_in && row_in(g, j);
         const int64_t r = ws.col + j * g.n1;
         p = in ? pt[r] : T(0);
-        v[0] = in ? invd[2 * r] * r_in[2 * r] : T(0);
-        v[1] = in ? invd[2 * r + 1] * r_in[2 * r + 1] : T(0);
+        rr[0] = in ? r_in[2 * r] : T(0);
+        rr[1] = in ? r_in[2 * r + 1] : T(0);
+        v[0] = in ? invd[2 * r] * rr[0] : T(0);
+        v[1] = in ? invd[2 * r + 1] * rr[1] : T(0);
     };
-    T pB, pT, vB[2], vT[2], c2[2] = {T(0), T(0)}, c3[2] = {T(0), T(0)};
-    ld(ws.j0 - 1, pB, vB);
-    ld(ws.j0, pT, vT);
+    T pB, pT, rB[2], rT[2], vB[2], vT[2], c2[2] = {T(0), T(0)}, c3[2] = {T(0), T(0)};
+    ld(ws.j0 - 1, pB, rB, vB);
+    ld(ws.j0, pT, rT, vT);
     for (int64_t j = ws.j0 - 1; j < ws.j1; ++j) {
-        T pN, vN[2];
-        ld(j + 2, pN, vN);
+        T pN, rN[2], vN[2];
+        ld(j + 2, pN, rN, vN);
         const bool wr = ws.writer && j >= ws.j0;
         const int64_t r = ws.col + j * g.n1;
-        T ro[2] = {T(0), T(0)};
-        if (wr) {
-            ro[0] = r_in[2 * r];
-            ro[1] = r_in[2 * r + 1];
-        }
+        const T ro[2] = {rB[0], rB[1]};
         T y[2], Hx[2][2], Hy[2][2];
         masked_grad<T>(g, ws, j, vB, vT, Hx, Hy);
         u_rows<T>(g, ws, j, Hx, Hy, pB, pT, c2, c3, y);
@@ -812,6 +811,8 @@ __global__ void __launch_bounds__(256) k_mf_restrict(MfGrid g, const T* __restri
         pT = pN;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
+            rB[c] = rT[c];
+            rT[c] = rN[c];
             vB[c] = vT[c];
             vT[c] = vN[c];
         }
