@@ -1755,7 +1755,9 @@ static void make_f32(AmgLevel& L, bool coarsest, hipStream_t s) {
         cast_f64_f32(a.val, b.val, nv, s);
     };
     cp(L.A, L.A32);
-    if (!coarsest) {
+    // a level with matrix-free transfers (L.mt) keeps its stored P and R for the Galerkin
+    // product only: no FP32 copies
+    if (!coarsest && !L.mt) {
         cp(L.P, L.P32);
         cp(L.R, L.R32);
     }
@@ -1927,6 +1929,7 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
             AmgLevel& L = *H.lv[l];
             const bool f32 = o.precision == 32;
             if (l > 0) tune_layout(L.A, 0, f32, s);
+            if (L.mt) continue;   // its transfers are matrix-free: P and R are not launched
             tune_layout(L.R, 1, f32, s);
             tune_layout(L.P, 2, f32, s);
         }
