@@ -49,7 +49,8 @@ def log(msg):
 
 PROFILE_OF = {"cheb_f64_b2_l0": "cheb_f64_b2_sneddon2d_2048.md", "cheb_f64_b2_i16_l0": "cheb_f64_b2_sneddon2d_2048.md",
               "mf_cheb_f64": "mf_cheb_f64_sneddon2d_2048.md", "mf_pcheb_f64": "mf_pcheb_f64_sneddon2d_2048.md",
-              "cheb_f64_b3_g16_l1": "cheb_f64_b3_g16_l1_sneddon2d_2048.md"}
+              "cheb_f64_b3_g16_l1": "cheb_f64_b3_g16_l1_sneddon2d_2048.md",
+              "cheb_f64_b3_g4_l1": "cheb_f64_b3_g4_l1_sneddon2d_2048.md"}
 
 
 def kernel_digest(src_text, kernel):
