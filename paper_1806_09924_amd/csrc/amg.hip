@@ -624,12 +624,11 @@ __global__ void k_single_index(SellV B, int64_t* __restrict__ bslot, int32_t* __
 // column of B's row k, -1 when the row is empty).  G lanes
 // per row (G >= the longest row of A), lane g takes entry g; the group sorts its values by a
 // bitonic network over lanes, marks the first of each run of equal values and places it by a
-// prefix count.  fill == false: row lengths to clen; fill == true: sorted columns (padding
-// repeats the smallest) to ccol.
+// prefix count: row lengths to clen, the sorted columns to stage (G slots per row), which
+// k_single_place moves into C's layout once the layout is known.
 template <int G>
 __global__ void __launch_bounds__(256) k_spgemm_single(SellV A, const int32_t* __restrict__ bcol, SellV Cm,
-                                                       int32_t* __restrict__ clen, int32_t* __restrict__ ccol,
-                                                       int fill) {
+                                                       int32_t* __restrict__ clen, int32_t* __restrict__ stage) {
     constexpr int RPW = kWave / G;
     constexpr int32_t kNone = 0x7fffffff;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, gi = lane / G, lg = lane % G;
@@ -660,16 +659,21 @@ __global__ void __launch_bounds__(256) k_spgemm_single(SellV A, const int32_t* _
         if (lg >= o) pos += t;
     }
     const int count = __shfl(pos, lane - lg + G - 1);
-    const int32_t mn = __shfl(v, lane - lg);
     if (!row_ok) return;
-    if (!fill) {
-        if (lg == 0) clen[r] = count;
-        return;
-    }
-    if (first) ccol[sslot(Cm.sp, Cm.C, r, pos - 1)] = v;
+    if (lg == 0) clen[r] = count;
+    if (first) stage[r * G + pos - 1] = v;
+}
+
+// Moves the sorted columns staged by k_spgemm_single (G per row) into C's layout; padding
+// repeats the smallest column (0 in an empty row).
+__global__ void k_single_place(SellV Cm, int G, const int32_t* __restrict__ stage, int32_t* __restrict__ ccol) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= Cm.n_rows) return;
+    const int n = Cm.len[r];
     const int64_t s0 = r / Cm.C;
     const int width = (Cm.sp[s0 + 1] - Cm.sp[s0]) / Cm.C;
-    for (int k = count + lg; k < width; k += G) ccol[sslot(Cm.sp, Cm.C, r, k)] = count > 0 ? mn : 0;
+    const int32_t f = n > 0 ? stage[r * G] : 0;
+    for (int k = 0; k < width; ++k) ccol[sslot(Cm.sp, Cm.C, r, k)] = k < n ? stage[r * G + k] : f;
 }
 
 __device__ __forceinline__ int find_sorted(const SellV& B, int64_t row, int32_t c) {
@@ -1356,21 +1360,23 @@ BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* 
         int G = 8;
         while (G < A.S->max_len) G <<= 1;
         const int g = nblk(std::max<int64_t>(1, A.rows()), kWavesPerBlock * (kWave / G));
-#define FR_SINGLE(G_, FILL_)                                                                              \
-        k_spgemm_single<G_><<<g, 256, 0, s>>>(sv(*A.S), bcol.p, sv(*Cm.S), Cm.S->row_len, Cm.S->col, FILL_);
-#define FR_SINGLE_ALL(FILL_)                                                                              \
-        switch (G) {                                                                                      \
-            case 8: FR_SINGLE(8, FILL_) break;                                                            \
-            case 16: FR_SINGLE(16, FILL_) break;                                                          \
-            case 32: FR_SINGLE(32, FILL_) break;                                                          \
-            default: FR_SINGLE(64, FILL_) break;                                                          \
-        }                                                                                                 \
-        FR_LAUNCH_CHECK();
-        FR_SINGLE_ALL(0)
-        finish_struct(*Cm.S, s);
-        FR_SINGLE_ALL(1)
-#undef FR_SINGLE_ALL
+        // one pass: row lengths, and each row's sorted columns staged at G per row
+        DBuf<int32_t> stage;
+        stage.alloc(size_t(std::max<int64_t>(1, A.rows())) * G, s);
+#define FR_SINGLE(G_) k_spgemm_single<G_><<<g, 256, 0, s>>>(sv(*A.S), bcol.p, sv(*Cm.S), Cm.S->row_len, stage.p);
+        switch (G) {
+            case 8: FR_SINGLE(8) break;
+            case 16: FR_SINGLE(16) break;
+            case 32: FR_SINGLE(32) break;
+            default: FR_SINGLE(64) break;
+        }
 #undef FR_SINGLE
+        FR_LAUNCH_CHECK();
+        finish_struct(*Cm.S, s);
+        if (A.rows() > 0) {
+            k_single_place<<<nblk(A.rows(), 256), 256, 0, s>>>(sv(*Cm.S), G, stage.p, Cm.S->col);
+            FR_LAUNCH_CHECK();
+        }
         Cm.own_val.alloc(size_t(std::max<int64_t>(1, Cm.S->n_slots)) * Cm.br * Cm.bc, s);
         Cm.val = Cm.own_val.p;
         spgemm_values<MODE>(A, B, Cm, invd, omega, s);
