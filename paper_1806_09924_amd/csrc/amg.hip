@@ -489,20 +489,64 @@ __device__ void spgemm_row_set(const SellV& A, const SellV& B, int64_t r, int32_
     wave_sync();
 }
 
+// With `stage` (HS * 3 / 4 slots per row, the most a row may hold before it overflows), the
+// row's columns are also written there, unordered, so that the fill needs no second pass over
+// A and B (k_spgemm_place).
 template <int G, int HS>
 __global__ void __launch_bounds__(256) k_spgemm_count(SellV A, SellV B, int32_t* __restrict__ clen,
-                                                      int* __restrict__ overflow) {
-    constexpr int RPW = kWave / G;
+                                                      int* __restrict__ overflow, int32_t* __restrict__ stage) {
+    constexpr int RPW = kWave / G, SW = (HS * 3) / 4;
     __shared__ int32_t tab[kWavesPerBlock][RPW * HS];
+    __shared__ int32_t nl[kWavesPerBlock][RPW];
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, gi = lane / G, lg = lane % G;
     const int64_t r = (int64_t(blockIdx.x) * kWavesPerBlock + w) * RPW + gi;
     int added = 0;
-    spgemm_row_set<G, HS>(A, B, r, &tab[w][gi * HS], lg, added, overflow);
+    if (lg == 0) nl[w][gi] = 0;
+    int32_t* mytab = &tab[w][gi * HS];
+    spgemm_row_set<G, HS>(A, B, r, mytab, lg, added, overflow);
     const int tot = group_sum<G>(added);
     if (r < A.n_rows && lg == 0) {
         clen[r] = tot;
-        if (tot > (HS * 3) / 4) atomicOr(overflow, 1);
+        if (tot > SW) atomicOr(overflow, 1);
     }
+    if (stage && r < A.n_rows && tot <= SW) {
+        for (int i = lg; i < HS; i += G) {
+            const int32_t v = mytab[i];
+            if (v >= 0) stage[r * SW + atomicAdd(&nl[w][gi], 1)] = v;
+        }
+    }
+}
+
+// The fill from the staged columns: each row's columns ranked (the set is the count's; the
+// staged order is not, the ranks are), padding repeats the smallest.  G lanes per row, the
+// row's list copied to LDS for the ranking.
+template <int G, int HS>
+__global__ void __launch_bounds__(256) k_spgemm_place(SellV Cm, const int32_t* __restrict__ stage,
+                                                      int32_t* __restrict__ ccol) {
+    constexpr int RPW = kWave / G, SW = (HS * 3) / 4;
+    __shared__ int32_t lst[kWavesPerBlock][RPW * SW];
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, gi = lane / G, lg = lane % G;
+    const int64_t r = (int64_t(blockIdx.x) * kWavesPerBlock + w) * RPW + gi;
+    int32_t* mylst = &lst[w][gi * SW];
+    const int n = r < Cm.n_rows ? Cm.len[r] : 0;
+    for (int i = lg; i < n; i += G) mylst[i] = stage[r * SW + i];
+    wave_sync();
+    if (r >= Cm.n_rows) return;
+    const int64_t s0 = r / Cm.C;
+    const int width = (Cm.sp[s0 + 1] - Cm.sp[s0]) / Cm.C;
+    int32_t first = -1;
+    for (int i = lg; i < n; i += G) {
+        const int32_t v = mylst[i];
+        int rk = 0;
+        for (int j = 0; j < n; ++j) rk += mylst[j] < v;
+        ccol[sslot(Cm.sp, Cm.C, r, rk)] = v;
+        if (rk == 0) first = v;
+    }
+    int32_t f = first;
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) f = max(f, __shfl_xor(f, o));
+    if (f < 0) f = 0;
+    for (int k = n + lg; k < width; k += G) ccol[sslot(Cm.sp, Cm.C, r, k)] = f;
 }
 
 template <int G, int HS>
@@ -1333,9 +1377,10 @@ void spgemm_values(const BMat<double>& A, const BMat<double>& B, BMat<double>& C
 
 template <int G, int HS>
 void spgemm_symbolic(const BMat<double>& A, const BMat<double>& B, BMat<double>& Cm, int* ovf, hipStream_t s,
-                     bool fill) {
+                     bool fill, int32_t* stage = nullptr) {
     const int g = nblk(std::max<int64_t>(1, A.rows()), kWavesPerBlock * (kWave / G));
-    if (!fill) k_spgemm_count<G, HS><<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), Cm.S->row_len, ovf);
+    if (!fill) k_spgemm_count<G, HS><<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), Cm.S->row_len, ovf, stage);
+    else if (stage) k_spgemm_place<G, HS><<<g, 256, 0, s>>>(sv(*Cm.S), stage, Cm.S->col);
     else k_spgemm_fill<G, HS><<<g, 256, 0, s>>>(sv(*A.S), sv(*B.S), sv(*Cm.S), Cm.S->col, ovf);
     FR_LAUNCH_CHECK();
 }
@@ -1407,28 +1452,43 @@ BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* 
     // wave per row with 1024 slots, then 4096 slots)
     int over = 0;
     int tier = 0;
+    // the counting pass stages each row's columns (3/4 of the tier's slots per row) when that
+    // takes at most 1 GiB; the fill then only ranks them
+    DBuf<int32_t> stage;
+    int32_t* st = nullptr;
+    auto stage_for = [&](int hs) {
+        const size_t need = size_t(std::max<int64_t>(1, A.rows())) * size_t(hs * 3 / 4);
+        st = nullptr;
+        if (need * sizeof(int32_t) > (size_t(1) << 30)) return;
+        stage.alloc(need, s);
+        st = stage.p;
+    };
     const bool short_rows = int64_t(A.S->max_len) * B.S->max_len <= 96;
     if (short_rows) {
         tier = -1;
-        spgemm_symbolic<8, 32>(A, B, Cm, ovf.p, s, false);
+        stage_for(32);
+        spgemm_symbolic<8, 32>(A, B, Cm, ovf.p, s, false, st);
         layout_from_lengths(*Cm.S, s, ovf.p, &over);
     }
     if (!short_rows || over) {
         tier = 0;
         ovf.zero(s);
-        spgemm_symbolic<8, 128>(A, B, Cm, ovf.p, s, false);
+        stage_for(128);
+        spgemm_symbolic<8, 128>(A, B, Cm, ovf.p, s, false, st);
         layout_from_lengths(*Cm.S, s, ovf.p, &over);
     }
     if (over) {
         tier = 1;
         ovf.zero(s);
-        spgemm_symbolic<64, 1024>(A, B, Cm, ovf.p, s, false);
+        stage_for(1024);
+        spgemm_symbolic<64, 1024>(A, B, Cm, ovf.p, s, false, st);
         layout_from_lengths(*Cm.S, s, ovf.p, &over);
     }
     if (over) {
         tier = 2;
         ovf.zero(s);
-        spgemm_symbolic<64, 4096>(A, B, Cm, ovf.p, s, false);
+        stage_for(4096);
+        spgemm_symbolic<64, 4096>(A, B, Cm, ovf.p, s, false, st);
         layout_from_lengths(*Cm.S, s, ovf.p, &over);
         if (over) {
             // rows beyond the largest hash set: the column bitmap, when C's columns fit in LDS
@@ -1439,10 +1499,10 @@ BMat<double> spgemm(const BMat<double>& A, const BMat<double>& B, const double* 
     }
     Cm.S->own_col.alloc(size_t(std::max<int64_t>(1, Cm.S->n_slots)), s);
     Cm.S->col = Cm.S->own_col.p;
-    if (tier == -1) spgemm_symbolic<8, 32>(A, B, Cm, errs, s, true);
-    else if (tier == 0) spgemm_symbolic<8, 128>(A, B, Cm, errs, s, true);
-    else if (tier == 1) spgemm_symbolic<64, 1024>(A, B, Cm, errs, s, true);
-    else spgemm_symbolic<64, 4096>(A, B, Cm, errs, s, true);
+    if (tier == -1) spgemm_symbolic<8, 32>(A, B, Cm, errs, s, true, st);
+    else if (tier == 0) spgemm_symbolic<8, 128>(A, B, Cm, errs, s, true, st);
+    else if (tier == 1) spgemm_symbolic<64, 1024>(A, B, Cm, errs, s, true, st);
+    else spgemm_symbolic<64, 4096>(A, B, Cm, errs, s, true, st);
     Cm.own_val.alloc(size_t(std::max<int64_t>(1, Cm.S->n_slots)) * Cm.br * Cm.bc, s);
     Cm.val = Cm.own_val.p;
     spgemm_values<MODE>(A, B, Cm, invd, omega, s);
