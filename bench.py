@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=512, help="cells per axis of the oracle's sample")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (reference for the HBM byte counters)")
-    ap.add_argument("--refresh-phi", type=int, default=2, help="amg_opts.refresh_phi (0, 1, 2)")
+    ap.add_argument("--refresh-phi", type=int, default=1, help="amg_opts.refresh_phi (0, 1, 2)")
     ap.add_argument("--tune-load", metavar="PATH",
                     help="launch shapes saved by --tune-save: used instead of timing candidates")
     ap.add_argument("--tune-save", metavar="PATH", help="write the tuner's launch shapes at the end")

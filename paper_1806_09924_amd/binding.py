@@ -178,7 +178,7 @@ def params(E=1.0, nu=0.2, Gc=1.0, kappa=1e-10, eps=1.0 / 16, p=1e-3, c_pdas=1.0,
 
 
 def amg_opts(precision=64, theta=-1.0, cheb_degree=2, cheb_ratio=8.0, coarse_max=96, max_levels=12,
-             reuse_u_block=1, refresh_phi=2, autotune=1, fine_matrix_free=7):
+             reuse_u_block=1, refresh_phi=1, autotune=1, fine_matrix_free=7):
     return AmgOpts(precision, theta, cheb_degree, cheb_ratio, coarse_max, max_levels, reuse_u_block, refresh_phi,
                    autotune, fine_matrix_free)
 

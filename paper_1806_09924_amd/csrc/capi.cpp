@@ -101,7 +101,7 @@ fr_amg_opts default_amg() {
     o.coarse_max = 96;
     o.max_levels = 10;
     o.reuse_u_block = 1;
-    o.refresh_phi = 2;
+    o.refresh_phi = 1;
     o.autotune = 1;
     o.fine_matrix_free = 7;
     return o;
