@@ -96,7 +96,9 @@ typedef struct {
     int refresh_phi;     /* amg_setup on a system whose phase-field hierarchy exists (fracture_newton
                             from its second Newton iteration on): 0 builds it anew; 1 (the default)
                             keeps its aggregates and sparsity and recomputes every level's values
-                            (the Jacobian pattern never changes; masked entries stay as zeros); 2
+                            (the Jacobian pattern never changes; masked entries stay as zeros; the
+                            prolongators are smoothed with the build's weights 4/(3 lambda_max),
+                            while each level's new lambda_max bounds its smoother); 2
                             recomputes only the finest level's diagonal and lambda_max and keeps
                             the coarse levels and transfers of the build (a lagged preconditioner,
                             as the displacement hierarchy under reuse_u_block; the finest level's

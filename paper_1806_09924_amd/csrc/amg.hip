@@ -1961,6 +1961,7 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
             {
                 ProfScope ps(nm_smooth.c_str(), s, 0.0);
                 const double omega = 4.0 / (3.0 * L->lmax);
+                L->omega = omega;
                 L->P = spgemm<1>(L->A, Pt, L->invd.p, omega, errs.p, s);
                 L->R = transpose(L->P, s);
             }
@@ -2009,25 +2010,38 @@ static void build_hierarchy(Hierarchy& H, BMat<double> A0, int ns0, const double
 
 // Same aggregates, tentative prolongators and sparsity; new values from the level-0 matrix
 // at a0 (whose structure is the one the hierarchy was built on).
-static void refresh_hierarchy(Hierarchy& H, double* a0, const fr_amg_opts& o, hipStream_t s,
+static void refresh_hierarchy(Hierarchy& H, double* a0, const fr_amg_opts& o, hipStream_t s, hipStream_t aux,
                               const MfState* mf0 = nullptr, int blk = 0) {
     const size_t nl = H.lv.size();
     H.lv[0]->A.val = a0;
     // refresh_phi 2: the finest level's diagonal and lambda_max only (coarse levels and the
     // transfers stay those of the build: a lagged preconditioner)
-    const bool fine_only = o.refresh_phi == 2;
+    if (o.refresh_phi == 2) {
+        AmgLevel& L = *H.lv[0];
+        DBuf<double> dnorm;
+        diag_info(L.A, L.invd, dnorm, s);
+        L.lmax = lambda_max(L.A, L.invd.p, s, mf0, blk);
+        if (o.precision == 32) make_f32(L, nl == 1, s);
+        return;
+    }
+    // Every level's new values; the prolongators are smoothed with the build's weights, so
+    // each level's lambda_max (the smoother's bound) is estimated on `aux` beside the products
+    // instead of ahead of them, and read once at the end.
+    struct Ev {
+        hipEvent_t e = nullptr;
+        Ev() { FR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming)); }
+        ~Ev() { if (e) (void)hipEventDestroy(e); }
+    } ev;
+    std::vector<PowerEst> pe(nl);
     for (size_t l = 0; l < nl; ++l) {
         AmgLevel& L = *H.lv[l];
         DBuf<double> dnorm;
         diag_info(L.A, L.invd, dnorm, s);
-        L.lmax = lambda_max(L.A, L.invd.p, s, l == 0 ? mf0 : nullptr, blk);
-        if (fine_only) {
-            if (o.precision == 32) make_f32(L, nl == 1, s);
-            return;
-        }
+        FR_HIP(hipEventRecord(ev.e, s));
+        FR_HIP(hipStreamWaitEvent(aux, ev.e, 0));
+        power_start(pe[l], L.A, L.invd.p, aux, l == 0 ? mf0 : nullptr, blk);
         if (l + 1 == nl) break;
-        const double omega = 4.0 / (3.0 * L.lmax);
-        spgemm_values<1>(L.A, L.Pt, L.P, L.invd.p, omega, s);
+        spgemm_values<1>(L.A, L.Pt, L.P, L.invd.p, L.omega, s);
         transpose_values(L.P, L.R, s);
         spgemm_values<0>(L.A, L.P, L.AP, nullptr, 0.0, s);
         spgemm_values<0>(L.R, L.AP, H.lv[l + 1]->A, nullptr, 0.0, s);
@@ -2035,6 +2049,7 @@ static void refresh_hierarchy(Hierarchy& H, double* a0, const fr_amg_opts& o, hi
     coarse_inverse(H, s);
     if (o.precision == 32)
         for (size_t l = 0; l < nl; ++l) make_f32(*H.lv[l], l + 1 == nl, s);
+    for (size_t l = 0; l < nl; ++l) H.lv[l]->lmax = power_finish(pe[l]);
 }
 
 static void ensure_side(DevAmg& amg) {
@@ -2075,7 +2090,7 @@ void amg_build(DevAmg& amg, DevSystem& sys, const fr_amg_opts& o, hipStream_t s)
     auto phi_setup = [&amg, &sys, &m, o, refresh_phi, side, mf_p]() {
         if (refresh_phi) {
             ProfScope ps("setup_refresh_phi", side, 0.0);
-            refresh_hierarchy(amg.h[1], sys.Jpp.val, o, side, mf_p, 1);
+            refresh_hierarchy(amg.h[1], sys.Jpp.val, o, side, amg.aux[1], mf_p, 1);
         } else {
             BMat<double> Ap;
             Ap.br = Ap.bc = 1;

@@ -287,6 +287,7 @@ struct AmgLevel {
     DBuf<double> invd;
     DBuf<float> invd32;
     double lmax = 0;
+    double omega = 0;                            // prolongator smoothing weight of the build, 4/(3 lmax)
     int ns = 1;                                  // near-nullspace size (block size of the next level)
     // V-cycle work vectors (scalar length n = rows * br)
     DBuf<double> vb, vx0, vx1, vd, vr;
