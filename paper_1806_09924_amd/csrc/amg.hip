@@ -1020,6 +1020,10 @@ __global__ void __launch_bounds__(256) k_spgemm_merge(SellV A, const double* __r
             for (int kb = lg; kb < lb; kb += G) {
                 const int64_t bs = b0 + int64_t(kb) * B.C;
                 const int32_t c = B.col[bs];
+                // B's block is loaded with its column, before the search, so the two loads
+                // are in flight together (the output row holds every column of the product)
+                double bb[BCA * BCB];
+                for (int e = 0; e < BCA * BCB; ++e) bb[e] = bv[bs * (BCA * BCB) + e];
                 int lo = 0, hi = lc - 1, p = -1;
                 while (lo <= hi) {
                     const int mid = (lo + hi) >> 1;
@@ -1029,7 +1033,6 @@ __global__ void __launch_bounds__(256) k_spgemm_merge(SellV A, const double* __r
                     else hi = mid - 1;
                 }
                 if (p < 0) continue;
-                const double* bb = bv + bs * (BCA * BCB);
                 for (int i = 0; i < BRA; ++i)
                     for (int j = 0; j < BCB; ++j) {
                         double t = 0.0;
