@@ -469,19 +469,41 @@ __device__ void spgemm_row_set(const SellV& A, const SellV& B, int64_t r, int32_
     if (r < A.n_rows) {
         const int la = A.len[r];
         bool full = false;
-        for (int ka = lg; ka < la && !full; ka += G) {
-            const int64_t k = A.col[sslot(A.sp, A.C, r, ka)];
-            const int lb = B.len[k];
-            const int64_t b0 = sslot(B.sp, B.C, k, 0);
-            // B's columns U at a time, all loaded before they are inserted
-            constexpr int U = 4;
-            for (int kb = 0; kb < lb && !full; kb += U) {
-                int32_t c[U];
+        // each lane takes two of A's entries per round (ka and ka + G) and loads the first U of
+        // B's columns of both rows before any insert, so the dependent loads (A's column, B's
+        // row start, B's columns) of both are in flight together
+        constexpr int U = 8;
+        for (int ka = lg; ka < la && !full; ka += 2 * G) {
+            const bool two = ka + G < la;
+            const int64_t k0 = A.col[sslot(A.sp, A.C, r, ka)];
+            const int64_t k1 = two ? A.col[sslot(A.sp, A.C, r, ka + G)] : k0;
+            const int lb0 = B.len[k0];
+            const int lb1 = two ? B.len[k1] : 0;
+            const int64_t b00 = sslot(B.sp, B.C, k0, 0);
+            const int64_t b01 = sslot(B.sp, B.C, k1, 0);
+            int32_t c0[U], c1[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) c[u] = kb + u < lb ? B.col[b0 + int64_t(kb + u) * B.C] : -1;
+            for (int u = 0; u < U; ++u) {
+                c0[u] = u < lb0 ? B.col[b00 + int64_t(u) * B.C] : -1;
+                c1[u] = u < lb1 ? B.col[b01 + int64_t(u) * B.C] : -1;
+            }
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (c[u] >= 0 && !full && !hash_insert<HS>(tab, c[u], added)) full = true;
+            for (int u = 0; u < U; ++u) {
+                if (c0[u] >= 0 && !full && !hash_insert<HS>(tab, c0[u], added)) full = true;
+                if (c1[u] >= 0 && !full && !hash_insert<HS>(tab, c1[u], added)) full = true;
+            }
+            // the rest of long rows of B, U columns at a time
+            for (int h = 0; h < 2 && !full; ++h) {
+                const int lb = h ? lb1 : lb0;
+                const int64_t b0 = h ? b01 : b00;
+                for (int kb = U; kb < lb && !full; kb += U) {
+                    int32_t c[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) c[u] = kb + u < lb ? B.col[b0 + int64_t(kb + u) * B.C] : -1;
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (c[u] >= 0 && !full && !hash_insert<HS>(tab, c[u], added)) full = true;
+                }
             }
         }
         if (full) atomicOr(overflow, 1);
